@@ -1,0 +1,378 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by the mathematics.
+
+Each test checks the oracle through a route that does not reuse its code: dense
+face-by-face assembly and direct solves, DCT/DST/FFT diagonalisation, the paper's
+printed Tables 2-3, exact identities of R and P, mass conservation, multigrid
+contraction, the paper's literal X-MCGS set order, and adjoint identities.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import fas_inputs as I
+import oracle as O
+from oracle import closed_forms as C
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BCS = ["neumann", "dirichlet", "periodic"]
+
+
+def _kap(shape, seed):
+    return np.exp(0.5 * I.random_field(shape, seed))
+
+
+# ---------------------------------------------------------------- operator and smoother
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("variable", [False, True])
+@pytest.mark.parametrize("n", [(8, 8), (8, 4), (4, 4, 4)])
+def test_apply_matches_dense_assembly(bc, variable, n):
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.37, kappa=1.3, bc=bc, coarsest=2)
+    kap = _kap(P.shape(), 11) if variable else None
+    u = I.random_field(P.shape(), 5)
+    A = C.assemble_dense(P, kap)
+    ref = (A @ u.ravel()).reshape(u.shape)
+    got = O.apply(P, 0, u, kap=kap)
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_apply_coarse_level_scaling(bc):
+    """Level l of the hierarchy is the same operator on a grid with h_l = 2^l h."""
+    P = O.Problem(n=(16, 16), h=1 / 16, dt=0.2, kappa=0.7, bc=bc, coarsest=2)
+    Pc = O.Problem(n=(4, 4), h=4 / 16, dt=0.2, kappa=0.7, bc=bc, coarsest=2)
+    u = I.random_field(P.shape(2), 8)
+    ref = (C.assemble_dense(Pc) @ u.ravel()).reshape(u.shape)
+    np.testing.assert_allclose(O.apply(P, 2, u), ref, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("variable", [False, True])
+@pytest.mark.parametrize("n", [(8, 8), (6, 4), (4, 4, 4)])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_sweep_is_red_black_gauss_seidel(bc, variable, n, reverse):
+    """One sweep equals x <- (D+L)^{-1}(b - U x) on the dense matrix with the unknowns
+    ordered odd-1-based-index-sum first (the other colour first for the reversed sweep)."""
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.9, kappa=1.1, bc=bc, coarsest=2)
+    kap = _kap(P.shape(), 3) if variable else None
+    f = I.random_field(P.shape(), 1)
+    u = I.random_field(P.shape(), 2)
+    A = C.assemble_dense(P, kap)
+    ref = C.rb_gauss_seidel_dense(A, f, u, first_odd_1based=not reverse, shape=P.shape())
+    O.smooth(P, 0, f, u, 1, reverse=reverse, kap=kap)
+    np.testing.assert_allclose(u, ref, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("n", [(16, 16), (32, 8), (8, 8, 8), (16, 8, 4)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_xmcgs_set_order_equals_red_black_bitwise(bc, n, dtype):
+    """The paper's 4-set (2D) / 8-set (3D) X-MCGS order and the oracle's two-colour
+    order give identical bits: sets 1-2 (1-4 in 3D) are exactly the odd-sum cells and
+    no two cells of one colour are neighbours."""
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.5, kappa=1.0, bc=bc, coarsest=2)
+    f = I.random_field(P.shape(), 4).astype(dtype)
+    u0 = I.random_field(P.shape(), 6).astype(dtype)
+    a = u0.copy()
+    b = u0.copy()
+    for _ in range(3):
+        C.xmcgs_sweep_literal(P, 0, f, a)
+    O.smooth(P, 0, f, b, 3)
+    assert np.array_equal(a, b)
+
+
+def test_z_order_differs_from_x_order():
+    """Control for the test above: an ordering with a different dependency structure
+    (Z order: (o,o),(o,e),(e,o),(e,e)) does not give the same bits."""
+    P = O.Problem(n=(16, 16), h=1 / 16, dt=0.5, bc="neumann", coarsest=2)
+    f = I.random_field(P.shape(), 4)
+    a = I.random_field(P.shape(), 6)
+    b = a.copy()
+    C.xmcgs_sweep_literal(P, 0, f, a, sets=[("o", "o"), ("o", "e"), ("e", "o"), ("e", "e")])
+    O.smooth(P, 0, f, b, 1)
+    assert not np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- transfer operators
+@pytest.mark.parametrize("n", [(8, 8), (8, 4, 4)])
+def test_restrict_prolong_identities(n):
+    P = O.Problem(n=n, h=1 / 8, coarsest=2)
+    d = P.dim
+    x = I.random_field(P.shape(0), 1)
+    c = I.random_field(P.shape(1), 2)
+    Rx = O.restrict(P, 0, x)
+    # R is the average of the 2^d children
+    blocks = x.reshape(*sum(([s // 2, 2] for s in P.shape(0)), []))
+    ref = blocks.mean(axis=tuple(range(1, 2 * d, 2)))
+    np.testing.assert_allclose(Rx, ref, rtol=1e-15, atol=1e-15)
+    # P c is piecewise constant: prolong_add(c, 0) onto zeros
+    fine = np.zeros(P.shape(0))
+    O.prolong_add(P, 0, c, np.zeros_like(c), fine)
+    rep = c
+    for ax in range(d):
+        rep = np.repeat(rep, 2, axis=ax)
+    assert np.array_equal(fine, rep)
+    # R^T = 2^-d P  (dot-product identity) and R P = I
+    assert abs(np.vdot(Rx, c) - np.vdot(x, fine) / 2**d) < 1e-12
+    np.testing.assert_allclose(O.restrict(P, 0, fine), c, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- direct solves (P1)
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("variable", [False, True])
+@pytest.mark.parametrize("n", [(4, 4), (8, 8), (8, 4), (4, 4, 4)])
+def test_converged_solve_matches_dense(bc, variable, n):
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.8, kappa=1.0, bc=bc, coarsest=2, nuc=60)
+    kap = _kap(P.shape(), 21) if variable else None
+    f = I.random_field(P.shape(), 7)
+    u = np.zeros_like(f)
+    st, cyc, _ = O.solve(P, f, u, tol=1e-14, kmax=300, kap=kap)
+    assert st == 0
+    ref = C.dense_solve(P, f, kap)
+    np.testing.assert_allclose(u, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- closed forms (P2-P4)
+def test_heat_256_neumann_matches_dct():
+    """256^2, dt=1e-3, 16 cosine modes: one backward-Euler step, solved to 1e-10
+    relative residual, equals the DCT-II solution of the same discrete system."""
+    u0 = I.heat_2d_small()
+    P = O.Problem(n=(256, 256), h=1 / 256, dt=1e-3, bc="neumann", coarsest=4, nuc=2)
+    u = u0.copy()
+    st, cyc, hist = O.solve(P, u0, u, 1e-10)
+    assert st == 0 and 6 <= cyc <= 9
+    ref = C.spectral_solve(P, u0)
+    assert np.abs(u - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_cosine_mode_is_an_eigenvector():
+    """A single Neumann cosine mode cos(k pi x)cos(l pi y) on cell centres is mapped to
+    itself times 1 + dt(lam_k + lam_l), lam_k = (4/h^2) sin^2(k pi h/2)."""
+    n, k, l, dt = 64, 3, 5, 1e-3
+    x = I.centres(n)
+    u = np.outer(np.cos(l * np.pi * x), np.cos(k * np.pi * x))
+    P = O.Problem(n=(n, n), h=1 / n, dt=dt, bc="neumann", coarsest=4)
+    lam = lambda m: 4 * n * n * np.sin(m * np.pi / (2 * n)) ** 2
+    np.testing.assert_allclose(O.apply(P, 0, u), (1 + dt * (lam(k) + lam(l))) * u, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc,n", [("dirichlet", (128, 128)), ("periodic", (128, 128)), ("neumann", (32, 32, 32)),
+                                  ("dirichlet", (32, 32, 32)), ("periodic", (128, 64))])
+def test_solve_matches_spectral(bc, n):
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.05, kappa=0.8, bc=bc, coarsest=4, nuc=30)
+    f = I.random_field(P.shape(), 3)
+    u = np.zeros_like(f)
+    st, cyc, _ = O.solve(P, f, u, 1e-12, kmax=100)
+    assert st == 0
+    ref = C.spectral_solve(P, f)
+    assert np.abs(u - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- paper Tables 2-3 (P3)
+def _paper_rows():
+    rows = []
+    with open(os.path.join(HERE, "golden", "paper_tables_2_3.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                d, n, e = line.split()
+                rows.append((int(d), int(n), float(e)))
+    return rows
+
+
+def _table_error(dim, n):
+    x = I.centres(n)
+    g = np.sin(np.pi * np.sin(np.pi * x))
+    g2 = (-np.pi**3 * np.sin(np.pi * x) * np.cos(np.pi * np.sin(np.pi * x))
+          - np.pi**4 * np.cos(np.pi * x) ** 2 * np.sin(np.pi * np.sin(np.pi * x)))
+    if dim == 2:
+        p = np.outer(g, g)
+        lap = np.outer(g, g2) + np.outer(g2, g)
+    else:
+        p = g[:, None, None] * g[None, :, None] * g[None, None, :]
+        lap = (g2[:, None, None] * g[None, :, None] * g[None, None, :]
+               + g[:, None, None] * g2[None, :, None] * g[None, None, :]
+               + g[:, None, None] * g[None, :, None] * g2[None, None, :])
+    f = p - lap
+    P = O.Problem(n=(n,) * dim, h=1.0 / n, dt=1.0, kappa=1.0, bc="dirichlet", coarsest=2, nuc=2)
+    u = np.zeros_like(f)
+    st, _, _ = O.solve(P, f, u, 1e-11, kmax=60)
+    assert st == 0
+    return (1.0 / n) ** (dim / 2) * np.sqrt(np.sum((u - p) ** 2))
+
+
+@pytest.mark.parametrize("dim,n", [(2, 1024), (3, 32), (3, 64)])
+def test_paper_tables_2_3(dim, n):
+    printed = {(d, m): e for d, m, e in _paper_rows()}[(dim, n)]
+    err = _table_error(dim, n)
+    # the table prints three significant digits
+    assert abs(err - printed) <= 0.5 * 10 ** (np.floor(np.log10(printed)) - 2) + 1e-15
+
+
+def test_paper_tables_order_two():
+    """Printed order 2.00: consecutive printed errors differ by a factor 4 (+-1%), and
+    the oracle's errors at 256^2/512^2 (not printed) continue the same law."""
+    rows = _paper_rows()
+    for d in (2, 3):
+        es = [e for dd, _, e in rows if dd == d]
+        for a, b in zip(es, es[1:]):
+            assert abs(np.log2(a / b) - 2.0) < 0.015
+    e256, e512 = _table_error(2, 256), _table_error(2, 512)
+    assert abs(np.log2(e256 / e512) - 2.0) < 0.01
+
+
+# ---------------------------------------------------------------- O(h^2) under Neumann (P8)
+def test_neumann_cosine_second_order():
+    """u - dt Lap u = a cos(k pi x) cos(l pi y) has the exact Neumann solution
+    a cos cos/(1 + dt pi^2 (k^2 + l^2)); the discrete solution converges at order 2."""
+    k, l, dt = 3, 2, 1e-2
+    errs = []
+    for n in (32, 64, 128):
+        x = I.centres(n)
+        f = np.outer(np.cos(l * np.pi * x), np.cos(k * np.pi * x))
+        exact = f / (1 + dt * np.pi**2 * (k * k + l * l))
+        P = O.Problem(n=(n, n), h=1 / n, dt=dt, bc="neumann", coarsest=4)
+        u = f.copy()
+        st, _, _ = O.solve(P, f, u, 1e-13, kmax=60)
+        assert st == 0
+        errs.append(np.abs(u - exact).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(orders - 2.0) < 0.05), orders
+
+
+# ---------------------------------------------------------------- mass (P6), contraction (P7)
+@pytest.mark.parametrize("variable", [False, True])
+def test_neumann_mass_conservation(variable):
+    """Each row sum of A is 1 under Neumann BCs, so sum(u) - sum(f) = -sum(r)."""
+    n = 128
+    P = O.Problem(n=(n, n), h=1 / n, dt=1e-3, bc="neumann", coarsest=4)
+    kap = _kap(P.shape(), 2) if variable else None
+    f = I.heat_2d_small(n)
+    u = f.copy()
+    st, _, _ = O.solve(P, f, u, 1e-10, kap=kap)
+    r = O.residual(P, 0, f, u, kap=kap)
+    assert abs(u.sum() - f.sum() + r.sum()) < 1e-9
+    assert abs(u.sum() - f.sum()) <= np.sqrt(u.size) * np.linalg.norm(r) + 1e-9
+
+
+def test_contraction_paper_setting_is_mesh_independent():
+    """Dirichlet, dt = kappa = 1, coarsest 2^2, s = 2 (Section 3.1): the residual
+    contraction per V-cycle stays near 0.1 and does not grow with n."""
+    rates = []
+    for n in (64, 128, 256):
+        P = O.Problem(n=(n, n), h=1 / n, dt=1.0, bc="dirichlet", coarsest=2, nuc=2)
+        f = I.random_field(P.shape(), 9)
+        u = I.random_field(P.shape(), 10, 0.0, 1.0)
+        _, _, hist = O.solve(P, f, u, 1e-30, kmax=8)
+        rates.append((hist[-1] / hist[2]) ** (1 / (len(hist) - 3)))
+    assert all(0.05 < r < 0.15 for r in rates), rates
+    assert max(rates) - min(rates) < 0.03, rates
+
+
+def test_contraction_heat_256():
+    P = O.Problem(n=(256, 256), h=1 / 256, dt=1e-3, bc="neumann", coarsest=4, nuc=2)
+    f = I.heat_2d_small()
+    u = f.copy()
+    _, _, hist = O.solve(P, f, u, 1e-30, kmax=6)
+    rate = (hist[-1] / hist[0]) ** (1 / (len(hist) - 1))
+    assert 0.02 < rate < 0.08, rate
+
+
+# ---------------------------------------------------------------- adjoint (P9)
+@pytest.mark.parametrize("n,bc", [((16, 16), "neumann"), ((16, 8), "dirichlet"), ((8, 8, 8), "neumann"),
+                                  ((16, 16), "periodic")])
+@pytest.mark.parametrize("variable", [False, True])
+def test_transposed_vcycle_dot_product(n, bc, variable):
+    """B = two V-cycles from zero (a linear map of the right-hand side); its transpose
+    is two transposed V-cycles from zero: <B x, y> = <x, B^T y>."""
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.3, bc=bc, coarsest=2, nuc=3)
+    kap = _kap(P.shape(), 4) if variable else None
+    x = I.random_field(P.shape(), 1)
+    y = I.random_field(P.shape(), 2)
+    Bx = np.zeros_like(x)
+    BTy = np.zeros_like(y)
+    for _ in range(2):
+        O.vcycle(P, x, Bx, 2, 1, kap=kap)
+        O.vcycle(P, y, BTy, 2, 1, transposed=True, kap=kap)
+    lhs, rhs = np.vdot(Bx, y), np.vdot(x, BTy)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    # and the forward cycle alone is not symmetric (nu1 != nu2), so the test has teeth
+    Bty = np.zeros_like(y)
+    for _ in range(2):
+        O.vcycle(P, y, Bty, 2, 1, kap=kap)
+    assert abs(np.vdot(x, Bty) - lhs) > 1e-9 * abs(lhs)
+
+
+def test_heat_adjoint_matches_dense_and_fd():
+    """Gradients of ||u_T - u_tgt||^2 over T backward-Euler steps on 8^2 with a cell
+    kappa: d/du0 against dense A^{-T} products, d/dkappa against central differences of
+    the dense-solve loss."""
+    n, T, dt = 8, 3, 0.05
+    P = O.Problem(n=(n, n), h=1 / n, dt=dt, bc="neumann", coarsest=2, nuc=40)
+    kap = _kap(P.shape(), 5)
+    u0 = I.random_field(P.shape(), 6)
+    tgt = I.random_field(P.shape(), 7)
+    loss, gu, gk = O.heat_adjoint(P, u0, kap, T, tgt, tol=1e-14, kmax=200)
+
+    def dense_loss(kv, uv):
+        A = C.assemble_dense(P, kv)
+        x = uv.ravel()
+        for _ in range(T):
+            x = np.linalg.solve(A, x)
+        return float(np.sum((x - tgt.ravel()) ** 2)), A, x
+
+    L0, A, xT = dense_loss(kap, u0)
+    assert abs(L0 - loss) < 1e-12 * L0
+    lam = 2 * (xT - tgt.ravel())
+    for _ in range(T):
+        lam = np.linalg.solve(A.T, lam)
+    np.testing.assert_allclose(gu.ravel(), lam, rtol=1e-10, atol=1e-12)
+    eps = 1e-6
+    fd = np.zeros(kap.size)
+    for p in range(kap.size):
+        kp, km = kap.copy().ravel(), kap.copy().ravel()
+        kp[p] += eps
+        km[p] -= eps
+        fd[p] = (dense_loss(kp.reshape(kap.shape), u0)[0] - dense_loss(km.reshape(kap.shape), u0)[0]) / (2 * eps)
+    np.testing.assert_allclose(gk.ravel(), fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+@pytest.mark.parametrize("bc", ["neumann", "dirichlet"])
+def test_kappa_grad_dirichlet_faces(bc):
+    """Single-solve kappa gradient, including Dirichlet boundary faces, against central
+    differences of the dense solve."""
+    n = 6
+    P = O.Problem(n=(n, n), h=1 / n, dt=0.3, bc=bc, coarsest=3, nuc=40)
+    kap = _kap(P.shape(), 8)
+    b = I.random_field(P.shape(), 9)
+    w = I.random_field(P.shape(), 10)
+
+    def J(kv):
+        return float(np.vdot(w, C.dense_solve(P, b, kv)))
+
+    u = C.dense_solve(P, b, kap)
+    mu = np.linalg.solve(C.assemble_dense(P, kap).T, w.ravel()).reshape(w.shape)
+    g = np.zeros_like(kap)
+    O.kappa_grad(P, kap, mu, u, g)
+    eps = 1e-6
+    for p in range(kap.size):
+        kp, km = kap.copy().ravel(), kap.copy().ravel()
+        kp[p] += eps
+        km[p] -= eps
+        fd = (J(kp.reshape(kap.shape)) - J(km.reshape(kap.shape))) / (2 * eps)
+        assert abs(g.ravel()[p] - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- mixed precision (P10)
+@pytest.mark.parametrize("variable", [False, True])
+def test_mixed_precision_reaches_fp64_solution(variable):
+    n = 128
+    P = O.Problem(n=(n, n), h=1 / n, dt=1e-3, bc="neumann", coarsest=4)
+    kap = _kap(P.shape(), 12) if variable else None
+    f = I.heat_2d_small(n)
+    u = f.copy()
+    st, outer, hist = O.solve_mixed(P, f, u, tol=1e-10, inner=2, kap=kap)
+    assert st == 0 and 2 <= outer <= 8, (outer, hist)
+    ref = f.copy()
+    O.solve(P, f, ref, 1e-13, kap=kap)
+    assert np.abs(u - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert hist[-1] <= 1e-10
