@@ -1,0 +1,164 @@
+/*
+ * fas.h - C ABI of the MI355X matrix-free FAS multigrid library (libfas.so).
+ *
+ * Method: the matrix-free Full Approximation Storage multigrid of arXiv 2510.11152,
+ * Section 2 (Alg. 1 applied recursively as in Remark 2), on cell-centred grids, with the
+ * X-shape multi-colour Gauss-Seidel smoother of Section 2.3 / Appendix B, the 2^d-cell
+ * average restriction and piecewise-constant prolongation of Appendix C, and smoothing
+ * (not a direct solve) on the coarsest level (Remark 1).  The operator is one
+ * backward-Euler heat step
+ *
+ *     A u = u - dt * div(kappa grad u) = f          (eq. PDE_discret with dt, kappa)
+ *
+ * discretised with the 5-point (2D) / 7-point (3D) stencil, spacing h equal on every
+ * axis (Section 2.1).  Boundary conditions: homogeneous Neumann (default), Dirichlet
+ * u = 0 through a ghost value equal to minus the adjacent cell (the reading that
+ * reproduces the paper's Tables 2-3), or periodic.  kappa is a constant or a cell field;
+ * face values of a cell field are harmonic means, and the coarse-level field is the
+ * restricted fine field.
+ *
+ * Conventions for every entry point
+ *   - Arrays are device pointers to contiguous storage of the grid's dtype, x fastest:
+ *     index = i + n0*(j + n1*k).  The caller owns all device memory, including the
+ *     workspace handed to fas_grid_create; the library never allocates or frees device
+ *     memory and keeps no pointer after fas_grid_destroy.
+ *   - All work is enqueued on the grid's HIP stream (fas_grid_create / fas_set_stream).
+ *     Entry points that report a norm or a convergence status synchronise that stream;
+ *     the others return as soon as the work is enqueued.
+ *   - Return value: FAS_OK (0), FAS_NOT_CONVERGED (+1, u holds the last iterate) or a
+ *     negative FAS_ERR_* code.  fas_last_error() gives a message for the calling
+ *     thread.  Nothing throws or aborts across the ABI.
+ *   - A grid is not thread-safe: calls that share a grid (hence a workspace) must not
+ *     overlap in time, on any stream.
+ */
+#ifndef FAS_H
+#define FAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FAS_OK 0
+#define FAS_NOT_CONVERGED 1
+#define FAS_ERR_ARG (-1)       /* null/aliased pointer, bad option or parameter       */
+#define FAS_ERR_SHAPE (-2)     /* sizes not coarsest*2^L with L >= 1, or too large     */
+#define FAS_ERR_NOMEM (-3)     /* workspace smaller than fas_workspace_size()          */
+#define FAS_ERR_HIP (-4)       /* a HIP runtime call failed                            */
+#define FAS_ERR_NONFINITE (-5) /* a residual norm became NaN or Inf                    */
+
+/* boundary conditions */
+#define FAS_BC_NEUMANN 0
+#define FAS_BC_DIRICHLET 1
+#define FAS_BC_PERIODIC 2
+
+/* storage / arithmetic type of a grid */
+#define FAS_F64 0
+#define FAS_F32 1
+
+/* fas_grid_create flags */
+#define FAS_FLAG_VARIABLE_KAPPA 1 /* reserve coarse-level storage for a cell kappa field   */
+#define FAS_FLAG_MIXED_INNER 2    /* FP32 grid used as the inner solver of fas_solve_mixed */
+
+/* fas_grid_set options */
+#define FAS_OPT_KMAX 1          /* maximum V-cycles of a solve (default 100; Table 1 kMax) */
+#define FAS_OPT_COARSE_SWEEPS 2 /* sweeps on the coarsest level (default 2; Remark 1)      */
+#define FAS_OPT_FUSED 3         /* 1 (default): fused tile kernels where available;
+                                   0: one kernel per colour phase everywhere              */
+
+typedef struct fas_grid* fas_grid_t;
+
+typedef struct {
+    int cycles;             /* V-cycles (or outer corrections) of the last solve        */
+    int status;             /* FAS_OK / FAS_NOT_CONVERGED / error of the last solve      */
+    double rhs_norm;        /* ||f||_2 of the last solve                                 */
+    double rel_res[64];     /* ||f - A u||_2 / ||f||_2 after cycle c (c < 64)            */
+} fas_stats_t;
+
+/* Bytes of device workspace a grid needs.  dim = 2 or 3; n[0..dim-1] cells per axis; the
+ * shortest axis must be coarsest * 2^L with L >= 1 and every axis divisible by 2^L
+ * (Section 2.1: M_0 = M_1/2, h_0 = 2 h_1).  coarsest: cells along the shortest axis of
+ * the coarsest level (even, >= 2).  Returns 0 for an invalid shape. */
+size_t fas_workspace_size(int dim, const int64_t n[3], int dtype, int coarsest, int flags);
+
+/* Create a grid plan over a caller-owned workspace of at least fas_workspace_size()
+ * bytes (256-byte aligned).  h: finest spacing.  bc: FAS_BC_*.  stream: hipStream_t
+ * (NULL = default stream).  *out receives the handle. */
+int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, int flags,
+                    void* workspace, size_t ws_bytes, void* stream, fas_grid_t* out);
+int fas_grid_destroy(fas_grid_t grid);
+int fas_grid_set(fas_grid_t grid, int option, double value);
+int fas_set_stream(fas_grid_t grid, void* stream);
+/* Number of coarsenings L (levels 0..L, level 0 finest) and the cells of level `level`. */
+int fas_grid_levels(fas_grid_t grid);
+int64_t fas_level_cells(fas_grid_t grid, int level);
+
+/* Coefficient arguments (kappa, kappa_cell) of the entry points below: kappa_cell NULL
+ * selects the constant kappa; otherwise kappa_cell is the finest-level cell field (grid
+ * dtype, finest size, all values > 0) and kappa is ignored.  A cell field requires a grid
+ * created with FAS_FLAG_VARIABLE_KAPPA. */
+
+/* Solve A u = rhs by V(nu1,nu2)-cycles (Alg. 1 outer loop) until
+ * ||rhs - A u||_2 <= tol * ||rhs||_2 or FAS_OPT_KMAX cycles.  u: initial guess in,
+ * iterate out.  rhs and u must not alias (FAS_ERR_ARG).  Synchronises the stream once
+ * per cycle to read the residual norm. */
+int fas_solve(fas_grid_t grid, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u,
+              double tol, int nu1, int nu2);
+
+/* One V(nu1,nu2)-cycle on u in place.  rel_res (nullable): if given, the stream is
+ * synchronised and ||rhs - A u||_2/||rhs||_2 after the cycle is written there. */
+int fas_vcycle(fas_grid_t grid, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u,
+               int nu1, int nu2, double* rel_res);
+
+/* Transposed cycle/solve (the adjoint of the cycle as a linear map of rhs): every sweep
+ * runs its two colours in reverse order and the pre/post sweep counts are swapped.  A is
+ * symmetric, so fas_solve_transposed converges to the same A^{-1} rhs. */
+int fas_vcycle_transposed(fas_grid_t grid, double dt, double kappa, const void* kappa_cell, const void* rhs,
+                          void* u, int nu1, int nu2, double* rel_res);
+int fas_solve_transposed(fas_grid_t grid, double dt, double kappa, const void* kappa_cell, const void* rhs,
+                         void* u, double tol, int nu1, int nu2);
+
+/* Building blocks on one level (0 = finest).  Arrays are that level's size.  For these
+ * calls with a cell field, kappa_cell is the field ON THAT LEVEL (the restricted field
+ * for level > 0).
+ *   fas_smooth:    `sweeps` X-MCGS sweeps in place (Section 2.3; reverse = 1 runs the
+ *                  colours in reverse order).
+ *   fas_residual:  r = rhs - A u (eq. residual); norm2 (nullable, synchronises) gets
+ *                  ||r||_2.
+ *   fas_restrict:  coarse = R fine, average of the 2^d children (Appendix C); level is
+ *                  the fine level.
+ *   fas_prolong_add: fine += P(c_new - c_old), piecewise constant (Appendix C, Alg. 1
+ *                  fine grid correction); level is the fine level. */
+int fas_smooth(fas_grid_t grid, int level, double dt, double kappa, const void* kappa_cell, const void* rhs,
+               void* u, int sweeps, int reverse);
+int fas_residual(fas_grid_t grid, int level, double dt, double kappa, const void* kappa_cell, const void* rhs,
+                 const void* u, void* r, double* norm2);
+int fas_restrict(fas_grid_t grid, int level, const void* fine, void* coarse);
+int fas_prolong_add(fas_grid_t grid, int level, const void* c_new, const void* c_old, void* fine);
+
+/* Gradient of a loss through one solve A(kappa) u = b given mu = A^{-T} dLoss/du:
+ * gkappa -= mu^T (dA/dkappa) u on the finest level (FP64 grid, cell kappa).  Face
+ * weight w = 2 ka kb/(ka + kb), dw/dka = 2 kb^2/(ka + kb)^2; a Dirichlet face of cell p
+ * contributes 2 mu_p u_p.  gkappa is accumulated (+=) in place. */
+int fas_kappa_grad(fas_grid_t grid, double dt, const void* kappa_cell, const void* mu, const void* u,
+                   void* gkappa);
+
+/* Mixed precision (FP32 storage and smoothing inside FP64 defect correction):
+ *   loop: r = rhs - A u (FP64); rho = ||r||_2; stop if rho <= tol*||rhs||_2;
+ *         r32 = fp32(r/rho); e = 0; `inner` FP32 V-cycles on A e = r32; u += rho*fp64(e)
+ * g64: FP64 grid; g32: FP32 grid of the same shape, bc and h, created with
+ * FAS_FLAG_MIXED_INNER (and FAS_FLAG_VARIABLE_KAPPA for a cell field, which is given in
+ * FP64 and rounded to FP32 for the inner cycle).  Stats on g64 count outer corrections. */
+int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, const void* kappa_cell,
+                    const void* rhs, void* u, double tol, int nu1, int nu2, int inner);
+
+int fas_get_stats(fas_grid_t grid, fas_stats_t* out);
+const char* fas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAS_H */

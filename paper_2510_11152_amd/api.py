@@ -1,0 +1,160 @@
+"""Python binding of libfas: argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the solver runs in the HIP
+kernels of libfas.so.  Tensors are contiguous, shaped (ny, nx) in 2D or (nz, ny, nx)
+in 3D (x fastest), on the grid's device, in the grid's dtype.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+_DT = {torch.float64: _lib.FAS_F64, torch.float32: _lib.FAS_F32}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """Grid plan + caller-owned workspace (a torch uint8 tensor).
+
+    n: cells per axis (nx, ny) or (nx, ny, nz); h: finest spacing; bc: 'neumann',
+    'dirichlet' or 'periodic'; coarsest: cells along the shortest axis of the coarsest
+    level; variable_kappa: reserve storage for a cell coefficient hierarchy;
+    mixed_inner: FP32 grid used as the inner solver of solve_mixed."""
+
+    def __init__(self, n, h, bc="neumann", dtype=torch.float64, coarsest=4, variable_kappa=False,
+                 mixed_inner=False, device="cuda", stream=None):
+        L = load()
+        self.n = tuple(int(x) for x in n)
+        self.dim = len(self.n)
+        self.h = float(h)
+        self.bc = bc
+        self.dtype = dtype
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        flags = (_lib.FAS_FLAG_VARIABLE_KAPPA if variable_kappa else 0) | (_lib.FAS_FLAG_MIXED_INNER if mixed_inner else 0)
+        n3 = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.dim)))
+        size = L.fas_workspace_size(self.dim, n3, _DT[dtype], coarsest, flags)
+        if size == 0:
+            raise ValueError("invalid grid: n=%s coarsest=%d" % (self.n, coarsest))
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h_out = ctypes.c_void_p()
+        check(L.fas_grid_create(self.dim, n3, self.h, _lib.FAS_BC[bc], _DT[dtype], coarsest, flags,
+                                _ptr(self.workspace), size, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_out)),
+              "fas_grid_create")
+        self.handle = h_out
+        self.levels = L.fas_grid_levels(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.load().fas_grid_destroy(h)
+            self.handle = None
+
+    def shape(self, level=0):
+        return tuple(m >> level for m in reversed(self.n))
+
+    def set(self, kmax=None, coarse_sweeps=None, fused=None):
+        L = load()
+        if kmax is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
+        if coarse_sweeps is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_grid_set")
+        if fused is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_FUSED, float(int(fused))), "fas_grid_set")
+        return self
+
+    def _arr(self, t, level=0, name="array", dtype=None):
+        if t is None:
+            return None
+        want = dtype or self.dtype
+        if t.dtype != want or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != self.shape(level):
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s (got %s %s %s)" % (
+                name, want, self.shape(level), self.device, t.dtype, tuple(t.shape), t.device))
+        return t
+
+    # ---------------------------------------------------------------- solves
+    def solve(self, rhs, u, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=2, transposed=False):
+        """Solve A u = rhs in place (u: initial guess in, solution out).  Returns the
+        status (0 converged, 1 kmax reached)."""
+        self._arr(rhs, name="rhs"), self._arr(u, name="u"), self._arr(kappa_cell, name="kappa_cell")
+        fn = load().fas_solve_transposed if transposed else load().fas_solve
+        return check(fn(self.handle, dt, kappa, _ptr(kappa_cell), _ptr(rhs), _ptr(u), tol, nu1, nu2),
+                     "fas_solve", allow_not_converged=True)
+
+    def vcycle(self, rhs, u, dt, kappa=1.0, kappa_cell=None, nu1=2, nu2=2, transposed=False, with_residual=False):
+        self._arr(rhs, name="rhs"), self._arr(u, name="u"), self._arr(kappa_cell, name="kappa_cell")
+        rr = ctypes.c_double(0.0)
+        fn = load().fas_vcycle_transposed if transposed else load().fas_vcycle
+        check(fn(self.handle, dt, kappa, _ptr(kappa_cell), _ptr(rhs), _ptr(u), nu1, nu2,
+                 ctypes.byref(rr) if with_residual else None), "fas_vcycle")
+        return rr.value if with_residual else None
+
+    # ---------------------------------------------------------------- building blocks
+    def smooth(self, level, rhs, u, dt, kappa=1.0, kappa_cell=None, sweeps=1, reverse=False):
+        self._arr(rhs, level, "rhs"), self._arr(u, level, "u"), self._arr(kappa_cell, level, "kappa_cell")
+        check(load().fas_smooth(self.handle, level, dt, kappa, _ptr(kappa_cell), _ptr(rhs), _ptr(u), sweeps,
+                                int(reverse)), "fas_smooth")
+
+    def residual(self, level, rhs, u, dt, kappa=1.0, kappa_cell=None, out=None, with_norm=False):
+        self._arr(rhs, level, "rhs"), self._arr(u, level, "u"), self._arr(kappa_cell, level, "kappa_cell")
+        r = torch.empty_like(u) if out is None else self._arr(out, level, "out")
+        nrm = ctypes.c_double(0.0)
+        check(load().fas_residual(self.handle, level, dt, kappa, _ptr(kappa_cell), _ptr(rhs), _ptr(u), _ptr(r),
+                                  ctypes.byref(nrm) if with_norm else None), "fas_residual")
+        return (r, nrm.value) if with_norm else r
+
+    def restrict(self, level, fine, out=None):
+        self._arr(fine, level, "fine")
+        c = torch.empty(self.shape(level + 1), dtype=self.dtype, device=self.device) if out is None else out
+        self._arr(c, level + 1, "out")
+        check(load().fas_restrict(self.handle, level, _ptr(fine), _ptr(c)), "fas_restrict")
+        return c
+
+    def prolong_add(self, level, c_new, c_old, fine):
+        self._arr(c_new, level + 1, "c_new"), self._arr(c_old, level + 1, "c_old"), self._arr(fine, level, "fine")
+        check(load().fas_prolong_add(self.handle, level, _ptr(c_new), _ptr(c_old), _ptr(fine)), "fas_prolong_add")
+
+    def kappa_grad(self, dt, kappa_cell, mu, u, gkappa):
+        for t, nm in ((kappa_cell, "kappa_cell"), (mu, "mu"), (u, "u"), (gkappa, "gkappa")):
+            self._arr(t, 0, nm)
+        check(load().fas_kappa_grad(self.handle, dt, _ptr(kappa_cell), _ptr(mu), _ptr(u), _ptr(gkappa)),
+              "fas_kappa_grad")
+
+    def stats(self):
+        s = _lib.FasStats()
+        check(load().fas_get_stats(self.handle, ctypes.byref(s)), "fas_get_stats")
+        c = s.cycles
+        return {"cycles": c, "status": s.status, "rhs_norm": s.rhs_norm,
+                "rel_res": [s.rel_res[i] for i in range(min(c + 1, 64))]}
+
+
+def solve_mixed(g64, g32, rhs, u, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=2, inner=2):
+    """FP64 defect correction around FP32 V-cycles (g32 built with mixed_inner=True)."""
+    g64._arr(rhs, name="rhs"), g64._arr(u, name="u"), g64._arr(kappa_cell, name="kappa_cell")
+    return check(load().fas_solve_mixed(g64.handle, g32.handle, dt, kappa, _ptr(kappa_cell), _ptr(rhs), _ptr(u),
+                                        tol, nu1, nu2, inner), "fas_solve_mixed", allow_not_converged=True)
+
+
+def heat(grid, u0, steps, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=2, keep=False):
+    """Backward-Euler heat steps: rhs = u^n, warm start u = u^n, solve.  Returns u^T
+    (and the list of states when keep=True)."""
+    u = u0.clone()
+    rhs = torch.empty_like(u)
+    states = [u.clone()] if keep else None
+    for _ in range(steps):
+        rhs.copy_(u)
+        st = grid.solve(rhs, u, dt, kappa, kappa_cell, tol, nu1, nu2)
+        if st != _lib.FAS_OK:
+            raise RuntimeError("heat step did not converge")
+        if keep:
+            states.append(u.clone())
+    return (u, states) if keep else u

@@ -1,0 +1,546 @@
+// C ABI of libfas: grid plan, workspace layout, the V-cycle / solve drivers
+// (Alg. 1 applied recursively, Remarks 1-2) and the mixed-precision defect correction.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "fas_internal.h"
+
+using fas::Error;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(F&& body)
+{
+    try {
+        return body();
+    } catch (const Error& e) {
+        return fail(e.code, e.what());
+    } catch (const std::exception& e) {
+        return fail(FAS_ERR_ARG, e.what());
+    } catch (...) {
+        return fail(FAS_ERR_ARG, "unknown error");
+    }
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout (offsets from the workspace base, each 256-byte aligned):
+//   level 0: x                      (second buffer of the finest level)
+//   level l >= 1: u, f, x           (paper's two arrays per level plus the second buffer)
+//   kappa levels 1..L, and level 0 of an FP32 grid (FAS_FLAG_VARIABLE_KAPPA)
+//   e, r32 of the finest level       (FAS_FLAG_MIXED_INNER)
+//   norm partial sums                (kPartials + 8 doubles)
+struct Layout {
+    int L;
+    int n[fas::kMaxLevels][3];
+    size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], kap[fas::kMaxLevels];
+    size_t mix_e, mix_r, partials, total;
+};
+
+// Returns 0 or an error code (FAS_ERR_SHAPE / FAS_ERR_ARG) with a message.
+int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, Layout* lay, std::string* why)
+{
+    if (dim != 2 && dim != 3) return *why = "dim must be 2 or 3", FAS_ERR_ARG;
+    if (dtype != FAS_F64 && dtype != FAS_F32) return *why = "dtype must be FAS_F64 or FAS_F32", FAS_ERR_ARG;
+    if (flags & ~(FAS_FLAG_VARIABLE_KAPPA | FAS_FLAG_MIXED_INNER)) return *why = "unknown flags", FAS_ERR_ARG;
+    if ((flags & FAS_FLAG_MIXED_INNER) && dtype != FAS_F32)
+        return *why = "FAS_FLAG_MIXED_INNER needs an FP32 grid", FAS_ERR_ARG;
+    if (coarsest < 2 || (coarsest & 1)) return *why = "coarsest must be even and >= 2", FAS_ERR_SHAPE;
+    int64_t nmin = n[0];
+    for (int a = 0; a < dim; ++a) {
+        if (n[a] < 1) return *why = "sizes must be positive", FAS_ERR_SHAPE;
+        if (n[a] < nmin) nmin = n[a];
+    }
+    if (nmin % coarsest) return *why = "shortest axis must be coarsest * 2^L", FAS_ERR_SHAPE;
+    int64_t ratio = nmin / coarsest;
+    int L = 0;
+    while (((int64_t)1 << L) < ratio) ++L;
+    if (((int64_t)1 << L) != ratio || L < 1) return *why = "shortest axis must be coarsest * 2^L, L >= 1", FAS_ERR_SHAPE;
+    if (L >= fas::kMaxLevels) return *why = "too many levels", FAS_ERR_SHAPE;
+    for (int a = 0; a < dim; ++a)
+        if (n[a] % ((int64_t)1 << L)) return *why = "every axis must be divisible by 2^L", FAS_ERR_SHAPE;
+    int64_t N0 = 1;
+    for (int a = 0; a < dim; ++a) N0 *= n[a];
+    if (N0 >= ((int64_t)1 << 31)) return *why = "grid too large (>= 2^31 cells)", FAS_ERR_SHAPE;
+    const size_t s = dtype == FAS_F64 ? 8 : 4;
+    lay->L = L;
+    size_t off = 0;
+    for (int l = 0; l <= L; ++l) {
+        int64_t Nl = 1;
+        for (int a = 0; a < 3; ++a) {
+            lay->n[l][a] = a < dim ? (int)(n[a] >> l) : 1;
+            Nl *= lay->n[l][a];
+        }
+        lay->u[l] = lay->f[l] = 0;
+        lay->x[l] = off;
+        off = align_up(off + Nl * s);
+        if (l >= 1) {
+            lay->u[l] = off;
+            off = align_up(off + Nl * s);
+            lay->f[l] = off;
+            off = align_up(off + Nl * s);
+        }
+        lay->kap[l] = 0;
+        const bool need_kap = (flags & FAS_FLAG_VARIABLE_KAPPA) && (l >= 1 || dtype == FAS_F32);
+        if (need_kap) {
+            lay->kap[l] = off;
+            off = align_up(off + Nl * s);
+        }
+    }
+    lay->mix_e = lay->mix_r = 0;
+    if (flags & FAS_FLAG_MIXED_INNER) {
+        lay->mix_e = off;
+        off = align_up(off + N0 * s);
+        lay->mix_r = off;
+        off = align_up(off + N0 * s);
+    }
+    lay->partials = off;
+    off = align_up(off + (fas::kPartials + 8) * sizeof(double));
+    lay->total = off;
+    return 0;
+}
+
+void check_grid(const fas_grid* g)
+{
+    if (!g) throw Error(FAS_ERR_ARG, "null grid");
+}
+
+void check_level(const fas_grid* g, int level, bool need_coarse)
+{
+    if (level < 0 || level > g->L || (need_coarse && level >= g->L))
+        throw Error(FAS_ERR_ARG, "level out of range");
+}
+
+// Operator coefficients for one call (Section 2.1: h_l = 2^l h).
+void set_coefs(fas_grid* g, double dt, double kappa, bool variable)
+{
+    if (!(dt > 0.0) || !isfinite(dt)) throw Error(FAS_ERR_ARG, "dt must be positive and finite");
+    if (!variable && (!(kappa > 0.0) || !isfinite(kappa))) throw Error(FAS_ERR_ARG, "kappa must be positive");
+    for (int l = 0; l <= g->L; ++l) {
+        const double hl = g->lev[l].h;
+        const double c = variable ? dt : dt * kappa;
+        fas::Coef& C = g->coef[l];
+        C.kd = c / (hl * hl);
+        for (int W = 0; W < 16; ++W) C.q[W] = 1.0 / (1.0 + C.kd * (double)W);
+        C.variable = variable;
+    }
+}
+
+// Cell-kappa hierarchy: level 0 is the caller's field (rounded to FP32 for an FP32
+// grid); level l+1 = R(level l).
+// Only level 0 is set up when coarse == false (callers that only evaluate the operator
+// on the finest level).
+void set_kappa(fas_grid* g, const void* kcell, bool source_is_f64, bool coarse = true)
+{
+    for (int l = 0; l <= g->L; ++l) g->lev[l].kap = nullptr;
+    if (!kcell) return;
+    if (!(g->flags & FAS_FLAG_VARIABLE_KAPPA))
+        throw Error(FAS_ERR_ARG, "cell kappa needs a grid created with FAS_FLAG_VARIABLE_KAPPA");
+    if (g->dtype == FAS_F32 && source_is_f64) {
+        g->lev[0].kap = g->lev[0].kap_slot;
+        fas::launch_cast_f32(g, g->lev[0].N, kcell, g->lev[0].kap);
+    } else {
+        g->lev[0].kap = const_cast<void*>(kcell);
+    }
+    if (!coarse) return;
+    for (int l = 0; l < g->L; ++l) {
+        g->lev[l + 1].kap = g->lev[l + 1].kap_slot;
+        fas::launch_restrict(g, l, g->lev[l].kap, g->lev[l + 1].kap);
+    }
+}
+
+double read_norm(fas_grid* g)
+{
+    if (!g->host) FAS_HIP_CHECK(hipHostMalloc((void**)&g->host, 64, hipHostMallocDefault));
+    FAS_HIP_CHECK(hipMemcpyAsync(g->host, g->partials + fas::kPartials, sizeof(double), hipMemcpyDeviceToHost,
+                                 g->stream));
+    FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
+    return sqrt(g->host[0]);
+}
+
+void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse)
+{
+    const int first = (g->dim + 1) & 1;
+    for (int s = 0; s < sweeps; ++s)
+        for (int ph = 0; ph < 2; ++ph) {
+            const int parity = ((ph == 0) != reverse) ? first : 1 - first;
+            fas::launch_smooth_phase(g, l, g->coef[l], g->lev[l].kap, f, u, parity);
+        }
+}
+
+// FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
+void vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev)
+{
+    if (l == g->L) {
+        smooth(g, l, f, u, g->nuc, rev);  // Remark 1: coarsest level smoothed, no direct solve
+        return;
+    }
+    smooth(g, l, f, u, pre, rev);
+    fas::Level& C = g->lev[l + 1];
+    // r = f - A u;  u_c = R u;  f_c = R r + A_c u_c
+    fas::launch_resid_restrict(g, l, g->coef[l], g->lev[l].kap, f, u, C.u, C.f);
+    fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
+    vcycle_level(g, l + 1, C.f, C.u, pre, post, rev);
+    // u += P(u_c - R u)
+    fas::launch_prolong_correct(g, l, C.u, u);
+    smooth(g, l, f, u, post, rev);
+}
+
+void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed)
+{
+    vcycle_level(g, 0, f, u, transposed ? nu2 : nu1, transposed ? nu1 : nu2, transposed);
+}
+
+void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1, int nu2, double tol)
+{
+    check_grid(g);
+    if (!rhs || !u) throw Error(FAS_ERR_ARG, "null rhs or u");
+    if (rhs == u) throw Error(FAS_ERR_ARG, "rhs and u must not alias");
+    if (nu1 < 0 || nu2 < 0 || nu1 + nu2 == 0) throw Error(FAS_ERR_ARG, "need nu1, nu2 >= 0 and nu1 + nu2 > 0");
+    if (!(tol >= 0.0)) throw Error(FAS_ERR_ARG, "tol must be >= 0");
+}
+
+int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const void* rhs, void* u, double tol,
+               int nu1, int nu2, bool transposed)
+{
+    check_solve_args(g, rhs, u, nu1, nu2, tol);
+    set_coefs(g, dt, kappa, kcell != nullptr);
+    set_kappa(g, kcell, g->dtype == FAS_F64);
+    memset(&g->stats, 0, sizeof(g->stats));
+    fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, nullptr);
+    const double nf = read_norm(g);
+    g->stats.rhs_norm = nf;
+    int status = FAS_NOT_CONVERGED;
+    int k;
+    for (k = 1; k <= g->kmax; ++k) {
+        vcycle_top(g, rhs, u, nu1, nu2, transposed);
+        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, u);
+        const double nr = read_norm(g);
+        const double rel = nf > 0.0 ? nr / nf : nr;
+        if (k <= 64) g->stats.rel_res[k - 1] = rel;
+        if (!isfinite(nr)) {
+            g->stats.cycles = k;
+            g->stats.status = FAS_ERR_NONFINITE;
+            throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
+        }
+        if (nr <= tol * nf || nr == 0.0) {
+            status = FAS_OK;
+            break;
+        }
+    }
+    g->stats.cycles = status == FAS_OK ? k : g->kmax;
+    g->stats.status = status;
+    if (status != FAS_OK) g_last_error = "not converged within kmax cycles";
+    return status;
+}
+
+int vcycle_impl(fas_grid* g, double dt, double kappa, const void* kcell, const void* rhs, void* u, int nu1, int nu2,
+                double* rel_res, bool transposed)
+{
+    check_solve_args(g, rhs, u, nu1, nu2, 0.0);
+    set_coefs(g, dt, kappa, kcell != nullptr);
+    set_kappa(g, kcell, g->dtype == FAS_F64);
+    vcycle_top(g, rhs, u, nu1, nu2, transposed);
+    if (rel_res) {
+        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, nullptr);
+        const double nf = read_norm(g);
+        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, u);
+        const double nr = read_norm(g);
+        *rel_res = nf > 0.0 ? nr / nf : nr;
+    }
+    return FAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fas_workspace_size(int dim, const int64_t n[3], int dtype, int coarsest, int flags)
+{
+    if (!n) return 0;
+    Layout lay;
+    std::string why;
+    if (plan(dim, n, dtype, coarsest, flags, &lay, &why)) return 0;
+    return lay.total;
+}
+
+int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, int flags, void* workspace,
+                    size_t ws_bytes, void* stream, fas_grid_t* out)
+{
+    return guarded([&]() -> int {
+        if (!out || !n) return fail(FAS_ERR_ARG, "null argument");
+        *out = nullptr;
+        if (!(h > 0.0) || !isfinite(h)) return fail(FAS_ERR_ARG, "h must be positive");
+        if (bc != FAS_BC_NEUMANN && bc != FAS_BC_DIRICHLET && bc != FAS_BC_PERIODIC)
+            return fail(FAS_ERR_ARG, "unknown boundary condition");
+        Layout lay;
+        std::string why;
+        int rc = plan(dim, n, dtype, coarsest, flags, &lay, &why);
+        if (rc) return fail(rc, why);
+        if (bc == FAS_BC_PERIODIC)
+            for (int a = 0; a < dim; ++a)
+                if (lay.n[lay.L][a] & 1) return fail(FAS_ERR_SHAPE, "periodic grids need even sizes on every level");
+        if (!workspace) return fail(FAS_ERR_ARG, "null workspace");
+        if ((uintptr_t)workspace % kAlign) return fail(FAS_ERR_ARG, "workspace must be 256-byte aligned");
+        if (ws_bytes < lay.total)
+            return fail(FAS_ERR_NOMEM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+        fas_grid* g = new fas_grid();
+        memset(g, 0, sizeof(*g));
+        g->dim = dim;
+        g->bc = bc;
+        g->dtype = dtype;
+        g->coarsest = coarsest;
+        g->flags = flags;
+        g->L = lay.L;
+        g->h = h;
+        for (int a = 0; a < 3; ++a) g->n[a] = a < dim ? n[a] : 1;
+        char* base = (char*)workspace;
+        for (int l = 0; l <= lay.L; ++l) {
+            fas::Level& Lv = g->lev[l];
+            Lv.N = 1;
+            for (int a = 0; a < 3; ++a) {
+                Lv.n[a] = lay.n[l][a];
+                Lv.N *= Lv.n[a];
+            }
+            Lv.h = h * (double)((int64_t)1 << l);
+            Lv.x = base + lay.x[l];
+            Lv.u = l ? base + lay.u[l] : nullptr;
+            Lv.f = l ? base + lay.f[l] : nullptr;
+            Lv.kap_slot = lay.kap[l] ? base + lay.kap[l] : nullptr;
+            Lv.kap = nullptr;
+        }
+        g->mix_e = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_e : nullptr;
+        g->mix_r = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_r : nullptr;
+        g->partials = (double*)(base + lay.partials);
+        g->stream = (hipStream_t)stream;
+        g->kmax = 100;
+        g->nuc = 2;
+        g->fused = 1;
+        g->host = nullptr;  // pinned scalar for norm read-back, allocated on first use
+        *out = g;
+        return FAS_OK;
+    });
+}
+
+int fas_grid_destroy(fas_grid_t g)
+{
+    if (!g) return FAS_OK;
+    if (g->host) (void)hipHostFree(g->host);
+    delete g;
+    return FAS_OK;
+}
+
+int fas_grid_set(fas_grid_t g, int option, double value)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        const int v = (int)value;
+        if ((double)v != value) return fail(FAS_ERR_ARG, "option value must be an integer");
+        switch (option) {
+            case FAS_OPT_KMAX:
+                if (v < 1) return fail(FAS_ERR_ARG, "kmax must be >= 1");
+                g->kmax = v;
+                return FAS_OK;
+            case FAS_OPT_COARSE_SWEEPS:
+                if (v < 1) return fail(FAS_ERR_ARG, "coarse sweeps must be >= 1");
+                g->nuc = v;
+                return FAS_OK;
+            case FAS_OPT_FUSED:
+                if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "fused must be 0 or 1");
+                g->fused = v;
+                return FAS_OK;
+        }
+        return fail(FAS_ERR_ARG, "unknown option");
+    });
+}
+
+int fas_set_stream(fas_grid_t g, void* stream)
+{
+    if (!g) return fail(FAS_ERR_ARG, "null grid");
+    g->stream = (hipStream_t)stream;
+    return FAS_OK;
+}
+
+int fas_grid_levels(fas_grid_t g) { return g ? g->L : fail(FAS_ERR_ARG, "null grid"); }
+
+int64_t fas_level_cells(fas_grid_t g, int level)
+{
+    if (!g || level < 0 || level > g->L) return fail(FAS_ERR_ARG, "bad grid or level");
+    return g->lev[level].N;
+}
+
+int fas_solve(fas_grid_t g, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u, double tol,
+              int nu1, int nu2)
+{
+    return guarded([&] { return solve_impl(g, dt, kappa, kappa_cell, rhs, u, tol, nu1, nu2, false); });
+}
+
+int fas_solve_transposed(fas_grid_t g, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u,
+                         double tol, int nu1, int nu2)
+{
+    return guarded([&] { return solve_impl(g, dt, kappa, kappa_cell, rhs, u, tol, nu1, nu2, true); });
+}
+
+int fas_vcycle(fas_grid_t g, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u, int nu1,
+               int nu2, double* rel_res)
+{
+    return guarded([&] { return vcycle_impl(g, dt, kappa, kappa_cell, rhs, u, nu1, nu2, rel_res, false); });
+}
+
+int fas_vcycle_transposed(fas_grid_t g, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u,
+                          int nu1, int nu2, double* rel_res)
+{
+    return guarded([&] { return vcycle_impl(g, dt, kappa, kappa_cell, rhs, u, nu1, nu2, rel_res, true); });
+}
+
+int fas_smooth(fas_grid_t g, int level, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u,
+               int sweeps, int reverse)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        check_level(g, level, false);
+        if (!rhs || !u || rhs == u || sweeps < 0) return fail(FAS_ERR_ARG, "bad smoother arguments");
+        if (kappa_cell && !(g->flags & FAS_FLAG_VARIABLE_KAPPA))
+            return fail(FAS_ERR_ARG, "cell kappa needs FAS_FLAG_VARIABLE_KAPPA");
+        set_coefs(g, dt, kappa, kappa_cell != nullptr);
+        const int first = (g->dim + 1) & 1;
+        for (int s = 0; s < sweeps; ++s)
+            for (int ph = 0; ph < 2; ++ph) {
+                const int parity = ((ph == 0) != (reverse != 0)) ? first : 1 - first;
+                fas::launch_smooth_phase(g, level, g->coef[level], kappa_cell, rhs, u, parity);
+            }
+        return FAS_OK;
+    });
+}
+
+int fas_residual(fas_grid_t g, int level, double dt, double kappa, const void* kappa_cell, const void* rhs,
+                 const void* u, void* r, double* norm2)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        check_level(g, level, false);
+        if (!rhs || !u || !r || r == u || r == rhs) return fail(FAS_ERR_ARG, "bad residual arguments");
+        if (kappa_cell && !(g->flags & FAS_FLAG_VARIABLE_KAPPA))
+            return fail(FAS_ERR_ARG, "cell kappa needs FAS_FLAG_VARIABLE_KAPPA");
+        set_coefs(g, dt, kappa, kappa_cell != nullptr);
+        fas::launch_residual(g, level, g->coef[level], kappa_cell, rhs, u, r);
+        if (norm2) {
+            fas::launch_resid_norm(g, level, g->coef[level], kappa_cell, r, nullptr);
+            *norm2 = read_norm(g);
+        }
+        return FAS_OK;
+    });
+}
+
+int fas_restrict(fas_grid_t g, int level, const void* fine, void* coarse)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        check_level(g, level, true);
+        if (!fine || !coarse || fine == coarse) return fail(FAS_ERR_ARG, "bad restriction arguments");
+        fas::launch_restrict(g, level, fine, coarse);
+        return FAS_OK;
+    });
+}
+
+int fas_prolong_add(fas_grid_t g, int level, const void* c_new, const void* c_old, void* fine)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        check_level(g, level, true);
+        if (!c_new || !c_old || !fine) return fail(FAS_ERR_ARG, "bad prolongation arguments");
+        fas::launch_prolong_add(g, level, c_new, c_old, fine);
+        return FAS_OK;
+    });
+}
+
+int fas_kappa_grad(fas_grid_t g, double dt, const void* kappa_cell, const void* mu, const void* u, void* gkappa)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        if (g->dtype != FAS_F64) return fail(FAS_ERR_ARG, "fas_kappa_grad needs an FP64 grid");
+        if (!kappa_cell || !mu || !u || !gkappa) return fail(FAS_ERR_ARG, "null argument");
+        if (gkappa == mu || gkappa == u || gkappa == kappa_cell) return fail(FAS_ERR_ARG, "gkappa must not alias");
+        set_coefs(g, dt, 1.0, true);
+        fas::launch_kappa_grad(g, g->coef[0], kappa_cell, mu, u, gkappa);
+        return FAS_OK;
+    });
+}
+
+int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, const void* kappa_cell, const void* rhs,
+                    void* u, double tol, int nu1, int nu2, int inner)
+{
+    return guarded([&]() -> int {
+        check_solve_args(g64, rhs, u, nu1, nu2, tol);
+        check_grid(g32);
+        if (g64->dtype != FAS_F64 || g32->dtype != FAS_F32 || !(g32->flags & FAS_FLAG_MIXED_INNER))
+            return fail(FAS_ERR_ARG, "need an FP64 grid and an FP32 grid created with FAS_FLAG_MIXED_INNER");
+        if (g64->dim != g32->dim || g64->bc != g32->bc || g64->h != g32->h || g64->L != g32->L)
+            return fail(FAS_ERR_ARG, "the two grids must describe the same hierarchy");
+        for (int a = 0; a < 3; ++a)
+            if (g64->n[a] != g32->n[a]) return fail(FAS_ERR_ARG, "the two grids must have the same shape");
+        if (inner < 1) return fail(FAS_ERR_ARG, "inner must be >= 1");
+        hipStream_t saved = g32->stream;
+        g32->stream = g64->stream;
+        struct Restore {
+            fas_grid* g;
+            hipStream_t s;
+            ~Restore() { g->stream = s; }
+        } restore{g32, saved};
+        set_coefs(g64, dt, kappa, kappa_cell != nullptr);
+        set_kappa(g64, kappa_cell, true, false);
+        set_coefs(g32, dt, kappa, kappa_cell != nullptr);
+        set_kappa(g32, kappa_cell, true);
+        memset(&g64->stats, 0, sizeof(g64->stats));
+        fas::launch_resid_norm(g64, 0, g64->coef[0], g64->lev[0].kap, rhs, nullptr);
+        const double nf = read_norm(g64);
+        g64->stats.rhs_norm = nf;
+        int status, it = 0;
+        for (;;) {
+            fas::launch_resid_norm(g64, 0, g64->coef[0], g64->lev[0].kap, rhs, u);
+            const double rho = read_norm(g64);
+            if (it < 64) g64->stats.rel_res[it] = nf > 0.0 ? rho / nf : rho;
+            if (!isfinite(rho)) throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
+            if (rho <= tol * nf || rho == 0.0) {
+                status = FAS_OK;
+                break;
+            }
+            if (it == g64->kmax) {
+                status = FAS_NOT_CONVERGED;
+                break;
+            }
+            fas::launch_scale_cast(g64, g64->coef[0], g64->lev[0].kap, rhs, u, rho, g32->mix_r, g32->mix_e);
+            for (int m = 0; m < inner; ++m) vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
+            fas::launch_update_mixed(g64, rho, g32->mix_e, u);
+            ++it;
+        }
+        g64->stats.cycles = it;
+        g64->stats.status = status;
+        if (status != FAS_OK) g_last_error = "not converged within kmax outer iterations";
+        return status;
+    });
+}
+
+int fas_get_stats(fas_grid_t g, fas_stats_t* out)
+{
+    if (!g || !out) return fail(FAS_ERR_ARG, "null argument");
+    *out = g->stats;
+    return FAS_OK;
+}
+
+const char* fas_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Host-side internals of libfas: the grid plan and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "../../include/fas.h"
+
+namespace fas {
+
+constexpr int kMaxLevels = 24;
+constexpr int kPartials = 2048;  // blocks of a norm reduction (fixed: deterministic order)
+
+// Error carried to the C ABI boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define FAS_HIP_CHECK(expr)                                                                         \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            throw ::fas::Error(FAS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+struct Level {
+    int n[3];      // cells per axis, n[2] = 1 in 2D
+    int64_t N;
+    double h;      // h * 2^l
+    void* u;       // level arrays (level 0: caller's, set per call)
+    void* f;
+    void* x;       // second buffer of the same size (out-of-place kernels)
+    void* kap;     // active cell kappa of this level for the current call, or nullptr
+    void* kap_slot;  // workspace storage for kappa of this level (nullptr if none)
+};
+
+// Per-call operator coefficients of one level, computed on the host in double:
+//   kd = dt*kappa/h_l^2 (constant kappa) or dt/h_l^2 (cell kappa); q[W] = 1/(1 + kd W)
+struct Coef {
+    double kd;
+    double q[16];
+    bool variable;
+};
+
+}  // namespace fas
+
+struct fas_grid {
+    int dim, bc, dtype, coarsest, flags, L;
+    int64_t n[3];
+    double h;
+    fas::Level lev[fas::kMaxLevels];
+    hipStream_t stream;
+    double* partials;    // kPartials doubles + result slots, device
+    double* host;        // pinned host scalars
+    void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
+    void* mix_r;
+    int kmax, nuc, fused;
+    fas::Coef coef[fas::kMaxLevels];
+    fas_stats_t stats;
+    size_t elem() const { return dtype == FAS_F64 ? 8 : 4; }
+};
+
+namespace fas {
+
+// ---- launchers (kernels_basic.hip) ----------------------------------------------------
+// All act on level `l` of grid g with coefficients c, on g->stream.
+void launch_smooth_phase(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, void* u,
+                         int parity);
+void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u,
+                     void* r);
+// Partial sums of r^2 (r = f - A u) into g->partials then a fixed-order total into
+// g->partials[kPartials]; rhs-only mode (u == nullptr) sums f^2.
+void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u);
+void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
+                           const void* u, void* uc, void* rc);
+void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc);
+void launch_prolong_correct(const fas_grid* g, int l, const void* uc, void* u);
+void launch_restrict(const fas_grid* g, int l, const void* fine, void* coarse);
+void launch_prolong_add(const fas_grid* g, int l, const void* cnew, const void* cold, void* fine);
+void launch_kappa_grad(const fas_grid* g, const Coef& c, const void* kap, const void* mu, const void* u,
+                       void* gk);
+// Mixed precision: r32 = fp32((f - A u)/rho), e = 0 (FP64 grid g, FP32 outputs).
+void launch_scale_cast(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u,
+                       double rho, void* r32, void* e32);
+void launch_update_mixed(const fas_grid* g, double rho, const void* e32, void* u);
+void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst32);
+
+}  // namespace fas

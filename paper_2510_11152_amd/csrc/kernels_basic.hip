@@ -1,0 +1,446 @@
+// Per-level kernels of the V-cycle, one thread per cell (or per coarse cell):
+// colour-phase smoother, residual, fused residual + restriction, FAS coarse right-hand
+// side, prolongation + correction, deterministic norms, kappa gradient and the
+// mixed-precision helpers.  These serve every level and every configuration; the fused
+// tile kernels replace them on large levels where they apply.
+#include <hip/hip_runtime.h>
+
+#include "fas_device.h"
+#include "fas_internal.h"
+
+namespace fas {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T>
+Op<T> make_op(const fas_grid* g, int l, const Coef& c, const void* kap)
+{
+    Op<T> op;
+    op.n0 = g->lev[l].n[0];
+    op.n1 = g->lev[l].n[1];
+    op.n2 = g->lev[l].n[2];
+    op.bc = g->bc;
+    op.k = (T)c.kd;
+    for (int W = 0; W < 16; ++W) op.q[W] = (T)c.q[W];
+    op.kap = (const T*)kap;
+    return op;
+}
+
+inline unsigned blocks_for(int64_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
+
+inline void check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+// --------------------------------------------------------------------------- smoother
+// One colour phase: every cell whose 0-based index sum has `parity`; one thread per
+// pair of x-neighbours (exactly one of the two has the parity).
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_smooth_phase(Op<T> op, const T* __restrict__ f, T* u, int parity)
+{
+    const int half = (op.n0 + 1) >> 1;
+    const int64_t total = (int64_t)half * op.n1 * op.n2;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= total) return;
+    const int t = (int)(tid % half);
+    const int64_t rest = tid / half;
+    const int j = (int)(rest % op.n1);
+    const int l = (int)(rest / op.n1);
+    const int i = 2 * t + ((parity + j + l) & 1);
+    if (i >= op.n0) return;
+    Nbhd<T, DIM> s;
+    gather<T, DIM, KV>(op, u, i, j, l, s);
+    const int64_t p = cell_index(op.n0, op.n1, i, j, l);
+    u[p] = gs_value<T, DIM, KV>(op, s, f[p]);
+}
+
+// --------------------------------------------------------------------------- residual
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_residual(Op<T> op, const T* __restrict__ f, const T* __restrict__ u,
+                                                     T* __restrict__ r)
+{
+    const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % op.n0);
+    const int j = (int)((p / op.n0) % op.n1);
+    const int l = (int)(p / ((int64_t)op.n0 * op.n1));
+    Nbhd<T, DIM> s;
+    gather<T, DIM, KV>(op, u, i, j, l, s);
+    r[p] = f[p] - apply_value<T, DIM, KV>(op, s, u[p]);
+}
+
+// Fixed-order block reduction of per-thread double sums into out[blockIdx.x].
+__device__ void block_sum_store(double v, double* out)
+{
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Sum of r^2 (r = f - A u), or of f^2 when u == nullptr; grid-stride with a fixed grid.
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_resid_norm(Op<T> op, const T* __restrict__ f,
+                                                       const T* __restrict__ u, double* __restrict__ partials)
+{
+    const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        T r;
+        if (u) {
+            const int i = (int)(p % op.n0);
+            const int j = (int)((p / op.n0) % op.n1);
+            const int l = (int)(p / ((int64_t)op.n0 * op.n1));
+            Nbhd<T, DIM> s;
+            gather<T, DIM, KV>(op, u, i, j, l, s);
+            r = f[p] - apply_value<T, DIM, KV>(op, s, u[p]);
+        } else {
+            r = f[p];
+        }
+        acc += (double)r * (double)r;
+    }
+    block_sum_store(acc, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(double* partials, int count)
+{
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < count; b += kBlock) acc += partials[b];
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[kPartials] = red[0];
+}
+
+// ----------------------------------------------------------- residual + restriction
+// One thread per coarse cell: uc = R u, rc = R (f - A u) over the 2^d children.
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(Op<T> op, const T* __restrict__ f,
+                                                           const T* __restrict__ u, T* __restrict__ uc,
+                                                           T* __restrict__ rc)
+{
+    const int m0 = op.n0 >> 1, m1 = op.n1 >> 1, m2 = DIM == 3 ? op.n2 >> 1 : 1;
+    const int64_t Nc = (int64_t)m0 * m1 * m2;
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= Nc) return;
+    const int I = (int)(P % m0);
+    const int J = (int)((P / m0) % m1);
+    const int K = (int)(P / ((int64_t)m0 * m1));
+    T uu[8], rr[8];
+#pragma unroll
+    for (int c = 0; c < (DIM == 3 ? 8 : 4); ++c) {
+        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), l = DIM == 3 ? 2 * K + (c >> 2) : 0;
+        const int64_t p = cell_index(op.n0, op.n1, i, j, l);
+        Nbhd<T, DIM> s;
+        gather<T, DIM, KV>(op, u, i, j, l, s);
+        uu[c] = u[p];
+        rr[c] = f[p] - apply_value<T, DIM, KV>(op, s, uu[c]);
+    }
+    if constexpr (DIM == 2) {
+        uc[P] = restrict4(uu[0], uu[1], uu[2], uu[3]);
+        rc[P] = restrict4(rr[0], rr[1], rr[2], rr[3]);
+    } else {
+        uc[P] = restrict8(uu[0], uu[1], uu[2], uu[3], uu[4], uu[5], uu[6], uu[7]);
+        rc[P] = restrict8(rr[0], rr[1], rr[2], rr[3], rr[4], rr[5], rr[6], rr[7]);
+    }
+}
+
+// FAS coarse right-hand side in place: fc = rc + Ac(uc) (Alg. 1 coarse source term; fc
+// holds rc on entry, the paper's memory reuse).
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs(Op<T> op, const T* __restrict__ uc, T* __restrict__ fc)
+{
+    const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % op.n0);
+    const int j = (int)((p / op.n0) % op.n1);
+    const int l = (int)(p / ((int64_t)op.n0 * op.n1));
+    Nbhd<T, DIM> s;
+    gather<T, DIM, KV>(op, uc, i, j, l, s);
+    fc[p] = fc[p] + apply_value<T, DIM, KV>(op, s, uc[p]);
+}
+
+// ----------------------------------------------------------- transfer operators
+template <typename T, int DIM>
+__device__ __forceinline__ T restrict_at(const T* __restrict__ x, int n0, int n1, int I, int J, int K)
+{
+    const int i = 2 * I, j = 2 * J;
+    if constexpr (DIM == 2) {
+        return restrict4(x[cell_index(n0, n1, i, j, 0)], x[cell_index(n0, n1, i + 1, j, 0)],
+                         x[cell_index(n0, n1, i, j + 1, 0)], x[cell_index(n0, n1, i + 1, j + 1, 0)]);
+    } else {
+        const int l = 2 * K;
+        return restrict8(x[cell_index(n0, n1, i, j, l)], x[cell_index(n0, n1, i + 1, j, l)],
+                         x[cell_index(n0, n1, i, j + 1, l)], x[cell_index(n0, n1, i + 1, j + 1, l)],
+                         x[cell_index(n0, n1, i, j, l + 1)], x[cell_index(n0, n1, i + 1, j, l + 1)],
+                         x[cell_index(n0, n1, i, j + 1, l + 1)], x[cell_index(n0, n1, i + 1, j + 1, l + 1)]);
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_restrict(int n0, int n1, int n2, const T* __restrict__ fine,
+                                                     T* __restrict__ coarse)
+{
+    const int m0 = n0 >> 1, m1 = n1 >> 1, m2 = DIM == 3 ? n2 >> 1 : 1;
+    const int64_t Nc = (int64_t)m0 * m1 * m2;
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= Nc) return;
+    const int I = (int)(P % m0);
+    const int J = (int)((P / m0) % m1);
+    const int K = (int)(P / ((int64_t)m0 * m1));
+    coarse[P] = restrict_at<T, DIM>(fine, n0, n1, I, J, K);
+}
+
+// u += P(uc - R u): the old coarse value R u is recomputed from the unchanged fine cells.
+// With cold != nullptr the old coarse value is read from cold instead.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong(int n0, int n1, int n2, const T* __restrict__ uc,
+                                                    const T* __restrict__ cold, T* __restrict__ u)
+{
+    const int m0 = n0 >> 1, m1 = n1 >> 1, m2 = DIM == 3 ? n2 >> 1 : 1;
+    const int64_t Nc = (int64_t)m0 * m1 * m2;
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= Nc) return;
+    const int I = (int)(P % m0);
+    const int J = (int)((P / m0) % m1);
+    const int K = (int)(P / ((int64_t)m0 * m1));
+    const T old = cold ? cold[P] : restrict_at<T, DIM>(u, n0, n1, I, J, K);
+    const T c = uc[P] - old;
+#pragma unroll
+    for (int ch = 0; ch < (DIM == 3 ? 8 : 4); ++ch) {
+        const int64_t p =
+            cell_index(n0, n1, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), DIM == 3 ? 2 * K + (ch >> 2) : 0);
+        u[p] = u[p] + c;
+    }
+}
+
+// ----------------------------------------------------------- kappa gradient (FP64)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_kappa_grad(Op<double> op, const double* __restrict__ mu,
+                                                       const double* __restrict__ u, double* __restrict__ g)
+{
+    const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int c[3] = {(int)(p % op.n0), (int)((p / op.n0) % op.n1), (int)(p / ((int64_t)op.n0 * op.n1))};
+    const int n[3] = {op.n0, op.n1, op.n2};
+    const double* kap = op.kap;
+    double t[6];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            int d[3] = {c[0], c[1], c[2]};
+            d[a] += side ? 1 : -1;
+            bool in = d[a] >= 0 && d[a] < n[a];
+            if (!in && op.bc == BC_PERIODIC) {
+                d[a] = d[a] < 0 ? n[a] - 1 : 0;
+                in = true;
+            }
+            double val;
+            if (in) {
+                const int64_t q = cell_index(op.n0, op.n1, d[0], d[1], d[2]);
+                const double s = kap[p] + kap[q];
+                const double dw = ((2.0 * kap[q]) * kap[q]) / (s * s);
+                val = dw * ((mu[p] - mu[q]) * (u[p] - u[q]));
+            } else {
+                val = op.bc == BC_DIRICHLET ? (2.0 * mu[p]) * u[p] : 0.0;
+            }
+            t[2 * a + side] = val;
+        }
+    }
+    double S = (t[0] + t[1]) + (t[2] + t[3]);
+    if constexpr (DIM == 3) S = S + (t[4] + t[5]);
+    g[p] = g[p] - op.k * S;
+}
+
+// ----------------------------------------------------------- mixed precision helpers
+template <int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_scale_cast(Op<double> op, const double* __restrict__ f,
+                                                       const double* __restrict__ u, double rho,
+                                                       float* __restrict__ r32, float* __restrict__ e32)
+{
+    const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % op.n0);
+    const int j = (int)((p / op.n0) % op.n1);
+    const int l = (int)(p / ((int64_t)op.n0 * op.n1));
+    Nbhd<double, DIM> s;
+    gather<double, DIM, KV>(op, u, i, j, l, s);
+    const double r = f[p] - apply_value<double, DIM, KV>(op, s, u[p]);
+    r32[p] = (float)(r / rho);
+    e32[p] = 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_mixed(int64_t N, double rho, const float* __restrict__ e,
+                                                         double* __restrict__ u)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    u[p] = u[p] + rho * (double)e[p];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t N, const double* __restrict__ src,
+                                                     float* __restrict__ dst)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    dst[p] = (float)src[p];
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------- dispatch
+#define FAS_DISPATCH(g, kap, BODY)                                                        \
+    do {                                                                                  \
+        const bool kv_ = (kap) != nullptr;                                                \
+        if ((g)->dtype == FAS_F64) {                                                      \
+            using T = double;                                                             \
+            if ((g)->dim == 2) {                                                          \
+                constexpr int D = 2;                                                      \
+                if (kv_) { constexpr bool KV = true; BODY; } else { constexpr bool KV = false; BODY; } \
+            } else {                                                                      \
+                constexpr int D = 3;                                                      \
+                if (kv_) { constexpr bool KV = true; BODY; } else { constexpr bool KV = false; BODY; } \
+            }                                                                             \
+        } else {                                                                          \
+            using T = float;                                                              \
+            if ((g)->dim == 2) {                                                          \
+                constexpr int D = 2;                                                      \
+                if (kv_) { constexpr bool KV = true; BODY; } else { constexpr bool KV = false; BODY; } \
+            } else {                                                                      \
+                constexpr int D = 3;                                                      \
+                if (kv_) { constexpr bool KV = true; BODY; } else { constexpr bool KV = false; BODY; } \
+            }                                                                             \
+        }                                                                                 \
+    } while (0)
+
+void launch_smooth_phase(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, void* u,
+                         int parity)
+{
+    const Level& L = g->lev[l];
+    const int64_t work = (int64_t)((L.n[0] + 1) / 2) * L.n[1] * L.n[2];
+    FAS_DISPATCH(g, kap, (k_smooth_phase<T, D, KV><<<blocks_for(work), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (T*)u, parity)));
+    check_launch();
+}
+
+void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u,
+                     void* r)
+{
+    FAS_DISPATCH(g, kap, (k_residual<T, D, KV><<<blocks_for(g->lev[l].N), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, (T*)r)));
+    check_launch();
+}
+
+void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u)
+{
+    unsigned nb = blocks_for(g->lev[l].N);
+    if (nb > (unsigned)kPartials) nb = kPartials;
+    FAS_DISPATCH(g, kap, (k_resid_norm<T, D, KV><<<nb, kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, g->partials)));
+    check_launch();
+    k_sum_partials<<<1, kBlock, 0, g->stream>>>(g->partials, (int)nb);
+    check_launch();
+}
+
+void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
+                           const void* u, void* uc, void* rc)
+{
+    FAS_DISPATCH(g, kap, (k_resid_restrict<T, D, KV><<<blocks_for(g->lev[l + 1].N), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, (T*)uc, (T*)rc)));
+    check_launch();
+}
+
+void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc)
+{
+    FAS_DISPATCH(g, kapc, (k_coarse_rhs<T, D, KV><<<blocks_for(g->lev[lc].N), kBlock, 0, g->stream>>>(
+                              make_op<T>(g, lc, c, kapc), (const T*)uc, (T*)fc)));
+    check_launch();
+}
+
+void launch_prolong_correct(const fas_grid* g, int l, const void* uc, void* u)
+{
+    launch_prolong_add(g, l, uc, nullptr, u);
+}
+
+void launch_prolong_add(const fas_grid* g, int l, const void* cnew, const void* cold, void* fine)
+{
+    const Level& L = g->lev[l];
+    const unsigned nb = blocks_for(g->lev[l + 1].N);
+    FAS_DISPATCH(g, (const void*)nullptr, (k_prolong<T, D><<<nb, kBlock, 0, g->stream>>>(
+                                              L.n[0], L.n[1], L.n[2], (const T*)cnew, (const T*)cold, (T*)fine)));
+    check_launch();
+}
+
+void launch_restrict(const fas_grid* g, int l, const void* fine, void* coarse)
+{
+    const Level& L = g->lev[l];
+    const unsigned nb = blocks_for(g->lev[l + 1].N);
+    FAS_DISPATCH(g, (const void*)nullptr, (k_restrict<T, D><<<nb, kBlock, 0, g->stream>>>(
+                                              L.n[0], L.n[1], L.n[2], (const T*)fine, (T*)coarse)));
+    check_launch();
+}
+
+void launch_kappa_grad(const fas_grid* g, const Coef& c, const void* kap, const void* mu, const void* u, void* gk)
+{
+    const Op<double> op = make_op<double>(g, 0, c, kap);
+    const unsigned nb = blocks_for(g->lev[0].N);
+    if (g->dim == 2)
+        k_kappa_grad<2><<<nb, kBlock, 0, g->stream>>>(op, (const double*)mu, (const double*)u, (double*)gk);
+    else
+        k_kappa_grad<3><<<nb, kBlock, 0, g->stream>>>(op, (const double*)mu, (const double*)u, (double*)gk);
+    check_launch();
+}
+
+void launch_scale_cast(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u, double rho,
+                       void* r32, void* e32)
+{
+    const Op<double> op = make_op<double>(g, 0, c, kap);
+    const unsigned nb = blocks_for(g->lev[0].N);
+    const bool kv = kap != nullptr;
+    auto F = (const double*)f;
+    auto U = (const double*)u;
+    if (g->dim == 2) {
+        if (kv)
+            k_scale_cast<2, true><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
+        else
+            k_scale_cast<2, false><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
+    } else {
+        if (kv)
+            k_scale_cast<3, true><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
+        else
+            k_scale_cast<3, false><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
+    }
+    check_launch();
+}
+
+void launch_update_mixed(const fas_grid* g, double rho, const void* e32, void* u)
+{
+    const int64_t N = g->lev[0].N;
+    k_update_mixed<<<blocks_for(N), kBlock, 0, g->stream>>>(N, rho, (const float*)e32, (double*)u);
+    check_launch();
+}
+
+void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst32)
+{
+    k_cast_f32<<<blocks_for(N), kBlock, 0, g->stream>>>(N, (const double*)src64, (float*)dst32);
+    check_launch();
+}
+
+}  // namespace fas

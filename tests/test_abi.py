@@ -1,0 +1,102 @@
+"""The C ABI library loads and exports every entry point include/fas.h declares, and
+its host-side argument checks report the documented status codes without touching a
+GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fas.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(fas_\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2510_11152_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libfas.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ("fas_solve", "fas_vcycle", "fas_smooth", "fas_residual", "fas_restrict", "fas_prolong_add",
+                 "fas_solve_mixed", "fas_kappa_grad", "fas_solve_transposed", "fas_last_error"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2510_11152_amd import _lib
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, "binding lacks " + name
+
+
+def _n3(*n):
+    return (ctypes.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+
+
+def test_workspace_size_shape_rules(lib):
+    from paper_2510_11152_amd import _lib as F
+    assert lib.fas_workspace_size(2, _n3(256, 256), F.FAS_F64, 4, 0) > 2 * 256 * 256 * 8 // 4
+    assert lib.fas_workspace_size(2, _n3(250, 256), F.FAS_F64, 4, 0) == 0   # not coarsest * 2^L
+    assert lib.fas_workspace_size(2, _n3(4, 4), F.FAS_F64, 4, 0) == 0       # L = 0
+    assert lib.fas_workspace_size(2, _n3(64, 64), F.FAS_F64, 3, 0) == 0     # odd coarsest
+    assert lib.fas_workspace_size(4, _n3(64, 64), F.FAS_F64, 4, 0) == 0     # bad dim
+    big = lib.fas_workspace_size(3, _n3(64, 64, 64), F.FAS_F64, 4, F.FAS_FLAG_VARIABLE_KAPPA)
+    small = lib.fas_workspace_size(3, _n3(64, 64, 64), F.FAS_F64, 4, 0)
+    assert big > small
+    assert lib.fas_workspace_size(2, _n3(64, 64), F.FAS_F32, 4, 0) < lib.fas_workspace_size(2, _n3(64, 64), F.FAS_F64, 4, 0)
+
+
+def test_create_errors_without_gpu(lib):
+    from paper_2510_11152_amd import _lib as F
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails first
+    n = _n3(64, 64)
+    need = lib.fas_workspace_size(2, n, F.FAS_F64, 4, 0)
+    assert lib.fas_grid_create(2, _n3(60, 64), 1 / 64, 0, F.FAS_F64, 4, 0, fake, need, None, ctypes.byref(out)) == F.FAS_ERR_SHAPE
+    assert lib.fas_grid_create(2, n, 1 / 64, 0, F.FAS_F64, 4, 0, fake, need - 1, None, ctypes.byref(out)) == F.FAS_ERR_NOMEM
+    assert b"too small" in lib.fas_last_error()
+    assert lib.fas_grid_create(2, n, 1 / 64, 7, F.FAS_F64, 4, 0, fake, need, None, ctypes.byref(out)) == F.FAS_ERR_ARG
+    assert lib.fas_grid_create(2, n, -1.0, 0, F.FAS_F64, 4, 0, fake, need, None, ctypes.byref(out)) == F.FAS_ERR_ARG
+    assert lib.fas_grid_create(2, n, 1 / 64, 0, F.FAS_F64, 4, 0, ctypes.c_void_p(4096 + 8), need, None,
+                               ctypes.byref(out)) == F.FAS_ERR_ARG  # misaligned
+    assert lib.fas_grid_create(2, _n3(6, 6), 1 / 6, 2, F.FAS_F64, 2, 0, fake, 1 << 20, None,
+                               ctypes.byref(out)) == F.FAS_ERR_SHAPE  # periodic odd coarsest level
+
+
+def test_solve_argument_errors_without_gpu(lib):
+    """A valid plan over a fake workspace: the calls below are rejected by host checks
+    before anything is enqueued."""
+    from paper_2510_11152_amd import _lib as F
+    out = ctypes.c_void_p()
+    n = _n3(64, 64)
+    need = lib.fas_workspace_size(2, n, F.FAS_F64, 4, 0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.fas_grid_create(2, n, 1 / 64, 0, F.FAS_F64, 4, 0, fake, need, None, ctypes.byref(out)) == F.FAS_OK
+    g = out
+    try:
+        assert lib.fas_grid_levels(g) == 4
+        assert lib.fas_level_cells(g, 4) == 16
+        buf = ctypes.c_void_p(1 << 22)
+        assert lib.fas_solve(g, 1e-3, 1.0, None, buf, buf, 1e-10, 2, 2) == F.FAS_ERR_ARG   # rhs aliases u
+        assert b"alias" in lib.fas_last_error()
+        assert lib.fas_solve(g, 1e-3, 1.0, None, None, buf, 1e-10, 2, 2) == F.FAS_ERR_ARG
+        assert lib.fas_solve(g, -1.0, 1.0, None, ctypes.c_void_p(1 << 23), buf, 1e-10, 2, 2) == F.FAS_ERR_ARG
+        assert lib.fas_solve(g, 1e-3, 1.0, ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 23), buf, 1e-10, 2, 2) == F.FAS_ERR_ARG  # no kappa storage
+        assert lib.fas_solve(g, 1e-3, 1.0, None, ctypes.c_void_p(1 << 23), buf, 1e-10, 0, 0) == F.FAS_ERR_ARG
+        assert lib.fas_grid_set(g, F.FAS_OPT_KMAX, 0) == F.FAS_ERR_ARG
+        assert lib.fas_grid_set(g, F.FAS_OPT_KMAX, 7) == F.FAS_OK
+        assert lib.fas_grid_set(g, 99, 1) == F.FAS_ERR_ARG
+        assert lib.fas_restrict(g, 4, buf, ctypes.c_void_p(1 << 23)) == F.FAS_ERR_ARG     # no coarser level
+        assert lib.fas_kappa_grad(g, 1e-3, None, buf, buf, buf) == F.FAS_ERR_ARG
+    finally:
+        assert lib.fas_grid_destroy(g) == F.FAS_OK

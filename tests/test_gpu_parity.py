@@ -1,0 +1,194 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on the same
+seeded inputs.  Integer-exact structure and identical per-point evaluation trees make
+every iterate bit-identical; only reductions (norms) may differ in the last bits, so
+solve-level comparisons allow the cycle count to differ by one."""
+import numpy as np
+import pytest
+import torch
+
+import fas_inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+TD = {np.float64: torch.float64, np.float32: torch.float32}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def grid_for(P, dtype, variable=False, mixed=False):
+    from paper_2510_11152_amd import Grid
+    return Grid(P.n, P.h, bc=P.bc, dtype=TD[dtype], coarsest=P.coarsest, variable_kappa=variable,
+                mixed_inner=mixed).set(coarse_sweeps=P.nuc)
+
+
+# (n, coarsest): square, rectangular, several tiles with a ragged remainder, 3D
+SHAPES = [((64, 64), 4), ((96, 64), 4), ((72, 48), 6), ((256, 256), 4), ((16, 16, 16), 4), ((32, 24, 16), 4)]
+BCS = ["neumann", "dirichlet", "periodic"]
+
+
+def _problem(n, coarsest, bc, dt=0.37, kappa=1.3, nuc=2):
+    return O.Problem(n=n, h=1.0 / n[0], dt=dt, kappa=kappa, bc=bc, coarsest=coarsest, nuc=nuc)
+
+
+def _kap_levels(P, kap, dtype, upto):
+    ks = [kap.astype(dtype)]
+    for l in range(upto):
+        ks.append(O.restrict(P, l, ks[-1]))
+    return ks
+
+
+def _two_colourable(n, coarsest, bc):
+    """Periodic grids need even sizes on every level (the library rejects the rest)."""
+    if bc != "periodic":
+        return True
+    L = (min(n) // coarsest).bit_length() - 1
+    return all((m >> L) % 2 == 0 for m in n)
+
+
+SMOOTH_CASES = [(n, c, bc) for n, c in SHAPES for bc in BCS if _two_colourable(n, c, bc)]
+
+
+@pytest.mark.parametrize("n,coarsest,bc", SMOOTH_CASES)
+@pytest.mark.parametrize("variable", [False, True])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_smooth_residual_bitwise(n, coarsest, bc, variable, dtype):
+    P = _problem(n, coarsest, bc)
+    g = grid_for(P, dtype, variable)
+    kap = np.exp(0.5 * I.random_field(P.shape(), 3)) if variable else None
+    ks = _kap_levels(P, kap, dtype, 1) if variable else [None, None]
+    for lev in (0, 1):
+        f = I.random_field(P.shape(lev), 10 + lev).astype(dtype)
+        u = I.random_field(P.shape(lev), 20 + lev).astype(dtype)
+        for reverse in (False, True):
+            uo = u.copy()
+            O.smooth(P, lev, f, uo, 2, reverse=reverse, kap=ks[lev])
+            ug = dev(u)
+            g.smooth(lev, dev(f), ug, P.dt, P.kappa, None if ks[lev] is None else dev(ks[lev]), sweeps=2,
+                     reverse=reverse)
+            assert np.array_equal(host(ug), uo), (lev, reverse)
+        ro = O.residual(P, lev, f, u, kap=ks[lev])
+        rg = g.residual(lev, dev(f), dev(u), P.dt, P.kappa, None if ks[lev] is None else dev(ks[lev]))
+        assert np.array_equal(host(rg), ro)
+
+
+@pytest.mark.parametrize("n,coarsest", SHAPES)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_restrict_prolong_bitwise(n, coarsest, dtype):
+    P = _problem(n, coarsest, "neumann")
+    g = grid_for(P, dtype)
+    x = I.random_field(P.shape(0), 1).astype(dtype)
+    c_new = I.random_field(P.shape(1), 2).astype(dtype)
+    c_old = I.random_field(P.shape(1), 3).astype(dtype)
+    assert np.array_equal(host(g.restrict(0, dev(x))), O.restrict(P, 0, x))
+    fo = x.copy()
+    O.prolong_add(P, 0, c_new, c_old, fo)
+    fg = dev(x)
+    g.prolong_add(0, dev(c_new), dev(c_old), fg)
+    assert np.array_equal(host(fg), fo)
+
+
+VC_CASES = [((64, 64), 4, "neumann"), ((96, 64), 4, "dirichlet"), ((72, 48), 6, "neumann"), ((96, 64), 4, "periodic"),
+            ((256, 256), 4, "neumann"), ((16, 16, 16), 4, "neumann"), ((32, 24, 16), 4, "dirichlet"),
+            ((16, 16, 16), 2, "periodic")]
+
+
+@pytest.mark.parametrize("n,coarsest,bc", VC_CASES)
+@pytest.mark.parametrize("variable", [False, True])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("transposed", [False, True])
+def test_vcycle_iterates_bitwise(n, coarsest, bc, variable, dtype, transposed):
+    P = _problem(n, coarsest, bc, dt=0.05, kappa=0.9, nuc=3)
+    g = grid_for(P, dtype, variable)
+    kap = np.exp(0.5 * I.random_field(P.shape(), 4)).astype(dtype) if variable else None
+    f = I.random_field(P.shape(), 5).astype(dtype)
+    u = I.random_field(P.shape(), 6).astype(dtype)
+    ug = dev(u)
+    fg = dev(f)
+    kg = None if kap is None else dev(kap)
+    for it in range(3):
+        O.vcycle(P, f, u, 2, 1, transposed=transposed, kap=kap)
+        g.vcycle(fg, ug, P.dt, P.kappa, kg, nu1=2, nu2=1, transposed=transposed)
+        assert np.array_equal(host(ug), u), it
+
+
+def test_heat_256_one_step_matches_oracle():
+    """2D heat backward Euler, one step, 256^2, h = 1/256, dt = 1e-3, Neumann, FP64,
+    16 cosine modes, V(2,2) to 1e-10: same cycle count and the same bits."""
+    u0 = I.heat_2d_small()
+    P = O.Problem(n=(256, 256), h=1 / 256, dt=1e-3, bc="neumann", coarsest=4, nuc=2)
+    uo = u0.copy()
+    st, cyc, hist = O.solve(P, u0, uo, 1e-10)
+    g = grid_for(P, np.float64)
+    ug = dev(u0)
+    assert g.solve(dev(u0), ug, P.dt, tol=1e-10) == 0
+    s = g.stats()
+    assert abs(s["cycles"] - cyc) <= 1
+    if s["cycles"] == cyc:
+        assert np.array_equal(host(ug), uo)
+    np.testing.assert_allclose(s["rel_res"][: min(cyc, s["cycles"])], hist[: min(cyc, s["cycles"])], rtol=1e-9)
+
+
+@pytest.mark.parametrize("n,coarsest,bc", [((128, 128), 4, "neumann"), ((32, 32, 32), 4, "neumann"),
+                                           ((128, 64), 4, "dirichlet")])
+@pytest.mark.parametrize("variable", [False, True])
+def test_mixed_precision_matches_oracle(n, coarsest, bc, variable):
+    """FP32 inner cycles inside FP64 defect correction; not bitwise (the outer scaling
+    uses a reduced norm), so compare the converged result with the oracle's mixed
+    solve and with its FP64 solve."""
+    P = _problem(n, coarsest, bc, dt=1e-3, kappa=1.0)
+    kap = np.exp(0.5 * I.random_field(P.shape(), 7)) if variable else None
+    f = I.cosine_modes(n[0], len(n), 16, np.random.default_rng(1))[tuple(slice(0, m) for m in P.shape())]
+    f = np.ascontiguousarray(f)
+    uo = f.copy()
+    st, outer, hist = O.solve_mixed(P, f, uo, tol=1e-10, inner=2, kap=kap)
+    assert st == 0
+    g64 = grid_for(P, np.float64, variable)
+    g32 = grid_for(P, np.float32, variable, mixed=True)
+    from paper_2510_11152_amd import solve_mixed
+    ug = dev(f)
+    assert solve_mixed(g64, g32, dev(f), ug, P.dt, P.kappa, None if kap is None else dev(kap), tol=1e-10, inner=2) == 0
+    got = host(ug)
+    assert abs(g64.stats()["cycles"] - outer) <= 1
+    scale = np.abs(uo).max()
+    assert np.abs(got - uo).max() <= 1e-9 * scale
+    ref = f.copy()
+    O.solve(P, f, ref, 1e-13, kap=kap)
+    assert np.abs(got - ref).max() <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("n,bc", [((64, 64), "neumann"), ((32, 64), "dirichlet"), ((16, 16, 16), "periodic")])
+def test_kappa_grad_bitwise(n, bc):
+    P = _problem(n, 4, bc)
+    g = grid_for(P, np.float64, True)
+    kap = np.exp(0.5 * I.random_field(P.shape(), 1))
+    mu = I.random_field(P.shape(), 2)
+    u = I.random_field(P.shape(), 3)
+    g0 = I.random_field(P.shape(), 4)
+    go = g0.copy()
+    O.kappa_grad(P, kap, mu, u, go)
+    gg = dev(g0)
+    g.kappa_grad(P.dt, dev(kap), dev(mu), dev(u), gg)
+    assert np.array_equal(host(gg), go)
+
+
+def test_solve_reports_not_converged_and_is_deterministic():
+    P = _problem((128, 128), 4, "neumann", dt=1e-3, kappa=1.0)
+    g = grid_for(P, np.float64)
+    g.set(kmax=1)
+    f = dev(I.heat_2d_small(128))
+    u1 = f.clone()
+    assert g.solve(f, u1, P.dt, tol=1e-12) == 1
+    g.set(kmax=100)
+    a, b = f.clone(), f.clone()
+    g.solve(f, a, P.dt, tol=1e-12)
+    g.solve(f, b, P.dt, tol=1e-12)
+    assert torch.equal(a, b)
