@@ -68,6 +68,16 @@ extern "C" {
 #define FAS_OPT_COARSE_SWEEPS 2 /* sweeps on the coarsest level (default 2; Remark 1)      */
 #define FAS_OPT_FUSED 3         /* 1 (default): fused tile kernels where available;
                                    0: one kernel per colour phase everywhere              */
+#define FAS_OPT_PROFILE 4       /* 1: time every finest-level kernel launch with HIP events
+                                   recorded on the grid's stream (read with
+                                   fas_get_profile); 0 (default): off                     */
+
+/* kernel classes reported by fas_get_profile */
+#define FAS_K_SMOOTH 0 /* stand-alone smoothing launches on the finest level              */
+#define FAS_K_PRE 1    /* residual + restriction (fused with pre-smoothing when fused)     */
+#define FAS_K_POST 2   /* prolongation + correction (fused with post-smoothing when fused) */
+#define FAS_K_NORM 3   /* residual-norm reduction                                          */
+#define FAS_K_COUNT 4
 
 typedef struct fas_grid* fas_grid_t;
 
@@ -155,7 +165,15 @@ int fas_kappa_grad(fas_grid_t grid, double dt, const void* kappa_cell, const voi
 int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, const void* kappa_cell,
                     const void* rhs, void* u, double tol, int nu1, int nu2, int inner);
 
+typedef struct {
+    int launches[FAS_K_COUNT]; /* finest-level launches per kernel class since the last reset */
+    double ms[FAS_K_COUNT];    /* summed HIP-event durations of those launches (ms)         */
+} fas_profile_t;
+
 int fas_get_stats(fas_grid_t grid, fas_stats_t* out);
+/* Accumulated kernel times of a grid with FAS_OPT_PROFILE on (synchronises the stream);
+ * reset != 0 clears the counters afterwards. */
+int fas_get_profile(fas_grid_t grid, fas_profile_t* out, int reset);
 const char* fas_last_error(void);
 
 #ifdef __cplusplus

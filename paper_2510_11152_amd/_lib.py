@@ -21,7 +21,8 @@ FAS_BC = {"neumann": 0, "dirichlet": 1, "periodic": 2}
 FAS_F64, FAS_F32 = 0, 1
 FAS_FLAG_VARIABLE_KAPPA = 1
 FAS_FLAG_MIXED_INNER = 2
-FAS_OPT_KMAX, FAS_OPT_COARSE_SWEEPS, FAS_OPT_FUSED = 1, 2, 3
+FAS_OPT_KMAX, FAS_OPT_COARSE_SWEEPS, FAS_OPT_FUSED, FAS_OPT_PROFILE = 1, 2, 3, 4
+FAS_K_NAMES = ("smooth", "pre", "post", "norm")
 
 # Every function the header declares, with (restype, argtypes).
 _vp, _i, _d, _sz, _i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
@@ -32,6 +33,10 @@ _pd = ctypes.POINTER(ctypes.c_double)
 class FasStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("status", ctypes.c_int), ("rhs_norm", ctypes.c_double),
                 ("rel_res", ctypes.c_double * 64)]
+
+
+class FasProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int * 4), ("ms", ctypes.c_double * 4)]
 
 
 SIGNATURES = {
@@ -53,6 +58,7 @@ SIGNATURES = {
     "fas_kappa_grad": (_i, [_vp, _d, _vp, _vp, _vp, _vp]),
     "fas_solve_mixed": (_i, [_vp, _vp, _d, _d, _vp, _vp, _vp, _d, _i, _i, _i]),
     "fas_get_stats": (_i, [_vp, ctypes.POINTER(FasStats)]),
+    "fas_get_profile": (_i, [_vp, ctypes.POINTER(FasProfile), _i]),
     "fas_last_error": (ctypes.c_char_p, []),
 }
 

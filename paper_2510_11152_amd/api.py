@@ -62,7 +62,7 @@ class Grid:
     def shape(self, level=0):
         return tuple(m >> level for m in reversed(self.n))
 
-    def set(self, kmax=None, coarse_sweeps=None, fused=None):
+    def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None):
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -70,7 +70,15 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_grid_set")
         if fused is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_FUSED, float(int(fused))), "fas_grid_set")
+        if profile is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_PROFILE, float(int(profile))), "fas_grid_set")
         return self
+
+    def profile(self, reset=True):
+        """{kernel class: (launches, total ms)} of finest-level launches (profile=True)."""
+        p = _lib.FasProfile()
+        check(load().fas_get_profile(self.handle, ctypes.byref(p), int(reset)), "fas_get_profile")
+        return {name: (p.launches[i], p.ms[i]) for i, name in enumerate(_lib.FAS_K_NAMES)}
 
     def _arr(self, t, level=0, name="array", dtype=None):
         if t is None:

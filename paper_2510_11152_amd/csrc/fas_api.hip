@@ -171,13 +171,50 @@ double read_norm(fas_grid* g)
     return sqrt(g->host[0]);
 }
 
+// ---- profiler: HIP events recorded on the grid stream around finest-level launches ----
+void prof_flush(fas_grid* g)
+{
+    if (!g->ev_n) return;
+    FAS_HIP_CHECK(hipEventSynchronize(g->ev[2 * g->ev_n - 1]));
+    for (int i = 0; i < g->ev_n; ++i) {
+        float ms = 0.f;
+        FAS_HIP_CHECK(hipEventElapsedTime(&ms, g->ev[2 * i], g->ev[2 * i + 1]));
+        g->prof.ms[g->ev_kind[i]] += ms;
+        g->prof.launches[g->ev_kind[i]] += 1;
+    }
+    g->ev_n = 0;
+}
+
+struct ProfScope {
+    fas_grid* g;
+    bool on;
+    ProfScope(fas_grid* g_, int level, int kind) : g(g_), on(g_->profile && level == 0)
+    {
+        if (!on) return;
+        if (g->ev_n == fas::kMaxEvents) prof_flush(g);
+        const int i = g->ev_n;
+        while (g->ev_created < 2 * (i + 1)) FAS_HIP_CHECK(hipEventCreate(&g->ev[g->ev_created++]));
+        g->ev_kind[i] = kind;
+        FAS_HIP_CHECK(hipEventRecord(g->ev[2 * i], g->stream));
+    }
+    void end()
+    {
+        if (!on) return;
+        FAS_HIP_CHECK(hipEventRecord(g->ev[2 * g->ev_n + 1], g->stream));
+        ++g->ev_n;
+        on = false;
+    }
+};
+
 void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse)
 {
     const int first = (g->dim + 1) & 1;
     for (int s = 0; s < sweeps; ++s)
         for (int ph = 0; ph < 2; ++ph) {
             const int parity = ((ph == 0) != reverse) ? first : 1 - first;
+            ProfScope ps(g, l, FAS_K_SMOOTH);
             fas::launch_smooth_phase(g, l, g->coef[l], g->lev[l].kap, f, u, parity);
+            ps.end();
         }
 }
 
@@ -191,11 +228,19 @@ void vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post,
     smooth(g, l, f, u, pre, rev);
     fas::Level& C = g->lev[l + 1];
     // r = f - A u;  u_c = R u;  f_c = R r + A_c u_c
-    fas::launch_resid_restrict(g, l, g->coef[l], g->lev[l].kap, f, u, C.u, C.f);
+    {
+        ProfScope ps(g, l, FAS_K_PRE);
+        fas::launch_resid_restrict(g, l, g->coef[l], g->lev[l].kap, f, u, C.u, C.f);
+        ps.end();
+    }
     fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
     vcycle_level(g, l + 1, C.f, C.u, pre, post, rev);
     // u += P(u_c - R u)
-    fas::launch_prolong_correct(g, l, C.u, u);
+    {
+        ProfScope ps(g, l, FAS_K_POST);
+        fas::launch_prolong_correct(g, l, C.u, u);
+        ps.end();
+    }
     smooth(g, l, f, u, post, rev);
 }
 
@@ -227,7 +272,11 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     int k;
     for (k = 1; k <= g->kmax; ++k) {
         vcycle_top(g, rhs, u, nu1, nu2, transposed);
-        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, u);
+        {
+            ProfScope ps(g, 0, FAS_K_NORM);
+            fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, u);
+            ps.end();
+        }
         const double nr = read_norm(g);
         const double rel = nf > 0.0 ? nr / nf : nr;
         if (k <= 64) g->stats.rel_res[k - 1] = rel;
@@ -339,6 +388,7 @@ int fas_grid_destroy(fas_grid_t g)
 {
     if (!g) return FAS_OK;
     if (g->host) (void)hipHostFree(g->host);
+    for (int i = 0; i < g->ev_created; ++i) (void)hipEventDestroy(g->ev[i]);
     delete g;
     return FAS_OK;
 }
@@ -357,6 +407,10 @@ int fas_grid_set(fas_grid_t g, int option, double value)
             case FAS_OPT_COARSE_SWEEPS:
                 if (v < 1) return fail(FAS_ERR_ARG, "coarse sweeps must be >= 1");
                 g->nuc = v;
+                return FAS_OK;
+            case FAS_OPT_PROFILE:
+                if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "profile must be 0 or 1");
+                g->profile = v;
                 return FAS_OK;
             case FAS_OPT_FUSED:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "fused must be 0 or 1");
@@ -539,6 +593,18 @@ int fas_get_stats(fas_grid_t g, fas_stats_t* out)
     if (!g || !out) return fail(FAS_ERR_ARG, "null argument");
     *out = g->stats;
     return FAS_OK;
+}
+
+int fas_get_profile(fas_grid_t g, fas_profile_t* out, int reset)
+{
+    return guarded([&]() -> int {
+        check_grid(g);
+        if (!out) return fail(FAS_ERR_ARG, "null argument");
+        prof_flush(g);
+        *out = g->prof;
+        if (reset) memset(&g->prof, 0, sizeof(g->prof));
+        return FAS_OK;
+    });
 }
 
 const char* fas_last_error(void) { return g_last_error.c_str(); }

@@ -11,6 +11,7 @@
 namespace fas {
 
 constexpr int kMaxLevels = 24;
+constexpr int kMaxEvents = 256;  // profiler event pairs held before a flush
 constexpr int kPartials = 2048;  // blocks of a norm reduction (fixed: deterministic order)
 
 // Error carried to the C ABI boundary.
@@ -60,6 +61,12 @@ struct fas_grid {
     int kmax, nuc, fused;
     fas::Coef coef[fas::kMaxLevels];
     fas_stats_t stats;
+    // profiler (FAS_OPT_PROFILE): event pairs around finest-level launches
+    int profile;
+    hipEvent_t ev[2 * fas::kMaxEvents];
+    int ev_kind[fas::kMaxEvents];
+    int ev_n, ev_created;
+    fas_profile_t prof;
     size_t elem() const { return dtype == FAS_F64 ? 8 : 4; }
 };
 
