@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include "fas_fused.h"
 #include "fas_internal.h"
 
 using fas::Error;
@@ -47,7 +48,8 @@ struct Layout {
     int L;
     int n[fas::kMaxLevels][3];
     size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], kap[fas::kMaxLevels];
-    size_t mix_e, mix_r, partials, total;
+    size_t mix_e, mix_r, partials, norm_out, total;
+    int npartials;
 };
 
 // Returns 0 or an error code (FAS_ERR_SHAPE / FAS_ERR_ARG) with a message.
@@ -107,8 +109,15 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, Layout
         lay->mix_r = off;
         off = align_up(off + N0 * s);
     }
+    // one partial sum per fused tile (tiles are at least 64 x 32 cells) or per block of
+    // the stand-alone norm kernel
+    int64_t tiles = 1;
+    for (int a = 0; a < dim; ++a) tiles *= (n[a] + (a == 0 ? 63 : 31)) / (a == 0 ? 64 : 32);
+    lay->npartials = (int)(tiles > fas::kPartials ? tiles : fas::kPartials);
     lay->partials = off;
-    off = align_up(off + (fas::kPartials + 8) * sizeof(double));
+    off = align_up(off + (size_t)lay->npartials * sizeof(double));
+    lay->norm_out = off;
+    off = align_up(off + 8 * sizeof(double));
     lay->total = off;
     return 0;
 }
@@ -165,7 +174,7 @@ void set_kappa(fas_grid* g, const void* kcell, bool source_is_f64, bool coarse =
 double read_norm(fas_grid* g)
 {
     if (!g->host) FAS_HIP_CHECK(hipHostMalloc((void**)&g->host, 64, hipHostMallocDefault));
-    FAS_HIP_CHECK(hipMemcpyAsync(g->host, g->partials + fas::kPartials, sizeof(double), hipMemcpyDeviceToHost,
+    FAS_HIP_CHECK(hipMemcpyAsync(g->host, g->norm_out, sizeof(double), hipMemcpyDeviceToHost,
                                  g->stream));
     FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
     return sqrt(g->host[0]);
@@ -219,14 +228,33 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 }
 
 // FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
-void vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev)
+// partials != nullptr asks the finest-level post-smoothing to leave per-tile residual
+// partial sums there; returns the number written (0 if it could not).
+int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials)
 {
     if (l == g->L) {
         smooth(g, l, f, u, g->nuc, rev);  // Remark 1: coarsest level smoothed, no direct solve
-        return;
+        return 0;
+    }
+    fas::Level& C = g->lev[l + 1];
+    const int first = ((g->dim + 1) & 1) ^ (rev ? 1 : 0);
+    if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
+        void* x = g->lev[l].x;
+        {
+            ProfScope ps(g, l, FAS_K_PRE);
+            fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, x, C.u, C.f);
+            ps.end();
+        }
+        fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
+        vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr);
+        {
+            ProfScope ps(g, l, FAS_K_POST);
+            fas::launch_fused_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
+            ps.end();
+        }
+        return partials ? fas::fused_tiles(g, l) : 0;
     }
     smooth(g, l, f, u, pre, rev);
-    fas::Level& C = g->lev[l + 1];
     // r = f - A u;  u_c = R u;  f_c = R r + A_c u_c
     {
         ProfScope ps(g, l, FAS_K_PRE);
@@ -234,7 +262,7 @@ void vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post,
         ps.end();
     }
     fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
-    vcycle_level(g, l + 1, C.f, C.u, pre, post, rev);
+    vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr);
     // u += P(u_c - R u)
     {
         ProfScope ps(g, l, FAS_K_POST);
@@ -242,11 +270,22 @@ void vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post,
         ps.end();
     }
     smooth(g, l, f, u, post, rev);
+    return 0;
 }
 
-void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed)
+// One cycle on the finest level; with want_norm the squared residual norm of the result
+// is left in g->norm_out (reduced from the fused kernel's partials when available).
+void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed, bool want_norm = false)
 {
-    vcycle_level(g, 0, f, u, transposed ? nu2 : nu1, transposed ? nu1 : nu2, transposed);
+    const int np = vcycle_level(g, 0, f, u, transposed ? nu2 : nu1, transposed ? nu1 : nu2, transposed,
+                                want_norm ? g->partials : nullptr);
+    if (!want_norm) return;
+    ProfScope ps(g, 0, FAS_K_NORM);
+    if (np > 0)
+        fas::launch_sum_partials(g, np);
+    else
+        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, f, u);
+    ps.end();
 }
 
 void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1, int nu2, double tol)
@@ -271,12 +310,7 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     int status = FAS_NOT_CONVERGED;
     int k;
     for (k = 1; k <= g->kmax; ++k) {
-        vcycle_top(g, rhs, u, nu1, nu2, transposed);
-        {
-            ProfScope ps(g, 0, FAS_K_NORM);
-            fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, u);
-            ps.end();
-        }
+        vcycle_top(g, rhs, u, nu1, nu2, transposed, true);
         const double nr = read_norm(g);
         const double rel = nf > 0.0 ? nr / nf : nr;
         if (k <= 64) g->stats.rel_res[k - 1] = rel;
@@ -302,11 +336,13 @@ int vcycle_impl(fas_grid* g, double dt, double kappa, const void* kcell, const v
     check_solve_args(g, rhs, u, nu1, nu2, 0.0);
     set_coefs(g, dt, kappa, kcell != nullptr);
     set_kappa(g, kcell, g->dtype == FAS_F64);
-    vcycle_top(g, rhs, u, nu1, nu2, transposed);
+    double nf = 0.0;
     if (rel_res) {
         fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, nullptr);
-        const double nf = read_norm(g);
-        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, u);
+        nf = read_norm(g);
+    }
+    vcycle_top(g, rhs, u, nu1, nu2, transposed, rel_res != nullptr);
+    if (rel_res) {
         const double nr = read_norm(g);
         *rel_res = nf > 0.0 ? nr / nf : nr;
     }
@@ -374,6 +410,8 @@ int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, in
         g->mix_e = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_e : nullptr;
         g->mix_r = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_r : nullptr;
         g->partials = (double*)(base + lay.partials);
+        g->norm_out = (double*)(base + lay.norm_out);
+        g->npartials = lay.npartials;
         g->stream = (hipStream_t)stream;
         g->kmax = 100;
         g->nuc = 2;

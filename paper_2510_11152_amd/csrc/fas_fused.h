@@ -1,0 +1,20 @@
+// Launchers of the fused tile kernels (kernels_fused2d.hip).
+#pragma once
+#include "fas_internal.h"
+
+namespace fas {
+
+// Whether level l (not the coarsest) runs the fused pre/post kernels.
+bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
+// Number of tiles (thus of norm partial sums) of a fused launch on level l.
+int fused_tiles(const fas_grid* g, int l);
+// pre: nu sweeps on u_in -> u_out, then uc = R u_out, rc = R(f - A u_out).
+// first: parity of the 0-based index sum updated first in each sweep.
+void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                      void* u_out, void* uc, void* rc);
+// post: u_out = nu sweeps of (u_in + P(uc - R u_in)); partials (nullable) gets one sum
+// of r^2 per tile, r = f - A u_out.
+void launch_fused_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                       const void* uc, void* u_out, double* partials);
+
+}  // namespace fas

@@ -54,7 +54,9 @@ struct fas_grid {
     double h;
     fas::Level lev[fas::kMaxLevels];
     hipStream_t stream;
-    double* partials;    // kPartials doubles + result slots, device
+    double* partials;    // per-block / per-tile partial sums of a norm (npartials), device
+    double* norm_out;    // reduced sum of squares, device
+    int npartials;
     double* host;        // pinned host scalars
     void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
     void* mix_r;
@@ -79,8 +81,10 @@ void launch_smooth_phase(const fas_grid* g, int l, const Coef& c, const void* ka
 void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u,
                      void* r);
 // Partial sums of r^2 (r = f - A u) into g->partials then a fixed-order total into
-// g->partials[kPartials]; rhs-only mode (u == nullptr) sums f^2.
+// g->norm_out[0]; rhs-only mode (u == nullptr) sums f^2.
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u);
+// Fixed-order total of g->partials[0..count) into g->norm_out[0].
+void launch_sum_partials(const fas_grid* g, int count);
 void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
                            const void* u, void* uc, void* rc);
 void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc);

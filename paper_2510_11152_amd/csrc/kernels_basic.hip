@@ -111,7 +111,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Op<T> op, const T* __rest
     block_sum_store(acc, partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_partials(double* partials, int count)
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials, int count,
+                                                          double* __restrict__ out)
 {
     double acc = 0.0;
     for (int b = threadIdx.x; b < count; b += kBlock) acc += partials[b];
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(double* partials, int c
         if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[kPartials] = red[0];
+    if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // ----------------------------------------------------------- residual + restriction
@@ -355,7 +356,12 @@ void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap,
     FAS_DISPATCH(g, kap, (k_resid_norm<T, D, KV><<<nb, kBlock, 0, g->stream>>>(
                              make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, g->partials)));
     check_launch();
-    k_sum_partials<<<1, kBlock, 0, g->stream>>>(g->partials, (int)nb);
+    launch_sum_partials(g, (int)nb);
+}
+
+void launch_sum_partials(const fas_grid* g, int count)
+{
+    k_sum_partials<<<1, kBlock, 0, g->stream>>>(g->partials, count, g->norm_out);
     check_launch();
 }
 

@@ -120,6 +120,29 @@ def test_vcycle_iterates_bitwise(n, coarsest, bc, variable, dtype, transposed):
         assert np.array_equal(host(ug), u), it
 
 
+@pytest.mark.parametrize("n,bc", [((1024, 512), "neumann"), ((512, 1024), "dirichlet"), ((1024, 512), "periodic")])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 3), (3, 0)])
+def test_vcycle_many_tiles_bitwise(n, bc, dtype, nu):
+    """Grids of many fused tiles (interior and boundary tiles, every nu variant):
+    V-cycles through the library equal the oracle's bits, and equal the library's own
+    one-phase-per-launch path."""
+    P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
+    g = grid_for(P, dtype)
+    f = I.random_field(P.shape(), 8).astype(dtype)
+    u = I.random_field(P.shape(), 9).astype(dtype)
+    ug, ub, fg = dev(u), dev(u), dev(f)
+    gb = grid_for(P, dtype).set(fused=False)
+    for it in range(2):
+        O.vcycle(P, f, u, nu[0], nu[1])
+        rel = g.vcycle(fg, ug, P.dt, nu1=nu[0], nu2=nu[1], with_residual=True)
+        gb.vcycle(fg, ub, P.dt, nu1=nu[0], nu2=nu[1])
+        assert np.array_equal(host(ug), u), it
+        assert torch.equal(ug, ub)
+        ro = np.linalg.norm(O.residual(P, 0, f, u).astype(np.float64)) / np.linalg.norm(f.astype(np.float64))
+        assert abs(rel - ro) <= 1e-10 * ro
+
+
 def test_heat_256_one_step_matches_oracle():
     """2D heat backward Euler, one step, 256^2, h = 1/256, dt = 1e-3, Neumann, FP64,
     16 cosine modes, V(2,2) to 1e-10: same cycle count and the same bits."""
