@@ -43,12 +43,12 @@ def kernel_bytes(s, d):
     return {
         # one colour phase: half the cells read u and f and write u (3s per full sweep)
         "smooth": 1.5 * s,
-        # residual + restriction: read u, f; write u_c, r_c
-        "pre": 2 * s + 2 * s / c,
-        # prolongation + correction: read u_c, read and write u
-        "post": 2 * s + s / c,
-        # residual norm: read u, f
-        "norm": 2 * s,
+        # fused pre-smoothing + residual + restriction: read u, f; write u, u_c, r_c
+        "pre": 3 * s + 2 * s / c,
+        # fused correction + post-smoothing + norm partials: read u, f, u_c; write u
+        "post": 3 * s + s / c,
+        # reduction of the per-wave partial sums (a few KB)
+        "norm": 0.0,
     }
 
 
@@ -125,12 +125,12 @@ def main():
 
     # roofline of the dominant finest-level kernel class
     kb = kernel_bytes(8, 2)
-    dom = max(prof, key=lambda k: prof[k][1])
+    dom = max((k for k in prof if kb[k] > 0), key=lambda k: prof[k][1])
     launches, ms = prof[dom]
     avg_s = ms / 1e3 / max(launches, 1)
     achieved = kb[dom] * n * n / avg_s / 1e9
     per_kernel = {k: {"launches": v[0], "avg_us": (v[1] * 1e3 / v[0]) if v[0] else None,
-                      "gbs": (kb[k] * n * n / (v[1] / 1e3 / v[0]) / 1e9) if v[0] else None}
+                      "gbs": (kb[k] * n * n / (v[1] / 1e3 / v[0]) / 1e9) if v[0] and kb[k] else None}
                   for k, v in prof.items()}
 
     result = {

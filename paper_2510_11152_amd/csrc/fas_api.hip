@@ -252,7 +252,7 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
             fas::launch_fused_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
             ps.end();
         }
-        return partials ? fas::fused_tiles(g, l) : 0;
+        return partials ? fas::fused_tiles(g, l, post) : 0;
     }
     smooth(g, l, f, u, pre, rev);
     // r = f - A u;  u_c = R u;  f_c = R r + A_c u_c

@@ -6,8 +6,8 @@ namespace fas {
 
 // Whether level l (not the coarsest) runs the fused pre/post kernels.
 bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
-// Number of tiles (thus of norm partial sums) of a fused launch on level l.
-int fused_tiles(const fas_grid* g, int l);
+// Number of norm partial sums a fused post launch on level l leaves (one per wave).
+int fused_tiles(const fas_grid* g, int l, int nu_post);
 // pre: nu sweeps on u_in -> u_out, then uc = R u_out, rc = R(f - A u_out).
 // first: parity of the 0-based index sum updated first in each sweep.
 void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,

@@ -1,21 +1,24 @@
-// Fused, temporally blocked 2D tile kernels for large levels (constant kappa).
+// Fused, temporally blocked 2D kernels for large levels (constant kappa), built as
+// wave-strip marches.
 //
 // pre  (Alg. 1 pre-smoothing, fine residual, restriction): one pass reads u and f once,
-//      runs nu X-MCGS sweeps on an LDS tile with a halo, writes the smoothed u to a
-//      second buffer, and writes u_c = R u and r_c = R (f - A u) for the coarse level.
+//      runs nu X-MCGS sweeps, writes the smoothed u to a second buffer, and writes
+//      u_c = R u and r_c = R (f - A u) for the coarse level.
 // post (fine grid correction and post-smoothing): one pass reads the pre-smoothed u, f
 //      and the new coarse values, applies u += P(u_c - R u), runs nu sweeps, writes u
-//      back, and (finest level) emits per-tile partial sums of the residual squares.
+//      back and, on the finest level, one partial sum of the squared residual per wave.
 //
-// Each sweep is two colour phases; a phase at radius R around the tile needs the
-// previous phase valid at radius R + 1, so a tile loads a halo of H = 2 nu + 2 cells
-// (even, so local and global index parity agree) and recomputes the halo cells
-// redundantly.  Point formulas are those of fas_device.h, so every cell gets the same
-// bits as in the one-phase-per-launch kernels.
-//
-// LDS layout: every row is split by the parity of the local x index, su[p][y][x >> 1]
-// with p = x & 1.  A colour phase touches one x-parity per row, so lanes access
-// consecutive words (no bank conflicts).
+// Geometry.  One wavefront owns a strip of 128 columns (lane k holds the cell pair
+// 2k, 2k+1 of every row) and a segment of rows, which it visits top to bottom keeping
+// a ring of rows in registers.  Horizontal neighbours come from the adjacent lane by a
+// DPP lane shift, vertical ones from the ring, so no LDS is used.  The nu sweeps are
+// pipelined over rows: when row t arrives, colour phase s (s = 1..2nu) updates row
+// t - s - LAG, in increasing s, which reproduces exactly the values of running the
+// phases one after the other over the whole grid (post waits one more row, LAG = 1, so
+// that a row's lower neighbour has received its coarse correction).  The outer
+// H = 2nu + 2 columns on each side of the strip and H rows above the segment are
+// recomputed as halo; a strip writes 128 - 2H columns and neighbouring strips overlap.
+// Point formulas are those of fas_device.h (same bits as every other kernel).
 #include <hip/hip_runtime.h>
 
 #include "fas_device.h"
@@ -26,269 +29,349 @@ namespace fas {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kWaves = 4;  // independent wavefronts per block
+constexpr int kThreads = 64 * kWaves;
+constexpr int kSegRows = 128;  // rows per segment
 
 template <typename T>
-struct TileShape;
-template <>
-struct TileShape<double> {
-    static constexpr int TX = 64, TY = 32;
-};
-template <>
-struct TileShape<float> {
-    static constexpr int TX = 64, TY = 64;
-};
-
-template <typename T>
-struct FusedArgs {
+struct StripArgs {
     int n0, n1;        // level size
     int bc;
     T k;               // dt*kappa/h^2 of the level
     T q[16];           // 1/(1 + k W)
-    int first;         // parity (0-based index sum) of the first phase of a sweep
-    int tiles_x, tiles_y, per_xcd;
+    int strips, segs;  // strips across x, row segments along y
+    int seg_rows;      // rows per segment (even)
     const T* f;
     const T* u_in;
     T* u_out;
     T* uc;             // pre: R u out;  post: new coarse values in
     T* rc;             // pre: R r out
-    double* partials;  // post: per-tile sum of r^2 (nullable)
+    double* partials;  // post: one sum of r^2 per wave (nullable)
 };
 
-// Map the block to a tile so that each XCD (blocks are dealt round-robin over 8 XCDs)
-// walks a contiguous band of tiles and neighbouring tiles share its L2.
-__device__ __forceinline__ int tile_of_block(int per_xcd)
+// Lane i receives the value of lane i - 1 (wave_shr:1) or of lane i + 1 (wave_shl:1);
+// the lane without a source receives 0.
+constexpr int kShr1 = 0x138;  // wave_shr:1
+constexpr int kShl1 = 0x130;  // wave_shl:1
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
 {
-    return (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
-template <typename T, int TX, int TY, int H>
-struct Tile {
-    static constexpr int WL = TX + 2 * H;  // loaded width (even)
-    static constexpr int HL = TY + 2 * H;
-    static constexpr int WH = WL / 2;
-    static constexpr int WF = WL - 2;      // f is loaded one cell less on each side
-    static constexpr int HF = HL - 2;
-    static constexpr int WFH = WF / 2;
-    T u[2][HL][WH];
-    T f[2][HF][WFH];
-    __device__ __forceinline__ T& U(int ly, int lx) { return u[lx & 1][ly][lx >> 1]; }
-    __device__ __forceinline__ T& F(int ly, int lx) { return f[(lx - 1) & 1][ly - 1][(lx - 1) >> 1]; }
-};
-
-// Global cell of a local coordinate; periodic grids wrap, others report out-of-domain.
-__device__ __forceinline__ bool map_cell(int g, int n, int bc, int& out)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
 {
-    if (g >= 0 && g < n) {
-        out = g;
-        return true;
-    }
-    if (bc == BC_PERIODIC) {
-        out = g < 0 ? g + n : g - n;
-        if (out < 0 || out >= n) out = ((g % n) + n) % n;
-        return true;
-    }
-    return false;
-}
-
-template <typename T, int TX, int TY, int H>
-__device__ __forceinline__ void load_tile(Tile<T, TX, TY, H>& t, const FusedArgs<T>& a, const T* __restrict__ src,
-                                          int x0, int y0)
-{
-    using TT = Tile<T, TX, TY, H>;
-    for (int idx = threadIdx.x; idx < TT::WL * TT::HL; idx += kThreads) {
-        const int ly = idx / TT::WL, lx = idx % TT::WL;
-        int gx, gy;
-        T v = (T)0;
-        if (map_cell(x0 - H + lx, a.n0, a.bc, gx) && map_cell(y0 - H + ly, a.n1, a.bc, gy))
-            v = src[(int64_t)gy * a.n0 + gx];
-        t.U(ly, lx) = v;
-    }
-    for (int idx = threadIdx.x; idx < TT::WF * TT::HF; idx += kThreads) {
-        const int ly = idx / TT::WF + 1, lx = idx % TT::WF + 1;
-        int gx, gy;
-        T v = (T)0;
-        if (map_cell(x0 - H + lx, a.n0, a.bc, gx) && map_cell(y0 - H + ly, a.n1, a.bc, gy))
-            v = a.f[(int64_t)gy * a.n0 + gx];
-        t.F(ly, lx) = v;
-    }
-}
-
-// Diagonal count of a cell on a non-periodic boundary tile (out-of-domain neighbours
-// hold 0 in LDS, so the neighbour sum needs no change).
-__device__ __forceinline__ int edge_w(const int gx, const int gy, const int n0, const int n1, const int bc)
-{
-    const int nout = (gx == 0) + (gx == n0 - 1) + (gy == 0) + (gy == n1 - 1);
-    return (4 - nout) + (bc == BC_DIRICHLET ? 2 * nout : 0);
-}
-
-// nstage colour phases on the tile, phase s covering radius H - 1 - s.
-template <typename T, int TX, int TY, int H, bool EDGE>
-__device__ __forceinline__ void run_phases(Tile<T, TX, TY, H>& t, const FusedArgs<T>& a, int x0, int y0, int nstage)
-{
-    using TT = Tile<T, TX, TY, H>;
-    const T k = a.k;
-    const T q4 = a.q[4];
-    for (int s = 0; s < nstage; ++s) {
-        const int par = (s & 1) ? 1 - a.first : a.first;
-        const int R = H - 1 - s;
-        const int ylo = H - R, yhi = H + TY + R;  // rows [ylo, yhi)
-        const int xlo = H - R, xhi = H + TX + R;
-        const int rows = yhi - ylo;
-        for (int idx = threadIdx.x; idx < rows * TT::WH; idx += kThreads) {
-            const int ly = ylo + idx / TT::WH;
-            const int kk = idx % TT::WH;
-            const int lx = 2 * kk + ((par + ly) & 1);
-            if (lx < xlo || lx >= xhi) continue;
-            const int gx = x0 - H + lx, gy = y0 - H + ly;
-            if constexpr (EDGE) {
-                if (gx < 0 || gx >= a.n0 || gy < 0 || gy >= a.n1) continue;
-            }
-            const T S = (t.U(ly, lx - 1) + t.U(ly, lx + 1)) + (t.U(ly - 1, lx) + t.U(ly + 1, lx));
-            T qv = q4;
-            if constexpr (EDGE) qv = a.q[edge_w(gx, gy, a.n0, a.n1, a.bc)];
-            t.U(ly, lx) = (t.F(ly, lx) + k * S) * qv;
-        }
-        __syncthreads();
-    }
-}
-
-template <typename T, int TX, int TY, int H, bool EDGE>
-__device__ __forceinline__ T resid_at(Tile<T, TX, TY, H>& t, const FusedArgs<T>& a, int ly, int lx, int gx, int gy)
-{
-    const T up = t.U(ly, lx);
-    const T S = (t.U(ly, lx - 1) + t.U(ly, lx + 1)) + (t.U(ly - 1, lx) + t.U(ly + 1, lx));
-    int W = 4;
-    if constexpr (EDGE) W = edge_w(gx, gy, a.n0, a.n1, a.bc);
-    return t.F(ly, lx) - (up + a.k * ((T)W * up - S));
-}
-
-template <typename T, int TX, int TY, int H>
-__device__ __forceinline__ void store_interior(Tile<T, TX, TY, H>& t, const FusedArgs<T>& a, int x0, int y0)
-{
-    for (int idx = threadIdx.x; idx < TX * TY; idx += kThreads) {
-        const int iy = idx / TX, ix = idx % TX;
-        const int gx = x0 + ix, gy = y0 + iy;
-        if (gx < a.n0 && gy < a.n1) a.u_out[(int64_t)gy * a.n0 + gx] = t.U(H + iy, H + ix);
-    }
-}
-
-// A tile takes the boundary-aware path when a non-periodic boundary is within its halo.
-template <int TX, int TY, int H, typename A>
-__device__ __forceinline__ bool edge_tile(const A& a, int x0, int y0)
-{
-    return a.bc != BC_PERIODIC && (x0 - H < 0 || y0 - H < 0 || x0 + TX + H > a.n0 || y0 + TY + H > a.n1);
-}
-
-template <typename T, int TX, int TY, int H, int NU, bool EDGE>
-__device__ __forceinline__ void pre_body(Tile<T, TX, TY, H>& t, const FusedArgs<T>& a, int x0, int y0)
-{
-    run_phases<T, TX, TY, H, EDGE>(t, a, x0, y0, 2 * NU);
-    store_interior<T, TX, TY, H>(t, a, x0, y0);
-    // residual at the 4 children of each coarse cell of the tile, then R u and R r
-    const int mc0 = a.n0 >> 1;
-    for (int idx = threadIdx.x; idx < (TX / 2) * (TY / 2); idx += kThreads) {
-        const int J = idx / (TX / 2), I = idx % (TX / 2);
-        const int gx = x0 + 2 * I, gy = y0 + 2 * J;
-        if (gx >= a.n0 || gy >= a.n1) continue;
-        const int lx = H + 2 * I, ly = H + 2 * J;
-        const T r00 = resid_at<T, TX, TY, H, EDGE>(t, a, ly, lx, gx, gy);
-        const T r10 = resid_at<T, TX, TY, H, EDGE>(t, a, ly, lx + 1, gx + 1, gy);
-        const T r01 = resid_at<T, TX, TY, H, EDGE>(t, a, ly + 1, lx, gx, gy + 1);
-        const T r11 = resid_at<T, TX, TY, H, EDGE>(t, a, ly + 1, lx + 1, gx + 1, gy + 1);
-        const int64_t P = (int64_t)(gy >> 1) * mc0 + (gx >> 1);
-        a.uc[P] = restrict4(t.U(ly, lx), t.U(ly, lx + 1), t.U(ly + 1, lx), t.U(ly + 1, lx + 1));
-        a.rc[P] = restrict4(r00, r10, r01, r11);
-    }
-}
-
-template <typename T, int NU>
-__global__ __launch_bounds__(kThreads) void k_fused_pre(FusedArgs<T> a)
-{
-    constexpr int TX = TileShape<T>::TX, TY = TileShape<T>::TY, H = 2 * NU + 2;
-    __shared__ Tile<T, TX, TY, H> t;
-    const int tile = tile_of_block(a.per_xcd);
-    if (tile >= a.tiles_x * a.tiles_y) return;
-    const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
-    load_tile<T, TX, TY, H>(t, a, a.u_in, x0, y0);
-    __syncthreads();
-    if (edge_tile<TX, TY, H>(a, x0, y0))
-        pre_body<T, TX, TY, H, NU, true>(t, a, x0, y0);
-    else
-        pre_body<T, TX, TY, H, NU, false>(t, a, x0, y0);
-}
-
-template <typename T, int TX, int TY, int H, int NU, bool EDGE, bool NORM>
-__device__ __forceinline__ void post_body(Tile<T, TX, TY, H>& t, const FusedArgs<T>& a, int x0, int y0, int tile,
-                                          double* red)
-{
-    run_phases<T, TX, TY, H, EDGE>(t, a, x0, y0, 2 * NU);
-    store_interior<T, TX, TY, H>(t, a, x0, y0);
-    if constexpr (NORM) {
-        double acc = 0.0;
-        for (int idx = threadIdx.x; idx < TX * TY; idx += kThreads) {
-            const int iy = idx / TX, ix = idx % TX;
-            const int gx = x0 + ix, gy = y0 + iy;
-            if (gx >= a.n0 || gy >= a.n1) continue;
-            const T r = resid_at<T, TX, TY, H, EDGE>(t, a, H + iy, H + ix, gx, gy);
-            acc += (double)r * (double)r;
-        }
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = kThreads / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) a.partials[tile] = red[0];
-    }
-}
-
-template <typename T, int NU, bool NORM>
-__global__ __launch_bounds__(kThreads) void k_fused_post(FusedArgs<T> a)
-{
-    constexpr int TX = TileShape<T>::TX, TY = TileShape<T>::TY, H = 2 * NU + 2;
-    using TT = Tile<T, TX, TY, H>;
-    __shared__ TT t;
-    __shared__ double red[NORM ? kThreads : 1];
-    const int tile = tile_of_block(a.per_xcd);
-    if (tile >= a.tiles_x * a.tiles_y) return;
-    const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
-    load_tile<T, TX, TY, H>(t, a, a.u_in, x0, y0);
-    __syncthreads();
-    // u += P(u_c - R u) on every loaded coarse cell (H even: coarse cells are whole)
-    const int mc0 = a.n0 >> 1, mc1 = a.n1 >> 1;
-    for (int idx = threadIdx.x; idx < TT::WH * (TT::HL / 2); idx += kThreads) {
-        const int cy = idx / TT::WH, cx = idx % TT::WH;
-        const int lx = 2 * cx, ly = 2 * cy;
-        int GX, GY;
-        if (!map_cell(((x0 - H) >> 1) + cx, mc0, a.bc, GX) || !map_cell(((y0 - H) >> 1) + cy, mc1, a.bc, GY)) continue;
-        const T old = restrict4(t.U(ly, lx), t.U(ly, lx + 1), t.U(ly + 1, lx), t.U(ly + 1, lx + 1));
-        const T c = a.uc[(int64_t)GY * mc0 + GX] - old;
-        t.U(ly, lx) = t.U(ly, lx) + c;
-        t.U(ly, lx + 1) = t.U(ly, lx + 1) + c;
-        t.U(ly + 1, lx) = t.U(ly + 1, lx) + c;
-        t.U(ly + 1, lx + 1) = t.U(ly + 1, lx + 1) + c;
-    }
-    __syncthreads();
-    if (edge_tile<TX, TY, H>(a, x0, y0))
-        post_body<T, TX, TY, H, NU, true, NORM>(t, a, x0, y0, tile, red);
-    else
-        post_body<T, TX, TY, H, NU, false, NORM>(t, a, x0, y0, tile, red);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 template <typename T>
-FusedArgs<T> make_args(const fas_grid* g, int l, const Coef& c, int first)
+struct Pair;
+template <>
+struct Pair<double> {
+    using V = double2;
+};
+template <>
+struct Pair<float> {
+    using V = float2;
+};
+
+__device__ __forceinline__ int wrap(int g, int n)
 {
-    FusedArgs<T> a{};
+    int w = g < 0 ? g + n : g - n;
+    if (w < 0 || w >= n) w = ((g % n) + n) % n;
+    return w;
+}
+
+// q[W] for a diagonal count W of a boundary cell (selects avoid a per-lane index into
+// the kernel arguments).
+template <typename T>
+__device__ __forceinline__ T pick_q(const StripArgs<T>& a, int W)
+{
+    T v = a.q[4];
+    v = W == 2 ? a.q[2] : v;
+    v = W == 3 ? a.q[3] : v;
+    v = W == 5 ? a.q[5] : v;
+    v = W == 6 ? a.q[6] : v;
+    return v;
+}
+
+template <int NU, int MODE>
+struct StripGeom {
+    static constexpr int S = 2 * NU;         // colour phases per pass
+    static constexpr int H = 2 * NU + 2;     // halo columns / rows above
+    static constexpr int TXS = 128 - 2 * H;  // columns written per strip
+    static constexpr int LAG = MODE;         // post: one row later (see header)
+    static constexpr int PF = 4;             // rows loaded ahead
+    static constexpr int RING = S + 8;       // rows held: >= S + 3 + LAG + PF, even
+};
+
+// The march of one wavefront.  EDGE: the strip or segment reaches past a domain edge
+// (rows/columns are wrapped for periodic grids, or zero and never updated otherwise;
+// boundary cells need their own diagonal counts).  Interior waves run without any of
+// that.  Loads are unconditional (boundary waves load a clamped address and select),
+// so each row's loads stay in flight for PF rows.
+template <typename T, int NU, int MODE, bool NORM, bool EDGE, int FIRST>
+__device__ __forceinline__ void march(const StripArgs<T>& a, int strip, int seg, int seg_rows, int wave_id)
+{
+    using G = StripGeom<NU, MODE>;
+    using V = typename Pair<T>::V;
+    constexpr int S = G::S, H = G::H, RING = G::RING, PF = G::PF, LAG = G::LAG;
+    const int lane = threadIdx.x & 63;
+    const bool periodic = a.bc == BC_PERIODIC;
+    const int x0 = strip * G::TXS;              // first written column
+    const int gxe = x0 - H + 2 * lane;          // even cell of this lane (global x)
+    const int y0 = seg * seg_rows;
+    const int rA = y0 - H;                      // first row visited (even)
+    const int yend = min(y0 + seg_rows, a.n1);  // rows written: [y0, yend)
+    const int nsteps = yend - rA + S + 1 + LAG;
+    const bool own = lane >= H / 2 && lane < 64 - H / 2 && gxe < a.n0;  // writes this pair
+    bool xin = true;
+    int gxl = gxe;
+    if constexpr (EDGE) {
+        if (periodic) {
+            gxl = wrap(gxe, a.n0);
+        } else {
+            xin = gxe >= 0 && gxe < a.n0;
+            gxl = min(max(gxe, 0), a.n0 - 2);
+        }
+    }
+    // boundary faces across x of the even / odd cell (n0 even: a pair is in or out)
+    const int bxe = (EDGE && !periodic) ? (gxe == 0) : 0;
+    const int bxo = (EDGE && !periodic) ? (gxe + 2 == a.n0) : 0;
+    const int dsgn = a.bc == BC_DIRICHLET ? 1 : -1;
+    const T k = a.k;
+    const T q4 = a.q[4];
+    const int mc0 = a.n0 >> 1;
+    const int gcx = gxl >> 1;  // coarse column of the pair
+
+    T ue[RING], uo[RING], fe[RING], fo[RING];
+    T cr[RING];  // post: new coarse value of the coarse row completed by an odd row
+    T re_prev = (T)0, ro_prev = (T)0;
+    double acc = 0.0;
+
+    // global row of visited row rho and whether it is inside a non-periodic domain
+    auto row_of = [&](int rho, int& gy) -> bool {
+        gy = rA + rho;
+        if constexpr (!EDGE) return true;
+        if (gy >= 0 && gy < a.n1) return true;
+        if (periodic) {
+            gy = wrap(gy, a.n1);
+            return true;
+        }
+        gy = min(max(gy, 0), a.n1 - 1);
+        return false;
+    };
+    // load visited row rho into ring slot p (ODD: rho is odd)
+    auto load_row = [&](int rho, int p, bool odd) {
+        int gy;
+        const bool yin = row_of(rho, gy);
+        const int64_t off = (int64_t)gy * a.n0 + gxl;
+        V zu = *reinterpret_cast<const V*>(a.u_in + off);
+        V zf = *reinterpret_cast<const V*>(a.f + off);
+        T c = (T)0;
+        if constexpr (MODE == 1) {
+            if (odd) c = a.uc[(int64_t)(gy >> 1) * mc0 + gcx];
+        }
+        if constexpr (EDGE) {
+            const bool in = yin && xin;
+            zu.x = in ? zu.x : (T)0;
+            zu.y = in ? zu.y : (T)0;
+            zf.x = in ? zf.x : (T)0;
+            zf.y = in ? zf.y : (T)0;
+        }
+        ue[p] = zu.x;
+        uo[p] = zu.y;
+        fe[p] = zf.x;
+        fo[p] = zf.y;
+        if constexpr (MODE == 1) cr[p] = c;
+    };
+    // Diagonal factor and count of the lane's even / odd cell, in an inner row or in the
+    // first or last row of the domain (n1 >= 64, so a row has at most one y-boundary
+    // face); fixed per wave.
+    T qe_in = q4, qe_bd = q4, qo_in = q4, qo_bd = q4;
+    T we_in = (T)4, we_bd = (T)4, wo_in = (T)4, wo_bd = (T)4;
+    if constexpr (EDGE) {
+        if (!periodic) {
+            const int ce = 4 + dsgn * bxe, co = 4 + dsgn * bxo;
+            qe_in = pick_q(a, ce);
+            qe_bd = pick_q(a, ce + dsgn);
+            qo_in = pick_q(a, co);
+            qo_bd = pick_q(a, co + dsgn);
+            we_in = (T)ce;
+            we_bd = (T)(ce + dsgn);
+            wo_in = (T)co;
+            wo_bd = (T)(co + dsgn);
+        }
+    }
+    auto ybound = [&](int gy) -> bool { return EDGE && !periodic && (gy == 0 || gy == a.n1 - 1); };
+
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load_row(p, p, p & 1);
+
+    // whole ring turns (the last turn may run past the segment: those rows are read in
+    // bounds, see k_strip, and never written)
+    const int nturns = (nsteps + RING - 1) / RING;
+    for (int turn = 0; turn < nturns; ++turn) {
+        const int rb = turn * RING;
+#pragma unroll
+        for (int j = 0; j < RING; ++j) {
+            const int rho = rb + j;
+            // prefetch row rho + PF
+            load_row(rho + PF, (j + PF) % RING, ((j + PF) & 1) != 0);
+            if constexpr (MODE == 1) {
+                // fine grid correction u += P(u_c - R u) once both rows of a coarse row
+                // are present (rho odd: rows rho - 1 and rho)
+                if (j & 1) {
+                    int gy;
+                    const bool yin = row_of(rho, gy);
+                    const int jp = (j + RING - 1) % RING;
+                    const T old = restrict4(ue[jp], uo[jp], ue[j], uo[j]);
+                    const T c = cr[j] - old;
+                    const bool apply = !EDGE || (yin && xin);
+                    ue[jp] = apply ? ue[jp] + c : ue[jp];
+                    uo[jp] = apply ? uo[jp] + c : uo[jp];
+                    ue[j] = apply ? ue[j] + c : ue[j];
+                    uo[j] = apply ? uo[j] + c : uo[j];
+                }
+            }
+            // colour phases: phase s updates row rho - s - LAG
+#pragma unroll
+            for (int s = 1; s <= S; ++s) {
+                const int r = rho - s - LAG;
+                if (r < 1) continue;
+                int gy;
+                const bool yin = row_of(r, gy);
+                if (EDGE && !yin) continue;
+                constexpr int sh = 2 * RING;
+                const int a0 = (j - s - LAG + sh) % RING;      // row r
+                const int am = (j - s - LAG - 1 + sh) % RING;  // row r - 1
+                const int ap = (j - s - LAG + 1 + sh) % RING;  // row r + 1
+                // colour of phase s; the pair's cell of that colour in row r is the even
+                // one when the row parity equals the colour (rA and x0 - H are even)
+                const int colour = ((s - 1) & 1) ^ FIRST;
+                const bool even_cell = (((j - s - LAG + sh) & 1) ^ colour) == 0;
+                if (even_cell) {
+                    const T w = dpp_move<kShr1>(uo[a0]);
+                    const T Ssum = (w + uo[a0]) + (ue[am] + ue[ap]);
+                    const T qv = ybound(gy) ? qe_bd : qe_in;
+                    const T nv = (fe[a0] + k * Ssum) * qv;
+                    ue[a0] = (!EDGE || xin) ? nv : ue[a0];
+                } else {
+                    const T e = dpp_move<kShl1>(ue[a0]);
+                    const T Ssum = (ue[a0] + e) + (uo[am] + uo[ap]);
+                    const T qv = ybound(gy) ? qo_bd : qo_in;
+                    const T nv = (fo[a0] + k * Ssum) * qv;
+                    uo[a0] = (!EDGE || xin) ? nv : uo[a0];
+                }
+            }
+            // row r = rho - S - 1 - LAG is final: write it, take its residual
+            {
+                const int r = rho - S - 1 - LAG;
+                if (r >= 1) {
+                    int gy;
+                    row_of(r, gy);
+                    const int graw = rA + r;
+                    const bool inseg = graw >= y0 && graw < yend;
+                    constexpr int sh = 2 * RING;
+                    const int a0 = (j - S - 1 - LAG + sh) % RING;
+                    const int am = (j - S - 2 - LAG + sh) % RING;
+                    const int ap = (j - S - LAG + sh) % RING;
+                    const T w = dpp_move<kShr1>(uo[a0]);
+                    const T e = dpp_move<kShl1>(ue[a0]);
+                    const T Se = (w + uo[a0]) + (ue[am] + ue[ap]);
+                    const T So = (ue[a0] + e) + (uo[am] + uo[ap]);
+                    const bool yb = ybound(gy);
+                    const T We = yb ? we_bd : we_in;
+                    const T Wo = yb ? wo_bd : wo_in;
+                    const T re = fe[a0] - (ue[a0] + k * (We * ue[a0] - Se));
+                    const T ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
+                    if (inseg && own) {
+                        V out;
+                        out.x = ue[a0];
+                        out.y = uo[a0];
+                        *reinterpret_cast<V*>(a.u_out + (int64_t)graw * a.n0 + gxe) = out;
+                        if constexpr (MODE == 0) {
+                            // rows (r - 1, r) form coarse row graw / 2 when r is odd
+                            if (((j - S - 1 - LAG + sh) & 1) && graw - 1 >= y0) {
+                                const T ucv = restrict4(ue[am], uo[am], ue[a0], uo[a0]);
+                                const T rcv = restrict4(re_prev, ro_prev, re, ro);
+                                const int64_t P = (int64_t)(graw >> 1) * mc0 + (gxe >> 1);
+                                a.uc[P] = ucv;
+                                a.rc[P] = rcv;
+                            }
+                        }
+                        if constexpr (NORM) {
+                            acc += (double)re * (double)re;
+                            acc += (double)ro * (double)ro;
+                        }
+                    }
+                    re_prev = re;
+                    ro_prev = ro;
+                }
+            }
+        }
+    }
+    if constexpr (NORM) {
+        // fixed butterfly over the 64 lanes (same order on every run)
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) a.partials[wave_id] = acc;
+    }
+}
+
+template <typename T, int NU, int MODE, bool NORM>
+__global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
+{
+    using G = StripGeom<NU, MODE>;
+    // the wave index is uniform across the wave: keep it (and all row bookkeeping) scalar
+    const int wave_id = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave_id >= a.strips * a.segs) return;
+    const int strip = wave_id % a.strips, seg = wave_id / a.strips;
+    const int x0 = strip * G::TXS, y0 = seg * a.seg_rows;
+    // rows read: [y0 - H, y0 - H + turns * RING + PF), columns [x0 - H, x0 - H + 128)
+    const int nsteps = a.seg_rows + G::H + G::S + 1 + G::LAG;
+    const int rows_read = (nsteps + G::RING - 1) / G::RING * G::RING + G::PF;
+    const bool edge = x0 - G::H < 0 || x0 - G::H + 128 > a.n0 || y0 - G::H < 0 || y0 - G::H + rows_read > a.n1;
+    if (edge) {
+        if (first)
+            march<T, NU, MODE, NORM, true, 1>(a, strip, seg, a.seg_rows, wave_id);
+        else
+            march<T, NU, MODE, NORM, true, 0>(a, strip, seg, a.seg_rows, wave_id);
+    } else {
+        if (first)
+            march<T, NU, MODE, NORM, false, 1>(a, strip, seg, a.seg_rows, wave_id);
+        else
+            march<T, NU, MODE, NORM, false, 0>(a, strip, seg, a.seg_rows, wave_id);
+    }
+}
+
+// Rows per segment: long segments amortise the warm-up rows, short ones give small
+// levels enough wavefronts (about 2048) to hide latency.
+inline int seg_rows_for(int n0, int n1, int txs)
+{
+    const int strips = (n0 + txs - 1) / txs;
+    int rows = kSegRows;
+    while (rows > 16 && (int64_t)strips * ((n1 + rows - 1) / rows) < 2048) rows >>= 1;
+    return rows;
+}
+
+template <typename T>
+StripArgs<T> make_args(const fas_grid* g, int l, const Coef& c, int nu)
+{
+    StripArgs<T> a{};
     a.n0 = g->lev[l].n[0];
     a.n1 = g->lev[l].n[1];
     a.bc = g->bc;
     a.k = (T)c.kd;
     for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
-    a.first = first;
-    a.tiles_x = (a.n0 + TileShape<T>::TX - 1) / TileShape<T>::TX;
-    a.tiles_y = (a.n1 + TileShape<T>::TY - 1) / TileShape<T>::TY;
-    a.per_xcd = (a.tiles_x * a.tiles_y + 7) / 8;
+    const int txs = 128 - 2 * (2 * nu + 2);
+    a.strips = (a.n0 + txs - 1) / txs;
+    a.seg_rows = seg_rows_for(a.n0, a.n1, txs);
+    a.segs = (a.n1 + a.seg_rows - 1) / a.seg_rows;
     return a;
 }
 
@@ -298,41 +381,15 @@ inline void check_launch()
     if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-template <typename T, int NU>
-void pre_nu(const fas_grid* g, FusedArgs<T>& a)
+template <typename T, int MODE, bool NORM>
+void launch_nu(const fas_grid* g, const StripArgs<T>& a, int nu, int first)
 {
-    k_fused_pre<T, NU><<<(unsigned)a.per_xcd * 8u, kThreads, 0, g->stream>>>(a);
-}
-
-template <typename T, int NU>
-void post_nu(const fas_grid* g, FusedArgs<T>& a, bool norm)
-{
-    if (norm)
-        k_fused_post<T, NU, true><<<(unsigned)a.per_xcd * 8u, kThreads, 0, g->stream>>>(a);
-    else
-        k_fused_post<T, NU, false><<<(unsigned)a.per_xcd * 8u, kThreads, 0, g->stream>>>(a);
-}
-
-template <typename T>
-void pre_dispatch(const fas_grid* g, FusedArgs<T>& a, int nu)
-{
+    const unsigned blocks = (unsigned)((a.strips * a.segs + kWaves - 1) / kWaves);
     switch (nu) {
-        case 0: pre_nu<T, 0>(g, a); break;
-        case 1: pre_nu<T, 1>(g, a); break;
-        case 2: pre_nu<T, 2>(g, a); break;
-        case 3: pre_nu<T, 3>(g, a); break;
-        default: throw Error(FAS_ERR_ARG, "fused kernels take nu <= 3");
-    }
-}
-
-template <typename T>
-void post_dispatch(const fas_grid* g, FusedArgs<T>& a, int nu, bool norm)
-{
-    switch (nu) {
-        case 0: post_nu<T, 0>(g, a, norm); break;
-        case 1: post_nu<T, 1>(g, a, norm); break;
-        case 2: post_nu<T, 2>(g, a, norm); break;
-        case 3: post_nu<T, 3>(g, a, norm); break;
+        case 0: k_strip<T, 0, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 1: k_strip<T, 1, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 2: k_strip<T, 2, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 3: k_strip<T, 3, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
         default: throw Error(FAS_ERR_ARG, "fused kernels take nu <= 3");
     }
 }
@@ -343,31 +400,33 @@ bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable)
 {
     if (!g->fused || g->dim != 2 || variable || l >= g->L) return false;
     if (nu_pre > 3 || nu_post > 3) return false;
-    // worthwhile once the level spans a few tiles
-    return g->lev[l].n[0] >= 64 && g->lev[l].n[1] >= 32;
+    // at least one full strip wide (so a periodic halo wraps at most once) and a few
+    // rows per segment
+    return g->lev[l].n[0] >= 128 && g->lev[l].n[1] >= 64;
 }
 
-int fused_tiles(const fas_grid* g, int l)
+int fused_tiles(const fas_grid* g, int l, int nu_post)
 {
-    const int TX = g->dtype == FAS_F64 ? TileShape<double>::TX : TileShape<float>::TX;
-    const int TY = g->dtype == FAS_F64 ? TileShape<double>::TY : TileShape<float>::TY;
-    const int tx = (g->lev[l].n[0] + TX - 1) / TX, ty = (g->lev[l].n[1] + TY - 1) / TY;
-    return tx * ty;
+    const int txs = 128 - 2 * (2 * nu_post + 2);
+    const int n0 = g->lev[l].n[0], n1 = g->lev[l].n[1];
+    const int strips = (n0 + txs - 1) / txs;
+    const int rows = seg_rows_for(n0, n1, txs);
+    return strips * ((n1 + rows - 1) / rows);
 }
 
 void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
                       void* u_out, void* uc, void* rc)
 {
     if (g->dtype == FAS_F64) {
-        auto a = make_args<double>(g, l, c, first);
+        auto a = make_args<double>(g, l, c, nu);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.rc = (double*)rc;
-        pre_dispatch<double>(g, a, nu);
+        launch_nu<double, 0, false>(g, a, nu, first);
     } else {
-        auto a = make_args<float>(g, l, c, first);
+        auto a = make_args<float>(g, l, c, nu);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
         a.uc = (float*)uc, a.rc = (float*)rc;
-        pre_dispatch<float>(g, a, nu);
+        launch_nu<float, 0, false>(g, a, nu, first);
     }
     check_launch();
 }
@@ -376,15 +435,21 @@ void launch_fused_post(const fas_grid* g, int l, const Coef& c, int first, int n
                        const void* uc, void* u_out, double* partials)
 {
     if (g->dtype == FAS_F64) {
-        auto a = make_args<double>(g, l, c, first);
+        auto a = make_args<double>(g, l, c, nu);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.partials = partials;
-        post_dispatch<double>(g, a, nu, partials != nullptr);
+        if (partials)
+            launch_nu<double, 1, true>(g, a, nu, first);
+        else
+            launch_nu<double, 1, false>(g, a, nu, first);
     } else {
-        auto a = make_args<float>(g, l, c, first);
+        auto a = make_args<float>(g, l, c, nu);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
         a.uc = (float*)uc, a.partials = partials;
-        post_dispatch<float>(g, a, nu, partials != nullptr);
+        if (partials)
+            launch_nu<float, 1, true>(g, a, nu, first);
+        else
+            launch_nu<float, 1, false>(g, a, nu, first);
     }
     check_launch();
 }
