@@ -7,6 +7,7 @@
 #include <string>
 
 #include "fas_fused.h"
+#include "fas_tail.h"
 #include "fas_internal.h"
 
 using fas::Error;
@@ -230,6 +231,23 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 // FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
 // partials != nullptr asks the finest-level post-smoothing to leave per-tile residual
 // partial sums there; returns the number written (0 if it could not).
+// Coarse part of a cycle below level l: the persistent tail when level l + 1 is its top
+// (the FAS right-hand side is formed inside it), else the coarse right-hand side and
+// the recursion.
+int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials);
+
+void coarse_part(fas_grid* g, int l, int pre, int post, bool rev)
+{
+    fas::Level& C = g->lev[l + 1];
+    const int first = ((g->dim + 1) & 1) ^ (rev ? 1 : 0);
+    if (g->fused && l + 1 == fas::tail_top(g)) {
+        fas::launch_tail(g, l + 1, g->coef, pre, post, first, C.u, C.f, true);
+        return;
+    }
+    fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
+    vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr);
+}
+
 int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials)
 {
     if (l == g->L) {
@@ -238,6 +256,11 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
     }
     fas::Level& C = g->lev[l + 1];
     const int first = ((g->dim + 1) & 1) ^ (rev ? 1 : 0);
+    if (l == 0 && g->fused && fas::tail_top(g) == 0) {
+        // the whole hierarchy fits one tail launch
+        fas::launch_tail(g, 0, g->coef, pre, post, first, u, f, false);
+        return 0;
+    }
     if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
         void* x = g->lev[l].x;
         {
@@ -245,8 +268,7 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
             fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, x, C.u, C.f);
             ps.end();
         }
-        fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
-        vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr);
+        coarse_part(g, l, pre, post, rev);
         {
             ProfScope ps(g, l, FAS_K_POST);
             fas::launch_fused_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
@@ -261,8 +283,7 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         fas::launch_resid_restrict(g, l, g->coef[l], g->lev[l].kap, f, u, C.u, C.f);
         ps.end();
     }
-    fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
-    vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr);
+    coarse_part(g, l, pre, post, rev);
     // u += P(u_c - R u)
     {
         ProfScope ps(g, l, FAS_K_POST);

@@ -1,0 +1,245 @@
+// Persistent coarse tail: every level from `top` down to the coarsest, in one workgroup
+// whose LDS holds u and f of all those levels (Remark 2's recursion below `top`, and
+// Remark 1's smoothing on the coarsest level).  One launch replaces a dozen tiny
+// launches per level; the per-point formulas are those of fas_device.h, so the values
+// are bit-identical to running the per-level kernels.
+#include <hip/hip_runtime.h>
+
+#include "fas_device.h"
+#include "fas_internal.h"
+#include "fas_tail.h"
+
+namespace fas {
+
+namespace {
+
+constexpr int kTailThreads = 1024;
+constexpr int kTailLds = 96 * 1024;  // bytes of LDS for the tail levels
+
+template <typename T>
+struct TailArgs {
+    int nl;                   // levels in the tail (top .. coarsest)
+    int pre, post, nuc;       // sweeps
+    int first;                // parity of the first phase of a sweep
+    int form_rhs;             // 1: f_top = r_top + A u_top (FAS coarse right-hand side)
+    int lds_off[kMaxTail];    // element offset of u of each level; f follows u
+    Op<T> op[kMaxTail];
+    T* u_top;                 // in: initial guess of the top level; out: its new values
+    const T* r_top;           // in: restricted residual (form_rhs) or the right-hand side
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ void cell_of(const Op<T>& op, int p, int& i, int& j, int& l)
+{
+    i = p % op.n0;
+    const int q = p / op.n0;
+    j = q % op.n1;
+    l = q / op.n1;
+}
+
+template <typename T, int DIM, bool KV>
+__device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int first, bool reverse)
+{
+    const int f0 = reverse ? 1 - first : first;
+    const int half = (op.n0 + 1) >> 1;
+    const int pairs = half * op.n1 * op.n2;
+    for (int s = 0; s < sweeps; ++s) {
+        for (int ph = 0; ph < 2; ++ph) {
+            const int parity = ph == 0 ? f0 : 1 - f0;
+            for (int t = threadIdx.x; t < pairs; t += kTailThreads) {
+                const int tt = t % half;
+                const int rest = t / half;
+                const int j = rest % op.n1, l = rest / op.n1;
+                const int i = 2 * tt + ((parity + j + l) & 1);
+                if (i >= op.n0) continue;
+                Nbhd<T, DIM> nb;
+                gather<T, DIM, KV>(op, U, i, j, l, nb);
+                const int p = (int)cell_index(op.n0, op.n1, i, j, l);
+                U[p] = gs_value<T, DIM, KV>(op, nb, F[p]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kTailLds];
+    T* base = reinterpret_cast<T*>(lds);
+    auto U = [&](int l) { return base + a.lds_off[l]; };
+    auto F = [&](int l) { return base + a.lds_off[l] + (a.op[l].n0 * a.op[l].n1 * a.op[l].n2); };
+    const int N0 = a.op[0].n0 * a.op[0].n1 * a.op[0].n2;
+    for (int p = threadIdx.x; p < N0; p += kTailThreads) {
+        U(0)[p] = a.u_top[p];
+        F(0)[p] = a.r_top[p];
+    }
+    __syncthreads();
+    if (a.form_rhs) {
+        // f = r_c + A_c u_c
+        for (int p = threadIdx.x; p < N0; p += kTailThreads) {
+            int i, j, l;
+            cell_of<T, DIM>(a.op[0], p, i, j, l);
+            Nbhd<T, DIM> nb;
+            gather<T, DIM, KV>(a.op[0], U(0), i, j, l, nb);
+            F(0)[p] = F(0)[p] + apply_value<T, DIM, KV>(a.op[0], nb, U(0)[p]);
+        }
+        __syncthreads();
+    }
+    const bool rev = false;
+    // descend: pre-smoothing, then u_c = R u, f_c = R (f - A u) + A_c u_c
+    for (int lv = 0; lv + 1 < a.nl; ++lv) {
+        const Op<T>& op = a.op[lv];
+        const Op<T>& oc = a.op[lv + 1];
+        T* u = U(lv);
+        const T* f = F(lv);
+        tail_smooth<T, DIM, KV>(op, u, f, a.pre, a.first, rev);
+        const int Nc = oc.n0 * oc.n1 * oc.n2;
+        for (int P = threadIdx.x; P < Nc; P += kTailThreads) {
+            int I, J, K;
+            cell_of<T, DIM>(oc, P, I, J, K);
+            T uu[8], rr[8];
+#pragma unroll
+            for (int c = 0; c < (DIM == 3 ? 8 : 4); ++c) {
+                const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), l = DIM == 3 ? 2 * K + (c >> 2) : 0;
+                const int p = (int)cell_index(op.n0, op.n1, i, j, l);
+                Nbhd<T, DIM> nb;
+                gather<T, DIM, KV>(op, u, i, j, l, nb);
+                uu[c] = u[p];
+                rr[c] = f[p] - apply_value<T, DIM, KV>(op, nb, uu[c]);
+            }
+            if constexpr (DIM == 2) {
+                U(lv + 1)[P] = restrict4(uu[0], uu[1], uu[2], uu[3]);
+                F(lv + 1)[P] = restrict4(rr[0], rr[1], rr[2], rr[3]);
+            } else {
+                U(lv + 1)[P] = restrict8(uu[0], uu[1], uu[2], uu[3], uu[4], uu[5], uu[6], uu[7]);
+                F(lv + 1)[P] = restrict8(rr[0], rr[1], rr[2], rr[3], rr[4], rr[5], rr[6], rr[7]);
+            }
+        }
+        __syncthreads();
+        for (int P = threadIdx.x; P < Nc; P += kTailThreads) {
+            int I, J, K;
+            cell_of<T, DIM>(oc, P, I, J, K);
+            Nbhd<T, DIM> nb;
+            gather<T, DIM, KV>(oc, U(lv + 1), I, J, K, nb);
+            F(lv + 1)[P] = F(lv + 1)[P] + apply_value<T, DIM, KV>(oc, nb, U(lv + 1)[P]);
+        }
+        __syncthreads();
+    }
+    // coarsest level: smoothing only (Remark 1)
+    tail_smooth<T, DIM, KV>(a.op[a.nl - 1], U(a.nl - 1), F(a.nl - 1), a.nuc, a.first, rev);
+    // ascend: u += P(u_c - R u), post-smoothing
+    for (int lv = a.nl - 2; lv >= 0; --lv) {
+        const Op<T>& op = a.op[lv];
+        const Op<T>& oc = a.op[lv + 1];
+        T* u = U(lv);
+        const int Nc = oc.n0 * oc.n1 * oc.n2;
+        for (int P = threadIdx.x; P < Nc; P += kTailThreads) {
+            int I, J, K;
+            cell_of<T, DIM>(oc, P, I, J, K);
+            const int i = 2 * I, j = 2 * J, l = 2 * K;
+            T old;
+            if constexpr (DIM == 2) {
+                old = restrict4(u[cell_index(op.n0, op.n1, i, j, 0)], u[cell_index(op.n0, op.n1, i + 1, j, 0)],
+                                u[cell_index(op.n0, op.n1, i, j + 1, 0)], u[cell_index(op.n0, op.n1, i + 1, j + 1, 0)]);
+            } else {
+                old = restrict8(u[cell_index(op.n0, op.n1, i, j, l)], u[cell_index(op.n0, op.n1, i + 1, j, l)],
+                                u[cell_index(op.n0, op.n1, i, j + 1, l)], u[cell_index(op.n0, op.n1, i + 1, j + 1, l)],
+                                u[cell_index(op.n0, op.n1, i, j, l + 1)], u[cell_index(op.n0, op.n1, i + 1, j, l + 1)],
+                                u[cell_index(op.n0, op.n1, i, j + 1, l + 1)],
+                                u[cell_index(op.n0, op.n1, i + 1, j + 1, l + 1)]);
+            }
+            const T c = U(lv + 1)[P] - old;
+#pragma unroll
+            for (int ch = 0; ch < (DIM == 3 ? 8 : 4); ++ch) {
+                const int p = (int)cell_index(op.n0, op.n1, i + (ch & 1), j + ((ch >> 1) & 1), DIM == 3 ? l + (ch >> 2) : 0);
+                u[p] = u[p] + c;
+            }
+        }
+        __syncthreads();
+        tail_smooth<T, DIM, KV>(op, u, F(lv), a.post, a.first, rev);
+    }
+    for (int p = threadIdx.x; p < N0; p += kTailThreads) a.u_top[p] = U(0)[p];
+}
+
+template <typename T>
+TailArgs<T> make_tail_args(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first)
+{
+    TailArgs<T> a{};
+    a.nl = g->L - top + 1;
+    a.pre = pre;
+    a.post = post;
+    a.nuc = g->nuc;
+    a.first = first;
+    int off = 0;
+    for (int i = 0; i < a.nl; ++i) {
+        const int l = top + i;
+        Op<T>& op = a.op[i];
+        op.n0 = g->lev[l].n[0];
+        op.n1 = g->lev[l].n[1];
+        op.n2 = g->lev[l].n[2];
+        op.bc = g->bc;
+        op.k = (T)coef[l].kd;
+        for (int W = 0; W < 16; ++W) op.q[W] = (T)coef[l].q[W];
+        op.kap = (const T*)g->lev[l].kap;
+        a.lds_off[i] = off;
+        off += 2 * (int)g->lev[l].N;
+    }
+    return a;
+}
+
+inline void check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+template <typename T>
+void launch_t(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first, void* u, const void* r,
+              int form_rhs)
+{
+    TailArgs<T> a = make_tail_args<T>(g, top, coef, pre, post, first);
+    a.u_top = (T*)u;
+    a.r_top = (const T*)r;
+    a.form_rhs = form_rhs;
+    const bool kv = g->lev[top].kap != nullptr;
+    if (g->dim == 2) {
+        if (kv)
+            k_tail<T, 2, true><<<1, kTailThreads, 0, g->stream>>>(a);
+        else
+            k_tail<T, 2, false><<<1, kTailThreads, 0, g->stream>>>(a);
+    } else {
+        if (kv)
+            k_tail<T, 3, true><<<1, kTailThreads, 0, g->stream>>>(a);
+        else
+            k_tail<T, 3, false><<<1, kTailThreads, 0, g->stream>>>(a);
+    }
+    check_launch();
+}
+
+}  // namespace
+
+int tail_top(const fas_grid* g)
+{
+    // the largest level from which every coarser level's u and f fit the tail's LDS
+    const size_t s = g->elem();
+    size_t bytes = 0;
+    int top = g->L + 1;
+    for (int l = g->L; l >= 0; --l) {
+        bytes += 2 * (size_t)g->lev[l].N * s;
+        if (bytes > (size_t)kTailLds || g->L - l + 1 > kMaxTail) break;
+        top = l;
+    }
+    return top;  // L + 1: not even the coarsest level fits
+}
+
+void launch_tail(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first, void* u, const void* r,
+                 bool form_rhs)
+{
+    if (g->dtype == FAS_F64)
+        launch_t<double>(g, top, coef, pre, post, first, u, r, form_rhs ? 1 : 0);
+    else
+        launch_t<float>(g, top, coef, pre, post, first, u, r, form_rhs ? 1 : 0);
+}
+
+}  // namespace fas
