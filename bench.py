@@ -33,7 +33,144 @@ def parse():
     ap.add_argument("--inner", type=int, default=3, help="FP32 V-cycles per outer correction (mixed form)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="batched,adjoint,3d",
+                    help="other workloads timed after the headline (comma list; 'none' to skip)")
     return ap.parse_args()
+
+
+def _timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    out = fn()
+    sync()
+    return time.perf_counter() - t0, out
+
+
+def bench_batched(dev):
+    """Uneven batch of 64 2D Neumann heat solves (sizes drawn from 128^2..2048^2, FP64,
+    dt = 1e-4, tol 1e-10): one batched solve per size against looping single solves;
+    then one grain-growth step of 1189 fields on 512^2 (periodic, h = 1, dt = 0.1, FP32,
+    tol 1e-6): right-hand side + one batched solve."""
+    import numpy as np
+    import torch
+
+    import fas_inputs
+    from paper_2510_11152_amd import GrainGrowth, Grid, solve_uneven
+
+    sync = torch.cuda.synchronize
+    fields = fas_inputs.uneven_batch()
+    rhs = [torch.from_numpy(f).to(dev) for f in fields]
+    grids = {}
+    for r in rhs:
+        m = r.shape[0]
+        if m not in grids:
+            grids[m] = Grid((m, m), 1.0 / m, coarsest=4, device=dev)
+
+    def looped():
+        cyc = []
+        for r in rhs:
+            u = r.clone()
+            g = grids[r.shape[0]]
+            g.solve(r, u, 1e-4, tol=1e-10)
+            cyc.append(g.stats()["cycles"])
+        return cyc
+
+    def batched():
+        us = [r.clone() for r in rhs]
+        return solve_uneven(rhs, us, 1e-4, tol=1e-10)
+
+    looped()
+    batched()
+    t_loop, cyc_loop = _timed(looped, sync)
+    t_batch, (st, cyc_b) = _timed(batched, sync)
+    out = {"uneven": {"problems": len(rhs), "cells": int(sum(r.numel() for r in rhs)),
+                      "sizes": sorted(set(int(r.shape[0]) for r in rhs)),
+                      "batched_s": t_batch, "looped_s": t_loop, "speedup": t_loop / t_batch,
+                      "all_converged": all(s == 0 for s in st), "max_cycles": int(max(cyc_b))}}
+    del rhs, grids
+    q, n = 1189, 512
+    eta = torch.from_numpy(fas_inputs.grain_init(q, n)).to(dev)
+    model = GrainGrowth(q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, device=dev)
+    model.step(eta.clone())
+    steps = 3
+    t_grain, cys = _timed(lambda: [model.step(eta) for _ in range(steps)], sync)
+    out["grain"] = {"fields": q, "grid": [n, n], "s_per_step": t_grain / steps,
+                    "field_cells_per_s": q * n * n * steps / t_grain, "cycles_per_field": float(np.mean(cys[-1]))}
+    del eta, model
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_adjoint(dev):
+    """Differentiable 2D heat at 2048^2: kappa = exp(0.5 g), 20 steps, dt = 1e-4,
+    checkpoint every 4; forward + backward (gradients for u0 and kappa)."""
+    import torch
+
+    import fas_inputs
+    from paper_2510_11152_amd import Grid, HeatSolveFn
+
+    n, T, dt = 2048, 20, 1e-4
+    kap, u0, tgt = (torch.from_numpy(a).to(dev) for a in fas_inputs.adjoint_inputs(n))
+    g = Grid((n, n), 1.0 / n, coarsest=4, variable_kappa=True, device=dev)
+
+    def run():
+        a = u0.clone().requires_grad_(True)
+        k = kap.clone().requires_grad_(True)
+        uT = HeatSolveFn.apply(a, k, g, T, dt, 4, 1e-10, 2, 2)
+        loss = ((uT - tgt) ** 2).sum()
+        loss.backward()
+        return float(loss.item())
+
+    run()
+    t, loss = _timed(run, torch.cuda.synchronize)
+    return {"grid": [n, n], "steps": T, "ckpt": 4, "forward_backward_s": t, "loss": loss}
+
+
+def bench_3d(dev, steps=5):
+    """3D heat at 512^3 (7-point, 8-set X-MCGS, Neumann, dt = 1e-4): plain FP64 V(2,2)
+    steps to 1e-10, then the same steps with FP32 inner cycles in FP64 correction."""
+    import numpy as np
+    import torch
+
+    import fas_inputs
+    from paper_2510_11152_amd import Grid, solve_mixed
+
+    n, dt = 512, 1e-4
+    u0 = torch.from_numpy(fas_inputs.heat_3d(n)).to(dev)
+    g = Grid((n, n, n), 1.0 / n, coarsest=4, device=dev)
+    rhs = torch.empty_like(u0)
+
+    def plain(u):
+        cyc = []
+        for _ in range(steps):
+            rhs.copy_(u)
+            assert g.solve(rhs, u, dt, tol=1e-10) == 0
+            cyc.append(g.stats()["cycles"])
+        return cyc
+
+    u = u0.clone()
+    plain(u)
+    u = u0.clone()
+    t_plain, cyc = _timed(lambda: plain(u), torch.cuda.synchronize)
+    out = {"grid": [n, n, n], "steps": steps, "plain_s_per_step": t_plain / steps, "cycles_per_step": float(np.mean(cyc))}
+    g32 = Grid((n, n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev)
+
+    def mixed(v):
+        outer = []
+        for _ in range(steps):
+            rhs.copy_(v)
+            assert solve_mixed(g, g32, rhs, v, dt, tol=1e-10, inner=3) == 0
+            outer.append(g.stats()["cycles"])
+        return outer
+
+    v = u0.clone()
+    t_mixed, outer = _timed(lambda: mixed(v), torch.cuda.synchronize)
+    out.update({"mixed_s_per_step": t_mixed / steps, "mixed_outer_per_step": float(np.mean(outer)),
+                "mixed_speedup": t_plain / t_mixed,
+                "mixed_max_rel_diff": (v - u).abs().max().item() / u.abs().max().item()})
+    del g, g32, u0, rhs, u, v
+    torch.cuda.empty_cache()
+    return out
 
 
 def kernel_bytes(s, d):
@@ -182,6 +319,19 @@ def main():
                            "max_rel_diff_vs_plain_fp64": diff}
         print("bench: mixed %.4f s/step outer %s" % (t_mixed, outer), file=sys.stderr, flush=True)
         del g32
+
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    del g, rhs
+    torch.cuda.empty_cache()
+    if "batched" in forms:
+        print("bench: batched forms", file=sys.stderr, flush=True)
+        result["batched"] = bench_batched(dev)
+    if "adjoint" in forms:
+        print("bench: adjoint form", file=sys.stderr, flush=True)
+        result["adjoint"] = bench_adjoint(dev)
+    if "3d" in forms:
+        print("bench: 3D heat", file=sys.stderr, flush=True)
+        result["heat3d"] = bench_3d(dev)
 
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on one cycle", file=sys.stderr, flush=True)

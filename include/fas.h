@@ -72,6 +72,13 @@ extern "C" {
                                    recorded on the grid's stream (read with
                                    fas_get_profile); 0 (default): off                     */
 
+#define FAS_OPT_GRAPH 5         /* 1: capture each V-cycle in a HIP graph (replayed while the
+                                   arrays, coefficients and sweep counts stay the same);
+                                   0 (default): launch kernels one by one                 */
+#define FAS_OPT_AUTOTUNE 6      /* 1: on a level's first fused pass, time the candidate
+                                   segment heights of the march kernels and keep the
+                                   fastest (cached per process); 0 (default): fixed rule   */
+
 /* kernel classes reported by fas_get_profile */
 #define FAS_K_SMOOTH 0 /* stand-alone smoothing launches on the finest level              */
 #define FAS_K_PRE 1    /* residual + restriction (fused with pre-smoothing when fused)     */
@@ -169,6 +176,30 @@ typedef struct {
     int launches[FAS_K_COUNT]; /* finest-level launches per kernel class since the last reset */
     double ms[FAS_K_COUNT];    /* summed HIP-event durations of those launches (ms)         */
 } fas_profile_t;
+
+/* Batched solves (spec form 2; the paper solves its q grain-growth fields one
+ * after the other): `batch` independent problems of one shape, bc, h and dtype, kappa
+ * constant.  Every array argument holds the whole batch contiguously: problem b's
+ * array starts b * (cells per problem) elements in.  Each kernel launch serves every
+ * unconverged problem at once; the coarse tail is one workgroup per problem in a
+ * single launch.  Problem b stops once ||rhs_b - A u_b|| <= tol ||rhs_b|| (its later
+ * launches skip it), so each member's iterates equal those of solving it alone. */
+size_t fas_workspace_size_batched(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int batch);
+int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, int flags,
+                            int batch, void* workspace, size_t ws_bytes, void* stream, fas_grid_t* out);
+/* status_out / cycles_out (nullable, batch entries each): per-problem status and
+ * V-cycles.  Returns FAS_OK if all converged, else FAS_NOT_CONVERGED or
+ * FAS_ERR_NONFINITE.  Synchronises the stream once per cycle (one int). */
+int fas_solve_batched(fas_grid_t grid, double dt, double kappa, const void* rhs, void* u, double tol, int nu1,
+                      int nu2, int* status_out, int* cycles_out);
+
+/* Right-hand side of one semi-implicit step of the multi-order-parameter grain-growth
+ * model (Section 3.3.1, eq. grain-growth-equations with L = alpha = beta = gamma = 1):
+ * free energy sum_i (-eta_i^2/2 + eta_i^4/4) + (3/2) sum_{i<j} eta_i^2 eta_j^2, so
+ *     f_i = eta_i - dt * ((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)),  S = sum_j eta_j^2,
+ * and (I - dt kappa Lap) eta_i^{n+1} = f_i is then one batched solve.  eta, f: q fields
+ * of ncells FP32 values each, contiguous, device; stream: hipStream_t. */
+int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f);
 
 int fas_get_stats(fas_grid_t grid, fas_stats_t* out);
 /* Accumulated kernel times of a grid with FAS_OPT_PROFILE on (synchronises the stream);

@@ -22,6 +22,7 @@ FAS_F64, FAS_F32 = 0, 1
 FAS_FLAG_VARIABLE_KAPPA = 1
 FAS_FLAG_MIXED_INNER = 2
 FAS_OPT_KMAX, FAS_OPT_COARSE_SWEEPS, FAS_OPT_FUSED, FAS_OPT_PROFILE = 1, 2, 3, 4
+FAS_OPT_GRAPH, FAS_OPT_AUTOTUNE = 5, 6
 FAS_K_NAMES = ("smooth", "pre", "post", "norm")
 
 # Every function the header declares, with (restype, argtypes).
@@ -57,6 +58,10 @@ SIGNATURES = {
     "fas_prolong_add": (_i, [_vp, _i, _vp, _vp, _vp]),
     "fas_kappa_grad": (_i, [_vp, _d, _vp, _vp, _vp, _vp]),
     "fas_solve_mixed": (_i, [_vp, _vp, _d, _d, _vp, _vp, _vp, _d, _i, _i, _i]),
+    "fas_workspace_size_batched": (_sz, [_i, _pi64, _i, _i, _i, _i]),
+    "fas_grid_create_batched": (_i, [_i, _pi64, _d, _i, _i, _i, _i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "fas_solve_batched": (_i, [_vp, _d, _d, _vp, _vp, _d, _i, _i, _vp, _vp]),
+    "fas_grain_rhs": (_i, [_vp, _i, _i64, _d, _vp, _vp]),
     "fas_get_stats": (_i, [_vp, ctypes.POINTER(FasStats)]),
     "fas_get_profile": (_i, [_vp, ctypes.POINTER(FasProfile), _i]),
     "fas_last_error": (ctypes.c_char_p, []),

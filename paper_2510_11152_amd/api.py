@@ -27,8 +27,9 @@ class Grid:
     mixed_inner: FP32 grid used as the inner solver of solve_mixed."""
 
     def __init__(self, n, h, bc="neumann", dtype=torch.float64, coarsest=4, variable_kappa=False,
-                 mixed_inner=False, device="cuda", stream=None):
+                 mixed_inner=False, device="cuda", stream=None, batch=1):
         L = load()
+        self.batch = int(batch)
         self.n = tuple(int(x) for x in n)
         self.dim = len(self.n)
         self.h = float(h)
@@ -39,7 +40,7 @@ class Grid:
             self.device = torch.device("cuda", torch.cuda.current_device())
         flags = (_lib.FAS_FLAG_VARIABLE_KAPPA if variable_kappa else 0) | (_lib.FAS_FLAG_MIXED_INNER if mixed_inner else 0)
         n3 = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.dim)))
-        size = L.fas_workspace_size(self.dim, n3, _DT[dtype], coarsest, flags)
+        size = L.fas_workspace_size_batched(self.dim, n3, _DT[dtype], coarsest, flags, self.batch)
         if size == 0:
             raise ValueError("invalid grid: n=%s coarsest=%d" % (self.n, coarsest))
         self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
@@ -47,9 +48,9 @@ class Grid:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         h_out = ctypes.c_void_p()
-        check(L.fas_grid_create(self.dim, n3, self.h, _lib.FAS_BC[bc], _DT[dtype], coarsest, flags,
-                                _ptr(self.workspace), size, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_out)),
-              "fas_grid_create")
+        check(L.fas_grid_create_batched(self.dim, n3, self.h, _lib.FAS_BC[bc], _DT[dtype], coarsest, flags,
+                                        self.batch, _ptr(self.workspace), size, ctypes.c_void_p(stream.cuda_stream),
+                                        ctypes.byref(h_out)), "fas_grid_create_batched")
         self.handle = h_out
         self.levels = L.fas_grid_levels(self.handle)
 
@@ -62,7 +63,7 @@ class Grid:
     def shape(self, level=0):
         return tuple(m >> level for m in reversed(self.n))
 
-    def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None):
+    def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None):
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -72,6 +73,10 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_FUSED, float(int(fused))), "fas_grid_set")
         if profile is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_PROFILE, float(int(profile))), "fas_grid_set")
+        if graph is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_GRAPH, float(int(graph))), "fas_grid_set")
+        if autotune is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_AUTOTUNE, float(int(autotune))), "fas_grid_set")
         return self
 
     def profile(self, reset=True):
@@ -137,6 +142,20 @@ class Grid:
         check(load().fas_kappa_grad(self.handle, dt, _ptr(kappa_cell), _ptr(mu), _ptr(u), _ptr(gkappa)),
               "fas_kappa_grad")
 
+    def solve_batched(self, rhs, u, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2):
+        """All `batch` problems at once; rhs, u shaped (batch, *shape).  Returns
+        (status per problem, V-cycles per problem) as lists."""
+        want = (self.batch,) + self.shape()
+        for t, nm in ((rhs, "rhs"), (u, "u")):
+            if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != want:
+                raise ValueError("%s must be a contiguous %s tensor of shape %s on %s" % (nm, self.dtype, want, self.device))
+        st = (ctypes.c_int * self.batch)()
+        cy = (ctypes.c_int * self.batch)()
+        code = load().fas_solve_batched(self.handle, dt, kappa, _ptr(rhs), _ptr(u), tol, nu1, nu2, st, cy)
+        if code not in (_lib.FAS_OK, _lib.FAS_NOT_CONVERGED):
+            check(code, "fas_solve_batched")
+        return list(st), list(cy)
+
     def stats(self):
         s = _lib.FasStats()
         check(load().fas_get_stats(self.handle, ctypes.byref(s)), "fas_get_stats")
@@ -166,3 +185,26 @@ def heat(grid, u0, steps, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=
         if keep:
             states.append(u.clone())
     return (u, states) if keep else u
+
+
+def solve_uneven(rhs_list, u_list, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2, coarsest=4, bc="neumann"):
+    """Problems of different sizes on the unit square (h = 1/n): one batched solve per
+    distinct shape.  u_list entries are updated in place.  Returns per-problem
+    (status, V-cycles) lists in input order."""
+    groups = {}
+    for i, (r, u) in enumerate(zip(rhs_list, u_list)):
+        if r.shape != u.shape or r.dtype != u.dtype:
+            raise ValueError("rhs and u of problem %d differ in shape or dtype" % i)
+        groups.setdefault((tuple(r.shape), r.dtype, r.device), []).append(i)
+    status = [None] * len(rhs_list)
+    cycles = [None] * len(rhs_list)
+    for (shape, dtype, device), idx in groups.items():
+        n = tuple(reversed(shape))
+        g = Grid(n, 1.0 / n[0], bc=bc, dtype=dtype, coarsest=coarsest, device=device, batch=len(idx))
+        R = torch.stack([rhs_list[i] for i in idx]).contiguous()
+        U = torch.stack([u_list[i] for i in idx]).contiguous()
+        st, cy = g.solve_batched(R, U, dt, kappa, tol, nu1, nu2)
+        for k, i in enumerate(idx):
+            u_list[i].copy_(U[k])
+            status[i], cycles[i] = st[k], cy[k]
+    return status, cycles

@@ -2,9 +2,12 @@
 // (Alg. 1 applied recursively, Remarks 1-2) and the mixed-precision defect correction.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <string>
+#include <vector>
 
 #include "fas_fused.h"
 #include "fas_tail.h"
@@ -49,13 +52,16 @@ struct Layout {
     int L;
     int n[fas::kMaxLevels][3];
     size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], kap[fas::kMaxLevels];
-    size_t mix_e, mix_r, partials, norm_out, total;
+    size_t mix_e, mix_r, partials, norm_out, active, cyc, rnorm, count, total;
     int npartials;
 };
 
 // Returns 0 or an error code (FAS_ERR_SHAPE / FAS_ERR_ARG) with a message.
-int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, Layout* lay, std::string* why)
+int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int batch, Layout* lay, std::string* why)
 {
+    if (batch < 1) return *why = "batch must be >= 1", FAS_ERR_ARG;
+    if (batch > 1 && (flags & (FAS_FLAG_VARIABLE_KAPPA | FAS_FLAG_MIXED_INNER)))
+        return *why = "batched grids take a constant kappa and no mixed-precision storage", FAS_ERR_ARG;
     if (dim != 2 && dim != 3) return *why = "dim must be 2 or 3", FAS_ERR_ARG;
     if (dtype != FAS_F64 && dtype != FAS_F32) return *why = "dtype must be FAS_F64 or FAS_F32", FAS_ERR_ARG;
     if (flags & ~(FAS_FLAG_VARIABLE_KAPPA | FAS_FLAG_MIXED_INNER)) return *why = "unknown flags", FAS_ERR_ARG;
@@ -78,7 +84,7 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, Layout
     int64_t N0 = 1;
     for (int a = 0; a < dim; ++a) N0 *= n[a];
     if (N0 >= ((int64_t)1 << 31)) return *why = "grid too large (>= 2^31 cells)", FAS_ERR_SHAPE;
-    const size_t s = dtype == FAS_F64 ? 8 : 4;
+    const size_t s = (dtype == FAS_F64 ? 8 : 4) * (size_t)batch;  // level arrays hold the whole batch
     lay->L = L;
     size_t off = 0;
     for (int l = 0; l <= L; ++l) {
@@ -114,11 +120,21 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, Layout
     // the stand-alone norm kernel
     int64_t tiles = 1;
     for (int a = 0; a < dim; ++a) tiles *= (n[a] + (a == 0 ? 63 : 31)) / (a == 0 ? 64 : 32);
-    lay->npartials = (int)(tiles > fas::kPartials ? tiles : fas::kPartials);
+    const int64_t per = tiles > fas::kPartials ? tiles : fas::kPartials;
+    if (per * batch >= ((int64_t)1 << 31)) return *why = "batch too large", FAS_ERR_SHAPE;
+    lay->npartials = (int)(per * batch);
     lay->partials = off;
     off = align_up(off + (size_t)lay->npartials * sizeof(double));
     lay->norm_out = off;
-    off = align_up(off + 8 * sizeof(double));
+    off = align_up(off + (size_t)(batch + 8) * sizeof(double));
+    lay->rnorm = off;
+    off = align_up(off + (size_t)batch * sizeof(double));
+    lay->active = off;
+    off = align_up(off + (size_t)batch * sizeof(int));
+    lay->cyc = off;
+    off = align_up(off + (size_t)batch * sizeof(int));
+    lay->count = off;
+    off = align_up(off + 8 * sizeof(int));
     lay->total = off;
     return 0;
 }
@@ -231,6 +247,8 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 // FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
 // partials != nullptr asks the finest-level post-smoothing to leave per-tile residual
 // partial sums there; returns the number written (0 if it could not).
+void autotune_level(fas_grid* g, int l, int first, int pre, const void* f, const void* u);
+
 // Coarse part of a cycle below level l: the persistent tail when level l + 1 is its top
 // (the FAS right-hand side is formed inside it), else the coarse right-hand side and
 // the recursion.
@@ -261,8 +279,37 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         fas::launch_tail(g, 0, g->coef, pre, post, first, u, f, false);
         return 0;
     }
+    if (fas::fused3_ok(g, l, g->lev[l].kap != nullptr) && pre >= 1 && post >= 1) {
+        // 3D: one sweep per pass, ping-pong between u and the level's second buffer
+        void* bufs[2] = {u, g->lev[l].x};
+        int cur = 0;
+        autotune_level(g, l, first, 1, f, u);
+        if (partials && fas::fused3_partials(g, l) > g->npartials / g->batch) partials = nullptr;
+        {
+            ProfScope ps(g, l, FAS_K_PRE);
+            for (int i = 0; i < pre - 1; ++i, cur ^= 1)
+                fas::launch_march3(g, l, g->coef[l], first, 2, 1, false, f, bufs[cur], bufs[cur ^ 1], nullptr, nullptr,
+                                   nullptr);
+            fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, bufs[cur], bufs[cur ^ 1], C.u, C.f, nullptr);
+            cur ^= 1;
+            ps.end();
+        }
+        coarse_part(g, l, pre, post, rev);
+        {
+            ProfScope ps(g, l, FAS_K_POST);
+            for (int i = 0; i < post; ++i, cur ^= 1)
+                fas::launch_march3(g, l, g->coef[l], first, i == 0 ? 1 : 2, 1, partials && i == post - 1, f, bufs[cur],
+                                   bufs[cur ^ 1], i == 0 ? C.u : nullptr, nullptr, partials);
+            ps.end();
+        }
+        if (cur != 0)
+            FAS_HIP_CHECK(hipMemcpyAsync(u, bufs[1], (size_t)g->lev[l].N * g->elem() * g->batch, hipMemcpyDeviceToDevice,
+                                         g->stream));
+        return partials ? fas::fused3_partials(g, l) : 0;
+    }
     if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
         void* x = g->lev[l].x;
+        autotune_level(g, l, first, pre, f, u);
         {
             ProfScope ps(g, l, FAS_K_PRE);
             fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, x, C.u, C.f);
@@ -309,9 +356,136 @@ void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
     ps.end();
 }
 
-void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1, int nu2, double tol)
+// ---- autotuner: segment height of the march kernels ------------------------------------
+// Candidates are timed on the level's own data (the pre pass is out of place, so running
+// it again recomputes the same outputs); the fastest is kept per grid and per process.
+std::map<std::string, int>& tune_cache()
+{
+    static std::map<std::string, int> cache;
+    return cache;
+}
+
+void autotune_level(fas_grid* g, int l, int first, int pre, const void* f, const void* u)
+{
+    if (!g->autotune || g->seg_rows[l]) return;
+    const bool d3 = g->dim == 3;
+    char key[160];
+    snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->lev[l].n[2], g->dtype,
+             g->batch, pre);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+        g->seg_rows[l] = it->second;
+        return;
+    }
+    const int cands2[] = {16, 32, 64, 128, 256};
+    const int cands3[] = {8, 16, 32, 64, 128};
+    hipEvent_t e0, e1;
+    FAS_HIP_CHECK(hipEventCreate(&e0));
+    FAS_HIP_CHECK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_rows = 0;
+    fas::Level& C = g->lev[l + 1];
+    for (int c = 0; c < 5; ++c) {
+        const int rows = d3 ? cands3[c] : cands2[c];
+        if (rows > (d3 ? g->lev[l].n[2] : g->lev[l].n[1])) break;
+        g->seg_rows[l] = rows;
+        float total = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            FAS_HIP_CHECK(hipEventRecord(e0, g->stream));
+            if (d3)
+                fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, u, g->lev[l].x, C.u, C.f, nullptr);
+            else
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, g->lev[l].x, C.u, C.f);
+            FAS_HIP_CHECK(hipEventRecord(e1, g->stream));
+            FAS_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            FAS_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep) total += ms;  // the first launch warms caches
+        }
+        if (total < best) {
+            best = total;
+            best_rows = rows;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->seg_rows[l] = best_rows;
+    tune_cache()[key] = best_rows;
+}
+
+// ---- HIP graph of one V-cycle ------------------------------------------------------------
+// Captured on a private stream (the caller's may be the legacy default stream, which
+// cannot be captured) and replayed on the grid's stream; valid while the arrays,
+// coefficients and sweep counts are those it was captured with.
+struct GraphCache {
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* rhs = nullptr;
+    void* u = nullptr;
+    const void* kap = nullptr;
+    double kd0 = 0.0;
+    int nu1 = -1, nu2 = -1, batch_active = 0;
+    bool transposed = false, want_norm = false;
+    int np = 0;
+    void drop()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed, bool want_norm);
+
+void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed, bool want_norm)
+{
+    if (!g->use_graph || g->profile) {
+        vcycle_top(g, f, u, nu1, nu2, transposed, want_norm);
+        return;
+    }
+    if (!g->graph_cache) g->graph_cache = new GraphCache();
+    GraphCache& gc = *(GraphCache*)g->graph_cache;
+    const bool same = gc.exec && gc.rhs == f && gc.u == u && gc.kap == g->lev[0].kap && gc.kd0 == g->coef[0].kd &&
+                      gc.nu1 == nu1 && gc.nu2 == nu2 && gc.transposed == transposed && gc.want_norm == want_norm &&
+                      gc.batch_active == (g->batch > 1);
+    if (!same) {
+        gc.drop();
+        if (!gc.cap) FAS_HIP_CHECK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+        hipStream_t saved = g->stream;
+        g->stream = gc.cap;
+        FAS_HIP_CHECK(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
+        try {
+            vcycle_top(g, f, u, nu1, nu2, transposed, want_norm);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(gc.cap, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            g->stream = saved;
+            throw;
+        }
+        g->stream = saved;
+        FAS_HIP_CHECK(hipStreamEndCapture(gc.cap, &gc.graph));
+        FAS_HIP_CHECK(hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0));
+        gc.rhs = f;
+        gc.u = u;
+        gc.kap = g->lev[0].kap;
+        gc.kd0 = g->coef[0].kd;
+        gc.nu1 = nu1;
+        gc.nu2 = nu2;
+        gc.transposed = transposed;
+        gc.want_norm = want_norm;
+        gc.batch_active = g->batch > 1;
+    }
+    FAS_HIP_CHECK(hipGraphLaunch(gc.exec, g->stream));
+}
+
+void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1, int nu2, double tol,
+                      bool batched = false)
 {
     check_grid(g);
+    if (g->batch > 1 && !batched) throw Error(FAS_ERR_ARG, "batched grid: use fas_solve_batched");
     if (!rhs || !u) throw Error(FAS_ERR_ARG, "null rhs or u");
     if (rhs == u) throw Error(FAS_ERR_ARG, "rhs and u must not alias");
     if (nu1 < 0 || nu2 < 0 || nu1 + nu2 == 0) throw Error(FAS_ERR_ARG, "need nu1, nu2 >= 0 and nu1 + nu2 > 0");
@@ -331,7 +505,7 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     int status = FAS_NOT_CONVERGED;
     int k;
     for (k = 1; k <= g->kmax; ++k) {
-        vcycle_top(g, rhs, u, nu1, nu2, transposed, true);
+        vcycle_run(g, rhs, u, nu1, nu2, transposed, true);
         const double nr = read_norm(g);
         const double rel = nf > 0.0 ? nr / nf : nr;
         if (k <= 64) g->stats.rel_res[k - 1] = rel;
@@ -376,15 +550,26 @@ extern "C" {
 
 size_t fas_workspace_size(int dim, const int64_t n[3], int dtype, int coarsest, int flags)
 {
+    return fas_workspace_size_batched(dim, n, dtype, coarsest, flags, 1);
+}
+
+size_t fas_workspace_size_batched(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int batch)
+{
     if (!n) return 0;
     Layout lay;
     std::string why;
-    if (plan(dim, n, dtype, coarsest, flags, &lay, &why)) return 0;
+    if (plan(dim, n, dtype, coarsest, flags, batch, &lay, &why)) return 0;
     return lay.total;
 }
 
 int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, int flags, void* workspace,
                     size_t ws_bytes, void* stream, fas_grid_t* out)
+{
+    return fas_grid_create_batched(dim, n, h, bc, dtype, coarsest, flags, 1, workspace, ws_bytes, stream, out);
+}
+
+int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, int flags,
+                            int batch, void* workspace, size_t ws_bytes, void* stream, fas_grid_t* out)
 {
     return guarded([&]() -> int {
         if (!out || !n) return fail(FAS_ERR_ARG, "null argument");
@@ -394,7 +579,7 @@ int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, in
             return fail(FAS_ERR_ARG, "unknown boundary condition");
         Layout lay;
         std::string why;
-        int rc = plan(dim, n, dtype, coarsest, flags, &lay, &why);
+        int rc = plan(dim, n, dtype, coarsest, flags, batch, &lay, &why);
         if (rc) return fail(rc, why);
         if (bc == FAS_BC_PERIODIC)
             for (int a = 0; a < dim; ++a)
@@ -433,6 +618,11 @@ int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, in
         g->partials = (double*)(base + lay.partials);
         g->norm_out = (double*)(base + lay.norm_out);
         g->npartials = lay.npartials;
+        g->batch = batch;
+        g->rnorm = (double*)(base + lay.rnorm);
+        g->active = (int*)(base + lay.active);
+        g->cyc = (int*)(base + lay.cyc);
+        g->count = (int*)(base + lay.count);
         g->stream = (hipStream_t)stream;
         g->kmax = 100;
         g->nuc = 2;
@@ -446,6 +636,12 @@ int fas_grid_create(int dim, const int64_t n[3], double h, int bc, int dtype, in
 int fas_grid_destroy(fas_grid_t g)
 {
     if (!g) return FAS_OK;
+    if (g->graph_cache) {
+        GraphCache* gc = (GraphCache*)g->graph_cache;
+        gc->drop();
+        if (gc->cap) (void)hipStreamDestroy(gc->cap);
+        delete gc;
+    }
     if (g->host) (void)hipHostFree(g->host);
     for (int i = 0; i < g->ev_created; ++i) (void)hipEventDestroy(g->ev[i]);
     delete g;
@@ -470,6 +666,16 @@ int fas_grid_set(fas_grid_t g, int option, double value)
             case FAS_OPT_PROFILE:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "profile must be 0 or 1");
                 g->profile = v;
+                return FAS_OK;
+            case FAS_OPT_GRAPH:
+                if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "graph must be 0 or 1");
+                g->use_graph = v;
+                return FAS_OK;
+            case FAS_OPT_AUTOTUNE:
+                if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "autotune must be 0 or 1");
+                g->autotune = v;
+                if (!v)
+                    for (int l = 0; l < fas::kMaxLevels; ++l) g->seg_rows[l] = 0;
                 return FAS_OK;
             case FAS_OPT_FUSED:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "fused must be 0 or 1");
@@ -524,6 +730,7 @@ int fas_smooth(fas_grid_t g, int level, double dt, double kappa, const void* kap
 {
     return guarded([&]() -> int {
         check_grid(g);
+        if (g->batch > 1) return fail(FAS_ERR_ARG, "building blocks take a single-problem grid");
         check_level(g, level, false);
         if (!rhs || !u || rhs == u || sweeps < 0) return fail(FAS_ERR_ARG, "bad smoother arguments");
         if (kappa_cell && !(g->flags & FAS_FLAG_VARIABLE_KAPPA))
@@ -544,6 +751,7 @@ int fas_residual(fas_grid_t g, int level, double dt, double kappa, const void* k
 {
     return guarded([&]() -> int {
         check_grid(g);
+        if (g->batch > 1) return fail(FAS_ERR_ARG, "building blocks take a single-problem grid");
         check_level(g, level, false);
         if (!rhs || !u || !r || r == u || r == rhs) return fail(FAS_ERR_ARG, "bad residual arguments");
         if (kappa_cell && !(g->flags & FAS_FLAG_VARIABLE_KAPPA))
@@ -562,6 +770,7 @@ int fas_restrict(fas_grid_t g, int level, const void* fine, void* coarse)
 {
     return guarded([&]() -> int {
         check_grid(g);
+        if (g->batch > 1) return fail(FAS_ERR_ARG, "building blocks take a single-problem grid");
         check_level(g, level, true);
         if (!fine || !coarse || fine == coarse) return fail(FAS_ERR_ARG, "bad restriction arguments");
         fas::launch_restrict(g, level, fine, coarse);
@@ -573,6 +782,7 @@ int fas_prolong_add(fas_grid_t g, int level, const void* c_new, const void* c_ol
 {
     return guarded([&]() -> int {
         check_grid(g);
+        if (g->batch > 1) return fail(FAS_ERR_ARG, "building blocks take a single-problem grid");
         check_level(g, level, true);
         if (!c_new || !c_old || !fine) return fail(FAS_ERR_ARG, "bad prolongation arguments");
         fas::launch_prolong_add(g, level, c_new, c_old, fine);
@@ -584,7 +794,7 @@ int fas_kappa_grad(fas_grid_t g, double dt, const void* kappa_cell, const void* 
 {
     return guarded([&]() -> int {
         check_grid(g);
-        if (g->dtype != FAS_F64) return fail(FAS_ERR_ARG, "fas_kappa_grad needs an FP64 grid");
+        if (g->dtype != FAS_F64 || g->batch > 1) return fail(FAS_ERR_ARG, "fas_kappa_grad needs a single FP64 grid");
         if (!kappa_cell || !mu || !u || !gkappa) return fail(FAS_ERR_ARG, "null argument");
         if (gkappa == mu || gkappa == u || gkappa == kappa_cell) return fail(FAS_ERR_ARG, "gkappa must not alias");
         set_coefs(g, dt, 1.0, true);
@@ -599,6 +809,7 @@ int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, con
     return guarded([&]() -> int {
         check_solve_args(g64, rhs, u, nu1, nu2, tol);
         check_grid(g32);
+        if (g32->batch > 1) return fail(FAS_ERR_ARG, "mixed precision takes single-problem grids");
         if (g64->dtype != FAS_F64 || g32->dtype != FAS_F32 || !(g32->flags & FAS_FLAG_MIXED_INNER))
             return fail(FAS_ERR_ARG, "need an FP64 grid and an FP32 grid created with FAS_FLAG_MIXED_INNER");
         if (g64->dim != g32->dim || g64->bc != g32->bc || g64->h != g32->h || g64->L != g32->L)
@@ -644,6 +855,58 @@ int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, con
         g64->stats.status = status;
         if (status != FAS_OK) g_last_error = "not converged within kmax outer iterations";
         return status;
+    });
+}
+
+int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, void* u, double tol, int nu1, int nu2,
+                      int* status_out, int* cycles_out)
+{
+    return guarded([&]() -> int {
+        check_solve_args(g, rhs, u, nu1, nu2, tol, true);
+        set_coefs(g, dt, kappa, false);
+        set_kappa(g, nullptr, false);
+        memset(&g->stats, 0, sizeof(g->stats));
+        fas::launch_init_active(g);
+        fas::launch_resid_norm(g, 0, g->coef[0], nullptr, rhs, nullptr);  // ||rhs||^2 per problem
+        FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, (size_t)g->batch * sizeof(double),
+                                     hipMemcpyDeviceToDevice, g->stream));
+        if (!g->host) FAS_HIP_CHECK(hipHostMalloc((void**)&g->host, 64, hipHostMallocDefault));
+        int k;
+        for (k = 1; k <= g->kmax; ++k) {
+            vcycle_run(g, rhs, u, nu1, nu2, false, true);
+            fas::launch_update_active(g, tol, k);
+            FAS_HIP_CHECK(hipMemcpyAsync(g->host, g->count, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+            FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
+            if (((int*)g->host)[0] == 0) break;
+        }
+        std::vector<int> cyc((size_t)g->batch);
+        FAS_HIP_CHECK(hipMemcpyAsync(cyc.data(), g->cyc, cyc.size() * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+        FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
+        int worst = FAS_OK, maxc = 0;
+        for (int b = 0; b < g->batch; ++b) {
+            const int c = cyc[(size_t)b];
+            const int st = c > 0 ? FAS_OK : (c < 0 ? FAS_ERR_NONFINITE : FAS_NOT_CONVERGED);
+            const int cycles = c > 0 ? c : (c < 0 ? -c : g->kmax);
+            if (status_out) status_out[b] = st;
+            if (cycles_out) cycles_out[b] = cycles;
+            if (st == FAS_ERR_NONFINITE) worst = FAS_ERR_NONFINITE;
+            else if (st == FAS_NOT_CONVERGED && worst == FAS_OK) worst = FAS_NOT_CONVERGED;
+            maxc = cycles > maxc ? cycles : maxc;
+        }
+        g->stats.cycles = maxc;
+        g->stats.status = worst;
+        if (worst == FAS_ERR_NONFINITE) return fail(FAS_ERR_NONFINITE, "a residual norm is not finite");
+        if (worst == FAS_NOT_CONVERGED) g_last_error = "some problems did not converge within kmax cycles";
+        return worst;
+    });
+}
+
+int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f)
+{
+    return guarded([&]() -> int {
+        if (q < 1 || ncells < 1 || !eta || !f || eta == f) return fail(FAS_ERR_ARG, "bad grain-growth arguments");
+        fas::launch_grain_rhs((hipStream_t)stream, q, ncells, (float)dt, (const float*)eta, (float*)f);
+        return FAS_OK;
     });
 }
 

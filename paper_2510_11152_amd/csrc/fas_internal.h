@@ -54,15 +54,25 @@ struct fas_grid {
     double h;
     fas::Level lev[fas::kMaxLevels];
     hipStream_t stream;
-    double* partials;    // per-block / per-tile partial sums of a norm (npartials), device
-    double* norm_out;    // reduced sum of squares, device
+    double* partials;    // per-block / per-wave partial sums of a norm (npartials), device
+    double* norm_out;    // reduced sum of squares, one per problem, device
     int npartials;
+    // batched grids: `batch` same-shape problems, level arrays contiguous across problems
+    int batch;
+    int* active;         // per-problem flag: still iterating (device)
+    int* cyc;            // per-problem cycle count at convergence (device)
+    double* rnorm;       // per-problem ||rhs||^2 (device)
+    int* count;          // number of active problems (device, 1 int)
     double* host;        // pinned host scalars
     void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
     void* mix_r;
     int kmax, nuc, fused;
     fas::Coef coef[fas::kMaxLevels];
     fas_stats_t stats;
+    // HIP graph of one V-cycle (FAS_OPT_GRAPH) and march segment heights (FAS_OPT_AUTOTUNE)
+    int use_graph, autotune;
+    void* graph_cache;            // GraphCache (fas_api.hip)
+    int seg_rows[fas::kMaxLevels];  // 0: default rule; else rows (2D) / planes (3D) per segment
     // profiler (FAS_OPT_PROFILE): event pairs around finest-level launches
     int profile;
     hipEvent_t ev[2 * fas::kMaxEvents];
@@ -98,5 +108,13 @@ void launch_scale_cast(const fas_grid* g, const Coef& c, const void* kap, const 
                        double rho, void* r32, void* e32);
 void launch_update_mixed(const fas_grid* g, double rho, const void* e32, void* u);
 void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst32);
+// Batched solves: every problem active, cycle counts zero.
+void launch_init_active(const fas_grid* g);
+// After cycle k: problems with norm_out <= tol^2 * rnorm (or 0) stop and record k;
+// a non-finite norm stops with -k; g->count gets the number still active.
+void launch_update_active(const fas_grid* g, double tol, int k);
+// Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32):
+// S = sum_j eta_j^2; f_i = eta_i - dt*((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)).
+void launch_grain_rhs(hipStream_t stream, int q, int64_t N, float dt, const float* eta, float* f);
 
 }  // namespace fas

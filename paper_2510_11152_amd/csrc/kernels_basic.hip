@@ -14,6 +14,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Batched grids: problem b = blockIdx.y; level arrays of consecutive problems are
+// `fine` (this level) / `coarse` (next level) elements apart; inactive problems skip.
+struct Batch {
+    int64_t fine, coarse;
+    const int* act;
+};
+
+__device__ __forceinline__ bool skip_problem(const Batch& bt) { return bt.act && !bt.act[blockIdx.y]; }
+
 template <typename T>
 Op<T> make_op(const fas_grid* g, int l, const Coef& c, const void* kap)
 {
@@ -30,6 +39,18 @@ Op<T> make_op(const fas_grid* g, int l, const Coef& c, const void* kap)
 
 inline unsigned blocks_for(int64_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
 
+// Batch descriptor of level l (its own arrays and the next level's).
+inline Batch batch_of(const fas_grid* g, int l)
+{
+    Batch b;
+    b.fine = g->lev[l].N;
+    b.coarse = l < g->L ? g->lev[l + 1].N : 0;
+    b.act = g->batch > 1 ? g->active : nullptr;
+    return b;
+}
+
+inline dim3 grid2(unsigned blocks, const fas_grid* g) { return dim3(blocks, (unsigned)g->batch, 1); }
+
 inline void check_launch()
 {
     hipError_t e = hipGetLastError();
@@ -40,8 +61,11 @@ inline void check_launch()
 // One colour phase: every cell whose 0-based index sum has `parity`; one thread per
 // pair of x-neighbours (exactly one of the two has the parity).
 template <typename T, int DIM, bool KV>
-__global__ __launch_bounds__(kBlock) void k_smooth_phase(Op<T> op, const T* __restrict__ f, T* u, int parity)
+__global__ __launch_bounds__(kBlock) void k_smooth_phase(Op<T> op, const T* __restrict__ f, T* u, int parity, Batch bt)
 {
+    if (skip_problem(bt)) return;
+    f += blockIdx.y * bt.fine;
+    u += blockIdx.y * bt.fine;
     const int half = (op.n0 + 1) >> 1;
     const int64_t total = (int64_t)half * op.n1 * op.n2;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,8 +85,12 @@ __global__ __launch_bounds__(kBlock) void k_smooth_phase(Op<T> op, const T* __re
 // --------------------------------------------------------------------------- residual
 template <typename T, int DIM, bool KV>
 __global__ __launch_bounds__(kBlock) void k_residual(Op<T> op, const T* __restrict__ f, const T* __restrict__ u,
-                                                     T* __restrict__ r)
+                                                     T* __restrict__ r, Batch bt)
 {
+    if (skip_problem(bt)) return;
+    f += blockIdx.y * bt.fine;
+    u += blockIdx.y * bt.fine;
+    r += blockIdx.y * bt.fine;
     const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -90,8 +118,12 @@ __device__ void block_sum_store(double v, double* out)
 // Sum of r^2 (r = f - A u), or of f^2 when u == nullptr; grid-stride with a fixed grid.
 template <typename T, int DIM, bool KV>
 __global__ __launch_bounds__(kBlock) void k_resid_norm(Op<T> op, const T* __restrict__ f,
-                                                       const T* __restrict__ u, double* __restrict__ partials)
+                                                       const T* __restrict__ u, double* __restrict__ partials, Batch bt)
 {
+    if (skip_problem(bt)) return;
+    f += blockIdx.y * bt.fine;
+    if (u) u += blockIdx.y * bt.fine;
+    partials += (int64_t)blockIdx.y * gridDim.x;
     const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
     double acc = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
@@ -111,9 +143,11 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Op<T> op, const T* __rest
     block_sum_store(acc, partials);
 }
 
+// One block per problem: out[b] = fixed-order sum of partials[b*count .. b*count + count).
 __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials, int count,
                                                           double* __restrict__ out)
 {
+    partials += (int64_t)blockIdx.x * count;
     double acc = 0.0;
     for (int b = threadIdx.x; b < count; b += kBlock) acc += partials[b];
     __shared__ double red[kBlock];
@@ -123,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
         if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // ----------------------------------------------------------- residual + restriction
@@ -131,8 +165,13 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
 template <typename T, int DIM, bool KV>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(Op<T> op, const T* __restrict__ f,
                                                            const T* __restrict__ u, T* __restrict__ uc,
-                                                           T* __restrict__ rc)
+                                                           T* __restrict__ rc, Batch bt)
 {
+    if (skip_problem(bt)) return;
+    f += blockIdx.y * bt.fine;
+    u += blockIdx.y * bt.fine;
+    uc += blockIdx.y * bt.coarse;
+    rc += blockIdx.y * bt.coarse;
     const int m0 = op.n0 >> 1, m1 = op.n1 >> 1, m2 = DIM == 3 ? op.n2 >> 1 : 1;
     const int64_t Nc = (int64_t)m0 * m1 * m2;
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,8 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Op<T> op, const T* __
 // FAS coarse right-hand side in place: fc = rc + Ac(uc) (Alg. 1 coarse source term; fc
 // holds rc on entry, the paper's memory reuse).
 template <typename T, int DIM, bool KV>
-__global__ __launch_bounds__(kBlock) void k_coarse_rhs(Op<T> op, const T* __restrict__ uc, T* __restrict__ fc)
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs(Op<T> op, const T* __restrict__ uc, T* __restrict__ fc,
+                                                       Batch bt)
 {
+    if (skip_problem(bt)) return;
+    uc += blockIdx.y * bt.fine;
+    fc += blockIdx.y * bt.fine;
     const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -194,8 +237,11 @@ __device__ __forceinline__ T restrict_at(const T* __restrict__ x, int n0, int n1
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_restrict(int n0, int n1, int n2, const T* __restrict__ fine,
-                                                     T* __restrict__ coarse)
+                                                     T* __restrict__ coarse, Batch bt)
 {
+    if (skip_problem(bt)) return;
+    fine += blockIdx.y * bt.fine;
+    coarse += blockIdx.y * bt.coarse;
     const int m0 = n0 >> 1, m1 = n1 >> 1, m2 = DIM == 3 ? n2 >> 1 : 1;
     const int64_t Nc = (int64_t)m0 * m1 * m2;
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -210,8 +256,12 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int n0, int n1, int n2, con
 // With cold != nullptr the old coarse value is read from cold instead.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_prolong(int n0, int n1, int n2, const T* __restrict__ uc,
-                                                    const T* __restrict__ cold, T* __restrict__ u)
+                                                    const T* __restrict__ cold, T* __restrict__ u, Batch bt)
 {
+    if (skip_problem(bt)) return;
+    uc += blockIdx.y * bt.coarse;
+    if (cold) cold += blockIdx.y * bt.coarse;
+    u += blockIdx.y * bt.fine;
     const int m0 = n0 >> 1, m1 = n1 >> 1, m2 = DIM == 3 ? n2 >> 1 : 1;
     const int64_t Nc = (int64_t)m0 * m1 * m2;
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,6 +354,66 @@ __global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t N, const double* __
     dst[p] = (float)src[p];
 }
 
+// ----------------------------------------------------------- batched convergence flags
+__global__ __launch_bounds__(kBlock) void k_init_active(int* act, int* cyc, int nb)
+{
+    for (int b = blockIdx.x * kBlock + threadIdx.x; b < nb; b += gridDim.x * kBlock) {
+        act[b] = 1;
+        cyc[b] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_active(const double* __restrict__ norm2,
+                                                          const double* __restrict__ rnorm2, double tol2, int k,
+                                                          int* __restrict__ act, int* __restrict__ cyc, int nb,
+                                                          int* __restrict__ count)
+{
+    __shared__ int red[kBlock];
+    int alive = 0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        if (!act[b]) continue;
+        const double nr = norm2[b];
+        if (!isfinite(nr)) {
+            act[b] = 0;
+            cyc[b] = -k;
+        } else if (nr <= tol2 * rnorm2[b] || nr == 0.0) {
+            act[b] = 0;
+            cyc[b] = k;
+        } else {
+            ++alive;
+        }
+    }
+    red[threadIdx.x] = alive;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[0] = red[0];
+}
+
+// ----------------------------------------------------------- grain-growth right-hand side
+// Fan-Chen free energy f = sum_i (-eta_i^2/2 + eta_i^4/4) + (3/2) sum_{i<j} eta_i^2 eta_j^2:
+// d f/d eta_i = (eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2), S = sum_j eta_j^2 (summed in j
+// order); semi-implicit step right-hand side f_i = eta_i - dt * d f/d eta_i.
+__global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, float dt, const float* __restrict__ eta,
+                                                      float* __restrict__ f)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    float S = eta[p] * eta[p];
+    for (int j = 1; j < q; ++j) {
+        const float e = eta[(int64_t)j * N + p];
+        S = S + e * e;
+    }
+    for (int i = 0; i < q; ++i) {
+        const float e = eta[(int64_t)i * N + p];
+        const float e2 = e * e;
+        const float g = (e2 * e - e) + (3.0f * e) * (S - e2);
+        f[(int64_t)i * N + p] = e - dt * g;
+    }
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------------- dispatch
@@ -336,47 +446,48 @@ void launch_smooth_phase(const fas_grid* g, int l, const Coef& c, const void* ka
 {
     const Level& L = g->lev[l];
     const int64_t work = (int64_t)((L.n[0] + 1) / 2) * L.n[1] * L.n[2];
-    FAS_DISPATCH(g, kap, (k_smooth_phase<T, D, KV><<<blocks_for(work), kBlock, 0, g->stream>>>(
-                             make_op<T>(g, l, c, kap), (const T*)f, (T*)u, parity)));
+    FAS_DISPATCH(g, kap, (k_smooth_phase<T, D, KV><<<grid2(blocks_for(work), g), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (T*)u, parity, batch_of(g, l))));
     check_launch();
 }
 
 void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u,
                      void* r)
 {
-    FAS_DISPATCH(g, kap, (k_residual<T, D, KV><<<blocks_for(g->lev[l].N), kBlock, 0, g->stream>>>(
-                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, (T*)r)));
+    FAS_DISPATCH(g, kap, (k_residual<T, D, KV><<<grid2(blocks_for(g->lev[l].N), g), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, (T*)r, batch_of(g, l))));
     check_launch();
 }
 
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u)
 {
     unsigned nb = blocks_for(g->lev[l].N);
-    if (nb > (unsigned)kPartials) nb = kPartials;
-    FAS_DISPATCH(g, kap, (k_resid_norm<T, D, KV><<<nb, kBlock, 0, g->stream>>>(
-                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, g->partials)));
+    const unsigned cap = (unsigned)(g->npartials / g->batch);
+    if (nb > cap) nb = cap;
+    FAS_DISPATCH(g, kap, (k_resid_norm<T, D, KV><<<grid2(nb, g), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, g->partials, batch_of(g, l))));
     check_launch();
     launch_sum_partials(g, (int)nb);
 }
 
 void launch_sum_partials(const fas_grid* g, int count)
 {
-    k_sum_partials<<<1, kBlock, 0, g->stream>>>(g->partials, count, g->norm_out);
+    k_sum_partials<<<(unsigned)g->batch, kBlock, 0, g->stream>>>(g->partials, count, g->norm_out);
     check_launch();
 }
 
 void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
                            const void* u, void* uc, void* rc)
 {
-    FAS_DISPATCH(g, kap, (k_resid_restrict<T, D, KV><<<blocks_for(g->lev[l + 1].N), kBlock, 0, g->stream>>>(
-                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, (T*)uc, (T*)rc)));
+    FAS_DISPATCH(g, kap, (k_resid_restrict<T, D, KV><<<grid2(blocks_for(g->lev[l + 1].N), g), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, (T*)uc, (T*)rc, batch_of(g, l))));
     check_launch();
 }
 
 void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc)
 {
-    FAS_DISPATCH(g, kapc, (k_coarse_rhs<T, D, KV><<<blocks_for(g->lev[lc].N), kBlock, 0, g->stream>>>(
-                              make_op<T>(g, lc, c, kapc), (const T*)uc, (T*)fc)));
+    FAS_DISPATCH(g, kapc, (k_coarse_rhs<T, D, KV><<<grid2(blocks_for(g->lev[lc].N), g), kBlock, 0, g->stream>>>(
+                              make_op<T>(g, lc, c, kapc), (const T*)uc, (T*)fc, batch_of(g, lc))));
     check_launch();
 }
 
@@ -389,8 +500,9 @@ void launch_prolong_add(const fas_grid* g, int l, const void* cnew, const void* 
 {
     const Level& L = g->lev[l];
     const unsigned nb = blocks_for(g->lev[l + 1].N);
-    FAS_DISPATCH(g, (const void*)nullptr, (k_prolong<T, D><<<nb, kBlock, 0, g->stream>>>(
-                                              L.n[0], L.n[1], L.n[2], (const T*)cnew, (const T*)cold, (T*)fine)));
+    FAS_DISPATCH(g, (const void*)nullptr, (k_prolong<T, D><<<grid2(nb, g), kBlock, 0, g->stream>>>(
+                                              L.n[0], L.n[1], L.n[2], (const T*)cnew, (const T*)cold, (T*)fine,
+                                              batch_of(g, l))));
     check_launch();
 }
 
@@ -398,8 +510,8 @@ void launch_restrict(const fas_grid* g, int l, const void* fine, void* coarse)
 {
     const Level& L = g->lev[l];
     const unsigned nb = blocks_for(g->lev[l + 1].N);
-    FAS_DISPATCH(g, (const void*)nullptr, (k_restrict<T, D><<<nb, kBlock, 0, g->stream>>>(
-                                              L.n[0], L.n[1], L.n[2], (const T*)fine, (T*)coarse)));
+    FAS_DISPATCH(g, (const void*)nullptr, (k_restrict<T, D><<<grid2(nb, g), kBlock, 0, g->stream>>>(
+                                              L.n[0], L.n[1], L.n[2], (const T*)fine, (T*)coarse, batch_of(g, l))));
     check_launch();
 }
 
@@ -446,6 +558,29 @@ void launch_update_mixed(const fas_grid* g, double rho, const void* e32, void* u
 void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst32)
 {
     k_cast_f32<<<blocks_for(N), kBlock, 0, g->stream>>>(N, (const double*)src64, (float*)dst32);
+    check_launch();
+}
+
+}  // namespace fas
+
+namespace fas {
+
+void launch_init_active(const fas_grid* g)
+{
+    k_init_active<<<blocks_for(g->batch), kBlock, 0, g->stream>>>(g->active, g->cyc, g->batch);
+    check_launch();
+}
+
+void launch_update_active(const fas_grid* g, double tol, int k)
+{
+    k_update_active<<<1, kBlock, 0, g->stream>>>(g->norm_out, g->rnorm, tol * tol, k, g->active, g->cyc, g->batch,
+                                                 g->count);
+    check_launch();
+}
+
+void launch_grain_rhs(hipStream_t stream, int q, int64_t N, float dt, const float* eta, float* f)
+{
+    k_grain_rhs<<<blocks_for(N), kBlock, 0, stream>>>(q, N, dt, eta, f);
     check_launch();
 }
 

@@ -47,6 +47,9 @@ struct StripArgs {
     T* uc;             // pre: R u out;  post: new coarse values in
     T* rc;             // pre: R r out
     double* partials;  // post: one sum of r^2 per wave (nullable)
+    int batch;         // problems; problem b's arrays start b * stride (b * cstride coarse)
+    int64_t stride, cstride;
+    const int* act;    // per-problem active flags (nullable)
 };
 
 // Lane i receives the value of lane i - 1 (wave_shr:1) or of lane i + 1 (wave_shl:1);
@@ -115,8 +118,20 @@ struct StripGeom {
 // boundary cells need their own diagonal counts).  Interior waves run without any of
 // that.  Loads are unconditional (boundary waves load a clamped address and select),
 // so each row's loads stay in flight for PF rows.
+// Per-problem arrays of a batched launch (the kernel arguments stay in place).
+template <typename T>
+struct Arrays {
+    const T* f;
+    const T* u_in;
+    T* u_out;
+    T* uc;
+    T* rc;
+    double* partials;
+};
+
 template <typename T, int NU, int MODE, bool NORM, bool EDGE, int FIRST>
-__device__ __forceinline__ void march(const StripArgs<T>& a, int strip, int seg, int seg_rows, int wave_id)
+__device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, int strip, int seg, int seg_rows,
+                                      int wave_id)
 {
     using G = StripGeom<NU, MODE>;
     using V = typename Pair<T>::V;
@@ -171,11 +186,11 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, int strip, int seg,
         int gy;
         const bool yin = row_of(rho, gy);
         const int64_t off = (int64_t)gy * a.n0 + gxl;
-        V zu = *reinterpret_cast<const V*>(a.u_in + off);
-        V zf = *reinterpret_cast<const V*>(a.f + off);
+        V zu = *reinterpret_cast<const V*>(A.u_in + off);
+        V zf = *reinterpret_cast<const V*>(A.f + off);
         T c = (T)0;
         if constexpr (MODE == 1) {
-            if (odd) c = a.uc[(int64_t)(gy >> 1) * mc0 + gcx];
+            if (odd) c = A.uc[(int64_t)(gy >> 1) * mc0 + gcx];
         }
         if constexpr (EDGE) {
             const bool in = yin && xin;
@@ -294,15 +309,15 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, int strip, int seg,
                         V out;
                         out.x = ue[a0];
                         out.y = uo[a0];
-                        *reinterpret_cast<V*>(a.u_out + (int64_t)graw * a.n0 + gxe) = out;
+                        *reinterpret_cast<V*>(A.u_out + (int64_t)graw * a.n0 + gxe) = out;
                         if constexpr (MODE == 0) {
                             // rows (r - 1, r) form coarse row graw / 2 when r is odd
                             if (((j - S - 1 - LAG + sh) & 1) && graw - 1 >= y0) {
                                 const T ucv = restrict4(ue[am], uo[am], ue[a0], uo[a0]);
                                 const T rcv = restrict4(re_prev, ro_prev, re, ro);
                                 const int64_t P = (int64_t)(graw >> 1) * mc0 + (gxe >> 1);
-                                a.uc[P] = ucv;
-                                a.rc[P] = rcv;
+                                A.uc[P] = ucv;
+                                A.rc[P] = rcv;
                             }
                         }
                         if constexpr (NORM) {
@@ -319,7 +334,7 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, int strip, int seg,
     if constexpr (NORM) {
         // fixed butterfly over the 64 lanes (same order on every run)
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) a.partials[wave_id] = acc;
+        if (lane == 0) A.partials[wave_id] = acc;
     }
 }
 
@@ -328,8 +343,17 @@ __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
 {
     using G = StripGeom<NU, MODE>;
     // the wave index is uniform across the wave: keep it (and all row bookkeeping) scalar
-    const int wave_id = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave_id >= a.strips * a.segs) return;
+    const int gw = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int per = a.strips * a.segs;
+    const int b = gw / per, wave_id = gw % per;
+    if (b >= a.batch || (a.act && !a.act[b])) return;
+    Arrays<T> A;
+    A.f = a.f + b * a.stride;
+    A.u_in = a.u_in + b * a.stride;
+    A.u_out = a.u_out + b * a.stride;
+    A.uc = a.uc + b * a.cstride;
+    A.rc = a.rc ? a.rc + b * a.cstride : nullptr;
+    A.partials = a.partials ? a.partials + (int64_t)b * per : nullptr;
     const int strip = wave_id % a.strips, seg = wave_id / a.strips;
     const int x0 = strip * G::TXS, y0 = seg * a.seg_rows;
     // rows read: [y0 - H, y0 - H + turns * RING + PF), columns [x0 - H, x0 - H + 128)
@@ -338,24 +362,24 @@ __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
     const bool edge = x0 - G::H < 0 || x0 - G::H + 128 > a.n0 || y0 - G::H < 0 || y0 - G::H + rows_read > a.n1;
     if (edge) {
         if (first)
-            march<T, NU, MODE, NORM, true, 1>(a, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, true, 1>(a, A, strip, seg, a.seg_rows, wave_id);
         else
-            march<T, NU, MODE, NORM, true, 0>(a, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, true, 0>(a, A, strip, seg, a.seg_rows, wave_id);
     } else {
         if (first)
-            march<T, NU, MODE, NORM, false, 1>(a, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, false, 1>(a, A, strip, seg, a.seg_rows, wave_id);
         else
-            march<T, NU, MODE, NORM, false, 0>(a, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, false, 0>(a, A, strip, seg, a.seg_rows, wave_id);
     }
 }
 
 // Rows per segment: long segments amortise the warm-up rows, short ones give small
-// levels enough wavefronts (about 2048) to hide latency.
-inline int seg_rows_for(int n0, int n1, int txs)
+// levels enough wavefronts (about 2048 over the batch) to hide latency.
+inline int seg_rows_for(int n0, int n1, int txs, int batch)
 {
     const int strips = (n0 + txs - 1) / txs;
     int rows = kSegRows;
-    while (rows > 16 && (int64_t)strips * ((n1 + rows - 1) / rows) < 2048) rows >>= 1;
+    while (rows > 16 && (int64_t)batch * strips * ((n1 + rows - 1) / rows) < 2048) rows >>= 1;
     return rows;
 }
 
@@ -370,8 +394,12 @@ StripArgs<T> make_args(const fas_grid* g, int l, const Coef& c, int nu)
     for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
     const int txs = 128 - 2 * (2 * nu + 2);
     a.strips = (a.n0 + txs - 1) / txs;
-    a.seg_rows = seg_rows_for(a.n0, a.n1, txs);
+    a.seg_rows = g->seg_rows[l] ? g->seg_rows[l] : seg_rows_for(a.n0, a.n1, txs, g->batch);
     a.segs = (a.n1 + a.seg_rows - 1) / a.seg_rows;
+    a.batch = g->batch;
+    a.stride = g->lev[l].N;
+    a.cstride = l < g->L ? g->lev[l + 1].N : 0;
+    a.act = g->batch > 1 ? g->active : nullptr;
     return a;
 }
 
@@ -384,7 +412,7 @@ inline void check_launch()
 template <typename T, int MODE, bool NORM>
 void launch_nu(const fas_grid* g, const StripArgs<T>& a, int nu, int first)
 {
-    const unsigned blocks = (unsigned)((a.strips * a.segs + kWaves - 1) / kWaves);
+    const unsigned blocks = (unsigned)(((int64_t)a.batch * a.strips * a.segs + kWaves - 1) / kWaves);
     switch (nu) {
         case 0: k_strip<T, 0, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
         case 1: k_strip<T, 1, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
@@ -410,7 +438,7 @@ int fused_tiles(const fas_grid* g, int l, int nu_post)
     const int txs = 128 - 2 * (2 * nu_post + 2);
     const int n0 = g->lev[l].n[0], n1 = g->lev[l].n[1];
     const int strips = (n0 + txs - 1) / txs;
-    const int rows = seg_rows_for(n0, n1, txs);
+    const int rows = g->seg_rows[l] ? g->seg_rows[l] : seg_rows_for(n0, n1, txs, g->batch);
     return strips * ((n1 + rows - 1) / rows);
 }
 

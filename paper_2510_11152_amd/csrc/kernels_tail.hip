@@ -26,6 +26,8 @@ struct TailArgs {
     Op<T> op[kMaxTail];
     T* u_top;                 // in: initial guess of the top level; out: its new values
     const T* r_top;           // in: restricted residual (form_rhs) or the right-hand side
+    int64_t stride;           // batched grids: problem b = blockIdx.x at b * stride
+    const int* act;           // per-problem active flags (nullable)
 };
 
 template <typename T, int DIM>
@@ -69,10 +71,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
     T* base = reinterpret_cast<T*>(lds);
     auto U = [&](int l) { return base + a.lds_off[l]; };
     auto F = [&](int l) { return base + a.lds_off[l] + (a.op[l].n0 * a.op[l].n1 * a.op[l].n2); };
+    if (a.act && !a.act[blockIdx.x]) return;
+    T* const u_top = a.u_top + blockIdx.x * a.stride;
+    const T* const r_top = a.r_top + blockIdx.x * a.stride;
     const int N0 = a.op[0].n0 * a.op[0].n1 * a.op[0].n2;
     for (int p = threadIdx.x; p < N0; p += kTailThreads) {
-        U(0)[p] = a.u_top[p];
-        F(0)[p] = a.r_top[p];
+        U(0)[p] = u_top[p];
+        F(0)[p] = r_top[p];
     }
     __syncthreads();
     if (a.form_rhs) {
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
         __syncthreads();
         tail_smooth<T, DIM, KV>(op, u, F(lv), a.post, a.first, rev);
     }
-    for (int p = threadIdx.x; p < N0; p += kTailThreads) a.u_top[p] = U(0)[p];
+    for (int p = threadIdx.x; p < N0; p += kTailThreads) u_top[p] = U(0)[p];
 }
 
 template <typename T>
@@ -202,17 +207,20 @@ void launch_t(const fas_grid* g, int top, const Coef* coef, int pre, int post, i
     a.u_top = (T*)u;
     a.r_top = (const T*)r;
     a.form_rhs = form_rhs;
+    a.stride = g->lev[top].N;
+    a.act = g->batch > 1 ? g->active : nullptr;
+    const unsigned nb = (unsigned)g->batch;
     const bool kv = g->lev[top].kap != nullptr;
     if (g->dim == 2) {
         if (kv)
-            k_tail<T, 2, true><<<1, kTailThreads, 0, g->stream>>>(a);
+            k_tail<T, 2, true><<<nb, kTailThreads, 0, g->stream>>>(a);
         else
-            k_tail<T, 2, false><<<1, kTailThreads, 0, g->stream>>>(a);
+            k_tail<T, 2, false><<<nb, kTailThreads, 0, g->stream>>>(a);
     } else {
         if (kv)
-            k_tail<T, 3, true><<<1, kTailThreads, 0, g->stream>>>(a);
+            k_tail<T, 3, true><<<nb, kTailThreads, 0, g->stream>>>(a);
         else
-            k_tail<T, 3, false><<<1, kTailThreads, 0, g->stream>>>(a);
+            k_tail<T, 3, false><<<nb, kTailThreads, 0, g->stream>>>(a);
     }
     check_launch();
 }

@@ -1,0 +1,102 @@
+"""Batched solves: every member of a batch equals the single-problem solve of the same
+precision and parameters (bit for bit when the cycle counts agree), the grain-growth
+right-hand side equals the oracle's, and a grain step matches the oracle's FP32 solves."""
+import numpy as np
+import pytest
+import torch
+
+import fas_inputs as I
+import oracle as O
+from oracle import grain as OG
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TD = {np.float64: torch.float64, np.float32: torch.float32}
+
+
+@pytest.mark.parametrize("n,bc,dtype,coarsest", [((256, 256), "neumann", np.float64, 4), ((128, 128), "periodic", np.float32, 4),
+                                                 ((512, 256), "dirichlet", np.float64, 4), ((64, 64), "neumann", np.float32, 4),
+                                                 ((16, 16, 16), "neumann", np.float64, 4)])
+def test_batch_members_equal_single_solves(n, bc, dtype, coarsest):
+    from paper_2510_11152_amd import Grid
+    B, dt, tol = 5, 2e-3, 1e-10 if dtype == np.float64 else 1e-5
+    P = O.Problem(n=n, h=1.0 / n[0], dt=dt, bc=bc, coarsest=coarsest)
+    shape = P.shape()
+    rhs = np.stack([I.random_field(shape, 100 + b) * (b + 1) for b in range(B)]).astype(dtype)
+    rhs[2] *= 0.0  # a zero right-hand side converges at once and then sits out
+    u0 = np.stack([I.random_field(shape, 200 + b) for b in range(B)]).astype(dtype)
+    gb = Grid(n, P.h, bc=bc, dtype=TD[dtype], coarsest=coarsest, batch=B)
+    ub = torch.from_numpy(u0).to(DEV)
+    st, cy = gb.solve_batched(torch.from_numpy(rhs).to(DEV), ub, dt, tol=tol)
+    assert all(s == 0 for s in st), st
+    gs = Grid(n, P.h, bc=bc, dtype=TD[dtype], coarsest=coarsest)
+    for b in range(B):
+        us = torch.from_numpy(u0[b].copy()).to(DEV)
+        assert gs.solve(torch.from_numpy(rhs[b].copy()).to(DEV), us, dt, tol=tol) == 0
+        c = gs.stats()["cycles"]
+        assert abs(c - cy[b]) <= 1, (b, c, cy[b])
+        if c == cy[b]:
+            assert torch.equal(us, ub[b]), b
+
+
+def test_grain_rhs_matches_oracle_bitwise():
+    from paper_2510_11152_amd import grain_rhs
+    eta = I.grain_init(q=37, n=64, seed=6)
+    eta[:, :8, :8] = np.random.default_rng(1).uniform(-1, 1, (37, 8, 8)).astype(np.float32)
+    f = grain_rhs(torch.from_numpy(eta).to(DEV), 0.1)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy(), OG.grain_rhs(eta, 0.1))
+
+
+def test_grain_step_matches_oracle():
+    """One step of the 2D grain-growth model (periodic, h = 1, dt = 0.1, kappa = 1,
+    FP32) on 12 fields of 128^2: each field's solve against the oracle's FP32 solve."""
+    from paper_2510_11152_amd import GrainGrowth
+    q, n, dt = 12, 128, 0.1
+    eta0 = I.grain_init(q=q, n=n, seed=6)
+    eta0 += np.float32(0.3) * np.sin(np.arange(n, dtype=np.float32) / 7.0)[None, None, :] * (np.arange(q) % 3 == 0)[:, None, None]
+    model = GrainGrowth(q, n, h=1.0, dt=dt, kappa=1.0, tol=1e-6)
+    eta = torch.from_numpy(eta0).to(DEV)
+    cy = model.step(eta)
+    got = eta.cpu().numpy()
+    f = OG.grain_rhs(eta0, dt)
+    P = O.Problem(n=(n, n), h=1.0, dt=dt, kappa=1.0, bc="periodic", coarsest=4, nuc=2)
+    for i in range(q):
+        ui = eta0[i].copy()
+        st, c, _ = O.solve(P, f[i], ui, 1e-6)
+        assert st == 0
+        assert abs(c - cy[i]) <= 1
+        if c == cy[i]:
+            assert np.array_equal(got[i], ui), i
+        else:
+            assert np.abs(got[i] - ui).max() <= 1e-5 * np.abs(ui).max()
+
+
+def test_uneven_batch_groups_equal_single_solves():
+    """Problems of several sizes: one batched solve per size group, each member equal to
+    its single solve."""
+    from paper_2510_11152_amd import solve_uneven, Grid
+    sizes = [64, 128, 64, 256, 128, 64]
+    fields = [I.cosine_modes(m, 2, 16, np.random.default_rng(50 + b)) for b, m in enumerate(sizes)]
+    us = [torch.from_numpy(f.copy()).to(DEV) for f in fields]
+    rhs = [torch.from_numpy(f.copy()).to(DEV) for f in fields]
+    st, cy = solve_uneven(rhs, us, dt=1e-4, tol=1e-10)
+    assert all(s == 0 for s in st)
+    for b, m in enumerate(sizes):
+        g = Grid((m, m), 1.0 / m, coarsest=4)
+        u = rhs[b].clone()
+        assert g.solve(rhs[b], u, 1e-4, tol=1e-10) == 0
+        if g.stats()["cycles"] == cy[b]:
+            assert torch.equal(u, us[b])
+
+
+def test_batched_graph_replay_equals_launches():
+    from paper_2510_11152_amd import Grid
+    B, n = 6, (256, 256)
+    P = O.Problem(n=n, h=1 / 256, dt=1e-3, bc="neumann", coarsest=4)
+    rhs = torch.from_numpy(np.stack([I.random_field(P.shape(), 300 + b) for b in range(B)])).to(DEV)
+    ua, ub = rhs.clone(), rhs.clone()
+    sa = Grid(n, P.h, batch=B).solve_batched(rhs, ua, P.dt, tol=1e-10)
+    sb = Grid(n, P.h, batch=B).set(graph=True).solve_batched(rhs, ub, P.dt, tol=1e-10)
+    assert sa == sb
+    assert torch.equal(ua, ub)

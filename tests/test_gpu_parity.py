@@ -215,3 +215,46 @@ def test_solve_reports_not_converged_and_is_deterministic():
     g.solve(f, a, P.dt, tol=1e-12)
     g.solve(f, b, P.dt, tol=1e-12)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n,bc", [((64, 64, 64), "neumann"), ((128, 64, 32), "dirichlet"), ((64, 64, 64), "periodic"),
+                                  ((96, 64, 32), "neumann")])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 1), (2, 1), (1, 3)])
+def test_vcycle_3d_plane_march_bitwise(n, bc, dtype, nu):
+    """3D grids large enough for the plane-march kernels (tiles with interior and
+    boundary tiles, ragged tiles, an odd number of passes): V-cycles equal the oracle's
+    bits and the library's own one-phase-per-launch path."""
+    P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
+    g = grid_for(P, dtype)
+    gb = grid_for(P, dtype).set(fused=False)
+    f = I.random_field(P.shape(), 18).astype(dtype)
+    u = I.random_field(P.shape(), 19).astype(dtype)
+    ug, ub, fg = dev(u), dev(u), dev(f)
+    for it in range(2):
+        O.vcycle(P, f, u, nu[0], nu[1])
+        rel = g.vcycle(fg, ug, P.dt, nu1=nu[0], nu2=nu[1], with_residual=True)
+        gb.vcycle(fg, ub, P.dt, nu1=nu[0], nu2=nu[1])
+        assert np.array_equal(host(ug), u), it
+        assert torch.equal(ug, ub)
+        ro = np.linalg.norm(O.residual(P, 0, f, u).astype(np.float64)) / np.linalg.norm(f.astype(np.float64))
+        assert abs(rel - ro) <= 1e-10 * ro
+
+
+@pytest.mark.parametrize("n,dtype", [((1024, 512), np.float64), ((64, 64, 64), np.float32), ((256, 256), np.float32)])
+def test_graph_and_autotune_give_the_same_bits(n, dtype):
+    """A solve with the V-cycle captured in a HIP graph, and with autotuned march segment
+    heights, gives the same iterate as the plain launches."""
+    P = _problem(n, 4, "neumann", dt=1e-3, kappa=1.0)
+    f = dev(I.random_field(P.shape(), 31).astype(dtype))
+    tol = 1e-9 if dtype == np.float64 else 1e-5
+    ref = f.clone()
+    g0 = grid_for(P, dtype)
+    assert g0.solve(f, ref, P.dt, tol=tol) == 0
+    for opts in ({"graph": True}, {"autotune": True}, {"graph": True, "autotune": True}):
+        g = grid_for(P, dtype).set(**opts)
+        for rep in range(2):  # second solve replays the cached graph
+            u = f.clone()
+            assert g.solve(f, u, P.dt, tol=tol) == 0
+            if g.stats()["cycles"] == g0.stats()["cycles"]:
+                assert torch.equal(u, ref), opts

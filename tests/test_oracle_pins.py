@@ -376,3 +376,15 @@ def test_mixed_precision_reaches_fp64_solution(variable):
     O.solve(P, f, ref, 1e-13, kap=kap)
     assert np.abs(u - ref).max() <= 1e-9 * np.abs(ref).max()
     assert hist[-1] <= 1e-10
+
+
+# ---------------------------------------------------------------- grain-growth right-hand side
+def test_grain_rhs_is_the_free_energy_derivative():
+    """f_i = eta_i - dt * d(free energy)/d eta_i: the closed-form derivative used by the
+    oracle against central differences of the energy itself."""
+    from oracle import grain as G
+    rng = np.random.default_rng(0)
+    eta = rng.uniform(-1, 1, (6, 8, 8))
+    a = G.grain_rhs(eta.astype(np.float32), 0.1).astype(np.float64)
+    b = G.grain_rhs_reference(eta.astype(np.float32).astype(np.float64), 0.1)
+    np.testing.assert_allclose(a, b, rtol=0, atol=2e-6)
