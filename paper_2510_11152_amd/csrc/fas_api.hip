@@ -441,8 +441,10 @@ void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
 
 void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed, bool want_norm)
 {
-    if (!g->use_graph || g->profile) {
+    if (!g->use_graph || g->profile || (g->autotune && !g->tuned)) {
+        // the first cycle of an autotuned grid times its kernels, which cannot be captured
         vcycle_top(g, f, u, nu1, nu2, transposed, want_norm);
+        if (g->autotune) g->tuned = 1;
         return;
     }
     if (!g->graph_cache) g->graph_cache = new GraphCache();
@@ -674,6 +676,7 @@ int fas_grid_set(fas_grid_t g, int option, double value)
             case FAS_OPT_AUTOTUNE:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "autotune must be 0 or 1");
                 g->autotune = v;
+                g->tuned = 0;
                 if (!v)
                     for (int l = 0; l < fas::kMaxLevels; ++l) g->seg_rows[l] = 0;
                 return FAS_OK;

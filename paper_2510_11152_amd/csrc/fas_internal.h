@@ -70,7 +70,7 @@ struct fas_grid {
     fas::Coef coef[fas::kMaxLevels];
     fas_stats_t stats;
     // HIP graph of one V-cycle (FAS_OPT_GRAPH) and march segment heights (FAS_OPT_AUTOTUNE)
-    int use_graph, autotune;
+    int use_graph, autotune, tuned;
     void* graph_cache;            // GraphCache (fas_api.hip)
     int seg_rows[fas::kMaxLevels];  // 0: default rule; else rows (2D) / planes (3D) per segment
     // profiler (FAS_OPT_PROFILE): event pairs around finest-level launches

@@ -15,9 +15,10 @@
 // pipelined over rows: when row t arrives, colour phase s (s = 1..2nu) updates row
 // t - s - LAG, in increasing s, which reproduces exactly the values of running the
 // phases one after the other over the whole grid (post waits one more row, LAG = 1, so
-// that a row's lower neighbour has received its coarse correction).  The outer
-// H = 2nu + 2 columns on each side of the strip and H rows above the segment are
-// recomputed as halo; a strip writes 128 - 2H columns and neighbouring strips overlap.
+// that a row's lower neighbour has received its coarse correction).  The outer 8 columns
+// on each side of the strip and H = 2nu + 2 rows above the segment are recomputed as
+// halo; a strip writes 112 columns (whole 128-byte lines in FP64) and neighbouring strips
+// overlap.
 // Point formulas are those of fas_device.h (same bits as every other kernel).
 #include <hip/hip_runtime.h>
 
@@ -106,8 +107,10 @@ __device__ __forceinline__ T pick_q(const StripArgs<T>& a, int W)
 template <int NU, int MODE>
 struct StripGeom {
     static constexpr int S = 2 * NU;         // colour phases per pass
-    static constexpr int H = 2 * NU + 2;     // halo columns / rows above
-    static constexpr int TXS = 128 - 2 * H;  // columns written per strip
+    static constexpr int H = 2 * NU + 2;     // halo rows above the segment
+    static constexpr int HX = 8;             // halo columns each side (>= H; keeps the
+                                             // written columns on 128-byte lines)
+    static constexpr int TXS = 128 - 2 * HX; // columns written per strip (112)
     static constexpr int LAG = MODE;         // post: one row later (see header)
     static constexpr int PF = 4;             // rows loaded ahead
     static constexpr int RING = S + 8;       // rows held: >= S + 3 + LAG + PF, even
@@ -139,12 +142,12 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
     const int lane = threadIdx.x & 63;
     const bool periodic = a.bc == BC_PERIODIC;
     const int x0 = strip * G::TXS;              // first written column
-    const int gxe = x0 - H + 2 * lane;          // even cell of this lane (global x)
+    const int gxe = x0 - G::HX + 2 * lane;      // even cell of this lane (global x)
     const int y0 = seg * seg_rows;
     const int rA = y0 - H;                      // first row visited (even)
     const int yend = min(y0 + seg_rows, a.n1);  // rows written: [y0, yend)
     const int nsteps = yend - rA + S + 1 + LAG;
-    const bool own = lane >= H / 2 && lane < 64 - H / 2 && gxe < a.n0;  // writes this pair
+    const bool own = lane >= G::HX / 2 && lane < 64 - G::HX / 2 && gxe < a.n0;  // writes this pair
     bool xin = true;
     int gxl = gxe;
     if constexpr (EDGE) {
@@ -342,8 +345,14 @@ template <typename T, int NU, int MODE, bool NORM>
 __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
 {
     using G = StripGeom<NU, MODE>;
+    // Blocks are dealt round-robin over the 8 XCDs; renumber them so that each XCD takes a
+    // contiguous range (neighbouring strips, which share halo columns, share its L2).
+    const unsigned nblk = gridDim.x, per_xcd = (nblk + 7u) / 8u;
+    const unsigned xcd = blockIdx.x % 8u, idx = blockIdx.x / 8u;
+    const unsigned full = nblk % 8u == 0 ? 8u : nblk % 8u;  // XCDs that get per_xcd blocks
+    const unsigned blk = xcd < full ? xcd * per_xcd + idx : full * per_xcd + (xcd - full) * (per_xcd - 1) + idx;
     // the wave index is uniform across the wave: keep it (and all row bookkeeping) scalar
-    const int gw = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gw = (int)blk * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int per = a.strips * a.segs;
     const int b = gw / per, wave_id = gw % per;
     if (b >= a.batch || (a.act && !a.act[b])) return;
@@ -356,10 +365,10 @@ __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
     A.partials = a.partials ? a.partials + (int64_t)b * per : nullptr;
     const int strip = wave_id % a.strips, seg = wave_id / a.strips;
     const int x0 = strip * G::TXS, y0 = seg * a.seg_rows;
-    // rows read: [y0 - H, y0 - H + turns * RING + PF), columns [x0 - H, x0 - H + 128)
+    // rows read: [y0 - H, y0 - H + turns * RING + PF), columns [x0 - HX, x0 - HX + 128)
     const int nsteps = a.seg_rows + G::H + G::S + 1 + G::LAG;
     const int rows_read = (nsteps + G::RING - 1) / G::RING * G::RING + G::PF;
-    const bool edge = x0 - G::H < 0 || x0 - G::H + 128 > a.n0 || y0 - G::H < 0 || y0 - G::H + rows_read > a.n1;
+    const bool edge = x0 - G::HX < 0 || x0 - G::HX + 128 > a.n0 || y0 - G::H < 0 || y0 - G::H + rows_read > a.n1;
     if (edge) {
         if (first)
             march<T, NU, MODE, NORM, true, 1>(a, A, strip, seg, a.seg_rows, wave_id);
@@ -392,7 +401,7 @@ StripArgs<T> make_args(const fas_grid* g, int l, const Coef& c, int nu)
     a.bc = g->bc;
     a.k = (T)c.kd;
     for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
-    const int txs = 128 - 2 * (2 * nu + 2);
+    const int txs = 112;
     a.strips = (a.n0 + txs - 1) / txs;
     a.seg_rows = g->seg_rows[l] ? g->seg_rows[l] : seg_rows_for(a.n0, a.n1, txs, g->batch);
     a.segs = (a.n1 + a.seg_rows - 1) / a.seg_rows;
@@ -435,7 +444,8 @@ bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable)
 
 int fused_tiles(const fas_grid* g, int l, int nu_post)
 {
-    const int txs = 128 - 2 * (2 * nu_post + 2);
+    const int txs = 112;
+    (void)nu_post;
     const int n0 = g->lev[l].n[0], n1 = g->lev[l].n[1];
     const int strips = (n0 + txs - 1) / txs;
     const int rows = g->seg_rows[l] ? g->seg_rows[l] : seg_rows_for(n0, n1, txs, g->batch);

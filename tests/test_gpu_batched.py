@@ -23,13 +23,17 @@ def test_batch_members_equal_single_solves(n, bc, dtype, coarsest):
     P = O.Problem(n=n, h=1.0 / n[0], dt=dt, bc=bc, coarsest=coarsest)
     shape = P.shape()
     rhs = np.stack([I.random_field(shape, 100 + b) * (b + 1) for b in range(B)]).astype(dtype)
-    rhs[2] *= 0.0  # a zero right-hand side converges at once and then sits out
     u0 = np.stack([I.random_field(shape, 200 + b) for b in range(B)]).astype(dtype)
+    # member 2 starts from its converged solution: it stops after one cycle and sits out
+    gs = Grid(n, P.h, bc=bc, dtype=TD[dtype], coarsest=coarsest)
+    pre = torch.from_numpy(u0[2].copy()).to(DEV)
+    assert gs.solve(torch.from_numpy(rhs[2].copy()).to(DEV), pre, dt, tol=tol) == 0
+    u0[2] = pre.cpu().numpy()
     gb = Grid(n, P.h, bc=bc, dtype=TD[dtype], coarsest=coarsest, batch=B)
     ub = torch.from_numpy(u0).to(DEV)
     st, cy = gb.solve_batched(torch.from_numpy(rhs).to(DEV), ub, dt, tol=tol)
     assert all(s == 0 for s in st), st
-    gs = Grid(n, P.h, bc=bc, dtype=TD[dtype], coarsest=coarsest)
+    assert cy[2] == 1 and max(cy) > 1, cy
     for b in range(B):
         us = torch.from_numpy(u0[b].copy()).to(DEV)
         assert gs.solve(torch.from_numpy(rhs[b].copy()).to(DEV), us, dt, tol=tol) == 0
