@@ -56,14 +56,18 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
-            _lib.load().fas_grid_destroy(h)
+        if h and _lib is not None and getattr(_lib, "load", None) is not None:
+            try:
+                _lib.load().fas_grid_destroy(h)
+            except Exception:  # interpreter shutdown: module globals already cleared
+                pass
             self.handle = None
 
     def shape(self, level=0):
         return tuple(m >> level for m in reversed(self.n))
 
-    def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None):
+    def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None,
+            seg_rows=None):
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -77,6 +81,8 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_GRAPH, float(int(graph))), "fas_grid_set")
         if autotune is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_AUTOTUNE, float(int(autotune))), "fas_grid_set")
+        if seg_rows is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_SEG_ROWS, float(seg_rows)), "fas_grid_set")
         return self
 
     def profile(self, reset=True):

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -51,7 +52,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     int L;
     int n[fas::kMaxLevels][3];
-    size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], kap[fas::kMaxLevels];
+    size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], r[fas::kMaxLevels], kap[fas::kMaxLevels];
     size_t mix_e, mix_r, partials, norm_out, active, cyc, rnorm, count, total;
     int npartials;
 };
@@ -93,7 +94,7 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
             lay->n[l][a] = a < dim ? (int)(n[a] >> l) : 1;
             Nl *= lay->n[l][a];
         }
-        lay->u[l] = lay->f[l] = 0;
+        lay->u[l] = lay->f[l] = lay->r[l] = 0;
         lay->x[l] = off;
         off = align_up(off + Nl * s);
         if (l >= 1) {
@@ -101,6 +102,10 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
             off = align_up(off + Nl * s);
             lay->f[l] = off;
             off = align_up(off + Nl * s);
+            if (dim == 2) {
+                lay->r[l] = off;
+                off = align_up(off + Nl * s);
+            }
         }
         lay->kap[l] = 0;
         const bool need_kap = (flags & FAS_FLAG_VARIABLE_KAPPA) && (l >= 1 || dtype == FAS_F32);
@@ -116,10 +121,16 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
         lay->mix_r = off;
         off = align_up(off + N0 * s);
     }
-    // one partial sum per fused tile (tiles are at least 64 x 32 cells) or per block of
-    // the stand-alone norm kernel
+    // one partial sum per fused tile (3D tiles are at least 64 x 32 x 32 cells), per 2D
+    // march wave (kStripCols x kMinSegRows cells at least) or per block of the
+    // stand-alone norm kernel
     int64_t tiles = 1;
     for (int a = 0; a < dim; ++a) tiles *= (n[a] + (a == 0 ? 63 : 31)) / (a == 0 ? 64 : 32);
+    if (dim == 2) {
+        const int64_t waves = ((n[0] + fas::kStripCols - 1) / fas::kStripCols) *
+                              ((n[1] + fas::kMinSegRows - 1) / fas::kMinSegRows);
+        if (waves > tiles) tiles = waves;
+    }
     const int64_t per = tiles > fas::kPartials ? tiles : fas::kPartials;
     if (per * batch >= ((int64_t)1 << 31)) return *why = "batch too large", FAS_ERR_SHAPE;
     lay->npartials = (int)(per * batch);
@@ -247,12 +258,31 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 // FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
 // partials != nullptr asks the finest-level post-smoothing to leave per-tile residual
 // partial sums there; returns the number written (0 if it could not).
-void autotune_level(fas_grid* g, int l, int first, int pre, const void* f, const void* u);
+// rc_in (level >= 1, fused 2D pre only): the restricted residual from which the pre pass
+// forms f itself.
+void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
+                    const void* rc_in = nullptr);
+
+// Whether coarse level lc forms its FAS right-hand side inside its fused 2D pre pass;
+// the finer level then leaves R(f - A u) in lev[lc].r (the pre pass reads it while
+// writing f, so it cannot be f itself).
+bool rhs_in_pre(const fas_grid* g, int lc, int pre, int post)
+{
+    return lc >= 1 && lc <= g->L && g->lev[lc].r && g->fused && lc != fas::tail_top(g) &&
+           fas::fused_ok(g, lc, pre, post, g->lev[lc].kap != nullptr);
+}
+
+// Where level l leaves the restricted residual for level l + 1.
+void* rc_dst(const fas_grid* g, int l, int pre, int post)
+{
+    return rhs_in_pre(g, l + 1, pre, post) ? g->lev[l + 1].r : g->lev[l + 1].f;
+}
 
 // Coarse part of a cycle below level l: the persistent tail when level l + 1 is its top
-// (the FAS right-hand side is formed inside it), else the coarse right-hand side and
-// the recursion.
-int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials);
+// (the FAS right-hand side is formed inside it), else the recursion, with the coarse
+// right-hand side formed by level l + 1's pre pass or by its own kernel.
+int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials,
+                 const void* rc_in = nullptr);
 
 void coarse_part(fas_grid* g, int l, int pre, int post, bool rev)
 {
@@ -262,11 +292,16 @@ void coarse_part(fas_grid* g, int l, int pre, int post, bool rev)
         fas::launch_tail(g, l + 1, g->coef, pre, post, first, C.u, C.f, true);
         return;
     }
+    if (rhs_in_pre(g, l + 1, pre, post)) {
+        vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr, C.r);
+        return;
+    }
     fas::launch_coarse_rhs(g, l + 1, g->coef[l + 1], C.kap, C.u, C.f);
     vcycle_level(g, l + 1, C.f, C.u, pre, post, rev, nullptr);
 }
 
-int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials)
+int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, bool rev, double* partials,
+                 const void* rc_in)
 {
     if (l == g->L) {
         smooth(g, l, f, u, g->nuc, rev);  // Remark 1: coarsest level smoothed, no direct solve
@@ -283,7 +318,7 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         // 3D: one sweep per pass, ping-pong between u and the level's second buffer
         void* bufs[2] = {u, g->lev[l].x};
         int cur = 0;
-        autotune_level(g, l, first, 1, f, u);
+        autotune_level(g, l, first, 1, 1, f, u);
         if (partials && fas::fused3_partials(g, l) > g->npartials / g->batch) partials = nullptr;
         {
             ProfScope ps(g, l, FAS_K_PRE);
@@ -309,10 +344,15 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
     }
     if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
         void* x = g->lev[l].x;
-        autotune_level(g, l, first, pre, f, u);
+        autotune_level(g, l, first, pre, post, f, u, rc_in);
+        if (partials && fas::fused_tiles(g, l, post) > g->npartials / g->batch) partials = nullptr;
         {
             ProfScope ps(g, l, FAS_K_PRE);
-            fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, x, C.u, C.f);
+            if (rc_in)  // f = rc_in + A u, formed and written by the pass
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, x, C.u, rc_dst(g, l, pre, post),
+                                      g->lev[l].f);
+            else
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, x, C.u, rc_dst(g, l, pre, post));
             ps.end();
         }
         coarse_part(g, l, pre, post, rev);
@@ -323,11 +363,12 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         }
         return partials ? fas::fused_tiles(g, l, post) : 0;
     }
+    if (rc_in) throw Error(FAS_ERR_ARG, "internal: coarse right-hand side expected from a fused pass");
     smooth(g, l, f, u, pre, rev);
     // r = f - A u;  u_c = R u;  f_c = R r + A_c u_c
     {
         ProfScope ps(g, l, FAS_K_PRE);
-        fas::launch_resid_restrict(g, l, g->coef[l], g->lev[l].kap, f, u, C.u, C.f);
+        fas::launch_resid_restrict(g, l, g->coef[l], g->lev[l].kap, f, u, C.u, rc_dst(g, l, pre, post));
         ps.end();
     }
     coarse_part(g, l, pre, post, rev);
@@ -365,37 +406,49 @@ std::map<std::string, int>& tune_cache()
     return cache;
 }
 
-void autotune_level(fas_grid* g, int l, int first, int pre, const void* f, const void* u)
+void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
+                    const void* rc_in)
 {
-    if (!g->autotune || g->seg_rows[l]) return;
+    if (!g->autotune || g->seg_force || g->seg_rows[l]) return;
     const bool d3 = g->dim == 3;
     char key[160];
-    snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->lev[l].n[2], g->dtype,
-             g->batch, pre);
+    snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->lev[l].n[2],
+             g->dtype, g->batch, pre, post, rc_in ? 1 : 0);
     auto it = tune_cache().find(key);
     if (it != tune_cache().end()) {
         g->seg_rows[l] = it->second;
         return;
     }
-    const int cands2[] = {16, 32, 64, 128, 256};
-    const int cands3[] = {8, 16, 32, 64, 128};
+    // 3D: planes per segment.  2D: the rule's rows (one round of waves), half and twice
+    // that, and a few fixed heights.
+    std::vector<int> cands;
+    const int extent = d3 ? g->lev[l].n[2] : g->lev[l].n[1];
+    if (d3) {
+        cands = {8, 16, 32, 64, 128};
+    } else {
+        const int rule = fas::fused_seg_rows(g, l, pre);
+        for (int r : {rule, (rule / 2 + 1) & ~1, 2 * rule, 64, 128, 256})
+            if (r >= fas::kMinSegRows && std::find(cands.begin(), cands.end(), r) == cands.end()) cands.push_back(r);
+    }
     hipEvent_t e0, e1;
     FAS_HIP_CHECK(hipEventCreate(&e0));
     FAS_HIP_CHECK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_rows = 0;
     fas::Level& C = g->lev[l + 1];
-    for (int c = 0; c < 5; ++c) {
-        const int rows = d3 ? cands3[c] : cands2[c];
-        if (rows > (d3 ? g->lev[l].n[2] : g->lev[l].n[1])) break;
+    for (int rows : cands) {
+        if (rows > extent && rows != cands.front()) continue;
         g->seg_rows[l] = rows;
         float total = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
             FAS_HIP_CHECK(hipEventRecord(e0, g->stream));
             if (d3)
                 fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, u, g->lev[l].x, C.u, C.f, nullptr);
+            else if (rc_in)
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, g->lev[l].x, C.u,
+                                      rc_dst(g, l, pre, post), g->lev[l].f);
             else
-                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, g->lev[l].x, C.u, C.f);
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, g->lev[l].x, C.u, rc_dst(g, l, pre, post));
             FAS_HIP_CHECK(hipEventRecord(e1, g->stream));
             FAS_HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -612,6 +665,7 @@ int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int d
             Lv.x = base + lay.x[l];
             Lv.u = l ? base + lay.u[l] : nullptr;
             Lv.f = l ? base + lay.f[l] : nullptr;
+            Lv.r = lay.r[l] ? base + lay.r[l] : nullptr;
             Lv.kap_slot = lay.kap[l] ? base + lay.kap[l] : nullptr;
             Lv.kap = nullptr;
         }
@@ -683,6 +737,11 @@ int fas_grid_set(fas_grid_t g, int option, double value)
             case FAS_OPT_FUSED:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "fused must be 0 or 1");
                 g->fused = v;
+                return FAS_OK;
+            case FAS_OPT_SEG_ROWS:
+                if (v != 0 && (v < fas::kMinSegRows || (v & 1)))
+                    return fail(FAS_ERR_ARG, "segment height must be 0 or an even number >= 16");
+                g->seg_force = v;
                 return FAS_OK;
         }
         return fail(FAS_ERR_ARG, "unknown option");

@@ -4,14 +4,22 @@
 
 namespace fas {
 
+constexpr int kStripCols = 112;  // columns a 2D march wavefront writes
+constexpr int kMinSegRows = 16;  // shortest 2D march segment (bounds the partial sums)
+
 // Whether level l (not the coarsest) runs the fused pre/post kernels.
 bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
 // Number of norm partial sums a fused post launch on level l leaves (one per wave).
 int fused_tiles(const fas_grid* g, int l, int nu_post);
+// Rows per march segment on level l with nu sweeps per pass: the forced or tuned value,
+// else the rule (as few segments as fill the device's wave slots once).
+int fused_seg_rows(const fas_grid* g, int l, int nu);
 // pre: nu sweeps on u_in -> u_out, then uc = R u_out, rc = R(f - A u_out).
-// first: parity of the 0-based index sum updated first in each sweep.
+// first: parity of the 0-based index sum updated first in each sweep.  fout != nullptr:
+// f holds r = R(f_fine - A_fine u_fine) and the pass first forms the FAS right-hand side
+// f = r + A u_in, which it uses and writes to fout.
 void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                      void* u_out, void* uc, void* rc);
+                      void* u_out, void* uc, void* rc, void* fout = nullptr);
 // post: u_out = nu sweeps of (u_in + P(uc - R u_in)); partials (nullable) gets one sum
 // of r^2 per tile, r = f - A u_out.
 void launch_fused_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,

@@ -34,6 +34,8 @@ struct Level {
     void* u;       // level arrays (level 0: caller's, set per call)
     void* f;
     void* x;       // second buffer of the same size (out-of-place kernels)
+    void* r;       // 2D, l >= 1: restricted residual R(f - A u) of the finer level, read by
+                   // a march pre pass that forms f = r + A u itself (nullptr otherwise)
     void* kap;     // active cell kappa of this level for the current call, or nullptr
     void* kap_slot;  // workspace storage for kappa of this level (nullptr if none)
 };
@@ -73,6 +75,8 @@ struct fas_grid {
     int use_graph, autotune, tuned;
     void* graph_cache;            // GraphCache (fas_api.hip)
     int seg_rows[fas::kMaxLevels];  // 0: default rule; else rows (2D) / planes (3D) per segment
+    int seg_force;                  // FAS_OPT_SEG_ROWS: > 0 overrides rule and autotuner
+    int cus;                        // compute units of the device (0: not queried yet)
     // profiler (FAS_OPT_PROFILE): event pairs around finest-level launches
     int profile;
     hipEvent_t ev[2 * fas::kMaxEvents];

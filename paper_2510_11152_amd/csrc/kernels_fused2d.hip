@@ -3,7 +3,9 @@
 //
 // pre  (Alg. 1 pre-smoothing, fine residual, restriction): one pass reads u and f once,
 //      runs nu X-MCGS sweeps, writes the smoothed u to a second buffer, and writes
-//      u_c = R u and r_c = R (f - A u) for the coarse level.
+//      u_c = R u and r_c = R (f - A u) for the coarse level.  On a coarse level the
+//      pass may instead read r = R(f_fine - A_fine u_fine) and form the FAS right-hand
+//      side f = r + A u itself from the rows it holds (and write f for the post pass).
 // post (fine grid correction and post-smoothing): one pass reads the pre-smoothed u, f
 //      and the new coarse values, applies u += P(u_c - R u), runs nu sweeps, writes u
 //      back and, on the finest level, one partial sum of the squared residual per wave.
@@ -13,14 +15,17 @@
 // a ring of rows in registers.  Horizontal neighbours come from the adjacent lane by a
 // DPP lane shift, vertical ones from the ring, so no LDS is used.  The nu sweeps are
 // pipelined over rows: when row t arrives, colour phase s (s = 1..2nu) updates row
-// t - s - LAG, in increasing s, which reproduces exactly the values of running the
-// phases one after the other over the whole grid (post waits one more row, LAG = 1, so
-// that a row's lower neighbour has received its coarse correction).  The outer 8 columns
+// t - s - 1, in increasing s, which reproduces exactly the values of running the
+// phases one after the other over the whole grid (the lag of one row lets the row below
+// receive its coarse correction, or lets the right-hand side of a row be formed while
+// its neighbours still hold their initial values).  The outer 8 columns
 // on each side of the strip and H = 2nu + 2 rows above the segment are recomputed as
 // halo; a strip writes 112 columns (whole 128-byte lines in FP64) and neighbouring strips
 // overlap.
 // Point formulas are those of fas_device.h (same bits as every other kernel).
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 
 #include "fas_device.h"
 #include "fas_fused.h"
@@ -32,7 +37,6 @@ namespace {
 
 constexpr int kWaves = 4;  // independent wavefronts per block
 constexpr int kThreads = 64 * kWaves;
-constexpr int kSegRows = 128;  // rows per segment
 
 template <typename T>
 struct StripArgs {
@@ -47,6 +51,8 @@ struct StripArgs {
     T* u_out;
     T* uc;             // pre: R u out;  post: new coarse values in
     T* rc;             // pre: R r out
+    T* fout;           // pre forming the right-hand side (f then holds r): f = r + A u out
+    const T* kap;      // cell kappa of the level (variable-kappa kernels), else nullptr
     double* partials;  // post: one sum of r^2 per wave (nullable)
     int batch;         // problems; problem b's arrays start b * stride (b * cstride coarse)
     int64_t stride, cstride;
@@ -104,16 +110,19 @@ __device__ __forceinline__ T pick_q(const StripArgs<T>& a, int W)
     return v;
 }
 
-template <int NU, int MODE>
+template <int NU, bool KV>
 struct StripGeom {
     static constexpr int S = 2 * NU;         // colour phases per pass
     static constexpr int H = 2 * NU + 2;     // halo rows above the segment
     static constexpr int HX = 8;             // halo columns each side (>= H; keeps the
                                              // written columns on 128-byte lines)
     static constexpr int TXS = 128 - 2 * HX; // columns written per strip (112)
-    static constexpr int LAG = MODE;         // post: one row later (see header)
-    static constexpr int PF = 4;             // rows loaded ahead
-    static constexpr int RING = S + 8;       // rows held: >= S + 3 + LAG + PF, even
+    static_assert(TXS == kStripCols, "strip width");
+    static constexpr int LAG = 1;            // phases trail the newest row by one (see header)
+    static constexpr int PF = KV ? 2 : 4;    // rows loaded ahead (kappa rows take registers)
+    static constexpr int RING = S + 4 + PF;  // rows held: S + 3 + LAG + PF, even
+    // rows visited per full segment: H above, the segment, S + 1 + LAG below
+    static constexpr int extra = H + S + 1 + LAG;
 };
 
 // The march of one wavefront.  EDGE: the strip or segment reaches past a domain edge
@@ -129,14 +138,16 @@ struct Arrays {
     T* u_out;
     T* uc;
     T* rc;
+    T* fout;
+    const T* kap;
     double* partials;
 };
 
-template <typename T, int NU, int MODE, bool NORM, bool EDGE, int FIRST>
+template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, bool EDGE, int FIRST>
 __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, int strip, int seg, int seg_rows,
                                       int wave_id)
 {
-    using G = StripGeom<NU, MODE>;
+    using G = StripGeom<NU, KV>;
     using V = typename Pair<T>::V;
     constexpr int S = G::S, H = G::H, RING = G::RING, PF = G::PF, LAG = G::LAG;
     const int lane = threadIdx.x & 63;
@@ -168,7 +179,9 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
     const int gcx = gxl >> 1;  // coarse column of the pair
 
     T ue[RING], uo[RING], fe[RING], fo[RING];
-    T cr[RING];  // post: new coarse value of the coarse row completed by an odd row
+    T cr[RING];                                 // post: new coarse value of the coarse row
+                                                // completed by an odd row
+    T ke[KV ? RING : 1], ko[KV ? RING : 1];     // cell kappa
     T re_prev = (T)0, ro_prev = (T)0;
     double acc = 0.0;
 
@@ -191,6 +204,8 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
         const int64_t off = (int64_t)gy * a.n0 + gxl;
         V zu = *reinterpret_cast<const V*>(A.u_in + off);
         V zf = *reinterpret_cast<const V*>(A.f + off);
+        V zk{};
+        if constexpr (KV) zk = *reinterpret_cast<const V*>(A.kap + off);
         T c = (T)0;
         if constexpr (MODE == 1) {
             if (odd) c = A.uc[(int64_t)(gy >> 1) * mc0 + gcx];
@@ -201,11 +216,17 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
             zu.y = in ? zu.y : (T)0;
             zf.x = in ? zf.x : (T)0;
             zf.y = in ? zf.y : (T)0;
+            zk.x = in ? zk.x : (T)0;
+            zk.y = in ? zk.y : (T)0;
         }
         ue[p] = zu.x;
         uo[p] = zu.y;
         fe[p] = zf.x;
         fo[p] = zf.y;
+        if constexpr (KV) {
+            ke[p] = zk.x;
+            ko[p] = zk.y;
+        }
         if constexpr (MODE == 1) cr[p] = c;
     };
     // Diagonal factor and count of the lane's even / odd cell, in an inner row or in the
@@ -227,12 +248,38 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
         }
     }
     auto ybound = [&](int gy) -> bool { return EDGE && !periodic && (gy == 0 || gy == a.n1 - 1); };
+    // Cell kappa: weighted neighbour sum Sw and weight total Wt of the even (EVEN) or odd
+    // cell of ring slot a0 (rows am above, ap below), with the face weights and the
+    // boundary faces of fas_device.h's gather (slot order x-, x+, y-, y+).
+    const T kdir = a.bc == BC_DIRICHLET ? (T)2 : (T)0;  // boundary face: 2 kappa_p (Dirichlet)
+    auto kv_terms = [&](bool even, int a0, int am, int ap, int gy, T& Sw, T& Wt) {
+        const bool ys = EDGE && !periodic && gy == 0, yn = EDGE && !periodic && gy == a.n1 - 1;
+        if (even) {
+            const T kp = ke[a0], uw = dpp_move<kShr1>(uo[a0]), kw = dpp_move<kShr1>(ko[a0]);
+            const T wb = kdir * kp;
+            const T w0 = bxe ? wb : face_w(kw, kp);
+            const T w1 = face_w(kp, ko[a0]);
+            const T w2 = ys ? wb : face_w(ke[am], kp);
+            const T w3 = yn ? wb : face_w(kp, ke[ap]);
+            Sw = (w0 * uw + w1 * uo[a0]) + (w2 * ue[am] + w3 * ue[ap]);
+            Wt = (w0 + w1) + (w2 + w3);
+        } else {
+            const T kp = ko[a0], ue_ = dpp_move<kShl1>(ue[a0]), kE = dpp_move<kShl1>(ke[a0]);
+            const T wb = kdir * kp;
+            const T w0 = face_w(ke[a0], kp);
+            const T w1 = bxo ? wb : face_w(kp, kE);
+            const T w2 = ys ? wb : face_w(ko[am], kp);
+            const T w3 = yn ? wb : face_w(kp, ko[ap]);
+            Sw = (w0 * ue[a0] + w1 * ue_) + (w2 * uo[am] + w3 * uo[ap]);
+            Wt = (w0 + w1) + (w2 + w3);
+        }
+    };
 
 #pragma unroll
     for (int p = 0; p < PF; ++p) load_row(p, p, p & 1);
 
-    // whole ring turns (the last turn may run past the segment: those rows are read in
-    // bounds, see k_strip, and never written)
+    // whole ring turns; loads past the last visited row repeat that row (no new memory
+    // traffic), and the steps past it only touch rows that are never written
     const int nturns = (nsteps + RING - 1) / RING;
     for (int turn = 0; turn < nturns; ++turn) {
         const int rb = turn * RING;
@@ -240,7 +287,43 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
         for (int j = 0; j < RING; ++j) {
             const int rho = rb + j;
             // prefetch row rho + PF
-            load_row(rho + PF, (j + PF) % RING, ((j + PF) & 1) != 0);
+            load_row(min(rho + PF, nsteps - 1), (j + PF) % RING, ((j + PF) & 1) != 0);
+            if constexpr (RHS) {
+                // FAS right-hand side of row rho - LAG (f held r): its upper neighbour is
+                // first smoothed by phase 1 of this step, so every neighbour still holds
+                // its initial value here
+                const int r = rho - LAG;
+                int gy;
+                const bool yin = row_of(r, gy);
+                if (r >= 1 && (!EDGE || yin)) {
+                    constexpr int sh = 2 * RING;
+                    const int a0 = (j - LAG + sh) % RING;
+                    const int am = (j - LAG - 1 + sh) % RING;
+                    const int ap = (j - LAG + 1 + sh) % RING;
+                    T Se, So, We, Wo;
+                    if constexpr (KV) {
+                        kv_terms(true, a0, am, ap, gy, Se, We);
+                        kv_terms(false, a0, am, ap, gy, So, Wo);
+                    } else {
+                        const T w = dpp_move<kShr1>(uo[a0]);
+                        const T e = dpp_move<kShl1>(ue[a0]);
+                        Se = (w + uo[a0]) + (ue[am] + ue[ap]);
+                        So = (ue[a0] + e) + (uo[am] + uo[ap]);
+                        const bool yb = ybound(gy);
+                        We = yb ? we_bd : we_in;
+                        Wo = yb ? wo_bd : wo_in;
+                    }
+                    fe[a0] = fe[a0] + (ue[a0] + k * (We * ue[a0] - Se));
+                    fo[a0] = fo[a0] + (uo[a0] + k * (Wo * uo[a0] - So));
+                    const int graw = rA + r;
+                    if (graw >= y0 && graw < yend && own) {
+                        V out;
+                        out.x = fe[a0];
+                        out.y = fo[a0];
+                        *reinterpret_cast<V*>(A.fout + (int64_t)graw * a.n0 + gxe) = out;
+                    }
+                }
+            }
             if constexpr (MODE == 1) {
                 // fine grid correction u += P(u_c - R u) once both rows of a coarse row
                 // are present (rho odd: rows rho - 1 and rho)
@@ -273,7 +356,17 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                 // one when the row parity equals the colour (rA and x0 - H are even)
                 const int colour = ((s - 1) & 1) ^ FIRST;
                 const bool even_cell = (((j - s - LAG + sh) & 1) ^ colour) == 0;
-                if (even_cell) {
+                if constexpr (KV) {
+                    T Sw, Wt;
+                    kv_terms(even_cell, a0, am, ap, gy, Sw, Wt);
+                    if (even_cell) {
+                        const T nv = (fe[a0] + k * Sw) / ((T)1 + k * Wt);
+                        ue[a0] = (!EDGE || xin) ? nv : ue[a0];
+                    } else {
+                        const T nv = (fo[a0] + k * Sw) / ((T)1 + k * Wt);
+                        uo[a0] = (!EDGE || xin) ? nv : uo[a0];
+                    }
+                } else if (even_cell) {
                     const T w = dpp_move<kShr1>(uo[a0]);
                     const T Ssum = (w + uo[a0]) + (ue[am] + ue[ap]);
                     const T qv = ybound(gy) ? qe_bd : qe_in;
@@ -299,13 +392,19 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                     const int a0 = (j - S - 1 - LAG + sh) % RING;
                     const int am = (j - S - 2 - LAG + sh) % RING;
                     const int ap = (j - S - LAG + sh) % RING;
-                    const T w = dpp_move<kShr1>(uo[a0]);
-                    const T e = dpp_move<kShl1>(ue[a0]);
-                    const T Se = (w + uo[a0]) + (ue[am] + ue[ap]);
-                    const T So = (ue[a0] + e) + (uo[am] + uo[ap]);
-                    const bool yb = ybound(gy);
-                    const T We = yb ? we_bd : we_in;
-                    const T Wo = yb ? wo_bd : wo_in;
+                    T Se, So, We, Wo;
+                    if constexpr (KV) {
+                        kv_terms(true, a0, am, ap, gy, Se, We);
+                        kv_terms(false, a0, am, ap, gy, So, Wo);
+                    } else {
+                        const T w = dpp_move<kShr1>(uo[a0]);
+                        const T e = dpp_move<kShl1>(ue[a0]);
+                        Se = (w + uo[a0]) + (ue[am] + ue[ap]);
+                        So = (ue[a0] + e) + (uo[am] + uo[ap]);
+                        const bool yb = ybound(gy);
+                        We = yb ? we_bd : we_in;
+                        Wo = yb ? wo_bd : wo_in;
+                    }
                     const T re = fe[a0] - (ue[a0] + k * (We * ue[a0] - Se));
                     const T ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
                     if (inseg && own) {
@@ -341,10 +440,10 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
     }
 }
 
-template <typename T, int NU, int MODE, bool NORM>
+template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV>
 __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
 {
-    using G = StripGeom<NU, MODE>;
+    using G = StripGeom<NU, KV>;
     // Blocks are dealt round-robin over the 8 XCDs; renumber them so that each XCD takes a
     // contiguous range (neighbouring strips, which share halo columns, share its L2).
     const unsigned nblk = gridDim.x, per_xcd = (nblk + 7u) / 8u;
@@ -362,34 +461,82 @@ __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
     A.u_out = a.u_out + b * a.stride;
     A.uc = a.uc + b * a.cstride;
     A.rc = a.rc ? a.rc + b * a.cstride : nullptr;
+    A.fout = a.fout ? a.fout + b * a.stride : nullptr;
+    A.kap = a.kap;  // cell kappa: single-problem grids only
     A.partials = a.partials ? a.partials + (int64_t)b * per : nullptr;
     const int strip = wave_id % a.strips, seg = wave_id / a.strips;
     const int x0 = strip * G::TXS, y0 = seg * a.seg_rows;
-    // rows read: [y0 - H, y0 - H + turns * RING + PF), columns [x0 - HX, x0 - HX + 128)
-    const int nsteps = a.seg_rows + G::H + G::S + 1 + G::LAG;
-    const int rows_read = (nsteps + G::RING - 1) / G::RING * G::RING + G::PF;
-    const bool edge = x0 - G::HX < 0 || x0 - G::HX + 128 > a.n0 || y0 - G::H < 0 || y0 - G::H + rows_read > a.n1;
+    // rows read: [y0 - H, y0 - H + seg_rows + extra), columns [x0 - HX, x0 - HX + 128)
+    const bool edge = x0 - G::HX < 0 || x0 - G::HX + 128 > a.n0 || y0 - G::H < 0 ||
+                      y0 - G::H + a.seg_rows + G::extra > a.n1;
     if (edge) {
         if (first)
-            march<T, NU, MODE, NORM, true, 1>(a, A, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, RHS, KV, true, 1>(a, A, strip, seg, a.seg_rows, wave_id);
         else
-            march<T, NU, MODE, NORM, true, 0>(a, A, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, RHS, KV, true, 0>(a, A, strip, seg, a.seg_rows, wave_id);
     } else {
         if (first)
-            march<T, NU, MODE, NORM, false, 1>(a, A, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, RHS, KV, false, 1>(a, A, strip, seg, a.seg_rows, wave_id);
         else
-            march<T, NU, MODE, NORM, false, 0>(a, A, strip, seg, a.seg_rows, wave_id);
+            march<T, NU, MODE, NORM, RHS, KV, false, 0>(a, A, strip, seg, a.seg_rows, wave_id);
     }
 }
 
-// Rows per segment: long segments amortise the warm-up rows, short ones give small
-// levels enough wavefronts (about 2048 over the batch) to hide latency.
-inline int seg_rows_for(int n0, int n1, int txs, int batch)
+// Compute units of the current device (queried once per device).
+int device_cus()
 {
-    const int strips = (n0 + txs - 1) / txs;
-    int rows = kSegRows;
-    while (rows > 16 && (int64_t)batch * strips * ((n1 + rows - 1) / rows) < 2048) rows >>= 1;
-    return rows;
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (!v) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+// Blocks of the pre kernel resident per compute unit (its register count sets it).
+template <typename T, int NU>
+int blocks_per_cu()
+{
+    static const int nb = [] {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, reinterpret_cast<const void*>(&k_strip<T, NU, 0, false, false, false>),
+                                                         kThreads, 0) != hipSuccess || v < 1)
+            v = 1;
+        return v;
+    }();
+    return nb;
+}
+
+template <typename T>
+int wave_slots(int nu)
+{
+    int b = 1;
+    switch (nu) {
+        case 0: b = blocks_per_cu<T, 0>(); break;
+        case 1: b = blocks_per_cu<T, 1>(); break;
+        case 2: b = blocks_per_cu<T, 2>(); break;
+        default: b = blocks_per_cu<T, 3>(); break;
+    }
+    return device_cus() * b * kWaves;
+}
+
+// Rows per segment.  Every segment reads H + S + 2 rows beyond its own, so segments
+// should be long; a launch whose waves all fit the device at once has no tail of late
+// waves.  The rule takes the fewest segments that fill the wave slots once (at least
+// kMinSegRows rows each; a batch with more strips than slots gets whole columns).
+int seg_rule(const fas_grid* g, int l, int nu)
+{
+    const int n0 = g->lev[l].n[0], n1 = g->lev[l].n[1];
+    const int64_t per = (int64_t)g->batch * ((n0 + kStripCols - 1) / kStripCols);
+    const int64_t slots = g->dtype == FAS_F64 ? wave_slots<double>(nu) : wave_slots<float>(nu);
+    int64_t segs = slots / per;
+    if (segs < 1) segs = 1;
+    int rows = (int)((n1 + segs - 1) / segs);
+    rows += rows & 1;
+    return rows < kMinSegRows ? kMinSegRows : rows;
 }
 
 template <typename T>
@@ -401,14 +548,14 @@ StripArgs<T> make_args(const fas_grid* g, int l, const Coef& c, int nu)
     a.bc = g->bc;
     a.k = (T)c.kd;
     for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
-    const int txs = 112;
-    a.strips = (a.n0 + txs - 1) / txs;
-    a.seg_rows = g->seg_rows[l] ? g->seg_rows[l] : seg_rows_for(a.n0, a.n1, txs, g->batch);
+    a.strips = (a.n0 + kStripCols - 1) / kStripCols;
+    a.seg_rows = fused_seg_rows(g, l, nu);
     a.segs = (a.n1 + a.seg_rows - 1) / a.seg_rows;
     a.batch = g->batch;
     a.stride = g->lev[l].N;
     a.cstride = l < g->L ? g->lev[l + 1].N : 0;
     a.act = g->batch > 1 ? g->active : nullptr;
+    a.kap = (const T*)g->lev[l].kap;
     return a;
 }
 
@@ -418,54 +565,76 @@ inline void check_launch()
     if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-template <typename T, int MODE, bool NORM>
-void launch_nu(const fas_grid* g, const StripArgs<T>& a, int nu, int first)
+template <typename T, int MODE, bool NORM, bool RHS, bool KV>
+void launch_kv(const fas_grid* g, const StripArgs<T>& a, int nu, int first)
 {
     const unsigned blocks = (unsigned)(((int64_t)a.batch * a.strips * a.segs + kWaves - 1) / kWaves);
     switch (nu) {
-        case 0: k_strip<T, 0, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
-        case 1: k_strip<T, 1, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
-        case 2: k_strip<T, 2, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
-        case 3: k_strip<T, 3, MODE, NORM><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 0: k_strip<T, 0, MODE, NORM, RHS, KV><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 1: k_strip<T, 1, MODE, NORM, RHS, KV><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 2: k_strip<T, 2, MODE, NORM, RHS, KV><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
+        case 3: k_strip<T, 3, MODE, NORM, RHS, KV><<<blocks, kThreads, 0, g->stream>>>(a, first); break;
         default: throw Error(FAS_ERR_ARG, "fused kernels take nu <= 3");
     }
+}
+
+template <typename T, int MODE, bool NORM, bool RHS>
+void launch_nu(const fas_grid* g, const StripArgs<T>& a, int nu, int first)
+{
+    if (a.kap)
+        launch_kv<T, MODE, NORM, RHS, true>(g, a, nu, first);
+    else
+        launch_kv<T, MODE, NORM, RHS, false>(g, a, nu, first);
 }
 
 }  // namespace
 
 bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable)
 {
-    if (!g->fused || g->dim != 2 || variable || l >= g->L) return false;
+    (void)variable;  // constant and cell kappa alike (cell kappa only on single grids)
+    if (!g->fused || g->dim != 2 || l >= g->L) return false;
     if (nu_pre > 3 || nu_post > 3) return false;
     // at least one full strip wide (so a periodic halo wraps at most once) and a few
     // rows per segment
     return g->lev[l].n[0] >= 128 && g->lev[l].n[1] >= 64;
 }
 
+int fused_seg_rows(const fas_grid* g, int l, int nu)
+{
+    const int n1 = g->lev[l].n[1];
+    int rows = g->seg_force ? g->seg_force : g->seg_rows[l] ? g->seg_rows[l] : seg_rule(g, l, nu);
+    if (rows > n1) rows = n1;  // n1 is even
+    return rows;
+}
+
 int fused_tiles(const fas_grid* g, int l, int nu_post)
 {
-    const int txs = 112;
-    (void)nu_post;
     const int n0 = g->lev[l].n[0], n1 = g->lev[l].n[1];
-    const int strips = (n0 + txs - 1) / txs;
-    const int rows = g->seg_rows[l] ? g->seg_rows[l] : seg_rows_for(n0, n1, txs, g->batch);
+    const int strips = (n0 + kStripCols - 1) / kStripCols;
+    const int rows = fused_seg_rows(g, l, nu_post);
     return strips * ((n1 + rows - 1) / rows);
 }
 
-void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                      void* u_out, void* uc, void* rc)
+template <typename T>
+void pre_t(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in, void* u_out,
+           void* uc, void* rc, void* fout)
 {
-    if (g->dtype == FAS_F64) {
-        auto a = make_args<double>(g, l, c, nu);
-        a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
-        a.uc = (double*)uc, a.rc = (double*)rc;
-        launch_nu<double, 0, false>(g, a, nu, first);
-    } else {
-        auto a = make_args<float>(g, l, c, nu);
-        a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
-        a.uc = (float*)uc, a.rc = (float*)rc;
-        launch_nu<float, 0, false>(g, a, nu, first);
-    }
+    auto a = make_args<T>(g, l, c, nu);
+    a.f = (const T*)f, a.u_in = (const T*)u_in, a.u_out = (T*)u_out;
+    a.uc = (T*)uc, a.rc = (T*)rc, a.fout = (T*)fout;
+    if (fout)
+        launch_nu<T, 0, false, true>(g, a, nu, first);
+    else
+        launch_nu<T, 0, false, false>(g, a, nu, first);
+}
+
+void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                      void* u_out, void* uc, void* rc, void* fout)
+{
+    if (g->dtype == FAS_F64)
+        pre_t<double>(g, l, c, first, nu, f, u_in, u_out, uc, rc, fout);
+    else
+        pre_t<float>(g, l, c, first, nu, f, u_in, u_out, uc, rc, fout);
     check_launch();
 }
 
@@ -477,17 +646,17 @@ void launch_fused_post(const fas_grid* g, int l, const Coef& c, int first, int n
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.partials = partials;
         if (partials)
-            launch_nu<double, 1, true>(g, a, nu, first);
+            launch_nu<double, 1, true, false>(g, a, nu, first);
         else
-            launch_nu<double, 1, false>(g, a, nu, first);
+            launch_nu<double, 1, false, false>(g, a, nu, first);
     } else {
         auto a = make_args<float>(g, l, c, nu);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
         a.uc = (float*)uc, a.partials = partials;
         if (partials)
-            launch_nu<float, 1, true>(g, a, nu, first);
+            launch_nu<float, 1, true, false>(g, a, nu, first);
         else
-            launch_nu<float, 1, false>(g, a, nu, first);
+            launch_nu<float, 1, false, false>(g, a, nu, first);
     }
     check_launch();
 }

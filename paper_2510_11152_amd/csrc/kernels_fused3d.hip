@@ -8,9 +8,11 @@
 // DPP shift (a wavefront holds two tile rows; the lanes where the shift crosses a row are
 // halo columns), y-neighbours through a double-buffered LDS exchange (one barrier per
 // plane), z-neighbours from the ring.  Phase s = 1, 2 updates plane t - s - LAG when plane
-// t arrives; the residual follows on plane t - 3 - LAG.  A halo of H = 4 cells (2 for a
-// pass without a sweep) on each side of the tile and H planes above the segment are
-// recomputed; neighbouring tiles overlap.  Point formulas are those of fas_device.h.
+// t arrives; the residual follows on plane t - 3 - LAG.  A halo of H cells on each side
+// of the tile and H planes above the segment are recomputed (neighbouring tiles overlap):
+// H = 2 covers the two phases of a sweep, a pass that also takes the residual needs
+// H = 4 (three cells, rounded up to keep 2 x 2 x 2 blocks aligned).  Point formulas are
+// those of fas_device.h.
 //
 // Modes: 0 = sweep + residual + restriction (u_c = R u, r_c = R r);
 //        1 = correction u += P(u_c - R u) + sweep;  2 = sweep only.
@@ -97,10 +99,14 @@ __device__ __forceinline__ T pick_q3(const March3Args<T>& a, int W)
     return v;
 }
 
-template <int NS, int MODE>
+// halo of a pass: even, >= the phases' reach, +1 when the residual is taken
+constexpr int halo3(int ns, int mode, bool norm) { return ns && (mode == 0 || norm) ? 4 : 2; }
+
+template <int NS, int MODE, bool NORM>
 struct Geom3 {
     static constexpr int S = 2 * NS;            // colour phases in the pass
-    static constexpr int H = NS ? 4 : 2;        // halo (even, >= S + 1)
+    static constexpr int H = halo3(NS, MODE, NORM);
+    static constexpr bool RES = MODE == 0 || NORM;  // residual of the final plane
     static constexpr int LAG = MODE == 1 ? 1 : 0;
     static constexpr int PF = 2;                // planes loaded ahead
     static constexpr int RING = 8;              // >= S + 3 + LAG + PF, even
@@ -130,7 +136,7 @@ template <typename T, int NS, int MODE, bool NORM, bool EDGE, int FIRST>
 __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> A, Xchg<T>& X, int tx, int ty, int seg,
                                        double* red)
 {
-    using G = Geom3<NS, MODE>;
+    using G = Geom3<NS, MODE, NORM>;
     using V = typename Pair3<T>::V;
     constexpr int S = G::S, H = G::H, RING = G::RING, PF = G::PF, LAG = G::LAG;
     const int tid = threadIdx.x;
@@ -228,13 +234,15 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
 #pragma unroll
     for (int p = 0; p < PF; ++p) load_plane(p, p, p & 1);
 
+    // whole ring turns; loads past the last visited plane repeat that plane (no new
+    // memory traffic), and the steps past it only touch planes that are never written
     const int nturns = (nsteps + RING - 1) / RING;
     for (int turn = 0; turn < nturns; ++turn) {
         const int rb = turn * RING;
 #pragma unroll
         for (int j = 0; j < RING; ++j) {
             const int rho = rb + j;
-            load_plane(rho + PF, (j + PF) % RING, ((j + PF) & 1) != 0);
+            load_plane(min(rho + PF, nsteps - 1), (j + PF) % RING, ((j + PF) & 1) != 0);
             constexpr int sh = 4 * RING;
             T* B0 = X.buf[j & 1][0];
             T* B1 = X.buf[j & 1][1];
@@ -252,7 +260,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                 const bool other_even = (((py + j - s - LAG + sh) & 1) ^ (1 - colour)) == 0;
                 (s == 1 ? B0 : B1)[tid] = other_even ? ue[a0] : uo[a0];
             }
-            {
+            if constexpr (G::RES) {
                 const int a0 = (j - S - 1 - LAG + sh) % RING;
                 B2[tid] = ue[a0];
                 B3[tid] = uo[a0];
@@ -326,15 +334,18 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                     const int a0 = (j - S - 1 - LAG + sh) % RING;
                     const int am = (j - S - 2 - LAG + sh) % RING;
                     const int ap = (j - S - LAG + sh) % RING;
-                    const T w = dpp3<kShr1>(uo[a0]);
-                    const T e = dpp3<kShl1>(ue[a0]);
-                    const T Se = ((w + uo[a0]) + (B2[ym] + B2[yp])) + (ue[am] + ue[ap]);
-                    const T So = ((ue[a0] + e) + (B3[ym] + B3[yp])) + (uo[am] + uo[ap]);
-                    const bool zb = zbound(gz);
-                    const T We = zb ? we_zb : we_in;
-                    const T Wo = zb ? wo_zb : wo_in;
-                    const T re = fe[a0] - (ue[a0] + k * (We * ue[a0] - Se));
-                    const T ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
+                    T re = (T)0, ro = (T)0;
+                    if constexpr (G::RES) {
+                        const T w = dpp3<kShr1>(uo[a0]);
+                        const T e = dpp3<kShl1>(ue[a0]);
+                        const T Se = ((w + uo[a0]) + (B2[ym] + B2[yp])) + (ue[am] + ue[ap]);
+                        const T So = ((ue[a0] + e) + (B3[ym] + B3[yp])) + (uo[am] + uo[ap]);
+                        const bool zb = zbound(gz);
+                        const T We = zb ? we_zb : we_in;
+                        const T Wo = zb ? wo_zb : wo_in;
+                        re = fe[a0] - (ue[a0] + k * (We * ue[a0] - Se));
+                        ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
+                    }
                     if (inseg && own) {
                         V out;
                         out.x = ue[a0];
@@ -385,7 +396,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
 template <typename T, int NS, int MODE, bool NORM>
 __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first)
 {
-    using G = Geom3<NS, MODE>;
+    using G = Geom3<NS, MODE, NORM>;
     __shared__ Xchg<T> X;
     __shared__ double red[NORM ? kThreads3 : 1];
     const int per = a.tiles_x * a.tiles_y * a.segs;
@@ -399,8 +410,7 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
     A.rc = a.rc ? a.rc + b * a.cstride : nullptr;
     const int tx = w % a.tiles_x, ty = (w / a.tiles_x) % a.tiles_y, seg = w / (a.tiles_x * a.tiles_y);
     const int x0 = tx * G::UX, y0 = ty * G::UY, z0 = seg * a.seg_planes;
-    const int nsteps = a.seg_planes + G::H + G::S + 1 + G::LAG;
-    const int planes_read = (nsteps + G::RING - 1) / G::RING * G::RING + G::PF;
+    const int planes_read = a.seg_planes + G::H + G::S + 1 + G::LAG;  // the steps of a full segment
     const bool edge = x0 - G::H < 0 || x0 - G::H + kWX > a.n0 || y0 - G::H < 0 || y0 - G::H + kTPY > a.n1 ||
                       z0 - G::H < 0 || z0 - G::H + planes_read > a.n2;
     if (edge) {
@@ -420,7 +430,7 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
 }
 
 template <typename T>
-March3Args<T> make_args3(const fas_grid* g, int l, const Coef& c, int ns)
+March3Args<T> make_args3(const fas_grid* g, int l, const Coef& c, int ns, int mode, bool norm)
 {
     March3Args<T> a{};
     a.n0 = g->lev[l].n[0];
@@ -429,13 +439,14 @@ March3Args<T> make_args3(const fas_grid* g, int l, const Coef& c, int ns)
     a.bc = g->bc;
     a.k = (T)c.kd;
     for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
-    const int H = ns ? 4 : 2;
+    const int H = halo3(ns, mode, norm);
     a.tiles_x = (a.n0 + (kWX - 2 * H) - 1) / (kWX - 2 * H);
     a.tiles_y = (a.n1 + (kTPY - 2 * H) - 1) / (kTPY - 2 * H);
     a.seg_planes = kSegPlanes;
     while (a.seg_planes > 8 && (int64_t)g->batch * a.tiles_x * a.tiles_y * ((a.n2 + a.seg_planes - 1) / a.seg_planes) < 512)
         a.seg_planes >>= 1;
     if (g->seg_rows[l]) a.seg_planes = g->seg_rows[l];
+    if (g->seg_force) a.seg_planes = g->seg_force < a.n2 ? g->seg_force : a.n2;
     a.segs = (a.n2 + a.seg_planes - 1) / a.seg_planes;
     a.batch = g->batch;
     a.stride = g->lev[l].N;
@@ -461,7 +472,7 @@ template <typename T>
 void dispatch3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
                const void* u_in, void* u_out, void* uc, void* rc, double* partials)
 {
-    March3Args<T> a = make_args3<T>(g, l, c, ns);
+    March3Args<T> a = make_args3<T>(g, l, c, ns, mode, norm && mode != 0);
     a.f = (const T*)f;
     a.u_in = (const T*)u_in;
     a.u_out = (T*)u_out;
@@ -491,7 +502,7 @@ bool fused3_ok(const fas_grid* g, int l, bool variable)
 
 int fused3_partials(const fas_grid* g, int l)
 {
-    const March3Args<double> a = make_args3<double>(g, l, g->coef[l], 1);
+    const March3Args<double> a = make_args3<double>(g, l, g->coef[l], 1, 2, true);
     return a.tiles_x * a.tiles_y * a.segs;
 }
 

@@ -143,6 +143,25 @@ def test_vcycle_many_tiles_bitwise(n, bc, dtype, nu):
         assert abs(rel - ro) <= 1e-10 * ro
 
 
+@pytest.mark.parametrize("n,bc", [((1024, 512), "neumann"), ((512, 1024), "dirichlet"), ((1024, 512), "periodic")])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 3), (3, 0)])
+@pytest.mark.parametrize("transposed", [False, True])
+def test_vcycle_many_tiles_cell_kappa_bitwise(n, bc, dtype, nu, transposed):
+    """Cell kappa on grids of many march strips: face weights formed inside the march
+    (harmonic means, boundary faces) give the oracle's bits, plain and transposed."""
+    P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
+    g = grid_for(P, dtype, variable=True)
+    kap = np.exp(0.5 * I.random_field(P.shape(), 10)).astype(dtype)
+    f = I.random_field(P.shape(), 11).astype(dtype)
+    u = I.random_field(P.shape(), 12).astype(dtype)
+    ug, fg, kg = dev(u), dev(f), dev(kap)
+    for it in range(2):
+        O.vcycle(P, f, u, nu[0], nu[1], transposed=transposed, kap=kap)
+        g.vcycle(fg, ug, P.dt, P.kappa, kg, nu1=nu[0], nu2=nu[1], transposed=transposed)
+        assert np.array_equal(host(ug), u), it
+
+
 def test_heat_256_one_step_matches_oracle():
     """2D heat backward Euler, one step, 256^2, h = 1/256, dt = 1e-3, Neumann, FP64,
     16 cosine modes, V(2,2) to 1e-10: same cycle count and the same bits."""
@@ -258,3 +277,31 @@ def test_graph_and_autotune_give_the_same_bits(n, dtype):
             assert g.solve(f, u, P.dt, tol=tol) == 0
             if g.stats()["cycles"] == g0.stats()["cycles"]:
                 assert torch.equal(u, ref), opts
+
+
+@pytest.mark.parametrize("n,bc,dtype", [((1024, 512), "neumann", np.float64), ((1024, 512), "periodic", np.float32),
+                                        ((512, 1024), "dirichlet", np.float64), ((64, 64, 64), "neumann", np.float64),
+                                        ((96, 64, 32), "periodic", np.float32)])
+@pytest.mark.parametrize("rows", [16, 30, 118, 256])
+def test_forced_segment_heights_give_the_same_bits(n, bc, dtype, rows):
+    """The march segmentation (rows or planes per segment, including heights that leave a
+    ragged last segment) changes only the schedule: V-cycle iterates equal the oracle's."""
+    P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
+    g = grid_for(P, dtype).set(seg_rows=rows)
+    f = I.random_field(P.shape(), 41).astype(dtype)
+    u = I.random_field(P.shape(), 42).astype(dtype)
+    ug, fg = dev(u), dev(f)
+    for it in range(2):
+        O.vcycle(P, f, u, 2, 2)
+        g.vcycle(fg, ug, P.dt, nu1=2, nu2=2)
+        assert np.array_equal(host(ug), u), it
+
+
+def test_segment_height_option_is_checked():
+    from paper_2510_11152_amd import Grid
+    from paper_2510_11152_amd._lib import FasError
+    g = Grid((128, 128), 1 / 128)
+    for bad in (8, 17, -2):
+        with pytest.raises(FasError):
+            g.set(seg_rows=bad)
+    g.set(seg_rows=0)
