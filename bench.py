@@ -23,6 +23,38 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 
+# rocprofv3 counter summary of the finest-level march kernels (FETCH_SIZE / WRITE_SIZE,
+# calibrated by a device copy of known size) and the sources it was taken from
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat8192_fp64_strip_traffic.md")
+STRIP_SOURCES = ["paper_2510_11152_amd/csrc/kernels_fused2d.hip", "paper_2510_11152_amd/csrc/fas_device.h"]
+
+
+def strip_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in STRIP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch of a finest-level kernel class from the committed counter
+    summary ('traffic-record:' line), or None when there is none for this grid or the
+    kernel sources have changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [ln for ln in fh if ln.startswith("traffic-record:")]
+    except OSError:
+        return None
+    if not lines:
+        return None
+    rec = json.loads(lines[-1].split(":", 1)[1])
+    if rec.get("sources_sha256") != strip_sources_sha256() or rec.get("grid") != [n, n]:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -189,9 +221,9 @@ def kernel_bytes(s, d):
     }
 
 
-def cpu_baseline(u0, n, dt, cycles_per_step):
-    """The oracle (single thread) on a bounded sample: one V(2,2) cycle of the first
-    heat step at full size, scaled to seconds per step by the GPU's cycles per step."""
+def cpu_baseline(u0, n, dt, cycles_per_step, cycles=2):
+    """The oracle (single thread) on a bounded sample: the first two V(2,2) cycles of the
+    first heat step at full size, scaled to seconds per step by the GPU's cycles per step."""
     import numpy as np
 
     import oracle
@@ -200,15 +232,17 @@ def cpu_baseline(u0, n, dt, cycles_per_step):
     f = np.ascontiguousarray(u0)
     u = f.copy()
     t0 = time.perf_counter()
-    oracle.vcycle(P, f, u, 2, 2)
-    t_cycle = time.perf_counter() - t0
+    for _ in range(cycles):
+        oracle.vcycle(P, f, u, 2, 2)
+    t_all = time.perf_counter() - t0
+    t_cycle = t_all / cycles
     return {
         "value": t_cycle * cycles_per_step,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "one FP64 V(2,2) cycle of step 1 at %d^2 (%.1f s, single thread), times %.2f GPU "
-                  "cycles per step" % (n, t_cycle, cycles_per_step),
+        "sample": "the first %d FP64 V(2,2) cycles of step 1 at %d^2 (%.1f s, single thread), per cycle times "
+                  "%.2f GPU cycles per step" % (cycles, n, t_all, cycles_per_step),
     }
 
 
@@ -289,7 +323,8 @@ def main():
                    "grid": [n, n], "steps_timed": args.steps, "nu1": 2, "nu2": 2, "coarsest": 4, "tol": tol},
         "cycles_per_step": float(np.mean(cycles)),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom, n),
+                     "algorithmic_bytes": kb[dom] * n * n},
         "kernels": per_kernel,
     }
 
