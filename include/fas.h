@@ -78,7 +78,7 @@ extern "C" {
 #define FAS_OPT_AUTOTUNE 6      /* 1: on a level's first fused pass, time the candidate
                                    segment heights of the march kernels and keep the
                                    fastest (cached per process); 0 (default): fixed rule   */
-#define FAS_OPT_SEG_ROWS 7       /* > 0 (even, >= 16): rows (2D) / planes (3D) per segment of
+#define FAS_OPT_SEG_ROWS 7       /* > 0 (even, >= 8): rows (2D) / planes (3D) per segment of
                                    every march launch, overriding rule and autotuner;
                                    0 (default): rule or autotuner                         */
 

@@ -740,7 +740,7 @@ int fas_grid_set(fas_grid_t g, int option, double value)
                 return FAS_OK;
             case FAS_OPT_SEG_ROWS:
                 if (v != 0 && (v < fas::kMinSegRows || (v & 1)))
-                    return fail(FAS_ERR_ARG, "segment height must be 0 or an even number >= 16");
+                    return fail(FAS_ERR_ARG, "segment height must be 0 or an even number >= 8");
                 g->seg_force = v;
                 return FAS_OK;
         }

@@ -26,6 +26,16 @@ struct Op {
     const T* kap;    // cell field of this level, or nullptr
 };
 
+// Workgroups are dealt round-robin over the 8 XCDs, each with its own L2.  This renumbers
+// block b of n so that each XCD takes one contiguous range of the work: neighbouring
+// tiles, which read each other's halo cells, then share an L2.  A bijection on [0, n).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n)
+{
+    const unsigned per = (n + 7u) / 8u, xcd = b % 8u, idx = b / 8u;
+    const unsigned full = n % 8u == 0 ? 8u : n % 8u;  // XCDs that receive `per` blocks
+    return xcd < full ? xcd * per + idx : full * per + (xcd - full) * (per - 1u) + idx;
+}
+
 __device__ __forceinline__ int64_t cell_index(int n0, int n1, int i, int j, int l)
 {
     return (int64_t)i + (int64_t)n0 * ((int64_t)j + (int64_t)n1 * l);

@@ -5,7 +5,7 @@
 namespace fas {
 
 constexpr int kStripCols = 112;  // columns a 2D march wavefront writes
-constexpr int kMinSegRows = 16;  // shortest 2D march segment (bounds the partial sums)
+constexpr int kMinSegRows = 8;   // shortest 2D march segment (bounds the partial sums)
 
 // Whether level l (not the coarsest) runs the fused pre/post kernels.
 bool fused_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);

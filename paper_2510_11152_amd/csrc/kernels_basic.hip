@@ -461,8 +461,8 @@ void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, c
 
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u)
 {
-    unsigned nb = blocks_for(g->lev[l].N);
     const unsigned cap = (unsigned)(g->npartials / g->batch);
+    unsigned nb = blocks_for(g->lev[l].N);
     if (nb > cap) nb = cap;
     FAS_DISPATCH(g, kap, (k_resid_norm<T, D, KV><<<grid2(nb, g), kBlock, 0, g->stream>>>(
                              make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, g->partials, batch_of(g, l))));

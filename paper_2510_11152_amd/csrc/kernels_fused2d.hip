@@ -97,17 +97,11 @@ __device__ __forceinline__ int wrap(int g, int n)
     return w;
 }
 
-// q[W] for a diagonal count W of a boundary cell (selects avoid a per-lane index into
-// the kernel arguments).
+// Value for a cell with xb / yb boundary faces across x / y: A (none), B (one), C (two).
 template <typename T>
-__device__ __forceinline__ T pick_q(const StripArgs<T>& a, int W)
+__device__ __forceinline__ T sel3(bool xb, bool yb, T A, T B, T C)
 {
-    T v = a.q[4];
-    v = W == 2 ? a.q[2] : v;
-    v = W == 3 ? a.q[3] : v;
-    v = W == 5 ? a.q[5] : v;
-    v = W == 6 ? a.q[6] : v;
-    return v;
+    return yb ? (xb ? C : B) : (xb ? B : A);
 }
 
 template <int NU, bool KV>
@@ -170,8 +164,8 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
         }
     }
     // boundary faces across x of the even / odd cell (n0 even: a pair is in or out)
-    const int bxe = (EDGE && !periodic) ? (gxe == 0) : 0;
-    const int bxo = (EDGE && !periodic) ? (gxe + 2 == a.n0) : 0;
+    const bool bxe = EDGE && !periodic && gxe == 0;
+    const bool bxo = EDGE && !periodic && gxe + 2 == a.n0;
     const int dsgn = a.bc == BC_DIRICHLET ? 1 : -1;
     const T k = a.k;
     const T q4 = a.q[4];
@@ -229,24 +223,14 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
         }
         if constexpr (MODE == 1) cr[p] = c;
     };
-    // Diagonal factor and count of the lane's even / odd cell, in an inner row or in the
-    // first or last row of the domain (n1 >= 64, so a row has at most one y-boundary
-    // face); fixed per wave.
-    T qe_in = q4, qe_bd = q4, qo_in = q4, qo_bd = q4;
-    T we_in = (T)4, we_bd = (T)4, wo_in = (T)4, wo_bd = (T)4;
-    if constexpr (EDGE) {
-        if (!periodic) {
-            const int ce = 4 + dsgn * bxe, co = 4 + dsgn * bxo;
-            qe_in = pick_q(a, ce);
-            qe_bd = pick_q(a, ce + dsgn);
-            qo_in = pick_q(a, co);
-            qo_bd = pick_q(a, co + dsgn);
-            we_in = (T)ce;
-            we_bd = (T)(ce + dsgn);
-            wo_in = (T)co;
-            wo_bd = (T)(co + dsgn);
-        }
-    }
+    // Diagonal count W of a cell (and q[W] = 1/(1 + k W)): 4, plus dsgn per boundary face
+    // (n1 >= 64, so a row has at most one y-boundary face).  Only three values occur, held
+    // as scalars; a cell picks one by its x-boundary face (per lane) and its row's y-boundary
+    // face (uniform), which keeps these out of vector registers.
+    const bool npe = EDGE && !periodic;
+    const bool dir = a.bc == BC_DIRICHLET;  // uniform: constant-index picks only
+    const T qA = q4, qB = npe ? (dir ? a.q[5] : a.q[3]) : q4, qC = npe ? (dir ? a.q[6] : a.q[2]) : q4;
+    const T wA = (T)4, wB = npe ? (T)(4 + dsgn) : (T)4, wC = npe ? (T)(4 + 2 * dsgn) : (T)4;
     auto ybound = [&](int gy) -> bool { return EDGE && !periodic && (gy == 0 || gy == a.n1 - 1); };
     // Cell kappa: weighted neighbour sum Sw and weight total Wt of the even (EVEN) or odd
     // cell of ring slot a0 (rows am above, ap below), with the face weights and the
@@ -310,8 +294,8 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                         Se = (w + uo[a0]) + (ue[am] + ue[ap]);
                         So = (ue[a0] + e) + (uo[am] + uo[ap]);
                         const bool yb = ybound(gy);
-                        We = yb ? we_bd : we_in;
-                        Wo = yb ? wo_bd : wo_in;
+                        We = sel3(bxe, yb, wA, wB, wC);
+                        Wo = sel3(bxo, yb, wA, wB, wC);
                     }
                     fe[a0] = fe[a0] + (ue[a0] + k * (We * ue[a0] - Se));
                     fo[a0] = fo[a0] + (uo[a0] + k * (Wo * uo[a0] - So));
@@ -369,13 +353,13 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                 } else if (even_cell) {
                     const T w = dpp_move<kShr1>(uo[a0]);
                     const T Ssum = (w + uo[a0]) + (ue[am] + ue[ap]);
-                    const T qv = ybound(gy) ? qe_bd : qe_in;
+                    const T qv = sel3(bxe, ybound(gy), qA, qB, qC);
                     const T nv = (fe[a0] + k * Ssum) * qv;
                     ue[a0] = (!EDGE || xin) ? nv : ue[a0];
                 } else {
                     const T e = dpp_move<kShl1>(ue[a0]);
                     const T Ssum = (ue[a0] + e) + (uo[am] + uo[ap]);
-                    const T qv = ybound(gy) ? qo_bd : qo_in;
+                    const T qv = sel3(bxo, ybound(gy), qA, qB, qC);
                     const T nv = (fo[a0] + k * Ssum) * qv;
                     uo[a0] = (!EDGE || xin) ? nv : uo[a0];
                 }
@@ -402,8 +386,8 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                         Se = (w + uo[a0]) + (ue[am] + ue[ap]);
                         So = (ue[a0] + e) + (uo[am] + uo[ap]);
                         const bool yb = ybound(gy);
-                        We = yb ? we_bd : we_in;
-                        Wo = yb ? wo_bd : wo_in;
+                        We = sel3(bxe, yb, wA, wB, wC);
+                        Wo = sel3(bxo, yb, wA, wB, wC);
                     }
                     const T re = fe[a0] - (ue[a0] + k * (We * ue[a0] - Se));
                     const T ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
@@ -444,12 +428,8 @@ template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV>
 __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
 {
     using G = StripGeom<NU, KV>;
-    // Blocks are dealt round-robin over the 8 XCDs; renumber them so that each XCD takes a
-    // contiguous range (neighbouring strips, which share halo columns, share its L2).
-    const unsigned nblk = gridDim.x, per_xcd = (nblk + 7u) / 8u;
-    const unsigned xcd = blockIdx.x % 8u, idx = blockIdx.x / 8u;
-    const unsigned full = nblk % 8u == 0 ? 8u : nblk % 8u;  // XCDs that get per_xcd blocks
-    const unsigned blk = xcd < full ? xcd * per_xcd + idx : full * per_xcd + (xcd - full) * (per_xcd - 1) + idx;
+    // neighbouring strips, which share halo columns, run on one XCD
+    const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
     // the wave index is uniform across the wave: keep it (and all row bookkeeping) scalar
     const int gw = (int)blk * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int per = a.strips * a.segs;

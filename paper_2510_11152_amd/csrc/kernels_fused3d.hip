@@ -399,6 +399,8 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
     using G = Geom3<NS, MODE, NORM>;
     __shared__ Xchg<T> X;
     __shared__ double red[NORM ? kThreads3 : 1];
+    // (dispatch order, tile x fastest: the blocks resident at one time cover one z-segment
+    // of neighbouring tiles across all XCDs; an XCD-contiguous renumbering measured slower)
     const int per = a.tiles_x * a.tiles_y * a.segs;
     const int b = blockIdx.x / per, w = blockIdx.x % per;
     if (a.act && !a.act[b]) return;
