@@ -26,7 +26,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 # rocprofv3 counter summary of the finest-level march kernels (FETCH_SIZE / WRITE_SIZE,
 # calibrated by a device copy of known size) and the sources it was taken from
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat8192_fp64_strip_traffic.md")
-STRIP_SOURCES = ["paper_2510_11152_amd/csrc/kernels_fused2d.hip", "paper_2510_11152_amd/csrc/fas_device.h"]
+STRIP_SOURCES = ["paper_2510_11152_amd/csrc/strip_march.h", "paper_2510_11152_amd/csrc/kernels_fused2d.hip",
+                 "paper_2510_11152_amd/csrc/fas_device.h"]
 
 
 def strip_sources_sha256():

@@ -25,6 +25,18 @@ void launch_fused_pre(const fas_grid* g, int l, const Coef& c, int first, int nu
 void launch_fused_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
                        const void* uc, void* u_out, double* partials);
 
+// Per-precision entry points of the 2D marches (strip_march.h, instantiated in
+// kernels_fused2d_f64.hip / kernels_fused2d_f32.hip); the launchers above dispatch here.
+template <typename T>
+void strip_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in, void* u_out,
+               void* uc, void* rc, void* fout);
+template <typename T>
+void strip_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                const void* uc, void* u_out, double* partials);
+// Waves of the pre kernel with nu sweeps resident per compute unit.
+template <typename T>
+int strip_waves_per_cu(int nu);
+
 // 3D plane-march kernels (kernels_fused3d.hip): one sweep per pass.
 bool fused3_ok(const fas_grid* g, int l, bool variable);
 // Norm partial sums one pass with a norm leaves per problem on level l.

@@ -120,13 +120,14 @@ def test_vcycle_iterates_bitwise(n, coarsest, bc, variable, dtype, transposed):
         assert np.array_equal(host(ug), u), it
 
 
-@pytest.mark.parametrize("n,bc", [((1024, 512), "neumann"), ((512, 1024), "dirichlet"), ((1024, 512), "periodic")])
+@pytest.mark.parametrize("n,bc", [((1024, 512), "neumann"), ((512, 1024), "dirichlet"), ((1024, 512), "periodic"),
+                                  ((4096, 128), "neumann"), ((4096, 128), "dirichlet"), ((4096, 128), "periodic")])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nu", [(2, 2), (1, 3), (3, 0)])
 def test_vcycle_many_tiles_bitwise(n, bc, dtype, nu):
-    """Grids of many fused tiles (interior and boundary tiles, every nu variant):
-    V-cycles through the library equal the oracle's bits, and equal the library's own
-    one-phase-per-launch path."""
+    """Grids of many fused tiles (interior and boundary tiles, every nu variant, wide
+    grids with a ragged last strip): V-cycles through the library equal the oracle's
+    bits, and equal the library's own one-phase-per-launch path."""
     P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
     g = grid_for(P, dtype)
     f = I.random_field(P.shape(), 8).astype(dtype)
@@ -281,7 +282,8 @@ def test_graph_and_autotune_give_the_same_bits(n, dtype):
 
 @pytest.mark.parametrize("n,bc,dtype", [((1024, 512), "neumann", np.float64), ((1024, 512), "periodic", np.float32),
                                         ((512, 1024), "dirichlet", np.float64), ((64, 64, 64), "neumann", np.float64),
-                                        ((96, 64, 32), "periodic", np.float32)])
+                                        ((96, 64, 32), "periodic", np.float32), ((4096, 128), "dirichlet", np.float64),
+                                        ((4096, 128), "periodic", np.float32)])
 @pytest.mark.parametrize("rows", [8, 30, 118, 256])
 def test_forced_segment_heights_give_the_same_bits(n, bc, dtype, rows):
     """The march segmentation (rows or planes per segment, including heights that leave a
@@ -305,3 +307,19 @@ def test_segment_height_option_is_checked():
         with pytest.raises(FasError):
             g.set(seg_rows=bad)
     g.set(seg_rows=0)
+
+
+@pytest.mark.parametrize("bc", ["neumann", "periodic"])
+def test_full_size_8192_march_equals_phase_kernels(bc):
+    """At the benchmark's full size (8192^2 FP64, the segment rule's launch shapes) one
+    V-cycle through the march kernels equals the one-phase-per-launch kernels bit for
+    bit; those match the oracle on every smaller case above."""
+    n = 8192
+    P = _problem((n, n), 4, bc, dt=1e-4, kappa=1.0, nuc=2)
+    f = dev(I.heat_2d_large(n))
+    ua, ub = f.clone(), f.clone()
+    grid_for(P, np.float64).vcycle(f, ua, P.dt, nu1=2, nu2=2)
+    grid_for(P, np.float64).set(fused=False).vcycle(f, ub, P.dt, nu1=2, nu2=2)
+    assert torch.equal(ua, ub)
+    del ua, ub, f
+    torch.cuda.empty_cache()
