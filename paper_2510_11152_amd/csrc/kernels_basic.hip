@@ -144,16 +144,21 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Op<T> op, const T* __rest
 }
 
 // One block per problem: out[b] = fixed-order sum of partials[b*count .. b*count + count).
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials, int count,
-                                                          double* __restrict__ out)
+// 1024 threads, each summing a strided subsequence (loads unrolled so that several are in
+// flight), then a fixed tree over the threads.
+constexpr int kSumBlock = 1024;
+
+__global__ __launch_bounds__(kSumBlock) void k_sum_partials(const double* __restrict__ partials, int count,
+                                                             double* __restrict__ out)
 {
     partials += (int64_t)blockIdx.x * count;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < count; b += kBlock) acc += partials[b];
-    __shared__ double red[kBlock];
+#pragma unroll 4
+    for (int b = threadIdx.x; b < count; b += kSumBlock) acc += partials[b];
+    __shared__ double red[kSumBlock];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
+    for (int s = kSumBlock / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
         __syncthreads();
     }
@@ -462,7 +467,9 @@ void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, c
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u)
 {
     const unsigned cap = (unsigned)(g->npartials / g->batch);
+    // a grid-stride loop: a few thousand blocks fill the device, and keep the final sum short
     unsigned nb = blocks_for(g->lev[l].N);
+    if (nb > (unsigned)fas::kPartials) nb = (unsigned)fas::kPartials;
     if (nb > cap) nb = cap;
     FAS_DISPATCH(g, kap, (k_resid_norm<T, D, KV><<<grid2(nb, g), kBlock, 0, g->stream>>>(
                              make_op<T>(g, l, c, kap), (const T*)f, (const T*)u, g->partials, batch_of(g, l))));
@@ -472,7 +479,7 @@ void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap,
 
 void launch_sum_partials(const fas_grid* g, int count)
 {
-    k_sum_partials<<<(unsigned)g->batch, kBlock, 0, g->stream>>>(g->partials, count, g->norm_out);
+    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials, count, g->norm_out);
     check_launch();
 }
 
