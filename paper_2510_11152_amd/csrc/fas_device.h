@@ -36,6 +36,25 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n)
     return xcd < full ? xcd * per + idx : full * per + (xcd - full) * (per - 1u) + idx;
 }
 
+// Streaming store of a cell pair: outputs are written once and read by a later launch, so
+// they need not displace the rows that neighbouring waves still read from the caches.
+__device__ __forceinline__ void store_pair_nt(double* p, double x, double y)
+{
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = x;
+    v.y = y;
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+__device__ __forceinline__ void store_pair_nt(float* p, float x, float y)
+{
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = x;
+    v.y = y;
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+
 __device__ __forceinline__ int64_t cell_index(int n0, int n1, int i, int j, int l)
 {
     return (int64_t)i + (int64_t)n0 * ((int64_t)j + (int64_t)n1 * l);

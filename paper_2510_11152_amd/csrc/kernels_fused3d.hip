@@ -347,10 +347,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                         ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
                     }
                     if (inseg && own) {
-                        V out;
-                        out.x = ue[a0];
-                        out.y = uo[a0];
-                        *reinterpret_cast<V*>(A.u_out + (int64_t)graw * plane + (int64_t)gy0 * a.n0 + gxe) = out;
+                        store_pair_nt(A.u_out + (int64_t)graw * plane + (int64_t)gy0 * a.n0 + gxe, ue[a0], uo[a0]);
                         if constexpr (NORM) {
                             acc += (double)re * (double)re;
                             acc += (double)ro * (double)ro;
@@ -372,8 +369,8 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                                 const T ucv = ((X.rs[0][tid] + X.rs[0][pr]) + (X.rs[2][tid] + X.rs[2][pr])) * (T)0.125;
                                 const T rcv = ((X.rs[1][tid] + X.rs[1][pr]) + (X.rs[3][tid] + X.rs[3][pr])) * (T)0.125;
                                 const int64_t P = (int64_t)(graw >> 1) * cplane + (int64_t)(gy0 >> 1) * mc0 + (gxe >> 1);
-                                A.uc[P] = ucv;
-                                A.rc[P] = rcv;
+                                __builtin_nontemporal_store(ucv, A.uc + P);
+                                __builtin_nontemporal_store(rcv, A.rc + P);
                             }
                         }
                         su_prev = su;

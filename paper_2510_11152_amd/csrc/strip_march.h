@@ -300,10 +300,7 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                     fo[a0] = fo[a0] + (uo[a0] + k * (Wo * uo[a0] - So));
                     const int graw = rA + r;
                     if (graw >= y0 && graw < yend && own) {
-                        V out;
-                        out.x = fe[a0];
-                        out.y = fo[a0];
-                        *reinterpret_cast<V*>(A.fout + (int64_t)graw * a.n0 + gxe) = out;
+                        store_pair_nt(A.fout + (int64_t)graw * a.n0 + gxe, fe[a0], fo[a0]);
                     }
                 }
             }
@@ -391,18 +388,15 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
                     const T re = fe[a0] - (ue[a0] + k * (We * ue[a0] - Se));
                     const T ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
                     if (inseg && own) {
-                        V out;
-                        out.x = ue[a0];
-                        out.y = uo[a0];
-                        *reinterpret_cast<V*>(A.u_out + (int64_t)graw * a.n0 + gxe) = out;
+                        store_pair_nt(A.u_out + (int64_t)graw * a.n0 + gxe, ue[a0], uo[a0]);
                         if constexpr (MODE == 0) {
                             // rows (r - 1, r) form coarse row graw / 2 when r is odd
                             if (((j - S - 1 - LAG + sh) & 1) && graw - 1 >= y0) {
                                 const T ucv = restrict4(ue[am], uo[am], ue[a0], uo[a0]);
                                 const T rcv = restrict4(re_prev, ro_prev, re, ro);
                                 const int64_t P = (int64_t)(graw >> 1) * mc0 + (gxe >> 1);
-                                A.uc[P] = ucv;
-                                A.rc[P] = rcv;
+                                __builtin_nontemporal_store(ucv, A.uc + P);
+                                __builtin_nontemporal_store(rcv, A.rc + P);
                             }
                         }
                         if constexpr (NORM) {
