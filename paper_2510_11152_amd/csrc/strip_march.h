@@ -103,7 +103,7 @@ __device__ __forceinline__ T sel3(bool xb, bool yb, T A, T B, T C)
     return yb ? (xb ? C : B) : (xb ? B : A);
 }
 
-template <int NU, bool KV>
+template <int NU, bool KV, bool EDGE, bool FULLPF>
 struct StripGeom {
     static constexpr int S = 2 * NU;         // colour phases per pass
     static constexpr int H = 2 * NU + 2;     // halo rows above the segment
@@ -112,7 +112,12 @@ struct StripGeom {
     static constexpr int TXS = 128 - 2 * HX; // columns written per strip (112)
     static_assert(TXS == kStripCols, "strip width");
     static constexpr int LAG = 1;            // phases trail the newest row by one (see header)
-    static constexpr int PF = KV ? 2 : 4;    // rows loaded ahead (kappa rows take registers)
+    // rows loaded ahead: 4; 2 where kappa rows take registers, and on the few waves at a
+    // domain edge of the coarser-level passes, whose selects would otherwise set the
+    // register count (and so the occupancy, 3 instead of 4) of the whole kernel.  The
+    // finest-level passes (FULLPF) keep 4 everywhere: there the edge waves, which finish
+    // last, would cost more than the occupancy gains.
+    static constexpr int PF = KV ? 2 : (EDGE && !FULLPF) ? 2 : 4;
     static constexpr int RING = S + 4 + PF;  // rows held: S + 3 + LAG + PF, even
     // rows visited per full segment: H above, the segment, S + 1 + LAG below
     static constexpr int extra = H + S + 1 + LAG;
@@ -140,7 +145,7 @@ template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, bool EDGE,
 __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, int strip, int seg, int seg_rows,
                                       int wave_id)
 {
-    using G = StripGeom<NU, KV>;
+    using G = StripGeom<NU, KV, EDGE, (MODE == 0 && !RHS) || NORM>;
     using V = typename Pair<T>::V;
     constexpr int S = G::S, H = G::H, RING = G::RING, PF = G::PF, LAG = G::LAG;
     const int lane = threadIdx.x & 63;
@@ -420,7 +425,7 @@ __device__ __forceinline__ void march(const StripArgs<T>& a, const Arrays<T> A, 
 template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV>
 __global__ __launch_bounds__(kThreads) void k_strip(StripArgs<T> a, int first)
 {
-    using G = StripGeom<NU, KV>;
+    using G = StripGeom<NU, KV, false, false>;  // HX, H, extra: the same for every wave
     // neighbouring strips, which share halo columns, run on one XCD
     const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
     // the wave index is uniform across the wave: keep it (and all row bookkeeping) scalar
