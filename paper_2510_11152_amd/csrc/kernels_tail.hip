@@ -30,34 +30,32 @@ struct TailArgs {
     const int* act;           // per-problem active flags (nullable)
 };
 
-template <typename T, int DIM>
-__device__ __forceinline__ void cell_of(const Op<T>& op, int p, int& i, int& j, int& l)
-{
-    i = p % op.n0;
-    const int q = p / op.n0;
-    j = q % op.n1;
-    l = q / op.n1;
-}
+// Cells are visited row by row: the 1024 threads form kTX columns by kTailThreads / kTX
+// rows (x fastest), so no thread divides by a level size.
+constexpr int kTX = 32;
+constexpr int kTY = kTailThreads / kTX;
 
 template <typename T, int DIM, bool KV>
 __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int first, bool reverse)
 {
     const int f0 = reverse ? 1 - first : first;
     const int half = (op.n0 + 1) >> 1;
-    const int pairs = half * op.n1 * op.n2;
+    const int rows = op.n1 * op.n2;
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
     for (int s = 0; s < sweeps; ++s) {
         for (int ph = 0; ph < 2; ++ph) {
             const int parity = ph == 0 ? f0 : 1 - f0;
-            for (int t = threadIdx.x; t < pairs; t += kTailThreads) {
-                const int tt = t % half;
-                const int rest = t / half;
-                const int j = rest % op.n1, l = rest / op.n1;
-                const int i = 2 * tt + ((parity + j + l) & 1);
-                if (i >= op.n0) continue;
-                Nbhd<T, DIM> nb;
-                gather<T, DIM, KV>(op, U, i, j, l, nb);
-                const int p = (int)cell_index(op.n0, op.n1, i, j, l);
-                U[p] = gs_value<T, DIM, KV>(op, nb, F[p]);
+            for (int row = ty; row < rows; row += kTY) {
+                const int l = DIM == 3 ? row / op.n1 : 0, j = DIM == 3 ? row - l * op.n1 : row;
+                const int odd = (parity + j + l) & 1;
+                for (int tt = tx; tt < half; tt += kTX) {
+                    const int i = 2 * tt + odd;
+                    if (i >= op.n0) continue;
+                    Nbhd<T, DIM> nb;
+                    gather<T, DIM, KV>(op, U, i, j, l, nb);
+                    const int p = (int)cell_index(op.n0, op.n1, i, j, l);
+                    U[p] = gs_value<T, DIM, KV>(op, nb, F[p]);
+                }
             }
             __syncthreads();
         }
@@ -80,14 +78,18 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
         F(0)[p] = r_top[p];
     }
     __syncthreads();
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
     if (a.form_rhs) {
         // f = r_c + A_c u_c
-        for (int p = threadIdx.x; p < N0; p += kTailThreads) {
-            int i, j, l;
-            cell_of<T, DIM>(a.op[0], p, i, j, l);
-            Nbhd<T, DIM> nb;
-            gather<T, DIM, KV>(a.op[0], U(0), i, j, l, nb);
-            F(0)[p] = F(0)[p] + apply_value<T, DIM, KV>(a.op[0], nb, U(0)[p]);
+        const Op<T>& op = a.op[0];
+        for (int row = ty; row < op.n1 * op.n2; row += kTY) {
+            const int l = DIM == 3 ? row / op.n1 : 0, j = DIM == 3 ? row - l * op.n1 : row;
+            for (int i = tx; i < op.n0; i += kTX) {
+                const int p = (int)cell_index(op.n0, op.n1, i, j, l);
+                Nbhd<T, DIM> nb;
+                gather<T, DIM, KV>(op, U(0), i, j, l, nb);
+                F(0)[p] = F(0)[p] + apply_value<T, DIM, KV>(op, nb, U(0)[p]);
+            }
         }
         __syncthreads();
     }
@@ -99,10 +101,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
         T* u = U(lv);
         const T* f = F(lv);
         tail_smooth<T, DIM, KV>(op, u, f, a.pre, a.first, rev);
-        const int Nc = oc.n0 * oc.n1 * oc.n2;
-        for (int P = threadIdx.x; P < Nc; P += kTailThreads) {
-            int I, J, K;
-            cell_of<T, DIM>(oc, P, I, J, K);
+        for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
+        for (int I = tx; I < oc.n0; I += kTX) {
+            const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
+            const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             T uu[8], rr[8];
 #pragma unroll
             for (int c = 0; c < (DIM == 3 ? 8 : 4); ++c) {
@@ -122,9 +124,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
             }
         }
         __syncthreads();
-        for (int P = threadIdx.x; P < Nc; P += kTailThreads) {
-            int I, J, K;
-            cell_of<T, DIM>(oc, P, I, J, K);
+        for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
+        for (int I = tx; I < oc.n0; I += kTX) {
+            const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
+            const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             Nbhd<T, DIM> nb;
             gather<T, DIM, KV>(oc, U(lv + 1), I, J, K, nb);
             F(lv + 1)[P] = F(lv + 1)[P] + apply_value<T, DIM, KV>(oc, nb, U(lv + 1)[P]);
@@ -138,10 +141,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
         const Op<T>& op = a.op[lv];
         const Op<T>& oc = a.op[lv + 1];
         T* u = U(lv);
-        const int Nc = oc.n0 * oc.n1 * oc.n2;
-        for (int P = threadIdx.x; P < Nc; P += kTailThreads) {
-            int I, J, K;
-            cell_of<T, DIM>(oc, P, I, J, K);
+        for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
+        for (int I = tx; I < oc.n0; I += kTX) {
+            const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
+            const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             const int i = 2 * I, j = 2 * J, l = 2 * K;
             T old;
             if constexpr (DIM == 2) {
