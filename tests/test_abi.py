@@ -96,6 +96,13 @@ def test_solve_argument_errors_without_gpu(lib):
         assert lib.fas_grid_set(g, F.FAS_OPT_KMAX, 0) == F.FAS_ERR_ARG
         assert lib.fas_grid_set(g, F.FAS_OPT_KMAX, 7) == F.FAS_OK
         assert lib.fas_grid_set(g, 99, 1) == F.FAS_ERR_ARG
+        for bad in (6, 17, -2, 8.5):                     # segment height: 0 or even >= 8
+            assert lib.fas_grid_set(g, F.FAS_OPT_SEG_ROWS, bad) == F.FAS_ERR_ARG
+        for good in (0, 8, 120):
+            assert lib.fas_grid_set(g, F.FAS_OPT_SEG_ROWS, good) == F.FAS_OK
+        for opt in (F.FAS_OPT_GRAPH, F.FAS_OPT_AUTOTUNE, F.FAS_OPT_PROFILE, F.FAS_OPT_FUSED):
+            assert lib.fas_grid_set(g, opt, 2) == F.FAS_ERR_ARG
+            assert lib.fas_grid_set(g, opt, 0) == F.FAS_OK
         assert lib.fas_restrict(g, 4, buf, ctypes.c_void_p(1 << 23)) == F.FAS_ERR_ARG     # no coarser level
         assert lib.fas_kappa_grad(g, 1e-3, None, buf, buf, buf) == F.FAS_ERR_ARG
     finally:
