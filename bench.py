@@ -188,6 +188,25 @@ def bench_3d(dev, steps=5, inner=4):
     u = u0.clone()
     t_plain, cyc = _timed(lambda: plain(u), torch.cuda.synchronize)
     out = {"grid": [n, n, n], "steps": steps, "plain_s_per_step": t_plain / steps, "cycles_per_step": float(np.mean(cyc))}
+    # finest-level plane-march passes of one more (untimed) step, HIP events around each
+    # class: pre = sweep pass + sweep/residual/restriction pass (3s + 3s + 2s/8 per cell),
+    # post = correction/sweep pass + sweep/norm pass (3s + s/8 + 3s), s = 8 B
+    g.set(profile=True)
+    g.profile(reset=True)
+    v = u.clone()
+    plain(v)
+    prof = g.profile(reset=True)
+    g.set(profile=False)
+    del v
+    bytes3 = {"pre": 8 * (6 + 2 / 8) * n ** 3, "post": 8 * (6 + 1 / 8) * n ** 3}
+    k3 = {}
+    for k in ("pre", "post"):
+        launches, ms = prof[k]
+        if launches:
+            gbs = bytes3[k] / (ms / 1e3 / launches) / 1e9
+            k3[k] = {"passes_per_launch": 2, "avg_us": ms * 1e3 / launches, "algorithmic_bytes": bytes3[k],
+                     "gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
+    out["finest_level_kernels"] = k3
     g32 = Grid((n, n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev)
 
     def mixed(v):

@@ -102,10 +102,8 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
             off = align_up(off + Nl * s);
             lay->f[l] = off;
             off = align_up(off + Nl * s);
-            if (dim == 2) {
-                lay->r[l] = off;
-                off = align_up(off + Nl * s);
-            }
+            lay->r[l] = off;
+            off = align_up(off + Nl * s);
         }
         lay->kap[l] = 0;
         const bool need_kap = (flags & FAS_FLAG_VARIABLE_KAPPA) && (l >= 1 || dtype == FAS_F32);
@@ -258,18 +256,21 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 // FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
 // partials != nullptr asks the finest-level post-smoothing to leave per-tile residual
 // partial sums there; returns the number written (0 if it could not).
-// rc_in (level >= 1, fused 2D pre only): the restricted residual from which the pre pass
+// rc_in (level >= 1, march levels only): the restricted residual from which the first pass
 // forms f itself.
 void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
                     const void* rc_in = nullptr);
 
-// Whether coarse level lc forms its FAS right-hand side inside its fused 2D pre pass;
-// the finer level then leaves R(f - A u) in lev[lc].r (the pre pass reads it while
-// writing f, so it cannot be f itself).
+// Whether coarse level lc forms its FAS right-hand side inside its first march pass (2D
+// strips or 3D planes); the finer level then leaves R(f - A u) in lev[lc].r (the pass
+// reads it while writing f, so it cannot be f itself).
 bool rhs_in_pre(const fas_grid* g, int lc, int pre, int post)
 {
-    return lc >= 1 && lc <= g->L && g->lev[lc].r && g->fused && lc != fas::tail_top(g) &&
-           fas::fused_ok(g, lc, pre, post, g->lev[lc].kap != nullptr);
+    if (lc < 1 || lc > g->L || !g->lev[lc].r || !g->fused || lc == fas::tail_top(g)) return false;
+    const bool kv = g->lev[lc].kap != nullptr;
+    // 3D: formed by the first sweep-only pass, so the level needs two pre-sweeps (the
+    // sweep-residual-restriction pass has no registers to spare for it)
+    return fas::fused_ok(g, lc, pre, post, kv) || (fas::fused3_ok(g, lc, kv) && pre >= 2 && post >= 1);
 }
 
 // Where level l leaves the restricted residual for level l + 1.
@@ -315,17 +316,21 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         return 0;
     }
     if (fas::fused3_ok(g, l, g->lev[l].kap != nullptr) && pre >= 1 && post >= 1) {
-        // 3D: one sweep per pass, ping-pong between u and the level's second buffer
+        // 3D: one sweep per pass, ping-pong between u and the level's second buffer; with
+        // rc_in the first pass reads it and forms f (= lev[l].f) for the passes after it
         void* bufs[2] = {u, g->lev[l].x};
         int cur = 0;
-        autotune_level(g, l, first, 1, 1, f, u);
+        autotune_level(g, l, first, pre, post, f, u);  // times the sweep-residual-restriction pass
         if (partials && fas::fused3_partials(g, l) > g->npartials / g->batch) partials = nullptr;
+        void* const rcd = rc_dst(g, l, pre, post);
         {
             ProfScope ps(g, l, FAS_K_PRE);
-            for (int i = 0; i < pre - 1; ++i, cur ^= 1)
-                fas::launch_march3(g, l, g->coef[l], first, 2, 1, false, f, bufs[cur], bufs[cur ^ 1], nullptr, nullptr,
-                                   nullptr);
-            fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, bufs[cur], bufs[cur ^ 1], C.u, C.f, nullptr);
+            for (int i = 0; i < pre - 1; ++i, cur ^= 1) {
+                const bool form = rc_in && i == 0;
+                fas::launch_march3(g, l, g->coef[l], first, 2, 1, false, form ? rc_in : f, bufs[cur], bufs[cur ^ 1],
+                                   nullptr, nullptr, nullptr, form ? g->lev[l].f : nullptr);
+            }
+            fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, bufs[cur], bufs[cur ^ 1], C.u, rcd, nullptr);
             cur ^= 1;
             ps.end();
         }
@@ -443,7 +448,8 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
         for (int rep = 0; rep < 3; ++rep) {
             FAS_HIP_CHECK(hipEventRecord(e0, g->stream));
             if (d3)
-                fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, u, g->lev[l].x, C.u, C.f, nullptr);
+                fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, u, g->lev[l].x, C.u, rc_dst(g, l, pre, post),
+                                   nullptr);
             else if (rc_in)
                 fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, g->lev[l].x, C.u,
                                       rc_dst(g, l, pre, post), g->lev[l].f);

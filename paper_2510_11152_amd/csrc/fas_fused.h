@@ -43,8 +43,9 @@ bool fused3_ok(const fas_grid* g, int l, bool variable);
 int fused3_partials(const fas_grid* g, int l);
 // mode 0: sweep, then uc = R u_out, rc = R(f - A u_out); mode 1: u_in + P(uc - R u_in),
 // then a sweep; mode 2: a sweep.  ns = sweeps in the pass (1).  norm: per-block sums of
-// r^2 (r = f - A u_out) into partials.
+// r^2 (r = f - A u_out) into partials.  fout != nullptr (mode 2, no norm): f holds
+// r = R(f_fine - A_fine u_fine) and the pass first forms f = r + A u_in into fout.
 void launch_march3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
-                   const void* u_in, void* u_out, void* uc, void* rc, double* partials);
+                   const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout = nullptr);
 
 }  // namespace fas

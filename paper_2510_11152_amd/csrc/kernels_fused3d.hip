@@ -16,6 +16,10 @@
 //
 // Modes: 0 = sweep + residual + restriction (u_c = R u, r_c = R r);
 //        1 = correction u += P(u_c - R u) + sweep;  2 = sweep only.
+// RHS (the first pass of a coarse level, mode 2): f holds r = R(f - A u) of the finer
+// level, and the pass first forms the FAS right-hand side f = r + A u, one plane ahead of
+// the sweep while every neighbour still holds its initial value, then uses it and writes
+// it for the level's later passes.
 // Any mode with NORM leaves one partial sum of the squared residual per block.
 #include <hip/hip_runtime.h>
 
@@ -47,6 +51,7 @@ struct March3Args {
     T* u_out;
     T* uc;
     T* rc;
+    T* fout;  // RHS passes: the formed right-hand side
     double* partials;
 };
 
@@ -102,12 +107,13 @@ __device__ __forceinline__ T pick_q3(const March3Args<T>& a, int W)
 // halo of a pass: even, >= the phases' reach, +1 when the residual is taken
 constexpr int halo3(int ns, int mode, bool norm) { return ns && (mode == 0 || norm) ? 4 : 2; }
 
-template <int NS, int MODE, bool NORM>
+template <int NS, int MODE, bool NORM, bool RHS>
 struct Geom3 {
     static constexpr int S = 2 * NS;            // colour phases in the pass
     static constexpr int H = halo3(NS, MODE, NORM);
     static constexpr bool RES = MODE == 0 || NORM;  // residual of the final plane
-    static constexpr int LAG = MODE == 1 ? 1 : 0;
+    // the correction (mode 1) and the right-hand side (RHS) need the plane below untouched
+    static constexpr int LAG = (MODE == 1 || RHS) ? 1 : 0;
     static constexpr int PF = 2;                // planes loaded ahead
     static constexpr int RING = 8;              // >= S + 3 + LAG + PF, even
     static constexpr int UX = kWX - 2 * H;      // cells written per tile in x
@@ -130,14 +136,16 @@ struct Arrays3 {
     T* u_out;
     T* uc;
     T* rc;
+    T* fout;
 };
 
-template <typename T, int NS, int MODE, bool NORM, bool EDGE, int FIRST>
+template <typename T, int NS, int MODE, bool NORM, bool RHS, bool EDGE, int FIRST>
 __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> A, Xchg<T>& X, int tx, int ty, int seg,
                                        double* red)
 {
-    using G = Geom3<NS, MODE, NORM>;
+    using G = Geom3<NS, MODE, NORM, RHS>;
     using V = typename Pair3<T>::V;
+    static_assert(!RHS || MODE == 2, "the right-hand side is formed by a level's first, sweep-only pass");
     constexpr int S = G::S, H = G::H, RING = G::RING, PF = G::PF, LAG = G::LAG;
     const int tid = threadIdx.x;
     const int px = tid % kTPX, py = tid / kTPX;
@@ -272,7 +280,35 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                     B5[tid] = ue[j] + uo[j];
                 }
             }
+            if constexpr (RHS) {
+                const int a0 = (j - LAG + sh) % RING;  // plane rho - 1, initial values
+                B4[tid] = ue[a0];
+                B5[tid] = uo[a0];
+            }
             __syncthreads();
+            if constexpr (RHS) {
+                // FAS right-hand side of plane rho - LAG (f held r)
+                const int r = rho - LAG;
+                int gz;
+                const bool zin = plane_of(r, gz);
+                if (r >= 1 && (!EDGE || zin)) {
+                    const int a0 = (j - LAG + sh) % RING;
+                    const int am = (j - LAG - 1 + sh) % RING;
+                    const int ap = (j - LAG + 1 + sh) % RING;
+                    const T w = dpp3<kShr1>(uo[a0]);
+                    const T e = dpp3<kShl1>(ue[a0]);
+                    const T Se = ((w + uo[a0]) + (B4[ym] + B4[yp])) + (ue[am] + ue[ap]);
+                    const T So = ((ue[a0] + e) + (B5[ym] + B5[yp])) + (uo[am] + uo[ap]);
+                    const bool zb = zbound(gz);
+                    const T We = zb ? we_zb : we_in;
+                    const T Wo = zb ? wo_zb : wo_in;
+                    fe[a0] = fe[a0] + (ue[a0] + k * (We * ue[a0] - Se));
+                    fo[a0] = fo[a0] + (uo[a0] + k * (Wo * uo[a0] - So));
+                    const int graw = rA + r;
+                    if (graw >= z0 && graw < zend && own)
+                        store_pair_nt(A.fout + (int64_t)graw * plane + (int64_t)gy0 * a.n0 + gxe, fe[a0], fo[a0]);
+                }
+            }
             if constexpr (MODE == 1) {
                 // fine grid correction on planes (rho - 1, rho) when rho is odd
                 if (j & 1) {
@@ -390,10 +426,10 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
     }
 }
 
-template <typename T, int NS, int MODE, bool NORM>
+template <typename T, int NS, int MODE, bool NORM, bool RHS>
 __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first)
 {
-    using G = Geom3<NS, MODE, NORM>;
+    using G = Geom3<NS, MODE, NORM, RHS>;
     __shared__ Xchg<T> X;
     __shared__ double red[NORM ? kThreads3 : 1];
     // (dispatch order, tile x fastest: the blocks resident at one time cover one z-segment
@@ -407,6 +443,7 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
     A.u_out = a.u_out + b * a.stride;
     A.uc = a.uc ? a.uc + b * a.cstride : nullptr;
     A.rc = a.rc ? a.rc + b * a.cstride : nullptr;
+    A.fout = a.fout ? a.fout + b * a.stride : nullptr;
     const int tx = w % a.tiles_x, ty = (w / a.tiles_x) % a.tiles_y, seg = w / (a.tiles_x * a.tiles_y);
     const int x0 = tx * G::UX, y0 = ty * G::UY, z0 = seg * a.seg_planes;
     const int planes_read = a.seg_planes + G::H + G::S + 1 + G::LAG;  // the steps of a full segment
@@ -414,14 +451,14 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
                       z0 - G::H < 0 || z0 - G::H + planes_read > a.n2;
     if (edge) {
         if (first)
-            march3<T, NS, MODE, NORM, true, 1>(a, A, X, tx, ty, seg, red);
+            march3<T, NS, MODE, NORM, RHS, true, 1>(a, A, X, tx, ty, seg, red);
         else
-            march3<T, NS, MODE, NORM, true, 0>(a, A, X, tx, ty, seg, red);
+            march3<T, NS, MODE, NORM, RHS, true, 0>(a, A, X, tx, ty, seg, red);
     } else {
         if (first)
-            march3<T, NS, MODE, NORM, false, 1>(a, A, X, tx, ty, seg, red);
+            march3<T, NS, MODE, NORM, RHS, false, 1>(a, A, X, tx, ty, seg, red);
         else
-            march3<T, NS, MODE, NORM, false, 0>(a, A, X, tx, ty, seg, red);
+            march3<T, NS, MODE, NORM, RHS, false, 0>(a, A, X, tx, ty, seg, red);
     }
     if constexpr (NORM) {
         if (threadIdx.x == 0) a.partials[(int64_t)b * per + w] = red[0];
@@ -460,16 +497,16 @@ inline void check_launch3()
     if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-template <typename T, int NS, int MODE, bool NORM>
+template <typename T, int NS, int MODE, bool NORM, bool RHS = false>
 void go3(const fas_grid* g, const March3Args<T>& a, int first)
 {
     const unsigned blocks = (unsigned)((int64_t)a.batch * a.tiles_x * a.tiles_y * a.segs);
-    k_march3<T, NS, MODE, NORM><<<blocks, kThreads3, 0, g->stream>>>(a, first);
+    k_march3<T, NS, MODE, NORM, RHS><<<blocks, kThreads3, 0, g->stream>>>(a, first);
 }
 
 template <typename T>
 void dispatch3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
-               const void* u_in, void* u_out, void* uc, void* rc, double* partials)
+               const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout)
 {
     March3Args<T> a = make_args3<T>(g, l, c, ns, mode, norm && mode != 0);
     a.f = (const T*)f;
@@ -478,8 +515,12 @@ void dispatch3(const fas_grid* g, int l, const Coef& c, int first, int mode, int
     a.uc = (T*)uc;
     a.rc = (T*)rc;
     a.partials = partials;
+    a.fout = (T*)fout;
     if (ns != 1) throw Error(FAS_ERR_ARG, "3D march kernels run one sweep per pass");
-    if (mode == 0) {
+    if (fout && (mode != 2 || norm)) throw Error(FAS_ERR_ARG, "internal: right-hand side formed by a sweep-only pass");
+    if (fout) {
+        go3<T, 1, 2, false, true>(g, a, first);
+    } else if (mode == 0) {
         go3<T, 1, 0, false>(g, a, first);
     } else if (mode == 1) {
         if (norm) go3<T, 1, 1, true>(g, a, first);
@@ -506,12 +547,12 @@ int fused3_partials(const fas_grid* g, int l)
 }
 
 void launch_march3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
-                   const void* u_in, void* u_out, void* uc, void* rc, double* partials)
+                   const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout)
 {
     if (g->dtype == FAS_F64)
-        dispatch3<double>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials);
+        dispatch3<double>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials, fout);
     else
-        dispatch3<float>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials);
+        dispatch3<float>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials, fout);
 }
 
 }  // namespace fas

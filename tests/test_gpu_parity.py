@@ -352,3 +352,19 @@ def test_full_size_8192_residual_matches_oracle():
     assert np.array_equal(host(r), ro)
     rn = float(np.sqrt(np.dot(ro.ravel(), ro.ravel())))
     assert abs(nrm - rn) <= 1e-12 * rn
+
+
+@pytest.mark.parametrize("transposed", [False, True])
+def test_full_size_2048_cell_kappa_march_equals_phase_kernels(transposed):
+    """At the differentiable workload's size (2048^2 FP64, kappa = exp(g/2) of a smooth
+    cosine field) one plain and one transposed V-cycle through the cell-kappa marches
+    equal the one-phase-per-launch kernels bit for bit."""
+    n = 2048
+    P = _problem((n, n), 4, "neumann", dt=1e-4, kappa=1.0, nuc=2)
+    kap = dev(I.kappa_field(n))
+    f = dev(I.random_field(P.shape(), 61))
+    ua, ub = f.clone(), f.clone()
+    grid_for(P, np.float64, variable=True).vcycle(f, ua, P.dt, 1.0, kap, nu1=2, nu2=2, transposed=transposed)
+    grid_for(P, np.float64, variable=True).set(fused=False).vcycle(f, ub, P.dt, 1.0, kap, nu1=2, nu2=2,
+                                                                   transposed=transposed)
+    assert torch.equal(ua, ub)
