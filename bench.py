@@ -395,7 +395,7 @@ def main():
         result["heat3d"] = bench_3d(dev, inner=args.inner3d)
 
     if not args.no_cpu_baseline:
-        print("bench: timing the oracle on one cycle", file=sys.stderr, flush=True)
+        print("bench: timing the oracle on two cycles", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(u0_h, n, dt, result["cycles_per_step"])
 
     result["device"] = torch.cuda.get_device_name(dev)
