@@ -78,14 +78,21 @@ struct Nbhd {
     int nout;
 };
 
-// Gather from a full level array in global memory.
+// Gather from a full level array (global memory or LDS).  Branch-free: every neighbour is
+// loaded from an in-range index (wrapped on periodic grids, clamped otherwise) and a
+// neighbour across a non-periodic boundary is then replaced by 0 (weight 0, or 2 kappa_p
+// on a Dirichlet face) by selects, which give the same values as skipping it.
 template <typename T, int DIM, bool KV>
 __device__ __forceinline__ void gather(const Op<T>& op, const T* __restrict__ u, int i, int j, int l,
                                        Nbhd<T, DIM>& s)
 {
     const int c[3] = {i, j, l};
     const int n[3] = {op.n0, op.n1, op.n2};
+    const bool periodic = op.bc == BC_PERIODIC;
     const int64_t p = cell_index(op.n0, op.n1, i, j, l);
+    T kp = (T)0;
+    if constexpr (KV) kp = op.kap[p];
+    const T wb = op.bc == BC_DIRICHLET ? (T)2 * kp : (T)0;  // weight of a boundary face
     s.nout = 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -93,20 +100,19 @@ __device__ __forceinline__ void gather(const Op<T>& op, const T* __restrict__ u,
         for (int side = 0; side < 2; ++side) {
             const int slot = 2 * a + side;
             int d[3] = {c[0], c[1], c[2]};
-            d[a] += side ? 1 : -1;
-            bool in = d[a] >= 0 && d[a] < n[a];
-            if (!in && op.bc == BC_PERIODIC) {
-                d[a] = d[a] < 0 ? n[a] - 1 : 0;
-                in = true;
-            }
-            if (in) {
-                const int64_t q = cell_index(op.n0, op.n1, d[0], d[1], d[2]);
-                s.v[slot] = u[q];
-                if constexpr (KV) s.w[slot] = side ? face_w(op.kap[p], op.kap[q]) : face_w(op.kap[q], op.kap[p]);
-            } else {
-                ++s.nout;
-                s.v[slot] = (T)0;
-                if constexpr (KV) s.w[slot] = op.bc == BC_DIRICHLET ? (T)2 * op.kap[p] : (T)0;
+            const int e = c[a] + (side ? 1 : -1);
+            const bool in = e >= 0 && e < n[a];
+            const int wrapped = e < 0 ? n[a] - 1 : (e >= n[a] ? 0 : e);
+            d[a] = periodic ? wrapped : (in ? e : c[a]);
+            const bool use = periodic || in;
+            const int64_t q = cell_index(op.n0, op.n1, d[0], d[1], d[2]);
+            const T v = u[q];
+            s.v[slot] = use ? v : (T)0;
+            s.nout += use ? 0 : 1;
+            if constexpr (KV) {
+                const T kq = op.kap[q];
+                const T w = side ? face_w(kp, kq) : face_w(kq, kp);
+                s.w[slot] = use ? w : wb;
             }
         }
     }
