@@ -161,7 +161,7 @@ def bench_adjoint(dev):
     return {"grid": [n, n], "steps": T, "ckpt": 4, "forward_backward_s": t, "loss": loss}
 
 
-def bench_3d(dev, steps=5, inner=4):
+def bench_3d(dev, steps=5, inner=4, cpu=True):
     """3D heat at 512^3 (7-point, 8-set X-MCGS, Neumann, dt = 1e-4): plain FP64 V(2,2)
     steps to 1e-10, then the same steps with FP32 inner cycles in FP64 correction."""
     import numpy as np
@@ -171,7 +171,8 @@ def bench_3d(dev, steps=5, inner=4):
     from paper_2510_11152_amd import Grid, solve_mixed
 
     n, dt = 512, 1e-4
-    u0 = torch.from_numpy(fas_inputs.heat_3d(n)).to(dev)
+    u0_h = fas_inputs.heat_3d(n)
+    u0 = torch.from_numpy(u0_h).to(dev)
     g = Grid((n, n, n), 1.0 / n, coarsest=4, device=dev)
     rhs = torch.empty_like(u0)
 
@@ -228,6 +229,21 @@ def bench_3d(dev, steps=5, inner=4):
                 "mixed_max_rel_diff": (v - u).abs().max().item() / u.abs().max().item()})
     del g, g32, u0, rhs, u, v
     torch.cuda.empty_cache()
+    if cpu:
+        # the oracle (one thread) on a bounded sample: the first V(2,2) cycle of step 1
+        import oracle
+
+        P = oracle.Problem(n=(n, n, n), h=1.0 / n, dt=dt, kappa=1.0, bc="neumann", coarsest=4, nuc=2)
+        f = np.ascontiguousarray(u0_h)
+        uh = f.copy()
+        t0 = time.perf_counter()
+        oracle.vcycle(P, f, uh, 2, 2)
+        t_cycle = time.perf_counter() - t0
+        value = t_cycle * out["cycles_per_step"]
+        out["cpu_baseline"] = {"value": value, "unit": "s", "cores": 1, "kind": "oracle",
+                               "sample": "the first FP64 V(2,2) cycle of step 1 at 512^3 (%.1f s, single thread), "
+                                         "times %.2f GPU cycles per step" % (t_cycle, out["cycles_per_step"])}
+        out["speedup_vs_cpu_baseline"] = value / out["plain_s_per_step"]
     return out
 
 
@@ -392,11 +408,12 @@ def main():
         result["adjoint"] = bench_adjoint(dev)
     if "3d" in forms:
         print("bench: 3D heat", file=sys.stderr, flush=True)
-        result["heat3d"] = bench_3d(dev, inner=args.inner3d)
+        result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline)
 
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on two cycles", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(u0_h, n, dt, result["cycles_per_step"])
+        result["speedup_vs_cpu_baseline"] = result["cpu_baseline"]["value"] / result["value"]
 
     result["device"] = torch.cuda.get_device_name(dev)
     print(json.dumps(result), flush=True)
