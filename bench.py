@@ -90,7 +90,7 @@ def bench_batched(dev):
     import torch
 
     import fas_inputs
-    from paper_2510_11152_amd import GrainGrowth, Grid, solve_uneven
+    from paper_2510_11152_amd import GrainGrowth, Grid, UnevenBatch
 
     sync = torch.cuda.synchronize
     fields = fas_inputs.uneven_batch()
@@ -110,9 +110,13 @@ def bench_batched(dev):
             cyc.append(g.stats()["cycles"])
         return cyc
 
+    # one batched solve per size group, grids planned once, V-cycles captured in HIP graphs
+    # and segment heights autotuned on the first solve
+    ub = UnevenBatch([tuple(r.shape) for r in rhs], device=dev, graph=True, autotune=True)
+
     def batched():
         us = [r.clone() for r in rhs]
-        return solve_uneven(rhs, us, 1e-4, tol=1e-10)
+        return ub.solve(rhs, us, 1e-4, tol=1e-10)
 
     looped()
     batched()
@@ -122,10 +126,10 @@ def bench_batched(dev):
                       "sizes": sorted(set(int(r.shape[0]) for r in rhs)),
                       "batched_s": t_batch, "looped_s": t_loop, "speedup": t_loop / t_batch,
                       "all_converged": all(s == 0 for s in st), "max_cycles": int(max(cyc_b))}}
-    del rhs, grids
+    del rhs, grids, ub
     q, n = 1189, 512
     eta = torch.from_numpy(fas_inputs.grain_init(q, n)).to(dev)
-    model = GrainGrowth(q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, device=dev)
+    model = GrainGrowth(q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, device=dev, graph=True, autotune=True)
     model.step(eta.clone())
     steps = 3
     t_grain, cys = _timed(lambda: [model.step(eta) for _ in range(steps)], sync)

@@ -193,24 +193,62 @@ def heat(grid, u0, steps, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=
     return (u, states) if keep else u
 
 
+class UnevenBatch:
+    """Problems of different sizes on the unit square (h = 1/n), solved as one batched
+    solve per distinct shape.  The grids of the groups are planned once, so repeated
+    solves reuse their workspaces and, with graph=True / autotune=True, their captured
+    V-cycles and tuned segment heights."""
+
+    def __init__(self, shapes, dtype=torch.float64, coarsest=4, bc="neumann", device="cuda", graph=False,
+                 autotune=False):
+        self.groups = {}
+        for i, shp in enumerate(shapes):
+            self.groups.setdefault(tuple(shp), []).append(i)
+        self.grids = {}
+        self.stacks = {}
+        for shp, idx in self.groups.items():
+            n = tuple(reversed(shp))
+            g = Grid(n, 1.0 / n[0], bc=bc, dtype=dtype, coarsest=coarsest, device=device, batch=len(idx))
+            self.grids[shp] = g.set(graph=graph, autotune=autotune)
+            # the stacked right-hand sides and iterates of the group (fixed addresses, so a
+            # captured cycle stays valid from one solve to the next)
+            self.stacks[shp] = (torch.empty((len(idx),) + shp, dtype=dtype, device=device),
+                                torch.empty((len(idx),) + shp, dtype=dtype, device=device))
+        self.count = len(shapes)
+
+    def solve(self, rhs_list, u_list, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2):
+        """u_list entries are updated in place; returns per-problem (status, V-cycles)
+        lists in input order."""
+        if len(rhs_list) != self.count or len(u_list) != self.count:
+            raise ValueError("expected %d problems" % self.count)
+        status = [None] * self.count
+        cycles = [None] * self.count
+        for shp, idx in self.groups.items():
+            R, U = self.stacks[shp]
+            for k, i in enumerate(idx):
+                r, u = rhs_list[i], u_list[i]
+                if tuple(r.shape) != shp or tuple(u.shape) != shp:
+                    raise ValueError("problem %d does not have shape %s" % (i, shp))
+                R[k].copy_(r)
+                U[k].copy_(u)
+            st, cy = self.grids[shp].solve_batched(R, U, dt, kappa, tol, nu1, nu2)
+            for k, i in enumerate(idx):
+                u_list[i].copy_(U[k])
+                status[i], cycles[i] = st[k], cy[k]
+        return status, cycles
+
+
 def solve_uneven(rhs_list, u_list, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2, coarsest=4, bc="neumann"):
     """Problems of different sizes on the unit square (h = 1/n): one batched solve per
-    distinct shape.  u_list entries are updated in place.  Returns per-problem
-    (status, V-cycles) lists in input order."""
-    groups = {}
+    distinct shape (a one-shot UnevenBatch).  u_list entries are updated in place.
+    Returns per-problem (status, V-cycles) lists in input order."""
     for i, (r, u) in enumerate(zip(rhs_list, u_list)):
         if r.shape != u.shape or r.dtype != u.dtype:
             raise ValueError("rhs and u of problem %d differ in shape or dtype" % i)
-        groups.setdefault((tuple(r.shape), r.dtype, r.device), []).append(i)
-    status = [None] * len(rhs_list)
-    cycles = [None] * len(rhs_list)
-    for (shape, dtype, device), idx in groups.items():
-        n = tuple(reversed(shape))
-        g = Grid(n, 1.0 / n[0], bc=bc, dtype=dtype, coarsest=coarsest, device=device, batch=len(idx))
-        R = torch.stack([rhs_list[i] for i in idx]).contiguous()
-        U = torch.stack([u_list[i] for i in idx]).contiguous()
-        st, cy = g.solve_batched(R, U, dt, kappa, tol, nu1, nu2)
-        for k, i in enumerate(idx):
-            u_list[i].copy_(U[k])
-            status[i], cycles[i] = st[k], cy[k]
-    return status, cycles
+    dtypes = {r.dtype for r in rhs_list}
+    devices = {r.device for r in rhs_list}
+    if len(dtypes) > 1 or len(devices) > 1:
+        raise ValueError("all problems must share one dtype and device")
+    batch = UnevenBatch([tuple(r.shape) for r in rhs_list], dtype=rhs_list[0].dtype, coarsest=coarsest, bc=bc,
+                        device=rhs_list[0].device)
+    return batch.solve(rhs_list, u_list, dt, kappa, tol, nu1, nu2)

@@ -33,10 +33,12 @@ class GrainGrowth:
     """q fields on an n x n periodic grid, spacing h, time step dt, gradient coefficient
     kappa; FP32 storage and solves (relative residual tol per field)."""
 
-    def __init__(self, q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, coarsest=4, nu1=2, nu2=2, device="cuda"):
+    def __init__(self, q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, coarsest=4, nu1=2, nu2=2, device="cuda",
+                 graph=False, autotune=False):
         self.q, self.n, self.h, self.dt, self.kappa, self.tol = q, n, h, dt, kappa, tol
         self.nu1, self.nu2 = nu1, nu2
         self.grid = Grid((n, n), h, bc="periodic", dtype=torch.float32, coarsest=coarsest, device=device, batch=q)
+        self.grid.set(graph=graph, autotune=autotune)
         self.rhs = None
 
     def step(self, eta):

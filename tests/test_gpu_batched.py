@@ -94,6 +94,25 @@ def test_uneven_batch_groups_equal_single_solves():
             assert torch.equal(u, us[b])
 
 
+def test_uneven_batch_reuse_with_graph_and_autotune():
+    """A planned UnevenBatch solved twice (the second solve replays the captured cycles and
+    the tuned segment heights) gives the one-shot solve's bits both times."""
+    from paper_2510_11152_amd import UnevenBatch, solve_uneven
+    sizes = [128, 64, 256, 128, 64]
+    fields = [I.cosine_modes(m, 2, 16, np.random.default_rng(70 + b)) for b, m in enumerate(sizes)]
+    rhs = [torch.from_numpy(f.copy()).to(DEV) for f in fields]
+    ref = [r.clone() for r in rhs]
+    st0, cy0 = solve_uneven(rhs, ref, dt=1e-4, tol=1e-10)
+    ub = UnevenBatch([tuple(r.shape) for r in rhs], device=DEV, graph=True, autotune=True)
+    for rep in range(2):
+        us = [r.clone() for r in rhs]
+        st, cy = ub.solve(rhs, us, 1e-4, tol=1e-10)
+        assert st == st0 and all(s == 0 for s in st)
+        for b in range(len(sizes)):
+            if cy[b] == cy0[b]:
+                assert torch.equal(us[b], ref[b]), (rep, b)
+
+
 def test_batched_graph_replay_equals_launches():
     from paper_2510_11152_amd import Grid
     B, n = 6, (256, 256)
