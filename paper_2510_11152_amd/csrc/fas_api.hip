@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -405,6 +406,13 @@ void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
 // ---- autotuner: segment height of the march kernels ------------------------------------
 // Candidates are timed on the level's own data (the pre pass is out of place, so running
 // it again recomputes the same outputs); the fastest is kept per grid and per process.
+// Shared by every grid of the process (grids on different threads included): guarded.
+std::mutex& tune_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
 std::map<std::string, int>& tune_cache()
 {
     static std::map<std::string, int> cache;
@@ -419,10 +427,13 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
     char key[160];
     snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->lev[l].n[2],
              g->dtype, g->batch, pre, post, rc_in ? 1 : 0);
-    auto it = tune_cache().find(key);
-    if (it != tune_cache().end()) {
-        g->seg_rows[l] = it->second;
-        return;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            g->seg_rows[l] = it->second;
+            return;
+        }
     }
     // 3D: planes per segment.  2D: the rule's rows (one round of waves), half and twice
     // that, and a few fixed heights.
@@ -469,7 +480,10 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     g->seg_rows[l] = best_rows;
-    tune_cache()[key] = best_rows;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        tune_cache()[key] = best_rows;
+    }
 }
 
 // ---- HIP graph of one V-cycle ------------------------------------------------------------
