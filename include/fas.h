@@ -183,7 +183,7 @@ typedef struct {
     double ms[FAS_K_COUNT];    /* summed HIP-event durations of those launches (ms)         */
 } fas_profile_t;
 
-/* Batched solves (spec form 2; the paper solves its q grain-growth fields one
+/* Batched solves (the paper solves its q grain-growth fields one
  * after the other): `batch` independent problems of one shape, bc, h and dtype, kappa
  * constant.  Every array argument holds the whole batch contiguously: problem b's
  * array starts b * (cells per problem) elements in.  Each kernel launch serves every

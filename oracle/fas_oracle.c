@@ -9,7 +9,7 @@
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (oracle/build.py).  No fast-math, no
  * FMA contraction, so each expression rounds exactly as written.
  *
- * Problem (spec form of eq. PDE_discret): one backward-Euler heat step
+ * Problem (eq. PDE_discret with a time step and a diffusion coefficient): one backward-Euler heat step
  *     u - dt * div(kappa grad u) = f   on a cell-centred grid, spacing h,
  * with homogeneous Neumann (default), Dirichlet (ghost = -adjacent value, the reading
  * that reproduces Tables 2-3) or periodic boundaries.  Layout: x fastest,
@@ -111,7 +111,7 @@ static int og_diag_count(const og_problem* P, int nout)
 #undef REAL
 #undef SFX
 
-/* Mixed precision (spec form 1; the paper is silent): FP64 defect correction
+/* Mixed precision (the paper is silent): FP64 defect correction
  * around FP32 V-cycles.  Per outer iteration:
  *     r = f - A u (FP64);  rho = ||r||;  stop if rho <= tol*||f||
  *     r32 = fp32(r / rho);  e = 0;  `inner` FP32 V-cycles on A e = r32
