@@ -23,17 +23,17 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 
-# rocprofv3 counter summary of the finest-level march kernels (FETCH_SIZE / WRITE_SIZE,
+# rocprofv3 counter summary of the finest-level pass kernels (FETCH_SIZE / WRITE_SIZE,
 # calibrated by a device copy of known size) and the sources it was taken from
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat8192_fp64_strip_traffic.md")
-STRIP_SOURCES = ["paper_2510_11152_amd/csrc/strip_march.h", "paper_2510_11152_amd/csrc/kernels_fused2d.hip",
-                 "paper_2510_11152_amd/csrc/fas_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "heat8192_fp64_tile_traffic.md")
+PASS_SOURCES = ["paper_2510_11152_amd/csrc/kernels_tile2d.hip", "paper_2510_11152_amd/csrc/fas_device.h",
+                "paper_2510_11152_amd/csrc/march_util.h"]
 
 
-def strip_sources_sha256():
+def pass_sources_sha256():
     import hashlib
     h = hashlib.sha256()
-    for rel in STRIP_SOURCES:
+    for rel in PASS_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -51,7 +51,7 @@ def measured_traffic(kernel, n):
     if not lines:
         return None
     rec = json.loads(lines[-1].split(":", 1)[1])
-    if rec.get("sources_sha256") != strip_sources_sha256() or rec.get("grid") != [n, n]:
+    if rec.get("sources_sha256") != pass_sources_sha256() or rec.get("grid") != [n, n]:
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["read_bytes"] + k["write_bytes"]

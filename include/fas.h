@@ -84,6 +84,13 @@ extern "C" {
 #define FAS_OPT_SEG_ROWS 7       /* > 0 (even, >= 8): rows (2D) / planes (3D) per segment of
                                    every march launch, overriding rule and autotuner;
                                    0 (default): rule or autotuner                         */
+#define FAS_OPT_TILE 8           /* >= 0: 2D levels of at most this many cells per problem run
+                                   their fused passes as block tiles (constant kappa, 1..3
+                                   sweeps), the others as row marches; 0: row marches
+                                   only; default: every level                             */
+#define FAS_OPT_TILE_WAVES 9     /* 6..16: waves per tile workgroup (rows written per tile
+                                   4 * waves - 4 nu - 4 in FP64, 8 * waves - 4 nu - 4 in
+                                   FP32); 0 (default): 8                                  */
 
 /* kernel classes reported by fas_get_profile */
 #define FAS_K_SMOOTH 0 /* stand-alone smoothing launches on the finest level              */

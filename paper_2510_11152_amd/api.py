@@ -67,7 +67,7 @@ class Grid:
         return tuple(m >> level for m in reversed(self.n))
 
     def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None,
-            seg_rows=None):
+            seg_rows=None, tile=None, tile_waves=None):
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -83,6 +83,10 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_AUTOTUNE, float(int(autotune))), "fas_grid_set")
         if seg_rows is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_SEG_ROWS, float(seg_rows)), "fas_grid_set")
+        if tile is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_TILE, float(tile)), "fas_grid_set")
+        if tile_waves is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_TILE_WAVES, float(tile_waves)), "fas_grid_set")
         return self
 
     def profile(self, reset=True):

@@ -350,24 +350,32 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
     }
     if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
         void* x = g->lev[l].x;
-        autotune_level(g, l, first, pre, post, f, u, rc_in);
-        if (partials && fas::fused_tiles(g, l, post) > g->npartials / g->batch) partials = nullptr;
+        // block tiles on the smaller levels, row marches on the larger ones
+        const bool tile = fas::tile_ok(g, l, pre, post, g->lev[l].kap != nullptr);
+        if (!tile) autotune_level(g, l, first, pre, post, f, u, rc_in);
+        const int np = tile ? fas::tile_count(g, l, post) : fas::fused_tiles(g, l, post);
+        if (partials && np > g->npartials / g->batch) partials = nullptr;
+        // rc_in: f = rc_in + A u, formed and written by the pre pass
+        const void* const fin = rc_in ? rc_in : f;
+        void* const fout = rc_in ? g->lev[l].f : nullptr;
         {
             ProfScope ps(g, l, FAS_K_PRE);
-            if (rc_in)  // f = rc_in + A u, formed and written by the pass
-                fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, x, C.u, rc_dst(g, l, pre, post),
-                                      g->lev[l].f);
+            if (tile)
+                fas::launch_tile_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout);
             else
-                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, x, C.u, rc_dst(g, l, pre, post));
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout);
             ps.end();
         }
         coarse_part(g, l, pre, post, rev);
         {
             ProfScope ps(g, l, FAS_K_POST);
-            fas::launch_fused_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
+            if (tile)
+                fas::launch_tile_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
+            else
+                fas::launch_fused_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
             ps.end();
         }
-        return partials ? fas::fused_tiles(g, l, post) : 0;
+        return partials ? np : 0;
     }
     if (rc_in) throw Error(FAS_ERR_ARG, "internal: coarse right-hand side expected from a fused pass");
     smooth(g, l, f, u, pre, rev);
@@ -703,6 +711,8 @@ int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int d
         g->kmax = 100;
         g->nuc = 2;
         g->fused = 1;
+        g->tile_max = INT64_MAX;
+        g->tile_waves = 0;
         g->host = nullptr;  // pinned scalar for norm read-back, allocated on first use
         *out = g;
         return FAS_OK;
@@ -762,6 +772,14 @@ int fas_grid_set(fas_grid_t g, int option, double value)
                 if (v != 0 && (v < fas::kMinSegRows || (v & 1)))
                     return fail(FAS_ERR_ARG, "segment height must be 0 or an even number >= 8");
                 g->seg_force = v;
+                return FAS_OK;
+            case FAS_OPT_TILE:
+                if (value < 0) return fail(FAS_ERR_ARG, "tile level size must be >= 0");
+                g->tile_max = v;
+                return FAS_OK;
+            case FAS_OPT_TILE_WAVES:
+                if (v != 0 && (v < 6 || v > 16)) return fail(FAS_ERR_ARG, "tile waves must be 0 or 6..16");
+                g->tile_waves = v;
                 return FAS_OK;
         }
         return fail(FAS_ERR_ARG, "unknown option");

@@ -37,6 +37,17 @@ void strip_post(const fas_grid* g, int l, const Coef& c, int first, int nu, cons
 template <typename T>
 int strip_waves_per_cu(int nu);
 
+// Block-tile passes of the 2D levels (kernels_tile2d.hip): the same passes and arguments
+// as launch_fused_pre / launch_fused_post, one tile per workgroup.  tile_ok: level l takes
+// them (a fused constant-kappa level of at most g->tile_max cells, both passes with 1..3
+// sweeps).  tile_count: norm partial sums a post launch leaves per problem.
+bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
+int tile_count(const fas_grid* g, int l, int nu);
+void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                     void* u_out, void* uc, void* rc, void* fout = nullptr);
+void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                      const void* uc, void* u_out, double* partials);
+
 // 3D plane-march kernels (kernels_fused3d.hip): one sweep per pass.
 bool fused3_ok(const fas_grid* g, int l, bool variable);
 // Norm partial sums one pass with a norm leaves per problem on level l.

@@ -77,6 +77,8 @@ struct fas_grid {
     int seg_rows[fas::kMaxLevels];  // 0: default rule; else rows (2D) / planes (3D) per segment
     int seg_force;                  // FAS_OPT_SEG_ROWS: > 0 overrides rule and autotuner
     int cus;                        // compute units of the device (0: not queried yet)
+    int64_t tile_max;               // FAS_OPT_TILE: largest 2D level (cells) run as block tiles
+    int tile_waves;                 // FAS_OPT_TILE_WAVES: waves per tile block (0: rule)
     // profiler (FAS_OPT_PROFILE): event pairs around finest-level launches
     int profile;
     hipEvent_t ev[2 * fas::kMaxEvents];

@@ -1,0 +1,411 @@
+// Fused 2D pre/post passes (constant kappa) as block tiles: the default fused pass on
+// every 2D level.
+//
+// A block of WV waves holds a whole tile in registers at once: the 128-column window of
+// a strip (one cell pair per lane, x-neighbours by DPP, 112 columns written) and four
+// (FP64) or eight (FP32) consecutive rows per wave.  The pass runs colour phase by colour phase; before each
+// phase every wave trades the top and bottom rows of its band through LDS (one barrier),
+// then updates its cells of that colour.  All loads of a tile are issued together, so
+// the tile waits on memory once, and the halo rows that neighbouring tiles share are
+// read close together in time from the same XCD's L2.  The wave-strip marches
+// (strip_march.h) instead visit a segment's rows one after another, so their launches
+// last at least (segment + halo) dependent row steps, which on small levels is most of
+// their time; on large levels they keep only a few rows of loads in flight per wave.
+// The marches remain for cell kappa and for passes without sweeps.
+//
+// Halo: the values valid after colour phase s are those at least s cells inside the
+// loaded window (the residual needs one more), so the tile recomputes H = 2nu + 2 rows
+// above and below and 8 columns on each side.
+//
+// The passes are those of the strips (Alg. 1): pre = nu X-MCGS sweeps, then
+// u_c = R u and r_c = R(f - A u), optionally forming the FAS right-hand side f = r + A u
+// first; post = u += P(u_c - R u), nu sweeps, optionally one sum of r^2 per tile.  The
+// point formulas and their evaluation trees are those of fas_device.h, so every value is
+// bit-identical to the strip and per-phase kernels.
+#include <hip/hip_runtime.h>
+
+#include "fas_device.h"
+#include "fas_fused.h"
+#include "fas_internal.h"
+#include "march_util.h"
+
+namespace fas {
+
+namespace {
+
+// Rows of the tile each wave holds: 4 in FP64, 8 in FP32 (half the registers per row).
+// Taller tiles recompute fewer halo rows; FP64 has the registers for 4 rows at three
+// 8-wave blocks per compute unit.
+template <typename T>
+constexpr int rows_per_wave()
+{
+    return sizeof(T) == 8 ? 4 : 8;
+}
+constexpr int kTileHX = 8;                  // halo columns each side
+constexpr int kTileCols = 128 - 2 * kTileHX;
+static_assert(kTileCols == kStripCols, "tile columns match the strips");
+constexpr int kMaxTileWaves = 16;
+
+template <typename T>
+struct TileArgs {
+    int n0, n1;          // level size (even)
+    int bc;
+    T k;                 // dt*kappa/h^2 of the level
+    T q[16];             // 1/(1 + k W)
+    int strips, tiles_y; // tiles across x and along y
+    int tile_rows;       // rows written per tile: WV * rows_per_wave - 2H (even)
+    const T* f;
+    const T* u_in;
+    T* u_out;
+    T* uc;               // pre: R u out;  post: new coarse values in
+    T* rc;               // pre: R r out
+    T* fout;             // pre forming the right-hand side (f then holds r): f = r + A u out
+    double* partials;    // post: one sum of r^2 per tile (nullable)
+    int batch;           // problems; problem b's arrays start b * stride (b * cstride coarse)
+    int64_t stride, cstride;
+    const int* act;      // per-problem active flags (nullable)
+};
+
+// LDS of a block: two exchange buffers of WV x (top, bottom) rows, then WV wave sums.
+template <typename T>
+size_t tile_lds_bytes(int wv)
+{
+    return 2 * (size_t)wv * 128 * sizeof(typename Pair<T>::V) + (size_t)wv * sizeof(double);
+}
+
+// One tile of problem b (tile t of per).  XE: the window reaches past a domain x-edge
+// (columns are wrapped, or zero and never updated, and edge cells have their own
+// diagonal counts); the other tiles run without any of that, which keeps the diagonal
+// coefficients in scalar registers.
+template <typename T, int NU, int MODE, bool NORM, bool RHS, int FIRST, bool XE>
+__device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, int per)
+{
+    using V = typename Pair<T>::V;
+    constexpr int S = 2 * NU, H = 2 * NU + 2, B = rows_per_wave<T>();
+    constexpr bool RES = MODE == 0 || NORM;  // the pass takes the residual
+    static_assert(NU >= 1 && H <= kTileHX, "halo columns");
+    extern __shared__ __attribute__((aligned(16))) char tile_lds[];
+    const int WV = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    V* const xch = reinterpret_cast<V*>(tile_lds);
+    double* const red = reinterpret_cast<double*>(tile_lds + 2 * (size_t)WV * 128 * sizeof(V));
+
+    const T* const f = a.f + b * a.stride;
+    const T* const u_in = a.u_in + b * a.stride;
+    T* const u_out = a.u_out + b * a.stride;
+
+    const int strip = t % a.strips, ty = t / a.strips;
+    const int x0 = strip * kTileCols, y0 = ty * a.tile_rows;
+    const int yend = min(y0 + a.tile_rows, a.n1);  // rows written: [y0, yend)
+    const int gxe = x0 - kTileHX + 2 * lane;       // even cell of this lane
+    const int rb = y0 - H + w * B;                 // row of the wave's first row (even)
+    const bool periodic = a.bc == BC_PERIODIC;
+    // A window reaches at most 8 columns / H rows before the domain and less than one
+    // domain size past it (levels are at least 128 x 64), so one wrap step is enough.
+    const bool xin = !XE || periodic || (gxe >= 0 && gxe < a.n0);
+    const int gxl = !XE ? gxe
+                        : periodic ? gxe + (gxe < 0 ? a.n0 : 0) - (gxe >= a.n0 ? a.n0 : 0)
+                                   : min(max(gxe, 0), a.n0 - 2);
+    const bool own = lane >= kTileHX / 2 && lane < 64 - kTileHX / 2 && (!XE || gxe < a.n0);  // writes this pair
+    // boundary faces across x of the even / odd cell (n0 even: a pair is in or out)
+    const bool bxe = XE && !periodic && gxe == 0;
+    const bool bxo = XE && !periodic && gxe + 2 == a.n0;
+    const bool dir = a.bc == BC_DIRICHLET;
+    const T k = a.k;
+    // diagonal count W (and q[W]) of a cell with no, one or two boundary faces
+    const T qA = a.q[4], qB = dir ? a.q[5] : a.q[3], qC = dir ? a.q[6] : a.q[2];
+    const T wA = (T)4, wB = dir ? (T)5 : (T)3, wC = dir ? (T)6 : (T)2;
+    const int mc0 = a.n0 >> 1;
+
+    T ue[B], uo[B], fe[B], fo[B];
+    T cr[B / 2];
+    bool yin[B], yb[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        const int gy = rb + r;
+        const bool in = periodic || (gy >= 0 && gy < a.n1);
+        const int gl = periodic ? gy + (gy < 0 ? a.n1 : 0) - (gy >= a.n1 ? a.n1 : 0) : min(max(gy, 0), a.n1 - 1);
+        yin[r] = in;
+        yb[r] = !periodic && (gy == 0 || gy == a.n1 - 1);
+        // uniform row base plus a 32-bit lane offset
+        const int64_t row = (int64_t)gl * a.n0;
+        const V zu = *reinterpret_cast<const V*>(u_in + row + (unsigned)gxl);
+        const V zf = *reinterpret_cast<const V*>(f + row + (unsigned)gxl);
+        const bool c = in && xin;  // outside a non-periodic domain: 0, never updated
+        ue[r] = c ? zu.x : (T)0;
+        uo[r] = c ? zu.y : (T)0;
+        fe[r] = c ? zf.x : (T)0;
+        fo[r] = c ? zf.y : (T)0;
+        if constexpr (MODE == 1) {
+            if ((r & 1) == 0) cr[r >> 1] = a.uc[b * a.cstride + (int64_t)(gl >> 1) * mc0 + (gxl >> 1)];
+        }
+    }
+    if constexpr (MODE == 1) {
+        // fine grid correction u += P(u_c - R u) on every 2 x 2 block held (rows 2m, 2m + 1)
+#pragma unroll
+        for (int m = 0; m < B / 2; ++m) {
+            const T old = restrict4(ue[2 * m], uo[2 * m], ue[2 * m + 1], uo[2 * m + 1]);
+            const T c = cr[m] - old;
+            const bool apply = yin[2 * m] && xin;
+            ue[2 * m] = apply ? ue[2 * m] + c : ue[2 * m];
+            uo[2 * m] = apply ? uo[2 * m] + c : uo[2 * m];
+            ue[2 * m + 1] = apply ? ue[2 * m + 1] + c : ue[2 * m + 1];
+            uo[2 * m + 1] = apply ? uo[2 * m + 1] + c : uo[2 * m + 1];
+        }
+    }
+
+    // The row above the wave's band (bottom row of wave w - 1) and the row below it (top
+    // row of wave w + 1), as they stand after the last phase.  Exchange e writes buffer
+    // e & 1: a wave can only overwrite a buffer after the next barrier, which every wave
+    // passes only once it has read that buffer.
+    V up, dn;
+    auto exchange = [&](int e) {
+        V* const buf = xch + (e & 1) * (WV * 128);
+        V top, bot;
+        top.x = ue[0];
+        top.y = uo[0];
+        bot.x = ue[B - 1];
+        bot.y = uo[B - 1];
+        buf[w * 128 + lane] = top;
+        buf[w * 128 + 64 + lane] = bot;
+        __syncthreads();
+        up.x = (T)0;
+        up.y = (T)0;
+        dn = up;
+        if (w > 0) up = buf[(w - 1) * 128 + 64 + lane];
+        if (w < WV - 1) dn = buf[(w + 1) * 128 + lane];
+    };
+    // Neighbour sums and diagonal counts of both cells of row r (A u needs them).
+    auto terms = [&](int r, T& Se, T& So, T& We, T& Wo) {
+        const T uem = r > 0 ? ue[r - 1] : up.x, uep = r < B - 1 ? ue[r + 1] : dn.x;
+        const T uom = r > 0 ? uo[r - 1] : up.y, uop = r < B - 1 ? uo[r + 1] : dn.y;
+        const T wv = dpp_move<kShr1>(uo[r]);
+        const T ev = dpp_move<kShl1>(ue[r]);
+        Se = (wv + uo[r]) + (uem + uep);
+        So = (ue[r] + ev) + (uom + uop);
+        We = sel3(bxe, yb[r], wA, wB, wC);
+        Wo = sel3(bxo, yb[r], wA, wB, wC);
+    };
+
+    exchange(0);
+    if constexpr (RHS) {
+        // FAS right-hand side from the initial values: f = r + A u
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            T Se, So, We, Wo;
+            terms(r, Se, So, We, Wo);
+            fe[r] = fe[r] + (ue[r] + k * (We * ue[r] - Se));
+            fo[r] = fo[r] + (uo[r] + k * (Wo * uo[r] - So));
+            const int gy = rb + r;
+            if (gy >= y0 && gy < yend && own)
+                store_pair_nt(a.fout + b * a.stride + (int64_t)gy * a.n0 + gxe, fe[r], fo[r]);
+        }
+    }
+    // colour phases; phase s updates the cells with (i + j) & 1 == colour
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+        if (s > 1) exchange(s - 1);
+        const int colour = ((s - 1) & 1) ^ FIRST;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const bool upd = yin[r] && xin;
+            if (((r & 1) ^ colour) == 0) {  // the even cell of the pair (rb is even)
+                const T uem = r > 0 ? ue[r - 1] : up.x, uep = r < B - 1 ? ue[r + 1] : dn.x;
+                const T wv = dpp_move<kShr1>(uo[r]);
+                const T Ssum = (wv + uo[r]) + (uem + uep);
+                const T qv = sel3(bxe, yb[r], qA, qB, qC);
+                const T nv = (fe[r] + k * Ssum) * qv;
+                ue[r] = upd ? nv : ue[r];
+            } else {
+                const T uom = r > 0 ? uo[r - 1] : up.y, uop = r < B - 1 ? uo[r + 1] : dn.y;
+                const T ev = dpp_move<kShl1>(ue[r]);
+                const T Ssum = (ue[r] + ev) + (uom + uop);
+                const T qv = sel3(bxo, yb[r], qA, qB, qC);
+                const T nv = (fo[r] + k * Ssum) * qv;
+                uo[r] = upd ? nv : uo[r];
+            }
+        }
+    }
+    // final rows: write them, and take the residual (restriction or norm) row by row
+    if constexpr (RES) exchange(S);
+    double acc = 0.0;
+    T re_prev = (T)0, ro_prev = (T)0;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        T re = (T)0, ro = (T)0;
+        if constexpr (RES) {
+            T Se, So, We, Wo;
+            terms(r, Se, So, We, Wo);
+            re = fe[r] - (ue[r] + k * (We * ue[r] - Se));
+            ro = fo[r] - (uo[r] + k * (Wo * uo[r] - So));
+        }
+        const int gy = rb + r;
+        if (gy >= y0 && gy < yend && own) {
+            store_pair_nt(u_out + (int64_t)gy * a.n0 + gxe, ue[r], uo[r]);
+            if constexpr (MODE == 0) {
+                // rows (r - 1, r) form coarse row gy / 2 when r is odd (y0, yend even)
+                if (r & 1) {
+                    const T ucv = restrict4(ue[r - 1], uo[r - 1], ue[r], uo[r]);
+                    const T rcv = restrict4(re_prev, ro_prev, re, ro);
+                    const int64_t P = b * a.cstride + (int64_t)(gy >> 1) * mc0 + (gxe >> 1);
+                    __builtin_nontemporal_store(ucv, a.uc + P);
+                    __builtin_nontemporal_store(rcv, a.rc + P);
+                }
+            }
+            if constexpr (NORM) {
+                acc += (double)re * (double)re;
+                acc += (double)ro * (double)ro;
+            }
+        }
+        re_prev = re;
+        ro_prev = ro;
+    }
+    if constexpr (NORM) {
+        // fixed butterfly over the lanes, then the waves in order
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) red[w] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int i = 0; i < WV; ++i) s += red[i];
+            a.partials[(int64_t)b * per + t] = s;
+        }
+    }
+}
+
+template <typename T, int NU, int MODE, bool NORM, bool RHS, int FIRST>
+__global__ __launch_bounds__(64 * kMaxTileWaves) void k_tile(TileArgs<T> a)
+{
+    // neighbouring tiles, which share halo cells, run on one XCD
+    const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int per = a.strips * a.tiles_y;
+    const int b = blk / per, t = blk % per;
+    if (b >= a.batch || (a.act && !a.act[b])) return;  // uniform over the block
+    const int x0 = (t % a.strips) * kTileCols;
+    if (x0 - kTileHX < 0 || x0 - kTileHX + 128 >= a.n0)
+        tile_pass<T, NU, MODE, NORM, RHS, FIRST, true>(a, b, t, per);
+    else
+        tile_pass<T, NU, MODE, NORM, RHS, FIRST, false>(a, b, t, per);
+}
+
+inline void check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+template <typename T, int MODE, bool NORM, bool RHS>
+void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int wv)
+{
+    const unsigned blocks = (unsigned)((int64_t)a.batch * a.strips * a.tiles_y);
+    const unsigned threads = 64u * (unsigned)wv;
+    const size_t lds = tile_lds_bytes<T>(wv);
+#define FAS_TILE_LAUNCH(NU_)                                                                     \
+    (first ? k_tile<T, NU_, MODE, NORM, RHS, 1><<<blocks, threads, lds, g->stream>>>(a)          \
+           : k_tile<T, NU_, MODE, NORM, RHS, 0><<<blocks, threads, lds, g->stream>>>(a))
+    switch (nu) {
+        case 1: FAS_TILE_LAUNCH(1); break;
+        case 2: FAS_TILE_LAUNCH(2); break;
+        case 3: FAS_TILE_LAUNCH(3); break;
+        default: throw Error(FAS_ERR_ARG, "tile kernels take 1 <= nu <= 3");
+    }
+#undef FAS_TILE_LAUNCH
+    check_launch();
+}
+
+int tile_rows_of(const fas_grid* g, int wv, int nu)
+{
+    return wv * (g->dtype == FAS_F64 ? rows_per_wave<double>() : rows_per_wave<float>()) - 2 * (2 * nu + 2);
+}
+
+template <typename T>
+TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int wv)
+{
+    TileArgs<T> a{};
+    a.n0 = g->lev[l].n[0];
+    a.n1 = g->lev[l].n[1];
+    a.bc = g->bc;
+    a.k = (T)c.kd;
+    for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
+    a.strips = (a.n0 + kTileCols - 1) / kTileCols;
+    a.tile_rows = tile_rows_of(g, wv, nu);
+    a.tiles_y = (a.n1 + a.tile_rows - 1) / a.tile_rows;
+    a.batch = g->batch;
+    a.stride = g->lev[l].N;
+    a.cstride = l < g->L ? g->lev[l + 1].N : 0;
+    a.act = g->batch > 1 ? g->active : nullptr;
+    return a;
+}
+
+}  // namespace
+
+bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable)
+{
+    if (variable || !fused_ok(g, l, nu_pre, nu_post, variable)) return false;
+    if (nu_pre < 1 || nu_post < 1) return false;
+    return (int64_t)g->lev[l].n[0] * g->lev[l].n[1] <= g->tile_max;
+}
+
+int tile_waves(const fas_grid* g, int l, int nu)
+{
+    (void)l;
+    (void)nu;
+    // 8 waves: two waves per SIMD; in FP64 (about 70 VGPRs) three blocks per compute unit.
+    // Blocks of 9-16 waves leave SIMDs unevenly or less filled.
+    return g->tile_waves ? g->tile_waves : 8;
+}
+
+int tile_count(const fas_grid* g, int l, int nu)
+{
+    const int rows = tile_rows_of(g, tile_waves(g, l, nu), nu);
+    return ((g->lev[l].n[0] + kTileCols - 1) / kTileCols) * ((g->lev[l].n[1] + rows - 1) / rows);
+}
+
+void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                     void* u_out, void* uc, void* rc, void* fout)
+{
+    const int wv = tile_waves(g, l, nu);
+    if (g->dtype == FAS_F64) {
+        auto a = make_tile_args<double>(g, l, c, nu, wv);
+        a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
+        a.uc = (double*)uc, a.rc = (double*)rc, a.fout = (double*)fout;
+        if (fout)
+            launch_tile<double, 0, false, true>(g, a, nu, first, wv);
+        else
+            launch_tile<double, 0, false, false>(g, a, nu, first, wv);
+    } else {
+        auto a = make_tile_args<float>(g, l, c, nu, wv);
+        a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
+        a.uc = (float*)uc, a.rc = (float*)rc, a.fout = (float*)fout;
+        if (fout)
+            launch_tile<float, 0, false, true>(g, a, nu, first, wv);
+        else
+            launch_tile<float, 0, false, false>(g, a, nu, first, wv);
+    }
+}
+
+void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
+                      const void* uc, void* u_out, double* partials)
+{
+    const int wv = tile_waves(g, l, nu);
+    if (g->dtype == FAS_F64) {
+        auto a = make_tile_args<double>(g, l, c, nu, wv);
+        a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
+        a.uc = (double*)uc, a.partials = partials;
+        if (partials)
+            launch_tile<double, 1, true, false>(g, a, nu, first, wv);
+        else
+            launch_tile<double, 1, false, false>(g, a, nu, first, wv);
+    } else {
+        auto a = make_tile_args<float>(g, l, c, nu, wv);
+        a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
+        a.uc = (float*)uc, a.partials = partials;
+        if (partials)
+            launch_tile<float, 1, true, false>(g, a, nu, first, wv);
+        else
+            launch_tile<float, 1, false, false>(g, a, nu, first, wv);
+    }
+}
+
+}  // namespace fas

@@ -29,6 +29,7 @@
 #include "fas_device.h"
 #include "fas_fused.h"
 #include "fas_internal.h"
+#include "march_util.h"
 
 namespace fas {
 
@@ -57,51 +58,6 @@ struct StripArgs {
     int64_t stride, cstride;
     const int* act;    // per-problem active flags (nullable)
 };
-
-// Lane i receives the value of lane i - 1 (wave_shr:1) or of lane i + 1 (wave_shl:1);
-// the lane without a source receives 0.
-constexpr int kShr1 = 0x138;  // wave_shr:1
-constexpr int kShl1 = 0x130;  // wave_shl:1
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-template <typename T>
-struct Pair;
-template <>
-struct Pair<double> {
-    using V = double2;
-};
-template <>
-struct Pair<float> {
-    using V = float2;
-};
-
-__device__ __forceinline__ int wrap(int g, int n)
-{
-    int w = g < 0 ? g + n : g - n;
-    if (w < 0 || w >= n) w = ((g % n) + n) % n;
-    return w;
-}
-
-// Value for a cell with xb / yb boundary faces across x / y: A (none), B (one), C (two).
-template <typename T>
-__device__ __forceinline__ T sel3(bool xb, bool yb, T A, T B, T C)
-{
-    return yb ? (xb ? C : B) : (xb ? B : A);
-}
 
 template <int NU, bool KV, bool EDGE, bool FULLPF>
 struct StripGeom {

@@ -100,6 +100,13 @@ def test_solve_argument_errors_without_gpu(lib):
             assert lib.fas_grid_set(g, F.FAS_OPT_SEG_ROWS, bad) == F.FAS_ERR_ARG
         for good in (0, 8, 120):
             assert lib.fas_grid_set(g, F.FAS_OPT_SEG_ROWS, good) == F.FAS_OK
+        for bad in (4, 17, -8, 8.5):                     # waves per tile workgroup: 0 or 6..16
+            assert lib.fas_grid_set(g, F.FAS_OPT_TILE_WAVES, bad) == F.FAS_ERR_ARG
+        for good in (0, 6, 11, 16):
+            assert lib.fas_grid_set(g, F.FAS_OPT_TILE_WAVES, good) == F.FAS_OK
+        assert lib.fas_grid_set(g, F.FAS_OPT_TILE, -1) == F.FAS_ERR_ARG
+        for good in (0, 4096, 1 << 20):
+            assert lib.fas_grid_set(g, F.FAS_OPT_TILE, good) == F.FAS_OK
         for opt in (F.FAS_OPT_GRAPH, F.FAS_OPT_AUTOTUNE, F.FAS_OPT_PROFILE, F.FAS_OPT_FUSED):
             assert lib.fas_grid_set(g, opt, 2) == F.FAS_ERR_ARG
             assert lib.fas_grid_set(g, opt, 0) == F.FAS_OK

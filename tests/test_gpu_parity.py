@@ -120,16 +120,22 @@ def test_vcycle_iterates_bitwise(n, coarsest, bc, variable, dtype, transposed):
         assert np.array_equal(host(ug), u), it
 
 
+# fused 2D passes: row marches only, block tiles on every fused level (16- and 8-wave tiles)
+FUSED_PATHS = {"march": {"tile": 0}, "tile16": {"tile": 1 << 30, "tile_waves": 16},
+               "tile8": {"tile": 1 << 30, "tile_waves": 8}}
+
+
 @pytest.mark.parametrize("n,bc", [((1024, 512), "neumann"), ((512, 1024), "dirichlet"), ((1024, 512), "periodic"),
                                   ((4096, 128), "neumann"), ((4096, 128), "dirichlet"), ((4096, 128), "periodic")])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nu", [(2, 2), (1, 3), (3, 0)])
-def test_vcycle_many_tiles_bitwise(n, bc, dtype, nu):
+@pytest.mark.parametrize("path", sorted(FUSED_PATHS))
+def test_vcycle_many_tiles_bitwise(n, bc, dtype, nu, path):
     """Grids of many fused tiles (interior and boundary tiles, every nu variant, wide
-    grids with a ragged last strip): V-cycles through the library equal the oracle's
-    bits, and equal the library's own one-phase-per-launch path."""
+    grids with a ragged last strip), through row marches or block tiles: V-cycles equal
+    the oracle's bits, and equal the library's own one-phase-per-launch path."""
     P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
-    g = grid_for(P, dtype)
+    g = grid_for(P, dtype).set(**FUSED_PATHS[path])
     f = I.random_field(P.shape(), 8).astype(dtype)
     u = I.random_field(P.shape(), 9).astype(dtype)
     ug, ub, fg = dev(u), dev(u), dev(f)
@@ -289,7 +295,7 @@ def test_forced_segment_heights_give_the_same_bits(n, bc, dtype, rows):
     """The march segmentation (rows or planes per segment, including heights that leave a
     ragged last segment) changes only the schedule: V-cycle iterates equal the oracle's."""
     P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
-    g = grid_for(P, dtype).set(seg_rows=rows)
+    g = grid_for(P, dtype).set(seg_rows=rows, tile=0)
     f = I.random_field(P.shape(), 41).astype(dtype)
     u = I.random_field(P.shape(), 42).astype(dtype)
     ug, fg = dev(u), dev(f)
@@ -297,6 +303,43 @@ def test_forced_segment_heights_give_the_same_bits(n, bc, dtype, rows):
         O.vcycle(P, f, u, 2, 2)
         g.vcycle(fg, ug, P.dt, nu1=2, nu2=2)
         assert np.array_equal(host(ug), u), it
+
+
+@pytest.mark.parametrize("n,coarsest,bc", [((128, 64), 4, "neumann"), ((352, 96), 6, "dirichlet"),
+                                           ((352, 96), 6, "periodic"), ((1024, 1024), 4, "periodic"),
+                                           ((2048, 256), 4, "neumann")])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nu", [(3, 1), (2, 2)])
+@pytest.mark.parametrize("waves", [6, 8, 16])
+@pytest.mark.parametrize("transposed", [False, True])
+def test_tile_passes_bitwise(n, coarsest, bc, dtype, nu, waves, transposed):
+    """Block tiles on every fused level (a level one window wide and a row of tiles high,
+    ragged last tiles across x and y, every boundary kind, both colour orders): V-cycle
+    iterates equal the oracle's bits, and the residual norm from the per-tile partial
+    sums agrees with the oracle's to 1e-10."""
+    P = _problem(n, coarsest, bc, dt=2e-4, kappa=1.0, nuc=2)
+    g = grid_for(P, dtype).set(tile=1 << 30, tile_waves=waves)
+    f = I.random_field(P.shape(), 71).astype(dtype)
+    u = I.random_field(P.shape(), 72).astype(dtype)
+    ug, fg = dev(u), dev(f)
+    for it in range(2):
+        O.vcycle(P, f, u, nu[0], nu[1], transposed=transposed)
+        rel = g.vcycle(fg, ug, P.dt, nu1=nu[0], nu2=nu[1], transposed=transposed, with_residual=True)
+        assert np.array_equal(host(ug), u), it
+        ro = np.linalg.norm(O.residual(P, 0, f, u).astype(np.float64)) / np.linalg.norm(f.astype(np.float64))
+        assert abs(rel - ro) <= 1e-10 * ro
+
+
+def test_tile_options_are_checked():
+    from paper_2510_11152_amd import Grid
+    from paper_2510_11152_amd._lib import FasError
+    g = Grid((128, 128), 1 / 128)
+    for bad in (4, 17, -8):
+        with pytest.raises(FasError):
+            g.set(tile_waves=bad)
+    with pytest.raises(FasError):
+        g.set(tile=-1)
+    g.set(tile=0, tile_waves=0)
 
 
 def test_segment_height_option_is_checked():
@@ -310,15 +353,17 @@ def test_segment_height_option_is_checked():
 
 
 @pytest.mark.parametrize("bc", ["neumann", "periodic"])
-def test_full_size_8192_march_equals_phase_kernels(bc):
-    """At the benchmark's full size (8192^2 FP64, the segment rule's launch shapes) one
-    V-cycle through the march kernels equals the one-phase-per-launch kernels bit for
-    bit; those match the oracle on every smaller case above."""
+@pytest.mark.parametrize("path", ["tile", "march"])
+def test_full_size_8192_fused_equals_phase_kernels(bc, path):
+    """At the benchmark's full size (8192^2 FP64; the default block tiles, as timed, and
+    the row marches with the segment rule's launch shapes) one V-cycle through the fused
+    passes equals the one-phase-per-launch kernels bit for bit; those match the oracle on
+    every smaller case above."""
     n = 8192
     P = _problem((n, n), 4, bc, dt=1e-4, kappa=1.0, nuc=2)
     f = dev(I.heat_2d_large(n))
     ua, ub = f.clone(), f.clone()
-    grid_for(P, np.float64).vcycle(f, ua, P.dt, nu1=2, nu2=2)
+    grid_for(P, np.float64).set(**({} if path == "tile" else {"tile": 0})).vcycle(f, ua, P.dt, nu1=2, nu2=2)
     grid_for(P, np.float64).set(fused=False).vcycle(f, ub, P.dt, nu1=2, nu2=2)
     assert torch.equal(ua, ub)
     del ua, ub, f
