@@ -1,5 +1,5 @@
-// Fused 2D pre/post passes (constant kappa) as block tiles: the default fused pass on
-// every 2D level.
+// Fused 2D pre/post passes as block tiles: the default fused pass on every 2D level
+// (constant or cell kappa).
 //
 // A block of WV waves holds a whole tile in registers at once: the 128-column window of
 // a strip (one cell pair per lane, x-neighbours by DPP, 112 columns written) and four
@@ -11,7 +11,7 @@
 // (strip_march.h) instead visit a segment's rows one after another, so their launches
 // last at least (segment + halo) dependent row steps, which on small levels is most of
 // their time; on large levels they keep only a few rows of loads in flight per wave.
-// The marches remain for cell kappa and for passes without sweeps.
+// The marches remain for passes without sweeps.
 //
 // Halo: the values valid after colour phase s are those at least s cells inside the
 // loaded window (the residual needs one more), so the tile recomputes H = 2nu + 2 rows
@@ -45,6 +45,7 @@ constexpr int kTileHX = 8;                  // halo columns each side
 constexpr int kTileCols = 128 - 2 * kTileHX;
 static_assert(kTileCols == kStripCols, "tile columns match the strips");
 constexpr int kMaxTileWaves = 16;
+constexpr int kMaxTileWavesKV = 8;  // cell kappa: more registers per lane
 
 template <typename T>
 struct TileArgs {
@@ -61,23 +62,25 @@ struct TileArgs {
     T* rc;               // pre: R r out
     T* fout;             // pre forming the right-hand side (f then holds r): f = r + A u out
     double* partials;    // post: one sum of r^2 per tile (nullable)
+    const T* kap;        // cell kappa of the level (single-problem grids), else nullptr
     int batch;           // problems; problem b's arrays start b * stride (b * cstride coarse)
     int64_t stride, cstride;
     const int* act;      // per-problem active flags (nullable)
 };
 
-// LDS of a block: two exchange buffers of WV x (top, bottom) rows, then WV wave sums.
+// LDS of a block: two exchange buffers of WV x (top, bottom) rows of u, one of kappa
+// (cell kappa), then WV wave sums.
 template <typename T>
-size_t tile_lds_bytes(int wv)
+size_t tile_lds_bytes(int wv, bool kv)
 {
-    return 2 * (size_t)wv * 128 * sizeof(typename Pair<T>::V) + (size_t)wv * sizeof(double);
+    return (kv ? 3 : 2) * (size_t)wv * 128 * sizeof(typename Pair<T>::V) + (size_t)wv * sizeof(double);
 }
 
 // One tile of problem b (tile t of per).  XE: the window reaches past a domain x-edge
 // (columns are wrapped, or zero and never updated, and edge cells have their own
 // diagonal counts); the other tiles run without any of that, which keeps the diagonal
 // coefficients in scalar registers.
-template <typename T, int NU, int MODE, bool NORM, bool RHS, int FIRST, bool XE>
+template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, int FIRST, bool XE>
 __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, int per)
 {
     using V = typename Pair<T>::V;
@@ -89,7 +92,8 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     V* const xch = reinterpret_cast<V*>(tile_lds);
-    double* const red = reinterpret_cast<double*>(tile_lds + 2 * (size_t)WV * 128 * sizeof(V));
+    V* const kxch = xch + 2 * WV * 128;  // cell kappa: band edges (traded once)
+    double* const red = reinterpret_cast<double*>(tile_lds + (KV ? 3 : 2) * (size_t)WV * 128 * sizeof(V));
 
     const T* const f = a.f + b * a.stride;
     const T* const u_in = a.u_in + b * a.stride;
@@ -116,18 +120,22 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
     // diagonal count W (and q[W]) of a cell with no, one or two boundary faces
     const T qA = a.q[4], qB = dir ? a.q[5] : a.q[3], qC = dir ? a.q[6] : a.q[2];
     const T wA = (T)4, wB = dir ? (T)5 : (T)3, wC = dir ? (T)6 : (T)2;
+    const T kdir = dir ? (T)2 : (T)0;  // cell kappa: a boundary face weighs kdir * kappa_p
     const int mc0 = a.n0 >> 1;
 
     T ue[B], uo[B], fe[B], fo[B];
+    T ke[KV ? B : 1], ko[KV ? B : 1];
     T cr[B / 2];
-    bool yin[B], yb[B];
+    bool yin[B], yb[B], ys[B], yn[B];
 #pragma unroll
     for (int r = 0; r < B; ++r) {
         const int gy = rb + r;
         const bool in = periodic || (gy >= 0 && gy < a.n1);
         const int gl = periodic ? gy + (gy < 0 ? a.n1 : 0) - (gy >= a.n1 ? a.n1 : 0) : min(max(gy, 0), a.n1 - 1);
         yin[r] = in;
-        yb[r] = !periodic && (gy == 0 || gy == a.n1 - 1);
+        ys[r] = !periodic && gy == 0;
+        yn[r] = !periodic && gy == a.n1 - 1;
+        yb[r] = ys[r] || yn[r];
         // uniform row base plus a 32-bit lane offset
         const int64_t row = (int64_t)gl * a.n0;
         const V zu = *reinterpret_cast<const V*>(u_in + row + (unsigned)gxl);
@@ -137,6 +145,11 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
         uo[r] = c ? zu.y : (T)0;
         fe[r] = c ? zf.x : (T)0;
         fo[r] = c ? zf.y : (T)0;
+        if constexpr (KV) {
+            const V zk = *reinterpret_cast<const V*>(a.kap + row + (unsigned)gxl);
+            ke[r] = c ? zk.x : (T)0;
+            ko[r] = c ? zk.y : (T)0;
+        }
         if constexpr (MODE == 1) {
             if ((r & 1) == 0) cr[r >> 1] = a.uc[b * a.cstride + (int64_t)(gl >> 1) * mc0 + (gxl >> 1)];
         }
@@ -176,19 +189,71 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
         if (w > 0) up = buf[(w - 1) * 128 + 64 + lane];
         if (w < WV - 1) dn = buf[(w + 1) * 128 + lane];
     };
-    // Neighbour sums and diagonal counts of both cells of row r (A u needs them).
+    // Cell kappa: the kappa rows above and below the band, read once.
+    V kup, kdn;
+    if constexpr (KV) {
+        V top, bot;
+        top.x = ke[0];
+        top.y = ko[0];
+        bot.x = ke[B - 1];
+        bot.y = ko[B - 1];
+        kxch[w * 128 + lane] = top;
+        kxch[w * 128 + 64 + lane] = bot;
+    }
+    // Cell kappa: weighted neighbour sum Sw and weight total Wt of the even (EVEN) or odd
+    // cell of row r, with the face weights and boundary faces of fas_device.h's gather
+    // (slot order x-, x+, y-, y+; a boundary face weighs kdir * kappa_p).
+    auto kv_terms = [&](bool even, int r, T& Sw, T& Wt) {
+        if (even) {
+            const T kp = ke[r], uw = dpp_move<kShr1>(uo[r]), kw = dpp_move<kShr1>(ko[r]);
+            const T uem = r > 0 ? ue[r - 1] : up.x, uep = r < B - 1 ? ue[r + 1] : dn.x;
+            const T kem = r > 0 ? ke[r - 1] : kup.x, kep = r < B - 1 ? ke[r + 1] : kdn.x;
+            const T wb = kdir * kp;
+            const T w0 = bxe ? wb : face_w(kw, kp);
+            const T w1 = face_w(kp, ko[r]);
+            const T w2 = ys[r] ? wb : face_w(kem, kp);
+            const T w3 = yn[r] ? wb : face_w(kp, kep);
+            Sw = (w0 * uw + w1 * uo[r]) + (w2 * uem + w3 * uep);
+            Wt = (w0 + w1) + (w2 + w3);
+        } else {
+            const T kp = ko[r], uE = dpp_move<kShl1>(ue[r]), kE = dpp_move<kShl1>(ke[r]);
+            const T uom = r > 0 ? uo[r - 1] : up.y, uop = r < B - 1 ? uo[r + 1] : dn.y;
+            const T kom = r > 0 ? ko[r - 1] : kup.y, kop = r < B - 1 ? ko[r + 1] : kdn.y;
+            const T wb = kdir * kp;
+            const T w0 = face_w(ke[r], kp);
+            const T w1 = bxo ? wb : face_w(kp, kE);
+            const T w2 = ys[r] ? wb : face_w(kom, kp);
+            const T w3 = yn[r] ? wb : face_w(kp, kop);
+            Sw = (w0 * ue[r] + w1 * uE) + (w2 * uom + w3 * uop);
+            Wt = (w0 + w1) + (w2 + w3);
+        }
+    };
+    // Neighbour sums and diagonal counts (weighted, with cell kappa) of both cells of
+    // row r: A u = u + k (W u - S).
     auto terms = [&](int r, T& Se, T& So, T& We, T& Wo) {
-        const T uem = r > 0 ? ue[r - 1] : up.x, uep = r < B - 1 ? ue[r + 1] : dn.x;
-        const T uom = r > 0 ? uo[r - 1] : up.y, uop = r < B - 1 ? uo[r + 1] : dn.y;
-        const T wv = dpp_move<kShr1>(uo[r]);
-        const T ev = dpp_move<kShl1>(ue[r]);
-        Se = (wv + uo[r]) + (uem + uep);
-        So = (ue[r] + ev) + (uom + uop);
-        We = sel3(bxe, yb[r], wA, wB, wC);
-        Wo = sel3(bxo, yb[r], wA, wB, wC);
+        if constexpr (KV) {
+            kv_terms(true, r, Se, We);
+            kv_terms(false, r, So, Wo);
+        } else {
+            const T uem = r > 0 ? ue[r - 1] : up.x, uep = r < B - 1 ? ue[r + 1] : dn.x;
+            const T uom = r > 0 ? uo[r - 1] : up.y, uop = r < B - 1 ? uo[r + 1] : dn.y;
+            const T wv = dpp_move<kShr1>(uo[r]);
+            const T ev = dpp_move<kShl1>(ue[r]);
+            Se = (wv + uo[r]) + (uem + uep);
+            So = (ue[r] + ev) + (uom + uop);
+            We = sel3(bxe, yb[r], wA, wB, wC);
+            Wo = sel3(bxo, yb[r], wA, wB, wC);
+        }
     };
 
-    exchange(0);
+    exchange(0);  // its barrier also publishes the kappa edges
+    if constexpr (KV) {
+        kup.x = (T)0;
+        kup.y = (T)0;
+        kdn = kup;
+        if (w > 0) kup = kxch[(w - 1) * 128 + 64 + lane];
+        if (w < WV - 1) kdn = kxch[(w + 1) * 128 + lane];
+    }
     if constexpr (RHS) {
         // FAS right-hand side from the initial values: f = r + A u
 #pragma unroll
@@ -210,7 +275,18 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
 #pragma unroll
         for (int r = 0; r < B; ++r) {
             const bool upd = yin[r] && xin;
-            if (((r & 1) ^ colour) == 0) {  // the even cell of the pair (rb is even)
+            if constexpr (KV) {
+                const bool even = ((r & 1) ^ colour) == 0;
+                T Sw, Wt;
+                kv_terms(even, r, Sw, Wt);
+                if (even) {
+                    const T nv = (fe[r] + k * Sw) / ((T)1 + k * Wt);
+                    ue[r] = upd ? nv : ue[r];
+                } else {
+                    const T nv = (fo[r] + k * Sw) / ((T)1 + k * Wt);
+                    uo[r] = upd ? nv : uo[r];
+                }
+            } else if (((r & 1) ^ colour) == 0) {  // the even cell of the pair (rb is even)
                 const T uem = r > 0 ? ue[r - 1] : up.x, uep = r < B - 1 ? ue[r + 1] : dn.x;
                 const T wv = dpp_move<kShr1>(uo[r]);
                 const T Ssum = (wv + uo[r]) + (uem + uep);
@@ -274,8 +350,8 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
     }
 }
 
-template <typename T, int NU, int MODE, bool NORM, bool RHS, int FIRST>
-__global__ __launch_bounds__(64 * kMaxTileWaves) void k_tile(TileArgs<T> a)
+template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, int FIRST>
+__global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k_tile(TileArgs<T> a)
 {
     // neighbouring tiles, which share halo cells, run on one XCD
     const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -284,9 +360,9 @@ __global__ __launch_bounds__(64 * kMaxTileWaves) void k_tile(TileArgs<T> a)
     if (b >= a.batch || (a.act && !a.act[b])) return;  // uniform over the block
     const int x0 = (t % a.strips) * kTileCols;
     if (x0 - kTileHX < 0 || x0 - kTileHX + 128 >= a.n0)
-        tile_pass<T, NU, MODE, NORM, RHS, FIRST, true>(a, b, t, per);
+        tile_pass<T, NU, MODE, NORM, RHS, KV, FIRST, true>(a, b, t, per);
     else
-        tile_pass<T, NU, MODE, NORM, RHS, FIRST, false>(a, b, t, per);
+        tile_pass<T, NU, MODE, NORM, RHS, KV, FIRST, false>(a, b, t, per);
 }
 
 inline void check_launch()
@@ -295,15 +371,15 @@ inline void check_launch()
     if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-template <typename T, int MODE, bool NORM, bool RHS>
-void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int wv)
+template <typename T, int MODE, bool NORM, bool RHS, bool KV>
+void launch_tile_kv(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int wv)
 {
     const unsigned blocks = (unsigned)((int64_t)a.batch * a.strips * a.tiles_y);
     const unsigned threads = 64u * (unsigned)wv;
-    const size_t lds = tile_lds_bytes<T>(wv);
+    const size_t lds = tile_lds_bytes<T>(wv, KV);
 #define FAS_TILE_LAUNCH(NU_)                                                                     \
-    (first ? k_tile<T, NU_, MODE, NORM, RHS, 1><<<blocks, threads, lds, g->stream>>>(a)          \
-           : k_tile<T, NU_, MODE, NORM, RHS, 0><<<blocks, threads, lds, g->stream>>>(a))
+    (first ? k_tile<T, NU_, MODE, NORM, RHS, KV, 1><<<blocks, threads, lds, g->stream>>>(a)      \
+           : k_tile<T, NU_, MODE, NORM, RHS, KV, 0><<<blocks, threads, lds, g->stream>>>(a))
     switch (nu) {
         case 1: FAS_TILE_LAUNCH(1); break;
         case 2: FAS_TILE_LAUNCH(2); break;
@@ -312,6 +388,15 @@ void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int
     }
 #undef FAS_TILE_LAUNCH
     check_launch();
+}
+
+template <typename T, int MODE, bool NORM, bool RHS>
+void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int wv)
+{
+    if (a.kap)
+        launch_tile_kv<T, MODE, NORM, RHS, true>(g, a, nu, first, wv);
+    else
+        launch_tile_kv<T, MODE, NORM, RHS, false>(g, a, nu, first, wv);
 }
 
 int tile_rows_of(const fas_grid* g, int wv, int nu)
@@ -335,6 +420,7 @@ TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int 
     a.stride = g->lev[l].N;
     a.cstride = l < g->L ? g->lev[l + 1].N : 0;
     a.act = g->batch > 1 ? g->active : nullptr;
+    a.kap = (const T*)g->lev[l].kap;  // cell kappa: single-problem grids only
     return a;
 }
 
@@ -342,15 +428,15 @@ TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int 
 
 bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable)
 {
-    if (variable || !fused_ok(g, l, nu_pre, nu_post, variable)) return false;
+    if (!fused_ok(g, l, nu_pre, nu_post, variable)) return false;
     if (nu_pre < 1 || nu_post < 1) return false;
     return (int64_t)g->lev[l].n[0] * g->lev[l].n[1] <= g->tile_max;
 }
 
 int tile_waves(const fas_grid* g, int l, int nu)
 {
-    (void)l;
     (void)nu;
+    if (g->lev[l].kap) return g->tile_waves && g->tile_waves < kMaxTileWavesKV ? g->tile_waves : kMaxTileWavesKV;
     // 8 waves: two waves per SIMD; in FP64 (about 70 VGPRs) three blocks per compute unit.
     // Blocks of 9-16 waves leave SIMDs unevenly or less filled.
     return g->tile_waves ? g->tile_waves : 8;

@@ -154,11 +154,12 @@ def test_vcycle_many_tiles_bitwise(n, bc, dtype, nu, path):
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nu", [(2, 2), (1, 3), (3, 0)])
 @pytest.mark.parametrize("transposed", [False, True])
-def test_vcycle_many_tiles_cell_kappa_bitwise(n, bc, dtype, nu, transposed):
-    """Cell kappa on grids of many march strips: face weights formed inside the march
-    (harmonic means, boundary faces) give the oracle's bits, plain and transposed."""
+@pytest.mark.parametrize("path", ["march", "tile8"])
+def test_vcycle_many_tiles_cell_kappa_bitwise(n, bc, dtype, nu, transposed, path):
+    """Cell kappa on grids of many tiles or march strips: face weights formed inside the
+    pass (harmonic means, boundary faces) give the oracle's bits, plain and transposed."""
     P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
-    g = grid_for(P, dtype, variable=True)
+    g = grid_for(P, dtype, variable=True).set(**FUSED_PATHS[path])
     kap = np.exp(0.5 * I.random_field(P.shape(), 10)).astype(dtype)
     f = I.random_field(P.shape(), 11).astype(dtype)
     u = I.random_field(P.shape(), 12).astype(dtype)
@@ -312,21 +313,25 @@ def test_forced_segment_heights_give_the_same_bits(n, bc, dtype, rows):
 @pytest.mark.parametrize("nu", [(3, 1), (2, 2)])
 @pytest.mark.parametrize("waves", [6, 8, 16])
 @pytest.mark.parametrize("transposed", [False, True])
-def test_tile_passes_bitwise(n, coarsest, bc, dtype, nu, waves, transposed):
+@pytest.mark.parametrize("variable", [False, True])
+def test_tile_passes_bitwise(n, coarsest, bc, dtype, nu, waves, transposed, variable):
     """Block tiles on every fused level (a level one window wide and a row of tiles high,
-    ragged last tiles across x and y, every boundary kind, both colour orders): V-cycle
-    iterates equal the oracle's bits, and the residual norm from the per-tile partial
-    sums agrees with the oracle's to 1e-10."""
+    ragged last tiles across x and y, every boundary kind, both colour orders, constant
+    and cell kappa; cell-kappa tiles take at most 8 waves): V-cycle iterates equal the
+    oracle's bits, and the residual norm from the per-tile partial sums agrees with the
+    oracle's to 1e-10."""
     P = _problem(n, coarsest, bc, dt=2e-4, kappa=1.0, nuc=2)
-    g = grid_for(P, dtype).set(tile=1 << 30, tile_waves=waves)
+    g = grid_for(P, dtype, variable).set(tile=1 << 30, tile_waves=waves)
     f = I.random_field(P.shape(), 71).astype(dtype)
     u = I.random_field(P.shape(), 72).astype(dtype)
+    kap = np.exp(0.5 * I.random_field(P.shape(), 73)).astype(dtype) if variable else None
     ug, fg = dev(u), dev(f)
+    kg = None if kap is None else dev(kap)
     for it in range(2):
-        O.vcycle(P, f, u, nu[0], nu[1], transposed=transposed)
-        rel = g.vcycle(fg, ug, P.dt, nu1=nu[0], nu2=nu[1], transposed=transposed, with_residual=True)
+        O.vcycle(P, f, u, nu[0], nu[1], transposed=transposed, kap=kap)
+        rel = g.vcycle(fg, ug, P.dt, P.kappa, kg, nu1=nu[0], nu2=nu[1], transposed=transposed, with_residual=True)
         assert np.array_equal(host(ug), u), it
-        ro = np.linalg.norm(O.residual(P, 0, f, u).astype(np.float64)) / np.linalg.norm(f.astype(np.float64))
+        ro = np.linalg.norm(O.residual(P, 0, f, u, kap=kap).astype(np.float64)) / np.linalg.norm(f.astype(np.float64))
         assert abs(rel - ro) <= 1e-10 * ro
 
 
@@ -400,16 +405,18 @@ def test_full_size_8192_residual_matches_oracle():
 
 
 @pytest.mark.parametrize("transposed", [False, True])
-def test_full_size_2048_cell_kappa_march_equals_phase_kernels(transposed):
+@pytest.mark.parametrize("path", ["tile", "march"])
+def test_full_size_2048_cell_kappa_fused_equals_phase_kernels(transposed, path):
     """At the differentiable workload's size (2048^2 FP64, kappa = exp(g/2) of a smooth
-    cosine field) one plain and one transposed V-cycle through the cell-kappa marches
-    equal the one-phase-per-launch kernels bit for bit."""
+    cosine field) one plain and one transposed V-cycle through the cell-kappa tiles (as
+    timed) and marches equal the one-phase-per-launch kernels bit for bit."""
     n = 2048
     P = _problem((n, n), 4, "neumann", dt=1e-4, kappa=1.0, nuc=2)
     kap = dev(I.kappa_field(n))
     f = dev(I.random_field(P.shape(), 61))
     ua, ub = f.clone(), f.clone()
-    grid_for(P, np.float64, variable=True).vcycle(f, ua, P.dt, 1.0, kap, nu1=2, nu2=2, transposed=transposed)
+    ga = grid_for(P, np.float64, variable=True).set(**({} if path == "tile" else {"tile": 0}))
+    ga.vcycle(f, ua, P.dt, 1.0, kap, nu1=2, nu2=2, transposed=transposed)
     grid_for(P, np.float64, variable=True).set(fused=False).vcycle(f, ub, P.dt, 1.0, kap, nu1=2, nu2=2,
                                                                    transposed=transposed)
     assert torch.equal(ua, ub)
