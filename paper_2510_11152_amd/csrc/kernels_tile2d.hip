@@ -14,8 +14,8 @@
 // The marches remain for passes without sweeps.
 //
 // Halo: the values valid after colour phase s are those at least s cells inside the
-// loaded window (the residual needs one more), so the tile recomputes H = 2nu + 2 rows
-// above and below and 8 columns on each side.
+// loaded window (the residual needs one more), so the tile recomputes H rows above and
+// below (2nu + 2 for passes that take the residual, else 2nu) and 8 columns on each side.
 //
 // The passes are those of the strips (Alg. 1): pre = nu X-MCGS sweeps, then
 // u_c = R u and r_c = R(f - A u), optionally forming the FAS right-hand side f = r + A u
@@ -42,6 +42,13 @@ constexpr int rows_per_wave()
     return sizeof(T) == 8 ? 4 : 8;
 }
 constexpr int kTileHX = 8;                  // halo columns each side
+
+// Halo rows above and below a tile: 2nu phases, one more for a residual, rounded up to
+// even (row pairs form coarse rows, and a row's parity fixes its colour).
+constexpr int tile_halo(int nu, bool residual)
+{
+    return residual ? 2 * nu + 2 : 2 * nu;
+}
 constexpr int kTileCols = 128 - 2 * kTileHX;
 static_assert(kTileCols == kStripCols, "tile columns match the strips");
 constexpr int kMaxTileWaves = 16;
@@ -54,7 +61,7 @@ struct TileArgs {
     T k;                 // dt*kappa/h^2 of the level
     T q[16];             // 1/(1 + k W)
     int strips, tiles_y; // tiles across x and along y
-    int tile_rows;       // rows written per tile: WV * rows_per_wave - 2H (even)
+    int tile_rows;       // rows written per tile: WV * rows_per_wave - 2 * halo (even)
     const T* f;
     const T* u_in;
     T* u_out;
@@ -84,8 +91,8 @@ template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, int FIRST,
 __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, int per)
 {
     using V = typename Pair<T>::V;
-    constexpr int S = 2 * NU, H = 2 * NU + 2, B = rows_per_wave<T>();
     constexpr bool RES = MODE == 0 || NORM;  // the pass takes the residual
+    constexpr int S = 2 * NU, H = tile_halo(NU, RES), B = rows_per_wave<T>();
     static_assert(NU >= 1 && H <= kTileHX, "halo columns");
     extern __shared__ __attribute__((aligned(16))) char tile_lds[];
     const int WV = blockDim.x >> 6;
@@ -399,13 +406,13 @@ void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int
         launch_tile_kv<T, MODE, NORM, RHS, false>(g, a, nu, first, wv);
 }
 
-int tile_rows_of(const fas_grid* g, int wv, int nu)
+int tile_rows_of(const fas_grid* g, int wv, int nu, bool residual)
 {
-    return wv * (g->dtype == FAS_F64 ? rows_per_wave<double>() : rows_per_wave<float>()) - 2 * (2 * nu + 2);
+    return wv * (g->dtype == FAS_F64 ? rows_per_wave<double>() : rows_per_wave<float>()) - 2 * tile_halo(nu, residual);
 }
 
 template <typename T>
-TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int wv)
+TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int wv, bool residual)
 {
     TileArgs<T> a{};
     a.n0 = g->lev[l].n[0];
@@ -414,7 +421,7 @@ TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int 
     a.k = (T)c.kd;
     for (int W = 0; W < 16; ++W) a.q[W] = (T)c.q[W];
     a.strips = (a.n0 + kTileCols - 1) / kTileCols;
-    a.tile_rows = tile_rows_of(g, wv, nu);
+    a.tile_rows = tile_rows_of(g, wv, nu, residual);
     a.tiles_y = (a.n1 + a.tile_rows - 1) / a.tile_rows;
     a.batch = g->batch;
     a.stride = g->lev[l].N;
@@ -444,7 +451,7 @@ int tile_waves(const fas_grid* g, int l, int nu)
 
 int tile_count(const fas_grid* g, int l, int nu)
 {
-    const int rows = tile_rows_of(g, tile_waves(g, l, nu), nu);
+    const int rows = tile_rows_of(g, tile_waves(g, l, nu), nu, true);
     return ((g->lev[l].n[0] + kTileCols - 1) / kTileCols) * ((g->lev[l].n[1] + rows - 1) / rows);
 }
 
@@ -453,7 +460,7 @@ void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu,
 {
     const int wv = tile_waves(g, l, nu);
     if (g->dtype == FAS_F64) {
-        auto a = make_tile_args<double>(g, l, c, nu, wv);
+        auto a = make_tile_args<double>(g, l, c, nu, wv, true);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.rc = (double*)rc, a.fout = (double*)fout;
         if (fout)
@@ -461,7 +468,7 @@ void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu,
         else
             launch_tile<double, 0, false, false>(g, a, nu, first, wv);
     } else {
-        auto a = make_tile_args<float>(g, l, c, nu, wv);
+        auto a = make_tile_args<float>(g, l, c, nu, wv, true);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
         a.uc = (float*)uc, a.rc = (float*)rc, a.fout = (float*)fout;
         if (fout)
@@ -476,7 +483,7 @@ void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu
 {
     const int wv = tile_waves(g, l, nu);
     if (g->dtype == FAS_F64) {
-        auto a = make_tile_args<double>(g, l, c, nu, wv);
+        auto a = make_tile_args<double>(g, l, c, nu, wv, partials != nullptr);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.partials = partials;
         if (partials)
@@ -484,7 +491,7 @@ void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu
         else
             launch_tile<double, 1, false, false>(g, a, nu, first, wv);
     } else {
-        auto a = make_tile_args<float>(g, l, c, nu, wv);
+        auto a = make_tile_args<float>(g, l, c, nu, wv, partials != nullptr);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
         a.uc = (float*)uc, a.partials = partials;
         if (partials)
