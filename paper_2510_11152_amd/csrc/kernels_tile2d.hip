@@ -75,6 +75,21 @@ struct TileArgs {
     const int* act;      // per-problem active flags (nullable)
 };
 
+// Tile t of a problem -> (strip, tile row).  Tiles are walked in groups of up to
+// kTileGroup strips, down the tile rows of a group, so the tiles that share halo rows
+// above and below run within a few tiles of each other (and, with xcd_block, on the same
+// XCD) rather than a whole row of tiles apart.  A bijection on [0, strips * tiles_y).
+constexpr int kTileGroup = 16;
+
+__device__ __forceinline__ void tile_coords(int t, int strips, int tiles_y, int& strip, int& ty)
+{
+    const int K = strips < kTileGroup ? strips : kTileGroup;
+    const int span = K * tiles_y, group = t / span, within = t % span;
+    const int width = strips - group * K < K ? strips - group * K : K;  // the last group may be narrower
+    ty = within / width;
+    strip = group * K + within % width;
+}
+
 // LDS of a block: two exchange buffers of WV x (top, bottom) rows of u, one of kappa
 // (cell kappa), then WV wave sums.
 template <typename T>
@@ -106,7 +121,8 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
     const T* const u_in = a.u_in + b * a.stride;
     T* const u_out = a.u_out + b * a.stride;
 
-    const int strip = t % a.strips, ty = t / a.strips;
+    int strip, ty;
+    tile_coords(t, a.strips, a.tiles_y, strip, ty);
     const int x0 = strip * kTileCols, y0 = ty * a.tile_rows;
     const int yend = min(y0 + a.tile_rows, a.n1);  // rows written: [y0, yend)
     const int gxe = x0 - kTileHX + 2 * lane;       // even cell of this lane
@@ -365,7 +381,9 @@ __global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k
     const int per = a.strips * a.tiles_y;
     const int b = blk / per, t = blk % per;
     if (b >= a.batch || (a.act && !a.act[b])) return;  // uniform over the block
-    const int x0 = (t % a.strips) * kTileCols;
+    int strip, ty;
+    tile_coords(t, a.strips, a.tiles_y, strip, ty);
+    const int x0 = strip * kTileCols;
     if (x0 - kTileHX < 0 || x0 - kTileHX + 128 >= a.n0)
         tile_pass<T, NU, MODE, NORM, RHS, KV, FIRST, true>(a, b, t, per);
     else
