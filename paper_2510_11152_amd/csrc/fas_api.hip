@@ -54,7 +54,7 @@ struct Layout {
     int L;
     int n[fas::kMaxLevels][3];
     size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], r[fas::kMaxLevels], kap[fas::kMaxLevels];
-    size_t mix_e, mix_r, partials, norm_out, active, cyc, rnorm, count, total;
+    size_t mix_e, mix_r, partials, norm_out, active, cyc, rnorm, count, hist, total;
     int npartials;
 };
 
@@ -145,6 +145,8 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
     off = align_up(off + (size_t)batch * sizeof(int));
     lay->count = off;
     off = align_up(off + 8 * sizeof(int));
+    lay->hist = off;  // after rnorm, active, cyc and count: one span for a single problem
+    off = align_up(off + fas::kHist * sizeof(double));
     lay->total = off;
     return 0;
 }
@@ -198,9 +200,11 @@ void set_kappa(fas_grid* g, const void* kcell, bool source_is_f64, bool coarse =
     }
 }
 
+void ensure_host(fas_grid* g);
+
 double read_norm(fas_grid* g)
 {
-    if (!g->host) FAS_HIP_CHECK(hipHostMalloc((void**)&g->host, 64, hipHostMallocDefault));
+    ensure_host(g);
     FAS_HIP_CHECK(hipMemcpyAsync(g->host, g->norm_out, sizeof(double), hipMemcpyDeviceToHost,
                                  g->stream));
     FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
@@ -532,7 +536,7 @@ void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
     GraphCache& gc = *(GraphCache*)g->graph_cache;
     const bool same = gc.exec && gc.rhs == f && gc.u == u && gc.kap == g->lev[0].kap && gc.kd0 == g->coef[0].kd &&
                       gc.nu1 == nu1 && gc.nu2 == nu2 && gc.transposed == transposed && gc.want_norm == want_norm &&
-                      gc.batch_active == (g->batch > 1);
+                      gc.batch_active == (fas::active_flags(g) != nullptr);
     if (!same) {
         gc.drop();
         if (!gc.cap) FAS_HIP_CHECK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
@@ -559,7 +563,7 @@ void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
         gc.nu2 = nu2;
         gc.transposed = transposed;
         gc.want_norm = want_norm;
-        gc.batch_active = g->batch > 1;
+        gc.batch_active = fas::active_flags(g) != nullptr;
     }
     FAS_HIP_CHECK(hipGraphLaunch(gc.exec, g->stream));
 }
@@ -575,6 +579,64 @@ void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1
     if (!(tol >= 0.0)) throw Error(FAS_ERR_ARG, "tol must be >= 0");
 }
 
+// The cycle loop of the solves.  cycle(k) enqueues V-cycle k, its convergence update
+// (which clears a problem's active flag once it has converged) and copies of what the host
+// needs into pinned slot k % 2; stopped(k) reads that slot and says whether the solve ends
+// at cycle k.  While likely_last(k) is false the loop enqueues cycle k + 1 before it waits
+// for cycle k, so the GPU does not idle while the host decides.  Every kernel checks the
+// active flags first, so a cycle enqueued after convergence does nothing (it still
+// dispatches its blocks, which is why the loop only runs ahead when convergence is not
+// expected; its profiler timings are dropped).  Returns the cycle at which the solve
+// ended, or kmax.
+struct GateScope {
+    fas_grid* g;
+    explicit GateScope(fas_grid* g_) : g(g_) { g->gate = 1; }
+    ~GateScope() { g->gate = 0; }
+};
+
+template <typename Cycle, typename Stopped, typename Last>
+int cycle_loop(fas_grid* g, Cycle cycle, Stopped stopped, Last likely_last)
+{
+    while (g->cyc_ev_created < 2)
+        FAS_HIP_CHECK(hipEventCreateWithFlags(&g->cyc_ev[g->cyc_ev_created++], hipEventDisableTiming));
+    GateScope gate(g);
+    // every cycle enqueued before this call runs for real, so the profiler may flush here
+    auto enqueue = [&](int k) {
+        if (g->profile && g->ev_n > fas::kMaxEvents - 32) prof_flush(g);
+        cycle(k);
+        FAS_HIP_CHECK(hipEventRecord(g->cyc_ev[k & 1], g->stream));
+    };
+    enqueue(1);
+    for (int k = 1;; ++k) {
+        int mark = -1;
+        if (k < g->kmax && !likely_last(k)) {
+            mark = g->ev_n;
+            enqueue(k + 1);
+        }
+        FAS_HIP_CHECK(hipEventSynchronize(g->cyc_ev[k & 1]));
+        if (stopped(k)) {
+            if (mark >= 0) g->ev_n = mark;  // cycle k + 1 did nothing
+            return k;
+        }
+        if (k == g->kmax) return k;
+        if (mark < 0) enqueue(k + 1);
+    }
+}
+
+constexpr size_t kHostBytes = 4096;  // pinned host buffer of a grid
+
+void ensure_host(fas_grid* g)
+{
+    if (!g->host) FAS_HIP_CHECK(hipHostMalloc((void**)&g->host, kHostBytes, hipHostMallocDefault));
+}
+
+// The single-problem solve.  Cycle k's stopping test (Alg. 1: ||f - A u|| <= tol ||f||,
+// squared) runs on the device, which clears the active flag on convergence and keeps the
+// squared norms in g->hist.  Making a result visible to the host stalls the GPU for tens
+// of microseconds (measured), so the host looks only at some cycles: after a solve that
+// took c cycles, the next one enqueues cycles 1 .. c - 2 without looking and then checks
+// every cycle.  A cycle enqueued after convergence does nothing (every kernel checks the
+// active flag; its profiler timings are dropped), so results never depend on this.
 int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const void* rhs, void* u, double tol,
                int nu1, int nu2, bool transposed)
 {
@@ -582,28 +644,69 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     set_coefs(g, dt, kappa, kcell != nullptr);
     set_kappa(g, kcell, g->dtype == FAS_F64);
     memset(&g->stats, 0, sizeof(g->stats));
+    ensure_host(g);
+    // status span: rnorm, active, cyc, count, hist (one problem) in workspace order
+    char* const span = (char*)g->rnorm;
+    const size_t span_bytes = (size_t)((char*)(g->hist + fas::kHist) - span);
+    if (span_bytes > kHostBytes) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
+    auto host_at = [&](const void* dev) { return (char*)g->host + ((const char*)dev - span); };
+    fas::launch_init_active(g);
     fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, nullptr);
-    const double nf = read_norm(g);
-    g->stats.rhs_norm = nf;
-    int status = FAS_NOT_CONVERGED;
-    int k;
-    for (k = 1; k <= g->kmax; ++k) {
+    FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    while (g->cyc_ev_created < 2)
+        FAS_HIP_CHECK(hipEventCreateWithFlags(&g->cyc_ev[g->cyc_ev_created++], hipEventDisableTiming));
+    GateScope gate(g);
+    const int horizon = g->last_cycles > 2 ? g->last_cycles - 2 : 0;  // cycles run without a look
+    g->last_cycles = 0;
+    std::vector<int> mark((size_t)g->kmax + 2, 0);  // profiler pairs recorded before cycle k
+    int end = 0, verified = 0;                        // cycle the solve stopped at; last cycle seen live
+    // copy the status span to the host after the last enqueued cycle; true if stopped
+    auto look = [&](int k) -> bool {
+        FAS_HIP_CHECK(hipMemcpyAsync(g->host, span, span_bytes, hipMemcpyDeviceToHost, g->stream));
+        FAS_HIP_CHECK(hipEventRecord(g->cyc_ev[0], g->stream));
+        FAS_HIP_CHECK(hipEventSynchronize(g->cyc_ev[0]));
+        if (*(const int*)host_at(g->count) != 0) {
+            verified = k;
+            return false;
+        }
+        end = *(const int*)host_at(g->cyc);  // k of the stop, -k if the norm was not finite
+        const int stop = end < 0 ? -end : end;
+        if (g->profile && stop < k) g->ev_n = mark[(size_t)stop + 1];  // cycles after it did nothing
+        return true;
+    };
+    bool stopped = false;
+    // profiler pairs one cycle may record (finest-level launches; per phase without fusion)
+    const int reserve = std::min(fas::kMaxEvents / 2, 2 * (nu1 + nu2) + 8);
+    for (int k = 1; k <= g->kmax && !stopped; ++k) {
+        if (g->profile && g->ev_n > fas::kMaxEvents - reserve) {
+            // before the profiler flushes, every cycle enqueued must be known to have run
+            if (k - 1 > verified && look(k - 1)) {
+                stopped = true;
+                break;
+            }
+            prof_flush(g);
+        }
+        mark[(size_t)k] = g->ev_n;
         vcycle_run(g, rhs, u, nu1, nu2, transposed, true);
-        const double nr = read_norm(g);
-        const double rel = nf > 0.0 ? nr / nf : nr;
-        if (k <= 64) g->stats.rel_res[k - 1] = rel;
-        if (!isfinite(nr)) {
-            g->stats.cycles = k;
-            g->stats.status = FAS_ERR_NONFINITE;
-            throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
-        }
-        if (nr <= tol * nf || nr == 0.0) {
-            status = FAS_OK;
-            break;
-        }
+        fas::launch_update_active(g, tol, k);
+        if (k > horizon || k == g->kmax) stopped = look(k);
     }
-    g->stats.cycles = status == FAS_OK ? k : g->kmax;
+    const double nf = sqrt(*(const double*)host_at(g->rnorm));
+    const double* hist = (const double*)host_at(g->hist);
+    const int cycles = !stopped ? g->kmax : (end < 0 ? -end : end);
+    g->stats.rhs_norm = nf;
+    for (int i = 0; i < cycles && i < 64 && i < fas::kHist; ++i) {
+        const double nr = sqrt(hist[i]);
+        g->stats.rel_res[i] = nf > 0.0 ? nr / nf : nr;
+    }
+    g->stats.cycles = cycles;
+    if (stopped && end < 0) {
+        g->stats.status = FAS_ERR_NONFINITE;
+        throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
+    }
+    const int status = stopped ? FAS_OK : FAS_NOT_CONVERGED;
     g->stats.status = status;
+    if (status == FAS_OK) g->last_cycles = cycles;
     if (status != FAS_OK) g_last_error = "not converged within kmax cycles";
     return status;
 }
@@ -707,6 +810,7 @@ int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int d
         g->active = (int*)(base + lay.active);
         g->cyc = (int*)(base + lay.cyc);
         g->count = (int*)(base + lay.count);
+        g->hist = (double*)(base + lay.hist);
         g->stream = (hipStream_t)stream;
         g->kmax = 100;
         g->nuc = 2;
@@ -730,6 +834,7 @@ int fas_grid_destroy(fas_grid_t g)
     }
     if (g->host) (void)hipHostFree(g->host);
     for (int i = 0; i < g->ev_created; ++i) (void)hipEventDestroy(g->ev[i]);
+    for (int i = 0; i < g->cyc_ev_created; ++i) (void)hipEventDestroy(g->cyc_ev[i]);
     delete g;
     return FAS_OK;
 }
@@ -970,15 +1075,19 @@ int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, vo
         fas::launch_resid_norm(g, 0, g->coef[0], nullptr, rhs, nullptr);  // ||rhs||^2 per problem
         FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, (size_t)g->batch * sizeof(double),
                                      hipMemcpyDeviceToDevice, g->stream));
-        if (!g->host) FAS_HIP_CHECK(hipHostMalloc((void**)&g->host, 64, hipHostMallocDefault));
-        int k;
-        for (k = 1; k <= g->kmax; ++k) {
-            vcycle_run(g, rhs, u, nu1, nu2, false, true);
-            fas::launch_update_active(g, tol, k);
-            FAS_HIP_CHECK(hipMemcpyAsync(g->host, g->count, sizeof(int), hipMemcpyDeviceToHost, g->stream));
-            FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
-            if (((int*)g->host)[0] == 0) break;
-        }
+        ensure_host(g);
+        int* const hcount = (int*)(g->host + 4);  // [k % 2]: problems still active after cycle k
+        cycle_loop(
+            g,
+            [&](int k) {
+                vcycle_run(g, rhs, u, nu1, nu2, false, true);
+                fas::launch_update_active(g, tol, k);
+                FAS_HIP_CHECK(
+                    hipMemcpyAsync(hcount + (k & 1), g->count, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+            },
+            [&](int k) -> bool { return hcount[k & 1] == 0; },
+            // a few problems may still need one more cycle: never run ahead
+            [](int) { return true; });
         std::vector<int> cyc((size_t)g->batch);
         FAS_HIP_CHECK(hipMemcpyAsync(cyc.data(), g->cyc, cyc.size() * sizeof(int), hipMemcpyDeviceToHost, g->stream));
         FAS_HIP_CHECK(hipStreamSynchronize(g->stream));

@@ -13,6 +13,7 @@ namespace fas {
 constexpr int kMaxLevels = 24;
 constexpr int kMaxEvents = 256;  // profiler event pairs held before a flush
 constexpr int kPartials = 2048;  // blocks of a norm reduction (fixed: deterministic order)
+constexpr int kHist = 64;        // cycles whose squared residual norms a solve keeps
 
 // Error carried to the C ABI boundary.
 struct Error : std::runtime_error {
@@ -65,6 +66,9 @@ struct fas_grid {
     int* cyc;            // per-problem cycle count at convergence (device)
     double* rnorm;       // per-problem ||rhs||^2 (device)
     int* count;          // number of active problems (device, 1 int)
+    double* hist;        // single problem: ||f - A u||^2 after cycles 1..kHist (device); the
+                         // regions rnorm .. hist + kHist are one span in this order
+    int last_cycles;     // cycles of the last converged solve (0: none yet)
     double* host;        // pinned host scalars
     void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
     void* mix_r;
@@ -79,6 +83,10 @@ struct fas_grid {
     int cus;                        // compute units of the device (0: not queried yet)
     int64_t tile_max;               // FAS_OPT_TILE: largest 2D level (cells) run as block tiles
     int tile_waves;                 // FAS_OPT_TILE_WAVES: waves per tile block (0: rule)
+    int gate;                       // a solve is running its cycle loop: kernels of a single
+                                    // problem check the active flag too
+    hipEvent_t cyc_ev[2];           // cycle loop: one event per cycle in flight
+    int cyc_ev_created;
     // profiler (FAS_OPT_PROFILE): event pairs around finest-level launches
     int profile;
     hipEvent_t ev[2 * fas::kMaxEvents];
@@ -89,6 +97,11 @@ struct fas_grid {
 };
 
 namespace fas {
+
+// Per-problem active flags the kernels check (a batched grid, or any grid inside a
+// solve's cycle loop, where a cycle already enqueued must do nothing once the solve has
+// converged), or nullptr.
+inline const int* active_flags(const fas_grid* g) { return g->batch > 1 || g->gate ? g->active : nullptr; }
 
 // ---- launchers (kernels_basic.hip) ----------------------------------------------------
 // All act on level `l` of grid g with coefficients c, on g->stream.
@@ -117,7 +130,8 @@ void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst3
 // Batched solves: every problem active, cycle counts zero.
 void launch_init_active(const fas_grid* g);
 // After cycle k: problems with norm_out <= tol^2 * rnorm (or 0) stop and record k;
-// a non-finite norm stops with -k; g->count gets the number still active.
+// a non-finite norm stops with -k; g->count gets the number still active; a single
+// problem also records norm_out in g->hist[k - 1] (k <= kHist) while active.
 void launch_update_active(const fas_grid* g, double tol, int k);
 // Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32):
 // S = sum_j eta_j^2; f_i = eta_i - dt*((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)).

@@ -45,7 +45,7 @@ inline Batch batch_of(const fas_grid* g, int l)
     Batch b;
     b.fine = g->lev[l].N;
     b.coarse = l < g->L ? g->lev[l + 1].N : 0;
-    b.act = g->batch > 1 ? g->active : nullptr;
+    b.act = active_flags(g);
     return b;
 }
 
@@ -371,13 +371,14 @@ __global__ __launch_bounds__(kBlock) void k_init_active(int* act, int* cyc, int 
 __global__ __launch_bounds__(kBlock) void k_update_active(const double* __restrict__ norm2,
                                                           const double* __restrict__ rnorm2, double tol2, int k,
                                                           int* __restrict__ act, int* __restrict__ cyc, int nb,
-                                                          int* __restrict__ count)
+                                                          int* __restrict__ count, double* __restrict__ hist)
 {
     __shared__ int red[kBlock];
     int alive = 0;
     for (int b = threadIdx.x; b < nb; b += kBlock) {
         if (!act[b]) continue;
         const double nr = norm2[b];
+        if (hist && k <= kHist) hist[k - 1] = nr;  // single problem: squared norm after cycle k
         if (!isfinite(nr)) {
             act[b] = 0;
             cyc[b] = -k;
@@ -581,7 +582,7 @@ void launch_init_active(const fas_grid* g)
 void launch_update_active(const fas_grid* g, double tol, int k)
 {
     k_update_active<<<1, kBlock, 0, g->stream>>>(g->norm_out, g->rnorm, tol * tol, k, g->active, g->cyc, g->batch,
-                                                 g->count);
+                                                 g->count, g->batch == 1 ? g->hist : nullptr);
     check_launch();
 }
 

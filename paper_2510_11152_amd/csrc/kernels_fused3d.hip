@@ -487,7 +487,7 @@ March3Args<T> make_args3(const fas_grid* g, int l, const Coef& c, int ns, int mo
     a.batch = g->batch;
     a.stride = g->lev[l].N;
     a.cstride = l < g->L ? g->lev[l + 1].N : 0;
-    a.act = g->batch > 1 ? g->active : nullptr;
+    a.act = active_flags(g);
     return a;
 }
 

@@ -211,7 +211,7 @@ void launch_t(const fas_grid* g, int top, const Coef* coef, int pre, int post, i
     a.r_top = (const T*)r;
     a.form_rhs = form_rhs;
     a.stride = g->lev[top].N;
-    a.act = g->batch > 1 ? g->active : nullptr;
+    a.act = active_flags(g);
     const unsigned nb = (unsigned)g->batch;
     const bool kv = g->lev[top].kap != nullptr;
     if (g->dim == 2) {

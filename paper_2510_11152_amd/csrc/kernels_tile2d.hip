@@ -444,7 +444,7 @@ TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int 
     a.batch = g->batch;
     a.stride = g->lev[l].N;
     a.cstride = l < g->L ? g->lev[l + 1].N : 0;
-    a.act = g->batch > 1 ? g->active : nullptr;
+    a.act = active_flags(g);
     a.kap = (const T*)g->lev[l].kap;  // cell kappa: single-problem grids only
     return a;
 }

@@ -445,7 +445,7 @@ StripArgs<T> make_args(const fas_grid* g, int l, const Coef& c, int nu)
     a.batch = g->batch;
     a.stride = g->lev[l].N;
     a.cstride = l < g->L ? g->lev[l + 1].N : 0;
-    a.act = g->batch > 1 ? g->active : nullptr;
+    a.act = active_flags(g);
     a.kap = (const T*)g->lev[l].kap;
     return a;
 }
