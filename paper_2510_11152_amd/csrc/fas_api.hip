@@ -362,13 +362,20 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         // rc_in: f = rc_in + A u, formed and written by the pre pass
         const void* const fin = rc_in ? rc_in : f;
         void* const fout = rc_in ? g->lev[l].f : nullptr;
+        // a solve's first pass also sums f^2 (its ||rhs||^2) per tile
+        const bool fnorm = tile && l == 0 && g->fnorm_pending;
         {
             ProfScope ps(g, l, FAS_K_PRE);
             if (tile)
-                fas::launch_tile_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout);
+                fas::launch_tile_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout,
+                                     fnorm ? g->partials : nullptr);
             else
                 fas::launch_fused_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout);
             ps.end();
+        }
+        if (fnorm) {
+            fas::launch_sum_partials(g, fas::tile_count(g, 0, pre), g->rnorm);
+            g->fnorm_pending = 0;
         }
         coarse_part(g, l, pre, post, rev);
         {
@@ -526,7 +533,8 @@ void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
 
 void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed, bool want_norm)
 {
-    if (!g->use_graph || g->profile || (g->autotune && !g->tuned)) {
+    // (a solve's first cycle, which also sums ||f||^2, is not the cycle a graph replays)
+    if (!g->use_graph || g->profile || (g->autotune && !g->tuned) || g->fnorm_pending) {
         // the first cycle of an autotuned grid times its kernels, which cannot be captured
         vcycle_top(g, f, u, nu1, nu2, transposed, want_norm);
         if (g->autotune) g->tuned = 1;
@@ -651,8 +659,19 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     if (span_bytes > kHostBytes) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
     auto host_at = [&](const void* dev) { return (char*)g->host + ((const char*)dev - span); };
     fas::launch_init_active(g);
-    fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, nullptr);
-    FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    // ||f||^2: summed by the first cycle's finest tile pre pass, which reads f anyway
+    // (the tile partial sums fit the partials buffer), else by a pass of its own
+    const int pre0 = transposed ? nu2 : nu1, post0 = transposed ? nu1 : nu2;
+    g->fnorm_pending = g->batch == 1 && fas::tail_top(g) > 0 && fas::tile_ok(g, 0, pre0, post0, kcell != nullptr) &&
+                       fas::tile_count(g, 0, pre0) <= g->npartials;
+    if (!g->fnorm_pending) {
+        fas::launch_resid_norm(g, 0, g->coef[0], g->lev[0].kap, rhs, nullptr);
+        FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    }
+    struct Pending {
+        fas_grid* g;
+        ~Pending() { g->fnorm_pending = 0; }
+    } pending{g};
     while (g->cyc_ev_created < 2)
         FAS_HIP_CHECK(hipEventCreateWithFlags(&g->cyc_ev[g->cyc_ev_created++], hipEventDisableTiming));
     GateScope gate(g);

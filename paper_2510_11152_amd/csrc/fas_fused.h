@@ -43,8 +43,10 @@ int strip_waves_per_cu(int nu);
 // sweeps).  tile_count: norm partial sums a post launch leaves per problem.
 bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
 int tile_count(const fas_grid* g, int l, int nu);
+// fpartials (nullable, not with fout): one sum of f^2 per tile as well (tile_count(g, l,
+// nu) of them).
 void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                     void* u_out, void* uc, void* rc, void* fout = nullptr);
+                     void* u_out, void* uc, void* rc, void* fout = nullptr, double* fpartials = nullptr);
 void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
                       const void* uc, void* u_out, double* partials);
 

@@ -69,6 +69,7 @@ struct fas_grid {
     double* hist;        // single problem: ||f - A u||^2 after cycles 1..kHist (device); the
                          // regions rnorm .. hist + kHist are one span in this order
     int last_cycles;     // cycles of the last converged solve (0: none yet)
+    int fnorm_pending;   // the next finest-level tile pre pass also sums f^2 into rnorm
     double* host;        // pinned host scalars
     void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
     void* mix_r;
@@ -112,8 +113,8 @@ void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, c
 // Partial sums of r^2 (r = f - A u) into g->partials then a fixed-order total into
 // g->norm_out[0]; rhs-only mode (u == nullptr) sums f^2.
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u);
-// Fixed-order total of g->partials[0..count) into g->norm_out[0].
-void launch_sum_partials(const fas_grid* g, int count);
+// Fixed-order total of g->partials[0..count) into out[0] (default g->norm_out).
+void launch_sum_partials(const fas_grid* g, int count, double* out = nullptr);
 void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
                            const void* u, void* uc, void* rc);
 void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc);

@@ -478,9 +478,9 @@ void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap,
     launch_sum_partials(g, (int)nb);
 }
 
-void launch_sum_partials(const fas_grid* g, int count)
+void launch_sum_partials(const fas_grid* g, int count, double* out)
 {
-    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials, count, g->norm_out);
+    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials, count, out ? out : g->norm_out);
     check_launch();
 }
 

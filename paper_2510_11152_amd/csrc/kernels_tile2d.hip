@@ -352,7 +352,10 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
                     __builtin_nontemporal_store(rcv, a.rc + P);
                 }
             }
-            if constexpr (NORM) {
+            if constexpr (NORM && MODE == 0) {  // pre: the right-hand side's f^2
+                acc += (double)fe[r] * (double)fe[r];
+                acc += (double)fo[r] * (double)fo[r];
+            } else if constexpr (NORM) {
                 acc += (double)re * (double)re;
                 acc += (double)ro * (double)ro;
             }
@@ -474,23 +477,28 @@ int tile_count(const fas_grid* g, int l, int nu)
 }
 
 void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                     void* u_out, void* uc, void* rc, void* fout)
+                     void* u_out, void* uc, void* rc, void* fout, double* fpartials)
 {
+    if (fout && fpartials) throw Error(FAS_ERR_ARG, "internal: a pre pass forms f or sums f^2, not both");
     const int wv = tile_waves(g, l, nu);
     if (g->dtype == FAS_F64) {
         auto a = make_tile_args<double>(g, l, c, nu, wv, true);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
-        a.uc = (double*)uc, a.rc = (double*)rc, a.fout = (double*)fout;
+        a.uc = (double*)uc, a.rc = (double*)rc, a.fout = (double*)fout, a.partials = fpartials;
         if (fout)
             launch_tile<double, 0, false, true>(g, a, nu, first, wv);
+        else if (fpartials)
+            launch_tile<double, 0, true, false>(g, a, nu, first, wv);
         else
             launch_tile<double, 0, false, false>(g, a, nu, first, wv);
     } else {
         auto a = make_tile_args<float>(g, l, c, nu, wv, true);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
-        a.uc = (float*)uc, a.rc = (float*)rc, a.fout = (float*)fout;
+        a.uc = (float*)uc, a.rc = (float*)rc, a.fout = (float*)fout, a.partials = fpartials;
         if (fout)
             launch_tile<float, 0, false, true>(g, a, nu, first, wv);
+        else if (fpartials)
+            launch_tile<float, 0, true, false>(g, a, nu, first, wv);
         else
             launch_tile<float, 0, false, false>(g, a, nu, first, wv);
     }

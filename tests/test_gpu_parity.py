@@ -170,21 +170,28 @@ def test_vcycle_many_tiles_cell_kappa_bitwise(n, bc, dtype, nu, transposed, path
         assert np.array_equal(host(ug), u), it
 
 
-def test_heat_256_one_step_matches_oracle():
-    """2D heat backward Euler, one step, 256^2, h = 1/256, dt = 1e-3, Neumann, FP64,
-    16 cosine modes, V(2,2) to 1e-10: same cycle count and the same bits."""
+def test_heat_256_steps_match_oracle():
+    """2D heat backward Euler, three steps, 256^2, h = 1/256, dt = 1e-3, Neumann, FP64,
+    16 cosine modes, V(2,2) to 1e-10: same cycle counts, the same bits, the same residual
+    history and ||f|| (which the first tile pass sums; later steps also run their first
+    cycles without a host check)."""
     u0 = I.heat_2d_small()
     P = O.Problem(n=(256, 256), h=1 / 256, dt=1e-3, bc="neumann", coarsest=4, nuc=2)
-    uo = u0.copy()
-    st, cyc, hist = O.solve(P, u0, uo, 1e-10)
     g = grid_for(P, np.float64)
-    ug = dev(u0)
-    assert g.solve(dev(u0), ug, P.dt, tol=1e-10) == 0
-    s = g.stats()
-    assert abs(s["cycles"] - cyc) <= 1
-    if s["cycles"] == cyc:
-        assert np.array_equal(host(ug), uo)
-    np.testing.assert_allclose(s["rel_res"][: min(cyc, s["cycles"])], hist[: min(cyc, s["cycles"])], rtol=1e-9)
+    rhs = u0.copy()
+    for step in range(3):
+        uo = rhs.copy()
+        st, cyc, hist = O.solve(P, rhs, uo, 1e-10)
+        ug = dev(rhs)
+        assert g.solve(dev(rhs), ug, P.dt, tol=1e-10) == 0
+        s = g.stats()
+        assert abs(s["cycles"] - cyc) <= 1, step
+        if s["cycles"] == cyc:
+            assert np.array_equal(host(ug), uo), step
+        np.testing.assert_allclose(s["rel_res"][: min(cyc, s["cycles"])], hist[: min(cyc, s["cycles"])], rtol=1e-9)
+        nf = float(np.sqrt(np.dot(rhs.ravel(), rhs.ravel())))
+        assert abs(s["rhs_norm"] - nf) <= 1e-12 * nf, step
+        rhs = uo
 
 
 @pytest.mark.parametrize("n,coarsest,bc", [((128, 128), 4, "neumann"), ((32, 32, 32), 4, "neumann"),
