@@ -414,6 +414,10 @@ void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
     const int np = vcycle_level(g, 0, f, u, transposed ? nu2 : nu1, transposed ? nu1 : nu2, transposed,
                                 want_norm ? g->partials : nullptr);
     if (!want_norm) return;
+    if (np > 0 && g->defer_norm) {  // summed by the caller's convergence update
+        g->deferred_np = np;
+        return;
+    }
     ProfScope ps(g, 0, FAS_K_NORM);
     if (np > 0)
         fas::launch_sum_partials(g, np);
@@ -546,6 +550,13 @@ void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
                       gc.nu1 == nu1 && gc.nu2 == nu2 && gc.transposed == transposed && gc.want_norm == want_norm &&
                       gc.batch_active == (fas::active_flags(g) != nullptr);
     if (!same) {
+        // the captured cycle sums its own norm
+        struct NoDefer {
+            fas_grid* g;
+            int saved;
+            ~NoDefer() { g->defer_norm = saved; }
+        } nd{g, g->defer_norm};
+        g->defer_norm = 0;
         gc.drop();
         if (!gc.cap) FAS_HIP_CHECK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
         hipStream_t saved = g->stream;
@@ -670,8 +681,15 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     }
     struct Pending {
         fas_grid* g;
-        ~Pending() { g->fnorm_pending = 0; }
+        ~Pending()
+        {
+            g->fnorm_pending = 0;
+            g->defer_norm = 0;
+            g->deferred_np = 0;
+        }
     } pending{g};
+    g->defer_norm = 1;  // a cycle's norm total and its convergence update: one launch
+    g->deferred_np = 0;
     while (g->cyc_ev_created < 2)
         FAS_HIP_CHECK(hipEventCreateWithFlags(&g->cyc_ev[g->cyc_ev_created++], hipEventDisableTiming));
     GateScope gate(g);
@@ -707,7 +725,11 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
         }
         mark[(size_t)k] = g->ev_n;
         vcycle_run(g, rhs, u, nu1, nu2, transposed, true);
-        fas::launch_update_active(g, tol, k);
+        if (g->deferred_np > 0)
+            fas::launch_sum_update(g, g->deferred_np, tol, k);
+        else
+            fas::launch_update_active(g, tol, k);
+        g->deferred_np = 0;
         if (k > horizon || k == g->kmax) stopped = look(k);
     }
     const double nf = sqrt(*(const double*)host_at(g->rnorm));

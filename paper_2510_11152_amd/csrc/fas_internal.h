@@ -70,6 +70,8 @@ struct fas_grid {
                          // regions rnorm .. hist + kHist are one span in this order
     int last_cycles;     // cycles of the last converged solve (0: none yet)
     int fnorm_pending;   // the next finest-level tile pre pass also sums f^2 into rnorm
+    int defer_norm;      // a cycle leaves its norm partials for the caller to sum ...
+    int deferred_np;     // ... and reports how many (0: the norm is already in norm_out)
     double* host;        // pinned host scalars
     void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
     void* mix_r;
@@ -134,6 +136,9 @@ void launch_init_active(const fas_grid* g);
 // a non-finite norm stops with -k; g->count gets the number still active; a single
 // problem also records norm_out in g->hist[k - 1] (k <= kHist) while active.
 void launch_update_active(const fas_grid* g, double tol, int k);
+// One problem: launch_sum_partials(g, count) and launch_update_active(g, tol, k) in one
+// launch (the same norm bits, the same flags).
+void launch_sum_update(const fas_grid* g, int count, double tol, int k);
 // Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32):
 // S = sum_j eta_j^2; f_i = eta_i - dt*((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)).
 void launch_grain_rhs(hipStream_t stream, int q, int64_t N, float dt, const float* eta, float* f);

@@ -148,10 +148,10 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Op<T> op, const T* __rest
 // flight), then a fixed tree over the threads.
 constexpr int kSumBlock = 1024;
 
-__global__ __launch_bounds__(kSumBlock) void k_sum_partials(const double* __restrict__ partials, int count,
-                                                             double* __restrict__ out)
+// Fixed-order total of partials[0..count) by one block of kSumBlock threads: strided
+// per-thread sums, then a binary tree in LDS.  Every thread returns the total.
+__device__ __forceinline__ double sum_block(const double* __restrict__ partials, int count)
 {
-    partials += (int64_t)blockIdx.x * count;
     double acc = 0.0;
 #pragma unroll 4
     for (int b = threadIdx.x; b < count; b += kSumBlock) acc += partials[b];
@@ -162,7 +162,38 @@ __global__ __launch_bounds__(kSumBlock) void k_sum_partials(const double* __rest
         if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    return red[0];
+}
+
+__global__ __launch_bounds__(kSumBlock) void k_sum_partials(const double* __restrict__ partials, int count,
+                                                             double* __restrict__ out)
+{
+    const double t = sum_block(partials + (int64_t)blockIdx.x * count, count);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// One problem: the norm total of cycle k (as k_sum_partials) and its convergence update
+// (as k_update_active) in one launch.
+__global__ __launch_bounds__(kSumBlock) void k_sum_update(const double* __restrict__ partials, int count,
+                                                           double* __restrict__ norm2, const double* __restrict__ rnorm2,
+                                                           double tol2, int k, int* __restrict__ act,
+                                                           int* __restrict__ cyc, int* __restrict__ alive,
+                                                           double* __restrict__ hist)
+{
+    const double nr = sum_block(partials, count);
+    if (threadIdx.x != 0) return;
+    norm2[0] = nr;
+    if (act[0]) {
+        if (k <= kHist) hist[k - 1] = nr;
+        if (!isfinite(nr)) {
+            act[0] = 0;
+            cyc[0] = -k;
+        } else if (nr <= tol2 * rnorm2[0] || nr == 0.0) {
+            act[0] = 0;
+            cyc[0] = k;
+        }
+    }
+    alive[0] = act[0];
 }
 
 // ----------------------------------------------------------- residual + restriction
@@ -481,6 +512,14 @@ void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap,
 void launch_sum_partials(const fas_grid* g, int count, double* out)
 {
     k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials, count, out ? out : g->norm_out);
+    check_launch();
+}
+
+void launch_sum_update(const fas_grid* g, int count, double tol, int k)
+{
+    if (g->batch != 1) throw Error(FAS_ERR_ARG, "internal: the fused norm update takes one problem");
+    k_sum_update<<<1, kSumBlock, 0, g->stream>>>(g->partials, count, g->norm_out, g->rnorm, tol * tol, k, g->active,
+                                                  g->cyc, g->count, g->hist);
     check_launch();
 }
 
