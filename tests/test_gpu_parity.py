@@ -194,6 +194,34 @@ def test_heat_256_steps_match_oracle():
         rhs = uo
 
 
+@pytest.mark.parametrize("n,dtype", [((512, 512), np.float64), ((256, 128), np.float32), ((32, 32, 32), np.float64)])
+@pytest.mark.parametrize("transposed", [False, True])
+def test_solve_after_a_longer_solve_is_unchanged(n, dtype, transposed):
+    """A solve enqueues the first cycles without a host check when the previous solve on
+    the grid took more cycles; cycles enqueued after its convergence must do nothing. A
+    loose-tolerance solve after a tight one (and a tight one after it, and a solve that
+    converges at once) equals the same solve on a fresh grid: bits, cycles, residuals."""
+    P = _problem(n, 4, "neumann", dt=1e-3, kappa=1.0, nuc=2)
+    tight, loose = (1e-10, 1e-3) if dtype == np.float64 else (1e-5, 1e-2)
+    f = dev(I.random_field(P.shape(), 81).astype(dtype))
+    g = grid_for(P, dtype)
+    u = f.clone()
+    assert g.solve(f, u, P.dt, tol=tight, transposed=transposed) == 0
+    long_cycles = g.stats()["cycles"]
+    for tol, u0 in ((loose, f), (tight, f), (loose, u.clone())):
+        ua, ub = u0.clone(), u0.clone()
+        assert g.solve(f, ua, P.dt, tol=tol, transposed=transposed) == 0
+        sa = g.stats()
+        fresh = grid_for(P, dtype)
+        assert fresh.solve(f, ub, P.dt, tol=tol, transposed=transposed) == 0
+        sb = fresh.stats()
+        assert sa["cycles"] == sb["cycles"], (tol, sa["cycles"], sb["cycles"])
+        assert torch.equal(ua, ub), tol
+        assert sa["rel_res"][: sa["cycles"]] == sb["rel_res"][: sb["cycles"]]
+        assert sa["rhs_norm"] == sb["rhs_norm"]
+    assert long_cycles > 3
+
+
 @pytest.mark.parametrize("n,coarsest,bc", [((128, 128), 4, "neumann"), ((32, 32, 32), 4, "neumann"),
                                            ((128, 64), 4, "dirichlet")])
 @pytest.mark.parametrize("variable", [False, True])
