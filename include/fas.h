@@ -85,12 +85,12 @@ extern "C" {
                                    every march launch, overriding rule and autotuner;
                                    0 (default): rule or autotuner                         */
 #define FAS_OPT_TILE 8           /* >= 0: 2D levels of at most this many cells per problem run
-                                   their fused passes as block tiles (constant kappa, 1..3
-                                   sweeps), the others as row marches; 0: row marches
+                                   their fused passes as block tiles (1..3 sweeps), the
+                                   others as row marches; 0: row marches
                                    only; default: every level                             */
 #define FAS_OPT_TILE_WAVES 9     /* 6..16: waves per tile workgroup (rows written per tile
                                    4 * waves - 4 nu - 4 in FP64, 8 * waves - 4 nu - 4 in
-                                   FP32); 0 (default): 8                                  */
+                                   FP32; cell kappa: at most 8); 0 (default): 8           */
 
 /* kernel classes reported by fas_get_profile */
 #define FAS_K_SMOOTH 0 /* stand-alone smoothing launches on the finest level              */
@@ -133,8 +133,11 @@ int64_t fas_level_cells(fas_grid_t grid, int level);
 
 /* Solve A u = rhs by V(nu1,nu2)-cycles (Alg. 1 outer loop) until
  * ||rhs - A u||_2 <= tol * ||rhs||_2 or FAS_OPT_KMAX cycles.  u: initial guess in,
- * iterate out.  rhs and u must not alias (FAS_ERR_ARG).  Synchronises the stream once
- * per cycle to read the residual norm. */
+ * iterate out.  rhs and u must not alias (FAS_ERR_ARG).  The test runs on the device
+ * after every cycle (squared norms compared); the call returns once the iterate is final.
+ * The host waits on the stream only near the expected end: after a solve on the grid that
+ * took c cycles, cycles 1..c-2 are enqueued without a wait (cycles enqueued after
+ * convergence do nothing).  fas_get_stats reports every cycle's relative residual. */
 int fas_solve(fas_grid_t grid, double dt, double kappa, const void* kappa_cell, const void* rhs, void* u,
               double tol, int nu1, int nu2);
 
