@@ -35,11 +35,48 @@ struct TailArgs {
 constexpr int kTX = 32;
 constexpr int kTY = kTailThreads / kTX;
 
+// 2D, constant kappa: the neighbourhood of cell (i, j) of a level held in LDS, with the
+// values and boundary-face count of fas_device.h's gather (neighbours across a periodic
+// edge wrapped, across another edge 0), from 32-bit indices: every tail phase is a chain
+// of these, so their index arithmetic is on its critical path.
+template <typename T>
+__device__ __forceinline__ void gather2(const Op<T>& op, const T* U, int i, int j, Nbhd<T, 2>& s)
+{
+    const bool per = op.bc == BC_PERIODIC;
+    const int n0 = op.n0, n1 = op.n1, p = i + n0 * j;
+    const bool xl = i > 0, xr = i < n0 - 1, yl = j > 0, yr = j < n1 - 1;
+    // an in-range index for each neighbour: wrapped on periodic grids, else the cell
+    const int qxm = xl ? p - 1 : (per ? p + n0 - 1 : p);
+    const int qxp = xr ? p + 1 : (per ? p - n0 + 1 : p);
+    const int qym = yl ? p - n0 : (per ? p + (n1 - 1) * n0 : p);
+    const int qyp = yr ? p + n0 : (per ? p - (n1 - 1) * n0 : p);
+    const T vxm = U[qxm], vxp = U[qxp], vym = U[qym], vyp = U[qyp];
+    s.v[0] = (per || xl) ? vxm : (T)0;
+    s.v[1] = (per || xr) ? vxp : (T)0;
+    s.v[2] = (per || yl) ? vym : (T)0;
+    s.v[3] = (per || yr) ? vyp : (T)0;
+    s.nout = per ? 0 : (!xl) + (!xr) + (!yl) + (!yr);
+}
+
+// Neighbourhood of cell (i, j, l) of a level held in LDS.
+template <typename T, int DIM, bool KV>
+__device__ __forceinline__ void tail_gather(const Op<T>& op, const T* U, int i, int j, int l, Nbhd<T, DIM>& s)
+{
+    if constexpr (DIM == 2 && !KV)
+        gather2<T>(op, U, i, j, s);
+    else
+        gather<T, DIM, KV>(op, U, i, j, l, s);
+}
+
 template <typename T, int DIM, bool KV>
 __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int first, bool reverse)
 {
     const int f0 = reverse ? 1 - first : first;
     const int half = (op.n0 + 1) >> 1;
+    // 2D constant kappa: q[W] for 0, 1 and 2 boundary faces (uniform picks; a per-cell
+    // index into the table would be a memory load per cell)
+    const T q0 = op.q[diag_count(op.bc, DIM, 0)], q1 = op.q[diag_count(op.bc, DIM, 1)],
+            q2 = op.q[diag_count(op.bc, DIM, 2)];
     const int rows = op.n1 * op.n2;
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
     for (int s = 0; s < sweeps; ++s) {
@@ -52,9 +89,14 @@ __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int f
                     const int i = 2 * tt + odd;
                     if (i >= op.n0) continue;
                     Nbhd<T, DIM> nb;
-                    gather<T, DIM, KV>(op, U, i, j, l, nb);
+                    tail_gather<T, DIM, KV>(op, U, i, j, l, nb);
                     const int p = (int)cell_index(op.n0, op.n1, i, j, l);
-                    U[p] = gs_value<T, DIM, KV>(op, nb, F[p]);
+                    if constexpr (DIM == 2 && !KV) {  // gs_value's tree
+                        const T S = nbsum<T, DIM>(nb.v);
+                        U[p] = (F[p] + op.k * S) * (nb.nout == 0 ? q0 : (nb.nout == 1 ? q1 : q2));
+                    } else {
+                        U[p] = gs_value<T, DIM, KV>(op, nb, F[p]);
+                    }
                 }
             }
             __syncthreads();
@@ -87,7 +129,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
             for (int i = tx; i < op.n0; i += kTX) {
                 const int p = (int)cell_index(op.n0, op.n1, i, j, l);
                 Nbhd<T, DIM> nb;
-                gather<T, DIM, KV>(op, U(0), i, j, l, nb);
+                tail_gather<T, DIM, KV>(op, U(0), i, j, l, nb);
                 F(0)[p] = F(0)[p] + apply_value<T, DIM, KV>(op, nb, U(0)[p]);
             }
         }
@@ -111,7 +153,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
                 const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), l = DIM == 3 ? 2 * K + (c >> 2) : 0;
                 const int p = (int)cell_index(op.n0, op.n1, i, j, l);
                 Nbhd<T, DIM> nb;
-                gather<T, DIM, KV>(op, u, i, j, l, nb);
+                tail_gather<T, DIM, KV>(op, u, i, j, l, nb);
                 uu[c] = u[p];
                 rr[c] = f[p] - apply_value<T, DIM, KV>(op, nb, uu[c]);
             }
@@ -129,7 +171,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
             const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
             const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             Nbhd<T, DIM> nb;
-            gather<T, DIM, KV>(oc, U(lv + 1), I, J, K, nb);
+            tail_gather<T, DIM, KV>(oc, U(lv + 1), I, J, K, nb);
             F(lv + 1)[P] = F(lv + 1)[P] + apply_value<T, DIM, KV>(oc, nb, U(lv + 1)[P]);
         }
         __syncthreads();
