@@ -598,49 +598,11 @@ void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1
     if (!(tol >= 0.0)) throw Error(FAS_ERR_ARG, "tol must be >= 0");
 }
 
-// The cycle loop of the solves.  cycle(k) enqueues V-cycle k, its convergence update
-// (which clears a problem's active flag once it has converged) and copies of what the host
-// needs into pinned slot k % 2; stopped(k) reads that slot and says whether the solve ends
-// at cycle k.  While likely_last(k) is false the loop enqueues cycle k + 1 before it waits
-// for cycle k, so the GPU does not idle while the host decides.  Every kernel checks the
-// active flags first, so a cycle enqueued after convergence does nothing (it still
-// dispatches its blocks, which is why the loop only runs ahead when convergence is not
-// expected; its profiler timings are dropped).  Returns the cycle at which the solve
-// ended, or kmax.
 struct GateScope {
     fas_grid* g;
     explicit GateScope(fas_grid* g_) : g(g_) { g->gate = 1; }
     ~GateScope() { g->gate = 0; }
 };
-
-template <typename Cycle, typename Stopped, typename Last>
-int cycle_loop(fas_grid* g, Cycle cycle, Stopped stopped, Last likely_last)
-{
-    while (g->cyc_ev_created < 2)
-        FAS_HIP_CHECK(hipEventCreateWithFlags(&g->cyc_ev[g->cyc_ev_created++], hipEventDisableTiming));
-    GateScope gate(g);
-    // every cycle enqueued before this call runs for real, so the profiler may flush here
-    auto enqueue = [&](int k) {
-        if (g->profile && g->ev_n > fas::kMaxEvents - 32) prof_flush(g);
-        cycle(k);
-        FAS_HIP_CHECK(hipEventRecord(g->cyc_ev[k & 1], g->stream));
-    };
-    enqueue(1);
-    for (int k = 1;; ++k) {
-        int mark = -1;
-        if (k < g->kmax && !likely_last(k)) {
-            mark = g->ev_n;
-            enqueue(k + 1);
-        }
-        FAS_HIP_CHECK(hipEventSynchronize(g->cyc_ev[k & 1]));
-        if (stopped(k)) {
-            if (mark >= 0) g->ev_n = mark;  // cycle k + 1 did nothing
-            return k;
-        }
-        if (k == g->kmax) return k;
-        if (mark < 0) enqueue(k + 1);
-    }
-}
 
 constexpr size_t kHostBytes = 4096;  // pinned host buffer of a grid
 
@@ -1117,18 +1079,20 @@ int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, vo
         FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, (size_t)g->batch * sizeof(double),
                                      hipMemcpyDeviceToDevice, g->stream));
         ensure_host(g);
-        int* const hcount = (int*)(g->host + 4);  // [k % 2]: problems still active after cycle k
-        cycle_loop(
-            g,
-            [&](int k) {
-                vcycle_run(g, rhs, u, nu1, nu2, false, true);
-                fas::launch_update_active(g, tol, k);
-                FAS_HIP_CHECK(
-                    hipMemcpyAsync(hcount + (k & 1), g->count, sizeof(int), hipMemcpyDeviceToHost, g->stream));
-            },
-            [&](int k) -> bool { return hcount[k & 1] == 0; },
-            // a few problems may still need one more cycle: never run ahead
-            [](int) { return true; });
+        // as the single solve: after a batched solve whose slowest problem took c cycles,
+        // cycles 1..c-2 run without a look (a problem that has converged skips them)
+        GateScope gate(g);
+        const int horizon = g->last_cycles > 2 && !g->profile ? g->last_cycles - 2 : 0;
+        g->last_cycles = 0;
+        int* const hcount = (int*)g->host;
+        for (int k = 1; k <= g->kmax; ++k) {
+            vcycle_run(g, rhs, u, nu1, nu2, false, true);
+            fas::launch_update_active(g, tol, k);
+            if (k <= horizon && k < g->kmax) continue;
+            FAS_HIP_CHECK(hipMemcpyAsync(hcount, g->count, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+            FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
+            if (hcount[0] == 0) break;
+        }
         std::vector<int> cyc((size_t)g->batch);
         FAS_HIP_CHECK(hipMemcpyAsync(cyc.data(), g->cyc, cyc.size() * sizeof(int), hipMemcpyDeviceToHost, g->stream));
         FAS_HIP_CHECK(hipStreamSynchronize(g->stream));
@@ -1145,6 +1109,7 @@ int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, vo
         }
         g->stats.cycles = maxc;
         g->stats.status = worst;
+        if (worst == FAS_OK) g->last_cycles = maxc;
         if (worst == FAS_ERR_NONFINITE) return fail(FAS_ERR_NONFINITE, "a residual norm is not finite");
         if (worst == FAS_NOT_CONVERGED) g_last_error = "some problems did not converge within kmax cycles";
         return worst;

@@ -123,3 +123,25 @@ def test_batched_graph_replay_equals_launches():
     sb = Grid(n, P.h, batch=B).set(graph=True).solve_batched(rhs, ub, P.dt, tol=1e-10)
     assert sa == sb
     assert torch.equal(ua, ub)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_solve_after_a_longer_solve_is_unchanged(graph):
+    """After a batched solve that took c cycles, the next one runs its first c - 2 cycles
+    without a host check; problems that converge inside that window must stay as they
+    are. A loose-tolerance batched solve after a tight one (and one from converged
+    iterates) equals the same solve on a fresh grid: statuses, cycles and bits."""
+    from paper_2510_11152_amd import Grid
+    B, n = 4, (256, 128)
+    P = O.Problem(n=n, h=1 / 256, dt=1e-3, bc="dirichlet", coarsest=4)
+    rhs = torch.from_numpy(np.stack([I.random_field(P.shape(), 400 + b) * (b + 1) for b in range(B)])).to(DEV)
+    g = Grid(n, P.h, bc="dirichlet", batch=B).set(graph=graph)
+    u = rhs.clone()
+    st, cy = g.solve_batched(rhs, u, P.dt, tol=1e-10)
+    assert all(s == 0 for s in st) and max(cy) > 3
+    for tol, u0 in ((1e-3, rhs), (1e-3, u.clone()), (1e-10, rhs)):
+        ua, ub = u0.clone(), u0.clone()
+        sa = g.solve_batched(rhs, ua, P.dt, tol=tol)
+        sb = Grid(n, P.h, bc="dirichlet", batch=B).set(graph=graph).solve_batched(rhs, ub, P.dt, tol=tol)
+        assert sa == sb, (tol, sa, sb)
+        assert torch.equal(ua, ub), tol
