@@ -21,10 +21,11 @@
  *   - Arrays are device pointers to contiguous storage of the grid's dtype, x fastest:
  *     index = i + n0*(j + n1*k).  The caller owns all device memory, including the
  *     workspace handed to fas_grid_create; the library never calls hipMalloc and keeps
- *     no pointer after fas_grid_destroy.  Its own runtime objects are a 64-byte pinned
- *     host scalar (norm read-back, on first use), HIP events (FAS_OPT_PROFILE and the
- *     FAS_OPT_AUTOTUNE timing), and a private capture stream with the instantiated graph
- *     (FAS_OPT_GRAPH), all released by fas_grid_destroy.
+ *     no pointer after fas_grid_destroy.  Its own runtime objects are a 4 KiB pinned
+ *     host buffer (norm and convergence read-back, on first use), HIP events (the solve
+ *     loop, FAS_OPT_PROFILE and the FAS_OPT_AUTOTUNE timing), and a private capture
+ *     stream with the instantiated graph (FAS_OPT_GRAPH), all released by
+ *     fas_grid_destroy.
  *   - All work is enqueued on the grid's HIP stream (fas_grid_create / fas_set_stream).
  *     Entry points that report a norm or a convergence status synchronise that stream;
  *     the others return as soon as the work is enqueued.
