@@ -3,9 +3,9 @@
 //
 // A block of WV waves holds a whole tile in registers at once: the 128-column window of
 // a strip (one cell pair per lane, x-neighbours by DPP, 112 columns written) and four
-// (FP64) or eight (FP32) consecutive rows per wave.  The pass runs colour phase by colour phase; before each
-// phase every wave trades the top and bottom rows of its band through LDS (one barrier),
-// then updates its cells of that colour.  All loads of a tile are issued together, so
+// (FP64) or eight (FP32) consecutive rows per wave.  The pass runs colour phase by colour
+// phase; before each phase every wave trades the top and bottom rows of its band through
+// LDS (one barrier), then updates its cells of that colour.  All loads of a tile are issued together, so
 // the tile waits on memory once, and the halo rows that neighbouring tiles share are
 // read close together in time from the same XCD's L2.  The wave-strip marches
 // (strip_march.h) instead visit a segment's rows one after another, so their launches
@@ -19,9 +19,10 @@
 //
 // The passes are those of the strips (Alg. 1): pre = nu X-MCGS sweeps, then
 // u_c = R u and r_c = R(f - A u), optionally forming the FAS right-hand side f = r + A u
-// first; post = u += P(u_c - R u), nu sweeps, optionally one sum of r^2 per tile.  The
-// point formulas and their evaluation trees are those of fas_device.h, so every value is
-// bit-identical to the strip and per-phase kernels.
+// first, or summing f^2 per tile (a solve's first pass); post = u += P(u_c - R u), nu
+// sweeps, optionally one sum of r^2 per tile.  The point formulas and their evaluation
+// trees are those of fas_device.h, so every value is bit-identical to the strip and
+// per-phase kernels.
 #include <hip/hip_runtime.h>
 
 #include "fas_device.h"
@@ -68,7 +69,7 @@ struct TileArgs {
     T* uc;               // pre: R u out;  post: new coarse values in
     T* rc;               // pre: R r out
     T* fout;             // pre forming the right-hand side (f then holds r): f = r + A u out
-    double* partials;    // post: one sum of r^2 per tile (nullable)
+    double* partials;    // one sum per tile (nullable): post r^2, pre f^2
     const T* kap;        // cell kappa of the level (single-problem grids), else nullptr
     int batch;           // problems; problem b's arrays start b * stride (b * cstride coarse)
     int64_t stride, cstride;
