@@ -1075,9 +1075,19 @@ int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, vo
         set_kappa(g, nullptr, false);
         memset(&g->stats, 0, sizeof(g->stats));
         fas::launch_init_active(g);
-        fas::launch_resid_norm(g, 0, g->coef[0], nullptr, rhs, nullptr);  // ||rhs||^2 per problem
-        FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, (size_t)g->batch * sizeof(double),
-                                     hipMemcpyDeviceToDevice, g->stream));
+        // ||rhs||^2 per problem: summed by the first cycle's finest tile pre pass (one
+        // partial per tile and problem), else by a pass of its own
+        g->fnorm_pending = fas::tail_top(g) > 0 && fas::tile_ok(g, 0, nu1, nu2, false) &&
+                           (int64_t)fas::tile_count(g, 0, nu1) * g->batch <= g->npartials;
+        struct Pending {
+            fas_grid* g;
+            ~Pending() { g->fnorm_pending = 0; }
+        } pending{g};
+        if (!g->fnorm_pending) {
+            fas::launch_resid_norm(g, 0, g->coef[0], nullptr, rhs, nullptr);
+            FAS_HIP_CHECK(hipMemcpyAsync(g->rnorm, g->norm_out, (size_t)g->batch * sizeof(double),
+                                         hipMemcpyDeviceToDevice, g->stream));
+        }
         ensure_host(g);
         // as the single solve: after a batched solve whose slowest problem took c cycles,
         // cycles 1..c-2 run without a look (a problem that has converged skips them)
