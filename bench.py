@@ -251,6 +251,41 @@ def bench_3d(dev, steps=5, inner=4, cpu=True):
     return out
 
 
+def stream_ceiling(dev, gib=1.0, reps=10):
+    """Attainable HBM bandwidth from the library's own streaming probe (fas_stream_probe):
+    read, copy and triad (c = a + b) over `gib` GiB arrays, 16 B per lane, best of a few
+    grid sizes; GB/s of bytes moved (read 1x, copy 2x, triad 3x the array)."""
+    import ctypes
+
+    import torch
+
+    from paper_2510_11152_amd import _lib
+
+    L = _lib.load()
+    nbytes = int(gib * 2 ** 30)
+    a = torch.full((nbytes // 8,), 1.0, dtype=torch.float64, device=dev)
+    b = torch.full_like(a, 2.0)
+    c = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    out = {"array_gib": gib}
+    for kind, name, moved in ((0, "read", 1), (1, "copy", 2), (2, "triad", 3)):
+        best = None
+        for blocks in (1024, 2048, 4096, 8192):
+            part = torch.empty(blocks, dtype=torch.float64, device=dev)
+            ms = ctypes.c_double(0.0)
+            _lib.check(L.fas_stream_probe(ctypes.c_void_p(stream), kind, nbytes, ctypes.c_void_p(a.data_ptr()),
+                                          ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                          ctypes.c_void_p(part.data_ptr()), blocks, reps, ctypes.byref(ms)),
+                       "fas_stream_probe")
+            gbs = moved * nbytes / (ms.value / 1e3) / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, blocks, ms.value * 1e3)
+        out[name] = {"gbs": best[0], "blocks": best[1], "avg_us": best[2]}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def kernel_bytes(s, d):
     """Algorithmic HBM bytes per finest cell of each finest-level kernel class (values
     in bytes; s = bytes per value, c = 2^d children per coarse cell)."""
@@ -350,6 +385,14 @@ def main():
                       "gbs": (kb[k] * n * n / (v[1] / 1e3 / v[0]) / 1e9) if v[0] and kb[k] else None}
                   for k, v in prof.items()}
 
+    ceiling = stream_ceiling(dev)
+    attain = max(ceiling["copy"]["gbs"], ceiling["triad"]["gbs"])
+    for k, v in per_kernel.items():
+        v["frac_of_peak"] = v["gbs"] / PEAK_HBM_GBS if v["gbs"] else None
+        v["frac_of_attainable"] = v["gbs"] / attain if v["gbs"] else None
+    print("bench: stream ceiling read %.0f copy %.0f triad %.0f GB/s" % (
+        ceiling["read"]["gbs"], ceiling["copy"]["gbs"], ceiling["triad"]["gbs"]), file=sys.stderr, flush=True)
+
     result = {
         "metric": "FAS solve s & HBM GB/s, 8192² heat to 1e-10; mixed/batched vs plain FP64",
         "value": t_plain,
@@ -370,7 +413,8 @@ def main():
         "cycles_per_step": float(np.mean(cycles)),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom, n),
-                     "algorithmic_bytes": kb[dom] * n * n},
+                     "algorithmic_bytes": kb[dom] * n * n, "attainable": attain,
+                     "frac_of_attainable": achieved / attain, "stream_probe": ceiling},
         "kernels": per_kernel,
     }
 

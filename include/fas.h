@@ -218,6 +218,16 @@ int fas_solve_batched(fas_grid_t grid, double dt, double kappa, const void* rhs,
  * of ncells FP32 values each, contiguous, device; stream: hipStream_t. */
 int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f);
 
+/* Measurement helper (not part of the method): the attainable HBM bandwidth the stencil
+ * passes are compared with.  kind 0 reads `bytes` of a (per-block sums into part[0..blocks)),
+ * 1 copies a to c, 2 writes c = a + b (two streams in, one out, like a smoothing pass).
+ * Arrays: device, 16-byte aligned, `bytes` each (a multiple of 16), FP64 contents.
+ * `blocks` workgroups of 256 lanes, 16 bytes per lane per step.  One warm-up launch, then
+ * `reps` launches timed with HIP events on `stream`; *ms_out gets the mean duration.
+ * Synchronises the stream. */
+int fas_stream_probe(void* stream, int kind, int64_t bytes, const void* a, const void* b, void* c, double* part,
+                     int blocks, int reps, double* ms_out);
+
 int fas_get_stats(fas_grid_t grid, fas_stats_t* out);
 /* Accumulated kernel times of a grid with FAS_OPT_PROFILE on (synchronises the stream);
  * reset != 0 clears the counters afterwards. */

@@ -114,10 +114,14 @@ static int og_diag_count(const og_problem* P, int nout)
 /* Mixed precision (the paper is silent): FP64 defect correction
  * around FP32 V-cycles.  Per outer iteration:
  *     r = f - A u (FP64);  rho = ||r||;  stop if rho <= tol*||f||
- *     r32 = fp32(r / rho);  e = 0;  `inner` FP32 V-cycles on A e = r32
- *     u = u + rho * fp64(e)
+ *     r32 = fp32(r);  e = 0;  `inner` FP32 V-cycles on A e = r32
+ *     u = u + fp64(e)
+ * The residual is not rescaled before the cast: FP32 arithmetic is exact under scaling
+ * by a power of two (away from overflow and subnormals), so a power-of-two scale would
+ * give the same bits, and FP32's exponent range holds any residual of interest here.
  * kap0 (nullable) is the FP64 cell coefficient; the FP32 cycle uses fp32(kap0).
  * hist (nullable) needs kmax+1 entries: ||r||/||f|| before each correction and at the end.
+ * tol = 0 runs exactly kmax corrections.
  * Returns 0 converged, 1 not converged; *outer = corrections applied. */
 int og_solve_mixed(const og_problem* P, const double* kap0, const double* f, double* u, double tol, int nu1,
                    int nu2, int inner, int kmax, int* outer, double* hist)
@@ -145,11 +149,11 @@ int og_solve_mixed(const og_problem* P, const double* kap0, const double* f, dou
             break;
         }
         for (long p = 0; p < N; ++p) {
-            r32[p] = (float)(r[p] / rho);
+            r32[p] = (float)r[p];
             e[p] = 0.0f;
         }
         for (int m = 0; m < inner; ++m) og_vcycle_s(P, k32, r32, e, nu1, nu2, 0);
-        for (long p = 0; p < N; ++p) u[p] = u[p] + rho * (double)e[p];
+        for (long p = 0; p < N; ++p) u[p] = u[p] + (double)e[p];
         ++it;
     }
     if (outer) *outer = it;

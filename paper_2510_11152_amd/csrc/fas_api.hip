@@ -364,11 +364,15 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         void* const fout = rc_in ? g->lev[l].f : nullptr;
         // a solve's first pass also sums f^2 (its ||rhs||^2) per tile
         const bool fnorm = tile && l == 0 && g->fnorm_pending;
+        // a defect correction's first inner cycle starts from zero; its last adds the
+        // finest-level result into the FP64 iterate (tile passes on level 0 only)
+        const bool zero = tile && l == 0 && g->zero_start;
+        double* const acc64 = tile && l == 0 ? g->accum64 : nullptr;
         {
             ProfScope ps(g, l, FAS_K_PRE);
             if (tile)
                 fas::launch_tile_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout,
-                                     fnorm ? g->partials : nullptr);
+                                     fnorm ? g->partials : nullptr, zero);
             else
                 fas::launch_fused_pre(g, l, g->coef[l], first, pre, fin, u, x, C.u, rc_dst(g, l, pre, post), fout);
             ps.end();
@@ -381,7 +385,7 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         {
             ProfScope ps(g, l, FAS_K_POST);
             if (tile)
-                fas::launch_tile_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
+                fas::launch_tile_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials, acc64);
             else
                 fas::launch_fused_post(g, l, g->coef[l], first, post, f, x, C.u, u, partials);
             ps.end();
@@ -405,6 +409,15 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
     }
     smooth(g, l, f, u, post, rev);
     return 0;
+}
+
+// Whether a V(pre, post)-cycle of g runs its finest level as tile passes (the passes that
+// can start from zero and add their result into an FP64 array).
+bool finest_is_tile(const fas_grid* g, int pre, int post, bool kv)
+{
+    if (g->fused && fas::tail_top(g) == 0) return false;
+    if (fas::fused3_ok(g, 0, kv) && pre >= 1 && post >= 1) return false;
+    return fas::fused_ok(g, 0, pre, post, kv) && fas::tile_ok(g, 0, pre, post, kv);
 }
 
 // One cycle on the finest level; with want_norm the squared residual norm of the result
@@ -522,6 +535,7 @@ struct GraphCache {
     const void* kap = nullptr;
     double kd0 = 0.0;
     int nu1 = -1, nu2 = -1, batch_active = 0;
+    int nuc = -1;  // coarsest-level sweeps baked into the captured launches
     bool transposed = false, want_norm = false;
     int np = 0;
     void drop()
@@ -532,6 +546,13 @@ struct GraphCache {
         graph = nullptr;
     }
 };
+
+// Drops the captured V-cycle of a grid: called whenever an option that selects kernels,
+// their launch shapes or their arguments changes (a replay would keep the old ones).
+void drop_graph(fas_grid* g)
+{
+    if (g->graph_cache) ((GraphCache*)g->graph_cache)->drop();
+}
 
 void vcycle_top(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool transposed, bool want_norm);
 
@@ -548,7 +569,7 @@ void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
     GraphCache& gc = *(GraphCache*)g->graph_cache;
     const bool same = gc.exec && gc.rhs == f && gc.u == u && gc.kap == g->lev[0].kap && gc.kd0 == g->coef[0].kd &&
                       gc.nu1 == nu1 && gc.nu2 == nu2 && gc.transposed == transposed && gc.want_norm == want_norm &&
-                      gc.batch_active == (fas::active_flags(g) != nullptr);
+                      gc.batch_active == (fas::active_flags(g) != nullptr) && gc.nuc == g->nuc;
     if (!same) {
         // the captured cycle sums its own norm
         struct NoDefer {
@@ -583,6 +604,7 @@ void vcycle_run(fas_grid* g, const void* f, void* u, int nu1, int nu2, bool tran
         gc.transposed = transposed;
         gc.want_norm = want_norm;
         gc.batch_active = fas::active_flags(g) != nullptr;
+        gc.nuc = g->nuc;
     }
     FAS_HIP_CHECK(hipGraphLaunch(gc.exec, g->stream));
 }
@@ -714,6 +736,110 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     return status;
 }
 
+// Mixed precision (FP32 storage and smoothing inside FP64 defect correction).  Evaluation
+// k = 1, 2, ... computes r = f - A u in FP64 with ||r||^2 (and, first, ||f||^2) and
+// r32 = fp32(r); the device tests ||r|| <= tol ||f|| as a solve's cycle does (the same
+// active flag, history and status span).  Unless it has stopped, `inner` FP32 V-cycles
+// solve A e = r32 from e = 0 and u += fp64(e).  On tile levels the first inner cycle's
+// pre pass starts from zero without reading e, and the last inner cycle's post pass adds
+// its result into u itself.  Every kernel, FP32 cycles included, checks the outer active
+// flag, so the host looks at the status only near the expected end, as in solve_impl.
+int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, const void* kcell, const void* rhs,
+                     void* u, double tol, int nu1, int nu2, int inner)
+{
+    check_solve_args(g64, rhs, u, nu1, nu2, tol);
+    check_grid(g32);
+    if (g32->batch > 1) throw Error(FAS_ERR_ARG, "mixed precision takes single-problem grids");
+    if (g64->dtype != FAS_F64 || g32->dtype != FAS_F32 || !(g32->flags & FAS_FLAG_MIXED_INNER))
+        throw Error(FAS_ERR_ARG, "need an FP64 grid and an FP32 grid created with FAS_FLAG_MIXED_INNER");
+    if (g64->dim != g32->dim || g64->bc != g32->bc || g64->h != g32->h || g64->L != g32->L)
+        throw Error(FAS_ERR_ARG, "the two grids must describe the same hierarchy");
+    for (int a = 0; a < 3; ++a)
+        if (g64->n[a] != g32->n[a]) throw Error(FAS_ERR_ARG, "the two grids must have the same shape");
+    if (inner < 1) throw Error(FAS_ERR_ARG, "inner must be >= 1");
+    // the inner grid runs on the outer grid's stream and checks the outer active flag
+    struct InnerScope {
+        fas_grid* g;
+        hipStream_t stream;
+        int* active;
+        ~InnerScope()
+        {
+            g->stream = stream;
+            g->active = active;
+            g->gate = 0;
+            g->zero_start = 0;
+            g->accum64 = nullptr;
+        }
+    } inner_scope{g32, g32->stream, g32->active};
+    g32->stream = g64->stream;
+    set_coefs(g64, dt, kappa, kcell != nullptr);
+    set_kappa(g64, kcell, true, false);
+    set_coefs(g32, dt, kappa, kcell != nullptr);
+    set_kappa(g32, kcell, true);
+    memset(&g64->stats, 0, sizeof(g64->stats));
+    ensure_host(g64);
+    char* const span = (char*)g64->rnorm;
+    const size_t span_bytes = (size_t)((char*)(g64->hist + fas::kHist) - span);
+    if (span_bytes > kHostBytes) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
+    auto host_at = [&](const void* dev) { return (char*)g64->host + ((const char*)dev - span); };
+    while (g64->cyc_ev_created < 2)
+        FAS_HIP_CHECK(hipEventCreateWithFlags(&g64->cyc_ev[g64->cyc_ev_created++], hipEventDisableTiming));
+    fas::launch_init_active(g64);
+    GateScope gate(g64);
+    g32->active = g64->active;
+    g32->gate = 1;
+    const bool tile_top = finest_is_tile(g32, nu1, nu2, kcell != nullptr);
+    const int kmax = std::min(g64->kmax, fas::kHist - 1);  // corrections
+    // after a solve that took c corrections, evaluations 1 .. c are enqueued without a look
+    const int horizon = g64->last_cycles > 0 ? g64->last_cycles : 0;
+    g64->last_cycles = 0;
+    int end = 0;
+    auto look = [&]() -> bool {
+        FAS_HIP_CHECK(hipMemcpyAsync(g64->host, span, span_bytes, hipMemcpyDeviceToHost, g64->stream));
+        FAS_HIP_CHECK(hipEventRecord(g64->cyc_ev[0], g64->stream));
+        FAS_HIP_CHECK(hipEventSynchronize(g64->cyc_ev[0]));
+        if (*(const int*)host_at(g64->count) != 0) return false;
+        end = *(const int*)host_at(g64->cyc);  // evaluation of the stop, -k if not finite
+        return true;
+    };
+    bool stopped = false;
+    for (int k = 1; k <= kmax + 1; ++k) {
+        const int np = fas::launch_mixed_resid(g64, g64->coef[0], g64->lev[0].kap, rhs, u, g32->mix_r, k == 1);
+        if (k == 1) fas::launch_sum_partials(g64, np, g64->rnorm, np);
+        fas::launch_sum_update(g64, np, tol, k);
+        if ((k > horizon || k == kmax + 1) && (stopped = look())) break;
+        if (k == kmax + 1) break;
+        for (int m = 0; m < inner; ++m) {
+            g32->zero_start = m == 0 && tile_top;
+            g32->accum64 = m == inner - 1 && tile_top ? (double*)u : nullptr;
+            if (m == 0 && !tile_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
+            vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
+        }
+        g32->zero_start = 0;
+        g32->accum64 = nullptr;
+        if (!tile_top) fas::launch_update_mixed(g64, g32->mix_e, u);
+    }
+    const double nf = sqrt(*(const double*)host_at(g64->rnorm));
+    const double* hist = (const double*)host_at(g64->hist);
+    const int evals = !stopped ? kmax + 1 : (end < 0 ? -end : end);
+    const int corrections = evals - 1;
+    g64->stats.rhs_norm = nf;
+    for (int i = 0; i < evals && i < 64; ++i) {
+        const double nr = sqrt(hist[i]);
+        g64->stats.rel_res[i] = nf > 0.0 ? nr / nf : nr;
+    }
+    g64->stats.cycles = corrections;
+    if (stopped && end < 0) {
+        g64->stats.status = FAS_ERR_NONFINITE;
+        throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
+    }
+    const int status = stopped ? FAS_OK : FAS_NOT_CONVERGED;
+    g64->stats.status = status;
+    if (status == FAS_OK) g64->last_cycles = corrections;
+    if (status != FAS_OK) g_last_error = "not converged within kmax outer iterations";
+    return status;
+}
+
 int vcycle_impl(fas_grid* g, double dt, double kappa, const void* kcell, const void* rhs, void* u, int nu1, int nu2,
                 double* rel_res, bool transposed)
 {
@@ -730,6 +856,72 @@ int vcycle_impl(fas_grid* g, double dt, double kappa, const void* kcell, const v
         const double nr = read_norm(g);
         *rel_res = nf > 0.0 ? nr / nf : nr;
     }
+    return FAS_OK;
+}
+
+// Fills *g (host memory owned by the caller) with the plan of a grid over `workspace`;
+// allocates nothing.  Returns FAS_OK or an error code with the message set.
+int setup_grid(fas_grid* g, int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, int flags,
+               int batch, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!n) return fail(FAS_ERR_ARG, "null argument");
+    if (!(h > 0.0) || !isfinite(h)) return fail(FAS_ERR_ARG, "h must be positive");
+    if (bc != FAS_BC_NEUMANN && bc != FAS_BC_DIRICHLET && bc != FAS_BC_PERIODIC)
+        return fail(FAS_ERR_ARG, "unknown boundary condition");
+    Layout lay;
+    std::string why;
+    int rc = plan(dim, n, dtype, coarsest, flags, batch, &lay, &why);
+    if (rc) return fail(rc, why);
+    if (bc == FAS_BC_PERIODIC)
+        for (int a = 0; a < dim; ++a)
+            if (lay.n[lay.L][a] & 1) return fail(FAS_ERR_SHAPE, "periodic grids need even sizes on every level");
+    if (!workspace) return fail(FAS_ERR_ARG, "null workspace");
+    if ((uintptr_t)workspace % kAlign) return fail(FAS_ERR_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < lay.total)
+        return fail(FAS_ERR_NOMEM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+    memset(g, 0, sizeof(*g));
+    g->dim = dim;
+    g->bc = bc;
+    g->dtype = dtype;
+    g->coarsest = coarsest;
+    g->flags = flags;
+    g->L = lay.L;
+    g->h = h;
+    for (int a = 0; a < 3; ++a) g->n[a] = a < dim ? n[a] : 1;
+    char* base = (char*)workspace;
+    for (int l = 0; l <= lay.L; ++l) {
+        fas::Level& Lv = g->lev[l];
+        Lv.N = 1;
+        for (int a = 0; a < 3; ++a) {
+            Lv.n[a] = lay.n[l][a];
+            Lv.N *= Lv.n[a];
+        }
+        Lv.h = h * (double)((int64_t)1 << l);
+        Lv.x = base + lay.x[l];
+        Lv.u = l ? base + lay.u[l] : nullptr;
+        Lv.f = l ? base + lay.f[l] : nullptr;
+        Lv.r = lay.r[l] ? base + lay.r[l] : nullptr;
+        Lv.kap_slot = lay.kap[l] ? base + lay.kap[l] : nullptr;
+        Lv.kap = nullptr;
+    }
+    g->mix_e = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_e : nullptr;
+    g->mix_r = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_r : nullptr;
+    g->partials = (double*)(base + lay.partials);
+    g->norm_out = (double*)(base + lay.norm_out);
+    g->npartials = lay.npartials;
+    g->batch = batch;
+    g->rnorm = (double*)(base + lay.rnorm);
+    g->active = (int*)(base + lay.active);
+    g->cyc = (int*)(base + lay.cyc);
+    g->count = (int*)(base + lay.count);
+    g->hist = (double*)(base + lay.hist);
+    g->stream = (hipStream_t)stream;
+    g->kmax = 100;
+    g->nuc = 2;
+    g->fused = 1;
+    g->tile_max = INT64_MAX;
+    g->tile_waves = 0;
+    g->host = nullptr;  // pinned scalar for norm read-back, allocated on first use
     return FAS_OK;
 }
 
@@ -763,64 +955,12 @@ int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int d
     return guarded([&]() -> int {
         if (!out || !n) return fail(FAS_ERR_ARG, "null argument");
         *out = nullptr;
-        if (!(h > 0.0) || !isfinite(h)) return fail(FAS_ERR_ARG, "h must be positive");
-        if (bc != FAS_BC_NEUMANN && bc != FAS_BC_DIRICHLET && bc != FAS_BC_PERIODIC)
-            return fail(FAS_ERR_ARG, "unknown boundary condition");
-        Layout lay;
-        std::string why;
-        int rc = plan(dim, n, dtype, coarsest, flags, batch, &lay, &why);
-        if (rc) return fail(rc, why);
-        if (bc == FAS_BC_PERIODIC)
-            for (int a = 0; a < dim; ++a)
-                if (lay.n[lay.L][a] & 1) return fail(FAS_ERR_SHAPE, "periodic grids need even sizes on every level");
-        if (!workspace) return fail(FAS_ERR_ARG, "null workspace");
-        if ((uintptr_t)workspace % kAlign) return fail(FAS_ERR_ARG, "workspace must be 256-byte aligned");
-        if (ws_bytes < lay.total)
-            return fail(FAS_ERR_NOMEM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
         fas_grid* g = new fas_grid();
-        memset(g, 0, sizeof(*g));
-        g->dim = dim;
-        g->bc = bc;
-        g->dtype = dtype;
-        g->coarsest = coarsest;
-        g->flags = flags;
-        g->L = lay.L;
-        g->h = h;
-        for (int a = 0; a < 3; ++a) g->n[a] = a < dim ? n[a] : 1;
-        char* base = (char*)workspace;
-        for (int l = 0; l <= lay.L; ++l) {
-            fas::Level& Lv = g->lev[l];
-            Lv.N = 1;
-            for (int a = 0; a < 3; ++a) {
-                Lv.n[a] = lay.n[l][a];
-                Lv.N *= Lv.n[a];
-            }
-            Lv.h = h * (double)((int64_t)1 << l);
-            Lv.x = base + lay.x[l];
-            Lv.u = l ? base + lay.u[l] : nullptr;
-            Lv.f = l ? base + lay.f[l] : nullptr;
-            Lv.r = lay.r[l] ? base + lay.r[l] : nullptr;
-            Lv.kap_slot = lay.kap[l] ? base + lay.kap[l] : nullptr;
-            Lv.kap = nullptr;
+        const int rc = setup_grid(g, dim, n, h, bc, dtype, coarsest, flags, batch, workspace, ws_bytes, stream);
+        if (rc) {
+            delete g;
+            return rc;
         }
-        g->mix_e = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_e : nullptr;
-        g->mix_r = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_r : nullptr;
-        g->partials = (double*)(base + lay.partials);
-        g->norm_out = (double*)(base + lay.norm_out);
-        g->npartials = lay.npartials;
-        g->batch = batch;
-        g->rnorm = (double*)(base + lay.rnorm);
-        g->active = (int*)(base + lay.active);
-        g->cyc = (int*)(base + lay.cyc);
-        g->count = (int*)(base + lay.count);
-        g->hist = (double*)(base + lay.hist);
-        g->stream = (hipStream_t)stream;
-        g->kmax = 100;
-        g->nuc = 2;
-        g->fused = 1;
-        g->tile_max = INT64_MAX;
-        g->tile_waves = 0;
-        g->host = nullptr;  // pinned scalar for norm read-back, allocated on first use
         *out = g;
         return FAS_OK;
     });
@@ -848,6 +988,7 @@ int fas_grid_set(fas_grid_t g, int option, double value)
         check_grid(g);
         const int v = (int)value;
         if ((double)v != value) return fail(FAS_ERR_ARG, "option value must be an integer");
+        if (option != FAS_OPT_KMAX && option != FAS_OPT_PROFILE) drop_graph(g);
         switch (option) {
             case FAS_OPT_KMAX:
                 if (v < 1) return fail(FAS_ERR_ARG, "kmax must be >= 1");
@@ -1014,56 +1155,7 @@ int fas_kappa_grad(fas_grid_t g, double dt, const void* kappa_cell, const void* 
 int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, const void* kappa_cell, const void* rhs,
                     void* u, double tol, int nu1, int nu2, int inner)
 {
-    return guarded([&]() -> int {
-        check_solve_args(g64, rhs, u, nu1, nu2, tol);
-        check_grid(g32);
-        if (g32->batch > 1) return fail(FAS_ERR_ARG, "mixed precision takes single-problem grids");
-        if (g64->dtype != FAS_F64 || g32->dtype != FAS_F32 || !(g32->flags & FAS_FLAG_MIXED_INNER))
-            return fail(FAS_ERR_ARG, "need an FP64 grid and an FP32 grid created with FAS_FLAG_MIXED_INNER");
-        if (g64->dim != g32->dim || g64->bc != g32->bc || g64->h != g32->h || g64->L != g32->L)
-            return fail(FAS_ERR_ARG, "the two grids must describe the same hierarchy");
-        for (int a = 0; a < 3; ++a)
-            if (g64->n[a] != g32->n[a]) return fail(FAS_ERR_ARG, "the two grids must have the same shape");
-        if (inner < 1) return fail(FAS_ERR_ARG, "inner must be >= 1");
-        hipStream_t saved = g32->stream;
-        g32->stream = g64->stream;
-        struct Restore {
-            fas_grid* g;
-            hipStream_t s;
-            ~Restore() { g->stream = s; }
-        } restore{g32, saved};
-        set_coefs(g64, dt, kappa, kappa_cell != nullptr);
-        set_kappa(g64, kappa_cell, true, false);
-        set_coefs(g32, dt, kappa, kappa_cell != nullptr);
-        set_kappa(g32, kappa_cell, true);
-        memset(&g64->stats, 0, sizeof(g64->stats));
-        fas::launch_resid_norm(g64, 0, g64->coef[0], g64->lev[0].kap, rhs, nullptr);
-        const double nf = read_norm(g64);
-        g64->stats.rhs_norm = nf;
-        int status, it = 0;
-        for (;;) {
-            fas::launch_resid_norm(g64, 0, g64->coef[0], g64->lev[0].kap, rhs, u);
-            const double rho = read_norm(g64);
-            if (it < 64) g64->stats.rel_res[it] = nf > 0.0 ? rho / nf : rho;
-            if (!isfinite(rho)) throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
-            if (rho <= tol * nf || rho == 0.0) {
-                status = FAS_OK;
-                break;
-            }
-            if (it == g64->kmax) {
-                status = FAS_NOT_CONVERGED;
-                break;
-            }
-            fas::launch_scale_cast(g64, g64->coef[0], g64->lev[0].kap, rhs, u, rho, g32->mix_r, g32->mix_e);
-            for (int m = 0; m < inner; ++m) vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
-            fas::launch_update_mixed(g64, rho, g32->mix_e, u);
-            ++it;
-        }
-        g64->stats.cycles = it;
-        g64->stats.status = status;
-        if (status != FAS_OK) g_last_error = "not converged within kmax outer iterations";
-        return status;
-    });
+    return guarded([&]() -> int { return solve_mixed_impl(g64, g32, dt, kappa, kappa_cell, rhs, u, tol, nu1, nu2, inner); });
 }
 
 int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, void* u, double tol, int nu1, int nu2,

@@ -44,11 +44,15 @@ int strip_waves_per_cu(int nu);
 bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
 int tile_count(const fas_grid* g, int l, int nu);
 // fpartials (nullable, not with fout): one sum of f^2 per tile as well (tile_count(g, l,
-// nu) of them).
+// nu) of them).  zero (FP32, neither fout nor fpartials): the pass starts from u = 0 and
+// does not read u_in.
 void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                     void* u_out, void* uc, void* rc, void* fout = nullptr, double* fpartials = nullptr);
+                     void* u_out, void* uc, void* rc, void* fout = nullptr, double* fpartials = nullptr,
+                     bool zero = false);
+// u64 (FP32 grid, no partials): instead of storing the result in u_out, add it to the FP64
+// array u64 of the level's size (u64 += fp64(u)).
 void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                      const void* uc, void* u_out, double* partials);
+                      const void* uc, void* u_out, double* partials, double* u64 = nullptr);
 
 // 3D plane-march kernels (kernels_fused3d.hip): one sweep per pass.
 bool fused3_ok(const fas_grid* g, int l, bool variable);

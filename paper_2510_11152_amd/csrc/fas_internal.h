@@ -73,8 +73,11 @@ struct fas_grid {
     int defer_norm;      // a cycle leaves its norm partials for the caller to sum ...
     int deferred_np;     // ... and reports how many (0: the norm is already in norm_out)
     double* host;        // pinned host scalars
-    void* mix_e;         // FP32 inner grid: correction e and scaled residual r32 (finest size)
+    void* mix_e;         // FP32 inner grid: correction e and residual r32 (finest size)
     void* mix_r;
+    int zero_start;      // the next finest-level tile pre pass starts from u = 0 (no read)
+    double* accum64;     // non-null: the finest-level tile post pass adds its result into
+                         // this FP64 array instead of storing it (nor the u argument)
     int kmax, nuc, fused;
     fas::Coef coef[fas::kMaxLevels];
     fas_stats_t stats;
@@ -115,8 +118,9 @@ void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, c
 // Partial sums of r^2 (r = f - A u) into g->partials then a fixed-order total into
 // g->norm_out[0]; rhs-only mode (u == nullptr) sums f^2.
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u);
-// Fixed-order total of g->partials[0..count) into out[0] (default g->norm_out).
-void launch_sum_partials(const fas_grid* g, int count, double* out = nullptr);
+// Fixed-order total of g->partials[offset..offset + count) into out[0] (default
+// g->norm_out).
+void launch_sum_partials(const fas_grid* g, int count, double* out = nullptr, int offset = 0);
 void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
                            const void* u, void* uc, void* rc);
 void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc);
@@ -125,10 +129,15 @@ void launch_restrict(const fas_grid* g, int l, const void* fine, void* coarse);
 void launch_prolong_add(const fas_grid* g, int l, const void* cnew, const void* cold, void* fine);
 void launch_kappa_grad(const fas_grid* g, const Coef& c, const void* kap, const void* mu, const void* u,
                        void* gk);
-// Mixed precision: r32 = fp32((f - A u)/rho), e = 0 (FP64 grid g, FP32 outputs).
-void launch_scale_cast(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u,
-                       double rho, void* r32, void* e32);
-void launch_update_mixed(const fas_grid* g, double rho, const void* e32, void* u);
+// Mixed precision, outer step (FP64 grid g, gated by its active flags): r = f - A u,
+// r32 = fp32(r), partial sums of r^2 in g->partials[0..count) and with fnorm of f^2 in
+// g->partials[count..2 count); returns count.
+int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u, void* r32,
+                       bool fnorm);
+// u += fp64(e32) on the finest level of g (gated).
+void launch_update_mixed(const fas_grid* g, const void* e32, void* u);
+// x[0..N) = 0 in FP32 (gated by g's active flags).
+void launch_zero_f32(const fas_grid* g, int64_t N, void* x);
 void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst32);
 // Batched solves: every problem active, cycle counts zero.
 void launch_init_active(const fas_grid* g);

@@ -5,6 +5,7 @@
 // tile kernels replace them on large levels where they apply.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fas_device.h"
@@ -358,30 +359,136 @@ __global__ __launch_bounds__(kBlock) void k_kappa_grad(Op<double> op, const doub
 }
 
 // ----------------------------------------------------------- mixed precision helpers
-template <int DIM, bool KV>
-__global__ __launch_bounds__(kBlock) void k_scale_cast(Op<double> op, const double* __restrict__ f,
-                                                       const double* __restrict__ u, double rho,
-                                                       float* __restrict__ r32, float* __restrict__ e32)
+// Neighbourhood of the even (EVEN) or odd cell of the x-pair (i, i + 1) of row (j, l),
+// constant kappa, from pair loads: the pair itself, the cells left of i and right of
+// i + 1, and the pairs of the rows (and planes) around it.  Values and boundary-face
+// count are those of gather() (a neighbour across a non-periodic boundary is 0, read
+// from an in-range index first).
+template <int DIM>
+struct PairNbhd {
+    double2 c;           // the pair
+    double xl, xr;       // cells i - 1 and i + 2
+    double2 ym, yp, zm, zp;
+    bool uxl, uxr, uym, uyp, uzm, uzp;  // the neighbour is inside (or wrapped)
+};
+
+template <int DIM>
+__device__ __forceinline__ void load_pair_nbhd(const Op<double>& op, const double* __restrict__ u, int i, int j, int l,
+                                               PairNbhd<DIM>& s)
 {
-    const int64_t N = (int64_t)op.n0 * op.n1 * op.n2;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    const int i = (int)(p % op.n0);
-    const int j = (int)((p / op.n0) % op.n1);
-    const int l = (int)(p / ((int64_t)op.n0 * op.n1));
-    Nbhd<double, DIM> s;
-    gather<double, DIM, KV>(op, u, i, j, l, s);
-    const double r = f[p] - apply_value<double, DIM, KV>(op, s, u[p]);
-    r32[p] = (float)(r / rho);
-    e32[p] = 0.0f;
+    const bool per = op.bc == BC_PERIODIC;
+    const int64_t row = cell_index(op.n0, op.n1, 0, j, l);
+    s.c = *reinterpret_cast<const double2*>(u + row + i);
+    s.uxl = per || i > 0;
+    s.uxr = per || i + 2 < op.n0;
+    const int il = i > 0 ? i - 1 : (per ? op.n0 - 1 : i);
+    const int ir = i + 2 < op.n0 ? i + 2 : (per ? 0 : i + 1);
+    s.xl = u[row + il];
+    s.xr = u[row + ir];
+    s.uym = per || j > 0;
+    s.uyp = per || j + 1 < op.n1;
+    const int jm = j > 0 ? j - 1 : (per ? op.n1 - 1 : j);
+    const int jp = j + 1 < op.n1 ? j + 1 : (per ? 0 : j);
+    s.ym = *reinterpret_cast<const double2*>(u + cell_index(op.n0, op.n1, i, jm, l));
+    s.yp = *reinterpret_cast<const double2*>(u + cell_index(op.n0, op.n1, i, jp, l));
+    if constexpr (DIM == 3) {
+        s.uzm = per || l > 0;
+        s.uzp = per || l + 1 < op.n2;
+        const int lm = l > 0 ? l - 1 : (per ? op.n2 - 1 : l);
+        const int lp = l + 1 < op.n2 ? l + 1 : (per ? 0 : l);
+        s.zm = *reinterpret_cast<const double2*>(u + cell_index(op.n0, op.n1, i, j, lm));
+        s.zp = *reinterpret_cast<const double2*>(u + cell_index(op.n0, op.n1, i, j, lp));
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_mixed(int64_t N, double rho, const float* __restrict__ e,
-                                                         double* __restrict__ u)
+template <int DIM, bool EVEN>
+__device__ __forceinline__ void pair_cell(const PairNbhd<DIM>& s, Nbhd<double, DIM>& nb)
 {
+    const double vxm = EVEN ? s.xl : s.c.x, vxp = EVEN ? s.c.y : s.xr;
+    const bool uxm = EVEN ? s.uxl : true, uxp = EVEN ? true : s.uxr;
+    nb.v[0] = uxm ? vxm : 0.0;
+    nb.v[1] = uxp ? vxp : 0.0;
+    nb.v[2] = s.uym ? (EVEN ? s.ym.x : s.ym.y) : 0.0;
+    nb.v[3] = s.uyp ? (EVEN ? s.yp.x : s.yp.y) : 0.0;
+    nb.nout = (uxm ? 0 : 1) + (uxp ? 0 : 1) + (s.uym ? 0 : 1) + (s.uyp ? 0 : 1);
+    if constexpr (DIM == 3) {
+        nb.v[4] = s.uzm ? (EVEN ? s.zm.x : s.zm.y) : 0.0;
+        nb.v[5] = s.uzp ? (EVEN ? s.zp.x : s.zp.y) : 0.0;
+        nb.nout += (s.uzm ? 0 : 1) + (s.uzp ? 0 : 1);
+    }
+}
+
+// Outer step of the mixed-precision defect correction: r = f - A u (FP64), r32 = fp32(r),
+// per-block sums of r^2 into rpart and (fpart != nullptr) of f^2 into fpart.  One thread
+// per x-pair of cells (n0 is even on every grid), grid-stride over a fixed grid so that
+// the partial sums have a fixed count and order.  act: the solve's active flag.
+template <int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_mixed_resid(Op<double> op, const double* __restrict__ f,
+                                                        const double* __restrict__ u, float* __restrict__ r32,
+                                                        double* __restrict__ rpart, double* __restrict__ fpart,
+                                                        const int* __restrict__ act)
+{
+    if (act && !act[0]) return;
+    const int half = op.n0 >> 1;
+    const int64_t pairs = (int64_t)half * op.n1 * op.n2;
+    double acc = 0.0, facc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < pairs; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = 2 * (int)(t % half);
+        const int64_t row = t / half;
+        const int j = (int)(row % op.n1), l = (int)(row / op.n1);
+        const int64_t p = cell_index(op.n0, op.n1, i, j, l);
+        const double2 fp = *reinterpret_cast<const double2*>(f + p);
+        double re, ro;
+        if constexpr (KV) {
+            Nbhd<double, DIM> nb;
+            gather<double, DIM, true>(op, u, i, j, l, nb);
+            re = fp.x - apply_value<double, DIM, true>(op, nb, u[p]);
+            gather<double, DIM, true>(op, u, i + 1, j, l, nb);
+            ro = fp.y - apply_value<double, DIM, true>(op, nb, u[p + 1]);
+        } else {
+            PairNbhd<DIM> s;
+            load_pair_nbhd<DIM>(op, u, i, j, l, s);
+            Nbhd<double, DIM> nb;
+            pair_cell<DIM, true>(s, nb);
+            re = fp.x - apply_value<double, DIM, false>(op, nb, s.c.x);
+            pair_cell<DIM, false>(s, nb);
+            ro = fp.y - apply_value<double, DIM, false>(op, nb, s.c.y);
+        }
+        float2 rv;
+        rv.x = (float)re;
+        rv.y = (float)ro;
+        *reinterpret_cast<float2*>(r32 + p) = rv;
+        acc += re * re;
+        acc += ro * ro;
+        if (fpart) {
+            facc += fp.x * fp.x;
+            facc += fp.y * fp.y;
+        }
+    }
+    block_sum_store(acc, rpart);
+    if (fpart) {
+        __syncthreads();
+        block_sum_store(facc, fpart);
+    }
+}
+
+// u += fp64(e) (the outer update of the defect correction when no inner pass folds it).
+__global__ __launch_bounds__(kBlock) void k_update_mixed(int64_t N, const float* __restrict__ e, double* __restrict__ u,
+                                                         const int* __restrict__ act)
+{
+    if (act && !act[0]) return;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    u[p] = u[p] + rho * (double)e[p];
+    u[p] = u[p] + (double)e[p];
+}
+
+// x = 0 (FP32), gated by a solve's active flag.
+__global__ __launch_bounds__(kBlock) void k_zero_f32(int64_t N, float* __restrict__ x, const int* __restrict__ act)
+{
+    if (act && !act[0]) return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    x[p] = 0.0f;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t N, const double* __restrict__ src,
@@ -543,9 +650,10 @@ void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap,
     launch_sum_partials(g, (int)nb);
 }
 
-void launch_sum_partials(const fas_grid* g, int count, double* out)
+void launch_sum_partials(const fas_grid* g, int count, double* out, int offset)
 {
-    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials, count, out ? out : g->norm_out);
+    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials + offset, count,
+                                                                    out ? out : g->norm_out);
     check_launch();
 }
 
@@ -607,32 +715,43 @@ void launch_kappa_grad(const fas_grid* g, const Coef& c, const void* kap, const 
     check_launch();
 }
 
-void launch_scale_cast(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u, double rho,
-                       void* r32, void* e32)
+int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u, void* r32,
+                       bool fnorm)
 {
     const Op<double> op = make_op<double>(g, 0, c, kap);
-    const unsigned nb = blocks_for(g->lev[0].N);
-    const bool kv = kap != nullptr;
+    const int64_t pairs = g->lev[0].N / 2;
+    // a fixed grid: at most half the partials buffer (the other half takes f^2)
+    unsigned nb = (unsigned)std::min<int64_t>((pairs + kBlock - 1) / kBlock, (int64_t)(g->npartials / 2));
+    if (nb > (unsigned)kPartials) nb = (unsigned)kPartials;
+    const int* act = active_flags(g);
     auto F = (const double*)f;
     auto U = (const double*)u;
+    double* fp = fnorm ? g->partials + nb : nullptr;
+    const bool kv = kap != nullptr;
+#define FAS_MIXED_RESID(D_, KV_) \
+    k_mixed_resid<D_, KV_><<<nb, kBlock, 0, g->stream>>>(op, F, U, (float*)r32, g->partials, fp, act)
     if (g->dim == 2) {
-        if (kv)
-            k_scale_cast<2, true><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
-        else
-            k_scale_cast<2, false><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
+        if (kv) FAS_MIXED_RESID(2, true);
+        else FAS_MIXED_RESID(2, false);
     } else {
-        if (kv)
-            k_scale_cast<3, true><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
-        else
-            k_scale_cast<3, false><<<nb, kBlock, 0, g->stream>>>(op, F, U, rho, (float*)r32, (float*)e32);
+        if (kv) FAS_MIXED_RESID(3, true);
+        else FAS_MIXED_RESID(3, false);
     }
+#undef FAS_MIXED_RESID
+    check_launch();
+    return (int)nb;
+}
+
+void launch_update_mixed(const fas_grid* g, const void* e32, void* u)
+{
+    const int64_t N = g->lev[0].N;
+    k_update_mixed<<<blocks_for(N), kBlock, 0, g->stream>>>(N, (const float*)e32, (double*)u, active_flags(g));
     check_launch();
 }
 
-void launch_update_mixed(const fas_grid* g, double rho, const void* e32, void* u)
+void launch_zero_f32(const fas_grid* g, int64_t N, void* x)
 {
-    const int64_t N = g->lev[0].N;
-    k_update_mixed<<<blocks_for(N), kBlock, 0, g->stream>>>(N, rho, (const float*)e32, (double*)u);
+    k_zero_f32<<<blocks_for(N), kBlock, 0, g->stream>>>(N, (float*)x, active_flags(g));
     check_launch();
 }
 

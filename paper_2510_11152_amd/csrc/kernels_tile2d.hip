@@ -19,8 +19,11 @@
 //
 // The passes are those of the strips (Alg. 1): pre = nu X-MCGS sweeps, then
 // u_c = R u and r_c = R(f - A u), optionally forming the FAS right-hand side f = r + A u
-// first, or summing f^2 per tile (a solve's first pass); post = u += P(u_c - R u), nu
-// sweeps, optionally one sum of r^2 per tile.  The point formulas and their evaluation
+// first, or summing f^2 per tile (a solve's first pass), or starting from u = 0 without
+// reading it (the first inner cycle of a defect correction); post = u += P(u_c - R u), nu
+// sweeps, optionally one sum of r^2 per tile, and in its accumulating form (FP32 only)
+// adding the result into an FP64 array instead of storing it (the last inner cycle of a
+// defect correction: the outer update u64 += fp64(e)).  The point formulas and their evaluation
 // trees are those of fas_device.h, so every value is bit-identical to the strip and
 // per-phase kernels.
 #include <hip/hip_runtime.h>
@@ -70,6 +73,7 @@ struct TileArgs {
     T* rc;               // pre: R r out
     T* fout;             // pre forming the right-hand side (f then holds r): f = r + A u out
     double* partials;    // one sum per tile (nullable): post r^2, pre f^2
+    double* u64;         // accumulating post pass: u64 += fp64(result) on the written cells
     const T* kap;        // cell kappa of the level (single-problem grids), else nullptr
     int batch;           // problems; problem b's arrays start b * stride (b * cstride coarse)
     int64_t stride, cstride;
@@ -99,14 +103,23 @@ size_t tile_lds_bytes(int wv, bool kv)
     return (kv ? 3 : 2) * (size_t)wv * 128 * sizeof(typename Pair<T>::V) + (size_t)wv * sizeof(double);
 }
 
+// Pass kinds: MODE 0 pre, 1 post, 2 accumulating post; IN selects how the pre pass
+// starts: from u_in (IN_U), forming the right-hand side first (IN_RHS) or from zero
+// (IN_ZERO, u_in not read).
+enum { IN_U = 0, IN_RHS = 1, IN_ZERO = 2 };
+
 // One tile of problem b (tile t of per).  XE: the window reaches past a domain x-edge
 // (columns are wrapped, or zero and never updated, and edge cells have their own
 // diagonal counts); the other tiles run without any of that, which keeps the diagonal
 // coefficients in scalar registers.
-template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, int FIRST, bool XE>
+template <typename T, int NU, int MODE, bool NORM, int IN, bool KV, int FIRST, bool XE>
 __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, int per)
 {
     using V = typename Pair<T>::V;
+    constexpr bool RHS = IN == IN_RHS;
+    constexpr bool POST = MODE >= 1;
+    static_assert(IN == IN_U || MODE == 0, "only a pre pass forms f or starts from zero");
+    static_assert(MODE != 2 || sizeof(T) == 4, "the accumulating pass adds FP32 results into FP64");
     constexpr bool RES = MODE == 0 || NORM;  // the pass takes the residual
     constexpr int S = 2 * NU, H = tile_halo(NU, RES), B = rows_per_wave<T>();
     static_assert(NU >= 1 && H <= kTileHX, "halo columns");
@@ -162,7 +175,13 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
         yb[r] = ys[r] || yn[r];
         // uniform row base plus a 32-bit lane offset
         const int64_t row = (int64_t)gl * a.n0;
-        const V zu = *reinterpret_cast<const V*>(u_in + row + (unsigned)gxl);
+        V zu;
+        if constexpr (IN == IN_ZERO) {
+            zu.x = (T)0;
+            zu.y = (T)0;
+        } else {
+            zu = *reinterpret_cast<const V*>(u_in + row + (unsigned)gxl);
+        }
         const V zf = *reinterpret_cast<const V*>(f + row + (unsigned)gxl);
         const bool c = in && xin;  // outside a non-periodic domain: 0, never updated
         ue[r] = c ? zu.x : (T)0;
@@ -174,11 +193,11 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
             ke[r] = c ? zk.x : (T)0;
             ko[r] = c ? zk.y : (T)0;
         }
-        if constexpr (MODE == 1) {
+        if constexpr (POST) {
             if ((r & 1) == 0) cr[r >> 1] = a.uc[b * a.cstride + (int64_t)(gl >> 1) * mc0 + (gxl >> 1)];
         }
     }
-    if constexpr (MODE == 1) {
+    if constexpr (POST) {
         // fine grid correction u += P(u_c - R u) on every 2 x 2 block held (rows 2m, 2m + 1)
 #pragma unroll
         for (int m = 0; m < B / 2; ++m) {
@@ -342,7 +361,14 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
         }
         const int gy = rb + r;
         if (gy >= y0 && gy < yend && own) {
-            store_pair_nt(u_out + (int64_t)gy * a.n0 + gxe, ue[r], uo[r]);
+            if constexpr (MODE == 2) {
+                // u64 += fp64(u) on the written cells (no other tile writes them)
+                double* const q = a.u64 + b * a.stride + (int64_t)gy * a.n0 + gxe;
+                const double2 o = *reinterpret_cast<const double2*>(q);
+                store_pair_nt(q, o.x + (double)ue[r], o.y + (double)uo[r]);
+            } else {
+                store_pair_nt(u_out + (int64_t)gy * a.n0 + gxe, ue[r], uo[r]);
+            }
             if constexpr (MODE == 0) {
                 // rows (r - 1, r) form coarse row gy / 2 when r is odd (y0, yend even)
                 if (r & 1) {
@@ -377,7 +403,7 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
     }
 }
 
-template <typename T, int NU, int MODE, bool NORM, bool RHS, bool KV, int FIRST>
+template <typename T, int NU, int MODE, bool NORM, int IN, bool KV, int FIRST>
 __global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k_tile(TileArgs<T> a)
 {
     // neighbouring tiles, which share halo cells, run on one XCD
@@ -389,9 +415,9 @@ __global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k
     tile_coords(t, a.strips, a.tiles_y, strip, ty);
     const int x0 = strip * kTileCols;
     if (x0 - kTileHX < 0 || x0 - kTileHX + 128 >= a.n0)
-        tile_pass<T, NU, MODE, NORM, RHS, KV, FIRST, true>(a, b, t, per);
+        tile_pass<T, NU, MODE, NORM, IN, KV, FIRST, true>(a, b, t, per);
     else
-        tile_pass<T, NU, MODE, NORM, RHS, KV, FIRST, false>(a, b, t, per);
+        tile_pass<T, NU, MODE, NORM, IN, KV, FIRST, false>(a, b, t, per);
 }
 
 inline void check_launch()
@@ -400,15 +426,15 @@ inline void check_launch()
     if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-template <typename T, int MODE, bool NORM, bool RHS, bool KV>
+template <typename T, int MODE, bool NORM, int IN, bool KV>
 void launch_tile_kv(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int wv)
 {
     const unsigned blocks = (unsigned)((int64_t)a.batch * a.strips * a.tiles_y);
     const unsigned threads = 64u * (unsigned)wv;
     const size_t lds = tile_lds_bytes<T>(wv, KV);
 #define FAS_TILE_LAUNCH(NU_)                                                                     \
-    (first ? k_tile<T, NU_, MODE, NORM, RHS, KV, 1><<<blocks, threads, lds, g->stream>>>(a)      \
-           : k_tile<T, NU_, MODE, NORM, RHS, KV, 0><<<blocks, threads, lds, g->stream>>>(a))
+    (first ? k_tile<T, NU_, MODE, NORM, IN, KV, 1><<<blocks, threads, lds, g->stream>>>(a)       \
+           : k_tile<T, NU_, MODE, NORM, IN, KV, 0><<<blocks, threads, lds, g->stream>>>(a))
     switch (nu) {
         case 1: FAS_TILE_LAUNCH(1); break;
         case 2: FAS_TILE_LAUNCH(2); break;
@@ -419,13 +445,13 @@ void launch_tile_kv(const fas_grid* g, const TileArgs<T>& a, int nu, int first, 
     check_launch();
 }
 
-template <typename T, int MODE, bool NORM, bool RHS>
+template <typename T, int MODE, bool NORM, int IN>
 void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int wv)
 {
     if (a.kap)
-        launch_tile_kv<T, MODE, NORM, RHS, true>(g, a, nu, first, wv);
+        launch_tile_kv<T, MODE, NORM, IN, true>(g, a, nu, first, wv);
     else
-        launch_tile_kv<T, MODE, NORM, RHS, false>(g, a, nu, first, wv);
+        launch_tile_kv<T, MODE, NORM, IN, false>(g, a, nu, first, wv);
 }
 
 int tile_rows_of(const fas_grid* g, int wv, int nu, bool residual)
@@ -478,53 +504,61 @@ int tile_count(const fas_grid* g, int l, int nu)
 }
 
 void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                     void* u_out, void* uc, void* rc, void* fout, double* fpartials)
+                     void* u_out, void* uc, void* rc, void* fout, double* fpartials, bool zero)
 {
     if (fout && fpartials) throw Error(FAS_ERR_ARG, "internal: a pre pass forms f or sums f^2, not both");
+    if (zero && (fout || fpartials || g->dtype != FAS_F32))
+        throw Error(FAS_ERR_ARG, "internal: a zero-start pre pass is an FP32 pass that forms nothing else");
     const int wv = tile_waves(g, l, nu);
     if (g->dtype == FAS_F64) {
         auto a = make_tile_args<double>(g, l, c, nu, wv, true);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.rc = (double*)rc, a.fout = (double*)fout, a.partials = fpartials;
         if (fout)
-            launch_tile<double, 0, false, true>(g, a, nu, first, wv);
+            launch_tile<double, 0, false, IN_RHS>(g, a, nu, first, wv);
         else if (fpartials)
-            launch_tile<double, 0, true, false>(g, a, nu, first, wv);
+            launch_tile<double, 0, true, IN_U>(g, a, nu, first, wv);
         else
-            launch_tile<double, 0, false, false>(g, a, nu, first, wv);
+            launch_tile<double, 0, false, IN_U>(g, a, nu, first, wv);
     } else {
         auto a = make_tile_args<float>(g, l, c, nu, wv, true);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
         a.uc = (float*)uc, a.rc = (float*)rc, a.fout = (float*)fout, a.partials = fpartials;
         if (fout)
-            launch_tile<float, 0, false, true>(g, a, nu, first, wv);
+            launch_tile<float, 0, false, IN_RHS>(g, a, nu, first, wv);
         else if (fpartials)
-            launch_tile<float, 0, true, false>(g, a, nu, first, wv);
+            launch_tile<float, 0, true, IN_U>(g, a, nu, first, wv);
+        else if (zero)
+            launch_tile<float, 0, false, IN_ZERO>(g, a, nu, first, wv);
         else
-            launch_tile<float, 0, false, false>(g, a, nu, first, wv);
+            launch_tile<float, 0, false, IN_U>(g, a, nu, first, wv);
     }
 }
 
 void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
-                      const void* uc, void* u_out, double* partials)
+                      const void* uc, void* u_out, double* partials, double* u64)
 {
+    if (u64 && (partials || g->dtype != FAS_F32))
+        throw Error(FAS_ERR_ARG, "internal: the accumulating post pass is an FP32 pass without a norm");
     const int wv = tile_waves(g, l, nu);
     if (g->dtype == FAS_F64) {
         auto a = make_tile_args<double>(g, l, c, nu, wv, partials != nullptr);
         a.f = (const double*)f, a.u_in = (const double*)u_in, a.u_out = (double*)u_out;
         a.uc = (double*)uc, a.partials = partials;
         if (partials)
-            launch_tile<double, 1, true, false>(g, a, nu, first, wv);
+            launch_tile<double, 1, true, IN_U>(g, a, nu, first, wv);
         else
-            launch_tile<double, 1, false, false>(g, a, nu, first, wv);
+            launch_tile<double, 1, false, IN_U>(g, a, nu, first, wv);
     } else {
         auto a = make_tile_args<float>(g, l, c, nu, wv, partials != nullptr);
         a.f = (const float*)f, a.u_in = (const float*)u_in, a.u_out = (float*)u_out;
-        a.uc = (float*)uc, a.partials = partials;
+        a.uc = (float*)uc, a.partials = partials, a.u64 = u64;
         if (partials)
-            launch_tile<float, 1, true, false>(g, a, nu, first, wv);
+            launch_tile<float, 1, true, IN_U>(g, a, nu, first, wv);
+        else if (u64)
+            launch_tile<float, 2, false, IN_U>(g, a, nu, first, wv);
         else
-            launch_tile<float, 1, false, false>(g, a, nu, first, wv);
+            launch_tile<float, 1, false, IN_U>(g, a, nu, first, wv);
     }
 }
 

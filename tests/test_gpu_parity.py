@@ -1,13 +1,15 @@
 """GPU parity: the HIP library (through the C ABI) against the CPU oracle on the same
 seeded inputs.  Integer-exact structure and identical per-point evaluation trees make
-every iterate bit-identical; only reductions (norms) may differ in the last bits, so
-solve-level comparisons allow the cycle count to differ by one."""
+every iterate bit-identical; only reductions (norms) may differ in the last bits, so a
+solve may stop one cycle away from the oracle's, and is then compared with the oracle
+at its own cycle count (parity_util.check_solve)."""
 import numpy as np
 import pytest
 import torch
 
 import fas_inputs as I
 import oracle as O
+from parity_util import check_mixed, check_solve
 
 pytestmark = pytest.mark.gpu
 
@@ -180,18 +182,14 @@ def test_heat_256_steps_match_oracle():
     g = grid_for(P, np.float64)
     rhs = u0.copy()
     for step in range(3):
-        uo = rhs.copy()
-        st, cyc, hist = O.solve(P, rhs, uo, 1e-10)
         ug = dev(rhs)
         assert g.solve(dev(rhs), ug, P.dt, tol=1e-10) == 0
         s = g.stats()
-        assert abs(s["cycles"] - cyc) <= 1, step
-        if s["cycles"] == cyc:
-            assert np.array_equal(host(ug), uo), step
-        np.testing.assert_allclose(s["rel_res"][: min(cyc, s["cycles"])], hist[: min(cyc, s["cycles"])], rtol=1e-9)
+        got = host(ug)
+        check_solve(P, rhs, rhs, got, s["cycles"], 1e-10, gpu_hist=s["rel_res"][: s["cycles"]])
         nf = float(np.sqrt(np.dot(rhs.ravel(), rhs.ravel())))
         assert abs(s["rhs_norm"] - nf) <= 1e-12 * nf, step
-        rhs = uo
+        rhs = got
 
 
 @pytest.mark.parametrize("n,dtype", [((512, 512), np.float64), ((256, 128), np.float32), ((32, 32, 32), np.float64)])
@@ -223,31 +221,33 @@ def test_solve_after_a_longer_solve_is_unchanged(n, dtype, transposed):
 
 
 @pytest.mark.parametrize("n,coarsest,bc", [((128, 128), 4, "neumann"), ((32, 32, 32), 4, "neumann"),
-                                           ((128, 64), 4, "dirichlet")])
+                                           ((128, 64), 4, "dirichlet"), ((512, 384), 6, "periodic"),
+                                           ((1024, 512), 4, "neumann"), ((64, 64, 64), 4, "dirichlet"),
+                                           ((32, 32), 4, "neumann")])
 @pytest.mark.parametrize("variable", [False, True])
-def test_mixed_precision_matches_oracle(n, coarsest, bc, variable):
-    """FP32 inner cycles inside FP64 defect correction; not bitwise (the outer scaling
-    uses a reduced norm), so compare the converged result with the oracle's mixed
-    solve and with its FP64 solve."""
+@pytest.mark.parametrize("inner", [1, 3])
+def test_mixed_precision_matches_oracle(n, coarsest, bc, variable, inner):
+    """FP32 inner cycles inside FP64 defect correction (tile passes that start from zero
+    and add into the FP64 iterate, 3D plane marches, a grid held entirely by the coarse
+    tail): the corrections equal the oracle's mixed solve bit for bit at equal correction
+    counts, with its residual history, and the result is within 1e-9 of the FP64 solution."""
     P = _problem(n, coarsest, bc, dt=1e-3, kappa=1.0)
     kap = np.exp(0.5 * I.random_field(P.shape(), 7)) if variable else None
-    f = I.cosine_modes(n[0], len(n), 16, np.random.default_rng(1))[tuple(slice(0, m) for m in P.shape())]
-    f = np.ascontiguousarray(f)
-    uo = f.copy()
-    st, outer, hist = O.solve_mixed(P, f, uo, tol=1e-10, inner=2, kap=kap)
-    assert st == 0
+    f = I.cosine_modes(max(n), len(n), 16, np.random.default_rng(1))[tuple(slice(0, m) for m in P.shape())]
+    f = np.ascontiguousarray(f) + 0.01 * I.random_field(P.shape(), 8)
     g64 = grid_for(P, np.float64, variable)
     g32 = grid_for(P, np.float32, variable, mixed=True)
     from paper_2510_11152_amd import solve_mixed
-    ug = dev(f)
-    assert solve_mixed(g64, g32, dev(f), ug, P.dt, P.kappa, None if kap is None else dev(kap), tol=1e-10, inner=2) == 0
-    got = host(ug)
-    assert abs(g64.stats()["cycles"] - outer) <= 1
-    scale = np.abs(uo).max()
-    assert np.abs(got - uo).max() <= 1e-9 * scale
+    kg = None if kap is None else dev(kap)
+    for rep in range(2):  # the second solve runs its first evaluations without a host check
+        ug = dev(f)
+        assert solve_mixed(g64, g32, dev(f), ug, P.dt, P.kappa, kg, tol=1e-10, inner=inner) == 0
+        s = g64.stats()
+        got = host(ug)
+        check_mixed(P, f, f, got, s["cycles"], 1e-10, inner=inner, kap=kap, gpu_hist=s["rel_res"][: s["cycles"] + 1])
     ref = f.copy()
     O.solve(P, f, ref, 1e-13, kap=kap)
-    assert np.abs(got - ref).max() <= 1e-9 * scale
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("n,bc", [((64, 64), "neumann"), ((32, 64), "dirichlet"), ((16, 16, 16), "periodic")])
@@ -313,13 +313,44 @@ def test_graph_and_autotune_give_the_same_bits(n, dtype):
     ref = f.clone()
     g0 = grid_for(P, dtype)
     assert g0.solve(f, ref, P.dt, tol=tol) == 0
+    c0 = g0.stats()["cycles"]
+    check_solve(P, host(f), host(f), host(ref), c0, tol)
     for opts in ({"graph": True}, {"autotune": True}, {"graph": True, "autotune": True}):
         g = grid_for(P, dtype).set(**opts)
         for rep in range(2):  # second solve replays the cached graph
             u = f.clone()
             assert g.solve(f, u, P.dt, tol=tol) == 0
-            if g.stats()["cycles"] == g0.stats()["cycles"]:
-                assert torch.equal(u, ref), opts
+            # the same kernels and partial sums: the same stopping decisions and bits
+            assert g.stats()["cycles"] == c0, (opts, rep)
+            assert torch.equal(u, ref), (opts, rep)
+
+
+@pytest.mark.parametrize("n", [(256, 256), (32, 32, 32)])
+def test_graph_replay_follows_option_changes(n):
+    """A captured cycle is dropped when an option that its launches depend on changes:
+    after set(coarse_sweeps=...) (or a change of the tile shape) a graph-replayed solve
+    equals a fresh grid's solve with the new options, bits and cycles."""
+    P = _problem(n, 4, "neumann", dt=1.0, kappa=1.0)
+    f = dev(I.random_field(P.shape(), 32))
+    g = grid_for(P, np.float64).set(graph=True, kmax=6)
+    u = f.clone()
+    g.solve(f, u, P.dt, tol=1e-9)
+    current = {"graph": True, "kmax": 6, "coarse_sweeps": P.nuc}
+    for opts in ({"coarse_sweeps": 7}, {"coarse_sweeps": 1}, {"tile_waves": 16} if len(n) == 2 else {"fused": False}):
+        g.set(**opts)
+        current.update(opts)
+        fresh = grid_for(P, np.float64).set(**current)
+        ua, ub = f.clone(), f.clone()
+        sa = g.solve(f, ua, P.dt, tol=1e-9)
+        sb = fresh.solve(f, ub, P.dt, tol=1e-9)
+        assert sa == sb and g.stats()["cycles"] == fresh.stats()["cycles"], opts
+        assert torch.equal(ua, ub), opts
+        # and both are the oracle's iterate after that many cycles
+        Pn = _problem(n, 4, "neumann", dt=1.0, kappa=1.0, nuc=current["coarse_sweeps"])
+        ref = host(f)
+        for _ in range(g.stats()["cycles"]):
+            O.vcycle(Pn, host(f), ref, 2, 2)
+        assert np.array_equal(host(ua), ref), opts
 
 
 @pytest.mark.parametrize("n,bc,dtype", [((1024, 512), "neumann", np.float64), ((1024, 512), "periodic", np.float32),
@@ -392,36 +423,87 @@ def test_segment_height_option_is_checked():
     g.set(seg_rows=0)
 
 
+# ---- full sizes, against the oracle --------------------------------------------------------
+# One oracle V-cycle costs about 5 s at 8192^2 and 11 s at 512^3 on one host core, so the
+# benchmark's own sizes are compared with the oracle directly, in the launch shapes the
+# benchmark times (default options).
+
+def _free(*ts):
+    del ts
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("bc", ["neumann", "periodic"])
-@pytest.mark.parametrize("path", ["tile", "march"])
-def test_full_size_8192_fused_equals_phase_kernels(bc, path):
-    """At the benchmark's full size (8192^2 FP64; the default block tiles, as timed, and
-    the row marches with the segment rule's launch shapes) one V-cycle through the fused
-    passes equals the one-phase-per-launch kernels bit for bit; those match the oracle on
-    every smaller case above."""
+def test_full_size_8192_vcycle_matches_oracle(bc):
+    """8192^2 FP64 (the 2D heat benchmark's grid, dt = 1e-4): one V(2,2) cycle through the
+    default block tiles, and through the row marches, equals the oracle's cycle bit for
+    bit on every cell; the cycle's residual norm (per-tile partial sums) agrees to 1e-12."""
     n = 8192
     P = _problem((n, n), 4, bc, dt=1e-4, kappa=1.0, nuc=2)
-    f = dev(I.heat_2d_large(n))
-    ua, ub = f.clone(), f.clone()
-    grid_for(P, np.float64).set(**({} if path == "tile" else {"tile": 0})).vcycle(f, ua, P.dt, nu1=2, nu2=2)
-    grid_for(P, np.float64).set(fused=False).vcycle(f, ub, P.dt, nu1=2, nu2=2)
-    assert torch.equal(ua, ub)
-    del ua, ub, f
+    f = I.heat_2d_large(n)
+    uo = f.copy()
+    O.vcycle(P, f, uo, 2, 2)
+    fg = dev(f)
+    for opts in ({}, {"tile": 0}):
+        ug = fg.clone()
+        rel = grid_for(P, np.float64).set(**opts).vcycle(fg, ug, P.dt, nu1=2, nu2=2, with_residual=True)
+        assert np.array_equal(host(ug), uo), opts
+        del ug
+        torch.cuda.empty_cache()
+    ro = np.linalg.norm(O.residual(P, 0, f, uo)) / np.linalg.norm(f)
+    assert abs(rel - ro) <= 1e-12 * ro
+
+
+def test_full_size_8192_heat_step_matches_oracle():
+    """The first step of the 8192^2 heat benchmark (FP64, dt = 1e-4, Neumann, V(2,2) to
+    1e-10 relative residual): the library's plain solve is the oracle's solve (bit for
+    bit at equal cycle counts, residual history to 1e-12); the mixed-precision solve (3
+    FP32 cycles per correction) is the oracle's mixed solve bit for bit and within 1e-9 of
+    its FP64 solution (max-norm error relative to max|u|)."""
+    from paper_2510_11152_amd import solve_mixed
+    n = 8192
+    P = _problem((n, n), 4, "neumann", dt=1e-4, kappa=1.0, nuc=2)
+    f = I.heat_2d_large(n)
+    uo = f.copy()
+    st, cyc, hist = O.solve(P, f, uo, 1e-10)
+    assert st == 0
+    fg = dev(f)
+    g = grid_for(P, np.float64)
+    ug = fg.clone()
+    assert g.solve(fg, ug, P.dt, tol=1e-10) == 0
+    s = g.stats()
+    check_solve(P, f, f, host(ug), s["cycles"], 1e-10, gpu_hist=s["rel_res"][: s["cycles"]],
+                oracle_result=(cyc, hist, uo))
+    del ug
+    g32 = grid_for(P, np.float32, mixed=True)
+    um = fg.clone()
+    assert solve_mixed(g, g32, fg, um, P.dt, tol=1e-10, inner=3) == 0
+    got = host(um)
+    s = g.stats()
+    check_mixed(P, f, f, got, s["cycles"], 1e-10, inner=3, gpu_hist=s["rel_res"][: s["cycles"] + 1])
+    err = np.abs(got - uo).max() / np.abs(uo).max()
+    print("8192^2 mixed vs FP64 oracle: max rel error %.3e, %d corrections" % (err, s["cycles"]))
+    assert err <= 1e-9
+    del um, fg, g, g32
     torch.cuda.empty_cache()
 
 
-def test_full_size_512cube_march_equals_phase_kernels():
-    """At the 3D benchmark's full size (512^3 FP64, plane-march launch shapes) one V-cycle
-    through the march kernels equals the one-phase-per-launch kernels bit for bit."""
+def test_full_size_512cube_vcycle_matches_oracle():
+    """512^3 FP64 (the 3D heat benchmark, plane-march launch shapes): one V(2,2) cycle
+    equals the oracle's cycle bit for bit on every cell."""
     n = 512
     P = _problem((n, n, n), 4, "neumann", dt=1e-4, kappa=1.0, nuc=2)
-    f = dev(I.heat_3d(n))
-    ua, ub = f.clone(), f.clone()
-    grid_for(P, np.float64).vcycle(f, ua, P.dt, nu1=2, nu2=2)
-    grid_for(P, np.float64).set(fused=False).vcycle(f, ub, P.dt, nu1=2, nu2=2)
-    assert torch.equal(ua, ub)
-    del ua, ub, f
+    f = I.heat_3d(n)
+    uo = f.copy()
+    O.vcycle(P, f, uo, 2, 2)
+    fg = dev(f)
+    ug = fg.clone()
+    rel = grid_for(P, np.float64).vcycle(fg, ug, P.dt, nu1=2, nu2=2, with_residual=True)
+    assert np.array_equal(host(ug), uo)
+    del ug, fg
     torch.cuda.empty_cache()
+    ro = np.linalg.norm(O.residual(P, 0, f, uo)) / np.linalg.norm(f)
+    assert abs(rel - ro) <= 1e-12 * ro
 
 
 def test_full_size_8192_residual_matches_oracle():
@@ -440,18 +522,53 @@ def test_full_size_8192_residual_matches_oracle():
 
 
 @pytest.mark.parametrize("transposed", [False, True])
-@pytest.mark.parametrize("path", ["tile", "march"])
-def test_full_size_2048_cell_kappa_fused_equals_phase_kernels(transposed, path):
-    """At the differentiable workload's size (2048^2 FP64, kappa = exp(g/2) of a smooth
-    cosine field) one plain and one transposed V-cycle through the cell-kappa tiles (as
-    timed) and marches equal the one-phase-per-launch kernels bit for bit."""
+def test_full_size_2048_cell_kappa_vcycle_matches_oracle(transposed):
+    """The differentiable workload's size (2048^2 FP64, kappa = exp(g/2) of a smooth
+    cosine field, harmonic-mean faces): two plain or transposed V(2,2) cycles through the
+    cell-kappa tiles (as timed) and through the marches equal the oracle's bit for bit;
+    a transposed solve to 1e-10 is the oracle's transposed solve."""
     n = 2048
     P = _problem((n, n), 4, "neumann", dt=1e-4, kappa=1.0, nuc=2)
-    kap = dev(I.kappa_field(n))
-    f = dev(I.random_field(P.shape(), 61))
-    ua, ub = f.clone(), f.clone()
-    ga = grid_for(P, np.float64, variable=True).set(**({} if path == "tile" else {"tile": 0}))
-    ga.vcycle(f, ua, P.dt, 1.0, kap, nu1=2, nu2=2, transposed=transposed)
-    grid_for(P, np.float64, variable=True).set(fused=False).vcycle(f, ub, P.dt, 1.0, kap, nu1=2, nu2=2,
-                                                                   transposed=transposed)
-    assert torch.equal(ua, ub)
+    kap = I.kappa_field(n)
+    f = I.random_field(P.shape(), 61)
+    uo = f.copy()
+    for _ in range(2):
+        O.vcycle(P, f, uo, 2, 2, transposed=transposed, kap=kap)
+    fg, kg = dev(f), dev(kap)
+    for opts in ({}, {"tile": 0}):
+        ug = fg.clone()
+        ga = grid_for(P, np.float64, variable=True).set(**opts)
+        for _ in range(2):
+            ga.vcycle(fg, ug, P.dt, 1.0, kg, nu1=2, nu2=2, transposed=transposed)
+        assert np.array_equal(host(ug), uo), opts
+    ug = fg.clone()
+    ga = grid_for(P, np.float64, variable=True)
+    assert ga.solve(fg, ug, P.dt, 1.0, kg, tol=1e-10, transposed=transposed) == 0
+    s = ga.stats()
+    check_solve(P, f, f, host(ug), s["cycles"], 1e-10, transposed=transposed, kap=kap,
+                gpu_hist=s["rel_res"][: s["cycles"]])
+
+
+@pytest.mark.parametrize("where", ["rhs", "u"])
+@pytest.mark.parametrize("form", ["plain", "mixed", "batched"])
+def test_non_finite_input_is_reported(where, form):
+    """A NaN in the right-hand side or the initial guess makes the residual norm NaN; the
+    solve stops with FAS_ERR_NONFINITE (raised as FasError) instead of iterating to kmax."""
+    from paper_2510_11152_amd import Grid, solve_mixed
+    from paper_2510_11152_amd._lib import FAS_ERR_NONFINITE, FasError
+    n = 128
+    P = _problem((n, n), 4, "neumann", dt=1e-3, kappa=1.0)
+    f = I.random_field(P.shape(), 90)
+    u = f.copy()
+    (f if where == "rhs" else u)[17, 33] = np.nan
+    with pytest.raises(FasError) as e:
+        if form == "plain":
+            grid_for(P, np.float64).solve(dev(f), dev(u), P.dt, tol=1e-10)
+        elif form == "mixed":
+            solve_mixed(grid_for(P, np.float64), grid_for(P, np.float32, mixed=True), dev(f), dev(u), P.dt, tol=1e-10)
+        else:
+            gb = Grid((n, n), P.h, batch=3)
+            F = dev(np.stack([I.random_field(P.shape(), 91), f, I.random_field(P.shape(), 92)]))
+            U = dev(np.stack([I.random_field(P.shape(), 93), u, I.random_field(P.shape(), 94)]))
+            gb.solve_batched(F, U, P.dt, tol=1e-10)
+    assert e.value.code == FAS_ERR_NONFINITE
