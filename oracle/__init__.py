@@ -33,7 +33,12 @@ class _OgProblem(ctypes.Structure):
         ("kappa", ctypes.c_double),
         ("coarsest", ctypes.c_int),
         ("nuc", ctypes.c_int),
+        ("order", ctypes.c_int),
+        ("symmetric", ctypes.c_int),
     ]
+
+
+ORDERS = {"x": 0, "u": 1, "z": 2}
 
 
 _lib = None
@@ -83,6 +88,8 @@ class Problem:
     bc: str = "neumann"
     coarsest: int = 4
     nuc: int = 2
+    order: str = "x"          # multi-colour set order of a sweep: "x", "u" or "z" (Section 2.3)
+    symmetric: bool = False   # every second sweep in reverse set order (1234-4321)
     _c: _OgProblem = field(default=None, repr=False, compare=False)
 
     @property
@@ -97,6 +104,7 @@ class Problem:
             p.n[a] = self.n[a] if a < self.dim else 1
         p.h, p.dt, p.kappa = float(self.h), float(self.dt), float(self.kappa)
         p.coarsest, p.nuc = int(self.coarsest), int(self.nuc)
+        p.order, p.symmetric = ORDERS[self.order], int(bool(self.symmetric))
         return p
 
     def shape(self, lev=0):

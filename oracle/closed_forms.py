@@ -171,3 +171,27 @@ def rb_gauss_seidel_dense(A, b, x, first_odd_1based=True, shape=None):
     out = np.empty(N)
     out[order] = xn
     return out.reshape(x.shape)
+
+
+def set_gauss_seidel_dense(A, b, x, sets, shape):
+    """One Gauss-Seidel sweep on the dense system with unknowns ordered set by set (each
+    set lexicographic): x <- (D+L)^{-1}(b - U x) under that permutation.  sets: parity
+    tuples of 1-based indices in (x, y[, z]) order, 'o' odd / 'e' even."""
+    grids = np.indices(shape) + 1  # 1-based indices, axes (z,) y, x
+    dim = len(shape)
+    order = []
+    for s in sets:
+        sel = np.ones(shape, dtype=bool)
+        for a in range(dim):
+            idx = grids[dim - 1 - a]  # axis a (x first) is the last array axis
+            sel &= (idx % 2 == 1) == (s[a] == "o")
+        order.append(np.nonzero(sel.ravel())[0])
+    order = np.concatenate(order)
+    assert len(order) == A.shape[0]
+    Ap = A[np.ix_(order, order)]
+    DL = np.tril(Ap)
+    U = Ap - DL
+    xn = np.linalg.solve(DL, b.ravel()[order] - U @ x.ravel()[order])
+    out = np.empty(A.shape[0])
+    out[order] = xn
+    return out.reshape(x.shape)

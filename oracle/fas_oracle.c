@@ -33,7 +33,41 @@ typedef struct {
     double kappa;  /* constant diffusivity, used when no cell field is given */
     int coarsest;  /* cells along the shortest axis of the coarsest level */
     int nuc;       /* sweeps on the coarsest level (Remark 1: smoothing, no direct solve) */
+    int order;     /* multi-colour set order of a sweep: OG_X (default), OG_U or OG_Z */
+    int symmetric; /* 1: every second sweep visits the sets in reverse (1234-4321) */
 } og_problem;
+
+#define OG_X 0
+#define OG_U 1
+#define OG_Z 2
+
+/* Set orders of one sweep (Section 2.3 and its figure of the three partitions; Appendix B
+ * for 3D).  A set is the cells whose 1-based index along each axis has a fixed parity; it
+ * is written as a bit mask, bit a set when the index along axis a (x, y, z) is odd.
+ *   X (2D): (o,e) (e,o) (e,e) (o,o)           -- Section 2.3, the paper's sets 1-4
+ *   U (2D): (o,o) (e,o) (e,e) (o,e)           -- the U-shaped path through the parity square
+ *   Z (2D): (o,o) (o,e) (e,o) (e,e)           -- the Z-shaped (row by row) path
+ *   X (3D): (o,e,e) (e,o,e) (e,e,o) (o,o,o) (o,e,o) (e,o,o) (e,e,e) (o,o,e)  -- Appendix B
+ *   U (3D): the reflected Gray-code path that extends the 2D U (x flips first)
+ *   Z (3D): the lexicographic path that extends the 2D Z (z fastest)
+ * The paper draws the 2D partitions only; the 3D U and Z paths are this oracle's reading. */
+static const int og_sets2[3][4] = {{1, 2, 0, 3}, {3, 2, 0, 1}, {3, 1, 2, 0}};
+static const int og_sets3[3][8] = {{1, 2, 4, 7, 5, 6, 0, 3}, {7, 6, 4, 5, 1, 0, 2, 3}, {7, 3, 5, 1, 6, 2, 4, 0}};
+
+static const int* og_set_order(const og_problem* P)
+{
+    int o = (P->order >= 0 && P->order <= 2) ? P->order : 0;
+    return P->dim == 2 ? og_sets2[o] : og_sets3[o];
+}
+
+/* Whether 0-based cell (i,j,l) is in set `mask` (a 1-based odd index is 0-based even). */
+static int og_in_set(int dim, int mask, long i, long j, long l)
+{
+    const long c[3] = {i, j, l};
+    for (int a = 0; a < dim; ++a)
+        if (((c[a] & 1) == 0) != ((mask >> a) & 1)) return 0;
+    return 1;
+}
 
 static long og_index(const long m[3], long i, long j, long l) { return i + m[0] * (j + m[1] * l); }
 

@@ -116,16 +116,48 @@ static REAL F(gs_point)(const og_problem* P, const long m[3], long i, long j, lo
     return (f[p] + k * Sw) / ((REAL)1 + k * Wt);
 }
 
-/* Smoother S (Section 2.3 and Appendix A/B): one sweep first updates the cells whose
- * 1-based index sum is odd (X-MCGS sets 1-2 in 2D, sets 1-4 in 3D), then the others
- * (sets 3-4 / 5-8), each phase visited lexicographically.  With 0-based indices the
+/* Smoother S (Section 2.3 and Appendix A/B), X order: one sweep first updates the cells
+ * whose 1-based index sum is odd (X-MCGS sets 1-2 in 2D, sets 1-4 in 3D), then the others
+ * (sets 3-4 / 5-8), each phase visited lexicographically.  Other set orders, and the
+ * symmetric sequence, go through smooth_sets.  With 0-based indices the
  * first phase is the odd-sum cells in 2D and the even-sum cells in 3D.  reverse != 0
  * runs the two phases in the opposite order, the transpose of the forward sweep. */
+/* Multi-colour sweeps through the 2^d index-parity sets in the order of P->order: each
+ * set in turn, its cells lexicographically (no two cells of a set are neighbours, so
+ * their order does not matter); with P->symmetric every second sweep takes the sets in
+ * reverse (the 1234-4321 sequence of Section 2.3), and reverse != 0 reverses every
+ * sweep once more (the transpose). */
+static void F(smooth_sets)(const og_problem* P, int lev, const REAL* kap, const REAL* f, REAL* u, int sweeps,
+                           int reverse)
+{
+    long m[3];
+    REAL k, q[16];
+    og_level_dims(P, lev, m);
+    F(level_coeffs)(P, lev, kap != 0, &k, q);
+    const int* order = og_set_order(P);
+    const int nsets = 1 << P->dim;
+    for (int s = 0; s < sweeps; ++s) {
+        int rev = (P->symmetric && (s & 1)) != (reverse != 0);
+        for (int t = 0; t < nsets; ++t) {
+            int mask = order[rev ? nsets - 1 - t : t];
+            for (long l = 0; l < m[2]; ++l)
+                for (long j = 0; j < m[1]; ++j)
+                    for (long i = 0; i < m[0]; ++i)
+                        if (og_in_set(P->dim, mask, i, j, l))
+                            u[og_index(m, i, j, l)] = F(gs_point)(P, m, i, j, l, u, f, kap, k, q);
+        }
+    }
+}
+
 void F(og_smooth)(const og_problem* P, int lev, const REAL* kap, const REAL* f, REAL* u, int sweeps,
                   int reverse)
 {
     long m[3];
     REAL k, q[16];
+    if (P->order != OG_X || P->symmetric) {
+        F(smooth_sets)(P, lev, kap, f, u, sweeps, reverse);
+        return;
+    }
     og_level_dims(P, lev, m);
     F(level_coeffs)(P, lev, kap != 0, &k, q);
     for (int s = 0; s < sweeps; ++s) {

@@ -93,6 +93,79 @@ def test_z_order_differs_from_x_order():
     assert not np.array_equal(a, b)
 
 
+# ---------------------------------------------------------------- set orders (U, Z, 1234-4321)
+# The orders as parity tuples of 1-based indices, x first (Section 2.3's figure in 2D; the
+# 3D U and Z paths extend them: Gray code with x flipping first, lexicographic with z fastest).
+SET_ORDERS = {
+    ("x", 2): [("o", "e"), ("e", "o"), ("e", "e"), ("o", "o")],
+    ("u", 2): [("o", "o"), ("e", "o"), ("e", "e"), ("o", "e")],
+    ("z", 2): [("o", "o"), ("o", "e"), ("e", "o"), ("e", "e")],
+    ("x", 3): [("o", "e", "e"), ("e", "o", "e"), ("e", "e", "o"), ("o", "o", "o"), ("o", "e", "o"), ("e", "o", "o"),
+               ("e", "e", "e"), ("o", "o", "e")],
+    ("u", 3): [("o", "o", "o"), ("e", "o", "o"), ("e", "e", "o"), ("o", "e", "o"), ("o", "e", "e"), ("e", "e", "e"),
+               ("e", "o", "e"), ("o", "o", "e")],
+    ("z", 3): [("o", "o", "o"), ("o", "o", "e"), ("o", "e", "o"), ("o", "e", "e"), ("e", "o", "o"), ("e", "o", "e"),
+               ("e", "e", "o"), ("e", "e", "e")],
+}
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("n", [(16, 16), (32, 8), (8, 8, 8), (16, 8, 4)])
+@pytest.mark.parametrize("order", ["x", "u", "z"])
+@pytest.mark.parametrize("symmetric", [False, True])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_set_order_sweeps_match_literal_sets(bc, n, order, symmetric, dtype):
+    """The oracle's set-ordered sweeps equal the literal strided set updates of the same
+    order, bit for bit; with the symmetric sequence every second sweep runs the sets in
+    reverse (one 1234-4321 step = a forward then a backward sweep)."""
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.5, kappa=1.0, bc=bc, coarsest=2, order=order, symmetric=symmetric)
+    sets = SET_ORDERS[(order, len(n))]
+    f = I.random_field(P.shape(), 14).astype(dtype)
+    a = I.random_field(P.shape(), 16).astype(dtype)
+    b = a.copy()
+    for s in range(3):
+        C.xmcgs_sweep_literal(P, 0, f, a, sets=sets[::-1] if symmetric and s % 2 else sets)
+    O.smooth(P, 0, f, b, 3)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("n", [(8, 8), (6, 4), (4, 4, 4)])
+@pytest.mark.parametrize("order", ["u", "z"])
+@pytest.mark.parametrize("variable", [False, True])
+def test_set_order_sweep_is_dense_gauss_seidel(bc, n, order, variable):
+    """One U- or Z-ordered sweep is Gauss-Seidel on the assembled matrix with the unknowns
+    permuted set by set: (D+L)^{-1}(b - U x)."""
+    P = O.Problem(n=n, h=1.0 / n[0], dt=0.7, kappa=1.3, bc=bc, coarsest=2, order=order)
+    kap = _kap(P.shape(), 5) if variable else None
+    f = I.random_field(P.shape(), 7)
+    u = I.random_field(P.shape(), 8)
+    ref = C.set_gauss_seidel_dense(C.assemble_dense(P, kap), f, u, SET_ORDERS[(order, len(n))], P.shape())
+    O.smooth(P, 0, f, u, 1, kap=kap)
+    np.testing.assert_allclose(u, ref, rtol=1e-13, atol=1e-14)
+
+
+def test_ordering_study_x_converges_fastest():
+    """Section 2.3's ordering study in the paper's setting (p - Lap p = f, Dirichlet,
+    coarsest 2^2, two sweeps per smoothing step) at 256^2: the X order with 1234-1234
+    needs the fewest V-cycles to 1e-9, and U and Z need markedly more (the paper reports
+    about 2x and 3x at 2048^2)."""
+    n = 256
+    f = I.random_field((n, n), 21)
+    counts = {}
+    for order in ("x", "u", "z"):
+        for sym in (False, True):
+            P = O.Problem(n=(n, n), h=1.0 / n, dt=1.0, kappa=1.0, bc="dirichlet", coarsest=2, nuc=2, order=order,
+                          symmetric=sym)
+            u = np.zeros_like(f)
+            st, c, _ = O.solve(P, f, u, 1e-9, kmax=200)
+            assert st == 0
+            counts[(order, sym)] = c
+    assert counts[("x", False)] == min(counts.values()), counts
+    assert counts[("u", False)] >= 1.5 * counts[("x", False)], counts
+    assert counts[("z", False)] >= 2.0 * counts[("x", False)], counts
+
+
 # ---------------------------------------------------------------- transfer operators
 @pytest.mark.parametrize("n", [(8, 8), (8, 4, 4)])
 def test_restrict_prolong_identities(n):
