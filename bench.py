@@ -68,7 +68,7 @@ def parse():
                     help="FP32 V-cycles per outer correction (3D mixed form; 4 reaches 1e-10 in two corrections)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="batched,adjoint,3d",
+    ap.add_argument("--forms", default="batched,adjoint,3d,orders",
                     help="other workloads timed after the headline (comma list; 'none' to skip)")
     return ap.parse_args()
 
@@ -83,7 +83,7 @@ def _timed(fn, sync):
 
 def bench_batched(dev):
     """Uneven batch of 64 2D Neumann heat solves (sizes drawn from 128^2..2048^2, FP64,
-    dt = 1e-4, tol 1e-10): one batched solve per size against looping single solves;
+    dt = 1e-4, tol 1e-10): one array-form batched solve against looping single solves;
     then one grain-growth step of 1189 fields on 512^2 (periodic, h = 1, dt = 0.1, FP32,
     tol 1e-6): right-hand side + one batched solve."""
     import numpy as np
@@ -101,27 +101,34 @@ def bench_batched(dev):
         if m not in grids:
             grids[m] = Grid((m, m), 1.0 / m, coarsest=4, device=dev)
 
+    ul = [r.clone() for r in rhs]
+
     def looped():
         cyc = []
-        for r in rhs:
-            u = r.clone()
+        for r, u in zip(rhs, ul):
+            u.copy_(r)
             g = grids[r.shape[0]]
             g.solve(r, u, 1e-4, tol=1e-10)
             cyc.append(g.stats()["cycles"])
         return cyc
 
-    # one batched solve per size group, grids planned once, V-cycles captured in HIP graphs
-    # and segment heights autotuned on the first solve
-    ub = UnevenBatch([tuple(r.shape) for r in rhs], device=dev, graph=True, autotune=True)
+    # all 64 problems in one fas_solve_batched call (one launch per pass over every
+    # problem), grids planned once; the iterates live in fixed buffers, so the launch
+    # descriptors written by the first solve are reused
+    ub = UnevenBatch([tuple(r.shape) for r in rhs], device=dev)
+    us = [r.clone() for r in rhs]
 
     def batched():
-        us = [r.clone() for r in rhs]
+        for u, r in zip(us, rhs):
+            u.copy_(r)
         return ub.solve(rhs, us, 1e-4, tol=1e-10)
 
     looped()
     batched()
     t_loop, cyc_loop = _timed(looped, sync)
     t_batch, (st, cyc_b) = _timed(batched, sync)
+    if list(cyc_b) != list(cyc_loop):
+        raise RuntimeError("batched and looped solves ran different cycle counts")
     out = {"uneven": {"problems": len(rhs), "cells": int(sum(r.numel() for r in rhs)),
                       "sizes": sorted(set(int(r.shape[0]) for r in rhs)),
                       "batched_s": t_batch, "looped_s": t_loop, "speedup": t_loop / t_batch,
@@ -136,6 +143,44 @@ def bench_batched(dev):
     out["grain"] = {"fields": q, "grid": [n, n], "s_per_step": t_grain / steps,
                     "field_cells_per_s": q * n * n * steps / t_grain, "cycles_per_field": float(np.mean(cys[-1]))}
     del eta, model
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_orders(dev, sizes=(1024, 2048)):
+    """The smoother-ordering study of Section 2.3 in its setting: p - Lap p = f on [0,1]^2
+    with Dirichlet boundaries, f from the exact solution prod sin(pi sin(pi x)), a zero
+    initial guess, V(2,2) cycles down to 2^2 (meshLevel = log2 n - 1), two sweeps on the
+    coarsest level, kMax = 100, stop when the paper's res = h ||f - A p||_2 < 1e-9.  X, U
+    and Z set orders, each with the 1234-1234 and 1234-4321 sequences; cycles and time."""
+    import torch
+
+    import fas_inputs
+    from paper_2510_11152_amd import Grid
+
+    out = {}
+    for n in sizes:
+        h = 1.0 / n
+        f_h, _ = fas_inputs.paper_sine_problem(n)
+        f = torch.from_numpy(f_h).to(dev)
+        tol = 1e-9 / (h * float(torch.linalg.vector_norm(f)))  # res = h ||r|| as a relative tolerance
+        g = Grid((n, n), h, bc="dirichlet", coarsest=2, device=dev).set(coarse_sweeps=2, kmax=100)
+        row = {}
+        for order in ("x", "u", "z"):
+            for sym in (False, True):
+                g.set(order=order, symmetric=sym)
+                u = torch.zeros_like(f)
+                g.solve(f, u, 1.0, tol=tol)  # warm-up (and the cycle count the timed solve reuses)
+                u.zero_()
+                t, st = _timed(lambda: g.solve(f, u, 1.0, tol=tol), torch.cuda.synchronize)
+                s = g.stats()
+                row[order.upper() + (" 1234-4321" if sym else " 1234-1234")] = {
+                    "cycles": s["cycles"], "converged": st == 0, "s": t,
+                    "res": h * s["rel_res"][s["cycles"] - 1] * float(torch.linalg.vector_norm(f))}
+        x = row["X 1234-1234"]["cycles"]
+        out["%d^2" % n] = {"configs": row,
+                           "cycles_vs_x": {k: v["cycles"] / x for k, v in row.items()}}
+        del g, f
     torch.cuda.empty_cache()
     return out
 
@@ -454,6 +499,9 @@ def main():
     if "adjoint" in forms:
         print("bench: adjoint form", file=sys.stderr, flush=True)
         result["adjoint"] = bench_adjoint(dev)
+    if "orders" in forms:
+        print("bench: smoother ordering study", file=sys.stderr, flush=True)
+        result["orders"] = bench_orders(dev)
     if "3d" in forms:
         print("bench: 3D heat", file=sys.stderr, flush=True)
         result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline)

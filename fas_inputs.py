@@ -88,3 +88,23 @@ def uneven_batch(seed=7, count=64, choices=(128, 256, 512, 1024, 2048)):
 def random_field(shape, seed, lo=-1.0, hi=1.0):
     """Uniform random field for unit tests."""
     return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+def paper_sine_problem(n, dim=2):
+    """The paper's convergence-test problem on [0,1]^dim (Section 3.1): exact solution
+    p = prod_axes sin(pi sin(pi x_axis)) on the cell centres and the continuous source
+    f = p - Lap p of p - Lap p = f (dt = kappa = 1).  Returns (f, p)."""
+    x = centres(n)
+    s = np.sin(np.pi * x)
+    g = np.sin(np.pi * s)
+    # d^2/dx^2 sin(pi sin(pi x)) = -pi^3 sin(pi x) cos(pi s) - pi^4 cos(pi x)^2 sin(pi s)
+    g2 = -np.pi ** 3 * s * np.cos(np.pi * s) - np.pi ** 4 * np.cos(np.pi * x) ** 2 * g
+    if dim == 2:
+        p = np.outer(g, g)
+        lap = np.outer(g, g2) + np.outer(g2, g)
+    else:
+        p = g[:, None, None] * g[None, :, None] * g[None, None, :]
+        lap = (g2[:, None, None] * g[None, :, None] * g[None, None, :]
+               + g[:, None, None] * g2[None, :, None] * g[None, None, :]
+               + g[:, None, None] * g[None, :, None] * g2[None, None, :])
+    return p - lap, p

@@ -79,9 +79,12 @@ extern "C" {
 #define FAS_OPT_GRAPH 5         /* 1: capture each V-cycle in a HIP graph (replayed while the
                                    arrays, coefficients and sweep counts stay the same);
                                    0 (default): launch kernels one by one                 */
-#define FAS_OPT_AUTOTUNE 6      /* 1: on a level's first fused pass, time the candidate
-                                   segment heights of the march kernels and keep the
-                                   fastest (cached per process); 0 (default): fixed rule   */
+#define FAS_OPT_AUTOTUNE 6      /* 1: on a level's first fused pass, time the candidates
+                                   and keep the fastest (cached per process): for block
+                                   tiles the waves per block (6, 8, 12, 16; cell kappa 6,
+                                   8) and the strips per group of the tile order (4, 8,
+                                   16, 32), for row marches the segment height;
+                                   0 (default): fixed rules                               */
 #define FAS_OPT_SEG_ROWS 7       /* > 0 (even, >= 8): rows (2D) / planes (3D) per segment of
                                    every march launch, overriding rule and autotuner;
                                    0 (default): rule or autotuner                         */
@@ -92,6 +95,24 @@ extern "C" {
 #define FAS_OPT_TILE_WAVES 9     /* 6..16: waves per tile workgroup (rows written per tile
                                    4 * waves - 4 nu - 4 in FP64, 8 * waves - 4 nu - 4 in
                                    FP32; cell kappa: at most 8); 0 (default): 8           */
+#define FAS_OPT_ORDER 10         /* set order of every smoothing sweep (Section 2.3): FAS_ORDER_X
+                                   (default; the paper's sets 1-4, Appendix B's sets 1-8 in
+                                   3D), FAS_ORDER_U or FAS_ORDER_Z.  Orders other than X, and
+                                   the symmetric sequence, run one launch per index-parity set
+                                   (no fused passes)                                       */
+#define FAS_OPT_SYMMETRIC 11     /* 1: every second sweep of a smoothing step visits the sets
+                                   in reverse order (the 1234-4321 sequence of Section 2.3);
+                                   0 (default): every sweep in order (1234-1234)          */
+
+/* FAS_OPT_ORDER values.  A set is written by the parities of its cells' 1-based indices
+ * along x, y (, z), o = odd, e = even:
+ *   X: 2D oe eo ee oo;  3D oee eoe eeo ooo oeo eoo eee ooe (Appendix B, sets 1-8)
+ *   U: 2D oo eo ee oe;  3D ooo eoo eeo oeo oee eee eoe ooe (Gray-code path, x first)
+ *   Z: 2D oo oe eo ee;  3D ooo ooe oeo oee eoo eoe eeo eee (lexicographic, z fastest)
+ * The paper draws the 2D U and Z partitions only; the 3D U and Z paths extend them. */
+#define FAS_ORDER_X 0
+#define FAS_ORDER_U 1
+#define FAS_ORDER_Z 2
 
 /* kernel classes reported by fas_get_profile */
 #define FAS_K_SMOOTH 0 /* stand-alone smoothing launches on the finest level              */
@@ -180,9 +201,15 @@ int fas_prolong_add(fas_grid_t grid, int level, const void* c_new, const void* c
 int fas_kappa_grad(fas_grid_t grid, double dt, const void* kappa_cell, const void* mu, const void* u,
                    void* gkappa);
 
-/* Mixed precision (FP32 storage and smoothing inside FP64 defect correction):
+/* Mixed precision (FP32 storage and smoothing inside FP64 defect correction; the paper is
+ * silent on precision beyond FP64):
  *   loop: r = rhs - A u (FP64); rho = ||r||_2; stop if rho <= tol*||rhs||_2;
- *         r32 = fp32(r/rho); e = 0; `inner` FP32 V-cycles on A e = r32; u += rho*fp64(e)
+ *         r32 = fp32(r); e = 0; `inner` FP32 V-cycles on A e = r32; u += fp64(e)
+ * (r is not divided by rho before the cast: FP32 arithmetic is exact under power-of-two
+ * scaling away from overflow and subnormals, so such a scale changes no bit, and a
+ * norm-valued one would only round once more).  One FP64 pass per correction forms r,
+ * its norm partial sums and r32; the stopping test runs on the device; the first inner
+ * cycle starts from e = 0 without reading it and the last adds e into u in its final pass.
  * g64: FP64 grid; g32: FP32 grid of the same shape, bc and h, created with
  * FAS_FLAG_MIXED_INNER (and FAS_FLAG_VARIABLE_KAPPA for a cell field, which is given in
  * FP64 and rounded to FP32 for the inner cycle).  Stats on g64 count outer corrections. */
@@ -206,9 +233,36 @@ int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int d
                             int batch, void* workspace, size_t ws_bytes, void* stream, fas_grid_t* out);
 /* status_out / cycles_out (nullable, batch entries each): per-problem status and
  * V-cycles.  Returns FAS_OK if all converged, else FAS_NOT_CONVERGED or
- * FAS_ERR_NONFINITE.  Synchronises the stream once per cycle (one int). */
-int fas_solve_batched(fas_grid_t grid, double dt, double kappa, const void* rhs, void* u, double tol, int nu1,
+ * FAS_ERR_NONFINITE.  The host waits on the stream near the expected end, as fas_solve. */
+int fas_solve_stacked(fas_grid_t grid, double dt, double kappa, const void* rhs, void* u, double tol, int nu1,
                       int nu2, int* status_out, int* cycles_out);
+
+/* Coefficient of one problem of an array-form batch: cell == NULL selects the constant
+ * kappa = scalar, else cell is the finest-level cell field (grid dtype). */
+typedef struct {
+    double scalar;
+    const void* cell;
+} fas_kappa_t;
+
+/* Array-form batched solve (the paper solves its grain-growth fields one after the other;
+ * here independent problems advance together): problem p solves A_p u[p] = rhs[p] on its
+ * own grid grids[p] (any sizes, spacings and boundary conditions; one dtype; kappa[p]
+ * constant for every problem or a cell field for every problem) to
+ * ||rhs_p - A_p u_p|| <= tol ||rhs_p||, each with the stopping test of fas_solve and at
+ * most grids[0]'s FAS_OPT_KMAX cycles.  Every pass of a V-cycle is one launch over all
+ * problems still iterating at that pass: a block finds its problem from the launch's
+ * block ranges and reads that problem's arrays and coefficients from a descriptor in the
+ * problem's own workspace (written when the arrays or coefficients change).  So each
+ * problem's iterates, norms and cycle count equal those of fas_solve on its own grid.
+ * This needs 2D grids whose levels above the coarse tail all take the tile passes
+ * (1 <= nu1, nu2 <= 3; the default options) and one tile shape (FAS_OPT_TILE_WAVES) for
+ * all; otherwise the problems are solved one after another with fas_solve.  All work is
+ * enqueued on grids[0]'s stream; grids must be distinct; rhs[p] and u[p] must not alias.
+ * status_out (nullable, nprob entries) gets each problem's status, fas_get_stats of grid
+ * p its cycles, ||rhs|| and relative residuals.  Returns FAS_OK when all converged, else
+ * FAS_NOT_CONVERGED or FAS_ERR_NONFINITE. */
+int fas_solve_batched(int nprob, const fas_grid_t* grids, double dt, const fas_kappa_t* kappa, const void* const* rhs,
+                      void* const* u, double tol, int nu1, int nu2, int* status_out);
 
 /* Right-hand side of one semi-implicit step of the multi-order-parameter grain-growth
  * model (Section 3.3.1, eq. grain-growth-equations with L = alpha = beta = gamma = 1):
@@ -217,6 +271,12 @@ int fas_solve_batched(fas_grid_t grid, double dt, double kappa, const void* rhs,
  * and (I - dt kappa Lap) eta_i^{n+1} = f_i is then one batched solve.  eta, f: q fields
  * of ncells FP32 values each, contiguous, device; stream: hipStream_t. */
 int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f);
+
+/* Grain map of a grain-growth state (Section 3.3.1: a grain is a region where one order
+ * parameter dominates): label[p] = the index i of the largest eta_i at cell p, the lowest
+ * index among equal values.  eta: q fields of ncells FP32 values, contiguous; label:
+ * ncells int32; device; stream: hipStream_t. */
+int fas_grain_argmax(void* stream, int q, int64_t ncells, const void* eta, void* label);
 
 /* Measurement helper (not part of the method): the attainable HBM bandwidth the stencil
  * passes are compared with.  kind 0 reads `bytes` of a (per-block sums into part[0..blocks)),

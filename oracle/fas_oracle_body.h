@@ -116,12 +116,6 @@ static REAL F(gs_point)(const og_problem* P, const long m[3], long i, long j, lo
     return (f[p] + k * Sw) / ((REAL)1 + k * Wt);
 }
 
-/* Smoother S (Section 2.3 and Appendix A/B), X order: one sweep first updates the cells
- * whose 1-based index sum is odd (X-MCGS sets 1-2 in 2D, sets 1-4 in 3D), then the others
- * (sets 3-4 / 5-8), each phase visited lexicographically.  Other set orders, and the
- * symmetric sequence, go through smooth_sets.  With 0-based indices the
- * first phase is the odd-sum cells in 2D and the even-sum cells in 3D.  reverse != 0
- * runs the two phases in the opposite order, the transpose of the forward sweep. */
 /* Multi-colour sweeps through the 2^d index-parity sets in the order of P->order: each
  * set in turn, its cells lexicographically (no two cells of a set are neighbours, so
  * their order does not matter); with P->symmetric every second sweep takes the sets in
@@ -149,6 +143,12 @@ static void F(smooth_sets)(const og_problem* P, int lev, const REAL* kap, const 
     }
 }
 
+/* Smoother S (Section 2.3 and Appendix A/B), X order: one sweep first updates the cells
+ * whose 1-based index sum is odd (X-MCGS sets 1-2 in 2D, sets 1-4 in 3D), then the others
+ * (sets 3-4 / 5-8), each phase visited lexicographically.  Other set orders, and the
+ * symmetric sequence, go through smooth_sets.  With 0-based indices the
+ * first phase is the odd-sum cells in 2D and the even-sum cells in 3D.  reverse != 0
+ * runs the two phases in the opposite order, the transpose of the forward sweep. */
 void F(og_smooth)(const og_problem* P, int lev, const REAL* kap, const REAL* f, REAL* u, int sweeps,
                   int reverse)
 {

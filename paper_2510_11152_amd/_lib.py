@@ -24,6 +24,8 @@ FAS_FLAG_MIXED_INNER = 2
 FAS_OPT_KMAX, FAS_OPT_COARSE_SWEEPS, FAS_OPT_FUSED, FAS_OPT_PROFILE = 1, 2, 3, 4
 FAS_OPT_GRAPH, FAS_OPT_AUTOTUNE, FAS_OPT_SEG_ROWS = 5, 6, 7
 FAS_OPT_TILE, FAS_OPT_TILE_WAVES = 8, 9
+FAS_OPT_ORDER, FAS_OPT_SYMMETRIC = 10, 11
+FAS_ORDER = {"x": 0, "u": 1, "z": 2}
 FAS_K_NAMES = ("smooth", "pre", "post", "norm")
 
 # Every function the header declares, with (restype, argtypes).
@@ -35,6 +37,10 @@ _pd = ctypes.POINTER(ctypes.c_double)
 class FasStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("status", ctypes.c_int), ("rhs_norm", ctypes.c_double),
                 ("rel_res", ctypes.c_double * 64)]
+
+
+class FasKappa(ctypes.Structure):
+    _fields_ = [("scalar", ctypes.c_double), ("cell", ctypes.c_void_p)]
 
 
 class FasProfile(ctypes.Structure):
@@ -61,8 +67,10 @@ SIGNATURES = {
     "fas_solve_mixed": (_i, [_vp, _vp, _d, _d, _vp, _vp, _vp, _d, _i, _i, _i]),
     "fas_workspace_size_batched": (_sz, [_i, _pi64, _i, _i, _i, _i]),
     "fas_grid_create_batched": (_i, [_i, _pi64, _d, _i, _i, _i, _i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
-    "fas_solve_batched": (_i, [_vp, _d, _d, _vp, _vp, _d, _i, _i, _vp, _vp]),
+    "fas_solve_stacked": (_i, [_vp, _d, _d, _vp, _vp, _d, _i, _i, _vp, _vp]),
+    "fas_solve_batched": (_i, [_i, _vp, _d, ctypes.POINTER(FasKappa), _vp, _vp, _d, _i, _i, _vp]),
     "fas_grain_rhs": (_i, [_vp, _i, _i64, _d, _vp, _vp]),
+    "fas_grain_argmax": (_i, [_vp, _i, _i64, _vp, _vp]),
     "fas_stream_probe": (_i, [_vp, _i, _i64, _vp, _vp, _vp, _vp, _i, _i, _pd]),
     "fas_get_stats": (_i, [_vp, ctypes.POINTER(FasStats)]),
     "fas_get_profile": (_i, [_vp, ctypes.POINTER(FasProfile), _i]),

@@ -67,7 +67,9 @@ class Grid:
         return tuple(m >> level for m in reversed(self.n))
 
     def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None,
-            seg_rows=None, tile=None, tile_waves=None):
+            seg_rows=None, tile=None, tile_waves=None, order=None, symmetric=None):
+        """Solver options (fas_grid_set).  order: smoother set order 'x' (default), 'u' or
+        'z'; symmetric: every second sweep in reverse set order (1234-4321)."""
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -87,6 +89,10 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_TILE, float(tile)), "fas_grid_set")
         if tile_waves is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_TILE_WAVES, float(tile_waves)), "fas_grid_set")
+        if order is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_ORDER, float(_lib.FAS_ORDER[order])), "fas_grid_set")
+        if symmetric is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_SYMMETRIC, float(int(symmetric))), "fas_grid_set")
         return self
 
     def profile(self, reset=True):
@@ -152,18 +158,18 @@ class Grid:
         check(load().fas_kappa_grad(self.handle, dt, _ptr(kappa_cell), _ptr(mu), _ptr(u), _ptr(gkappa)),
               "fas_kappa_grad")
 
-    def solve_batched(self, rhs, u, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2):
-        """All `batch` problems at once; rhs, u shaped (batch, *shape).  Returns
-        (status per problem, V-cycles per problem) as lists."""
+    def solve_stacked(self, rhs, u, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2):
+        """All `batch` problems of a stacked grid at once; rhs, u shaped (batch, *shape).
+        Returns (status per problem, V-cycles per problem) as lists."""
         want = (self.batch,) + self.shape()
         for t, nm in ((rhs, "rhs"), (u, "u")):
             if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != want:
                 raise ValueError("%s must be a contiguous %s tensor of shape %s on %s" % (nm, self.dtype, want, self.device))
         st = (ctypes.c_int * self.batch)()
         cy = (ctypes.c_int * self.batch)()
-        code = load().fas_solve_batched(self.handle, dt, kappa, _ptr(rhs), _ptr(u), tol, nu1, nu2, st, cy)
+        code = load().fas_solve_stacked(self.handle, dt, kappa, _ptr(rhs), _ptr(u), tol, nu1, nu2, st, cy)
         if code not in (_lib.FAS_OK, _lib.FAS_NOT_CONVERGED):
-            check(code, "fas_solve_batched")
+            check(code, "fas_solve_stacked")
         return list(st), list(cy)
 
     def stats(self):
@@ -197,55 +203,53 @@ def heat(grid, u0, steps, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=
     return (u, states) if keep else u
 
 
-class UnevenBatch:
-    """Problems of different sizes on the unit square (h = 1/n), solved as one batched
-    solve per distinct shape.  The grids of the groups are planned once, so repeated
-    solves reuse their workspaces and, with graph=True / autotune=True, their captured
-    V-cycles and tuned segment heights."""
+def solve_batched(grids, rhs_list, u_list, dt, kappa=1.0, kappa_cells=None, tol=1e-10, nu1=2, nu2=2):
+    """Problem p solves A_p u_list[p] = rhs_list[p] on grids[p], all advanced together by
+    fas_solve_batched (one launch per pass over every problem).  kappa: one constant or
+    one per problem; kappa_cells: None or one cell field per problem.  u_list entries
+    are updated in place.  Returns the per-problem status list (fas_get_stats of each
+    grid gives its cycles)."""
+    m = len(grids)
+    if len(rhs_list) != m or len(u_list) != m:
+        raise ValueError("expected %d right-hand sides and iterates" % m)
+    kap = list(kappa) if isinstance(kappa, (list, tuple)) else [kappa] * m
+    cells = list(kappa_cells) if kappa_cells is not None else [None] * m
+    if len(kap) != m or len(cells) != m:
+        raise ValueError("expected one kappa per problem")
+    for g, r, u, c in zip(grids, rhs_list, u_list, cells):
+        g._arr(r, name="rhs"), g._arr(u, name="u"), g._arr(c, name="kappa_cell")
+    K = (_lib.FasKappa * m)(*[_lib.FasKappa(float(k), _ptr(c)) for k, c in zip(kap, cells)])
+    G = (ctypes.c_void_p * m)(*[g.handle for g in grids])
+    R = (ctypes.c_void_p * m)(*[r.data_ptr() for r in rhs_list])
+    U = (ctypes.c_void_p * m)(*[u.data_ptr() for u in u_list])
+    st = (ctypes.c_int * m)()
+    code = load().fas_solve_batched(m, G, dt, K, R, U, tol, nu1, nu2, st)
+    if code not in (_lib.FAS_OK, _lib.FAS_NOT_CONVERGED):
+        check(code, "fas_solve_batched")
+    return list(st)
 
-    def __init__(self, shapes, dtype=torch.float64, coarsest=4, bc="neumann", device="cuda", graph=False,
-                 autotune=False):
-        self.groups = {}
-        for i, shp in enumerate(shapes):
-            self.groups.setdefault(tuple(shp), []).append(i)
-        self.grids = {}
-        self.stacks = {}
-        for shp, idx in self.groups.items():
-            n = tuple(reversed(shp))
-            g = Grid(n, 1.0 / n[0], bc=bc, dtype=dtype, coarsest=coarsest, device=device, batch=len(idx))
-            self.grids[shp] = g.set(graph=graph, autotune=autotune)
-            # the stacked right-hand sides and iterates of the group (fixed addresses, so a
-            # captured cycle stays valid from one solve to the next)
-            self.stacks[shp] = (torch.empty((len(idx),) + shp, dtype=dtype, device=device),
-                                torch.empty((len(idx),) + shp, dtype=dtype, device=device))
-        self.count = len(shapes)
+
+class UnevenBatch:
+    """Problems of different sizes on the unit square (h = 1/n), one grid each, solved
+    together by one fas_solve_batched call.  The grids are planned once, so repeated
+    solves reuse their workspaces and launch descriptors."""
+
+    def __init__(self, shapes, dtype=torch.float64, coarsest=4, bc="neumann", device="cuda"):
+        self.shapes = [tuple(s) for s in shapes]
+        self.grids = [Grid(tuple(reversed(s)), 1.0 / s[-1], bc=bc, dtype=dtype, coarsest=coarsest, device=device)
+                      for s in self.shapes]
 
     def solve(self, rhs_list, u_list, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2):
         """u_list entries are updated in place; returns per-problem (status, V-cycles)
         lists in input order."""
-        if len(rhs_list) != self.count or len(u_list) != self.count:
-            raise ValueError("expected %d problems" % self.count)
-        status = [None] * self.count
-        cycles = [None] * self.count
-        for shp, idx in self.groups.items():
-            R, U = self.stacks[shp]
-            for k, i in enumerate(idx):
-                r, u = rhs_list[i], u_list[i]
-                if tuple(r.shape) != shp or tuple(u.shape) != shp:
-                    raise ValueError("problem %d does not have shape %s" % (i, shp))
-                R[k].copy_(r)
-                U[k].copy_(u)
-            st, cy = self.grids[shp].solve_batched(R, U, dt, kappa, tol, nu1, nu2)
-            for k, i in enumerate(idx):
-                u_list[i].copy_(U[k])
-                status[i], cycles[i] = st[k], cy[k]
-        return status, cycles
+        status = solve_batched(self.grids, rhs_list, u_list, dt, kappa, None, tol, nu1, nu2)
+        return status, [g.stats()["cycles"] for g in self.grids]
 
 
 def solve_uneven(rhs_list, u_list, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2, coarsest=4, bc="neumann"):
-    """Problems of different sizes on the unit square (h = 1/n): one batched solve per
-    distinct shape (a one-shot UnevenBatch).  u_list entries are updated in place.
-    Returns per-problem (status, V-cycles) lists in input order."""
+    """Problems of different sizes on the unit square (h = 1/n), solved together (a
+    one-shot UnevenBatch).  u_list entries are updated in place.  Returns per-problem
+    (status, V-cycles) lists in input order."""
     for i, (r, u) in enumerate(zip(rhs_list, u_list)):
         if r.shape != u.shape or r.dtype != u.dtype:
             raise ValueError("rhs and u of problem %d differ in shape or dtype" % i)

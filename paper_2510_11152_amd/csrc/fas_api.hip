@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "fas_batch.h"
 #include "fas_fused.h"
 #include "fas_tail.h"
 #include "fas_internal.h"
@@ -54,7 +55,7 @@ struct Layout {
     int L;
     int n[fas::kMaxLevels][3];
     size_t x[fas::kMaxLevels], u[fas::kMaxLevels], f[fas::kMaxLevels], r[fas::kMaxLevels], kap[fas::kMaxLevels];
-    size_t mix_e, mix_r, partials, norm_out, active, cyc, rnorm, count, hist, total;
+    size_t mix_e, mix_r, partials, fpartials, norm_out, active, cyc, rnorm, count, hist, desc, total;
     int npartials;
 };
 
@@ -135,6 +136,8 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
     lay->npartials = (int)(per * batch);
     lay->partials = off;
     off = align_up(off + (size_t)lay->npartials * sizeof(double));
+    lay->fpartials = off;  // ||rhs||^2 partial sums of an array-form batched solve
+    off = align_up(off + (size_t)lay->npartials * sizeof(double));
     lay->norm_out = off;
     off = align_up(off + (size_t)(batch + 8) * sizeof(double));
     lay->rnorm = off;
@@ -147,6 +150,8 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
     off = align_up(off + 8 * sizeof(int));
     lay->hist = off;  // after rnorm, active, cyc and count: one span for a single problem
     off = align_up(off + fas::kHist * sizeof(double));
+    lay->desc = off;  // launch descriptors of an array-form batched solve
+    off = align_up(off + fas::kDescBytes);
     lay->total = off;
     return 0;
 }
@@ -246,16 +251,67 @@ struct ProfScope {
     }
 };
 
-void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse)
+// Set orders of one sweep (Section 2.3 and its figure of the X, U and Z partitions; the
+// 3D X order is the sets 1-8 of Appendix B).  A set is written by the parities of its
+// cells' 1-based indices along x, y (, z): 'o' odd, 'e' even.  The paper draws only the
+// 2D U and Z partitions; in 3D, U is read as the Gray-code path that extends the 2D U
+// (x flips first) and Z as the lexicographic path that extends the 2D Z (z fastest).
+const char* const kSetOrders[2][3] = {
+    {"oe eo ee oo", "oo eo ee oe", "oo oe eo ee"},
+    {"oee eoe eeo ooo oeo eoo eee ooe", "ooo eoo eeo oeo oee eee eoe ooe", "ooo ooe oeo oee eoo eoe eeo eee"},
+};
+
+// The sets of g's order as masks for launch_smooth_set (bit a: odd 1-based index along
+// axis a); returns their number, 2^dim.
+int set_masks(const fas_grid* g, int masks[8])
 {
+    const char* s = kSetOrders[g->dim - 2][g->order];
+    int n = 0;
+    while (*s) {
+        int m = 0;
+        for (int a = 0; a < g->dim; ++a, ++s) m |= (*s == 'o' ? 1 : 0) << a;
+        masks[n++] = m;
+        if (*s == ' ') ++s;
+    }
+    return n;
+}
+
+// Whether every sweep of g reduces to two colours: the X sets 1-2 (1-4 in 3D) are exactly
+// the cells with an odd 1-based index sum and no two of them are neighbours, so the X
+// order is red-black Gauss-Seidel with that colour first, which the fused kernels run.
+bool two_colour(const fas_grid* g) { return g->order == FAS_ORDER_X && !g->symmetric; }
+
+// `sweeps` smoothing sweeps of level l with cell field kap (nullptr: constant kappa).
+// reverse runs every sweep backwards (the transpose of the forward sweep); with the
+// symmetric sequence every second sweep is reversed as well.
+void smooth_kap(fas_grid* g, int l, const void* kap, const void* f, void* u, int sweeps, bool reverse)
+{
+    if (!two_colour(g)) {
+        int masks[8];
+        const int ns = set_masks(g, masks);
+        for (int s = 0; s < sweeps; ++s) {
+            const bool rev = (g->symmetric && (s & 1)) != reverse;
+            for (int t = 0; t < ns; ++t) {
+                ProfScope ps(g, l, FAS_K_SMOOTH);
+                fas::launch_smooth_set(g, l, g->coef[l], kap, f, u, masks[rev ? ns - 1 - t : t]);
+                ps.end();
+            }
+        }
+        return;
+    }
     const int first = (g->dim + 1) & 1;
     for (int s = 0; s < sweeps; ++s)
         for (int ph = 0; ph < 2; ++ph) {
             const int parity = ((ph == 0) != reverse) ? first : 1 - first;
             ProfScope ps(g, l, FAS_K_SMOOTH);
-            fas::launch_smooth_phase(g, l, g->coef[l], g->lev[l].kap, f, u, parity);
+            fas::launch_smooth_phase(g, l, g->coef[l], kap, f, u, parity);
             ps.end();
         }
+}
+
+void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse)
+{
+    smooth_kap(g, l, g->lev[l].kap, f, u, sweeps, reverse);
 }
 
 // FAS V-cycle below level l (Alg. 1 with the coarse steps replaced by recursion).
@@ -265,6 +321,9 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 // forms f itself.
 void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
                     const void* rc_in = nullptr);
+
+void autotune_tile(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
+                   const void* rc_in);
 
 // Whether coarse level lc forms its FAS right-hand side inside its first march pass (2D
 // strips or 3D planes); the finer level then leaves R(f - A u) in lev[lc].r (the pass
@@ -356,7 +415,10 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         void* x = g->lev[l].x;
         // block tiles on the smaller levels, row marches on the larger ones
         const bool tile = fas::tile_ok(g, l, pre, post, g->lev[l].kap != nullptr);
-        if (!tile) autotune_level(g, l, first, pre, post, f, u, rc_in);
+        if (tile)
+            autotune_tile(g, l, first, pre, post, f, u, rc_in);
+        else
+            autotune_level(g, l, first, pre, post, f, u, rc_in);
         const int np = tile ? fas::tile_count(g, l, post) : fas::fused_tiles(g, l, post);
         if (partials && np > g->npartials / g->batch) partials = nullptr;
         // rc_in: f = rc_in + A u, formed and written by the pre pass
@@ -522,6 +584,71 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
     }
 }
 
+// ---- autotuner: tile shape of the 2D block-tile passes ------------------------------------
+// On a level's first tile pass, times the pre pass (out of place: running it again
+// recomputes the same outputs) for every pair of waves per block and strips per group of
+// the tile order, and keeps the fastest, per grid and per process (keyed by level shape,
+// dtype, batch, sweeps, coefficient kind and pass form).  The values a pass computes do
+// not depend on the shape; only the grouping of the per-tile norm sums does.
+void autotune_tile(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
+                   const void* rc_in)
+{
+    if (!g->autotune || g->tile_waves || g->tile_wv[l]) return;
+    const bool kv = g->lev[l].kap != nullptr;
+    char key[160];
+    snprintf(key, sizeof key, "tile:%d:%d:%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->dtype,
+             g->batch, pre, post, kv ? 1 : 0, rc_in ? 1 : 0);
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            g->tile_wv[l] = it->second >> 8;
+            g->tile_grp[l] = it->second & 255;
+            return;
+        }
+    }
+    hipEvent_t e0, e1;
+    FAS_HIP_CHECK(hipEventCreate(&e0));
+    FAS_HIP_CHECK(hipEventCreate(&e1));
+    fas::Level& C = g->lev[l + 1];
+    const void* fin = rc_in ? rc_in : f;
+    void* const fout = rc_in ? g->lev[l].f : nullptr;
+    float best = 1e30f;
+    int best_wv = 8, best_grp = 16;
+    const int cap = g->npartials / g->batch;
+    for (int wv : fas::kTileWaveChoices) {
+        if (kv && wv > 8) continue;
+        const int cp = fas::tile_count_with(g, l, pre, wv), cq = fas::tile_count_with(g, l, post, wv);
+        if (cp < 1 || cq < 1 || cp > cap || cq > cap) continue;
+        for (int grp : fas::kTileGroupChoices) {
+            g->tile_wv[l] = wv;
+            g->tile_grp[l] = grp;
+            float total = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {
+                FAS_HIP_CHECK(hipEventRecord(e0, g->stream));
+                fas::launch_tile_pre(g, l, g->coef[l], first, pre, fin, u, g->lev[l].x, C.u, rc_dst(g, l, pre, post),
+                                     fout);
+                FAS_HIP_CHECK(hipEventRecord(e1, g->stream));
+                FAS_HIP_CHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                FAS_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep) total += ms;  // the first launch warms caches
+            }
+            if (total < best) {
+                best = total;
+                best_wv = wv;
+                best_grp = grp;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->tile_wv[l] = best_wv;
+    g->tile_grp[l] = best_grp;
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    tune_cache()[key] = (best_wv << 8) | best_grp;
+}
+
 // ---- HIP graph of one V-cycle ------------------------------------------------------------
 // Captured on a private stream (the caller's may be the legacy default stream, which
 // cannot be captured) and replayed on the grid's stream; valid while the arrays,
@@ -626,7 +753,8 @@ struct GateScope {
     ~GateScope() { g->gate = 0; }
 };
 
-constexpr size_t kHostBytes = 4096;  // pinned host buffer of a grid
+constexpr size_t kHostStatus = 4096;                          // status read-back
+constexpr size_t kHostBytes = kHostStatus + fas::kDescBytes;  // + descriptors of a batched solve
 
 void ensure_host(fas_grid* g)
 {
@@ -651,7 +779,7 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
     // status span: rnorm, active, cyc, count, hist (one problem) in workspace order
     char* const span = (char*)g->rnorm;
     const size_t span_bytes = (size_t)((char*)(g->hist + fas::kHist) - span);
-    if (span_bytes > kHostBytes) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
+    if (span_bytes > kHostStatus) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
     auto host_at = [&](const void* dev) { return (char*)g->host + ((const char*)dev - span); };
     fas::launch_init_active(g);
     // ||f||^2: summed by the first cycle's finest tile pre pass, which reads f anyway
@@ -780,7 +908,7 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
     ensure_host(g64);
     char* const span = (char*)g64->rnorm;
     const size_t span_bytes = (size_t)((char*)(g64->hist + fas::kHist) - span);
-    if (span_bytes > kHostBytes) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
+    if (span_bytes > kHostStatus) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
     auto host_at = [&](const void* dev) { return (char*)g64->host + ((const char*)dev - span); };
     while (g64->cyc_ev_created < 2)
         FAS_HIP_CHECK(hipEventCreateWithFlags(&g64->cyc_ev[g64->cyc_ev_created++], hipEventDisableTiming));
@@ -907,6 +1035,8 @@ int setup_grid(fas_grid* g, int dim, const int64_t n[3], double h, int bc, int d
     g->mix_e = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_e : nullptr;
     g->mix_r = (flags & FAS_FLAG_MIXED_INNER) ? base + lay.mix_r : nullptr;
     g->partials = (double*)(base + lay.partials);
+    g->fpartials = (double*)(base + lay.fpartials);
+    g->desc = base + lay.desc;
     g->norm_out = (double*)(base + lay.norm_out);
     g->npartials = lay.npartials;
     g->batch = batch;
@@ -919,10 +1049,279 @@ int setup_grid(fas_grid* g, int dim, const int64_t n[3], double h, int bc, int d
     g->kmax = 100;
     g->nuc = 2;
     g->fused = 1;
+    g->fused_opt = 1;
+    g->order = FAS_ORDER_X;
+    g->symmetric = 0;
     g->tile_max = INT64_MAX;
     g->tile_waves = 0;
     g->host = nullptr;  // pinned scalar for norm read-back, allocated on first use
     return FAS_OK;
+}
+
+// ---- array-form batched solve ------------------------------------------------------------
+// Problems of any sizes, each on its own grid, advanced together: per V-cycle, the pre
+// passes from the tallest hierarchy's finest level down (one table launch per height,
+// serving every problem with a tile level at that height: height = levels below), the
+// tails (one workgroup per problem), the post passes back up, then the norm totals and
+// stopping tests of all problems in one launch.  Every problem's passes are those of its
+// single solve with the same arguments, so its iterates, norms and cycle count are the
+// single solve's.
+
+// Whether problem grid g takes the table path: 2D, two-colour fused passes, a tile pass
+// (1..3 sweeps) on every level above its tail, and the tile partial sums in its buffers.
+bool table_ok(const fas_grid* g, int nu1, int nu2, bool kv)
+{
+    if (g->dim != 2 || g->batch != 1 || !g->fused) return false;
+    const int T = fas::tail_top(g);
+    if (T < 1 || T > g->L) return false;
+    for (int l = 0; l < T; ++l)
+        if (!fas::tile_ok(g, l, nu1, nu2, kv)) return false;
+    return fas::tile_count(g, 0, nu1) <= g->npartials && fas::tile_count(g, 0, nu2) <= g->npartials;
+}
+
+struct TableProblem {
+    fas_grid* g;
+    int T;                  // tile levels 0..T-1, tail from level T
+    int height;             // levels below the finest (L)
+    size_t tile_bytes;
+    int blocks[3][fas::kMaxLevels];  // blocks of pre, first-cycle pre and post launches per level
+    char* host;             // staging of the descriptors (pinned)
+    // device addresses in the grid's descriptor region
+    const void* status() const { return g->desc; }
+    const void* tail() const { return (const char*)g->desc + 256; }
+    const void* tile(int kind, int l) const
+    {
+        return (const char*)g->desc + 256 + 2048 + (size_t)(3 * l + kind) * tile_bytes;
+    }
+};
+
+// Builds problem p's descriptors in its pinned staging area and uploads them when they
+// differ from what the grid's descriptor region already holds.
+void build_table_problem(TableProblem& P, const void* rhs, void* u, int nu1, int nu2, int wv, hipStream_t stream)
+{
+    fas_grid* g = P.g;
+    ensure_host(g);
+    const size_t tb = fas::tile_desc_bytes(g->dtype);
+    P.tile_bytes = tb;
+    if (256 + 2048 + (size_t)3 * P.T * tb > fas::kDescBytes || fas::tail_desc_bytes(g->dtype) > 2048 ||
+        sizeof(fas::StatusDesc) > 256)
+        throw Error(FAS_ERR_ARG, "internal: batched-solve descriptors exceed their region");
+    std::vector<char> d(fas::kDescBytes, 0);
+    const int first = (g->dim + 1) & 1;
+    const int* act = g->active;
+    for (int l = 0; l < P.T; ++l) {
+        fas::Level& F = g->lev[l];
+        fas::Level& C = g->lev[l + 1];
+        void* const rc = l + 1 == P.T ? C.f : C.r;  // the tail forms f from C.f in place
+        const void* fin = l == 0 ? rhs : F.r;
+        void* const fout = l == 0 ? nullptr : F.f;
+        void* const uin = l == 0 ? u : F.u;
+        char* const base = d.data() + 256 + 2048;
+        P.blocks[0][l] = fas::fill_tile_desc(g, l, g->coef[l], nu1, wv, false, fin, uin, F.x, C.u, rc, fout, nullptr,
+                                             act, base + (size_t)(3 * l + 0) * tb);
+        P.blocks[1][l] = l == 0 ? fas::fill_tile_desc(g, l, g->coef[l], nu1, wv, false, fin, uin, F.x, C.u, rc, nullptr,
+                                                      g->fpartials, act, base + (size_t)(3 * l + 1) * tb)
+                                : P.blocks[0][l];
+        // post: f, u_in = the pre pass's output, u_out, uc = the coarse level's new values
+        P.blocks[2][l] = fas::fill_tile_desc(g, l, g->coef[l], nu2, wv, true, l == 0 ? rhs : F.f, F.x,
+                                             l == 0 ? u : F.u, C.u, nullptr, nullptr,
+                                             l == 0 ? g->partials : nullptr, act, base + (size_t)(3 * l + 2) * tb);
+    }
+    fas::fill_tail_desc(g, P.T, g->coef, nu1, nu2, first, g->lev[P.T].u, g->lev[P.T].f, true, act, d.data() + 256);
+    fas::StatusDesc sd{};
+    sd.partials = g->partials;
+    sd.fpartials = g->fpartials;
+    sd.count = P.blocks[2][0];
+    sd.fcount = P.blocks[1][0];
+    sd.rnorm = g->rnorm;
+    sd.norm_out = g->norm_out;
+    sd.act = g->active;
+    sd.cyc = g->cyc;
+    sd.hist = g->hist;
+    memcpy(d.data(), &sd, sizeof(sd));
+    P.host = (char*)g->host + kHostStatus;
+    if (!g->desc_valid || memcmp(P.host, d.data(), fas::kDescBytes) != 0) {
+        memcpy(P.host, d.data(), fas::kDescBytes);
+        FAS_HIP_CHECK(hipMemcpyAsync(g->desc, P.host, fas::kDescBytes, hipMemcpyHostToDevice, stream));
+        g->desc_valid = 1;
+    }
+}
+
+// Table launches over a list of (descriptor, blocks) entries, in chunks of kBatchChunk.
+template <typename Launch>
+void for_chunks(const std::vector<std::pair<const void*, int>>& items, Launch&& launch)
+{
+    for (size_t i0 = 0; i0 < items.size(); i0 += fas::kBatchChunk) {
+        fas::TableLaunch t;
+        memset(&t, 0, sizeof(t));
+        t.np = (int)std::min(items.size() - i0, (size_t)fas::kBatchChunk);
+        int acc = 0;
+        for (int p = 0; p < t.np; ++p) {
+            t.desc[p] = items[i0 + p].first;
+            t.first[p] = acc;
+            acc += items[i0 + p].second;
+        }
+        t.first[t.np] = acc;
+        launch(t, i0);
+    }
+}
+
+int solve_table_impl(int nprob, fas_grid* const* grids, double dt, const fas_kappa_t* kappa,
+                     const void* const* rhs, void* const* u, double tol, int nu1, int nu2, int* status_out)
+{
+    fas_grid* const lead = grids[0];
+    hipStream_t stream = lead->stream;
+    const bool kv = kappa[0].cell != nullptr;
+    const int dtype = lead->dtype;
+    // every problem's work runs on the first grid's stream
+    struct StreamScope {
+        int n;
+        fas_grid* const* g;
+        std::vector<hipStream_t> saved;
+        ~StreamScope()
+        {
+            for (int p = 0; p < n; ++p) g[p]->stream = saved[(size_t)p];
+        }
+    } scope{nprob, grids, {}};
+    for (int p = 0; p < nprob; ++p) scope.saved.push_back(grids[p]->stream);
+    for (int p = 0; p < nprob; ++p) grids[p]->stream = stream;
+    const int wv = fas::tile_waves(lead, 0, nu1);
+    std::vector<TableProblem> P((size_t)nprob);
+    int hmax = 0;
+    for (int p = 0; p < nprob; ++p) {
+        fas_grid* g = grids[p];
+        set_coefs(g, dt, kappa[p].scalar, kv);
+        set_kappa(g, kappa[p].cell, dtype == FAS_F64);
+        memset(&g->stats, 0, sizeof(g->stats));
+        TableProblem& Q = P[(size_t)p];
+        Q.g = g;
+        Q.T = fas::tail_top(g);
+        Q.height = g->L;
+        hmax = std::max(hmax, g->L);
+        if (fas::tile_waves(g, 0, nu1) != wv || fas::tile_waves(g, 0, nu2) != wv)
+            throw Error(FAS_ERR_ARG, "batched problems must share the tile shape (FAS_OPT_TILE_WAVES)");
+        build_table_problem(Q, rhs[p], u[p], nu1, nu2, wv, stream);
+    }
+    // launch lists per height (pre, first-cycle pre, post) and tails per height
+    typedef std::vector<std::pair<const void*, int>> Items;
+    std::vector<Items> pre((size_t)hmax + 1), pre1((size_t)hmax + 1), post((size_t)hmax + 1), tail((size_t)hmax + 1);
+    Items status;
+    for (const TableProblem& Q : P) {
+        for (int l = 0; l < Q.T; ++l) {
+            const size_t h = (size_t)(Q.height - l);
+            pre[h].push_back({Q.tile(0, l), Q.blocks[0][l]});
+            pre1[h].push_back({Q.tile(l == 0 ? 1 : 0, l), Q.blocks[1][l]});
+            post[h].push_back({Q.tile(2, l), Q.blocks[2][l]});
+        }
+        tail[(size_t)(Q.height - Q.T)].push_back({Q.tail(), 1});
+        status.push_back({Q.status(), 1});
+    }
+    const int first = (lead->dim + 1) & 1;
+    for_chunks(status, [&](const fas::TableLaunch& t, size_t) { fas::launch_batch_init(stream, t); });
+    ensure_host(lead);
+    const int horizon = lead->last_cycles > 2 ? lead->last_cycles - 2 : 0;
+    lead->last_cycles = 0;
+    const int kmax = lead->kmax;
+    int* const hcount = (int*)lead->host;
+    for (int k = 1; k <= kmax; ++k) {
+        for (int h = hmax; h >= 0; --h) {
+            for_chunks(k == 1 ? pre1[(size_t)h] : pre[(size_t)h], [&](const fas::TableLaunch& t, size_t) {
+                fas::launch_tile_table(stream, dtype, false, nu1, first, kv, wv, t);
+            });
+            for_chunks(tail[(size_t)h],
+                       [&](const fas::TableLaunch& t, size_t) { fas::launch_tail_table(stream, dtype, 2, kv, t); });
+        }
+        for (int h = 0; h <= hmax; ++h)
+            for_chunks(post[(size_t)h], [&](const fas::TableLaunch& t, size_t) {
+                fas::launch_tile_table(stream, dtype, true, nu2, first, kv, wv, t);
+            });
+        if (k == 1) for_chunks(status, [&](const fas::TableLaunch& t, size_t) { fas::launch_batch_fsum(stream, t); });
+        for_chunks(status, [&](const fas::TableLaunch& t, size_t) { fas::launch_batch_update(stream, t, tol, k); });
+        for_chunks(status, [&](const fas::TableLaunch& t, size_t i0) {
+            fas::launch_batch_alive(stream, t, lead->count, i0 > 0);
+        });
+        if (k <= horizon && k < kmax) continue;
+        FAS_HIP_CHECK(hipMemcpyAsync(hcount, lead->count, sizeof(int), hipMemcpyDeviceToHost, stream));
+        FAS_HIP_CHECK(hipStreamSynchronize(stream));
+        if (hcount[0] == 0) break;
+    }
+    // per problem: {cycle of the stop, ||rhs||^2, squared norms after each cycle} gathered
+    // into the first grid's partial-sum buffer, free once the cycles are done
+    const int stride = (int)std::min<int64_t>(fas::kHist + 2, lead->npartials / nprob);
+    if (stride < 2) throw Error(FAS_ERR_ARG, "internal: batch status does not fit the partial-sum buffer");
+    for_chunks(status, [&](const fas::TableLaunch& t, size_t i0) {
+        fas::launch_batch_gather(stream, t, lead->partials, (int)i0, stride);
+    });
+    std::vector<double> gat((size_t)nprob * stride);
+    FAS_HIP_CHECK(hipMemcpyAsync(gat.data(), lead->partials, gat.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 stream));
+    FAS_HIP_CHECK(hipStreamSynchronize(stream));
+    int worst = FAS_OK, maxc = 0;
+    for (int p = 0; p < nprob; ++p) {
+        const double* r = gat.data() + (size_t)p * stride;
+        const int c = (int)r[0];
+        const int st = c > 0 ? FAS_OK : (c < 0 ? FAS_ERR_NONFINITE : FAS_NOT_CONVERGED);
+        const int cycles = c > 0 ? c : (c < 0 ? -c : kmax);
+        fas_stats_t& S = grids[p]->stats;
+        S.cycles = cycles;
+        S.status = st;
+        S.rhs_norm = sqrt(r[1]);
+        for (int i = 0; i < cycles && i < stride - 2; ++i) {
+            const double nr = sqrt(r[2 + i]);
+            S.rel_res[i] = S.rhs_norm > 0.0 ? nr / S.rhs_norm : nr;
+        }
+        if (status_out) status_out[p] = st;
+        if (st == FAS_ERR_NONFINITE) worst = FAS_ERR_NONFINITE;
+        else if (st == FAS_NOT_CONVERGED && worst == FAS_OK) worst = FAS_NOT_CONVERGED;
+        maxc = std::max(maxc, cycles);
+    }
+    if (worst == FAS_OK) lead->last_cycles = maxc;
+    if (worst == FAS_ERR_NONFINITE) throw Error(FAS_ERR_NONFINITE, "a residual norm is not finite");
+    if (worst == FAS_NOT_CONVERGED) g_last_error = "some problems did not converge within kmax cycles";
+    return worst;
+}
+
+int solve_batched_impl(int nprob, const fas_grid_t* grids, double dt, const fas_kappa_t* kappa,
+                       const void* const* rhs, void* const* u, double tol, int nu1, int nu2, int* status_out)
+{
+    if (nprob < 1 || !grids || !kappa || !rhs || !u) throw Error(FAS_ERR_ARG, "bad batch arguments");
+    std::vector<fas_grid*> gs((size_t)nprob);
+    for (int p = 0; p < nprob; ++p) {
+        fas_grid* g = grids[p];
+        check_solve_args(g, rhs[p], u[p], nu1, nu2, tol);
+        if (g->dtype != grids[0]->dtype) throw Error(FAS_ERR_ARG, "batched problems must share the dtype");
+        if ((kappa[p].cell != nullptr) != (kappa[0].cell != nullptr))
+            throw Error(FAS_ERR_ARG, "batched problems take all constant kappa or all cell kappa");
+        gs[(size_t)p] = g;
+    }
+    {
+        std::vector<fas_grid*> sorted = gs;
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            throw Error(FAS_ERR_ARG, "a grid appears twice in one batch");
+    }
+    const bool kv = kappa[0].cell != nullptr;
+    bool table = true;
+    for (int p = 0; p < nprob && table; ++p) table = table_ok(gs[(size_t)p], nu1, nu2, kv);
+    if (table) return solve_table_impl(nprob, gs.data(), dt, kappa, rhs, u, tol, nu1, nu2, status_out);
+    // otherwise (3D grids, levels without tile passes, other set orders): one solve after
+    // another, each on its own grid's stream
+    int worst = FAS_OK;
+    for (int p = 0; p < nprob; ++p) {
+        int st;
+        try {
+            st = solve_impl(gs[(size_t)p], dt, kappa[p].scalar, kappa[p].cell, rhs[p], u[p], tol, nu1, nu2, false);
+        } catch (const Error& e) {
+            if (e.code != FAS_ERR_NONFINITE) throw;
+            st = FAS_ERR_NONFINITE;
+        }
+        if (status_out) status_out[p] = st;
+        if (st == FAS_ERR_NONFINITE) worst = FAS_ERR_NONFINITE;
+        else if (st == FAS_NOT_CONVERGED && worst == FAS_OK) worst = FAS_NOT_CONVERGED;
+    }
+    if (worst == FAS_ERR_NONFINITE) throw Error(FAS_ERR_NONFINITE, "a residual norm is not finite");
+    if (worst == FAS_NOT_CONVERGED) g_last_error = "some problems did not converge within kmax cycles";
+    return worst;
 }
 
 }  // namespace
@@ -1011,11 +1410,23 @@ int fas_grid_set(fas_grid_t g, int option, double value)
                 g->autotune = v;
                 g->tuned = 0;
                 if (!v)
-                    for (int l = 0; l < fas::kMaxLevels; ++l) g->seg_rows[l] = 0;
+                    for (int l = 0; l < fas::kMaxLevels; ++l) g->seg_rows[l] = g->tile_wv[l] = g->tile_grp[l] = 0;
                 return FAS_OK;
             case FAS_OPT_FUSED:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "fused must be 0 or 1");
-                g->fused = v;
+                g->fused_opt = v;
+                g->fused = v && two_colour(g);
+                return FAS_OK;
+            case FAS_OPT_ORDER:
+                if (v != FAS_ORDER_X && v != FAS_ORDER_U && v != FAS_ORDER_Z)
+                    return fail(FAS_ERR_ARG, "order must be FAS_ORDER_X, FAS_ORDER_U or FAS_ORDER_Z");
+                g->order = v;
+                g->fused = g->fused_opt && two_colour(g);
+                return FAS_OK;
+            case FAS_OPT_SYMMETRIC:
+                if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "symmetric must be 0 or 1");
+                g->symmetric = v;
+                g->fused = g->fused_opt && two_colour(g);
                 return FAS_OK;
             case FAS_OPT_SEG_ROWS:
                 if (v != 0 && (v < fas::kMinSegRows || (v & 1)))
@@ -1085,12 +1496,7 @@ int fas_smooth(fas_grid_t g, int level, double dt, double kappa, const void* kap
         if (kappa_cell && !(g->flags & FAS_FLAG_VARIABLE_KAPPA))
             return fail(FAS_ERR_ARG, "cell kappa needs FAS_FLAG_VARIABLE_KAPPA");
         set_coefs(g, dt, kappa, kappa_cell != nullptr);
-        const int first = (g->dim + 1) & 1;
-        for (int s = 0; s < sweeps; ++s)
-            for (int ph = 0; ph < 2; ++ph) {
-                const int parity = ((ph == 0) != (reverse != 0)) ? first : 1 - first;
-                fas::launch_smooth_phase(g, level, g->coef[level], kappa_cell, rhs, u, parity);
-            }
+        smooth_kap(g, level, kappa_cell, rhs, u, sweeps, reverse != 0);
         return FAS_OK;
     });
 }
@@ -1158,7 +1564,7 @@ int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, con
     return guarded([&]() -> int { return solve_mixed_impl(g64, g32, dt, kappa, kappa_cell, rhs, u, tol, nu1, nu2, inner); });
 }
 
-int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, void* u, double tol, int nu1, int nu2,
+int fas_solve_stacked(fas_grid_t g, double dt, double kappa, const void* rhs, void* u, double tol, int nu1, int nu2,
                       int* status_out, int* cycles_out)
 {
     return guarded([&]() -> int {
@@ -1218,11 +1624,28 @@ int fas_solve_batched(fas_grid_t g, double dt, double kappa, const void* rhs, vo
     });
 }
 
+int fas_solve_batched(int nprob, const fas_grid_t* grids, double dt, const fas_kappa_t* kappa, const void* const* rhs,
+                      void* const* u, double tol, int nu1, int nu2, int* status_out)
+{
+    return guarded([&]() -> int {
+        return solve_batched_impl(nprob, grids, dt, kappa, rhs, u, tol, nu1, nu2, status_out);
+    });
+}
+
 int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f)
 {
     return guarded([&]() -> int {
         if (q < 1 || ncells < 1 || !eta || !f || eta == f) return fail(FAS_ERR_ARG, "bad grain-growth arguments");
         fas::launch_grain_rhs((hipStream_t)stream, q, ncells, (float)dt, (const float*)eta, (float*)f);
+        return FAS_OK;
+    });
+}
+
+int fas_grain_argmax(void* stream, int q, int64_t ncells, const void* eta, void* label)
+{
+    return guarded([&]() -> int {
+        if (q < 1 || ncells < 1 || !eta || !label) return fail(FAS_ERR_ARG, "bad grain-map arguments");
+        fas::launch_grain_argmax((hipStream_t)stream, q, ncells, (const float*)eta, (int*)label);
         return FAS_OK;
     });
 }

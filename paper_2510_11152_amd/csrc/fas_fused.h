@@ -43,6 +43,14 @@ int strip_waves_per_cu(int nu);
 // sweeps).  tile_count: norm partial sums a post launch leaves per problem.
 bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable);
 int tile_count(const fas_grid* g, int l, int nu);
+// Norm partial sums of a post launch on level l with wv waves per block (-1: no rows left
+// to write).
+int tile_count_with(const fas_grid* g, int l, int nu, int wv);
+// Waves per block, and strips per group of the tile order, of level l's tile passes.
+int tile_waves(const fas_grid* g, int l, int nu);
+int tile_group(const fas_grid* g, int l);
+constexpr int kTileWaveChoices[] = {6, 8, 12, 16};  // candidates of the autotuner
+constexpr int kTileGroupChoices[] = {4, 8, 16, 32};
 // fpartials (nullable, not with fout): one sum of f^2 per tile as well (tile_count(g, l,
 // nu) of them).  zero (FP32, neither fout nor fpartials): the pass starts from u = 0 and
 // does not read u_in.

@@ -58,6 +58,9 @@ struct fas_grid {
     fas::Level lev[fas::kMaxLevels];
     hipStream_t stream;
     double* partials;    // per-block / per-wave partial sums of a norm (npartials), device
+    double* fpartials;   // array-form batched solve: per-tile sums of rhs^2 (npartials), device
+    void* desc;          // array-form batched solve: launch descriptors (kDescBytes), device
+    int desc_valid;      // the pinned host copy holds what desc holds
     double* norm_out;    // reduced sum of squares, one per problem, device
     int npartials;
     // batched grids: `batch` same-shape problems, level arrays contiguous across problems
@@ -78,7 +81,9 @@ struct fas_grid {
     int zero_start;      // the next finest-level tile pre pass starts from u = 0 (no read)
     double* accum64;     // non-null: the finest-level tile post pass adds its result into
                          // this FP64 array instead of storing it (nor the u argument)
-    int kmax, nuc, fused;
+    int kmax, nuc, fused;   // fused: fused kernels in use (fused_opt with a two-colour order)
+    int fused_opt;          // FAS_OPT_FUSED as set
+    int order, symmetric;   // FAS_OPT_ORDER / FAS_OPT_SYMMETRIC
     fas::Coef coef[fas::kMaxLevels];
     fas_stats_t stats;
     // HIP graph of one V-cycle (FAS_OPT_GRAPH) and march segment heights (FAS_OPT_AUTOTUNE)
@@ -89,6 +94,8 @@ struct fas_grid {
     int cus;                        // compute units of the device (0: not queried yet)
     int64_t tile_max;               // FAS_OPT_TILE: largest 2D level (cells) run as block tiles
     int tile_waves;                 // FAS_OPT_TILE_WAVES: waves per tile block (0: rule)
+    int tile_wv[fas::kMaxLevels];   // FAS_OPT_AUTOTUNE: tuned waves per tile block (0: rule)
+    int tile_grp[fas::kMaxLevels];  // FAS_OPT_AUTOTUNE: tuned strips per tile group (0: rule)
     int gate;                       // a solve is running its cycle loop: kernels of a single
                                     // problem check the active flag too
     hipEvent_t cyc_ev[2];           // cycle loop: one event per cycle in flight
@@ -113,6 +120,9 @@ inline const int* active_flags(const fas_grid* g) { return g->batch > 1 || g->ga
 // All act on level `l` of grid g with coefficients c, on g->stream.
 void launch_smooth_phase(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, void* u,
                          int parity);
+// One index-parity set: cells whose 0-based index along axis a is even exactly when bit
+// a of mask is set.
+void launch_smooth_set(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, void* u, int mask);
 void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u,
                      void* r);
 // Partial sums of r^2 (r = f - A u) into g->partials then a fixed-order total into
@@ -151,5 +161,7 @@ void launch_sum_update(const fas_grid* g, int count, double tol, int k);
 // Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32):
 // S = sum_j eta_j^2; f_i = eta_i - dt*((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)).
 void launch_grain_rhs(hipStream_t stream, int q, int64_t N, float dt, const float* eta, float* f);
+// label[p] = the index of the largest of eta_0[p] .. eta_{q-1}[p] (lowest among equals).
+void launch_grain_argmax(hipStream_t stream, int q, int64_t N, const float* eta, int* label);
 
 }  // namespace fas

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "fas_batch.h"
 #include "fas_device.h"
 #include "fas_internal.h"
 
@@ -79,6 +80,34 @@ __global__ __launch_bounds__(kBlock) void k_smooth_phase(Op<T> op, const T* __re
     const int l = (int)(rest / op.n1);
     const int i = 2 * t + ((parity + j + l) & 1);
     if (i >= op.n0) return;
+    Nbhd<T, DIM> s;
+    gather<T, DIM, KV>(op, u, i, j, l, s);
+    const int64_t p = cell_index(op.n0, op.n1, i, j, l);
+    u[p] = gs_value<T, DIM, KV>(op, s, f[p]);
+}
+
+// One index-parity set (the multi-colour sets of Section 2.3 / Appendix B): the cells
+// whose 0-based index along axis a is even exactly when bit a of `mask` is set (a 1-based
+// odd index).  No two cells of a set are neighbours, so one thread per cell updates the
+// set in any order.  Loads and stores are 2-strided in x: these sweeps serve the set
+// orders that do not reduce to two colours (U, Z, symmetric), which are compared for
+// convergence, not speed.
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kBlock) void k_smooth_set(Op<T> op, const T* __restrict__ f, T* u, int mask, Batch bt)
+{
+    if (skip_problem(bt)) return;
+    f += blockIdx.y * bt.fine;
+    u += blockIdx.y * bt.fine;
+    const int o0 = (mask & 1) ? 0 : 1, o1 = (mask & 2) ? 0 : 1, o2 = DIM == 3 && !(mask & 4) ? 1 : 0;
+    const int m0 = (op.n0 - o0 + 1) >> 1, m1 = (op.n1 - o1 + 1) >> 1;
+    const int m2 = DIM == 3 ? (op.n2 - o2 + 1) >> 1 : 1;
+    const int64_t total = (int64_t)m0 * m1 * m2;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= total) return;
+    const int i = 2 * (int)(tid % m0) + o0;
+    const int64_t rest = tid / m0;
+    const int j = 2 * (int)(rest % m1) + o1;
+    const int l = 2 * (int)(rest / m1) + o2;
     Nbhd<T, DIM> s;
     gather<T, DIM, KV>(op, u, i, j, l, s);
     const int64_t p = cell_index(op.n0, op.n1, i, j, l);
@@ -594,6 +623,71 @@ __global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, float dt
 
 }  // namespace
 
+// ------------------------------------------------- array-form batches (StatusDesc each)
+__device__ __forceinline__ const StatusDesc& status_of(const TableLaunch& t, int p)
+{
+    return *reinterpret_cast<const StatusDesc*>(t.desc[p]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_init(TableLaunch t)
+{
+    const int p = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (p >= t.np) return;
+    const StatusDesc& d = status_of(t, p);
+    d.act[0] = 1;
+    d.cyc[0] = 0;
+}
+
+// One block per problem: ||rhs||^2 from the first cycle's per-tile f^2 sums.
+__global__ __launch_bounds__(kSumBlock) void k_batch_fsum(TableLaunch t)
+{
+    const StatusDesc& d = status_of(t, (int)blockIdx.x);
+    const double s = sum_block(d.fpartials, d.fcount);
+    if (threadIdx.x == 0) d.rnorm[0] = s;
+}
+
+// One block per problem: the norm total of cycle k and its stopping test, as
+// k_sum_update does for a single solve (the same sum, the same tests).
+__global__ __launch_bounds__(kSumBlock) void k_batch_update(TableLaunch t, double tol2, int k)
+{
+    const StatusDesc& d = status_of(t, (int)blockIdx.x);
+    if (!d.act[0]) return;  // uniform over the block
+    const double nr = sum_block(d.partials, d.count);
+    if (threadIdx.x != 0) return;
+    d.norm_out[0] = nr;
+    if (k <= kHist) d.hist[k - 1] = nr;
+    if (!isfinite(nr)) {
+        d.act[0] = 0;
+        d.cyc[0] = -k;
+    } else if (nr <= tol2 * d.rnorm[0] || nr == 0.0) {
+        d.act[0] = 0;
+        d.cyc[0] = k;
+    }
+}
+
+// One block: the problems still active, into count[0] (added to it when accumulating).
+__global__ __launch_bounds__(kBlock) void k_batch_alive(TableLaunch t, int* count, int accumulate)
+{
+    __shared__ int red[kBlock];
+    int alive = 0;
+    for (int p = threadIdx.x; p < t.np; p += kBlock) alive += status_of(t, p).act[0] ? 1 : 0;
+    red[threadIdx.x] = alive;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[0] = (accumulate ? count[0] : 0) + red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_gather(TableLaunch t, double* out, int base, int stride)
+{
+    const StatusDesc& d = status_of(t, (int)blockIdx.x);
+    double* const o = out + (int64_t)(base + (int)blockIdx.x) * stride;
+    for (int i = threadIdx.x; i < stride; i += kBlock)
+        o[i] = i == 0 ? (double)d.cyc[0] : (i == 1 ? d.rnorm[0] : d.hist[i - 2]);
+}
+
 // --------------------------------------------------------------------------- dispatch
 #define FAS_DISPATCH(g, kap, BODY)                                                        \
     do {                                                                                  \
@@ -626,6 +720,46 @@ void launch_smooth_phase(const fas_grid* g, int l, const Coef& c, const void* ka
     const int64_t work = (int64_t)((L.n[0] + 1) / 2) * L.n[1] * L.n[2];
     FAS_DISPATCH(g, kap, (k_smooth_phase<T, D, KV><<<grid2(blocks_for(work), g), kBlock, 0, g->stream>>>(
                              make_op<T>(g, l, c, kap), (const T*)f, (T*)u, parity, batch_of(g, l))));
+    check_launch();
+}
+
+void launch_batch_init(hipStream_t stream, const TableLaunch& t)
+{
+    k_batch_init<<<blocks_for(t.np), kBlock, 0, stream>>>(t);
+    check_launch();
+}
+
+void launch_batch_fsum(hipStream_t stream, const TableLaunch& t)
+{
+    k_batch_fsum<<<(unsigned)t.np, kSumBlock, 0, stream>>>(t);
+    check_launch();
+}
+
+void launch_batch_update(hipStream_t stream, const TableLaunch& t, double tol, int k)
+{
+    k_batch_update<<<(unsigned)t.np, kSumBlock, 0, stream>>>(t, tol * tol, k);
+    check_launch();
+}
+
+void launch_batch_alive(hipStream_t stream, const TableLaunch& t, int* count, bool accumulate)
+{
+    k_batch_alive<<<1, kBlock, 0, stream>>>(t, count, accumulate ? 1 : 0);
+    check_launch();
+}
+
+void launch_batch_gather(hipStream_t stream, const TableLaunch& t, double* out, int base, int stride)
+{
+    if (stride < 2 || stride > kHist + 2) throw Error(FAS_ERR_ARG, "internal: gather stride");
+    k_batch_gather<<<(unsigned)t.np, kBlock, 0, stream>>>(t, out, base, stride);
+    check_launch();
+}
+
+void launch_smooth_set(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, void* u, int mask)
+{
+    const Level& L = g->lev[l];
+    const int64_t work = (int64_t)((L.n[0] + 1) / 2) * ((L.n[1] + 1) / 2) * (g->dim == 3 ? (L.n[2] + 1) / 2 : 1);
+    FAS_DISPATCH(g, kap, (k_smooth_set<T, D, KV><<<grid2(blocks_for(work), g), kBlock, 0, g->stream>>>(
+                             make_op<T>(g, l, c, kap), (const T*)f, (T*)u, mask, batch_of(g, l))));
     check_launch();
 }
 
@@ -775,6 +909,32 @@ void launch_update_active(const fas_grid* g, double tol, int k)
 {
     k_update_active<<<1, kBlock, 0, g->stream>>>(g->norm_out, g->rnorm, tol * tol, k, g->active, g->cyc, g->batch,
                                                  g->count, g->batch == 1 ? g->hist : nullptr);
+    check_launch();
+}
+
+// Grain map of a multi-order-parameter state: per cell, the field with the largest value
+// (the lowest index among equal maxima), as read off the order parameters to find grains.
+__global__ __launch_bounds__(kBlock) void k_grain_argmax(int q, int64_t N, const float* __restrict__ eta,
+                                                         int* __restrict__ label)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    float best = eta[p];
+    int arg = 0;
+#pragma unroll 8
+    for (int i = 1; i < q; ++i) {
+        const float v = eta[(int64_t)i * N + p];
+        if (v > best) {
+            best = v;
+            arg = i;
+        }
+    }
+    label[p] = arg;
+}
+
+void launch_grain_argmax(hipStream_t stream, int q, int64_t N, const float* eta, int* label)
+{
+    k_grain_argmax<<<blocks_for(N), kBlock, 0, stream>>>(q, N, eta, label);
     check_launch();
 }
 

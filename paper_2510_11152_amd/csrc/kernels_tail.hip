@@ -4,7 +4,9 @@
 // launches per level; the per-point formulas are those of fas_device.h, so the values
 // are bit-identical to running the per-level kernels.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
+#include "fas_batch.h"
 #include "fas_device.h"
 #include "fas_internal.h"
 #include "fas_tail.h"
@@ -104,16 +106,14 @@ __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int f
     }
 }
 
+// The tail of one problem: its top level's u (in and out) and r (or f) at u_top / r_top.
 template <typename T, int DIM, bool KV>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
+__device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, const T* const r_top)
 {
     __shared__ __attribute__((aligned(16))) char lds[kTailLds];
     T* base = reinterpret_cast<T*>(lds);
     auto U = [&](int l) { return base + a.lds_off[l]; };
     auto F = [&](int l) { return base + a.lds_off[l] + (a.op[l].n0 * a.op[l].n1 * a.op[l].n2); };
-    if (a.act && !a.act[blockIdx.x]) return;
-    T* const u_top = a.u_top + blockIdx.x * a.stride;
-    const T* const r_top = a.r_top + blockIdx.x * a.stride;
     const int N0 = a.op[0].n0 * a.op[0].n1 * a.op[0].n2;
     for (int p = threadIdx.x; p < N0; p += kTailThreads) {
         U(0)[p] = u_top[p];
@@ -212,6 +212,23 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
     for (int p = threadIdx.x; p < N0; p += kTailThreads) u_top[p] = U(0)[p];
 }
 
+// Problem b = blockIdx.x of a stacked batch (arrays b * stride apart).
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a)
+{
+    if (a.act && !a.act[blockIdx.x]) return;
+    tail_body<T, DIM, KV>(a, a.u_top + blockIdx.x * a.stride, a.r_top + blockIdx.x * a.stride);
+}
+
+// Table launch (array-form batches): problem blockIdx.x's descriptor.
+template <typename T, int DIM, bool KV>
+__global__ __launch_bounds__(kTailThreads) void k_tail_table(TableLaunch tl)
+{
+    const TailArgs<T>& a = *reinterpret_cast<const TailArgs<T>*>(tl.desc[blockIdx.x]);
+    if (a.act && !a.act[0]) return;
+    tail_body<T, DIM, KV>(a, a.u_top, a.r_top);
+}
+
 template <typename T>
 TailArgs<T> make_tail_args(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first)
 {
@@ -284,6 +301,57 @@ int tail_top(const fas_grid* g)
         top = l;
     }
     return top;  // L + 1: not even the coarsest level fits
+}
+
+size_t tail_desc_bytes(int dtype)
+{
+    return dtype == FAS_F64 ? sizeof(TailArgs<double>) : sizeof(TailArgs<float>);
+}
+
+template <typename T>
+void fill_tail_desc_t(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first, void* u,
+                      const void* r, bool form_rhs, const int* act, void* out)
+{
+    TailArgs<T> a = make_tail_args<T>(g, top, coef, pre, post, first);
+    a.u_top = (T*)u;
+    a.r_top = (const T*)r;
+    a.form_rhs = form_rhs ? 1 : 0;
+    a.stride = 0;
+    a.act = act;
+    memcpy(out, &a, sizeof(a));
+}
+
+void fill_tail_desc(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first, void* u, const void* r,
+                    bool form_rhs, const int* act, void* out)
+{
+    if (!u || !r || !act || top < 0 || top > g->L || g->L - top + 1 > kMaxTail)
+        throw Error(FAS_ERR_ARG, "internal: tail descriptor with a missing array or level");
+    if (g->dtype == FAS_F64)
+        fill_tail_desc_t<double>(g, top, coef, pre, post, first, u, r, form_rhs, act, out);
+    else
+        fill_tail_desc_t<float>(g, top, coef, pre, post, first, u, r, form_rhs, act, out);
+}
+
+void launch_tail_table(hipStream_t stream, int dtype, int dim, bool kv, const TableLaunch& t)
+{
+    if (t.np < 1 || t.np > kBatchChunk) throw Error(FAS_ERR_ARG, "internal: table launch size");
+    const unsigned nb = (unsigned)t.np;
+#define FAS_TAIL_T(T_)                                                                         \
+    do {                                                                                       \
+        if (dim == 2) {                                                                        \
+            if (kv) k_tail_table<T_, 2, true><<<nb, kTailThreads, 0, stream>>>(t);             \
+            else k_tail_table<T_, 2, false><<<nb, kTailThreads, 0, stream>>>(t);               \
+        } else {                                                                               \
+            if (kv) k_tail_table<T_, 3, true><<<nb, kTailThreads, 0, stream>>>(t);             \
+            else k_tail_table<T_, 3, false><<<nb, kTailThreads, 0, stream>>>(t);               \
+        }                                                                                      \
+    } while (0)
+    if (dtype == FAS_F64)
+        FAS_TAIL_T(double);
+    else
+        FAS_TAIL_T(float);
+#undef FAS_TAIL_T
+    check_launch();
 }
 
 void launch_tail(const fas_grid* g, int top, const Coef* coef, int pre, int post, int first, void* u, const void* r,

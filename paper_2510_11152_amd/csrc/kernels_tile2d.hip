@@ -27,7 +27,9 @@
 // trees are those of fas_device.h, so every value is bit-identical to the strip and
 // per-phase kernels.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
+#include "fas_batch.h"
 #include "fas_device.h"
 #include "fas_fused.h"
 #include "fas_internal.h"
@@ -65,6 +67,7 @@ struct TileArgs {
     T k;                 // dt*kappa/h^2 of the level
     T q[16];             // 1/(1 + k W)
     int strips, tiles_y; // tiles across x and along y
+    int group;           // strips per group of the tile order (tile_coords)
     int tile_rows;       // rows written per tile: WV * rows_per_wave - 2 * halo (even)
     const T* f;
     const T* u_in;
@@ -80,19 +83,19 @@ struct TileArgs {
     const int* act;      // per-problem active flags (nullable)
 };
 
-// Tile t of a problem -> (strip, tile row).  Tiles are walked in groups of up to
-// kTileGroup strips, down the tile rows of a group, so the tiles that share halo rows
-// above and below run within a few tiles of each other (and, with xcd_block, on the same
-// XCD) rather than a whole row of tiles apart.  A bijection on [0, strips * tiles_y).
-constexpr int kTileGroup = 16;
+// Tile t of a problem -> (strip, tile row).  Tiles are walked in groups of up to `group`
+// strips, down the tile rows of a group, so the tiles that share halo rows above and
+// below run within a few tiles of each other (and, with xcd_block, on the same XCD)
+// rather than a whole row of tiles apart.  A bijection on [0, strips * tiles_y).
+constexpr int kTileGroup = 16;  // strips per group unless tuned
 
-__device__ __forceinline__ void tile_coords(int t, int strips, int tiles_y, int& strip, int& ty)
+__device__ __forceinline__ void tile_coords(int t, int strips, int tiles_y, int group, int& strip, int& ty)
 {
-    const int K = strips < kTileGroup ? strips : kTileGroup;
-    const int span = K * tiles_y, group = t / span, within = t % span;
-    const int width = strips - group * K < K ? strips - group * K : K;  // the last group may be narrower
+    const int K = strips < group ? strips : group;
+    const int span = K * tiles_y, gi = t / span, within = t % span;
+    const int width = strips - gi * K < K ? strips - gi * K : K;  // the last group may be narrower
     ty = within / width;
-    strip = group * K + within % width;
+    strip = gi * K + within % width;
 }
 
 // LDS of a block: two exchange buffers of WV x (top, bottom) rows of u, one of kappa
@@ -136,7 +139,7 @@ __device__ __forceinline__ void tile_pass(const TileArgs<T>& a, int b, int t, in
     T* const u_out = a.u_out + b * a.stride;
 
     int strip, ty;
-    tile_coords(t, a.strips, a.tiles_y, strip, ty);
+    tile_coords(t, a.strips, a.tiles_y, a.group, strip, ty);
     const int x0 = strip * kTileCols, y0 = ty * a.tile_rows;
     const int yend = min(y0 + a.tile_rows, a.n1);  // rows written: [y0, yend)
     const int gxe = x0 - kTileHX + 2 * lane;       // even cell of this lane
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k
     const int b = blk / per, t = blk % per;
     if (b >= a.batch || (a.act && !a.act[b])) return;  // uniform over the block
     int strip, ty;
-    tile_coords(t, a.strips, a.tiles_y, strip, ty);
+    tile_coords(t, a.strips, a.tiles_y, a.group, strip, ty);
     const int x0 = strip * kTileCols;
     if (x0 - kTileHX < 0 || x0 - kTileHX + 128 >= a.n0)
         tile_pass<T, NU, MODE, NORM, IN, KV, FIRST, true>(a, b, t, per);
@@ -420,10 +423,77 @@ __global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k
         tile_pass<T, NU, MODE, NORM, IN, KV, FIRST, false>(a, b, t, per);
 }
 
+// Table launches (array-form batches, fas_batch.h): the launch's blocks are renumbered
+// over the XCDs as one range, the problem is the one whose block range holds the block,
+// and its arguments come from its descriptor.  A pre-pass descriptor with fout forms the
+// FAS right-hand side, one with partials sums f^2 per tile; a post-pass descriptor with
+// partials sums the residual's squares per tile.
+template <typename T, int NU, bool POSTP, bool KV, int FIRST>
+__global__ __launch_bounds__(64 * (KV ? kMaxTileWavesKV : kMaxTileWaves)) void k_tile_table(TableLaunch tl)
+{
+    const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+    int lo = 0, hi = tl.np - 1;  // the problem p with first[p] <= blk < first[p + 1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk >= tl.first[mid])
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const TileArgs<T> a = *reinterpret_cast<const TileArgs<T>*>(tl.desc[lo]);
+    if (a.act && !a.act[0]) return;  // uniform over the block
+    const int per = a.strips * a.tiles_y;
+    const int t = blk - tl.first[lo];
+    int strip, ty;
+    tile_coords(t, a.strips, a.tiles_y, a.group, strip, ty);
+    const int x0 = strip * kTileCols;
+    const bool xe = x0 - kTileHX < 0 || x0 - kTileHX + 128 >= a.n0;
+#define FAS_TILE_PASS(MODE_, NORM_, IN_)                                        \
+    do {                                                                        \
+        if (xe)                                                                 \
+            tile_pass<T, NU, MODE_, NORM_, IN_, KV, FIRST, true>(a, 0, t, per);  \
+        else                                                                    \
+            tile_pass<T, NU, MODE_, NORM_, IN_, KV, FIRST, false>(a, 0, t, per); \
+    } while (0)
+    if constexpr (POSTP) {
+        if (a.partials)
+            FAS_TILE_PASS(1, true, IN_U);
+        else
+            FAS_TILE_PASS(1, false, IN_U);
+    } else {
+        if (a.fout)
+            FAS_TILE_PASS(0, false, IN_RHS);
+        else if (a.partials)
+            FAS_TILE_PASS(0, true, IN_U);
+        else
+            FAS_TILE_PASS(0, false, IN_U);
+    }
+#undef FAS_TILE_PASS
+}
+
 inline void check_launch()
 {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error(FAS_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+template <typename T, bool POSTP, bool KV>
+void launch_tile_table_t(hipStream_t stream, int nu, int first, int wv, const TableLaunch& t)
+{
+    const unsigned blocks = (unsigned)t.first[t.np];
+    const unsigned threads = 64u * (unsigned)wv;
+    const size_t lds = tile_lds_bytes<T>(wv, KV);
+#define FAS_TT_LAUNCH(NU_)                                                                       \
+    (first ? k_tile_table<T, NU_, POSTP, KV, 1><<<blocks, threads, lds, stream>>>(t)             \
+           : k_tile_table<T, NU_, POSTP, KV, 0><<<blocks, threads, lds, stream>>>(t))
+    switch (nu) {
+        case 1: FAS_TT_LAUNCH(1); break;
+        case 2: FAS_TT_LAUNCH(2); break;
+        case 3: FAS_TT_LAUNCH(3); break;
+        default: throw Error(FAS_ERR_ARG, "tile kernels take 1 <= nu <= 3");
+    }
+#undef FAS_TT_LAUNCH
+    check_launch();
 }
 
 template <typename T, int MODE, bool NORM, int IN, bool KV>
@@ -454,6 +524,9 @@ void launch_tile(const fas_grid* g, const TileArgs<T>& a, int nu, int first, int
         launch_tile_kv<T, MODE, NORM, IN, false>(g, a, nu, first, wv);
 }
 
+// Strips per group of level l: tuned, else the rule.
+int tile_group(const fas_grid* g, int l) { return g->tile_grp[l] ? g->tile_grp[l] : kTileGroup; }
+
 int tile_rows_of(const fas_grid* g, int wv, int nu, bool residual)
 {
     return wv * (g->dtype == FAS_F64 ? rows_per_wave<double>() : rows_per_wave<float>()) - 2 * tile_halo(nu, residual);
@@ -471,6 +544,7 @@ TileArgs<T> make_tile_args(const fas_grid* g, int l, const Coef& c, int nu, int 
     a.strips = (a.n0 + kTileCols - 1) / kTileCols;
     a.tile_rows = tile_rows_of(g, wv, nu, residual);
     a.tiles_y = (a.n1 + a.tile_rows - 1) / a.tile_rows;
+    a.group = tile_group(g, l);
     a.batch = g->batch;
     a.stride = g->lev[l].N;
     a.cstride = l < g->L ? g->lev[l + 1].N : 0;
@@ -491,10 +565,18 @@ bool tile_ok(const fas_grid* g, int l, int nu_pre, int nu_post, bool variable)
 int tile_waves(const fas_grid* g, int l, int nu)
 {
     (void)nu;
-    if (g->lev[l].kap) return g->tile_waves && g->tile_waves < kMaxTileWavesKV ? g->tile_waves : kMaxTileWavesKV;
-    // 8 waves: two waves per SIMD; in FP64 (about 70 VGPRs) three blocks per compute unit.
-    // Blocks of 9-16 waves leave SIMDs unevenly or less filled.
-    return g->tile_waves ? g->tile_waves : 8;
+    // forced (FAS_OPT_TILE_WAVES), else tuned (FAS_OPT_AUTOTUNE), else the rule: 8 waves,
+    // two per SIMD; in FP64 (about 70 VGPRs) three blocks per compute unit
+    const int w = g->tile_waves ? g->tile_waves : (g->tile_wv[l] ? g->tile_wv[l] : 8);
+    if (g->lev[l].kap) return w < kMaxTileWavesKV ? w : kMaxTileWavesKV;
+    return w;
+}
+
+int tile_count_with(const fas_grid* g, int l, int nu, int wv)
+{
+    const int rows = tile_rows_of(g, wv, nu, true);
+    if (rows < 2) return -1;
+    return ((g->lev[l].n[0] + kTileCols - 1) / kTileCols) * ((g->lev[l].n[1] + rows - 1) / rows);
 }
 
 int tile_count(const fas_grid* g, int l, int nu)
@@ -533,6 +615,65 @@ void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu,
         else
             launch_tile<float, 0, false, IN_U>(g, a, nu, first, wv);
     }
+}
+
+size_t tile_desc_bytes(int dtype)
+{
+    return dtype == FAS_F64 ? sizeof(TileArgs<double>) : sizeof(TileArgs<float>);
+}
+
+template <typename T>
+int fill_tile_desc_t(const fas_grid* g, int l, const Coef& c, int nu, int wv, bool post, const void* f,
+                     const void* u_in, void* u_out, void* uc, void* rc, void* fout, double* partials, const int* act,
+                     void* out)
+{
+    TileArgs<T> a = make_tile_args<T>(g, l, c, nu, wv, !post || partials != nullptr);
+    a.batch = 1;
+    a.stride = 0;
+    a.cstride = 0;
+    a.act = act;
+    a.f = (const T*)f;
+    a.u_in = (const T*)u_in;
+    a.u_out = (T*)u_out;
+    a.uc = (T*)uc;
+    a.rc = (T*)rc;
+    a.fout = (T*)fout;
+    a.partials = partials;
+    a.u64 = nullptr;
+    memcpy(out, &a, sizeof(a));
+    return a.strips * a.tiles_y;
+}
+
+int fill_tile_desc(const fas_grid* g, int l, const Coef& c, int nu, int wv, bool post, const void* f,
+                   const void* u_in, void* u_out, void* uc, void* rc, void* fout, double* partials, const int* act,
+                   void* out)
+{
+    if (post && (fout || rc)) throw Error(FAS_ERR_ARG, "internal: a post pass forms no right-hand side");
+    if (fout && partials) throw Error(FAS_ERR_ARG, "internal: a pre pass forms f or sums f^2, not both");
+    // every array the pass reads or writes must be there (a kernel would dereference it)
+    if (!f || !u_in || !u_out || !uc || (!post && !rc) || !act || u_in == u_out)
+        throw Error(FAS_ERR_ARG, "internal: tile-pass descriptor with a missing or aliased array");
+    if (l < 0 || l >= g->L) throw Error(FAS_ERR_ARG, "internal: tile-pass descriptor level");
+    if (g->dtype == FAS_F64)
+        return fill_tile_desc_t<double>(g, l, c, nu, wv, post, f, u_in, u_out, uc, rc, fout, partials, act, out);
+    return fill_tile_desc_t<float>(g, l, c, nu, wv, post, f, u_in, u_out, uc, rc, fout, partials, act, out);
+}
+
+void launch_tile_table(hipStream_t stream, int dtype, bool post, int nu, int first, bool kv, int wv,
+                       const TableLaunch& t)
+{
+    if (t.np < 1 || t.np > kBatchChunk) throw Error(FAS_ERR_ARG, "internal: table launch size");
+    if (wv < 6 || wv > (kv ? kMaxTileWavesKV : kMaxTileWaves)) throw Error(FAS_ERR_ARG, "internal: tile waves");
+    if (t.first[t.np] <= 0) return;
+#define FAS_TT(T_, P_, K_) launch_tile_table_t<T_, P_, K_>(stream, nu, first, wv, t)
+    if (dtype == FAS_F64) {
+        if (post) { if (kv) FAS_TT(double, true, true); else FAS_TT(double, true, false); }
+        else { if (kv) FAS_TT(double, false, true); else FAS_TT(double, false, false); }
+    } else {
+        if (post) { if (kv) FAS_TT(float, true, true); else FAS_TT(float, true, false); }
+        else { if (kv) FAS_TT(float, false, true); else FAS_TT(float, false, false); }
+    }
+#undef FAS_TT
 }
 
 void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,

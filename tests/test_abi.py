@@ -110,6 +110,13 @@ def test_solve_argument_errors_without_gpu(lib):
         for opt in (F.FAS_OPT_GRAPH, F.FAS_OPT_AUTOTUNE, F.FAS_OPT_PROFILE, F.FAS_OPT_FUSED):
             assert lib.fas_grid_set(g, opt, 2) == F.FAS_ERR_ARG
             assert lib.fas_grid_set(g, opt, 0) == F.FAS_OK
+        for bad in (-1, 3, 1.5):                         # set order: X, U or Z
+            assert lib.fas_grid_set(g, F.FAS_OPT_ORDER, bad) == F.FAS_ERR_ARG
+        for good in (F.FAS_ORDER["u"], F.FAS_ORDER["z"], F.FAS_ORDER["x"]):
+            assert lib.fas_grid_set(g, F.FAS_OPT_ORDER, good) == F.FAS_OK
+        assert lib.fas_grid_set(g, F.FAS_OPT_SYMMETRIC, 2) == F.FAS_ERR_ARG
+        assert lib.fas_grid_set(g, F.FAS_OPT_SYMMETRIC, 1) == F.FAS_OK
+        assert lib.fas_grid_set(g, F.FAS_OPT_SYMMETRIC, 0) == F.FAS_OK
         assert lib.fas_restrict(g, 4, buf, ctypes.c_void_p(1 << 23)) == F.FAS_ERR_ARG     # no coarser level
         assert lib.fas_kappa_grad(g, 1e-3, None, buf, buf, buf) == F.FAS_ERR_ARG
     finally:

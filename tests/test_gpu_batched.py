@@ -1,4 +1,4 @@
-"""Batched solves: every member of a batch equals the single-problem solve of the same
+"""Batched solves (stacked grids and array-form batches of grids): every member of a batch equals the single-problem solve of the same
 precision and parameters (the same kernels, partial sums and stopping decisions: equal
 cycle counts and bits) and the oracle's solve of that member; the grain-growth
 right-hand side equals the oracle's, and a grain step matches the oracle's FP32 solves."""
@@ -33,7 +33,7 @@ def test_batch_members_equal_single_solves(n, bc, dtype, coarsest):
     u0[2] = pre.cpu().numpy()
     gb = Grid(n, P.h, bc=bc, dtype=TD[dtype], coarsest=coarsest, batch=B)
     ub = torch.from_numpy(u0).to(DEV)
-    st, cy = gb.solve_batched(torch.from_numpy(rhs).to(DEV), ub, dt, tol=tol)
+    st, cy = gb.solve_stacked(torch.from_numpy(rhs).to(DEV), ub, dt, tol=tol)
     assert all(s == 0 for s in st), st
     assert cy[2] == 1 and max(cy) > 1, cy
     got = ub.cpu().numpy()
@@ -93,43 +93,162 @@ def test_grain_full_size_sampled_fields_match_oracle():
     torch.cuda.empty_cache()
 
 
-def test_uneven_batch_groups_equal_single_solves():
-    """Problems of several sizes: one batched solve per size group, each member equal to
-    its single solve."""
-    from paper_2510_11152_amd import solve_uneven, Grid
-    sizes = [64, 128, 64, 256, 128, 64]
-    fields = [I.cosine_modes(m, 2, 16, np.random.default_rng(50 + b)) for b, m in enumerate(sizes)]
-    us = [torch.from_numpy(f.copy()).to(DEV) for f in fields]
-    rhs = [torch.from_numpy(f.copy()).to(DEV) for f in fields]
-    st, cy = solve_uneven(rhs, us, dt=1e-4, tol=1e-10)
-    assert all(s == 0 for s in st)
+def _single(m_shape, h, bc, dtype, rhs, u0, dt, kappa, kcell=None, nu=(2, 2), tol=1e-10, coarsest=4):
+    from paper_2510_11152_amd import Grid
+    g = Grid(m_shape, h, bc=bc, dtype=dtype, coarsest=coarsest, variable_kappa=kcell is not None)
+    u = u0.clone()
+    st = g.solve(rhs, u, dt, kappa=kappa, kappa_cell=kcell, tol=tol, nu1=nu[0], nu2=nu[1])
+    return st, g.stats(), u
+
+
+# array-form batches: (nx, ny), bc, kappa per problem
+ARRAY_CASES = {
+    "uneven_square": ([(128, 128), (512, 512), (256, 256), (128, 128), (1024, 1024), (256, 256)], "neumann"),
+    "rectangular_mixed_bc": ([(256, 128), (512, 256), (384, 128), (256, 256)], None),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ARRAY_CASES))
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 3)])
+def test_array_batch_members_equal_single_solves(case, dtype, nu):
+    """fas_solve_batched over grids of different sizes, spacings, boundary conditions and
+    constant kappas (one launch per pass over all of them): every member's status, cycle
+    count, residual history and bits equal its own fas_solve; two members also against the
+    oracle."""
+    from paper_2510_11152_amd import Grid, solve_batched
+    shapes, bc0 = ARRAY_CASES[case]
+    bcs = ["neumann", "dirichlet", "periodic", "neumann"]
+    tol = 1e-10 if dtype == np.float64 else 1e-5
+    td = TD[dtype]
+    grids, rhs, u0, kap, meta = [], [], [], [], []
+    for b, n in enumerate(shapes):
+        bc = bc0 or bcs[b % len(bcs)]
+        h = 1.0 / n[0]
+        k = 0.5 + 0.25 * b
+        shape = (n[1], n[0])
+        f = I.cosine_modes(n[0], 2, 16, np.random.default_rng(500 + b))[: n[1], :] if n[0] == n[1] else \
+            I.random_field(shape, 500 + b)
+        grids.append(Grid(n, h, bc=bc, dtype=td, coarsest=4))
+        rhs.append(torch.from_numpy(np.ascontiguousarray(f)).to(DEV, td))
+        u0.append(torch.from_numpy(I.random_field(shape, 600 + b) * 0.1).to(DEV, td))
+        kap.append(k)
+        meta.append((n, h, bc))
+    us = [u.clone() for u in u0]
+    # dt kappa / h^2 up to about 60 (FP64) / 6 (FP32): away from the slow coarse-grid regime
+    # of large dt kappa / h_c^2 under Neumann boundaries, where FP32 stalls above 1e-5
+    dt = 2e-4 if dtype == np.float64 else 2e-5
+    st = solve_batched(grids, rhs, us, dt, kap, tol=tol, nu1=nu[0], nu2=nu[1])
+    assert all(s == 0 for s in st), st
+    for b, (n, h, bc) in enumerate(meta):
+        s1, stats1, u1 = _single(n, h, bc, td, rhs[b], u0[b], dt, kap[b], nu=nu, tol=tol)
+        sb = grids[b].stats()
+        assert s1 == st[b] == sb["status"], (b, s1, st[b])
+        assert sb["cycles"] == stats1["cycles"], (b, sb["cycles"], stats1["cycles"])
+        assert torch.equal(us[b], u1), b
+        assert sb["rel_res"][: sb["cycles"]] == stats1["rel_res"][: stats1["cycles"]], b
+    for b in (0, len(meta) - 1):
+        n, h, bc = meta[b]
+        P = O.Problem(n=n, h=h, dt=dt, kappa=kap[b], bc=bc, coarsest=4, nuc=2)
+        check_solve(P, rhs[b].cpu().numpy(), u0[b].cpu().numpy(), us[b].cpu().numpy(), grids[b].stats()["cycles"],
+                    tol, nu1=nu[0], nu2=nu[1])
+
+
+def test_array_batch_cell_kappa_equals_single_solves():
+    """Cell kappa per problem (harmonic-mean faces, restricted coarse fields)."""
+    from paper_2510_11152_amd import Grid, solve_batched
+    sizes = [256, 128, 512]
+    grids, rhs, u0, cells = [], [], [], []
     for b, m in enumerate(sizes):
-        g = Grid((m, m), 1.0 / m, coarsest=4)
-        u = rhs[b].clone()
-        assert g.solve(rhs[b], u, 1e-4, tol=1e-10) == 0
-        assert g.stats()["cycles"] == cy[b], b
+        grids.append(Grid((m, m), 1.0 / m, coarsest=4, variable_kappa=True))
+        rhs.append(torch.from_numpy(I.random_field((m, m), 700 + b)).to(DEV))
+        u0.append(torch.zeros((m, m), dtype=torch.float64, device=DEV))
+        cells.append(torch.from_numpy(np.exp(0.5 * I.random_field((m, m), 710 + b))).to(DEV))
+    us = [u.clone() for u in u0]
+    st = solve_batched(grids, rhs, us, 2e-4, 1.0, cells, tol=1e-10)
+    assert all(s == 0 for s in st), st
+    for b, m in enumerate(sizes):
+        s1, stats1, u1 = _single((m, m), 1.0 / m, "neumann", torch.float64, rhs[b], u0[b], 2e-4, 1.0, cells[b])
+        assert grids[b].stats()["cycles"] == stats1["cycles"], b
+        assert torch.equal(us[b], u1), b
+    m = sizes[1]
+    P = O.Problem(n=(m, m), h=1.0 / m, dt=2e-4, bc="neumann", coarsest=4, nuc=2)
+    check_solve(P, rhs[1].cpu().numpy(), u0[1].cpu().numpy(), us[1].cpu().numpy(), grids[1].stats()["cycles"],
+                1e-10, kap=cells[1].cpu().numpy())
+
+
+def test_array_batch_more_problems_than_one_launch_holds():
+    """70 problems: each pass runs as two table launches (64 problems each at most); the
+    alive count adds over them.  The problems' kappas span two decades, so they stop at
+    different cycles."""
+    from paper_2510_11152_amd import Grid, solve_batched
+    B, m = 70, 128
+    grids = [Grid((m, m), 1.0 / m, coarsest=4) for _ in range(B)]
+    rhs = [torch.from_numpy(I.random_field((m, m), 800 + b)).to(DEV) for b in range(B)]
+    u0 = [torch.from_numpy(I.random_field((m, m), 900 + b)).to(DEV) for b in range(B)]
+    kap = [0.01 * 2.0 ** (b % 7) for b in range(B)]
+    us = [u.clone() for u in u0]
+    st = solve_batched(grids, rhs, us, 1e-3, kap, tol=1e-9)
+    assert all(s == 0 for s in st)
+    cycles = [g.stats()["cycles"] for g in grids]
+    assert len(set(cycles)) > 1, cycles
+    g1 = Grid((m, m), 1.0 / m, coarsest=4)
+    for b in range(B):
+        u = u0[b].clone()
+        assert g1.solve(rhs[b], u, 1e-3, kappa=kap[b], tol=1e-9) == 0
+        assert g1.stats()["cycles"] == cycles[b], b
         assert torch.equal(u, us[b]), b
-        P = O.Problem(n=(m, m), h=1.0 / m, dt=1e-4, bc="neumann", coarsest=4, nuc=2)
-        check_solve(P, fields[b], fields[b], us[b].cpu().numpy(), cy[b], 1e-10)
 
 
-def test_uneven_batch_reuse_with_graph_and_autotune():
-    """A planned UnevenBatch solved twice (the second solve replays the captured cycles and
-    the tuned segment heights) gives the one-shot solve's bits both times."""
-    from paper_2510_11152_amd import UnevenBatch, solve_uneven
-    sizes = [128, 64, 256, 128, 64]
+def test_array_batch_reuse_and_changed_arguments():
+    """A planned UnevenBatch solved again with other iterates, another kappa and a looser
+    tolerance: descriptors are rewritten where the arguments changed, and every solve
+    equals single solves."""
+    from paper_2510_11152_amd import UnevenBatch
+    sizes = [128, 256, 128, 512]
     fields = [I.cosine_modes(m, 2, 16, np.random.default_rng(70 + b)) for b, m in enumerate(sizes)]
     rhs = [torch.from_numpy(f.copy()).to(DEV) for f in fields]
-    ref = [r.clone() for r in rhs]
-    st0, cy0 = solve_uneven(rhs, ref, dt=1e-4, tol=1e-10)
-    ub = UnevenBatch([tuple(r.shape) for r in rhs], device=DEV, graph=True, autotune=True)
-    for rep in range(2):
-        us = [r.clone() for r in rhs]
-        st, cy = ub.solve(rhs, us, 1e-4, tol=1e-10)
-        assert st == st0 and all(s == 0 for s in st)
-        assert cy == cy0, rep
-        for b in range(len(sizes)):
-            assert torch.equal(us[b], ref[b]), (rep, b)
+    ub = UnevenBatch([tuple(r.shape) for r in rhs], device=DEV)
+    for rep, (kappa, tol) in enumerate(((1.0, 1e-10), (1.0, 1e-10), (2.5, 1e-6), (1.0, 1e-10))):
+        us = [r.clone() * (1 + rep) for r in rhs]
+        u0 = [u.clone() for u in us]
+        st, cy = ub.solve(rhs, us, 1e-4, kappa=kappa, tol=tol)
+        assert all(s == 0 for s in st)
+        for b, m in enumerate(sizes):
+            s1, stats1, u1 = _single((m, m), 1.0 / m, "neumann", torch.float64, rhs[b], u0[b], 1e-4, kappa, tol=tol)
+            assert stats1["cycles"] == cy[b], (rep, b)
+            assert torch.equal(us[b], u1), (rep, b)
+
+
+def test_array_batch_fallback_solves_each_problem():
+    """Problems the table launches do not take (a 64^2 grid, whose whole hierarchy is one
+    coarse tail; a 3D grid) are solved one after another: still each its fas_solve."""
+    from paper_2510_11152_amd import Grid, solve_batched
+    specs = [((64, 64), 1 / 64), ((128, 128), 1 / 128), ((32, 32, 32), 1 / 32)]
+    grids = [Grid(n, h, coarsest=4) for n, h in specs]
+    rhs = [torch.from_numpy(I.random_field(tuple(reversed(n)), 1000 + b)).to(DEV) for b, (n, _) in enumerate(specs)]
+    us = [r.clone() for r in rhs]
+    st = solve_batched(grids, rhs, us, 1e-3, 1.0, tol=1e-10)
+    assert all(s == 0 for s in st)
+    for b, (n, h) in enumerate(specs):
+        s1, stats1, u1 = _single(n, h, "neumann", torch.float64, rhs[b], rhs[b], 1e-3, 1.0)
+        assert grids[b].stats()["cycles"] == stats1["cycles"]
+        assert torch.equal(us[b], u1), b
+
+
+def test_array_batch_argument_checks():
+    from paper_2510_11152_amd import Grid, solve_batched
+    from paper_2510_11152_amd._lib import FasError
+    g1, g2 = Grid((128, 128), 1 / 128), Grid((256, 256), 1 / 256)
+    r1, r2 = torch.zeros((128, 128), dtype=torch.float64, device=DEV), torch.zeros((256, 256), dtype=torch.float64, device=DEV)
+    with pytest.raises(FasError):  # the same grid twice
+        solve_batched([g1, g1], [r1, r1.clone()], [r1.clone(), r1.clone()], 1e-3)
+    with pytest.raises(FasError):  # rhs aliases u
+        solve_batched([g1, g2], [r1, r2], [r1, r2.clone()], 1e-3)
+    g3 = Grid((128, 128), 1 / 128, dtype=torch.float32)
+    r3 = torch.zeros((128, 128), dtype=torch.float32, device=DEV)
+    with pytest.raises(FasError):  # mixed dtypes
+        solve_batched([g1, g3], [r1, r3], [r1.clone(), r3.clone()], 1e-3)
 
 
 def test_batched_graph_replay_equals_launches():
@@ -138,8 +257,8 @@ def test_batched_graph_replay_equals_launches():
     P = O.Problem(n=n, h=1 / 256, dt=1e-3, bc="neumann", coarsest=4)
     rhs = torch.from_numpy(np.stack([I.random_field(P.shape(), 300 + b) for b in range(B)])).to(DEV)
     ua, ub = rhs.clone(), rhs.clone()
-    sa = Grid(n, P.h, batch=B).solve_batched(rhs, ua, P.dt, tol=1e-10)
-    sb = Grid(n, P.h, batch=B).set(graph=True).solve_batched(rhs, ub, P.dt, tol=1e-10)
+    sa = Grid(n, P.h, batch=B).solve_stacked(rhs, ua, P.dt, tol=1e-10)
+    sb = Grid(n, P.h, batch=B).set(graph=True).solve_stacked(rhs, ub, P.dt, tol=1e-10)
     assert sa == sb
     assert torch.equal(ua, ub)
     got, r = ua.cpu().numpy(), rhs.cpu().numpy()
@@ -159,11 +278,24 @@ def test_batched_solve_after_a_longer_solve_is_unchanged(graph):
     rhs = torch.from_numpy(np.stack([I.random_field(P.shape(), 400 + b) * (b + 1) for b in range(B)])).to(DEV)
     g = Grid(n, P.h, bc="dirichlet", batch=B).set(graph=graph)
     u = rhs.clone()
-    st, cy = g.solve_batched(rhs, u, P.dt, tol=1e-10)
+    st, cy = g.solve_stacked(rhs, u, P.dt, tol=1e-10)
     assert all(s == 0 for s in st) and max(cy) > 3
     for tol, u0 in ((1e-3, rhs), (1e-3, u.clone()), (1e-10, rhs)):
         ua, ub = u0.clone(), u0.clone()
-        sa = g.solve_batched(rhs, ua, P.dt, tol=tol)
-        sb = Grid(n, P.h, bc="dirichlet", batch=B).set(graph=graph).solve_batched(rhs, ub, P.dt, tol=tol)
+        sa = g.solve_stacked(rhs, ua, P.dt, tol=tol)
+        sb = Grid(n, P.h, bc="dirichlet", batch=B).set(graph=graph).solve_stacked(rhs, ub, P.dt, tol=tol)
         assert sa == sb, (tol, sa, sb)
         assert torch.equal(ua, ub), tol
+
+
+def test_grain_map_is_the_dominant_field():
+    """fas_grain_argmax: per cell the index of the largest order parameter, the lowest
+    index among equal values (numpy's argmax), on a state with planted ties."""
+    from paper_2510_11152_amd import grain_map
+    q, n = 23, 64
+    eta = I.grain_init(q=q, n=n, seed=11) * 1000.0
+    eta = np.round(eta).astype(np.float32) / 1000.0   # coarse values: many exact ties
+    eta[5, 3, :] = eta[2, 3, :] = 0.9                 # a tie between fields 2 and 5 along a row
+    lab = grain_map(torch.from_numpy(eta).to(DEV))
+    torch.cuda.synchronize()
+    assert np.array_equal(lab.cpu().numpy(), np.argmax(eta, axis=0).astype(np.int32))

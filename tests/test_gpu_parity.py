@@ -377,7 +377,7 @@ def test_forced_segment_heights_give_the_same_bits(n, bc, dtype, rows):
                                            ((2048, 256), 4, "neumann")])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nu", [(3, 1), (2, 2)])
-@pytest.mark.parametrize("waves", [6, 8, 16])
+@pytest.mark.parametrize("waves", [6, 8, 12, 16])
 @pytest.mark.parametrize("transposed", [False, True])
 @pytest.mark.parametrize("variable", [False, True])
 def test_tile_passes_bitwise(n, coarsest, bc, dtype, nu, waves, transposed, variable):
@@ -550,7 +550,7 @@ def test_full_size_2048_cell_kappa_vcycle_matches_oracle(transposed):
 
 
 @pytest.mark.parametrize("where", ["rhs", "u"])
-@pytest.mark.parametrize("form", ["plain", "mixed", "batched"])
+@pytest.mark.parametrize("form", ["plain", "mixed", "stacked", "array"])
 def test_non_finite_input_is_reported(where, form):
     """A NaN in the right-hand side or the initial guess makes the residual norm NaN; the
     solve stops with FAS_ERR_NONFINITE (raised as FasError) instead of iterating to kmax."""
@@ -566,9 +566,15 @@ def test_non_finite_input_is_reported(where, form):
             grid_for(P, np.float64).solve(dev(f), dev(u), P.dt, tol=1e-10)
         elif form == "mixed":
             solve_mixed(grid_for(P, np.float64), grid_for(P, np.float32, mixed=True), dev(f), dev(u), P.dt, tol=1e-10)
-        else:
+        elif form == "stacked":
             gb = Grid((n, n), P.h, batch=3)
             F = dev(np.stack([I.random_field(P.shape(), 91), f, I.random_field(P.shape(), 92)]))
             U = dev(np.stack([I.random_field(P.shape(), 93), u, I.random_field(P.shape(), 94)]))
-            gb.solve_batched(F, U, P.dt, tol=1e-10)
+            gb.solve_stacked(F, U, P.dt, tol=1e-10)
+        else:
+            from paper_2510_11152_amd import solve_batched
+            gs = [Grid((n, n), P.h), Grid((2 * n, 2 * n), P.h / 2)]
+            F = [dev(f), dev(I.random_field((2 * n, 2 * n), 95))]
+            U = [dev(u), dev(I.random_field((2 * n, 2 * n), 96))]
+            solve_batched(gs, F, U, P.dt, tol=1e-10)
     assert e.value.code == FAS_ERR_NONFINITE
