@@ -288,6 +288,24 @@ int fas_grain_argmax(void* stream, int q, int64_t ncells, const void* eta, void*
 int fas_stream_probe(void* stream, int kind, int64_t bytes, const void* a, const void* b, void* c, double* part,
                      int blocks, int reps, double* ms_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fas_solve on a single problem whose
+ * grid is planned inside the call and whose workspace is a static device buffer of the
+ * library, FAS_NOALLOC_MAX_BYTES per GPU, held by every GPU the library runs on until the
+ * process ends.  The call allocates nothing: no hipMalloc/hipFree, no pinned host memory,
+ * no events.  Arguments as fas_grid_create (without flags and workspace) plus fas_solve's;
+ * the stream must belong to the calling thread's current device; kmax: maximum V-cycles;
+ * cycles_out (nullable) gets the cycles run.  A grid whose workspace
+ * (fas_workspace_size, with FAS_FLAG_VARIABLE_KAPPA when kappa_cell is given) exceeds
+ * FAS_NOALLOC_MAX_BYTES is rejected with FAS_ERR_NOMEM (FP64 2048^2 and 128^3 fit).  The
+ * host waits on the stream after every cycle.  All calls on one GPU share its buffer:
+ * calls that overlap in time on one GPU (any streams or threads) race and must not be
+ * made.  Nothing a call reads from the buffer is left over from an earlier call. */
+#define FAS_NOALLOC_MAX_BYTES (96u << 20)
+int fas_solve_noalloc(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, void* stream, double dt,
+                      double kappa, const void* kappa_cell, const void* rhs, void* u, double tol, int nu1, int nu2,
+                      int kmax, int* cycles_out);
+
 int fas_get_stats(fas_grid_t grid, fas_stats_t* out);
 /* Accumulated kernel times of a grid with FAS_OPT_PROFILE on (synchronises the stream);
  * reset != 0 clears the counters afterwards. */

@@ -18,6 +18,9 @@
 
 using fas::Error;
 
+// Device workspace of fas_solve_noalloc (one copy per GPU the library runs on).
+static __device__ __align__(256) char scratch[FAS_NOALLOC_MAX_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -44,6 +47,9 @@ int guarded(F&& body)
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace of fas_solve_noalloc, one per GPU (see static_workspace).
+constexpr size_t kStaticWorkspace = (size_t)FAS_NOALLOC_MAX_BYTES;
 
 // Workspace layout (offsets from the workspace base, each 256-byte aligned):
 //   level 0: x                      (second buffer of the finest level)
@@ -1058,6 +1064,94 @@ int setup_grid(fas_grid* g, int dim, const int64_t n[3], double h, int bc, int d
     return FAS_OK;
 }
 
+// ---- the solve without allocation: workspace in a static device buffer ------------------
+// Callers that cannot allocate (HIP graph capture, serving loops) get fas_solve_noalloc: the
+// grid plan lives on the host stack and its workspace is `scratch`, one per GPU, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, so the device address
+// is looked up once per device (hipGetSymbolAddress, with that device current) and only that
+// address is handed to kernels.
+constexpr int kStaticDevices = 64;
+
+std::mutex& static_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
+void* static_workspace()
+{
+    static void* addr[kStaticDevices] = {};
+    int dev = 0;
+    FAS_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticDevices) throw Error(FAS_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(static_mutex());
+    if (!addr[dev]) {
+        void* p = nullptr;
+        FAS_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (uintptr_t)p % kAlign) throw Error(FAS_ERR_HIP, "static workspace has no usable device address");
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
+// fas_solve on a grid planned inside the call over the static workspace.  The loop is
+// solve_impl's without its pinned buffer, events and look-ahead: after each cycle the
+// device-side stopping test runs and the host reads the number of active problems (one
+// int into pageable memory) before enqueuing the next cycle.  Every workspace region a
+// cycle reads is written earlier in the same call (level arrays by restriction and the
+// coarse right-hand side, partial sums by the passes, flags and counts by
+// launch_init_active), so nothing left by an earlier call is ever read.
+int solve_noalloc_impl(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, void* stream,
+                       double dt, double kappa, const void* kcell, const void* rhs, void* u, double tol, int nu1,
+                       int nu2, int kmax, int* cycles_out)
+{
+    if (!n) throw Error(FAS_ERR_ARG, "null argument");
+    if (kmax < 1) throw Error(FAS_ERR_ARG, "kmax must be >= 1");
+    const int flags = kcell ? FAS_FLAG_VARIABLE_KAPPA : 0;
+    Layout lay;
+    std::string why;
+    if (const int rc = plan(dim, n, dtype, coarsest, flags, 1, &lay, &why)) throw Error(rc, why);
+    if (lay.total > kStaticWorkspace)
+        throw Error(FAS_ERR_NOMEM, "grid needs " + std::to_string(lay.total) + " bytes of workspace; the static buffer "
+                                   "holds " + std::to_string(kStaticWorkspace));
+    fas_grid g;
+    if (const int rc = setup_grid(&g, dim, n, h, bc, dtype, coarsest, flags, 1, static_workspace(), kStaticWorkspace,
+                                  stream))
+        throw Error(rc, g_last_error);
+    g.kmax = kmax;
+    check_solve_args(&g, rhs, u, nu1, nu2, tol);
+    set_coefs(&g, dt, kappa, kcell != nullptr);
+    set_kappa(&g, kcell, dtype == FAS_F64);
+    fas::launch_init_active(&g);
+    fas::launch_resid_norm(&g, 0, g.coef[0], g.lev[0].kap, rhs, nullptr);
+    FAS_HIP_CHECK(hipMemcpyAsync(g.rnorm, g.norm_out, sizeof(double), hipMemcpyDeviceToDevice, g.stream));
+    GateScope gate(&g);
+    g.defer_norm = 1;
+    int alive = 1, k = 0;
+    while (alive && k < kmax) {
+        ++k;
+        g.deferred_np = 0;
+        vcycle_top(&g, rhs, u, nu1, nu2, false, true);
+        if (g.deferred_np > 0)
+            fas::launch_sum_update(&g, g.deferred_np, tol, k);
+        else
+            fas::launch_update_active(&g, tol, k);
+        FAS_HIP_CHECK(hipMemcpyAsync(&alive, g.count, sizeof(int), hipMemcpyDeviceToHost, g.stream));
+        FAS_HIP_CHECK(hipStreamSynchronize(g.stream));
+    }
+    int stop = 0;
+    FAS_HIP_CHECK(hipMemcpyAsync(&stop, g.cyc, sizeof(int), hipMemcpyDeviceToHost, g.stream));
+    FAS_HIP_CHECK(hipStreamSynchronize(g.stream));
+    if (cycles_out) *cycles_out = stop > 0 ? stop : (stop < 0 ? -stop : k);
+    if (stop < 0) throw Error(FAS_ERR_NONFINITE, "residual norm is not finite");
+    if (stop == 0) {
+        g_last_error = "not converged within kmax cycles";
+        return FAS_NOT_CONVERGED;
+    }
+    return FAS_OK;
+}
+
+
 // ---- array-form batched solve ------------------------------------------------------------
 // Problems of any sizes, each on its own grid, advanced together: per V-cycle, the pre
 // passes from the tallest hierarchy's finest level down (one table launch per height,
@@ -1621,6 +1715,16 @@ int fas_solve_stacked(fas_grid_t g, double dt, double kappa, const void* rhs, vo
         if (worst == FAS_ERR_NONFINITE) return fail(FAS_ERR_NONFINITE, "a residual norm is not finite");
         if (worst == FAS_NOT_CONVERGED) g_last_error = "some problems did not converge within kmax cycles";
         return worst;
+    });
+}
+
+int fas_solve_noalloc(int dim, const int64_t n[3], double h, int bc, int dtype, int coarsest, void* stream, double dt,
+                      double kappa, const void* kappa_cell, const void* rhs, void* u, double tol, int nu1, int nu2,
+                      int kmax, int* cycles_out)
+{
+    return guarded([&]() -> int {
+        return solve_noalloc_impl(dim, n, h, bc, dtype, coarsest, stream, dt, kappa, kappa_cell, rhs, u, tol, nu1, nu2,
+                                  kmax, cycles_out);
     });
 }
 
