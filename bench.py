@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="batched,adjoint,3d,orders",
-                    help="other workloads timed after the headline (comma list; 'none' to skip)")
+                    help="other workloads timed after the headline (comma list; 'none' to skip; "
+                         "'table45' adds per-cycle times at the paper's Table 4/5 sizes)")
     return ap.parse_args()
 
 
@@ -182,6 +183,47 @@ def bench_orders(dev, sizes=(1024, 2048)):
                            "cycles_vs_x": {k: v["cycles"] / x for k, v in row.items()}}
         del g, f
     torch.cuda.empty_cache()
+    return out
+
+
+def bench_table45(dev, cpu=True, reps=10):
+    """Per-V-cycle times at the sizes of the paper's Tables 4 and 5 (2D 1024^2 .. 16384^2,
+    3D 128^3 .. 512^3), in their setting: p - Lap p = f (dt = kappa = 1), Dirichlet, the
+    sine test solution, zero initial guess, V(2,2) down to 2^d (meshLevel = log2 N - 1).
+    GPU: the mean of `reps` cycles after one warm-up cycle (the paper averages ten);
+    oracle: one cycle on one thread (sizes up to 8192^2 and 256^3; the larger ones are
+    quoted from the paper's own one-core column only)."""
+    import numpy as np
+    import torch
+
+    import fas_inputs
+    from paper_2510_11152_amd import Grid
+
+    out = {"host": host_cpu(), "rows": []}
+    for dim, n in ((2, 1024), (2, 2048), (2, 4096), (2, 8192), (2, 16384), (3, 128), (3, 256), (3, 512)):
+        f_h, _ = fas_inputs.paper_sine_problem(n, dim)
+        f = torch.from_numpy(f_h).to(dev)
+        u = torch.zeros_like(f)
+        g = Grid((n,) * dim, 1.0 / n, bc="dirichlet", coarsest=2, device=dev).set(coarse_sweeps=2)
+        g.vcycle(f, u, 1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.vcycle(f, u, 1.0)
+        torch.cuda.synchronize()
+        row = {"dim": dim, "n": n, "gpu_s_per_cycle": (time.perf_counter() - t0) / reps}
+        del g, u, f
+        torch.cuda.empty_cache()
+        if cpu and ((dim == 2 and n <= 8192) or (dim == 3 and n <= 256)):
+            import oracle
+
+            P = oracle.Problem(n=(n,) * dim, h=1.0 / n, dt=1.0, kappa=1.0, bc="dirichlet", coarsest=2, nuc=2)
+            uh = np.zeros_like(f_h)
+            t0 = time.perf_counter()
+            oracle.vcycle(P, np.ascontiguousarray(f_h), uh, 2, 2)
+            row["oracle_s_per_cycle"] = time.perf_counter() - t0
+        print("bench: table 4/5 %dD %d: %s" % (dim, n, row), file=sys.stderr, flush=True)
+        out["rows"].append(row)
     return out
 
 
@@ -347,6 +389,22 @@ def kernel_bytes(s, d):
     }
 
 
+def host_cpu():
+    """The host the oracle runs on: CPU model (/proc/cpuinfo), logical CPUs, and the CPUs
+    this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "oracle_threads": 1}
+
+
 def cpu_baseline(u0, n, dt, cycles_per_step, cycles=2):
     """The oracle (single thread) on a bounded sample: the first two V(2,2) cycles of the
     first heat step at full size, scaled to seconds per step by the GPU's cycles per step."""
@@ -369,6 +427,7 @@ def cpu_baseline(u0, n, dt, cycles_per_step, cycles=2):
         "kind": "oracle",
         "sample": "the first %d FP64 V(2,2) cycles of step 1 at %d^2 (%.1f s, single thread), per cycle times "
                   "%.2f GPU cycles per step" % (cycles, n, t_all, cycles_per_step),
+        "host": host_cpu(),
     }
 
 
@@ -499,6 +558,9 @@ def main():
     if "adjoint" in forms:
         print("bench: adjoint form", file=sys.stderr, flush=True)
         result["adjoint"] = bench_adjoint(dev)
+    if "table45" in forms:
+        print("bench: per-cycle times at the paper's Table 4/5 sizes", file=sys.stderr, flush=True)
+        result["table45"] = bench_table45(dev, cpu=not args.no_cpu_baseline)
     if "orders" in forms:
         print("bench: smoother ordering study", file=sys.stderr, flush=True)
         result["orders"] = bench_orders(dev)
