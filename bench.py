@@ -145,6 +145,66 @@ def bench_batched(dev):
                     "field_cells_per_s": q * n * n * steps / t_grain, "cycles_per_field": float(np.mean(cys[-1]))}
     del eta, model
     torch.cuda.empty_cache()
+    out["grain_1e-10"] = bench_grain_tight(dev, q, n)
+    return out
+
+
+def bench_grain_tight(dev, q=1189, n=512, steps=2):
+    """The grain-growth step at 1e-10 relative residual per field, from the seeded state:
+    the mixed form (FP64 state and right-hand side, defect correction around two FP32
+    V-cycles, all fields per launch) against plain FP64 solves looped over the fields (the
+    baseline: one fas_solve per field) and the stacked plain FP64 form."""
+    import numpy as np
+    import torch
+
+    import fas_inputs
+    from paper_2510_11152_amd import GrainGrowth, Grid, grain_rhs
+
+    sync = torch.cuda.synchronize
+    eta0 = torch.from_numpy(fas_inputs.grain_init(q, n).astype(np.float64)).to(dev)
+    kw = dict(h=1.0, dt=0.1, kappa=1.0, tol=1e-10, device=dev)
+    mixed = GrainGrowth(q, n, precision="mixed", inner=2, autotune=True, **kw)
+    stacked = GrainGrowth(q, n, precision="fp64", autotune=True, **kw)
+    g1 = Grid((n, n), 1.0, bc="periodic", coarsest=4, device=dev)
+    rhs = torch.empty_like(eta0)
+
+    def looped(eta):
+        cyc = []
+        for _ in range(steps):
+            grain_rhs(eta, 0.1, rhs)
+            for i in range(q):
+                if g1.solve(rhs[i], eta[i], 0.1, tol=1e-10) != 0:
+                    raise RuntimeError("a looped grain solve did not converge")
+                cyc.append(g1.stats()["cycles"])
+        return cyc
+
+    def run(model, eta):
+        return [model.step(eta) for _ in range(steps)]
+
+    res = {}
+    for name, fn in (("mixed", lambda e: run(mixed, e)), ("stacked_fp64", lambda e: run(stacked, e)),
+                     ("looped_fp64", looped)):
+        e = eta0.clone()
+        fn(e)  # warm-up (autotuning, descriptors)
+        e = eta0.clone()
+        t, cyc = _timed(lambda: fn(e), sync)
+        res[name] = (t / steps, e, cyc)
+    ref = res["looped_fp64"][1]
+    scale = ref.abs().max().item()
+    out = {"fields": q, "grid": [n, n], "tol": 1e-10, "steps_timed": steps,
+           "looped_fp64_s_per_step": res["looped_fp64"][0],
+           "stacked_fp64_s_per_step": res["stacked_fp64"][0],
+           "mixed_s_per_step": res["mixed"][0],
+           "mixed_inner_cycles": 2,
+           "mixed_outer_per_field": float(np.mean(res["mixed"][2][-1])),
+           "fp64_cycles_per_field": float(np.mean(res["stacked_fp64"][2][-1])),
+           "mixed_speedup_vs_looped_fp64": res["looped_fp64"][0] / res["mixed"][0],
+           "mixed_speedup_vs_stacked_fp64": res["stacked_fp64"][0] / res["mixed"][0],
+           "stacked_fp64_speedup_vs_looped": res["looped_fp64"][0] / res["stacked_fp64"][0],
+           "mixed_max_rel_diff_vs_looped_fp64": (res["mixed"][1] - ref).abs().max().item() / scale,
+           "stacked_fp64_equals_looped": bool(torch.equal(res["stacked_fp64"][1], ref))}
+    del res, ref, mixed, stacked, g1, rhs, eta0
+    torch.cuda.empty_cache()
     return out
 
 

@@ -237,6 +237,17 @@ int fas_grid_create_batched(int dim, const int64_t n[3], double h, int bc, int d
 int fas_solve_stacked(fas_grid_t grid, double dt, double kappa, const void* rhs, void* u, double tol, int nu1,
                       int nu2, int* status_out, int* cycles_out);
 
+/* The mixed-precision defect correction of fas_solve_mixed over every problem of stacked
+ * grids: g64 an FP64 grid and g32 an FP32 grid (FAS_FLAG_MIXED_INNER) of the same shape,
+ * spacing, boundary condition and batch, kappa constant.  Every evaluation of the FP64
+ * residuals, norms and stopping tests and every pass of the inner FP32 cycles serves all
+ * problems still iterating in one launch; problem b stops once
+ * ||rhs_b - A u_b|| <= tol ||rhs_b||, so its iterates are those of solving it alone.
+ * status_out / cycles_out (nullable, batch entries): status and outer corrections per
+ * problem.  Returns FAS_OK if all converged, else FAS_NOT_CONVERGED or FAS_ERR_NONFINITE. */
+int fas_solve_stacked_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, const void* rhs, void* u,
+                            double tol, int nu1, int nu2, int inner, int* status_out, int* cycles_out);
+
 /* Coefficient of one problem of an array-form batch: cell == NULL selects the constant
  * kappa = scalar, else cell is the finest-level cell field (grid dtype). */
 typedef struct {
@@ -269,8 +280,9 @@ int fas_solve_batched(int nprob, const fas_grid_t* grids, double dt, const fas_k
  * free energy sum_i (-eta_i^2/2 + eta_i^4/4) + (3/2) sum_{i<j} eta_i^2 eta_j^2, so
  *     f_i = eta_i - dt * ((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)),  S = sum_j eta_j^2,
  * and (I - dt kappa Lap) eta_i^{n+1} = f_i is then one batched solve.  eta, f: q fields
- * of ncells FP32 values each, contiguous, device; stream: hipStream_t. */
-int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f);
+ * of ncells values of `dtype` (FAS_F32 or FAS_F64) each, contiguous, device; S is summed
+ * in field order and every operation rounds in that precision; stream: hipStream_t. */
+int fas_grain_rhs(void* stream, int dtype, int q, int64_t ncells, double dt, const void* eta, void* f);
 
 /* Grain map of a grain-growth state (Section 3.3.1: a grain is a region where one order
  * parameter dominates): label[p] = the index i of the largest eta_i at cell p, the lowest

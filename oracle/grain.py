@@ -7,15 +7,16 @@ dt, has the right-hand side
 
     f_i = eta_i - dt * ((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)),  S = sum_j eta_j^2.
 
-Plain numpy in float32 (the precision of the batched FP32 solves), S summed field by
-field in index order; each operation rounds to float32 as written.
+Plain numpy in the state's precision (float32 for the FP32 solves, float64 for the FP64
+and mixed forms), S summed field by field in index order; each operation rounds in that
+precision as written.
 """
 import numpy as np
 
 
-def grain_rhs(eta, dt):
-    eta = np.asarray(eta, dtype=np.float32)
-    dt = np.float32(dt)
+def grain_rhs(eta, dt, dtype=np.float32):
+    eta = np.asarray(eta, dtype=dtype)
+    dt = dtype(dt)
     S = eta[0] * eta[0]
     for j in range(1, eta.shape[0]):
         S = S + eta[j] * eta[j]
@@ -23,7 +24,7 @@ def grain_rhs(eta, dt):
     for i in range(eta.shape[0]):
         e = eta[i]
         e2 = e * e
-        g = (e2 * e - e) + (np.float32(3.0) * e) * (S - e2)
+        g = (e2 * e - e) + (dtype(3.0) * e) * (S - e2)
         out[i] = e - dt * g
     return out
 

@@ -187,6 +187,23 @@ def solve_mixed(g64, g32, rhs, u, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1
                                         tol, nu1, nu2, inner), "fas_solve_mixed", allow_not_converged=True)
 
 
+def solve_stacked_mixed(g64, g32, rhs, u, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2, inner=2):
+    """FP64 defect correction around FP32 V-cycles for every problem of stacked grids
+    (g64 FP64, g32 FP32 with mixed_inner=True, the same batch); rhs, u shaped (batch,
+    *shape).  Returns (status per problem, outer corrections per problem)."""
+    want = (g64.batch,) + g64.shape()
+    for t, nm in ((rhs, "rhs"), (u, "u")):
+        if t.dtype != torch.float64 or t.device != g64.device or not t.is_contiguous() or tuple(t.shape) != want:
+            raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s" % (nm, want, g64.device))
+    st = (ctypes.c_int * g64.batch)()
+    cy = (ctypes.c_int * g64.batch)()
+    code = load().fas_solve_stacked_mixed(g64.handle, g32.handle, dt, kappa, _ptr(rhs), _ptr(u), tol, nu1, nu2,
+                                          inner, st, cy)
+    if code not in (_lib.FAS_OK, _lib.FAS_NOT_CONVERGED):
+        check(code, "fas_solve_stacked_mixed")
+    return list(st), list(cy)
+
+
 def heat(grid, u0, steps, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=2, keep=False):
     """Backward-Euler heat steps: rhs = u^n, warm start u = u^n, solve.  Returns u^T
     (and the list of states when keep=True)."""

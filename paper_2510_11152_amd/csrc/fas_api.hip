@@ -69,8 +69,8 @@ struct Layout {
 int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int batch, Layout* lay, std::string* why)
 {
     if (batch < 1) return *why = "batch must be >= 1", FAS_ERR_ARG;
-    if (batch > 1 && (flags & (FAS_FLAG_VARIABLE_KAPPA | FAS_FLAG_MIXED_INNER)))
-        return *why = "batched grids take a constant kappa and no mixed-precision storage", FAS_ERR_ARG;
+    if (batch > 1 && (flags & FAS_FLAG_VARIABLE_KAPPA))
+        return *why = "batched grids take a constant kappa", FAS_ERR_ARG;
     if (dim != 2 && dim != 3) return *why = "dim must be 2 or 3", FAS_ERR_ARG;
     if (dtype != FAS_F64 && dtype != FAS_F32) return *why = "dtype must be FAS_F64 or FAS_F32", FAS_ERR_ARG;
     if (flags & ~(FAS_FLAG_VARIABLE_KAPPA | FAS_FLAG_MIXED_INNER)) return *why = "unknown flags", FAS_ERR_ARG;
@@ -746,7 +746,7 @@ void check_solve_args(const fas_grid* g, const void* rhs, const void* u, int nu1
                       bool batched = false)
 {
     check_grid(g);
-    if (g->batch > 1 && !batched) throw Error(FAS_ERR_ARG, "batched grid: use fas_solve_batched");
+    if (g->batch > 1 && !batched) throw Error(FAS_ERR_ARG, "stacked grid: use fas_solve_stacked");
     if (!rhs || !u) throw Error(FAS_ERR_ARG, "null rhs or u");
     if (rhs == u) throw Error(FAS_ERR_ARG, "rhs and u must not alias");
     if (nu1 < 0 || nu2 < 0 || nu1 + nu2 == 0) throw Error(FAS_ERR_ARG, "need nu1, nu2 >= 0 and nu1 + nu2 > 0");
@@ -878,12 +878,17 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
 // pre pass starts from zero without reading e, and the last inner cycle's post pass adds
 // its result into u itself.  Every kernel, FP32 cycles included, checks the outer active
 // flag, so the host looks at the status only near the expected end, as in solve_impl.
+int solve_mixed_stacked(fas_grid* g64, fas_grid* g32, const void* rhs, void* u, double tol, int nu1, int nu2,
+                        int inner, bool tile_top, int* status_out, int* cycles_out);
+
 int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, const void* kcell, const void* rhs,
-                     void* u, double tol, int nu1, int nu2, int inner)
+                     void* u, double tol, int nu1, int nu2, int inner, bool stacked = false, int* status_out = nullptr,
+                     int* cycles_out = nullptr)
 {
-    check_solve_args(g64, rhs, u, nu1, nu2, tol);
+    check_solve_args(g64, rhs, u, nu1, nu2, tol, stacked);
     check_grid(g32);
-    if (g32->batch > 1) throw Error(FAS_ERR_ARG, "mixed precision takes single-problem grids");
+    if (g32->batch != g64->batch) throw Error(FAS_ERR_ARG, "the two grids must hold the same number of problems");
+    if (stacked && kcell) throw Error(FAS_ERR_ARG, "stacked grids take a constant kappa");
     if (g64->dtype != FAS_F64 || g32->dtype != FAS_F32 || !(g32->flags & FAS_FLAG_MIXED_INNER))
         throw Error(FAS_ERR_ARG, "need an FP64 grid and an FP32 grid created with FAS_FLAG_MIXED_INNER");
     if (g64->dim != g32->dim || g64->bc != g32->bc || g64->h != g32->h || g64->L != g32->L)
@@ -912,10 +917,6 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
     set_kappa(g32, kcell, true);
     memset(&g64->stats, 0, sizeof(g64->stats));
     ensure_host(g64);
-    char* const span = (char*)g64->rnorm;
-    const size_t span_bytes = (size_t)((char*)(g64->hist + fas::kHist) - span);
-    if (span_bytes > kHostStatus) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
-    auto host_at = [&](const void* dev) { return (char*)g64->host + ((const char*)dev - span); };
     while (g64->cyc_ev_created < 2)
         FAS_HIP_CHECK(hipEventCreateWithFlags(&g64->cyc_ev[g64->cyc_ev_created++], hipEventDisableTiming));
     fas::launch_init_active(g64);
@@ -923,6 +924,11 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
     g32->active = g64->active;
     g32->gate = 1;
     const bool tile_top = finest_is_tile(g32, nu1, nu2, kcell != nullptr);
+    if (stacked) return solve_mixed_stacked(g64, g32, rhs, u, tol, nu1, nu2, inner, tile_top, status_out, cycles_out);
+    char* const span = (char*)g64->rnorm;
+    const size_t span_bytes = (size_t)((char*)(g64->hist + fas::kHist) - span);
+    if (span_bytes > kHostStatus) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
+    auto host_at = [&](const void* dev) { return (char*)g64->host + ((const char*)dev - span); };
     const int kmax = std::min(g64->kmax, fas::kHist - 1);  // corrections
     // after a solve that took c corrections, evaluations 1 .. c are enqueued without a look
     const int horizon = g64->last_cycles > 0 ? g64->last_cycles : 0;
@@ -939,7 +945,7 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
     bool stopped = false;
     for (int k = 1; k <= kmax + 1; ++k) {
         const int np = fas::launch_mixed_resid(g64, g64->coef[0], g64->lev[0].kap, rhs, u, g32->mix_r, k == 1);
-        if (k == 1) fas::launch_sum_partials(g64, np, g64->rnorm, np);
+        if (k == 1) fas::launch_sum_partials(g64, np, g64->rnorm, g64->fpartials);
         fas::launch_sum_update(g64, np, tol, k);
         if ((k > horizon || k == kmax + 1) && (stopped = look())) break;
         if (k == kmax + 1) break;
@@ -972,6 +978,63 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
     if (status == FAS_OK) g64->last_cycles = corrections;
     if (status != FAS_OK) g_last_error = "not converged within kmax outer iterations";
     return status;
+}
+
+// The defect correction of solve_mixed_impl over every problem of stacked grids: each
+// evaluation's residual, norms and stopping tests, and each inner cycle, serve all
+// problems still iterating in one launch per pass.  The host reads the number still
+// active near the expected end (after a solve whose slowest problem took c corrections,
+// evaluations 1 .. c run without a look).  Every problem's iterates are those of its own
+// mixed solve.
+int solve_mixed_stacked(fas_grid* g64, fas_grid* g32, const void* rhs, void* u, double tol, int nu1, int nu2,
+                        int inner, bool tile_top, int* status_out, int* cycles_out)
+{
+    const int kmax = std::min(g64->kmax, fas::kHist - 1);
+    const int horizon = g64->last_cycles > 0 ? g64->last_cycles : 0;
+    g64->last_cycles = 0;
+    int* const hcount = (int*)g64->host;
+    for (int k = 1; k <= kmax + 1; ++k) {
+        const int np = fas::launch_mixed_resid(g64, g64->coef[0], nullptr, rhs, u, g32->mix_r, k == 1);
+        if (k == 1) fas::launch_sum_partials(g64, np, g64->rnorm, g64->fpartials);
+        fas::launch_sum_partials(g64, np);
+        fas::launch_update_active(g64, tol, k);
+        if (k > horizon || k == kmax + 1) {
+            FAS_HIP_CHECK(hipMemcpyAsync(hcount, g64->count, sizeof(int), hipMemcpyDeviceToHost, g64->stream));
+            FAS_HIP_CHECK(hipStreamSynchronize(g64->stream));
+            if (hcount[0] == 0) break;
+        }
+        if (k == kmax + 1) break;
+        for (int m = 0; m < inner; ++m) {
+            g32->zero_start = m == 0 && tile_top;
+            g32->accum64 = m == inner - 1 && tile_top ? (double*)u : nullptr;
+            if (m == 0 && !tile_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
+            vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
+        }
+        g32->zero_start = 0;
+        g32->accum64 = nullptr;
+        if (!tile_top) fas::launch_update_mixed(g64, g32->mix_e, u);
+    }
+    // cyc[b]: evaluation at which problem b stopped (0: none, -k: not finite)
+    std::vector<int> cyc((size_t)g64->batch);
+    FAS_HIP_CHECK(hipMemcpyAsync(cyc.data(), g64->cyc, cyc.size() * sizeof(int), hipMemcpyDeviceToHost, g64->stream));
+    FAS_HIP_CHECK(hipStreamSynchronize(g64->stream));
+    int worst = FAS_OK, maxc = 0;
+    for (int b = 0; b < g64->batch; ++b) {
+        const int c = cyc[(size_t)b];
+        const int st = c > 0 ? FAS_OK : (c < 0 ? FAS_ERR_NONFINITE : FAS_NOT_CONVERGED);
+        const int corrections = (c > 0 ? c : (c < 0 ? -c : kmax + 1)) - 1;
+        if (status_out) status_out[b] = st;
+        if (cycles_out) cycles_out[b] = corrections;
+        if (st == FAS_ERR_NONFINITE) worst = FAS_ERR_NONFINITE;
+        else if (st == FAS_NOT_CONVERGED && worst == FAS_OK) worst = FAS_NOT_CONVERGED;
+        maxc = std::max(maxc, corrections);
+    }
+    g64->stats.cycles = maxc;
+    g64->stats.status = worst;
+    if (worst == FAS_OK) g64->last_cycles = maxc;
+    if (worst == FAS_ERR_NONFINITE) throw Error(FAS_ERR_NONFINITE, "a residual norm is not finite");
+    if (worst == FAS_NOT_CONVERGED) g_last_error = "some problems did not converge within kmax outer iterations";
+    return worst;
 }
 
 int vcycle_impl(fas_grid* g, double dt, double kappa, const void* kcell, const void* rhs, void* u, int nu1, int nu2,
@@ -1658,6 +1721,15 @@ int fas_solve_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, con
     return guarded([&]() -> int { return solve_mixed_impl(g64, g32, dt, kappa, kappa_cell, rhs, u, tol, nu1, nu2, inner); });
 }
 
+int fas_solve_stacked_mixed(fas_grid_t g64, fas_grid_t g32, double dt, double kappa, const void* rhs, void* u,
+                            double tol, int nu1, int nu2, int inner, int* status_out, int* cycles_out)
+{
+    return guarded([&]() -> int {
+        return solve_mixed_impl(g64, g32, dt, kappa, nullptr, rhs, u, tol, nu1, nu2, inner, true, status_out,
+                                cycles_out);
+    });
+}
+
 int fas_solve_stacked(fas_grid_t g, double dt, double kappa, const void* rhs, void* u, double tol, int nu1, int nu2,
                       int* status_out, int* cycles_out)
 {
@@ -1736,11 +1808,12 @@ int fas_solve_batched(int nprob, const fas_grid_t* grids, double dt, const fas_k
     });
 }
 
-int fas_grain_rhs(void* stream, int q, int64_t ncells, double dt, const void* eta, void* f)
+int fas_grain_rhs(void* stream, int dtype, int q, int64_t ncells, double dt, const void* eta, void* f)
 {
     return guarded([&]() -> int {
         if (q < 1 || ncells < 1 || !eta || !f || eta == f) return fail(FAS_ERR_ARG, "bad grain-growth arguments");
-        fas::launch_grain_rhs((hipStream_t)stream, q, ncells, (float)dt, (const float*)eta, (float*)f);
+        if (dtype != FAS_F64 && dtype != FAS_F32) return fail(FAS_ERR_ARG, "dtype must be FAS_F64 or FAS_F32");
+        fas::launch_grain_rhs((hipStream_t)stream, dtype, q, ncells, dt, eta, f);
         return FAS_OK;
     });
 }

@@ -128,9 +128,9 @@ void launch_residual(const fas_grid* g, int l, const Coef& c, const void* kap, c
 // Partial sums of r^2 (r = f - A u) into g->partials then a fixed-order total into
 // g->norm_out[0]; rhs-only mode (u == nullptr) sums f^2.
 void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f, const void* u);
-// Fixed-order total of g->partials[offset..offset + count) into out[0] (default
-// g->norm_out).
-void launch_sum_partials(const fas_grid* g, int count, double* out = nullptr, int offset = 0);
+// Fixed-order total of src[b * count .. (b + 1) * count) (default g->partials) into out[b]
+// (default g->norm_out), for every problem b of g.
+void launch_sum_partials(const fas_grid* g, int count, double* out = nullptr, const double* src = nullptr);
 void launch_resid_restrict(const fas_grid* g, int l, const Coef& c, const void* kap, const void* f,
                            const void* u, void* uc, void* rc);
 void launch_coarse_rhs(const fas_grid* g, int lc, const Coef& c, const void* kapc, const void* uc, void* fc);
@@ -139,14 +139,15 @@ void launch_restrict(const fas_grid* g, int l, const void* fine, void* coarse);
 void launch_prolong_add(const fas_grid* g, int l, const void* cnew, const void* cold, void* fine);
 void launch_kappa_grad(const fas_grid* g, const Coef& c, const void* kap, const void* mu, const void* u,
                        void* gk);
-// Mixed precision, outer step (FP64 grid g, gated by its active flags): r = f - A u,
-// r32 = fp32(r), partial sums of r^2 in g->partials[0..count) and with fnorm of f^2 in
-// g->partials[count..2 count); returns count.
+// Mixed precision, outer step (FP64 grid g, gated by its active flags; problem b of a
+// stacked grid at b * cells): r = f - A u, r32 = fp32(r), partial sums of r^2 in
+// g->partials[b * count .. (b + 1) * count) and with fnorm of f^2 at the same places of
+// g->fpartials; returns count.
 int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const void* f, const void* u, void* r32,
                        bool fnorm);
-// u += fp64(e32) on the finest level of g (gated).
+// u += fp64(e32) on the finest level of g, every problem (gated).
 void launch_update_mixed(const fas_grid* g, const void* e32, void* u);
-// x[0..N) = 0 in FP32 (gated by g's active flags).
+// x = 0 in FP32, N cells per problem of g (gated by g's active flags).
 void launch_zero_f32(const fas_grid* g, int64_t N, void* x);
 void launch_cast_f32(const fas_grid* g, int64_t N, const void* src64, void* dst32);
 // Batched solves: every problem active, cycle counts zero.
@@ -160,7 +161,7 @@ void launch_update_active(const fas_grid* g, double tol, int k);
 void launch_sum_update(const fas_grid* g, int count, double tol, int k);
 // Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32):
 // S = sum_j eta_j^2; f_i = eta_i - dt*((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)).
-void launch_grain_rhs(hipStream_t stream, int q, int64_t N, float dt, const float* eta, float* f);
+void launch_grain_rhs(hipStream_t stream, int dtype, int q, int64_t N, double dt, const void* eta, void* f);
 // label[p] = the index of the largest of eta_0[p] .. eta_{q-1}[p] (lowest among equals).
 void launch_grain_argmax(hipStream_t stream, int q, int64_t N, const float* eta, int* label);
 

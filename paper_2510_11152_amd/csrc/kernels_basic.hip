@@ -455,9 +455,17 @@ template <int DIM, bool KV>
 __global__ __launch_bounds__(kBlock) void k_mixed_resid(Op<double> op, const double* __restrict__ f,
                                                         const double* __restrict__ u, float* __restrict__ r32,
                                                         double* __restrict__ rpart, double* __restrict__ fpart,
-                                                        const int* __restrict__ act)
+                                                        const int* __restrict__ act, int64_t stride)
 {
-    if (act && !act[0]) return;
+    // problem b = blockIdx.y of a stacked grid: arrays b * stride apart, partial sums per
+    // problem gridDim.x apart
+    const int b = (int)blockIdx.y;
+    if (act && !act[b]) return;
+    f += b * stride;
+    u += b * stride;
+    r32 += b * stride;
+    rpart += (int64_t)b * gridDim.x;
+    if (fpart) fpart += (int64_t)b * gridDim.x;
     const int half = op.n0 >> 1;
     const int64_t pairs = (int64_t)half * op.n1 * op.n2;
     double acc = 0.0, facc = 0.0;
@@ -502,22 +510,25 @@ __global__ __launch_bounds__(kBlock) void k_mixed_resid(Op<double> op, const dou
 }
 
 // u += fp64(e) (the outer update of the defect correction when no inner pass folds it).
+// Problem b = blockIdx.y of N cells (arrays b * N apart), gated by its active flag.
 __global__ __launch_bounds__(kBlock) void k_update_mixed(int64_t N, const float* __restrict__ e, double* __restrict__ u,
                                                          const int* __restrict__ act)
 {
-    if (act && !act[0]) return;
+    const int b = (int)blockIdx.y;
+    if (act && !act[b]) return;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    u[p] = u[p] + (double)e[p];
+    u[b * N + p] = u[b * N + p] + (double)e[b * N + p];
 }
 
-// x = 0 (FP32), gated by a solve's active flag.
+// x = 0 (FP32), problem b = blockIdx.y of N cells, gated by its active flag.
 __global__ __launch_bounds__(kBlock) void k_zero_f32(int64_t N, float* __restrict__ x, const int* __restrict__ act)
 {
-    if (act && !act[0]) return;
+    const int b = (int)blockIdx.y;
+    if (act && !act[b]) return;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    x[p] = 0.0f;
+    x[b * N + p] = 0.0f;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t N, const double* __restrict__ src,
@@ -574,14 +585,15 @@ __global__ __launch_bounds__(kBlock) void k_update_active(const double* __restri
 // W consecutive cells per thread (W = 2: float2 accesses, N even), the field loops
 // unrolled so that many fields' loads are in flight; each cell's sum over j keeps its
 // order.
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, float dt, const float* __restrict__ eta,
-                                                      float* __restrict__ f)
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, T dt, const T* __restrict__ eta,
+                                                      T* __restrict__ f)
 {
-    using V = typename std::conditional<W == 2, float2, float>::type;
+    using V2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    using V = typename std::conditional<W == 2, V2, T>::type;
     const int64_t p = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W;
     if (p >= N) return;
-    auto ld = [&](int64_t o, float* e) {
+    auto ld = [&](int64_t o, T* e) {
         if constexpr (W == 2) {
             const V v = *reinterpret_cast<const V*>(eta + o);
             e[0] = v.x;
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, float dt
             e[0] = eta[o];
         }
     };
-    float S[W], e[W];
+    T S[W], e[W];
     ld(p, e);
 #pragma unroll
     for (int c = 0; c < W; ++c) S[c] = e[c] * e[c];
@@ -603,11 +615,11 @@ __global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, float dt
 #pragma unroll 8
     for (int i = 0; i < q; ++i) {
         ld((int64_t)i * N + p, e);
-        float r[W];
+        T r[W];
 #pragma unroll
         for (int c = 0; c < W; ++c) {
-            const float e2 = e[c] * e[c];
-            const float g = (e2 * e[c] - e[c]) + (3.0f * e[c]) * (S[c] - e2);
+            const T e2 = e[c] * e[c];
+            const T g = (e2 * e[c] - e[c]) + ((T)3 * e[c]) * (S[c] - e2);
             r[c] = e[c] - dt * g;
         }
         if constexpr (W == 2) {
@@ -784,9 +796,9 @@ void launch_resid_norm(const fas_grid* g, int l, const Coef& c, const void* kap,
     launch_sum_partials(g, (int)nb);
 }
 
-void launch_sum_partials(const fas_grid* g, int count, double* out, int offset)
+void launch_sum_partials(const fas_grid* g, int count, double* out, const double* src)
 {
-    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(g->partials + offset, count,
+    k_sum_partials<<<(unsigned)g->batch, kSumBlock, 0, g->stream>>>(src ? src : g->partials, count,
                                                                     out ? out : g->norm_out);
     check_launch();
 }
@@ -854,16 +866,18 @@ int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const 
 {
     const Op<double> op = make_op<double>(g, 0, c, kap);
     const int64_t pairs = g->lev[0].N / 2;
-    // a fixed grid: at most half the partials buffer (the other half takes f^2)
-    unsigned nb = (unsigned)std::min<int64_t>((pairs + kBlock - 1) / kBlock, (int64_t)(g->npartials / 2));
+    // a fixed grid per problem: r^2 partial sums in g->partials, f^2 in g->fpartials
+    unsigned nb = (unsigned)std::min<int64_t>((pairs + kBlock - 1) / kBlock, (int64_t)(g->npartials / g->batch));
     if (nb > (unsigned)kPartials) nb = (unsigned)kPartials;
     const int* act = active_flags(g);
     auto F = (const double*)f;
     auto U = (const double*)u;
-    double* fp = fnorm ? g->partials + nb : nullptr;
+    double* fp = fnorm ? g->fpartials : nullptr;
     const bool kv = kap != nullptr;
+    const dim3 grid(nb, (unsigned)g->batch, 1);
+    const int64_t stride = g->lev[0].N;
 #define FAS_MIXED_RESID(D_, KV_) \
-    k_mixed_resid<D_, KV_><<<nb, kBlock, 0, g->stream>>>(op, F, U, (float*)r32, g->partials, fp, act)
+    k_mixed_resid<D_, KV_><<<grid, kBlock, 0, g->stream>>>(op, F, U, (float*)r32, g->partials, fp, act, stride)
     if (g->dim == 2) {
         if (kv) FAS_MIXED_RESID(2, true);
         else FAS_MIXED_RESID(2, false);
@@ -879,13 +893,14 @@ int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const 
 void launch_update_mixed(const fas_grid* g, const void* e32, void* u)
 {
     const int64_t N = g->lev[0].N;
-    k_update_mixed<<<blocks_for(N), kBlock, 0, g->stream>>>(N, (const float*)e32, (double*)u, active_flags(g));
+    k_update_mixed<<<grid2(blocks_for(N), g), kBlock, 0, g->stream>>>(N, (const float*)e32, (double*)u,
+                                                                      active_flags(g));
     check_launch();
 }
 
 void launch_zero_f32(const fas_grid* g, int64_t N, void* x)
 {
-    k_zero_f32<<<blocks_for(N), kBlock, 0, g->stream>>>(N, (float*)x, active_flags(g));
+    k_zero_f32<<<grid2(blocks_for(N), g), kBlock, 0, g->stream>>>(N, (float*)x, active_flags(g));
     check_launch();
 }
 
@@ -938,14 +953,24 @@ void launch_grain_argmax(hipStream_t stream, int q, int64_t N, const float* eta,
     check_launch();
 }
 
-void launch_grain_rhs(hipStream_t stream, int q, int64_t N, float dt, const float* eta, float* f)
+template <typename T>
+void launch_grain_rhs_t(hipStream_t stream, int q, int64_t N, T dt, const T* eta, T* f)
 {
-    // N even and 8-byte aligned arrays: float2 accesses stay aligned in every field
-    if (N % 2 == 0 && ((uintptr_t)eta % 8) == 0 && ((uintptr_t)f % 8) == 0)
-        k_grain_rhs<2><<<blocks_for(N / 2), kBlock, 0, stream>>>(q, N, dt, eta, f);
+    // N even and pair-aligned arrays: pair accesses stay aligned in every field
+    const uintptr_t al = 2 * sizeof(T);
+    if (N % 2 == 0 && ((uintptr_t)eta % al) == 0 && ((uintptr_t)f % al) == 0)
+        k_grain_rhs<T, 2><<<blocks_for(N / 2), kBlock, 0, stream>>>(q, N, dt, eta, f);
     else
-        k_grain_rhs<1><<<blocks_for(N), kBlock, 0, stream>>>(q, N, dt, eta, f);
+        k_grain_rhs<T, 1><<<blocks_for(N), kBlock, 0, stream>>>(q, N, dt, eta, f);
     check_launch();
+}
+
+void launch_grain_rhs(hipStream_t stream, int dtype, int q, int64_t N, double dt, const void* eta, void* f)
+{
+    if (dtype == FAS_F64)
+        launch_grain_rhs_t<double>(stream, q, N, dt, (const double*)eta, (double*)f);
+    else
+        launch_grain_rhs_t<float>(stream, q, N, (float)dt, (const float*)eta, (float*)f);
 }
 
 }  // namespace fas

@@ -14,43 +14,53 @@ import ctypes
 import torch
 
 from . import _lib
-from .api import Grid
+from .api import Grid, solve_stacked_mixed
+
+
+_DT = {torch.float32: _lib.FAS_F32, torch.float64: _lib.FAS_F64}
 
 
 def grain_rhs(eta, dt, out=None):
-    """f_i for every field; eta: (q, ny, nx) float32 contiguous on the device."""
-    if eta.dtype != torch.float32 or not eta.is_contiguous() or eta.dim() != 3:
-        raise ValueError("eta must be a contiguous float32 (q, ny, nx) tensor")
+    """f_i for every field; eta: (q, ...) float32 or float64 (2D or 3D fields), contiguous,
+    on the device (the right-hand side is computed in eta's precision)."""
+    if eta.dtype not in _DT or not eta.is_contiguous() or eta.dim() < 3:
+        raise ValueError("eta must be a contiguous float32 or float64 (q, ...) tensor of 2D or 3D fields")
     out = torch.empty_like(eta) if out is None else out
+    if out.shape != eta.shape or out.dtype != eta.dtype or not out.is_contiguous():
+        raise ValueError("out must match eta")
     stream = torch.cuda.current_stream(eta.device).cuda_stream
-    q, ny, nx = eta.shape
-    _lib.check(_lib.load().fas_grain_rhs(ctypes.c_void_p(stream), q, ny * nx, dt, ctypes.c_void_p(eta.data_ptr()),
-                                         ctypes.c_void_p(out.data_ptr())), "fas_grain_rhs")
+    q = eta.shape[0]
+    _lib.check(_lib.load().fas_grain_rhs(ctypes.c_void_p(stream), _DT[eta.dtype], q, eta.numel() // q, dt,
+                                         ctypes.c_void_p(eta.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+               "fas_grain_rhs")
     return out
 
 
 def grain_map(eta, out=None):
-    """Per cell, the index of the dominant order parameter (fas_grain_argmax); eta: (q, ny,
-    nx) float32 on the device.  Returns an int32 (ny, nx) tensor."""
-    if eta.dtype != torch.float32 or not eta.is_contiguous() or eta.dim() != 3:
-        raise ValueError("eta must be a contiguous float32 (q, ny, nx) tensor")
-    q, ny, nx = eta.shape
-    out = torch.empty((ny, nx), dtype=torch.int32, device=eta.device) if out is None else out
+    """Per cell, the index of the dominant order parameter (fas_grain_argmax); eta: (q, ...)
+    float32 on the device (2D or 3D fields).  Returns an int32 tensor of the field shape."""
+    if eta.dtype != torch.float32 or not eta.is_contiguous() or eta.dim() < 3:
+        raise ValueError("eta must be a contiguous float32 (q, ...) tensor of 2D or 3D fields")
+    q = eta.shape[0]
+    cells = eta.numel() // q
+    out = torch.empty(eta.shape[1:], dtype=torch.int32, device=eta.device) if out is None else out
+    if out.dtype != torch.int32 or not out.is_contiguous() or out.numel() != cells:
+        raise ValueError("out must be a contiguous int32 tensor of the field shape")
     stream = torch.cuda.current_stream(eta.device).cuda_stream
-    _lib.check(_lib.load().fas_grain_argmax(ctypes.c_void_p(stream), q, ny * nx, ctypes.c_void_p(eta.data_ptr()),
+    _lib.check(_lib.load().fas_grain_argmax(ctypes.c_void_p(stream), q, cells, ctypes.c_void_p(eta.data_ptr()),
                                             ctypes.c_void_p(out.data_ptr())), "fas_grain_argmax")
     return out
 
 
 def count_grains(label):
-    """Grains of a periodic grain map (numpy int array, ny x nx): connected regions (4-
-    neighbour, wrapped at the edges) of one dominant index.  Returns (grains, mean area in
+    """Grains of a periodic grain map (numpy int array, 2D or 3D): connected regions (face
+    neighbours, wrapped at the edges) of one dominant index.  Returns (grains, mean size in
     cells).  Host-side labelling by repeated minimum propagation over equal neighbours."""
     import numpy as np
     lab = np.asarray(label)
     comp = np.arange(lab.size, dtype=np.int64).reshape(lab.shape)
-    same = [(lab == np.roll(lab, s, axis=a)) for a, s in ((0, 1), (0, -1), (1, 1), (1, -1))]
-    shifts = ((0, 1), (0, -1), (1, 1), (1, -1))
+    shifts = tuple((a, s) for a in range(lab.ndim) for s in (1, -1))
+    same = [(lab == np.roll(lab, s, axis=a)) for a, s in shifts]
     while True:
         new = comp
         for (a, s), eq in zip(shifts, same):
@@ -65,21 +75,36 @@ def count_grains(label):
 
 
 class GrainGrowth:
-    """q fields on an n x n periodic grid, spacing h, time step dt, gradient coefficient
-    kappa; FP32 storage and solves (relative residual tol per field)."""
+    """q fields on an n^dim periodic grid, spacing h, time step dt, gradient coefficient
+    kappa, solved to relative residual tol per field.  precision: 'fp32' (FP32 state and
+    solves, one stacked grid), 'fp64' (FP64 state and solves) or 'mixed' (FP64 state,
+    right-hand side and defect correction around `inner` FP32 V-cycles, two stacked
+    grids)."""
 
     def __init__(self, q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, coarsest=4, nu1=2, nu2=2, device="cuda",
-                 graph=False, autotune=False):
+                 graph=False, autotune=False, precision="fp32", inner=2, dim=2):
+        if precision not in ("fp32", "fp64", "mixed"):
+            raise ValueError("precision must be 'fp32', 'fp64' or 'mixed'")
         self.q, self.n, self.h, self.dt, self.kappa, self.tol = q, n, h, dt, kappa, tol
-        self.nu1, self.nu2 = nu1, nu2
-        self.grid = Grid((n, n), h, bc="periodic", dtype=torch.float32, coarsest=coarsest, device=device, batch=q)
+        self.nu1, self.nu2, self.precision, self.inner = nu1, nu2, precision, inner
+        dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.grid = Grid((n,) * dim, h, bc="periodic", dtype=dtype, coarsest=coarsest, device=device, batch=q)
         self.grid.set(graph=graph, autotune=autotune)
+        self.inner_grid = None
+        if precision == "mixed":
+            self.inner_grid = Grid((n,) * dim, h, bc="periodic", dtype=torch.float32, coarsest=coarsest,
+                                   device=device, batch=q, mixed_inner=True).set(autotune=autotune)
         self.rhs = None
 
     def step(self, eta):
-        """Advance eta (q, n, n) in place by one step; returns per-field cycle counts."""
+        """Advance eta (q, n, n[, n]) in place by one step; returns per-field cycle counts (outer
+        corrections in the mixed form)."""
         self.rhs = grain_rhs(eta, self.dt, self.rhs)
-        st, cy = self.grid.solve_stacked(self.rhs, eta, self.dt, self.kappa, self.tol, self.nu1, self.nu2)
+        if self.inner_grid is not None:
+            st, cy = solve_stacked_mixed(self.grid, self.inner_grid, self.rhs, eta, self.dt, self.kappa, self.tol,
+                                         self.nu1, self.nu2, self.inner)
+        else:
+            st, cy = self.grid.solve_stacked(self.rhs, eta, self.dt, self.kappa, self.tol, self.nu1, self.nu2)
         if any(s != 0 for s in st):
             raise RuntimeError("grain-growth solve did not converge for %d fields" % sum(s != 0 for s in st))
         return cy

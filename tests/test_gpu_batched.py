@@ -18,7 +18,9 @@ TD = {np.float64: torch.float64, np.float32: torch.float32}
 
 @pytest.mark.parametrize("n,bc,dtype,coarsest", [((256, 256), "neumann", np.float64, 4), ((128, 128), "periodic", np.float32, 4),
                                                  ((512, 256), "dirichlet", np.float64, 4), ((64, 64), "neumann", np.float32, 4),
-                                                 ((16, 16, 16), "neumann", np.float64, 4)])
+                                                 ((16, 16, 16), "neumann", np.float64, 4),
+                                                 ((64, 64, 64), "periodic", np.float32, 4),
+                                                 ((64, 32, 32), "neumann", np.float64, 4)])
 def test_batch_members_equal_single_solves(n, bc, dtype, coarsest):
     from paper_2510_11152_amd import Grid
     B, dt, tol = 5, 2e-3, 1e-10 if dtype == np.float64 else 1e-5
@@ -299,3 +301,60 @@ def test_grain_map_is_the_dominant_field():
     lab = grain_map(torch.from_numpy(eta).to(DEV))
     torch.cuda.synchronize()
     assert np.array_equal(lab.cpu().numpy(), np.argmax(eta, axis=0).astype(np.int32))
+
+
+def test_grain_rhs_fp64_matches_oracle_bitwise():
+    from paper_2510_11152_amd import grain_rhs
+    eta = I.grain_init(q=29, n=64, seed=8).astype(np.float64)
+    eta[:, :8, :8] = np.random.default_rng(2).uniform(-1, 1, (29, 8, 8))
+    f = grain_rhs(torch.from_numpy(eta).to(DEV), 0.1)
+    torch.cuda.synchronize()
+    assert np.array_equal(f.cpu().numpy(), OG.grain_rhs(eta, 0.1, dtype=np.float64))
+
+
+@pytest.mark.parametrize("n,bc,inner", [((128, 128), "periodic", 2), ((256, 128), "neumann", 3), ((64, 64), "dirichlet", 2),
+                                        ((16, 16, 16), "neumann", 2)])
+def test_stacked_mixed_members_equal_single_mixed_solves(n, bc, inner):
+    """fas_solve_stacked_mixed: each member's iterate and outer-correction count equal its
+    own fas_solve_mixed (same kernels and stopping tests), and one member against the
+    oracle's mixed solve."""
+    from paper_2510_11152_amd import Grid, solve_mixed, solve_stacked_mixed
+    from parity_util import check_mixed
+    B, dt = 4, 1e-3
+    P = O.Problem(n=n, h=1.0 / n[0], dt=dt, bc=bc, coarsest=4, nuc=2)
+    shape = P.shape()
+    rhs = np.stack([I.random_field(shape, 1100 + b) * (b + 1) for b in range(B)])
+    u0 = np.stack([I.random_field(shape, 1200 + b) for b in range(B)])
+    g64 = Grid(n, P.h, bc=bc, batch=B)
+    g32 = Grid(n, P.h, bc=bc, dtype=torch.float32, batch=B, mixed_inner=True)
+    ub = torch.from_numpy(u0.copy()).to(DEV)
+    st, cy = solve_stacked_mixed(g64, g32, torch.from_numpy(rhs).to(DEV), ub, dt, tol=1e-10, inner=inner)
+    assert all(s == 0 for s in st), st
+    s64 = Grid(n, P.h, bc=bc)
+    s32 = Grid(n, P.h, bc=bc, dtype=torch.float32, mixed_inner=True)
+    for b in range(B):
+        us = torch.from_numpy(u0[b].copy()).to(DEV)
+        assert solve_mixed(s64, s32, torch.from_numpy(rhs[b].copy()).to(DEV), us, dt, tol=1e-10, inner=inner) == 0
+        assert s64.stats()["cycles"] == cy[b], (b, s64.stats()["cycles"], cy[b])
+        assert torch.equal(us, ub[b]), b
+    check_mixed(P, rhs[1], u0[1], ub[1].cpu().numpy(), cy[1], 1e-10, inner=inner)
+
+
+def test_grain_mixed_step_matches_oracle():
+    """One grain-growth step in the mixed form (FP64 state and right-hand side, FP32 inner
+    cycles, tol 1e-10) on 10 fields of 128^2: the right-hand side bit for bit and each
+    field's defect correction against the oracle's mixed solve."""
+    from paper_2510_11152_amd import GrainGrowth
+    from parity_util import check_mixed
+    q, n, dt = 10, 128, 0.1
+    eta0 = I.grain_init(q=q, n=n, seed=9).astype(np.float64)
+    eta0 += 0.3 * np.sin(np.arange(n) / 5.0)[None, None, :] * (np.arange(q) % 2 == 0)[:, None, None]
+    model = GrainGrowth(q, n, h=1.0, dt=dt, kappa=1.0, tol=1e-10, precision="mixed", inner=2)
+    eta = torch.from_numpy(eta0).to(DEV)
+    cy = model.step(eta)
+    f = OG.grain_rhs(eta0, dt, dtype=np.float64)
+    assert np.array_equal(model.rhs.cpu().numpy(), f)
+    P = O.Problem(n=(n, n), h=1.0, dt=dt, kappa=1.0, bc="periodic", coarsest=4, nuc=2)
+    got = eta.cpu().numpy()
+    for i in range(q):
+        check_mixed(P, f[i], eta0[i], got[i], cy[i], 1e-10, inner=2)

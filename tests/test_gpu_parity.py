@@ -550,7 +550,7 @@ def test_full_size_2048_cell_kappa_vcycle_matches_oracle(transposed):
 
 
 @pytest.mark.parametrize("where", ["rhs", "u"])
-@pytest.mark.parametrize("form", ["plain", "mixed", "stacked", "array"])
+@pytest.mark.parametrize("form", ["plain", "mixed", "stacked", "array", "stacked_mixed"])
 def test_non_finite_input_is_reported(where, form):
     """A NaN in the right-hand side or the initial guess makes the residual norm NaN; the
     solve stops with FAS_ERR_NONFINITE (raised as FasError) instead of iterating to kmax."""
@@ -566,6 +566,12 @@ def test_non_finite_input_is_reported(where, form):
             grid_for(P, np.float64).solve(dev(f), dev(u), P.dt, tol=1e-10)
         elif form == "mixed":
             solve_mixed(grid_for(P, np.float64), grid_for(P, np.float32, mixed=True), dev(f), dev(u), P.dt, tol=1e-10)
+        elif form == "stacked_mixed":
+            from paper_2510_11152_amd import solve_stacked_mixed
+            g64, g32 = Grid((n, n), P.h, batch=3), Grid((n, n), P.h, dtype=torch.float32, batch=3, mixed_inner=True)
+            F = dev(np.stack([I.random_field(P.shape(), 91), f, I.random_field(P.shape(), 92)]))
+            U = dev(np.stack([I.random_field(P.shape(), 93), u, I.random_field(P.shape(), 94)]))
+            solve_stacked_mixed(g64, g32, F, U, P.dt, tol=1e-10)
         elif form == "stacked":
             gb = Grid((n, n), P.h, batch=3)
             F = dev(np.stack([I.random_field(P.shape(), 91), f, I.random_field(P.shape(), 92)]))

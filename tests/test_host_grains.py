@@ -38,3 +38,13 @@ def test_count_grains_matches_bfs(seed, k, shape):
     g, area = count_grains(lab)
     assert g == _bfs_count(lab)
     assert area == pytest.approx(lab.size / g)
+
+
+def test_growth_law_fit_recovers_the_exponent():
+    """R^m = R0^m + k t sampled exactly: the fit picks m and k back (m = 2 curvature-driven
+    growth in 2D, m = 3 for comparison)."""
+    from paper_2510_11152_amd.grain_run import fit_growth_law
+    t = np.linspace(50.0, 1000.0, 25)
+    for m, r0, k in ((2.0, 3.0, 0.5), (3.0, 2.0, 0.2)):
+        best, fits = fit_growth_law(t, (r0 ** m + k * t) ** (1.0 / m))
+        assert abs(best["m"] - m) < 1e-9 and abs(best["k"] - k) < 1e-9 and best["r2"] > 1 - 1e-12

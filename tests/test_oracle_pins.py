@@ -461,3 +461,7 @@ def test_grain_rhs_is_the_free_energy_derivative():
     a = G.grain_rhs(eta.astype(np.float32), 0.1).astype(np.float64)
     b = G.grain_rhs_reference(eta.astype(np.float32).astype(np.float64), 0.1)
     np.testing.assert_allclose(a, b, rtol=0, atol=2e-6)
+    # the FP64 form: a central difference with step 1e-5 of the quartic energy is off by
+    # h^2/6 times its third derivative (below 1e-9 here) plus rounding (about 1e-11 / h)
+    a64 = G.grain_rhs(eta, 0.1, dtype=np.float64)
+    np.testing.assert_allclose(a64, G.grain_rhs_reference(eta, 0.1), rtol=0, atol=1e-8)
