@@ -104,6 +104,11 @@ extern "C" {
                                    in reverse order (the 1234-4321 sequence of Section 2.3);
                                    0 (default): every sweep in order (1234-1234)          */
 
+#define FAS_OPT_ATOL 12          /* >= 0 (any double): a solve also stops once ||f - A u||_2 <= atol
+                                   (Algorithm 1 tests an absolute residual; the relative test
+                                   of fas_solve is this library's default); 0 (default): none.
+                                   For every solve form; stacked problems share the grid's value */
+
 /* FAS_OPT_ORDER values.  A set is written by the parities of its cells' 1-based indices
  * along x, y (, z), o = odd, e = even:
  *   X: 2D oe eo ee oo;  3D oee eoe eeo ooo oeo eoo eee ooe (Appendix B, sets 1-8)

@@ -35,6 +35,7 @@ class _OgProblem(ctypes.Structure):
         ("nuc", ctypes.c_int),
         ("order", ctypes.c_int),
         ("symmetric", ctypes.c_int),
+        ("atol", ctypes.c_double),
     ]
 
 
@@ -90,6 +91,7 @@ class Problem:
     nuc: int = 2
     order: str = "x"          # multi-colour set order of a sweep: "x", "u" or "z" (Section 2.3)
     symmetric: bool = False   # every second sweep in reverse set order (1234-4321)
+    atol: float = 0.0         # a solve also stops once ||f - A u||_2 <= atol (Algorithm 1's absolute test)
     _c: _OgProblem = field(default=None, repr=False, compare=False)
 
     @property
@@ -105,6 +107,7 @@ class Problem:
         p.h, p.dt, p.kappa = float(self.h), float(self.dt), float(self.kappa)
         p.coarsest, p.nuc = int(self.coarsest), int(self.nuc)
         p.order, p.symmetric = ORDERS[self.order], int(bool(self.symmetric))
+        p.atol = float(self.atol)
         return p
 
     def shape(self, lev=0):
@@ -187,7 +190,7 @@ def vcycle(P, f, u, nu1=2, nu2=2, transposed=False, kap=None):
 
 
 def solve(P, f, u, tol=1e-10, nu1=2, nu2=2, kmax=100, transposed=False, kap=None):
-    """V-cycles until ||f - A u|| <= tol*||f||.  Returns (status, cycles, rel_hist)."""
+    """V-cycles until ||f - A u|| <= tol*||f|| (or <= P.atol).  Returns (status, cycles, rel_hist)."""
     _check(P, 0, f, u, kap)
     hist = np.zeros(kmax, dtype=np.float64)
     cyc = ctypes.c_int(0)

@@ -35,6 +35,8 @@ typedef struct {
     int nuc;       /* sweeps on the coarsest level (Remark 1: smoothing, no direct solve) */
     int order;     /* multi-colour set order of a sweep: OG_X (default), OG_U or OG_Z */
     int symmetric; /* 1: every second sweep visits the sets in reverse (1234-4321) */
+    double atol;   /* absolute stopping tolerance on ||f - A u||_2 (0: none); Algorithm 1 tests
+                      an absolute residual, the relative test is this build's default */
 } og_problem;
 
 #define OG_X 0
@@ -147,7 +149,7 @@ static int og_diag_count(const og_problem* P, int nout)
 
 /* Mixed precision (the paper is silent): FP64 defect correction
  * around FP32 V-cycles.  Per outer iteration:
- *     r = f - A u (FP64);  rho = ||r||;  stop if rho <= tol*||f||
+ *     r = f - A u (FP64);  rho = ||r||;  stop if rho <= tol*||f|| or rho <= P->atol
  *     r32 = fp32(r);  e = 0;  `inner` FP32 V-cycles on A e = r32
  *     u = u + fp64(e)
  * The residual is not rescaled before the cast: FP32 arithmetic is exact under scaling
@@ -174,7 +176,7 @@ int og_solve_mixed(const og_problem* P, const double* kap0, const double* f, dou
         og_residual_d(P, 0, kap0, f, u, r);
         double rho = norm2_d(N, r);
         if (hist) hist[it] = nf > 0.0 ? rho / nf : rho;
-        if (rho <= tol * nf || rho == 0.0) {
+        if (rho <= tol * nf || rho <= P->atol || rho == 0.0) {
             status = 0;
             break;
         }

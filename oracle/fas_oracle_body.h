@@ -338,8 +338,8 @@ int F(og_vcycle)(const og_problem* P, const REAL* kap0, const REAL* f, REAL* u, 
     return 0;
 }
 
-/* Solve loop (Alg. 1 outer loop): V-cycles until ||f - L(u)||_2 <= tol*||f||_2 or kmax
- * cycles.  hist (nullable, kmax entries) receives ||r||_2/||f||_2 after each cycle.
+/* Solve loop (Alg. 1 outer loop): V-cycles until ||f - L(u)||_2 <= tol*||f||_2 (or, with
+ * P->atol > 0, ||f - L(u)||_2 <= P->atol: Algorithm 1's absolute test) or kmax cycles.  hist (nullable, kmax entries) receives ||r||_2/||f||_2 after each cycle.
  * Returns 0 when converged, 1 when kmax was reached, -1 on a bad shape. */
 int F(og_solve)(const og_problem* P, const REAL* kap0, const REAL* f, REAL* u, double tol, int nu1, int nu2,
                 int kmax, int transposed, int* cycles, double* hist)
@@ -357,7 +357,7 @@ int F(og_solve)(const og_problem* P, const REAL* kap0, const REAL* f, REAL* u, d
         F(og_residual)(P, 0, kap0, f, u, H.r);
         double nr = F(norm2)(N, H.r);
         if (hist) hist[k - 1] = nf > 0.0 ? nr / nf : nr;
-        if (nr <= tol * nf || nr == 0.0) {
+        if (nr <= tol * nf || nr <= P->atol || nr == 0.0) {
             status = 0;
             break;
         }

@@ -67,9 +67,10 @@ class Grid:
         return tuple(m >> level for m in reversed(self.n))
 
     def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None,
-            seg_rows=None, tile=None, tile_waves=None, order=None, symmetric=None):
+            seg_rows=None, tile=None, tile_waves=None, order=None, symmetric=None, atol=None):
         """Solver options (fas_grid_set).  order: smoother set order 'x' (default), 'u' or
-        'z'; symmetric: every second sweep in reverse set order (1234-4321)."""
+        'z'; symmetric: every second sweep in reverse set order (1234-4321); atol: a solve
+        also stops once ||rhs - A u||_2 <= atol (0: none)."""
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -93,6 +94,8 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_ORDER, float(_lib.FAS_ORDER[order])), "fas_grid_set")
         if symmetric is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_SYMMETRIC, float(int(symmetric))), "fas_grid_set")
+        if atol is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_ATOL, float(atol)), "fas_grid_set")
         return self
 
     def profile(self, reset=True):

@@ -1295,6 +1295,7 @@ void build_table_problem(TableProblem& P, const void* rhs, void* u, int nu1, int
     sd.act = g->active;
     sd.cyc = g->cyc;
     sd.hist = g->hist;
+    sd.atol2 = g->atol * g->atol;
     memcpy(d.data(), &sd, sizeof(sd));
     P.host = (char*)g->host + kHostStatus;
     if (!g->desc_valid || memcmp(P.host, d.data(), fas::kDescBytes) != 0) {
@@ -1542,6 +1543,12 @@ int fas_grid_set(fas_grid_t g, int option, double value)
 {
     return guarded([&]() -> int {
         check_grid(g);
+        if (option == FAS_OPT_ATOL) {
+            if (!(value >= 0.0) || !isfinite(value)) return fail(FAS_ERR_ARG, "atol must be finite and >= 0");
+            g->atol = value;
+            g->desc_valid = 0;  // the batched solve's status descriptor holds it
+            return FAS_OK;
+        }
         const int v = (int)value;
         if ((double)v != value) return fail(FAS_ERR_ARG, "option value must be an integer");
         if (option != FAS_OPT_KMAX && option != FAS_OPT_PROFILE) drop_graph(g);

@@ -29,6 +29,7 @@ struct StatusDesc {
     int* act;                 // still iterating
     int* cyc;                 // cycle of the stop (0: none yet; -k: not finite at k)
     double* hist;             // squared norms after cycles 1..kHist
+    double atol2;             // absolute stopping tolerance, squared (0: none)
 };
 
 // ---- 2D tile passes (kernels_tile2d.hip) -------------------------------------------------

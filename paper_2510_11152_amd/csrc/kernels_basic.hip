@@ -208,9 +208,9 @@ __global__ __launch_bounds__(kSumBlock) void k_sum_partials(const double* __rest
 // (as k_update_active) in one launch.
 __global__ __launch_bounds__(kSumBlock) void k_sum_update(const double* __restrict__ partials, int count,
                                                            double* __restrict__ norm2, const double* __restrict__ rnorm2,
-                                                           double tol2, int k, int* __restrict__ act,
-                                                           int* __restrict__ cyc, int* __restrict__ alive,
-                                                           double* __restrict__ hist)
+                                                           double tol2, double atol2, int k,
+                                                           int* __restrict__ act, int* __restrict__ cyc,
+                                                           int* __restrict__ alive, double* __restrict__ hist)
 {
     const double nr = sum_block(partials, count);
     if (threadIdx.x != 0) return;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kSumBlock) void k_sum_update(const double* __restri
         if (!isfinite(nr)) {
             act[0] = 0;
             cyc[0] = -k;
-        } else if (nr <= tol2 * rnorm2[0] || nr == 0.0) {
+        } else if (nr <= tol2 * rnorm2[0] || nr <= atol2 || nr == 0.0) {
             act[0] = 0;
             cyc[0] = k;
         }
@@ -549,9 +549,10 @@ __global__ __launch_bounds__(kBlock) void k_init_active(int* act, int* cyc, int 
 }
 
 __global__ __launch_bounds__(kBlock) void k_update_active(const double* __restrict__ norm2,
-                                                          const double* __restrict__ rnorm2, double tol2, int k,
-                                                          int* __restrict__ act, int* __restrict__ cyc, int nb,
-                                                          int* __restrict__ count, double* __restrict__ hist)
+                                                          const double* __restrict__ rnorm2, double tol2,
+                                                          double atol2, int k, int* __restrict__ act,
+                                                          int* __restrict__ cyc, int nb, int* __restrict__ count,
+                                                          double* __restrict__ hist)
 {
     __shared__ int red[kBlock];
     int alive = 0;
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_update_active(const double* __restri
         if (!isfinite(nr)) {
             act[b] = 0;
             cyc[b] = -k;
-        } else if (nr <= tol2 * rnorm2[b] || nr == 0.0) {
+        } else if (nr <= tol2 * rnorm2[b] || nr <= atol2 || nr == 0.0) {
             act[b] = 0;
             cyc[b] = k;
         } else {
@@ -671,7 +672,7 @@ __global__ __launch_bounds__(kSumBlock) void k_batch_update(TableLaunch t, doubl
     if (!isfinite(nr)) {
         d.act[0] = 0;
         d.cyc[0] = -k;
-    } else if (nr <= tol2 * d.rnorm[0] || nr == 0.0) {
+    } else if (nr <= tol2 * d.rnorm[0] || nr <= d.atol2 || nr == 0.0) {
         d.act[0] = 0;
         d.cyc[0] = k;
     }
@@ -806,7 +807,8 @@ void launch_sum_partials(const fas_grid* g, int count, double* out, const double
 void launch_sum_update(const fas_grid* g, int count, double tol, int k)
 {
     if (g->batch != 1) throw Error(FAS_ERR_ARG, "internal: the fused norm update takes one problem");
-    k_sum_update<<<1, kSumBlock, 0, g->stream>>>(g->partials, count, g->norm_out, g->rnorm, tol * tol, k, g->active,
+    k_sum_update<<<1, kSumBlock, 0, g->stream>>>(g->partials, count, g->norm_out, g->rnorm, tol * tol,
+                                                 g->atol * g->atol, k, g->active,
                                                   g->cyc, g->count, g->hist);
     check_launch();
 }
@@ -922,7 +924,8 @@ void launch_init_active(const fas_grid* g)
 
 void launch_update_active(const fas_grid* g, double tol, int k)
 {
-    k_update_active<<<1, kBlock, 0, g->stream>>>(g->norm_out, g->rnorm, tol * tol, k, g->active, g->cyc, g->batch,
+    k_update_active<<<1, kBlock, 0, g->stream>>>(g->norm_out, g->rnorm, tol * tol, g->atol * g->atol, k, g->active,
+                                                 g->cyc, g->batch,
                                                  g->count, g->batch == 1 ? g->hist : nullptr);
     check_launch();
 }

@@ -76,20 +76,22 @@ def count_grains(label):
 
 class GrainGrowth:
     """q fields on an n^dim periodic grid, spacing h, time step dt, gradient coefficient
-    kappa, solved to relative residual tol per field.  precision: 'fp32' (FP32 state and
+    kappa, solved to relative residual tol per field (or absolute residual atol: a field
+    whose grains have vanished decays towards zero, where a relative test is out of reach
+    in FP32).  precision: 'fp32' (FP32 state and
     solves, one stacked grid), 'fp64' (FP64 state and solves) or 'mixed' (FP64 state,
     right-hand side and defect correction around `inner` FP32 V-cycles, two stacked
     grids)."""
 
     def __init__(self, q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, coarsest=4, nu1=2, nu2=2, device="cuda",
-                 graph=False, autotune=False, precision="fp32", inner=2, dim=2):
+                 graph=False, autotune=False, precision="fp32", inner=2, dim=2, atol=0.0):
         if precision not in ("fp32", "fp64", "mixed"):
             raise ValueError("precision must be 'fp32', 'fp64' or 'mixed'")
         self.q, self.n, self.h, self.dt, self.kappa, self.tol = q, n, h, dt, kappa, tol
         self.nu1, self.nu2, self.precision, self.inner = nu1, nu2, precision, inner
         dtype = torch.float32 if precision == "fp32" else torch.float64
         self.grid = Grid((n,) * dim, h, bc="periodic", dtype=dtype, coarsest=coarsest, device=device, batch=q)
-        self.grid.set(graph=graph, autotune=autotune)
+        self.grid.set(graph=graph, autotune=autotune, atol=atol)
         self.inner_grid = None
         if precision == "mixed":
             self.inner_grid = Grid((n,) * dim, h, bc="periodic", dtype=torch.float32, coarsest=coarsest,

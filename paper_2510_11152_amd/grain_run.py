@@ -7,7 +7,8 @@ and the growth law R^m - R_0^m = k t fitted to it.
 A grain is a connected region (face neighbours, periodic) where one order parameter is the
 largest (fas_grain_argmax on the GPU, labelling on the host); R = sqrt(A / pi) in 2D and
 (3 V / (4 pi))^(1/3) in 3D from the mean grain size.  Initial state: eta_i uniform in
-(-0.001, 0.001) from the seed, h = 1, dt = 0.1, kappa = 1, FP32 solves to 1e-6.
+(-0.001, 0.001) from the seed, h = 1, dt = 0.1, kappa = 1, FP32 solves to a relative
+residual of 1e-6, or an absolute one of 1e-6 sqrt(cells) (a field of order one).
 """
 import argparse
 import json
@@ -56,7 +57,10 @@ def main(argv=None):
     dev = torch.device("cuda", 0)
     shape = (a.q,) + (a.n,) * a.dim
     eta = torch.from_numpy(np.random.default_rng(a.seed).uniform(-0.001, 0.001, shape).astype(np.float32)).to(dev)
-    model = GrainGrowth(a.q, a.n, dt=0.1, kappa=1.0, tol=1e-6, device=dev, dim=a.dim)
+    # absolute floor: tol times the norm of one field of order one over the grid, so a field
+    # whose grains have all vanished (its values decaying towards zero) stops at once
+    atol = 1e-6 * math.sqrt(a.n ** a.dim)
+    model = GrainGrowth(a.q, a.n, dt=0.1, kappa=1.0, tol=1e-6, device=dev, dim=a.dim, atol=atol)
     rows = []
     lab = torch.empty(shape[1:], dtype=torch.int32, device=dev)
     t_solve = 0.0

@@ -117,6 +117,10 @@ def test_solve_argument_errors_without_gpu(lib):
         assert lib.fas_grid_set(g, F.FAS_OPT_SYMMETRIC, 2) == F.FAS_ERR_ARG
         assert lib.fas_grid_set(g, F.FAS_OPT_SYMMETRIC, 1) == F.FAS_OK
         assert lib.fas_grid_set(g, F.FAS_OPT_SYMMETRIC, 0) == F.FAS_OK
+        for bad in (-1e-9, float("nan"), float("inf")):   # absolute tolerance: finite, >= 0
+            assert lib.fas_grid_set(g, F.FAS_OPT_ATOL, bad) == F.FAS_ERR_ARG
+        for good in (0.0, 1.5e-9, 3.0):
+            assert lib.fas_grid_set(g, F.FAS_OPT_ATOL, good) == F.FAS_OK
         assert lib.fas_restrict(g, 4, buf, ctypes.c_void_p(1 << 23)) == F.FAS_ERR_ARG     # no coarser level
         assert lib.fas_kappa_grad(g, 1e-3, None, buf, buf, buf) == F.FAS_ERR_ARG
     finally:

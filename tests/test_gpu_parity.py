@@ -584,3 +584,48 @@ def test_non_finite_input_is_reported(where, form):
             U = [dev(u), dev(I.random_field((2 * n, 2 * n), 96))]
             solve_batched(gs, F, U, P.dt, tol=1e-10)
     assert e.value.code == FAS_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("form", ["plain", "mixed", "stacked", "array"])
+def test_absolute_tolerance_matches_oracle(form):
+    """FAS_OPT_ATOL (Algorithm 1's absolute test): with the relative test off, a solve stops
+    at the oracle's cycle, the first whose ||f - A u||_2 <= atol; a stacked or array-form
+    member whose right-hand side is tiny stops after its first cycle."""
+    from paper_2510_11152_amd import Grid, solve_batched, solve_mixed, solve_stacked_mixed
+    n = 256
+    P0 = _problem((n, n), 4, "periodic", dt=2e-3, kappa=1.0)
+    f = I.random_field(P0.shape(), 120)
+    u0 = np.zeros_like(f)
+    st, cyc, hist = O.solve(P0, f, u0.copy(), 1e-12)
+    nf = np.sqrt(np.sum(f * f))
+    k = max(2, cyc // 2)
+    atol = 0.5 * (hist[k - 2] + hist[k - 1]) * nf  # between cycle k-1's and cycle k's residual
+    P = _problem((n, n), 4, "periodic", dt=2e-3, kappa=1.0)
+    P.atol = atol
+    if form == "plain":
+        g = grid_for(P, np.float64).set(atol=atol)
+        ug = dev(u0)
+        assert g.solve(dev(f), ug, P.dt, tol=0.0) == 0
+        check_solve(P, f, u0, host(ug), g.stats()["cycles"], 0.0)
+        assert g.stats()["cycles"] == k
+    elif form == "mixed":
+        g64, g32 = grid_for(P, np.float64).set(atol=atol), grid_for(P, np.float32, mixed=True)
+        ug = dev(u0)
+        assert solve_mixed(g64, g32, dev(f), ug, P.dt, tol=0.0) == 0
+        check_mixed(P, f, u0, host(ug), g64.stats()["cycles"], 0.0)
+    else:
+        tiny = f * 1e-30
+        if form == "stacked":
+            gb = Grid((n, n), P.h, bc="periodic", batch=2).set(atol=atol)
+            U = dev(np.stack([u0, u0]))
+            st, cy = gb.solve_stacked(dev(np.stack([f, tiny])), U, P.dt, tol=0.0)
+        else:
+            gs = [Grid((n, n), P.h, bc="periodic").set(atol=atol), Grid((n, n), P.h, bc="periodic").set(atol=atol)]
+            U = [dev(u0), dev(u0)]
+            st = solve_batched(gs, [dev(f), dev(tiny)], U, P.dt, tol=0.0)
+            cy = [g.stats()["cycles"] for g in gs]
+        assert st == [0, 0] and cy == [k, 1], (st, cy)
+        uo = u0.copy()
+        for _ in range(k):
+            O.vcycle(P, f, uo, 2, 2)
+        assert np.array_equal(host(U[0]), uo)

@@ -465,3 +465,25 @@ def test_grain_rhs_is_the_free_energy_derivative():
     # h^2/6 times its third derivative (below 1e-9 here) plus rounding (about 1e-11 / h)
     a64 = G.grain_rhs(eta, 0.1, dtype=np.float64)
     np.testing.assert_allclose(a64, G.grain_rhs_reference(eta, 0.1), rtol=0, atol=1e-8)
+
+
+# ---------------------------------------------------------------- absolute stopping test
+def test_absolute_tolerance_stops_at_the_first_small_residual():
+    """Algorithm 1's absolute test: with tol = 0 and atol > 0 the solve stops after the
+    first cycle whose ||f - A u||_2, evaluated here with the dense matrix, is <= atol; and
+    not a cycle earlier."""
+    P = O.Problem(n=(16, 16), h=1 / 16, dt=0.5, kappa=1.0, bc="dirichlet", coarsest=2, nuc=2)
+    A = C.assemble_dense(P)
+    f = I.random_field(P.shape(), 3)
+    res = []
+    u = np.zeros_like(f)
+    for _ in range(8):
+        O.vcycle(P, f, u, 2, 2)
+        res.append(np.linalg.norm(f.ravel() - A @ u.ravel()))
+    k = 5
+    atol = 0.5 * (res[k - 2] + res[k - 1])  # between cycle k-1's and cycle k's residual
+    Pa = O.Problem(n=(16, 16), h=1 / 16, dt=0.5, kappa=1.0, bc="dirichlet", coarsest=2, nuc=2, atol=atol)
+    u = np.zeros_like(f)
+    st, cyc, _ = O.solve(Pa, f, u, tol=0.0, kmax=50)
+    assert st == 0 and cyc == k
+    assert np.linalg.norm(f.ravel() - A @ u.ravel()) <= atol
