@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--inner3d", type=int, default=4,
                     help="FP32 V-cycles per outer correction (3D mixed form; 4 reaches 1e-10 in two corrections)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule for the 8192^2 grids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="batched,adjoint,3d,orders",
                     help="other workloads timed after the headline (comma list; 'none' to skip; "
@@ -512,7 +513,8 @@ def main():
     u0_h = fas_inputs.heat_2d_large(n)
     u0 = torch.from_numpy(u0_h).to(dev)
 
-    g = Grid((n, n), 1.0 / n, dtype=torch.float64, coarsest=4, device=dev)
+    # tile shapes picked by the library's autotuner on the first (warm-up) solve
+    g = Grid((n, n), 1.0 / n, dtype=torch.float64, coarsest=4, device=dev).set(autotune=not args.no_autotune)
     rhs = torch.empty_like(u0)
 
     def step_plain(u):
@@ -522,7 +524,12 @@ def main():
             raise RuntimeError("plain solve did not converge")
         return g.stats()["cycles"]
 
-    # warm-up, then the timed steps
+    # plan time: with autotuning, one V-cycle times the tile-shape candidates of every level
+    # (kept by the grid), then the warm-up steps, then the timed steps
+    if not args.no_autotune:
+        tune = u0.clone()
+        g.vcycle(u0, tune, dt)
+        del tune
     u = u0.clone()
     for _ in range(args.warmup):
         step_plain(u)
@@ -573,7 +580,8 @@ def main():
         "config": {"workload": "2D backward-Euler heat %d^2, h=1/%d, dt=1e-4, kappa=1, Neumann; 64-mode cosine "
                                "+ uniform(-0.01,0.01) noise (seed 1); V(2,2) X-MCGS down to 4^2, relative "
                                "residual 1e-10 per step" % (n, n),
-                   "grid": [n, n], "steps_timed": args.steps, "nu1": 2, "nu2": 2, "coarsest": 4, "tol": tol},
+                   "grid": [n, n], "steps_timed": args.steps, "nu1": 2, "nu2": 2, "coarsest": 4, "tol": tol,
+                   "autotune": not args.no_autotune},
         "cycles_per_step": float(np.mean(cycles)),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom, n),
@@ -583,7 +591,8 @@ def main():
     }
 
     if not args.no_mixed:
-        g32 = Grid((n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev)
+        g32 = Grid((n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev).set(
+            autotune=not args.no_autotune)
         outer = []
 
         def step_mixed(u):
@@ -593,6 +602,11 @@ def main():
                 raise RuntimeError("mixed solve did not converge")
             return g.stats()["cycles"]
 
+        if not args.no_autotune:
+            # plan time for the FP32 inner grid: one inner V-cycle tunes its levels
+            e = torch.zeros(u0.shape, dtype=torch.float32, device=dev)
+            g32.vcycle(u0.float(), e, dt)
+            del e
         u = u0.clone()
         for _ in range(args.warmup):
             step_mixed(u)

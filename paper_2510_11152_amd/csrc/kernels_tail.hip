@@ -16,7 +16,8 @@ namespace fas {
 namespace {
 
 constexpr int kTailThreads = 1024;
-constexpr int kTailLds = 96 * 1024;  // bytes of LDS for the tail levels
+constexpr int kTailLds = 96 * 1024;     // bytes of LDS for u and f of the tail levels
+constexpr int kTailLdsKV = 144 * 1024;  // cell kappa: u, f and kappa of the tail levels
 
 template <typename T>
 struct TailArgs {
@@ -25,6 +26,7 @@ struct TailArgs {
     int first;                // parity of the first phase of a sweep
     int form_rhs;             // 1: f_top = r_top + A u_top (FAS coarse right-hand side)
     int lds_off[kMaxTail];    // element offset of u of each level; f follows u
+    int kap_off[kMaxTail];    // cell kappa: element offset of each level's kappa copy
     Op<T> op[kMaxTail];
     T* u_top;                 // in: initial guess of the top level; out: its new values
     const T* r_top;           // in: restricted residual (form_rhs) or the right-hand side
@@ -110,20 +112,36 @@ __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int f
 template <typename T, int DIM, bool KV>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, const T* const r_top)
 {
-    __shared__ __attribute__((aligned(16))) char lds[kTailLds];
+    // cell kappa: every level's kappa is copied into LDS too, so the face weights of each
+    // phase read it there rather than from global memory
+    __shared__ __attribute__((aligned(16))) char lds[KV ? kTailLdsKV : kTailLds];
     T* base = reinterpret_cast<T*>(lds);
     auto U = [&](int l) { return base + a.lds_off[l]; };
     auto F = [&](int l) { return base + a.lds_off[l] + (a.op[l].n0 * a.op[l].n1 * a.op[l].n2); };
+    // the operator of level l, its cell kappa (if any) read from the LDS copy
+    auto OP = [&](int l) {
+        Op<T> o = a.op[l];
+        if constexpr (KV) o.kap = base + a.kap_off[l];
+        return o;
+    };
     const int N0 = a.op[0].n0 * a.op[0].n1 * a.op[0].n2;
     for (int p = threadIdx.x; p < N0; p += kTailThreads) {
         U(0)[p] = u_top[p];
         F(0)[p] = r_top[p];
     }
+    if constexpr (KV) {
+        for (int l = 0; l < a.nl; ++l) {
+            const int Nl = a.op[l].n0 * a.op[l].n1 * a.op[l].n2;
+            T* const kl = base + a.kap_off[l];
+            const T* const kg = a.op[l].kap;
+            for (int p = threadIdx.x; p < Nl; p += kTailThreads) kl[p] = kg[p];
+        }
+    }
     __syncthreads();
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
     if (a.form_rhs) {
         // f = r_c + A_c u_c
-        const Op<T>& op = a.op[0];
+        const Op<T> op = OP(0);
         for (int row = ty; row < op.n1 * op.n2; row += kTY) {
             const int l = DIM == 3 ? row / op.n1 : 0, j = DIM == 3 ? row - l * op.n1 : row;
             for (int i = tx; i < op.n0; i += kTX) {
@@ -138,8 +156,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
     const bool rev = false;
     // descend: pre-smoothing, then u_c = R u, f_c = R (f - A u) + A_c u_c
     for (int lv = 0; lv + 1 < a.nl; ++lv) {
-        const Op<T>& op = a.op[lv];
-        const Op<T>& oc = a.op[lv + 1];
+        const Op<T> op = OP(lv);
+        const Op<T> oc = OP(lv + 1);
         T* u = U(lv);
         const T* f = F(lv);
         tail_smooth<T, DIM, KV>(op, u, f, a.pre, a.first, rev);
@@ -177,11 +195,11 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         __syncthreads();
     }
     // coarsest level: smoothing only (Remark 1)
-    tail_smooth<T, DIM, KV>(a.op[a.nl - 1], U(a.nl - 1), F(a.nl - 1), a.nuc, a.first, rev);
+    tail_smooth<T, DIM, KV>(OP(a.nl - 1), U(a.nl - 1), F(a.nl - 1), a.nuc, a.first, rev);
     // ascend: u += P(u_c - R u), post-smoothing
     for (int lv = a.nl - 2; lv >= 0; --lv) {
-        const Op<T>& op = a.op[lv];
-        const Op<T>& oc = a.op[lv + 1];
+        const Op<T> op = OP(lv);
+        const Op<T> oc = OP(lv + 1);
         T* u = U(lv);
         for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
         for (int I = tx; I < oc.n0; I += kTX) {
@@ -252,6 +270,13 @@ TailArgs<T> make_tail_args(const fas_grid* g, int top, const Coef* coef, int pre
         a.lds_off[i] = off;
         off += 2 * (int)g->lev[l].N;
     }
+    const bool kv = g->lev[top].kap != nullptr;
+    for (int i = 0; i < a.nl; ++i) {  // cell kappa: copies after every level's u and f
+        a.kap_off[i] = off;
+        if (kv) off += (int)g->lev[top + i].N;
+    }
+    if ((size_t)off * sizeof(T) > (size_t)(kv ? kTailLdsKV : kTailLds))
+        throw Error(FAS_ERR_ARG, "internal: tail levels exceed the tail's LDS");
     return a;
 }
 
@@ -291,13 +316,16 @@ void launch_t(const fas_grid* g, int top, const Coef* coef, int pre, int post, i
 
 int tail_top(const fas_grid* g)
 {
-    // the largest level from which every coarser level's u and f fit the tail's LDS
+    // the largest level from which every coarser level's u and f (and the cell kappa on a
+    // grid that may take one) fit the tail's LDS; the two budgets admit the same levels
     const size_t s = g->elem();
+    const bool kv = (g->flags & FAS_FLAG_VARIABLE_KAPPA) != 0;
+    const size_t cap = kv ? (size_t)kTailLdsKV : (size_t)kTailLds;
     size_t bytes = 0;
     int top = g->L + 1;
     for (int l = g->L; l >= 0; --l) {
-        bytes += 2 * (size_t)g->lev[l].N * s;
-        if (bytes > (size_t)kTailLds || g->L - l + 1 > kMaxTail) break;
+        bytes += (kv ? 3 : 2) * (size_t)g->lev[l].N * s;
+        if (bytes > cap || g->L - l + 1 > kMaxTail) break;
         top = l;
     }
     return top;  // L + 1: not even the coarsest level fits

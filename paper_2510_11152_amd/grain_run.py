@@ -46,6 +46,10 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=250)
     ap.add_argument("--fit-from", type=float, default=0.2, help="fit over measurements after this fraction of the run")
     ap.add_argument("--seed", type=int, default=6)
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64", "mixed"))
+    ap.add_argument("--tol", type=float, default=None, help="relative tolerance (default 1e-6 fp32, 1e-10 else)")
+    ap.add_argument("--atol-factor", type=float, default=None,
+                    help="absolute tolerance as a multiple of sqrt(cells) (default: tol)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
@@ -56,11 +60,14 @@ def main(argv=None):
 
     dev = torch.device("cuda", 0)
     shape = (a.q,) + (a.n,) * a.dim
-    eta = torch.from_numpy(np.random.default_rng(a.seed).uniform(-0.001, 0.001, shape).astype(np.float32)).to(dev)
-    # absolute floor: tol times the norm of one field of order one over the grid, so a field
-    # whose grains have all vanished (its values decaying towards zero) stops at once
-    atol = 1e-6 * math.sqrt(a.n ** a.dim)
-    model = GrainGrowth(a.q, a.n, dt=0.1, kappa=1.0, tol=1e-6, device=dev, dim=a.dim, atol=atol)
+    tdt = np.float32 if a.precision == "fp32" else np.float64
+    eta = torch.from_numpy(np.random.default_rng(a.seed).uniform(-0.001, 0.001, shape).astype(tdt)).to(dev)
+    tol = a.tol if a.tol is not None else (1e-6 if a.precision == "fp32" else 1e-10)
+    # absolute floor: by default tol times the norm of one field of order one over the grid,
+    # so a field whose grains have all vanished (its values decaying towards zero) stops
+    atol = (tol if a.atol_factor is None else a.atol_factor) * math.sqrt(a.n ** a.dim)
+    model = GrainGrowth(a.q, a.n, dt=0.1, kappa=1.0, tol=tol, device=dev, dim=a.dim, atol=atol,
+                        precision=a.precision)
     rows = []
     lab = torch.empty(shape[1:], dtype=torch.int32, device=dev)
     t_solve = 0.0
@@ -71,7 +78,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         t_solve += time.perf_counter() - t0
         if k % a.every == 0 or k == a.steps:
-            grains, size = count_grains(grain_map(eta, lab).cpu().numpy())
+            grains, size = count_grains(grain_map(eta if eta.dtype == torch.float32 else eta.float(), lab).cpu().numpy())
             R = math.sqrt(size / math.pi) if a.dim == 2 else (3.0 * size / (4.0 * math.pi)) ** (1.0 / 3.0)
             rows.append({"step": k, "t": k * 0.1, "grains": grains, "mean_size": size, "R": R})
             print("grain run: step %d t %.1f grains %d R %.3f (%.3f ms/step)" % (k, k * 0.1, grains, R,
@@ -80,6 +87,7 @@ def main(argv=None):
     best, fits = fit_growth_law([r["t"] for r in sel], [r["R"] for r in sel])
     m2 = min(fits, key=lambda f: abs(f["m"] - 2.0))
     out = {"dim": a.dim, "fields": a.q, "grid": [a.n] * a.dim, "steps": a.steps, "dt": 0.1, "kappa": 1.0, "h": 1.0,
+           "precision": a.precision, "tol": tol, "atol": atol,
            "solve_and_rhs_s_per_step": t_solve / a.steps, "measurements": rows,
            "fit_window_t": [sel[0]["t"], sel[-1]["t"]] if sel else None,
            "best_fit": best, "fit_m2": m2}
