@@ -281,13 +281,17 @@ int fas_solve_batched(int nprob, const fas_grid_t* grids, double dt, const fas_k
                       void* const* u, double tol, int nu1, int nu2, int* status_out);
 
 /* Right-hand side of one semi-implicit step of the multi-order-parameter grain-growth
- * model (Section 3.3.1, eq. grain-growth-equations with L = alpha = beta = gamma = 1):
- * free energy sum_i (-eta_i^2/2 + eta_i^4/4) + (3/2) sum_{i<j} eta_i^2 eta_j^2, so
- *     f_i = eta_i - dt * ((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)),  S = sum_j eta_j^2,
- * and (I - dt kappa Lap) eta_i^{n+1} = f_i is then one batched solve.  eta, f: q fields
- * of ncells values of `dtype` (FAS_F32 or FAS_F64) each, contiguous, device; S is summed
- * in field order and every operation rounds in that precision; stream: hipStream_t. */
-int fas_grain_rhs(void* stream, int dtype, int q, int64_t ncells, double dt, const void* eta, void* f);
+ * model (Section 3.3.1, eq. grain-growth-equations with L = 1): free energy
+ * sum_i (-alpha eta_i^2/2 + beta eta_i^4/4) + gamma sum_{i<j} eta_i^2 eta_j^2, so
+ *     f_i = eta_i - dt * ((beta eta_i^3 - alpha eta_i) + 2 gamma eta_i (S - eta_i^2)),
+ *     S = sum_j eta_j^2,
+ * and (I - dt kappa Lap) eta_i^{n+1} = f_i is then one batched solve (the paper's
+ * coefficients: alpha = beta = gamma = 1; the grain workload here: gamma = 1.5).  eta, f:
+ * q fields of ncells values of `dtype` (FAS_F32 or FAS_F64) each, contiguous, device; S is
+ * summed in field order and every operation rounds in that precision (2 gamma rounded
+ * once); stream: hipStream_t. */
+int fas_grain_rhs(void* stream, int dtype, int q, int64_t ncells, double dt, double alpha, double beta, double gamma,
+                  const void* eta, void* f);
 
 /* Grain map of a grain-growth state (Section 3.3.1: a grain is a region where one order
  * parameter dominates): label[p] = the index i of the largest eta_i at cell p, the lowest

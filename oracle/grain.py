@@ -14,9 +14,11 @@ precision as written.
 import numpy as np
 
 
-def grain_rhs(eta, dt, dtype=np.float32):
+def grain_rhs(eta, dt, dtype=np.float32, alpha=1.0, beta=1.0, gamma=1.5):
+    """f_i = eta_i - dt ((beta eta_i^3 - alpha eta_i) + 2 gamma eta_i (S - eta_i^2)); the
+    defaults are the grain workload's coefficients (the paper uses alpha = beta = gamma = 1)."""
     eta = np.asarray(eta, dtype=dtype)
-    dt = dtype(dt)
+    dt, a, b, g2 = dtype(dt), dtype(alpha), dtype(beta), dtype(2.0 * gamma)
     S = eta[0] * eta[0]
     for j in range(1, eta.shape[0]):
         S = S + eta[j] * eta[j]
@@ -24,12 +26,12 @@ def grain_rhs(eta, dt, dtype=np.float32):
     for i in range(eta.shape[0]):
         e = eta[i]
         e2 = e * e
-        g = (e2 * e - e) + (dtype(3.0) * e) * (S - e2)
+        g = ((b * e2) * e - a * e) + (g2 * e) * (S - e2)
         out[i] = e - dt * g
     return out
 
 
-def grain_rhs_reference(eta, dt):
+def grain_rhs_reference(eta, dt, alpha=1.0, beta=1.0, gamma=1.5):
     """The same quantity from the free energy in float64 by central differences of
     f(eta) along each eta_i (an independent check of the derivative, not of rounding)."""
     eta = np.asarray(eta, dtype=np.float64)
@@ -37,7 +39,7 @@ def grain_rhs_reference(eta, dt):
     def energy(x):
         sq = x * x
         pair = 0.5 * (sq.sum(axis=0) ** 2 - (sq * sq).sum(axis=0))   # sum_{i<j} eta_i^2 eta_j^2
-        return (-0.5 * sq + 0.25 * sq * sq).sum(axis=0) + 1.5 * pair
+        return (-0.5 * alpha * sq + 0.25 * beta * sq * sq).sum(axis=0) + gamma * pair
 
     d = np.empty_like(eta)
     h = 1e-5

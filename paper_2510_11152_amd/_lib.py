@@ -69,7 +69,7 @@ SIGNATURES = {
     "fas_grid_create_batched": (_i, [_i, _pi64, _d, _i, _i, _i, _i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     "fas_solve_stacked": (_i, [_vp, _d, _d, _vp, _vp, _d, _i, _i, _vp, _vp]),
     "fas_solve_batched": (_i, [_i, _vp, _d, ctypes.POINTER(FasKappa), _vp, _vp, _d, _i, _i, _vp]),
-    "fas_grain_rhs": (_i, [_vp, _i, _i, _i64, _d, _vp, _vp]),
+    "fas_grain_rhs": (_i, [_vp, _i, _i, _i64, _d, _d, _d, _d, _vp, _vp]),
     "fas_solve_stacked_mixed": (_i, [_vp, _vp, _d, _d, _vp, _vp, _d, _i, _i, _i, _vp, _vp]),
     "fas_grain_argmax": (_i, [_vp, _i, _i64, _vp, _vp]),
     "fas_solve_noalloc": (_i, [_i, _pi64, _d, _i, _i, _i, _vp, _d, _d, _vp, _vp, _vp, _d, _i, _i, _i,

@@ -1815,12 +1815,15 @@ int fas_solve_batched(int nprob, const fas_grid_t* grids, double dt, const fas_k
     });
 }
 
-int fas_grain_rhs(void* stream, int dtype, int q, int64_t ncells, double dt, const void* eta, void* f)
+int fas_grain_rhs(void* stream, int dtype, int q, int64_t ncells, double dt, double alpha, double beta, double gamma,
+                  const void* eta, void* f)
 {
     return guarded([&]() -> int {
         if (q < 1 || ncells < 1 || !eta || !f || eta == f) return fail(FAS_ERR_ARG, "bad grain-growth arguments");
         if (dtype != FAS_F64 && dtype != FAS_F32) return fail(FAS_ERR_ARG, "dtype must be FAS_F64 or FAS_F32");
-        fas::launch_grain_rhs((hipStream_t)stream, dtype, q, ncells, dt, eta, f);
+        if (!isfinite(dt) || !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma))
+            return fail(FAS_ERR_ARG, "grain-growth coefficients must be finite");
+        fas::launch_grain_rhs((hipStream_t)stream, dtype, q, ncells, dt, alpha, beta, gamma, eta, f);
         return FAS_OK;
     });
 }

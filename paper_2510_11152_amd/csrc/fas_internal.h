@@ -160,9 +160,10 @@ void launch_update_active(const fas_grid* g, double tol, int k);
 // One problem: launch_sum_partials(g, count) and launch_update_active(g, tol, k) in one
 // launch (the same norm bits, the same flags).
 void launch_sum_update(const fas_grid* g, int count, double tol, int k);
-// Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32):
-// S = sum_j eta_j^2; f_i = eta_i - dt*((eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2)).
-void launch_grain_rhs(hipStream_t stream, int dtype, int q, int64_t N, double dt, const void* eta, void* f);
+// Allen-Cahn grain-growth right-hand side for q fields of N cells (FP32 or FP64):
+// S = sum_j eta_j^2; f_i = eta_i - dt*((beta eta_i^3 - alpha eta_i) + 2 gamma eta_i (S - eta_i^2)).
+void launch_grain_rhs(hipStream_t stream, int dtype, int q, int64_t N, double dt, double alpha, double beta,
+                      double gamma, const void* eta, void* f);
 // label[p] = the index of the largest of eta_0[p] .. eta_{q-1}[p] (lowest among equals).
 void launch_grain_argmax(hipStream_t stream, int q, int64_t N, const float* eta, int* label);
 

@@ -580,15 +580,16 @@ __global__ __launch_bounds__(kBlock) void k_update_active(const double* __restri
 }
 
 // ----------------------------------------------------------- grain-growth right-hand side
-// Fan-Chen free energy f = sum_i (-eta_i^2/2 + eta_i^4/4) + (3/2) sum_{i<j} eta_i^2 eta_j^2:
-// d f/d eta_i = (eta_i^3 - eta_i) + 3 eta_i (S - eta_i^2), S = sum_j eta_j^2 (summed in j
-// order); semi-implicit step right-hand side f_i = eta_i - dt * d f/d eta_i.
+// Fan-Chen free energy f = sum_i (-alpha eta_i^2/2 + beta eta_i^4/4) + gamma sum_{i<j}
+// eta_i^2 eta_j^2: d f/d eta_i = (beta eta_i^3 - alpha eta_i) + 2 gamma eta_i (S - eta_i^2),
+// S = sum_j eta_j^2 (summed in j order); semi-implicit step right-hand side
+// f_i = eta_i - dt * d f/d eta_i.
 // W consecutive cells per thread (W = 2: float2 accesses, N even), the field loops
 // unrolled so that many fields' loads are in flight; each cell's sum over j keeps its
 // order.
 template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, T dt, const T* __restrict__ eta,
-                                                      T* __restrict__ f)
+__global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, T dt, T alpha, T beta, T gamma2,
+                                                      const T* __restrict__ eta, T* __restrict__ f)
 {
     using V2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
     using V = typename std::conditional<W == 2, V2, T>::type;
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_grain_rhs(int q, int64_t N, T dt, co
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             const T e2 = e[c] * e[c];
-            const T g = (e2 * e[c] - e[c]) + ((T)3 * e[c]) * (S[c] - e2);
+            const T g = ((beta * e2) * e[c] - alpha * e[c]) + (gamma2 * e[c]) * (S[c] - e2);
             r[c] = e[c] - dt * g;
         }
         if constexpr (W == 2) {
@@ -957,23 +958,26 @@ void launch_grain_argmax(hipStream_t stream, int q, int64_t N, const float* eta,
 }
 
 template <typename T>
-void launch_grain_rhs_t(hipStream_t stream, int q, int64_t N, T dt, const T* eta, T* f)
+void launch_grain_rhs_t(hipStream_t stream, int q, int64_t N, T dt, T alpha, T beta, T gamma2, const T* eta, T* f)
 {
     // N even and pair-aligned arrays: pair accesses stay aligned in every field
     const uintptr_t al = 2 * sizeof(T);
     if (N % 2 == 0 && ((uintptr_t)eta % al) == 0 && ((uintptr_t)f % al) == 0)
-        k_grain_rhs<T, 2><<<blocks_for(N / 2), kBlock, 0, stream>>>(q, N, dt, eta, f);
+        k_grain_rhs<T, 2><<<blocks_for(N / 2), kBlock, 0, stream>>>(q, N, dt, alpha, beta, gamma2, eta, f);
     else
-        k_grain_rhs<T, 1><<<blocks_for(N), kBlock, 0, stream>>>(q, N, dt, eta, f);
+        k_grain_rhs<T, 1><<<blocks_for(N), kBlock, 0, stream>>>(q, N, dt, alpha, beta, gamma2, eta, f);
     check_launch();
 }
 
-void launch_grain_rhs(hipStream_t stream, int dtype, int q, int64_t N, double dt, const void* eta, void* f)
+void launch_grain_rhs(hipStream_t stream, int dtype, int q, int64_t N, double dt, double alpha, double beta,
+                      double gamma, const void* eta, void* f)
 {
+    // the pair term's coefficient 2 gamma is rounded once, in the arithmetic's precision
     if (dtype == FAS_F64)
-        launch_grain_rhs_t<double>(stream, q, N, dt, (const double*)eta, (double*)f);
+        launch_grain_rhs_t<double>(stream, q, N, dt, alpha, beta, 2.0 * gamma, (const double*)eta, (double*)f);
     else
-        launch_grain_rhs_t<float>(stream, q, N, (float)dt, (const float*)eta, (float*)f);
+        launch_grain_rhs_t<float>(stream, q, N, (float)dt, (float)alpha, (float)beta, (float)(2.0 * gamma),
+                                  (const float*)eta, (float*)f);
 }
 
 }  // namespace fas

@@ -20,9 +20,11 @@ from .api import Grid, solve_stacked_mixed
 _DT = {torch.float32: _lib.FAS_F32, torch.float64: _lib.FAS_F64}
 
 
-def grain_rhs(eta, dt, out=None):
+def grain_rhs(eta, dt, out=None, alpha=1.0, beta=1.0, gamma=1.5):
     """f_i for every field; eta: (q, ...) float32 or float64 (2D or 3D fields), contiguous,
-    on the device (the right-hand side is computed in eta's precision)."""
+    on the device (the right-hand side is computed in eta's precision).  alpha, beta,
+    gamma: the free energy's coefficients (the paper: 1, 1, 1; the grain workload: 1, 1,
+    1.5)."""
     if eta.dtype not in _DT or not eta.is_contiguous() or eta.dim() < 3:
         raise ValueError("eta must be a contiguous float32 or float64 (q, ...) tensor of 2D or 3D fields")
     out = torch.empty_like(eta) if out is None else out
@@ -30,8 +32,9 @@ def grain_rhs(eta, dt, out=None):
         raise ValueError("out must match eta")
     stream = torch.cuda.current_stream(eta.device).cuda_stream
     q = eta.shape[0]
-    _lib.check(_lib.load().fas_grain_rhs(ctypes.c_void_p(stream), _DT[eta.dtype], q, eta.numel() // q, dt,
-                                         ctypes.c_void_p(eta.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+    _lib.check(_lib.load().fas_grain_rhs(ctypes.c_void_p(stream), _DT[eta.dtype], q, eta.numel() // q, dt, alpha,
+                                         beta, gamma, ctypes.c_void_p(eta.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr())),
                "fas_grain_rhs")
     return out
 
@@ -84,11 +87,13 @@ class GrainGrowth:
     grids)."""
 
     def __init__(self, q, n, h=1.0, dt=0.1, kappa=1.0, tol=1e-6, coarsest=4, nu1=2, nu2=2, device="cuda",
-                 graph=False, autotune=False, precision="fp32", inner=2, dim=2, atol=0.0):
+                 graph=False, autotune=False, precision="fp32", inner=2, dim=2, atol=0.0, alpha=1.0, beta=1.0,
+                 gamma=1.5):
         if precision not in ("fp32", "fp64", "mixed"):
             raise ValueError("precision must be 'fp32', 'fp64' or 'mixed'")
         self.q, self.n, self.h, self.dt, self.kappa, self.tol = q, n, h, dt, kappa, tol
         self.nu1, self.nu2, self.precision, self.inner = nu1, nu2, precision, inner
+        self.alpha, self.beta, self.gamma = alpha, beta, gamma
         dtype = torch.float32 if precision == "fp32" else torch.float64
         self.grid = Grid((n,) * dim, h, bc="periodic", dtype=dtype, coarsest=coarsest, device=device, batch=q)
         self.grid.set(graph=graph, autotune=autotune, atol=atol)
@@ -101,7 +106,7 @@ class GrainGrowth:
     def step(self, eta):
         """Advance eta (q, n, n[, n]) in place by one step; returns per-field cycle counts (outer
         corrections in the mixed form)."""
-        self.rhs = grain_rhs(eta, self.dt, self.rhs)
+        self.rhs = grain_rhs(eta, self.dt, self.rhs, self.alpha, self.beta, self.gamma)
         if self.inner_grid is not None:
             st, cy = solve_stacked_mixed(self.grid, self.inner_grid, self.rhs, eta, self.dt, self.kappa, self.tol,
                                          self.nu1, self.nu2, self.inner)

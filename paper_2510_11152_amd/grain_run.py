@@ -47,6 +47,9 @@ def main(argv=None):
     ap.add_argument("--fit-from", type=float, default=0.2, help="fit over measurements after this fraction of the run")
     ap.add_argument("--seed", type=int, default=6)
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64", "mixed"))
+    ap.add_argument("--paper", action="store_true",
+                    help="the paper's setting: alpha = beta = gamma = 1, kappa = 2, h = 2, dt = 0.25 (default: "
+                         "the grain workload's gamma = 1.5, kappa = 1, h = 1, dt = 0.1)")
     ap.add_argument("--tol", type=float, default=None, help="relative tolerance (default 1e-6 fp32, 1e-10 else)")
     ap.add_argument("--atol-factor", type=float, default=None,
                     help="absolute tolerance as a multiple of sqrt(cells) (default: tol)")
@@ -66,8 +69,9 @@ def main(argv=None):
     # absolute floor: by default tol times the norm of one field of order one over the grid,
     # so a field whose grains have all vanished (its values decaying towards zero) stops
     atol = (tol if a.atol_factor is None else a.atol_factor) * math.sqrt(a.n ** a.dim)
-    model = GrainGrowth(a.q, a.n, dt=0.1, kappa=1.0, tol=tol, device=dev, dim=a.dim, atol=atol,
-                        precision=a.precision)
+    h, dt, kappa, gamma = (2.0, 0.25, 2.0, 1.0) if a.paper else (1.0, 0.1, 1.0, 1.5)
+    model = GrainGrowth(a.q, a.n, h=h, dt=dt, kappa=kappa, tol=tol, device=dev, dim=a.dim, atol=atol,
+                        precision=a.precision, gamma=gamma)
     rows = []
     lab = torch.empty(shape[1:], dtype=torch.int32, device=dev)
     t_solve = 0.0
@@ -79,14 +83,16 @@ def main(argv=None):
         t_solve += time.perf_counter() - t0
         if k % a.every == 0 or k == a.steps:
             grains, size = count_grains(grain_map(eta if eta.dtype == torch.float32 else eta.float(), lab).cpu().numpy())
-            R = math.sqrt(size / math.pi) if a.dim == 2 else (3.0 * size / (4.0 * math.pi)) ** (1.0 / 3.0)
-            rows.append({"step": k, "t": k * 0.1, "grains": grains, "mean_size": size, "R": R})
-            print("grain run: step %d t %.1f grains %d R %.3f (%.3f ms/step)" % (k, k * 0.1, grains, R,
+            # grain size in length units (cells of area h^dim)
+            R = h * (math.sqrt(size / math.pi) if a.dim == 2 else (3.0 * size / (4.0 * math.pi)) ** (1.0 / 3.0))
+            rows.append({"step": k, "t": k * dt, "grains": grains, "mean_size": size, "R": R})
+            print("grain run: step %d t %.1f grains %d R %.3f (%.3f ms/step)" % (k, k * dt, grains, R,
                                                                                  1e3 * t_solve / k), flush=True)
     sel = [r for r in rows if r["step"] >= a.fit_from * a.steps and r["grains"] > 1]
     best, fits = fit_growth_law([r["t"] for r in sel], [r["R"] for r in sel])
     m2 = min(fits, key=lambda f: abs(f["m"] - 2.0))
-    out = {"dim": a.dim, "fields": a.q, "grid": [a.n] * a.dim, "steps": a.steps, "dt": 0.1, "kappa": 1.0, "h": 1.0,
+    out = {"dim": a.dim, "fields": a.q, "grid": [a.n] * a.dim, "steps": a.steps, "dt": dt, "kappa": kappa, "h": h,
+           "alpha": 1.0, "beta": 1.0, "gamma": gamma,
            "precision": a.precision, "tol": tol, "atol": atol,
            "solve_and_rhs_s_per_step": t_solve / a.steps, "measurements": rows,
            "fit_window_t": [sel[0]["t"], sel[-1]["t"]] if sel else None,

@@ -303,13 +303,16 @@ def test_grain_map_is_the_dominant_field():
     assert np.array_equal(lab.cpu().numpy(), np.argmax(eta, axis=0).astype(np.int32))
 
 
-def test_grain_rhs_fp64_matches_oracle_bitwise():
+@pytest.mark.parametrize("coef", [(1.0, 1.0, 1.5), (1.0, 1.0, 1.0), (0.7, 1.3, 2.1)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_grain_rhs_coefficients_match_oracle_bitwise(coef, dtype):
     from paper_2510_11152_amd import grain_rhs
-    eta = I.grain_init(q=29, n=64, seed=8).astype(np.float64)
-    eta[:, :8, :8] = np.random.default_rng(2).uniform(-1, 1, (29, 8, 8))
-    f = grain_rhs(torch.from_numpy(eta).to(DEV), 0.1)
+    eta = I.grain_init(q=29, n=64, seed=8).astype(dtype)
+    eta[:, :8, :8] = np.random.default_rng(2).uniform(-1, 1, (29, 8, 8)).astype(dtype)
+    al, be, ga = coef
+    f = grain_rhs(torch.from_numpy(eta).to(DEV), 0.25, alpha=al, beta=be, gamma=ga)
     torch.cuda.synchronize()
-    assert np.array_equal(f.cpu().numpy(), OG.grain_rhs(eta, 0.1, dtype=np.float64))
+    assert np.array_equal(f.cpu().numpy(), OG.grain_rhs(eta, 0.25, dtype, al, be, ga))
 
 
 @pytest.mark.parametrize("n,bc,inner", [((128, 128), "periodic", 2), ((256, 128), "neumann", 3), ((64, 64), "dirichlet", 2),

@@ -465,6 +465,10 @@ def test_grain_rhs_is_the_free_energy_derivative():
     # h^2/6 times its third derivative (below 1e-9 here) plus rounding (about 1e-11 / h)
     a64 = G.grain_rhs(eta, 0.1, dtype=np.float64)
     np.testing.assert_allclose(a64, G.grain_rhs_reference(eta, 0.1), rtol=0, atol=1e-8)
+    # other coefficients (the paper's alpha = beta = gamma = 1, and unequal ones)
+    for al, be, ga in ((1.0, 1.0, 1.0), (0.7, 1.3, 2.1)):
+        np.testing.assert_allclose(G.grain_rhs(eta, 0.25, np.float64, al, be, ga),
+                                   G.grain_rhs_reference(eta, 0.25, al, be, ga), rtol=0, atol=1e-8)
 
 
 # ---------------------------------------------------------------- absolute stopping test
