@@ -134,6 +134,19 @@ __global__ __launch_bounds__(kBlock) void k_residual(Op<T> op, const T* __restri
     r[p] = f[p] - apply_value<T, DIM, KV>(op, s, u[p]);
 }
 
+// Fixed-order block reduction of per-thread double sums into out[idx].
+__device__ void block_sum_at(double v, double* out, int idx)
+{
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[idx] = red[0];
+}
+
 // Fixed-order block reduction of per-thread double sums into out[blockIdx.x].
 __device__ void block_sum_store(double v, double* out)
 {
@@ -510,6 +523,82 @@ __global__ __launch_bounds__(kBlock) void k_mixed_resid(Op<double> op, const dou
 }
 
 // u += fp64(e) (the outer update of the defect correction when no inner pass folds it).
+// The same outer step on 2D grids with a constant coefficient, as row marches: thread t of
+// block (x, y) owns the column pair 2 (x kBlock + t), 2 (x kBlock + t) + 1 and walks the
+// rows of segment y in order, keeping rows j - 1, j, j + 1 of u in registers, so u is read
+// about once (x-neighbours come from the same rows in cache).  Problem b = blockIdx.z; one
+// partial sum per block (fixed order).  The point formulas are those of the grid-stride
+// kernel above, so r32 is the same; only the partial sums are grouped differently.
+constexpr int kMixedSeg = 32;  // rows per segment
+
+__global__ __launch_bounds__(kBlock) void k_mixed_resid_rows(Op<double> op, const double* __restrict__ f,
+                                                             const double* __restrict__ u, float* __restrict__ r32,
+                                                             double* __restrict__ rpart, double* __restrict__ fpart,
+                                                             const int* __restrict__ act, int64_t stride)
+{
+    const int b = (int)blockIdx.z;
+    if (act && !act[b]) return;
+    f += b * stride;
+    u += b * stride;
+    r32 += b * stride;
+    const int nblk = (int)(gridDim.x * gridDim.y), blk = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    rpart += (int64_t)b * nblk;
+    if (fpart) fpart += (int64_t)b * nblk;
+    const bool per = op.bc == BC_PERIODIC;
+    const int i = 2 * (int)(blockIdx.x * kBlock + threadIdx.x);
+    const bool col = i < op.n0;
+    const int ic = col ? i : op.n0 - 2;  // columns past the grid load the last pair and store nothing
+    const bool uxl = per || ic > 0, uxr = per || ic + 2 < op.n0;
+    const int il = ic > 0 ? ic - 1 : (per ? op.n0 - 1 : ic);
+    const int ir = ic + 2 < op.n0 ? ic + 2 : (per ? 0 : ic + 1);
+    const int j0 = (int)blockIdx.y * kMixedSeg, j1 = min(j0 + kMixedSeg, op.n1);
+    auto row = [&](int j) { return (int64_t)j * op.n0; };
+    const int jm0 = j0 > 0 ? j0 - 1 : (per ? op.n1 - 1 : j0);
+    double2 um = *reinterpret_cast<const double2*>(u + row(jm0) + ic);
+    double2 uc = *reinterpret_cast<const double2*>(u + row(j0) + ic);
+    double acc = 0.0, facc = 0.0;
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+        const int jp = j + 1 < op.n1 ? j + 1 : (per ? 0 : j);
+        const double2 up = *reinterpret_cast<const double2*>(u + row(jp) + ic);
+        const double2 fp = *reinterpret_cast<const double2*>(f + row(j) + ic);
+        PairNbhd<2> s;
+        s.c = uc;
+        s.xl = u[row(j) + il];
+        s.xr = u[row(j) + ir];
+        s.ym = um;
+        s.yp = up;
+        s.uxl = uxl;
+        s.uxr = uxr;
+        s.uym = per || j > 0;
+        s.uyp = per || j + 1 < op.n1;
+        Nbhd<double, 2> nb;
+        pair_cell<2, true>(s, nb);
+        const double re = fp.x - apply_value<double, 2, false>(op, nb, uc.x);
+        pair_cell<2, false>(s, nb);
+        const double ro = fp.y - apply_value<double, 2, false>(op, nb, uc.y);
+        if (col) {
+            float2 rv;
+            rv.x = (float)re;
+            rv.y = (float)ro;
+            *reinterpret_cast<float2*>(r32 + row(j) + i) = rv;
+            acc += re * re;
+            acc += ro * ro;
+            if (fpart) {
+                facc += fp.x * fp.x;
+                facc += fp.y * fp.y;
+            }
+        }
+        um = uc;
+        uc = up;
+    }
+    block_sum_at(acc, rpart, blk);
+    if (fpart) {
+        __syncthreads();
+        block_sum_at(facc, fpart, blk);
+    }
+}
+
 // Problem b = blockIdx.y of N cells (arrays b * N apart), gated by its active flag.
 __global__ __launch_bounds__(kBlock) void k_update_mixed(int64_t N, const float* __restrict__ e, double* __restrict__ u,
                                                          const int* __restrict__ act)
@@ -877,8 +966,19 @@ int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const 
     auto U = (const double*)u;
     double* fp = fnorm ? g->fpartials : nullptr;
     const bool kv = kap != nullptr;
-    const dim3 grid(nb, (unsigned)g->batch, 1);
     const int64_t stride = g->lev[0].N;
+    if (g->dim == 2 && !kap) {
+        // row marches: one block per 512 columns and kMixedSeg rows
+        const unsigned bx = (unsigned)((g->lev[0].n[0] / 2 + kBlock - 1) / kBlock);
+        const unsigned by = (unsigned)((g->lev[0].n[1] + kMixedSeg - 1) / kMixedSeg);
+        if ((int64_t)bx * by <= (int64_t)(g->npartials / g->batch)) {
+            k_mixed_resid_rows<<<dim3(bx, by, (unsigned)g->batch), kBlock, 0, g->stream>>>(
+                op, F, U, (float*)r32, g->partials, fp, act, stride);
+            check_launch();
+            return (int)(bx * by);
+        }
+    }
+    const dim3 grid(nb, (unsigned)g->batch, 1);
 #define FAS_MIXED_RESID(D_, KV_) \
     k_mixed_resid<D_, KV_><<<grid, kBlock, 0, g->stream>>>(op, F, U, (float*)r32, g->partials, fp, act, stride)
     if (g->dim == 2) {
