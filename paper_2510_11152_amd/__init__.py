@@ -1,4 +1,4 @@
-"""MI355X-native matrix-free FAS multigrid (arXiv 2510.11152) on cell-centred grids.
+"""MI355X-native matrix-free FAS multigrid (arXiv 2510.11152) on cell-centred and staggered grids.
 
 The solver runs in hand-written HIP kernels behind the C ABI of include/fas.h
 (libfas.so); this package only marshals torch tensors into those calls.
@@ -7,3 +7,4 @@ from .api import (Grid, UnevenBatch, heat, solve_batched, solve_mixed, solve_sta
                   solve_uneven)
 from .autograd import HeatSolveFn, heat_loss_and_grads  # noqa: F401
 from .grain import GrainGrowth, count_grains, grain_map, grain_rhs  # noqa: F401
+from .staggered import NavierStokes2D, StaggeredSolver  # noqa: F401

@@ -27,6 +27,8 @@ FAS_OPT_TILE, FAS_OPT_TILE_WAVES = 8, 9
 FAS_OPT_ORDER, FAS_OPT_SYMMETRIC, FAS_OPT_ATOL = 10, 11, 12
 FAS_ORDER = {"x": 0, "u": 1, "z": 2}
 FAS_K_NAMES = ("smooth", "pre", "post", "norm")
+FAS_LOC = {"cell": 0, "edge_x": 1, "edge_y": 2}
+FAS_NS_LAYOUT = {"memory_efficient": 0, "classical": 1}
 
 # Every function the header declares, with (restype, argtypes).
 _vp, _i, _d, _sz, _i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
@@ -75,6 +77,22 @@ SIGNATURES = {
     "fas_solve_noalloc": (_i, [_i, _pi64, _d, _i, _i, _i, _vp, _d, _d, _vp, _vp, _vp, _d, _i, _i, _i,
                                ctypes.POINTER(ctypes.c_int)]),
     "fas_stream_probe": (_i, [_vp, _i, _i64, _vp, _vp, _vp, _vp, _i, _i, _pd]),
+    "fas_stag_workspace_size": (_sz, [_i, _i64, _i64, _i]),
+    "fas_stag_create": (_i, [_i, _i64, _i64, _d, _i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "fas_stag_destroy": (_i, [_vp]),
+    "fas_stag_set": (_i, [_vp, _i, _d]),
+    "fas_stag_levels": (_i, [_vp]),
+    "fas_stag_solve": (_i, [_vp, _d, _d, _vp, _vp, _d, _i, _i, _i, ctypes.POINTER(ctypes.c_int), _pd]),
+    "fas_stag_vcycle": (_i, [_vp, _d, _d, _vp, _vp, _i, _i]),
+    "fas_stag_smooth": (_i, [_vp, _d, _d, _vp, _vp, _i]),
+    "fas_stag_residual": (_i, [_vp, _d, _d, _vp, _vp, _vp, _pd]),
+    "fas_ns_fields": (_i, [_i]),
+    "fas_ns_workspace_size": (_sz, [_i64, _i64, _i]),
+    "fas_ns_create": (_i, [_i64, _i64, _d, _d, _i, _i, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "fas_ns_destroy": (_i, [_vp]),
+    "fas_ns_set": (_i, [_vp, _i, _d]),
+    "fas_ns_step": (_i, [_vp, _d, _d, _i, _vp, _vp, _vp, _d, _i, _i, _i, ctypes.POINTER(ctypes.c_int), _pd]),
+    "fas_ns_memory": (_i, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "fas_get_stats": (_i, [_vp, ctypes.POINTER(FasStats)]),
     "fas_get_profile": (_i, [_vp, ctypes.POINTER(FasProfile), _i]),
     "fas_last_error": (ctypes.c_char_p, []),

@@ -13,8 +13,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfas.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["fas_api.hip", "kernels_basic.hip", "kernels_fused2d.hip", "kernels_fused2d_f64.hip", "kernels_fused2d_f32.hip",
-           "kernels_tile2d.hip", "kernels_fused3d.hip", "kernels_tail.hip", "kernels_stream.hip"]
-HEADERS = ["fas_device.h", "fas_internal.h", "fas_fused.h", "fas_tail.h", "strip_march.h", "march_util.h"]
+           "kernels_tile2d.hip", "kernels_fused3d.hip", "kernels_tail.hip", "kernels_stream.hip", "kernels_stag.hip",
+           "stag_api.hip"]
+HEADERS = ["fas_device.h", "fas_internal.h", "fas_fused.h", "fas_tail.h", "strip_march.h", "march_util.h", "stag_internal.h"]
 ARCH = os.environ.get("FAS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1484,6 +1484,8 @@ int solve_batched_impl(int nprob, const fas_grid_t* grids, double dt, const fas_
 
 }  // namespace
 
+void fas::set_last_error(const std::string& msg) { g_last_error = msg; }
+
 extern "C" {
 
 size_t fas_workspace_size(int dim, const int64_t n[3], int dtype, int coarsest, int flags)

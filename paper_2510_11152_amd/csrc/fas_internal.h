@@ -21,6 +21,10 @@ struct Error : std::runtime_error {
     Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// Message returned by fas_last_error() for the calling thread (set by every entry point
+// that fails).
+void set_last_error(const std::string& msg);
+
 #define FAS_HIP_CHECK(expr)                                                                         \
     do {                                                                                            \
         hipError_t e_ = (expr);                                                                     \

@@ -1,0 +1,503 @@
+// Kernels of the staggered-grid FAS solver (Section 4.1, Appendices C-D) and of the
+// first-order projection step (Section 4.2, Scheme 1).
+//
+// Point formulas (one fixed evaluation tree each; the library is built with
+// -ffp-contract=off so every kernel rounds them identically):
+//   s = (W + E) + (S + N)             neighbours, 0.0 for ghosts and wall points
+//   k = 4 + (#odd ghosts) - (#even ghosts),   D = a h^2 + c k
+//   sweep update   w = (c s + h^2 f) / D
+//   operator       L w = (D w - c s) * (1 / h^2),    residual r = f - L w
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fas_device.h"
+#include "stag_internal.h"
+
+namespace fas {
+namespace stag {
+
+namespace {
+
+__device__ __forceinline__ double kshift(int kind) { return kind == K_CN ? -1.0 : (kind == K_CD ? 1.0 : 0.0); }
+
+// k of the point (x, y) of level L.
+__device__ __forceinline__ double kcount(const Lev& L, int x, int y)
+{
+    double k = 4.0;
+    if (x == 0) k += kshift(L.kx);
+    if (x == L.nx - 1) k += kshift(L.kx);
+    if (y == 0) k += kshift(L.ky);
+    if (y == L.ny - 1) k += kshift(L.ky);
+    return k;
+}
+
+__device__ __forceinline__ double diag(const Lev& L, int x, int y) { return L.a * L.h2 + L.c * kcount(L, x, y); }
+
+__device__ __forceinline__ double nbsum(const Lev& L, const double* u, int x, int y)
+{
+    const size_t i = (size_t)y * L.nx + x;
+    const double W = x > 0 ? u[i - 1] : 0.0;
+    const double E = x < L.nx - 1 ? u[i + 1] : 0.0;
+    const double S = y > 0 ? u[i - L.nx] : 0.0;
+    const double N = y < L.ny - 1 ? u[i + L.nx] : 0.0;
+    return (W + E) + (S + N);
+}
+
+__device__ __forceinline__ double resid_at(const Lev& L, const double* f, const double* u, int x, int y)
+{
+    const size_t i = (size_t)y * L.nx + x;
+    return f[i] - (diag(L, x, y) * u[i] - L.c * nbsum(L, u, x, y)) * L.ih2;
+}
+
+// ---- red-black sweeps on an LDS tile --------------------------------------------------------
+// A 256-thread block loads a 64 x 64 window (lane = column, each wave 16 rows) of the iterate
+// and the right-hand side, runs nu red-black sweeps on it in LDS and writes the window's
+// interior of (64 - 4 nu)^2 values.  Half-sweep k can only update values at distance >= k
+// from the window's edge correctly; after 2 nu half-sweeps the interior (distance >= 2 nu) is
+// exactly what nu sweeps over the whole grid give.  Values outside the grid stay 0 in LDS
+// (the 0.0 neighbours of the point formula).  Within a half-sweep the updated points read
+// only points of the other colour, so the update runs in place in LDS.
+template <int NU>
+__global__ __launch_bounds__(256) void k_sweep(Lev L, const double* __restrict__ f, const double* __restrict__ uin,
+                                               double* __restrict__ uout, int tiles_x)
+{
+    constexpr int T = kTile, H = 2 * NU, OUT = T - 2 * H, RPW = T / 4;
+    __shared__ double su[T][T];
+    __shared__ double sf[T][T];
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int tx = (int)(b % (unsigned)tiles_x), ty = (int)(b / (unsigned)tiles_x);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gx = tx * OUT - H + lane;
+    const int ybase = ty * OUT - H;
+    const bool xin = gx >= 0 && gx < L.nx;
+    for (int i = 0; i < RPW; ++i) {
+        const int r = w * RPW + i, gy = ybase + r;
+        double uv = 0.0, fv = 0.0;
+        if (xin && gy >= 0 && gy < L.ny) {
+            const size_t idx = (size_t)gy * L.nx + gx;
+            uv = uin[idx];
+            fv = f[idx];
+        }
+        su[r][lane] = uv;
+        sf[r][lane] = fv;
+    }
+    double kx = 4.0;
+    if (gx == 0) kx += kshift(L.kx);
+    if (gx == L.nx - 1) kx += kshift(L.kx);
+    const bool col_ok = xin && lane >= 1 && lane <= T - 2;
+    __syncthreads();
+#pragma unroll
+    for (int hs = 0; hs < 2 * NU; ++hs) {
+        const int colour = (hs & 1) ^ 1;  // sets 1-2 (odd index sum) first
+        if (col_ok) {
+            for (int i = 0; i < RPW; ++i) {
+                const int r = w * RPW + i, gy = ybase + r;
+                if (r < 1 || r > T - 2 || gy < 0 || gy >= L.ny || ((gx + gy) & 1) != colour) continue;
+                double k = kx;
+                if (gy == 0) k += kshift(L.ky);
+                if (gy == L.ny - 1) k += kshift(L.ky);
+                const double D = L.a * L.h2 + L.c * k;
+                const double s = (su[r][lane - 1] + su[r][lane + 1]) + (su[r - 1][lane] + su[r + 1][lane]);
+                su[r][lane] = (L.c * s + L.h2 * sf[r][lane]) / D;
+            }
+        }
+        __syncthreads();
+    }
+    if (xin && lane >= H && lane < H + OUT) {
+        for (int i = 0; i < RPW; ++i) {
+            const int r = w * RPW + i, gy = ybase + r;
+            if (r >= H && r < H + OUT && gy >= 0 && gy < L.ny) uout[(size_t)gy * L.nx + gx] = su[r][lane];
+        }
+    }
+}
+
+// ---- transfers ------------------------------------------------------------------------------
+// Restriction (Appendix C for cells; Appendix D's six-point form for edges) of the iterate
+// and of the residual, computed at the fine taps on the fly.
+template <int LOC>
+__global__ __launch_bounds__(256) void k_restrict(Lev Lf, const double* __restrict__ f, const double* __restrict__ u,
+                                                  int ncx, int ncy, double* __restrict__ uc,
+                                                  double* __restrict__ uc0, double* __restrict__ rc)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ncx * ncy) return;
+    const int K = (int)(t % ncx), J = (int)(t / ncx);
+    double ru, rr;
+    if (LOC == LOC_CELL) {
+        const int x = 2 * K, y = 2 * J;
+        const size_t i = (size_t)y * Lf.nx + x;
+        ru = ((u[i] + u[i + 1]) + (u[i + Lf.nx] + u[i + Lf.nx + 1])) * 0.25;
+        rr = ((resid_at(Lf, f, u, x, y) + resid_at(Lf, f, u, x + 1, y)) +
+              (resid_at(Lf, f, u, x, y + 1) + resid_at(Lf, f, u, x + 1, y + 1))) * 0.25;
+    } else if (LOC == LOC_EDGE_X) {
+        double gu[2], gr[2];
+        for (int q = 0; q < 2; ++q) {
+            const int y = 2 * J + q, x = 2 * K;
+            const size_t i = (size_t)y * Lf.nx + x;
+            gu[q] = (u[i] + 2.0 * u[i + 1]) + u[i + 2];
+            gr[q] = (resid_at(Lf, f, u, x, y) + 2.0 * resid_at(Lf, f, u, x + 1, y)) + resid_at(Lf, f, u, x + 2, y);
+        }
+        ru = (gu[0] + gu[1]) * 0.125;
+        rr = (gr[0] + gr[1]) * 0.125;
+    } else {
+        double gu[2], gr[2];
+        for (int q = 0; q < 2; ++q) {
+            const int x = 2 * K + q, y = 2 * J;
+            const size_t i = (size_t)y * Lf.nx + x;
+            gu[q] = (u[i] + 2.0 * u[i + Lf.nx]) + u[i + 2 * (size_t)Lf.nx];
+            gr[q] = (resid_at(Lf, f, u, x, y) + 2.0 * resid_at(Lf, f, u, x, y + 1)) + resid_at(Lf, f, u, x, y + 2);
+        }
+        ru = (gu[0] + gu[1]) * 0.125;
+        rr = (gr[0] + gr[1]) * 0.125;
+    }
+    uc[t] = ru;
+    uc0[t] = ru;
+    rc[t] = rr;
+}
+
+__global__ __launch_bounds__(256) void k_coarse_rhs(Lev L, double* __restrict__ f, const double* __restrict__ u)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)L.nx * L.ny) return;
+    const int x = (int)(t % L.nx), y = (int)(t / L.nx);
+    f[t] = f[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
+}
+
+// Prolongation of the correction e = uc - uc0 (Appendix C: injection; Appendix D: linear
+// along the cell-centred axis with odd ghosts first, then midpoint means along the edge axis
+// with 0 at the wall points).
+struct Coarse {
+    const double* uc;
+    const double* uc0;
+    int ncx, ncy;
+    __device__ __forceinline__ double e(int K, int J) const
+    {
+        const size_t i = (size_t)J * ncx + K;
+        return uc[i] - uc0[i];
+    }
+};
+
+// Linear interpolation along the cell-centred axis: fine index q inside coarse cell Q, the
+// coarse values e(Q) and its neighbour (odd ghost beyond the last cell).
+__device__ __forceinline__ double lin_cell(double e0, double enb) { return (3.0 * e0 + enb) * 0.25; }
+
+template <int LOC>
+__global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double* usrc, double* udst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Lf.nx * Lf.ny) return;
+    const int x = (int)(t % Lf.nx), y = (int)(t / Lf.nx);
+    double pe;
+    if (LOC == LOC_CELL) {
+        pe = C.e(x >> 1, y >> 1);
+    } else if (LOC == LOC_EDGE_X) {
+        const int J = y >> 1;
+        auto col = [&](int K) {
+            const double e0 = C.e(K, J);
+            const double nb = (y & 1) ? (J < C.ncy - 1 ? C.e(K, J + 1) : -e0) : (J > 0 ? C.e(K, J - 1) : -e0);
+            return lin_cell(e0, nb);
+        };
+        const int K = x >> 1;
+        if (x & 1) {
+            pe = col(K);
+        } else {
+            const double left = K >= 1 ? col(K - 1) : 0.0;
+            const double right = K <= C.ncx - 1 ? col(K) : 0.0;
+            pe = (left + right) * 0.5;
+        }
+    } else {
+        const int K = x >> 1;
+        auto row = [&](int J) {
+            const double e0 = C.e(K, J);
+            const double nb = (x & 1) ? (K < C.ncx - 1 ? C.e(K + 1, J) : -e0) : (K > 0 ? C.e(K - 1, J) : -e0);
+            return lin_cell(e0, nb);
+        };
+        const int J = y >> 1;
+        if (y & 1) {
+            pe = row(J);
+        } else {
+            const double below = J >= 1 ? row(J - 1) : 0.0;
+            const double above = J <= C.ncy - 1 ? row(J) : 0.0;
+            pe = (below + above) * 0.5;
+        }
+    }
+    udst[t] = usrc[t] + pe;
+}
+
+// ---- residual norm -------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_resnorm(Lev L, const double* __restrict__ f, const double* __restrict__ u,
+                                                 double* __restrict__ r, double* __restrict__ partials)
+{
+    __shared__ double sh[256];
+    const int64_t n = (int64_t)L.nx * L.ny;
+    double acc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+        const int x = (int)(t % L.nx), y = (int)(t / L.nx);
+        const double rv = resid_at(L, f, u, x, y);
+        if (r) r[t] = rv;
+        acc = acc + rv * rv;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ partials, int n, double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc = acc + partials[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src, double* __restrict__ dst, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) dst[t] = src[t];
+}
+
+// ---- projection step ------------------------------------------------------------------------
+constexpr double kWenoEps = 1e-6;
+
+// Third-order WENO derivatives (Hamilton-Jacobi form, Jiang-Shu smoothness ratio) at the
+// centre of five values along one axis: the left-biased phi^- and the right-biased phi^+.
+__device__ __forceinline__ void weno_pair(double pm2, double pm1, double p0, double pp1, double pp2, double ih,
+                                          double& minus, double& plus)
+{
+    const double d0 = pm1 - pm2, d1 = p0 - pm1, d2 = pp1 - p0;
+    const double rm = (kWenoEps + (d1 - d0) * (d1 - d0)) / (kWenoEps + (d2 - d1) * (d2 - d1));
+    const double wm = 1.0 / (1.0 + 2.0 * (rm * rm));
+    minus = ((d1 + d2) - wm * ((d0 - 2.0 * d1) + d2)) * (0.5 * ih);
+    const double e0 = pp2 - pp1, e1 = pp1 - p0, e2 = p0 - pm1;
+    const double rp = (kWenoEps + (e1 - e0) * (e1 - e0)) / (kWenoEps + (e2 - e1) * (e2 - e1));
+    const double wp = 1.0 / (1.0 + 2.0 * (rp * rp));
+    plus = ((e1 + e2) - wp * ((e0 - 2.0 * e1) + e2)) * (0.5 * ih);
+}
+
+// Branch-free upwinding: max(a, 0) phi^- + min(a, 0) phi^+.
+__device__ __forceinline__ double upwind(double a, double minus, double plus)
+{
+    return (a > 0.0 ? a : 0.0) * minus + (a < 0.0 ? a : 0.0) * plus;
+}
+
+__device__ __forceinline__ double forcing(const NsArgs& A, const double* const* F, size_t i)
+{
+    double s = 0.0;
+    for (int k = 0; k < A.nforce; ++k) s = k == 0 ? A.coef[0] * F[0][i] : s + A.coef[k] * F[k][i];
+    return s;
+}
+
+// u extended by two layers beyond each wall: wall points x = 0, 1 hold 0, their odd
+// reflections beyond; along y cell-type ghosts 2 g - mirror (g = 0 below, lid above).
+__device__ __forceinline__ double u_ext(const double* u, int m, int ny, int a, int b, double lid)
+{
+    if (b >= 0 && b < ny) {
+        if (a >= 0 && a < m) return u[(size_t)b * m + a];
+        if (a == -1 || a == m) return 0.0;
+        if (a == -2) return 2.0 * 0.0 - u[(size_t)b * m];
+        return 2.0 * 0.0 - u[(size_t)b * m + m - 1];  // a == m + 1
+    }
+    if (b == -1) return 2.0 * 0.0 - u[a];
+    if (b == -2) return 2.0 * 0.0 - u[(size_t)m + a];
+    if (b == ny) return 2.0 * lid - u[(size_t)(ny - 1) * m + a];
+    return 2.0 * lid - u[(size_t)(ny - 2) * m + a];  // b == ny + 1
+}
+
+// v extended likewise: wall points y = 0, 1 hold 0 with odd reflections beyond; along x
+// cell-type ghosts 2 * 0 - mirror.
+__device__ __forceinline__ double v_ext(const double* v, int nx, int m, int ii, int jj)
+{
+    if (ii >= 0 && ii < nx) {
+        if (jj >= 0 && jj < m) return v[(size_t)jj * nx + ii];
+        if (jj == -1 || jj == m) return 0.0;
+        if (jj == -2) return 2.0 * 0.0 - v[ii];
+        return 2.0 * 0.0 - v[(size_t)(m - 1) * nx + ii];  // jj == m + 1
+    }
+    if (ii == -1) return 2.0 * 0.0 - v[(size_t)jj * nx];
+    if (ii == -2) return 2.0 * 0.0 - v[(size_t)jj * nx + 1];
+    if (ii == nx) return 2.0 * 0.0 - v[(size_t)jj * nx + nx - 1];
+    return 2.0 * 0.0 - v[(size_t)jj * nx + nx - 2];  // ii == nx + 1
+}
+
+__global__ __launch_bounds__(256) void k_rhs_u(NsArgs A, const double* __restrict__ u, const double* __restrict__ v,
+                                               const double* __restrict__ p, double* __restrict__ fu)
+{
+    const int m = A.nx - 1, ny = A.ny;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * ny) return;
+    const int a = (int)(t % m), b = (int)(t / m);
+    const double u0 = u[t];
+    double xm, xp, ym, yp;
+    weno_pair(u_ext(u, m, ny, a - 2, b, A.lid), u_ext(u, m, ny, a - 1, b, A.lid), u0,
+              u_ext(u, m, ny, a + 1, b, A.lid), u_ext(u, m, ny, a + 2, b, A.lid), A.ih, xm, xp);
+    weno_pair(u_ext(u, m, ny, a, b - 2, A.lid), u_ext(u, m, ny, a, b - 1, A.lid), u0,
+              u_ext(u, m, ny, a, b + 1, A.lid), u_ext(u, m, ny, a, b + 2, A.lid), A.ih, ym, yp);
+    // mean of the four v around the point (wall values 0 below the first, above the last row)
+    const int nx = A.nx;
+    const double sW = b > 0 ? v[(size_t)(b - 1) * nx + a] : 0.0;
+    const double sE = b > 0 ? v[(size_t)(b - 1) * nx + a + 1] : 0.0;
+    const double nW = b < ny - 1 ? v[(size_t)b * nx + a] : 0.0;
+    const double nE = b < ny - 1 ? v[(size_t)b * nx + a + 1] : 0.0;
+    const double vbar = ((sW + sE) + (nW + nE)) * 0.25;
+    const double conv = upwind(u0, xm, xp) + upwind(vbar, ym, yp);
+    const double gp = (p[(size_t)b * nx + a + 1] - p[(size_t)b * nx + a]) * A.ih;
+    const double F = forcing(A, A.fu, (size_t)t);
+    double r = u0 + A.dt * ((F - conv) - gp);
+    if (b == ny - 1) r = r + A.lift;
+    fu[t] = r;
+}
+
+__global__ __launch_bounds__(256) void k_rhs_v(NsArgs A, const double* __restrict__ u, const double* __restrict__ v,
+                                               const double* __restrict__ p, double* __restrict__ fv)
+{
+    const int nx = A.nx, m = A.ny - 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * nx) return;
+    const int ii = (int)(t % nx), jj = (int)(t / nx);
+    const double v0 = v[t];
+    double xm, xp, ym, yp;
+    weno_pair(v_ext(v, nx, m, ii - 2, jj), v_ext(v, nx, m, ii - 1, jj), v0, v_ext(v, nx, m, ii + 1, jj),
+              v_ext(v, nx, m, ii + 2, jj), A.ih, xm, xp);
+    weno_pair(v_ext(v, nx, m, ii, jj - 2), v_ext(v, nx, m, ii, jj - 1), v0, v_ext(v, nx, m, ii, jj + 1),
+              v_ext(v, nx, m, ii, jj + 2), A.ih, ym, yp);
+    // mean of the four u around the point (wall values 0 left of the first, right of the
+    // last column)
+    const int mu = nx - 1;
+    const double sW = ii > 0 ? u[(size_t)jj * mu + ii - 1] : 0.0;
+    const double sE = ii < nx - 1 ? u[(size_t)jj * mu + ii] : 0.0;
+    const double nW = ii > 0 ? u[(size_t)(jj + 1) * mu + ii - 1] : 0.0;
+    const double nE = ii < nx - 1 ? u[(size_t)(jj + 1) * mu + ii] : 0.0;
+    const double ubar = ((sW + sE) + (nW + nE)) * 0.25;
+    const double conv = upwind(ubar, xm, xp) + upwind(v0, ym, yp);
+    const double gp = (p[(size_t)(jj + 1) * nx + ii] - p[(size_t)jj * nx + ii]) * A.ih;
+    const double F = forcing(A, A.fv, (size_t)t);
+    fv[t] = v0 + A.dt * ((F - conv) - gp);
+}
+
+__global__ __launch_bounds__(256) void k_neg_div(NsArgs A, const double* __restrict__ ut, const double* __restrict__ vt,
+                                                 double* __restrict__ fp)
+{
+    const int nx = A.nx, ny = A.ny;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nx * ny) return;
+    const int i = (int)(t % nx), j = (int)(t / nx);
+    const int mu = nx - 1;
+    const double uW = i > 0 ? ut[(size_t)j * mu + i - 1] : 0.0;
+    const double uE = i < nx - 1 ? ut[(size_t)j * mu + i] : 0.0;
+    const double vS = j > 0 ? vt[(size_t)(j - 1) * nx + i] : 0.0;
+    const double vN = j < ny - 1 ? vt[(size_t)j * nx + i] : 0.0;
+    fp[t] = -(((uE - uW) + (vN - vS)) * A.ih);
+}
+
+__global__ __launch_bounds__(256) void k_project(NsArgs A, const double* __restrict__ ut, const double* __restrict__ vt,
+                                                 const double* __restrict__ pt, const double* p_in,
+                                                 double* __restrict__ u_out, double* __restrict__ v_out,
+                                                 double* p_out)
+{
+    const int nx = A.nx, ny = A.ny;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nx * ny) return;
+    const int i = (int)(t % nx), j = (int)(t / nx);
+    const double pc = pt[t];
+    if (i < nx - 1) {
+        const size_t k = (size_t)j * (nx - 1) + i;
+        u_out[k] = ut[k] - A.dt * ((pt[t + 1] - pc) * A.ih);
+    }
+    if (j < ny - 1) v_out[t] = vt[t] - A.dt * ((pt[t + nx] - pc) * A.ih);
+    p_out[t] = p_in[t] + pc;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_sweep(hipStream_t s, const Lev& L, int nu, const double* f, const double* uin, double* uout)
+{
+    const int out = sweep_out(nu);
+    const int tx = (L.nx + out - 1) / out, ty = (L.ny + out - 1) / out;
+    if (nu == 1)
+        hipLaunchKernelGGL(k_sweep<1>, dim3(tx * ty), dim3(256), 0, s, L, f, uin, uout, tx);
+    else
+        hipLaunchKernelGGL(k_sweep<2>, dim3(tx * ty), dim3(256), 0, s, L, f, uin, uout, tx);
+}
+
+void launch_restrict(hipStream_t s, int loc, const Lev& Lf, const double* f, const double* u, int ncx, int ncy,
+                     double* uc, double* uc0, double* rc)
+{
+    const unsigned nb = blocks_for((int64_t)ncx * ncy);
+    if (loc == LOC_CELL)
+        hipLaunchKernelGGL(k_restrict<LOC_CELL>, dim3(nb), dim3(256), 0, s, Lf, f, u, ncx, ncy, uc, uc0, rc);
+    else if (loc == LOC_EDGE_X)
+        hipLaunchKernelGGL(k_restrict<LOC_EDGE_X>, dim3(nb), dim3(256), 0, s, Lf, f, u, ncx, ncy, uc, uc0, rc);
+    else
+        hipLaunchKernelGGL(k_restrict<LOC_EDGE_Y>, dim3(nb), dim3(256), 0, s, Lf, f, u, ncx, ncy, uc, uc0, rc);
+}
+
+void launch_coarse_rhs(hipStream_t s, const Lev& Lc, double* f, const double* u)
+{
+    hipLaunchKernelGGL(k_coarse_rhs, dim3(blocks_for((int64_t)Lc.nx * Lc.ny)), dim3(256), 0, s, Lc, f, u);
+}
+
+void launch_correct(hipStream_t s, int loc, const Lev& Lf, const double* uc, const double* uc0, int ncx, int ncy,
+                    const double* usrc, double* udst)
+{
+    const Coarse C{uc, uc0, ncx, ncy};
+    const unsigned nb = blocks_for((int64_t)Lf.nx * Lf.ny);
+    if (loc == LOC_CELL)
+        hipLaunchKernelGGL(k_correct<LOC_CELL>, dim3(nb), dim3(256), 0, s, Lf, C, usrc, udst);
+    else if (loc == LOC_EDGE_X)
+        hipLaunchKernelGGL(k_correct<LOC_EDGE_X>, dim3(nb), dim3(256), 0, s, Lf, C, usrc, udst);
+    else
+        hipLaunchKernelGGL(k_correct<LOC_EDGE_Y>, dim3(nb), dim3(256), 0, s, Lf, C, usrc, udst);
+}
+
+void launch_resnorm(hipStream_t s, const Lev& L, const double* f, const double* u, double* r, double* partials,
+                    double* out)
+{
+    const int64_t n = (int64_t)L.nx * L.ny;
+    const int nb = (int)std::min<int64_t>(kNormBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_resnorm, dim3(nb), dim3(256), 0, s, L, f, u, r, partials);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partials, nb, out);
+}
+
+void launch_copy(hipStream_t s, const double* src, double* dst, int64_t n)
+{
+    const unsigned nb = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_rhs_u(hipStream_t s, const NsArgs& a, const double* u, const double* v, const double* p, double* fu)
+{
+    hipLaunchKernelGGL(k_rhs_u, dim3(blocks_for((int64_t)(a.nx - 1) * a.ny)), dim3(256), 0, s, a, u, v, p, fu);
+}
+
+void launch_rhs_v(hipStream_t s, const NsArgs& a, const double* u, const double* v, const double* p, double* fv)
+{
+    hipLaunchKernelGGL(k_rhs_v, dim3(blocks_for((int64_t)a.nx * (a.ny - 1))), dim3(256), 0, s, a, u, v, p, fv);
+}
+
+void launch_neg_div(hipStream_t s, const NsArgs& a, const double* ut, const double* vt, double* fp)
+{
+    hipLaunchKernelGGL(k_neg_div, dim3(blocks_for((int64_t)a.nx * a.ny)), dim3(256), 0, s, a, ut, vt, fp);
+}
+
+void launch_project(hipStream_t s, const NsArgs& a, const double* ut, const double* vt, const double* pt,
+                    const double* p_in, double* u_out, double* v_out, double* p_out)
+{
+    hipLaunchKernelGGL(k_project, dim3(blocks_for((int64_t)a.nx * a.ny)), dim3(256), 0, s, a, ut, vt, pt, p_in, u_out,
+                       v_out, p_out);
+}
+
+}  // namespace stag
+}  // namespace fas

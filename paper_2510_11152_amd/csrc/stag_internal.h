@@ -1,0 +1,65 @@
+// Internal interface of the staggered-grid solver and the projection step
+// (kernels_stag.hip: kernels and launchers; stag_api.hip: the C ABI of include/fas_stag.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fas {
+namespace stag {
+
+// Kind of one axis of a variable's index set (Section 2.1).
+enum { K_CN = 0,   // cell-centred, even ghost (homogeneous Neumann)
+       K_CD = 1,   // cell-centred, odd ghost (homogeneous Dirichlet)
+       K_V = 2 };  // edge-centred: the wall points hold 0
+enum { LOC_CELL = 0, LOC_EDGE_X = 1, LOC_EDGE_Y = 2 };
+
+// One level of one variable: a w - c Lap_h w, unknowns nx x ny (row-major, x fastest).
+struct Lev {
+    int nx, ny;
+    int kx, ky;
+    double a, c, h2, ih2;
+};
+
+// Red-black sweep tiles: 64 x 64 values in LDS, nu sweeps (1 or 2) per launch.
+constexpr int kTile = 64;
+inline int sweep_out(int nu) { return kTile - 4 * nu; }
+constexpr int kNormBlocks = 1024;
+
+// nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers).
+void launch_sweep(hipStream_t s, const Lev& L, int nu, const double* f, const double* uin, double* uout);
+// Coarse iterate, its copy and the restricted residual of fine level Lf (location loc):
+// uc = uc0 = R u, rc = R (f - L u); coarse sizes ncx x ncy.
+void launch_restrict(hipStream_t s, int loc, const Lev& Lf, const double* f, const double* u, int ncx, int ncy,
+                     double* uc, double* uc0, double* rc);
+// f = f + L_c u on level Lc, in place (the FAS coarse right-hand side from R r).
+void launch_coarse_rhs(hipStream_t s, const Lev& Lc, double* f, const double* u);
+// udst = usrc + P (uc - uc0) on fine level Lf (udst may equal usrc).
+void launch_correct(hipStream_t s, int loc, const Lev& Lf, const double* uc, const double* uc0, int ncx, int ncy,
+                    const double* usrc, double* udst);
+// sum (f - L u)^2 into out[0] (fixed order); r (optional) receives the residual.
+void launch_resnorm(hipStream_t s, const Lev& L, const double* f, const double* u, double* r, double* partials,
+                    double* out);
+void launch_copy(hipStream_t s, const double* src, double* dst, int64_t n);
+
+// ---- projection step (Section 4.2) ---------------------------------------------------------
+struct NsArgs {
+    int nx, ny;              // cells
+    double dt, ih, ih2, lift;  // lift = (2 c lid) / h^2 with c = dt / Re
+    double lid;
+    int nforce;
+    const double* fu[4];
+    const double* fv[4];
+    double coef[4];
+};
+// f_u (ny x (nx-1)) from u^n, v^n, p^n; f_v ((ny-1) x nx).
+void launch_rhs_u(hipStream_t s, const NsArgs& a, const double* u, const double* v, const double* p, double* fu);
+void launch_rhs_v(hipStream_t s, const NsArgs& a, const double* u, const double* v, const double* p, double* fv);
+// f_p = -div(ut, vt) per cell.
+void launch_neg_div(hipStream_t s, const NsArgs& a, const double* ut, const double* vt, double* fp);
+// u_out = ut - dt d_x pt, v_out = vt - dt d_y pt, p_out = p_in + pt (p_out may equal p_in).
+void launch_project(hipStream_t s, const NsArgs& a, const double* ut, const double* vt, const double* pt,
+                    const double* p_in, double* u_out, double* v_out, double* p_out);
+
+}  // namespace stag
+}  // namespace fas

@@ -2,17 +2,18 @@
 its host-side argument checks report the documented status codes without touching a
 GPU."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fas.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def _declared():
-    txt = open(HEADER).read()
+    txt = "".join(open(h).read() for h in HEADERS)
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(fas_\w+)\s*\(", txt, flags=re.M)))
 
@@ -28,7 +29,8 @@ def lib():
 def test_header_declares_entry_points():
     names = _declared()
     for want in ("fas_solve", "fas_vcycle", "fas_smooth", "fas_residual", "fas_restrict", "fas_prolong_add",
-                 "fas_solve_mixed", "fas_kappa_grad", "fas_solve_transposed", "fas_last_error"):
+                 "fas_solve_mixed", "fas_kappa_grad", "fas_solve_transposed", "fas_last_error",
+                 "fas_stag_solve", "fas_stag_vcycle", "fas_ns_step", "fas_ns_create"):
         assert want in names
 
 
@@ -125,3 +127,51 @@ def test_solve_argument_errors_without_gpu(lib):
         assert lib.fas_kappa_grad(g, 1e-3, None, buf, buf, buf) == F.FAS_ERR_ARG
     finally:
         assert lib.fas_grid_destroy(g) == F.FAS_OK
+
+
+def test_staggered_workspace_size_shape_rules(lib):
+    for loc in (0, 1, 2):
+        assert lib.fas_stag_workspace_size(loc, 64, 64, 4) > 0
+        assert lib.fas_stag_workspace_size(loc, 64, 16, 4) > 0
+        assert lib.fas_stag_workspace_size(loc, 48, 48, 4) > 0      # 48 = 6 * 2^3
+        assert lib.fas_stag_workspace_size(loc, 4, 4, 4) == 0       # one level only
+        assert lib.fas_stag_workspace_size(loc, 64, 64, 1) == 0     # coarsest < 2
+    assert lib.fas_stag_workspace_size(3, 64, 64, 4) == 0           # unknown location
+    assert lib.fas_ns_workspace_size(64, 64, 4) >= lib.fas_stag_workspace_size(0, 64, 64, 4) + 64 * 64 * 8
+    assert lib.fas_ns_fields(0) == 6 and lib.fas_ns_fields(1) == 9 and lib.fas_ns_fields(2) == 0
+
+
+def test_staggered_create_errors_without_gpu(lib):
+    from paper_2510_11152_amd import _lib
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 40)   # never dereferenced by create
+    size = lib.fas_stag_workspace_size(1, 64, 64, 4)
+    assert lib.fas_stag_create(1, 64, 64, 1 / 64, 1, 4, fake, size - 1, None, ctypes.byref(out)) == _lib.FAS_ERR_NOMEM
+    assert lib.fas_stag_create(1, 64, 64, 1 / 64, 0, 4, fake, size, None, ctypes.byref(out)) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_create(1, 64, 64, -1.0, 1, 4, fake, size, None, ctypes.byref(out)) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_create(1, 4, 4, 0.25, 1, 4, fake, size, None, ctypes.byref(out)) == _lib.FAS_ERR_SHAPE
+    assert lib.fas_stag_create(1, 64, 64, 1 / 64, 1, 4, fake, size, None, ctypes.byref(out)) == _lib.FAS_OK
+    s = out
+    assert lib.fas_stag_levels(s) == 5                               # 64 .. 4
+    assert lib.fas_stag_set(s, _lib.FAS_OPT_COARSE_SWEEPS, 0.0) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_set(s, _lib.FAS_OPT_KMAX, 10.0) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_set(s, _lib.FAS_OPT_COARSE_SWEEPS, 8.0) == _lib.FAS_OK
+    buf = ctypes.c_void_p(1 << 41)
+    assert lib.fas_stag_solve(s, 1.0, 0.1, buf, buf, 1e-9, 2, 2, 20, None, None) == _lib.FAS_ERR_ARG   # aliased
+    assert lib.fas_stag_vcycle(s, 1.0, 0.1, None, buf, 2, 2) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_destroy(s) == _lib.FAS_OK
+    # projection step
+    ws = lib.fas_ns_workspace_size(64, 64, 4)
+    fields = (ctypes.c_void_p * 6)(*[(i + 2) << 40 for i in range(6)])
+    assert lib.fas_ns_create(64, 64, 1 / 64, 10.0, 0, 4, fields, fake, ws - 1, None, ctypes.byref(out)) == _lib.FAS_ERR_NOMEM
+    dup = (ctypes.c_void_p * 6)(*[(2 << 40)] * 6)
+    assert lib.fas_ns_create(64, 64, 1 / 64, 10.0, 0, 4, dup, fake, ws, None, ctypes.byref(out)) == _lib.FAS_ERR_ARG
+    assert lib.fas_ns_create(64, 64, 1 / 64, 10.0, 5, 4, fields, fake, ws, None, ctypes.byref(out)) == _lib.FAS_ERR_ARG
+    assert lib.fas_ns_create(64, 64, 1 / 64, 10.0, 0, 4, fields, fake, ws, None, ctypes.byref(out)) == _lib.FAS_OK
+    ns = out
+    fb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fas_ns_memory(ns, ctypes.byref(fb), ctypes.byref(wb)) == _lib.FAS_OK
+    assert fb.value == 2 * (63 * 64 * 2 + 64 * 64) * 8 and wb.value == ws
+    assert lib.fas_ns_step(ns, -1.0, 0.0, 0, None, None, None, 1e-9, 2, 2, 20, None, None) == _lib.FAS_ERR_ARG
+    assert lib.fas_ns_step(ns, 0.1, 0.0, 5, None, None, None, 1e-9, 2, 2, 20, None, None) == _lib.FAS_ERR_ARG
+    assert lib.fas_ns_destroy(ns) == _lib.FAS_OK
