@@ -71,7 +71,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule for the 8192^2 grids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="batched,adjoint,3d,orders",
+    ap.add_argument("--ns-dts", default="0.1,0.05,0.025,0.0125,0.00625",
+                    help="time steps of the projection convergence study (comma list)")
+    ap.add_argument("--forms", default="batched,adjoint,3d,orders,ns",
                     help="other workloads timed after the headline (comma list; 'none' to skip; "
                          "'table45' adds per-cycle times at the paper's Table 4/5 sizes)")
     return ap.parse_args()
@@ -401,6 +403,135 @@ def bench_3d(dev, steps=5, inner=4, cpu=True):
     return out
 
 
+def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=True):
+    """Section 4.4.3: Scheme 1 (first-order projection) on the staggered 4096^2 grid, Re = 10,
+    tol 1e-9, V(2,2), manufactured source at t^{n+1}, t = 0 .. 1 for each dt; L2 errors at
+    t = 1 against the exact solution and their orders.  Then both field layouts at one dt
+    (fields, workspace, peak device memory, time per step), and the red-black sweep
+    kernel's bandwidth on the finest u grid timed with HIP events."""
+    import numpy as np
+    import torch
+
+    from oracle import ns as ons
+    from paper_2510_11152_amd import NavierStokes2D, StaggeredSolver
+
+    h = 1.0 / n
+    Fu, Fv = ons.manufactured_fields(n, n, h, re)
+    Fu = [torch.from_numpy(x).to(dev) for x in Fu]
+    Fv = [torch.from_numpy(x).to(dev) for x in Fv]
+    ue, ve, pe = ons.exact(n, n, h, 1.0)
+    u0, v0, p0 = ons.exact(n, n, h, 0.0)
+    out = {"grid": [n, n], "re": re, "tol": 1e-9, "rows": []}
+    total_steps, total_s, cycles = 0, 0.0, [0, 0, 0]
+    prev = None
+    for dt in dts:
+        G = NavierStokes2D(n, n, h, re)
+        G.u.copy_(torch.from_numpy(u0))
+        G.v.copy_(torch.from_numpy(v0))
+        G.p.copy_(torch.from_numpy(p0))
+        steps = int(round(1.0 / dt))
+
+        def run():
+            cyc = [0, 0, 0]
+            for k in range(steps):
+                st, c, _ = G.step(dt, 0.0, Fu, Fv, ons.manufactured_coef((k + 1) * dt), tol=1e-9)
+                if st != 0:
+                    raise RuntimeError("a projection solve did not converge at step %d" % k)
+                cyc = [a + b for a, b in zip(cyc, c)]
+            return cyc
+
+        t, cyc = _timed(run, torch.cuda.synchronize)
+        u, v, p = G.u.cpu().numpy(), G.v.cpu().numpy(), G.p.cpu().numpy()
+        errs = [ons.l2(u - ue, h), ons.l2(v - ve, h), ons.l2((p - p.mean()) - (pe - pe.mean()), h)]
+        row = {"dt": dt, "steps": steps, "s": t, "ms_per_step": 1e3 * t / steps, "errors_uvp": errs,
+               "cycles_per_step_uvp": [c / steps for c in cyc]}
+        if prev is not None:
+            row["orders_uvp"] = [float(np.log2(a / b)) for a, b in zip(prev, errs)]
+        prev = errs
+        out["rows"].append(row)
+        total_steps += steps
+        total_s += t
+        cycles = [a + b for a, b in zip(cycles, cyc)]
+        print("bench: ns dt %.5f %.2f ms/step errors %s" % (dt, row["ms_per_step"], errs), file=sys.stderr,
+              flush=True)
+        del G
+    out["ms_per_step"] = 1e3 * total_s / total_steps
+    out["cycles_per_step_uvp"] = [c / total_steps for c in cycles]
+    # both layouts at dt = 1/40: memory and time
+    layouts = {}
+    for layout in ("memory_efficient", "classical"):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats(dev)
+        base = torch.cuda.memory_allocated(dev)
+        G = NavierStokes2D(n, n, h, re, layout=layout)
+        fb, wb = G.memory()
+        dt = 0.025
+
+        def run():
+            for k in range(40):
+                G.step(dt, 0.0, Fu, Fv, ons.manufactured_coef((k + 1) * dt), tol=1e-9)
+
+        t, _ = _timed(run, torch.cuda.synchronize)
+        layouts[layout] = {"fields": len(G.fields), "field_bytes": fb, "workspace_bytes": wb,
+                           "peak_bytes": torch.cuda.max_memory_allocated(dev) - base, "ms_per_step": 1e3 * t / 40}
+        del G
+    layouts["field_bytes_saved"] = 1.0 - layouts["memory_efficient"]["field_bytes"] / layouts["classical"]["field_bytes"]
+    layouts["time_ratio_classical_over_memory_efficient"] = (layouts["classical"]["ms_per_step"] /
+                                                            layouts["memory_efficient"]["ms_per_step"])
+    out["layouts_dt_1_40"] = layouts
+    # the finest-level red-black sweep kernel (two sweeps per launch) on the u grid
+    S = StaggeredSolver("edge_x", n, n, h)
+    f = torch.randn(S.shape, dtype=torch.float64, device=dev)
+    w = torch.randn_like(f)
+    S.smooth(1.0, 0.1 / re, f, w, 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        S.smooth(1.0, 0.1 / re, f, w, 4)       # two launches of the two-sweep kernel
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / (2 * reps)
+    cells = S.shape[0] * S.shape[1]
+    alg = 24.0 * cells                          # read w and f, write w: 3 x 8 bytes per value
+    out["sweep_kernel"] = {"kernel": "k_sweep<2> (two red-black sweeps)", "grid": list(S.shape), "avg_us": us,
+                           "algorithmic_bytes": alg, "gbs": alg / (us * 1e-6) / 1e9,
+                           "frac": alg / (us * 1e-6) / 8e12}
+    del S, f, w
+    if cpu:
+        out["cpu_baseline"] = ns_cpu_baseline(n, re, out["cycles_per_step_uvp"])
+        out["speedup_vs_cpu_baseline"] = out["cpu_baseline"]["value"] / (out["ms_per_step"] / 1e3)
+    torch.cuda.empty_cache()
+    return out
+
+
+def ns_cpu_baseline(n, re, cycles_uvp):
+    """The oracle on a bounded sample of one 4096^2 projection step: the u momentum
+    right-hand side and one V(2,2) cycle of the u solve, extrapolated to a step as two
+    right-hand sides and the GPU's mean cycles of the three solves."""
+    import numpy as np
+
+    from oracle import ns as ons
+    from oracle import staggered as ost
+
+    h = 1.0 / n
+    u, v, p = ons.exact(n, n, h, 0.3)
+    t0 = time.perf_counter()
+    fu = ons.momentum_rhs_u(u, v, p, h, 0.025, 0.0)
+    t_rhs = time.perf_counter() - t0
+    P = ost.StagProblem(ost.EDGE_X, n, n, h)
+    w = np.zeros(P.shape())
+    t0 = time.perf_counter()
+    ost.vcycle(P, 1.0, 0.025 / re, fu, w)
+    t_cyc = time.perf_counter() - t0
+    value = 2 * t_rhs + sum(cycles_uvp) * t_cyc
+    return {"value": value, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": "one u right-hand side (%.1f s) and one u V(2,2) cycle (%.1f s) at 4096^2, per step "
+                      "2 right-hand sides + %.1f cycles (numpy, one thread)" % (t_rhs, t_cyc, sum(cycles_uvp))}
+
+
 def stream_ceiling(dev, gib=1.0, reps=10):
     """Attainable HBM bandwidth from the library's own streaming probe (fas_stream_probe):
     read, copy and triad (c = a + b) over `gib` GiB arrays, 16 B per lane, best of a few
@@ -644,6 +775,10 @@ def main():
     if "3d" in forms:
         print("bench: 3D heat", file=sys.stderr, flush=True)
         result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline)
+    if "ns" in forms:
+        print("bench: staggered projection step (4096^2)", file=sys.stderr, flush=True)
+        result["ns"] = bench_ns(dev, dts=tuple(float(x) for x in args.ns_dts.split(",")),
+                                cpu=not args.no_cpu_baseline)
 
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on two cycles", file=sys.stderr, flush=True)

@@ -50,64 +50,87 @@ __device__ __forceinline__ double resid_at(const Lev& L, const double* f, const 
     return f[i] - (diag(L, x, y) * u[i] - L.c * nbsum(L, u, x, y)) * L.ih2;
 }
 
-// ---- red-black sweeps on an LDS tile --------------------------------------------------------
-// A 256-thread block loads a 64 x 64 window (lane = column, each wave 16 rows) of the iterate
-// and the right-hand side, runs nu red-black sweeps on it in LDS and writes the window's
-// interior of (64 - 4 nu)^2 values.  Half-sweep k can only update values at distance >= k
-// from the window's edge correctly; after 2 nu half-sweeps the interior (distance >= 2 nu) is
-// exactly what nu sweeps over the whole grid give.  Values outside the grid stay 0 in LDS
-// (the 0.0 neighbours of the point formula).  Within a half-sweep the updated points read
-// only points of the other colour, so the update runs in place in LDS.
+// ---- red-black sweeps on an LDS window ------------------------------------------------------
+// A 512-thread block (8 waves) loads a 128 x 64 window of the iterate into LDS: lane l of a
+// wave owns the column pair (2l, 2l + 1) of the window and each wave 8 rows, whose
+// right-hand side values stay in registers.  The block runs nu red-black sweeps on the window
+// and writes its interior, (128 - 4 nu) x (64 - 4 nu) values.  Half-sweep k updates values
+// at distance >= k from the window's edge correctly, so after 2 nu half-sweeps the interior
+// (distance >= 2 nu) holds exactly what nu sweeps over the whole grid give.  Values outside
+// the grid stay 0 in LDS (the 0.0 neighbours of the point formula).  Within a half-sweep the
+// updated points read only points of the other colour, so the update runs in place.
+//
+// The window origin is even (2 nu and the interior width are even), so in a row of one
+// colour exactly one column of every pair is updated, the same one for the whole wave: every
+// lane updates one point per row.  Even and odd columns sit in separate LDS arrays, which
+// makes every LDS access of a wave 64 consecutive doubles.
 template <int NU>
-__global__ __launch_bounds__(256) void k_sweep(Lev L, const double* __restrict__ f, const double* __restrict__ uin,
+__global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__ f, const double* __restrict__ uin,
                                                double* __restrict__ uout, int tiles_x)
 {
-    constexpr int T = kTile, H = 2 * NU, OUT = T - 2 * H, RPW = T / 4;
-    __shared__ double su[T][T];
-    __shared__ double sf[T][T];
+    constexpr int WY = kWinRows, H = 2 * NU, OX = 2 * kTile - 2 * H, OY = WY - 2 * H, RPW = WY / 8;
+    __shared__ double se[WY][kTile];  // even columns of the window
+    __shared__ double so[WY][kTile];  // odd columns
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     const int tx = (int)(b % (unsigned)tiles_x), ty = (int)(b / (unsigned)tiles_x);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int gx = tx * OUT - H + lane;
-    const int ybase = ty * OUT - H;
-    const bool xin = gx >= 0 && gx < L.nx;
+    const int x0 = tx * OX - H + 2 * lane;  // grid column of the lane's even column
+    const int yw = ty * OY - H + w * RPW;   // grid row of the wave's first row
+    const bool in0 = x0 >= 0 && x0 < L.nx, in1 = x0 + 1 >= 0 && x0 + 1 < L.nx;
+    double u0[RPW], u1[RPW], f0[RPW], f1[RPW];
+#pragma unroll
     for (int i = 0; i < RPW; ++i) {
-        const int r = w * RPW + i, gy = ybase + r;
-        double uv = 0.0, fv = 0.0;
-        if (xin && gy >= 0 && gy < L.ny) {
-            const size_t idx = (size_t)gy * L.nx + gx;
-            uv = uin[idx];
-            fv = f[idx];
-        }
-        su[r][lane] = uv;
-        sf[r][lane] = fv;
+        const int gy = yw + i;
+        const bool row = gy >= 0 && gy < L.ny;
+        const size_t idx = row ? (size_t)gy * L.nx + (size_t)(in0 ? x0 : 0) : 0;
+        u0[i] = row && in0 ? uin[idx] : 0.0;
+        f0[i] = row && in0 ? f[idx] : 0.0;
+        u1[i] = row && in1 ? uin[(size_t)gy * L.nx + x0 + 1] : 0.0;
+        f1[i] = row && in1 ? f[(size_t)gy * L.nx + x0 + 1] : 0.0;
     }
-    double kx = 4.0;
-    if (gx == 0) kx += kshift(L.kx);
-    if (gx == L.nx - 1) kx += kshift(L.kx);
-    const bool col_ok = xin && lane >= 1 && lane <= T - 2;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        se[w * RPW + i][lane] = u0[i];
+        so[w * RPW + i][lane] = u1[i];
+    }
+    // k along x of the two columns
+    double kx0 = 4.0, kx1 = 4.0;
+    if (x0 == 0) kx0 += kshift(L.kx);
+    if (x0 == L.nx - 1) kx0 += kshift(L.kx);
+    if (x0 + 1 == 0) kx1 += kshift(L.kx);
+    if (x0 + 1 == L.nx - 1) kx1 += kshift(L.kx);
     __syncthreads();
 #pragma unroll
     for (int hs = 0; hs < 2 * NU; ++hs) {
         const int colour = (hs & 1) ^ 1;  // sets 1-2 (odd index sum) first
-        if (col_ok) {
-            for (int i = 0; i < RPW; ++i) {
-                const int r = w * RPW + i, gy = ybase + r;
-                if (r < 1 || r > T - 2 || gy < 0 || gy >= L.ny || ((gx + gy) & 1) != colour) continue;
-                double k = kx;
-                if (gy == 0) k += kshift(L.ky);
-                if (gy == L.ny - 1) k += kshift(L.ky);
-                const double D = L.a * L.h2 + L.c * k;
-                const double s = (su[r][lane - 1] + su[r][lane + 1]) + (su[r - 1][lane] + su[r + 1][lane]);
-                su[r][lane] = (L.c * s + L.h2 * sf[r][lane]) / D;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = w * RPW + i, gy = yw + i;
+            if (r < 1 || r > WY - 2 || gy < 0 || gy >= L.ny) continue;
+            const int odd = (colour + gy) & 1;  // the pair's column with this colour (wave-uniform)
+            double k = odd ? kx1 : kx0;
+            if (gy == 0) k += kshift(L.ky);
+            if (gy == L.ny - 1) k += kshift(L.ky);
+            const double D = L.a * L.h2 + L.c * k;
+            if (odd) {
+                if (lane == 63 || !in1) continue;
+                const double s = (se[r][lane] + se[r][lane + 1]) + (so[r - 1][lane] + so[r + 1][lane]);
+                so[r][lane] = (L.c * s + L.h2 * f1[i]) / D;
+            } else {
+                if (lane == 0 || !in0) continue;
+                const double s = (so[r][lane - 1] + so[r][lane]) + (se[r - 1][lane] + se[r + 1][lane]);
+                se[r][lane] = (L.c * s + L.h2 * f0[i]) / D;
             }
         }
         __syncthreads();
     }
-    if (xin && lane >= H && lane < H + OUT) {
+    if (2 * lane >= H && 2 * lane < H + OX) {
+#pragma unroll
         for (int i = 0; i < RPW; ++i) {
-            const int r = w * RPW + i, gy = ybase + r;
-            if (r >= H && r < H + OUT && gy >= 0 && gy < L.ny) uout[(size_t)gy * L.nx + gx] = su[r][lane];
+            const int r = w * RPW + i, gy = yw + i;
+            if (r < H || r >= H + OY || gy < 0 || gy >= L.ny) continue;
+            if (in0) uout[(size_t)gy * L.nx + x0] = se[r][lane];
+            if (in1) uout[(size_t)gy * L.nx + x0 + 1] = so[r][lane];
         }
     }
 }
@@ -424,12 +447,12 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 void launch_sweep(hipStream_t s, const Lev& L, int nu, const double* f, const double* uin, double* uout)
 {
-    const int out = sweep_out(nu);
-    const int tx = (L.nx + out - 1) / out, ty = (L.ny + out - 1) / out;
+    const int ox = 2 * kTile - 4 * nu, oy = kWinRows - 4 * nu;
+    const int tx = (L.nx + ox - 1) / ox, ty = (L.ny + oy - 1) / oy;
     if (nu == 1)
-        hipLaunchKernelGGL(k_sweep<1>, dim3(tx * ty), dim3(256), 0, s, L, f, uin, uout, tx);
+        hipLaunchKernelGGL(k_sweep<1>, dim3(tx * ty), dim3(512), 0, s, L, f, uin, uout, tx);
     else
-        hipLaunchKernelGGL(k_sweep<2>, dim3(tx * ty), dim3(256), 0, s, L, f, uin, uout, tx);
+        hipLaunchKernelGGL(k_sweep<2>, dim3(tx * ty), dim3(512), 0, s, L, f, uin, uout, tx);
 }
 
 void launch_restrict(hipStream_t s, int loc, const Lev& Lf, const double* f, const double* u, int ncx, int ncy,

@@ -21,9 +21,10 @@ struct Lev {
     double a, c, h2, ih2;
 };
 
-// Red-black sweep tiles: 64 x 64 values in LDS, nu sweeps (1 or 2) per launch.
+// Red-black sweep windows: 2 * kTile columns (a column pair per lane) x kWinRows rows in
+// LDS, nu sweeps (1 or 2) per launch.
 constexpr int kTile = 64;
-inline int sweep_out(int nu) { return kTile - 4 * nu; }
+constexpr int kWinRows = 64;
 constexpr int kNormBlocks = 1024;
 
 // nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers).
