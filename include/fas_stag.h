@@ -53,7 +53,10 @@ size_t fas_stag_workspace_size(int loc, int64_t nx, int64_t ny, int coarsest);
 int fas_stag_create(int loc, int64_t nx, int64_t ny, double h, int cell_bc, int coarsest, void* workspace,
                     size_t workspace_bytes, void* stream, fas_stag_t** out);
 int fas_stag_destroy(fas_stag_t* s);
-/* FAS_OPT_COARSE_SWEEPS (>= 1) is the only option (FAS_ERR_ARG otherwise). */
+/* Options (FAS_ERR_ARG for any other): FAS_OPT_COARSE_SWEEPS (>= 1) and FAS_OPT_FUSED
+ * (1, the default: the levels from 64 x 64 unknowns down run as one persistent workgroup
+ * with every array in LDS, and the FAS correction is applied inside the first
+ * post-smoothing launch; 0: one kernel per step and level).  Both give identical results. */
 int fas_stag_set(fas_stag_t* s, int option, double value);
 int fas_stag_levels(const fas_stag_t* s);
 
@@ -107,7 +110,7 @@ size_t fas_ns_workspace_size(int64_t nx, int64_t ny, int coarsest);
 int fas_ns_create(int64_t nx, int64_t ny, double h, double re, int layout, int coarsest, void* const* fields,
                   void* workspace, size_t workspace_bytes, void* stream, fas_ns_t** out);
 int fas_ns_destroy(fas_ns_t* ns);
-/* Applies to the three solvers (FAS_OPT_COARSE_SWEEPS). */
+/* Applies an option of fas_stag_set to the three solvers. */
 int fas_ns_set(fas_ns_t* ns, int option, double value);
 /* One step of size dt.  force_u / force_v: nforce device fields each (NULL if nforce = 0),
  * coef: nforce host doubles.  Each solve stops at h ||r||_2 <= tol or kmax cycles.

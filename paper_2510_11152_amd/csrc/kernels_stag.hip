@@ -50,6 +50,110 @@ __device__ __forceinline__ double resid_at(const Lev& L, const double* f, const 
     return f[i] - (diag(L, x, y) * u[i] - L.c * nbsum(L, u, x, y)) * L.ih2;
 }
 
+// ---- transfers ------------------------------------------------------------------------------
+// Restriction (Appendix C for cells; Appendix D's six-point form for edges) of the iterate
+// and of the residual (computed at the fine taps on the fly) at coarse point (K, J).
+template <int LOC>
+__device__ __forceinline__ void restrict_point(const Lev& Lf, const double* f, const double* u, int K, int J,
+                                               double& ru, double& rr)
+{
+    if (LOC == LOC_CELL) {
+        const int x = 2 * K, y = 2 * J;
+        const size_t i = (size_t)y * Lf.nx + x;
+        ru = ((u[i] + u[i + 1]) + (u[i + Lf.nx] + u[i + Lf.nx + 1])) * 0.25;
+        rr = ((resid_at(Lf, f, u, x, y) + resid_at(Lf, f, u, x + 1, y)) +
+              (resid_at(Lf, f, u, x, y + 1) + resid_at(Lf, f, u, x + 1, y + 1))) * 0.25;
+    } else if (LOC == LOC_EDGE_X) {
+        double gu[2], gr[2];
+        for (int q = 0; q < 2; ++q) {
+            const int y = 2 * J + q, x = 2 * K;
+            const size_t i = (size_t)y * Lf.nx + x;
+            gu[q] = (u[i] + 2.0 * u[i + 1]) + u[i + 2];
+            gr[q] = (resid_at(Lf, f, u, x, y) + 2.0 * resid_at(Lf, f, u, x + 1, y)) + resid_at(Lf, f, u, x + 2, y);
+        }
+        ru = (gu[0] + gu[1]) * 0.125;
+        rr = (gr[0] + gr[1]) * 0.125;
+    } else {
+        double gu[2], gr[2];
+        for (int q = 0; q < 2; ++q) {
+            const int x = 2 * K + q, y = 2 * J;
+            const size_t i = (size_t)y * Lf.nx + x;
+            gu[q] = (u[i] + 2.0 * u[i + Lf.nx]) + u[i + 2 * (size_t)Lf.nx];
+            gr[q] = (resid_at(Lf, f, u, x, y) + 2.0 * resid_at(Lf, f, u, x, y + 1)) + resid_at(Lf, f, u, x, y + 2);
+        }
+        ru = (gu[0] + gu[1]) * 0.125;
+        rr = (gr[0] + gr[1]) * 0.125;
+    }
+}
+
+// Prolongation of the correction e = uc - uc0 (Appendix C: injection; Appendix D: linear
+// along the cell-centred axis with odd ghosts first, then midpoint means along the edge axis
+// with 0 at the wall points).  Coarse (stag_internal.h) gives e(K, J).
+// Linear interpolation along a cell-centred axis from the coarse value of the cell and that
+// of its neighbour on the side of the fine point (odd ghost beyond the last cell).
+__device__ __forceinline__ double lin_cell(double e0, double enb) { return (3.0 * e0 + enb) * 0.25; }
+
+// P e at fine point (x, y).
+template <int LOC>
+__device__ __forceinline__ double prolong_point(const Coarse& C, int x, int y)
+{
+    if (LOC == LOC_CELL) return C.e(x >> 1, y >> 1);
+    if (LOC == LOC_EDGE_X) {
+        const int J = y >> 1;
+        auto col = [&](int K) {
+            const double e0 = C.e(K, J);
+            const double nb = (y & 1) ? (J < C.ncy - 1 ? C.e(K, J + 1) : -e0) : (J > 0 ? C.e(K, J - 1) : -e0);
+            return lin_cell(e0, nb);
+        };
+        const int K = x >> 1;
+        if (x & 1) return col(K);
+        const double left = K >= 1 ? col(K - 1) : 0.0;
+        const double right = K <= C.ncx - 1 ? col(K) : 0.0;
+        return (left + right) * 0.5;
+    }
+    const int K = x >> 1;
+    auto row = [&](int J) {
+        const double e0 = C.e(K, J);
+        const double nb = (x & 1) ? (K < C.ncx - 1 ? C.e(K + 1, J) : -e0) : (K > 0 ? C.e(K - 1, J) : -e0);
+        return lin_cell(e0, nb);
+    };
+    const int J = y >> 1;
+    if (y & 1) return row(J);
+    const double below = J >= 1 ? row(J - 1) : 0.0;
+    const double above = J <= C.ncy - 1 ? row(J) : 0.0;
+    return (below + above) * 0.5;
+}
+
+template <int LOC>
+__global__ __launch_bounds__(256) void k_restrict(Lev Lf, const double* __restrict__ f, const double* __restrict__ u,
+                                                  int ncx, int ncy, double* __restrict__ uc,
+                                                  double* __restrict__ uc0, double* __restrict__ rc)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ncx * ncy) return;
+    double ru, rr;
+    restrict_point<LOC>(Lf, f, u, (int)(t % ncx), (int)(t / ncx), ru, rr);
+    uc[t] = ru;
+    uc0[t] = ru;
+    rc[t] = rr;
+}
+
+__global__ __launch_bounds__(256) void k_coarse_rhs(Lev L, double* __restrict__ f, const double* __restrict__ u)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)L.nx * L.ny) return;
+    const int x = (int)(t % L.nx), y = (int)(t / L.nx);
+    f[t] = f[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
+}
+
+template <int LOC>
+__global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double* usrc, double* udst)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Lf.nx * Lf.ny) return;
+    udst[t] = usrc[t] + prolong_point<LOC>(C, (int)(t % Lf.nx), (int)(t / Lf.nx));
+}
+
 // ---- red-black sweeps on an LDS window ------------------------------------------------------
 // A 512-thread block (8 waves) loads a 128 x 64 window of the iterate into LDS: lane l of a
 // wave owns the column pair (2l, 2l + 1) of the window and each wave 8 rows, whose
@@ -64,9 +168,12 @@ __device__ __forceinline__ double resid_at(const Lev& L, const double* f, const 
 // colour exactly one column of every pair is updated, the same one for the whole wave: every
 // lane updates one point per row.  Even and odd columns sit in separate LDS arrays, which
 // makes every LDS access of a wave 64 consecutive doubles.
-template <int NU>
+//
+// CORR: the FAS correction is applied as the window is loaded (u = uin + P e, the same point
+// formula as k_correct), so the corrected iterate before the post-smoothing is never stored.
+template <int NU, int LOC, bool CORR>
 __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__ f, const double* __restrict__ uin,
-                                               double* __restrict__ uout, int tiles_x)
+                                               double* __restrict__ uout, int tiles_x, Coarse C)
 {
     constexpr int WY = kWinRows, H = 2 * NU, OX = 2 * kTile - 2 * H, OY = WY - 2 * H, RPW = WY / 8;
     __shared__ double se[WY][kTile];  // even columns of the window
@@ -87,6 +194,15 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
         f0[i] = row && in0 ? f[idx] : 0.0;
         u1[i] = row && in1 ? uin[(size_t)gy * L.nx + x0 + 1] : 0.0;
         f1[i] = row && in1 ? f[(size_t)gy * L.nx + x0 + 1] : 0.0;
+    }
+    if (CORR) {
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int gy = yw + i;
+            if (gy < 0 || gy >= L.ny) continue;
+            if (in0) u0[i] = u0[i] + prolong_point<LOC>(C, x0, gy);
+            if (in1) u1[i] = u1[i] + prolong_point<LOC>(C, x0 + 1, gy);
+        }
     }
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
@@ -135,117 +251,72 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
     }
 }
 
-// ---- transfers ------------------------------------------------------------------------------
-// Restriction (Appendix C for cells; Appendix D's six-point form for edges) of the iterate
-// and of the residual, computed at the fine taps on the fly.
-template <int LOC>
-__global__ __launch_bounds__(256) void k_restrict(Lev Lf, const double* __restrict__ f, const double* __restrict__ u,
-                                                  int ncx, int ncy, double* __restrict__ uc,
-                                                  double* __restrict__ uc0, double* __restrict__ rc)
+// ---- persistent coarse tail ------------------------------------------------------------------
+// One 1024-thread workgroup runs the V-cycle of the coarsest levels (top .. coarsest) with
+// every array in LDS: the top level's iterate and right-hand side are loaded once and the
+// iterate is written back at the end, instead of five launches per level.  Each step uses
+// the point formulas of the per-level kernels, so the result is the same bit for bit.
+__device__ void tail_smooth(const Lev& L, const double* f, double* u, int nu)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)ncx * ncy) return;
-    const int K = (int)(t % ncx), J = (int)(t / ncx);
-    double ru, rr;
-    if (LOC == LOC_CELL) {
-        const int x = 2 * K, y = 2 * J;
-        const size_t i = (size_t)y * Lf.nx + x;
-        ru = ((u[i] + u[i + 1]) + (u[i + Lf.nx] + u[i + Lf.nx + 1])) * 0.25;
-        rr = ((resid_at(Lf, f, u, x, y) + resid_at(Lf, f, u, x + 1, y)) +
-              (resid_at(Lf, f, u, x, y + 1) + resid_at(Lf, f, u, x + 1, y + 1))) * 0.25;
-    } else if (LOC == LOC_EDGE_X) {
-        double gu[2], gr[2];
-        for (int q = 0; q < 2; ++q) {
-            const int y = 2 * J + q, x = 2 * K;
-            const size_t i = (size_t)y * Lf.nx + x;
-            gu[q] = (u[i] + 2.0 * u[i + 1]) + u[i + 2];
-            gr[q] = (resid_at(Lf, f, u, x, y) + 2.0 * resid_at(Lf, f, u, x + 1, y)) + resid_at(Lf, f, u, x + 2, y);
+    const int n = L.nx * L.ny;
+    for (int sw = 0; sw < nu; ++sw) {
+        for (int colour = 1; colour >= 0; --colour) {  // sets 1-2 (odd index sum) first
+            for (int t = threadIdx.x; t < n; t += blockDim.x) {
+                const int x = t % L.nx, y = t / L.nx;
+                if (((x + y) & 1) != colour) continue;
+                u[t] = (L.c * nbsum(L, u, x, y) + L.h2 * f[t]) / diag(L, x, y);
+            }
+            __syncthreads();
         }
-        ru = (gu[0] + gu[1]) * 0.125;
-        rr = (gr[0] + gr[1]) * 0.125;
-    } else {
-        double gu[2], gr[2];
-        for (int q = 0; q < 2; ++q) {
-            const int x = 2 * K + q, y = 2 * J;
-            const size_t i = (size_t)y * Lf.nx + x;
-            gu[q] = (u[i] + 2.0 * u[i + Lf.nx]) + u[i + 2 * (size_t)Lf.nx];
-            gr[q] = (resid_at(Lf, f, u, x, y) + 2.0 * resid_at(Lf, f, u, x, y + 1)) + resid_at(Lf, f, u, x, y + 2);
-        }
-        ru = (gu[0] + gu[1]) * 0.125;
-        rr = (gr[0] + gr[1]) * 0.125;
     }
-    uc[t] = ru;
-    uc0[t] = ru;
-    rc[t] = rr;
 }
 
-__global__ __launch_bounds__(256) void k_coarse_rhs(Lev L, double* __restrict__ f, const double* __restrict__ u)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)L.nx * L.ny) return;
-    const int x = (int)(t % L.nx), y = (int)(t / L.nx);
-    f[t] = f[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
-}
-
-// Prolongation of the correction e = uc - uc0 (Appendix C: injection; Appendix D: linear
-// along the cell-centred axis with odd ghosts first, then midpoint means along the edge axis
-// with 0 at the wall points).
-struct Coarse {
-    const double* uc;
-    const double* uc0;
-    int ncx, ncy;
-    __device__ __forceinline__ double e(int K, int J) const
-    {
-        const size_t i = (size_t)J * ncx + K;
-        return uc[i] - uc0[i];
-    }
-};
-
-// Linear interpolation along the cell-centred axis: fine index q inside coarse cell Q, the
-// coarse values e(Q) and its neighbour (odd ghost beyond the last cell).
-__device__ __forceinline__ double lin_cell(double e0, double enb) { return (3.0 * e0 + enb) * 0.25; }
-
 template <int LOC>
-__global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double* usrc, double* udst)
+__global__ __launch_bounds__(1024) void k_tail(TailArgs A)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)Lf.nx * Lf.ny) return;
-    const int x = (int)(t % Lf.nx), y = (int)(t / Lf.nx);
-    double pe;
-    if (LOC == LOC_CELL) {
-        pe = C.e(x >> 1, y >> 1);
-    } else if (LOC == LOC_EDGE_X) {
-        const int J = y >> 1;
-        auto col = [&](int K) {
-            const double e0 = C.e(K, J);
-            const double nb = (y & 1) ? (J < C.ncy - 1 ? C.e(K, J + 1) : -e0) : (J > 0 ? C.e(K, J - 1) : -e0);
-            return lin_cell(e0, nb);
-        };
-        const int K = x >> 1;
-        if (x & 1) {
-            pe = col(K);
-        } else {
-            const double left = K >= 1 ? col(K - 1) : 0.0;
-            const double right = K <= C.ncx - 1 ? col(K) : 0.0;
-            pe = (left + right) * 0.5;
-        }
-    } else {
-        const int K = x >> 1;
-        auto row = [&](int J) {
-            const double e0 = C.e(K, J);
-            const double nb = (x & 1) ? (K < C.ncx - 1 ? C.e(K + 1, J) : -e0) : (K > 0 ? C.e(K - 1, J) : -e0);
-            return lin_cell(e0, nb);
-        };
-        const int J = y >> 1;
-        if (y & 1) {
-            pe = row(J);
-        } else {
-            const double below = J >= 1 ? row(J - 1) : 0.0;
-            const double above = J <= C.ncy - 1 ? row(J) : 0.0;
-            pe = (below + above) * 0.5;
-        }
+    __shared__ double lds[kTailDoubles];
+    const int n0 = A.op[0].nx * A.op[0].ny;
+    for (int t = threadIdx.x; t < n0; t += blockDim.x) {
+        lds[A.ou[0] + t] = A.u[t];
+        lds[A.of[0] + t] = A.f[t];
     }
-    udst[t] = usrc[t] + pe;
+    __syncthreads();
+    for (int l = 0; l + 1 < A.nlev; ++l) {
+        const Lev& L = A.op[l];
+        const Lev& Lc = A.op[l + 1];
+        double* u = lds + A.ou[l];
+        const double* f = lds + A.of[l];
+        tail_smooth(L, f, u, A.nu1);
+        double* uc = lds + A.ou[l + 1];
+        double* uc0 = lds + A.ou0[l + 1];
+        double* fc = lds + A.of[l + 1];
+        const int nc = Lc.nx * Lc.ny;
+        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+            double ru, rr;
+            restrict_point<LOC>(L, f, u, t % Lc.nx, t / Lc.nx, ru, rr);
+            uc[t] = ru;
+            uc0[t] = ru;
+            fc[t] = rr;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+            const int x = t % Lc.nx, y = t / Lc.nx;
+            fc[t] = fc[t] + (diag(Lc, x, y) * uc[t] - Lc.c * nbsum(Lc, uc, x, y)) * Lc.ih2;
+        }
+        __syncthreads();
+    }
+    const int lc = A.nlev - 1;
+    tail_smooth(A.op[lc], lds + A.of[lc], lds + A.ou[lc], A.nuc);  // Remark 1
+    for (int l = A.nlev - 2; l >= 0; --l) {
+        const Lev& L = A.op[l];
+        const Coarse C{lds + A.ou[l + 1], lds + A.ou0[l + 1], A.op[l + 1].nx, A.op[l + 1].ny};
+        double* u = lds + A.ou[l];
+        const int n = L.nx * L.ny;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) u[t] = u[t] + prolong_point<LOC>(C, t % L.nx, t / L.nx);
+        __syncthreads();
+        tail_smooth(L, lds + A.of[l], u, A.nu2);
+    }
+    for (int t = threadIdx.x; t < n0; t += blockDim.x) A.u[t] = lds[A.ou[0] + t];
 }
 
 // ---- residual norm -------------------------------------------------------------------------
@@ -445,14 +516,50 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-void launch_sweep(hipStream_t s, const Lev& L, int nu, const double* f, const double* uin, double* uout)
+template <int NU, int LOC>
+void sweep_loc(hipStream_t s, dim3 grid, const Lev& L, const double* f, const double* uin, double* uout, int tx,
+               const Coarse* corr)
+{
+    const Coarse C = corr ? *corr : Coarse{nullptr, nullptr, 0, 0};
+    if (corr)
+        hipLaunchKernelGGL((k_sweep<NU, LOC, true>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C);
+    else
+        hipLaunchKernelGGL((k_sweep<NU, LOC, false>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C);
+}
+
+void launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
+                  const Coarse* corr)
 {
     const int ox = 2 * kTile - 4 * nu, oy = kWinRows - 4 * nu;
     const int tx = (L.nx + ox - 1) / ox, ty = (L.ny + oy - 1) / oy;
-    if (nu == 1)
-        hipLaunchKernelGGL(k_sweep<1>, dim3(tx * ty), dim3(512), 0, s, L, f, uin, uout, tx);
+    const dim3 grid(tx * ty);
+    // without a correction the location does not matter: one instantiation serves all
+    if (!corr || loc == LOC_CELL) {
+        if (nu == 1)
+            sweep_loc<1, LOC_CELL>(s, grid, L, f, uin, uout, tx, corr);
+        else
+            sweep_loc<2, LOC_CELL>(s, grid, L, f, uin, uout, tx, corr);
+    } else if (loc == LOC_EDGE_X) {
+        if (nu == 1)
+            sweep_loc<1, LOC_EDGE_X>(s, grid, L, f, uin, uout, tx, corr);
+        else
+            sweep_loc<2, LOC_EDGE_X>(s, grid, L, f, uin, uout, tx, corr);
+    } else {
+        if (nu == 1)
+            sweep_loc<1, LOC_EDGE_Y>(s, grid, L, f, uin, uout, tx, corr);
+        else
+            sweep_loc<2, LOC_EDGE_Y>(s, grid, L, f, uin, uout, tx, corr);
+    }
+}
+
+void launch_tail(hipStream_t s, int loc, const TailArgs& A)
+{
+    if (loc == LOC_CELL)
+        hipLaunchKernelGGL(k_tail<LOC_CELL>, dim3(1), dim3(1024), 0, s, A);
+    else if (loc == LOC_EDGE_X)
+        hipLaunchKernelGGL(k_tail<LOC_EDGE_X>, dim3(1), dim3(1024), 0, s, A);
     else
-        hipLaunchKernelGGL(k_sweep<2>, dim3(tx * ty), dim3(512), 0, s, L, f, uin, uout, tx);
+        hipLaunchKernelGGL(k_tail<LOC_EDGE_Y>, dim3(1), dim3(1024), 0, s, A);
 }
 
 void launch_restrict(hipStream_t s, int loc, const Lev& Lf, const double* f, const double* u, int ncx, int ncy,

@@ -17,6 +17,10 @@ using namespace fas::stag;
 
 struct fas_stag {
     int loc, cell_bc, coarsest, nuc;
+    int fused;      // 1: persistent tail for the coarse levels and the correction fused into
+                    // the first post-smoothing launch; 0: one kernel per step and level
+    int tail_top;   // first level of the persistent tail
+    int tail_ou[fas::stag::kTailMaxLevels], tail_of[fas::stag::kTailMaxLevels], tail_ou0[fas::stag::kTailMaxLevels];
     int kx, ky;
     int64_t mx, my;  // cells of the finest level
     double h;
@@ -132,9 +136,10 @@ Lev level_op(const fas_stag& S, int l, double a, double c)
 
 // nu sweeps from buffer cur (alt: the other buffer of the level).  The launches do two sweeps
 // each, one when nu is odd; with `want` set, one two-sweep launch becomes two one-sweep
-// launches (or a copy follows) so that the result lands in `want`.  Returns the buffer that
-// holds the result.
-double* sweeps(hipStream_t st, const Lev& L, const double* f, double* cur, double* alt, int nu, double* want)
+// launches (or a copy follows) so that the result lands in `want`.  corr: FAS correction
+// applied as the first launch loads its window.  Returns the buffer that holds the result.
+double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* cur, double* alt, int nu, double* want,
+               const Coarse* corr = nullptr)
 {
     if (nu <= 0) {
         if (want && want != cur) {
@@ -160,7 +165,7 @@ double* sweeps(hipStream_t st, const Lev& L, const double* f, double* cur, doubl
     double* a = cur;
     double* b = alt;
     for (int i = 0; i < twos + ones; ++i) {
-        launch_sweep(st, L, i < twos ? 2 : 1, f, a, b);
+        launch_sweep(st, loc, L, i < twos ? 2 : 1, f, a, b, i == 0 ? corr : nullptr);
         std::swap(a, b);
     }
     if (copy_after) {
@@ -178,19 +183,41 @@ void vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, 
 {
     const Lev L = level_op(S, l, a, c);
     double* ut = S.lev[l].ut;
-    if (l == S.L - 1) {
-        sweeps(S.stream, L, f, u, ut, S.nuc, u);  // Remark 1: the coarsest level is smoothed
+    if (S.fused && l == S.tail_top) {
+        TailArgs A{};
+        A.nlev = S.L - l;
+        for (int k = 0; k < A.nlev; ++k) {
+            A.op[k] = level_op(S, l + k, a, c);
+            A.ou[k] = S.tail_ou[k];
+            A.of[k] = S.tail_of[k];
+            A.ou0[k] = S.tail_ou0[k];
+        }
+        A.u = u;
+        A.f = f;
+        A.nu1 = nu1;
+        A.nu2 = nu2;
+        A.nuc = S.nuc;
+        launch_tail(S.stream, S.loc, A);
         return;
     }
-    double* cur = sweeps(S.stream, L, f, u, ut, nu1, nullptr);
+    if (l == S.L - 1) {
+        sweeps(S.stream, S.loc, L, f, u, ut, S.nuc, u);  // Remark 1: the coarsest level is smoothed
+        return;
+    }
+    double* cur = sweeps(S.stream, S.loc, L, f, u, ut, nu1, nullptr);
     auto& C = S.lev[l + 1];
     launch_restrict(S.stream, S.loc, L, f, cur, C.nx, C.ny, C.u, C.u0, C.f);
     launch_coarse_rhs(S.stream, level_op(S, l + 1, a, c), C.f, C.u);
     vcycle(S, l + 1, a, c, C.f, C.u, nu1, nu2);
+    if (S.fused && nu2 > 0) {
+        const Coarse corr{C.u, C.u0, C.nx, C.ny};
+        sweeps(S.stream, S.loc, L, f, cur, cur == u ? ut : u, nu2, u, &corr);
+        return;
+    }
     // the correction goes to the buffer from which nu2 sweeps end in u
     double* dst = launches(nu2) % 2 == 0 ? u : ut;
     launch_correct(S.stream, S.loc, L, C.u, C.u0, C.nx, C.ny, cur, dst);
-    sweeps(S.stream, L, f, dst, dst == u ? ut : u, nu2, u);
+    sweeps(S.stream, S.loc, L, f, dst, dst == u ? ut : u, nu2, u);
 }
 
 double residual_norm(fas_stag& S, double a, double c, const double* f, const double* u, double* r)
@@ -266,12 +293,35 @@ void init_stag(fas_stag& S, int loc, int64_t mx, int64_t my, double h, int cell_
     }
     S.partials = reinterpret_cast<double*>(ws + off);
     S.norm = S.partials + kNormBlocks;
+    // persistent tail: the first level from which every level down to the coarsest fits
+    S.fused = 1;
+    S.tail_top = -1;
+    for (int top = 0; top < S.L; ++top) {
+        if ((int64_t)S.lev[top].nx * S.lev[top].ny > kTailTopMax || S.L - top > kTailMaxLevels) continue;
+        int need = 0;
+        for (int l = top; l < S.L; ++l) need += (l == top ? 2 : 3) * S.lev[l].nx * S.lev[l].ny;
+        if (need > kTailDoubles) continue;
+        int o = 0;
+        for (int l = top; l < S.L; ++l) {
+            const int n = S.lev[l].nx * S.lev[l].ny, k = l - top;
+            S.tail_ou[k] = o;
+            S.tail_of[k] = o + n;
+            S.tail_ou0[k] = l == top ? -1 : o + 2 * n;
+            o += (l == top ? 2 : 3) * n;
+        }
+        S.tail_top = top;
+        break;
+    }
 }
 
 int set_option(fas_stag& S, int option, double value)
 {
+    if (option == FAS_OPT_FUSED && (value == 0.0 || value == 1.0)) {
+        S.fused = (int)value;
+        return FAS_OK;
+    }
     if (option != FAS_OPT_COARSE_SWEEPS || !(value >= 1.0) || value > 1e6)
-        throw Error(FAS_ERR_ARG, "only FAS_OPT_COARSE_SWEEPS (>= 1) applies to a staggered solver");
+        throw Error(FAS_ERR_ARG, "a staggered solver takes FAS_OPT_COARSE_SWEEPS (>= 1) and FAS_OPT_FUSED (0 or 1)");
     S.nuc = (int)value;
     return FAS_OK;
 }
@@ -356,7 +406,7 @@ int fas_stag_smooth(fas_stag_t* s, double a, double c, const void* f, void* w, i
         check_pointers(f, w);
         if (nu < 0) throw Error(FAS_ERR_ARG, "negative sweep count");
         double* u = static_cast<double*>(w);
-        sweeps(s->stream, level_op(*s, 0, a, c), static_cast<const double*>(f), u, s->lev[0].ut, nu, u);
+        sweeps(s->stream, s->loc, level_op(*s, 0, a, c), static_cast<const double*>(f), u, s->lev[0].ut, nu, u);
         FAS_HIP_CHECK(hipGetLastError());
         return FAS_OK;
     });

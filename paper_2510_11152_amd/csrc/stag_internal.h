@@ -27,8 +27,38 @@ constexpr int kTile = 64;
 constexpr int kWinRows = 64;
 constexpr int kNormBlocks = 1024;
 
-// nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers).
-void launch_sweep(hipStream_t s, const Lev& L, int nu, const double* f, const double* uin, double* uout);
+// The coarse iterate after the coarse solve and its restricted copy from before it: the FAS
+// correction is e = uc - uc0 (coarse unknowns ncx x ncy).
+struct Coarse {
+    const double* uc;
+    const double* uc0;
+    int ncx, ncy;
+    __host__ __device__ __forceinline__ double e(int K, int J) const
+    {
+        const size_t i = (size_t)J * ncx + K;
+        return uc[i] - uc0[i];
+    }
+};
+
+// nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers).  With corr,
+// the window is loaded as uin + P e (the correction of level L from corr), as k_correct would
+// have written it.
+void launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
+                  const Coarse* corr);
+
+// Persistent tail: levels top .. coarsest in one workgroup's LDS.
+constexpr int kTailMaxLevels = 12;
+constexpr int kTailDoubles = 16384;  // 128 KiB of LDS
+constexpr int kTailTopMax = 4096;    // unknowns of the tail's top level (4 per thread)
+struct TailArgs {
+    int nlev;                                   // levels in the tail (top first)
+    Lev op[kTailMaxLevels];
+    int ou[kTailMaxLevels], of[kTailMaxLevels], ou0[kTailMaxLevels];  // LDS offsets (doubles)
+    double* u;                                  // top level iterate (in and out)
+    const double* f;                            // top level right-hand side
+    int nu1, nu2, nuc;
+};
+void launch_tail(hipStream_t s, int loc, const TailArgs& A);
 // Coarse iterate, its copy and the restricted residual of fine level Lf (location loc):
 // uc = uc0 = R u, rc = R (f - L u); coarse sizes ncx x ncy.
 void launch_restrict(hipStream_t s, int loc, const Lev& Lf, const double* f, const double* u, int ncx, int ncy,

@@ -66,8 +66,13 @@ class StaggeredSolver:
                 pass
             self.handle = None
 
-    def set(self, coarse_sweeps):
-        check(load().fas_stag_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_stag_set")
+    def set(self, coarse_sweeps=None, fused=None):
+        """coarse_sweeps: sweeps on the coarsest level; fused: 1 (default) persistent tail
+        and fused correction, 0 one kernel per step and level (identical results)."""
+        if coarse_sweeps is not None:
+            check(load().fas_stag_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_stag_set")
+        if fused is not None:
+            check(load().fas_stag_set(self.handle, _lib.FAS_OPT_FUSED, float(int(fused))), "fas_stag_set")
 
     def _args(self, f, w):
         _check_array(f, self.shape, self.device, "f")
@@ -144,8 +149,11 @@ class NavierStokes2D:
                 pass
             self.handle = None
 
-    def set(self, coarse_sweeps):
-        check(load().fas_ns_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_ns_set")
+    def set(self, coarse_sweeps=None, fused=None):
+        if coarse_sweeps is not None:
+            check(load().fas_ns_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_ns_set")
+        if fused is not None:
+            check(load().fas_ns_set(self.handle, _lib.FAS_OPT_FUSED, float(int(fused))), "fas_ns_set")
 
     def step(self, dt, lid=0.0, force_u=(), force_v=(), coef=(), tol=1e-9, nu1=2, nu2=2, kmax=20):
         """One step; force_u / force_v: up to 4 source fields each (device tensors of the u

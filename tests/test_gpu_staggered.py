@@ -38,9 +38,10 @@ def host(t):
     return t.cpu().numpy()
 
 
-def _pair(loc, bc, code, nx, ny, coarsest=4):
+def _pair(loc, bc, code, nx, ny, coarsest=4, fused=1):
     from paper_2510_11152_amd import StaggeredSolver
     S = StaggeredSolver(loc, nx, ny, 1.0 / nx, bc=bc, coarsest=coarsest)
+    S.set(fused=fused)
     P = ost.StagProblem(code, nx, ny, 1.0 / nx, cell_bc=bc, coarsest=coarsest)
     assert S.levels == P.levels and S.shape == P.shape()
     return S, P
@@ -58,7 +59,7 @@ def _inputs(P, seed, compatible):
     return f, rng.standard_normal(P.shape())
 
 
-SIZES = [(64, 64), (192, 192), (128, 32), (96, 48)]
+SIZES = [(64, 64), (192, 192), (128, 32), (96, 48), (512, 256)]
 
 
 @pytest.mark.parametrize("loc,bc,code", LOCS)
@@ -92,10 +93,11 @@ def test_residual_bitwise(loc, bc, code, nx, ny):
 
 @pytest.mark.parametrize("loc,bc,code", LOCS)
 @pytest.mark.parametrize("nx,ny", SIZES)
-@pytest.mark.parametrize("nu1,nu2", [(2, 2), (1, 1), (3, 2), (0, 1)])
-def test_vcycle_bitwise(loc, bc, code, nx, ny, nu1, nu2):
-    say("vcycle", loc, bc, nx, ny, nu1, nu2)
-    S, P = _pair(loc, bc, code, nx, ny)
+@pytest.mark.parametrize("nu1,nu2", [(2, 2), (1, 1), (3, 2), (0, 1), (2, 0)])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_vcycle_bitwise(loc, bc, code, nx, ny, nu1, nu2, fused):
+    say("vcycle", loc, bc, nx, ny, nu1, nu2, fused)
+    S, P = _pair(loc, bc, code, nx, ny, fused=fused)
     a, c = _coef(bc)
     f, w = _inputs(P, 11, a == 0.0)
     wd = dev(w)
@@ -109,11 +111,12 @@ def test_vcycle_bitwise(loc, bc, code, nx, ny, nu1, nu2):
 
 
 @pytest.mark.parametrize("coarse_sweeps", [1, 3, 16])
-def test_vcycle_coarse_sweeps_bitwise(coarse_sweeps):
-    say("vcycle coarse sweeps", coarse_sweeps)
+@pytest.mark.parametrize("fused", [1, 0])
+def test_vcycle_coarse_sweeps_bitwise(coarse_sweeps, fused):
+    say("vcycle coarse sweeps", coarse_sweeps, fused)
     from paper_2510_11152_amd import StaggeredSolver
     S = StaggeredSolver("edge_y", 64, 64, 1 / 64)
-    S.set(coarse_sweeps)
+    S.set(coarse_sweeps, fused)
     P = ost.StagProblem(ost.EDGE_Y, 64, 64, 1 / 64, nuc=coarse_sweeps)
     f, w = _inputs(P, 2, False)
     wd = dev(w)
@@ -142,9 +145,10 @@ def check_solve(S, P, a, c, f, w0, tol, kmax=30):
 
 @pytest.mark.parametrize("loc,bc,code", LOCS)
 @pytest.mark.parametrize("nx,ny", [(128, 128), (192, 96)])
-def test_solve_matches_oracle(loc, bc, code, nx, ny):
-    say("solve", loc, bc, nx, ny)
-    S, P = _pair(loc, bc, code, nx, ny)
+@pytest.mark.parametrize("fused", [1, 0])
+def test_solve_matches_oracle(loc, bc, code, nx, ny, fused):
+    say("solve", loc, bc, nx, ny, fused)
+    S, P = _pair(loc, bc, code, nx, ny, fused=fused)
     a, c = _coef(bc)
     f, w = _inputs(P, 17, a == 0.0)
     cyc = check_solve(S, P, a, c, f, w, 1e-10, kmax=40)
