@@ -171,18 +171,27 @@ __global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double*
 //
 // CORR: the FAS correction is applied as the window is loaded (u = uin + P e, the same point
 // formula as k_correct), so the corrected iterate before the post-smoothing is never stored.
-template <int NU, int LOC, bool CORR>
+//
+// NORM: the written region keeps one more ring of margin (2 nu + 1), so that the residual
+// f - L u of every written value can be formed from the window; each block writes the sum of
+// its residuals' squares to partials (one value per block, summed afterwards in a fixed
+// order).  This replaces a separate residual pass after the cycle.
+template <int NU, int LOC, bool CORR, bool NORM>
 __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__ f, const double* __restrict__ uin,
-                                               double* __restrict__ uout, int tiles_x, Coarse C)
+                                               double* __restrict__ uout, int tiles_x, Coarse C,
+                                               double* __restrict__ partials)
 {
-    constexpr int WY = kWinRows, H = 2 * NU, OX = 2 * kTile - 2 * H, OY = WY - 2 * H, RPW = WY / 8;
+    // margins of the written region: 2 nu (the sweeps' reach), one more for NORM (two along x,
+    // which keeps the window origin even)
+    constexpr int WY = kWinRows, HX = 2 * NU + (NORM ? 2 : 0), HY = 2 * NU + (NORM ? 1 : 0);
+    constexpr int OX = 2 * kTile - 2 * HX, OY = WY - 2 * HY, RPW = WY / 8;
     __shared__ double se[WY][kTile];  // even columns of the window
     __shared__ double so[WY][kTile];  // odd columns
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     const int tx = (int)(b % (unsigned)tiles_x), ty = (int)(b / (unsigned)tiles_x);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int x0 = tx * OX - H + 2 * lane;  // grid column of the lane's even column
-    const int yw = ty * OY - H + w * RPW;   // grid row of the wave's first row
+    const int x0 = tx * OX - HX + 2 * lane;  // grid column of the lane's even column
+    const int yw = ty * OY - HY + w * RPW;   // grid row of the wave's first row
     const bool in0 = x0 >= 0 && x0 < L.nx, in1 = x0 + 1 >= 0 && x0 + 1 < L.nx;
     double u0[RPW], u1[RPW], f0[RPW], f1[RPW];
 #pragma unroll
@@ -240,13 +249,43 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
         }
         __syncthreads();
     }
-    if (2 * lane >= H && 2 * lane < H + OX) {
+    double acc = 0.0;
+    if (2 * lane >= HX && 2 * lane < HX + OX) {
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int r = w * RPW + i, gy = yw + i;
-            if (r < H || r >= H + OY || gy < 0 || gy >= L.ny) continue;
+            if (r < HY || r >= HY + OY || gy < 0 || gy >= L.ny) continue;
             if (in0) uout[(size_t)gy * L.nx + x0] = se[r][lane];
             if (in1) uout[(size_t)gy * L.nx + x0 + 1] = so[r][lane];
+            if (NORM) {
+                double ky = 0.0;
+                if (gy == 0) ky += kshift(L.ky);
+                if (gy == L.ny - 1) ky += kshift(L.ky);
+                if (in0) {
+                    const double D = L.a * L.h2 + L.c * (kx0 + ky);
+                    const double s = (so[r][lane - 1] + so[r][lane]) + (se[r - 1][lane] + se[r + 1][lane]);
+                    const double rv = f0[i] - (D * se[r][lane] - L.c * s) * L.ih2;
+                    acc = acc + rv * rv;
+                }
+                if (in1) {
+                    const double D = L.a * L.h2 + L.c * (kx1 + ky);
+                    const double s = (se[r][lane] + se[r][lane + 1]) + (so[r - 1][lane] + so[r + 1][lane]);
+                    const double rv = f1[i] - (D * so[r][lane] - L.c * s) * L.ih2;
+                    acc = acc + rv * rv;
+                }
+            }
+        }
+    }
+    if (NORM) {
+        // fixed-order reduction: butterfly within each wave, then the 8 wave sums in order
+        for (int o = 32; o > 0; o >>= 1) acc = acc + __shfl_xor(acc, o, 64);
+        __shared__ double red[8];
+        if (lane == 0) red[w] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = red[0];
+            for (int k = 1; k < 8; ++k) t = t + red[k];
+            partials[blockIdx.x] = t;
         }
     }
 }
@@ -516,40 +555,61 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-template <int NU, int LOC>
+template <int NU, int LOC, bool NORM>
 void sweep_loc(hipStream_t s, dim3 grid, const Lev& L, const double* f, const double* uin, double* uout, int tx,
-               const Coarse* corr)
+               const Coarse* corr, double* partials)
 {
     const Coarse C = corr ? *corr : Coarse{nullptr, nullptr, 0, 0};
     if (corr)
-        hipLaunchKernelGGL((k_sweep<NU, LOC, true>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C);
+        hipLaunchKernelGGL((k_sweep<NU, LOC, true, NORM>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C, partials);
     else
-        hipLaunchKernelGGL((k_sweep<NU, LOC, false>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C);
+        hipLaunchKernelGGL((k_sweep<NU, LOC, false, NORM>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C, partials);
 }
 
-void launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
-                  const Coarse* corr)
+template <int LOC>
+void sweep_nu(hipStream_t s, dim3 grid, const Lev& L, int nu, const double* f, const double* uin, double* uout, int tx,
+              const Coarse* corr, double* partials)
 {
-    const int ox = 2 * kTile - 4 * nu, oy = kWinRows - 4 * nu;
-    const int tx = (L.nx + ox - 1) / ox, ty = (L.ny + oy - 1) / oy;
-    const dim3 grid(tx * ty);
-    // without a correction the location does not matter: one instantiation serves all
-    if (!corr || loc == LOC_CELL) {
+    if (partials) {
         if (nu == 1)
-            sweep_loc<1, LOC_CELL>(s, grid, L, f, uin, uout, tx, corr);
+            sweep_loc<1, LOC, true>(s, grid, L, f, uin, uout, tx, corr, partials);
         else
-            sweep_loc<2, LOC_CELL>(s, grid, L, f, uin, uout, tx, corr);
-    } else if (loc == LOC_EDGE_X) {
-        if (nu == 1)
-            sweep_loc<1, LOC_EDGE_X>(s, grid, L, f, uin, uout, tx, corr);
-        else
-            sweep_loc<2, LOC_EDGE_X>(s, grid, L, f, uin, uout, tx, corr);
+            sweep_loc<2, LOC, true>(s, grid, L, f, uin, uout, tx, corr, partials);
     } else {
         if (nu == 1)
-            sweep_loc<1, LOC_EDGE_Y>(s, grid, L, f, uin, uout, tx, corr);
+            sweep_loc<1, LOC, false>(s, grid, L, f, uin, uout, tx, corr, partials);
         else
-            sweep_loc<2, LOC_EDGE_Y>(s, grid, L, f, uin, uout, tx, corr);
+            sweep_loc<2, LOC, false>(s, grid, L, f, uin, uout, tx, corr, partials);
     }
+}
+
+int sweep_blocks(const Lev& L, int nu, bool norm, int* tiles_x)
+{
+    const int ox = 2 * kTile - 2 * (2 * nu + (norm ? 2 : 0)), oy = kWinRows - 2 * (2 * nu + (norm ? 1 : 0));
+    const int tx = (L.nx + ox - 1) / ox, ty = (L.ny + oy - 1) / oy;
+    if (tiles_x) *tiles_x = tx;
+    return tx * ty;
+}
+
+int launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
+                 const Coarse* corr, double* partials)
+{
+    int tx;
+    const int nb = sweep_blocks(L, nu, partials != nullptr, &tx);
+    const dim3 grid(nb);
+    // without a correction the location does not matter: one instantiation serves all
+    if (!corr || loc == LOC_CELL)
+        sweep_nu<LOC_CELL>(s, grid, L, nu, f, uin, uout, tx, corr, partials);
+    else if (loc == LOC_EDGE_X)
+        sweep_nu<LOC_EDGE_X>(s, grid, L, nu, f, uin, uout, tx, corr, partials);
+    else
+        sweep_nu<LOC_EDGE_Y>(s, grid, L, nu, f, uin, uout, tx, corr, partials);
+    return nb;
+}
+
+void launch_sum(hipStream_t s, const double* partials, int n, double* out)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partials, n, out);
 }
 
 void launch_tail(hipStream_t s, int loc, const TailArgs& A)

@@ -104,6 +104,17 @@ void check_shape(int loc, int64_t mx, int64_t my, int coarsest)
     if (L < 2) throw Error(FAS_ERR_SHAPE, "at least two levels are needed");
 }
 
+// Partial sums a norm needs: the residual pass, or the finest sweep launch with the norm.
+int partials_count(int loc, int64_t mx, int64_t my)
+{
+    int64_t nx, ny;
+    unknowns(loc, mx, my, nx, ny);
+    Lev L{};
+    L.nx = (int)nx;
+    L.ny = (int)ny;
+    return std::max(kNormBlocks, std::max(sweep_blocks(L, 1, true, nullptr), sweep_blocks(L, 2, true, nullptr)));
+}
+
 // Bytes of the workspace of one staggered variable (0 on a bad shape).
 size_t stag_bytes(int loc, int64_t mx, int64_t my, int coarsest)
 {
@@ -115,7 +126,7 @@ size_t stag_bytes(int loc, int64_t mx, int64_t my, int coarsest)
         const size_t arr = align_up((size_t)(nx * ny) * sizeof(double));
         b += l == 0 ? arr : 4 * arr;
     }
-    b += align_up((kNormBlocks + 8) * sizeof(double));
+    b += align_up((partials_count(loc, mx, my) + 8) * sizeof(double));
     return b;
 }
 
@@ -139,7 +150,7 @@ Lev level_op(const fas_stag& S, int l, double a, double c)
 // launches (or a copy follows) so that the result lands in `want`.  corr: FAS correction
 // applied as the first launch loads its window.  Returns the buffer that holds the result.
 double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* cur, double* alt, int nu, double* want,
-               const Coarse* corr = nullptr)
+               const Coarse* corr = nullptr, double* partials = nullptr, int* norm_blocks = nullptr)
 {
     if (nu <= 0) {
         if (want && want != cur) {
@@ -164,8 +175,12 @@ double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* c
     }
     double* a = cur;
     double* b = alt;
-    for (int i = 0; i < twos + ones; ++i) {
-        launch_sweep(st, loc, L, i < twos ? 2 : 1, f, a, b, i == 0 ? corr : nullptr);
+    const int n = twos + ones;
+    for (int i = 0; i < n; ++i) {
+        const bool last = i == n - 1 && !copy_after;
+        const int nb = launch_sweep(st, loc, L, i < twos ? 2 : 1, f, a, b, i == 0 ? corr : nullptr,
+                                    last ? partials : nullptr);
+        if (last && partials && norm_blocks) *norm_blocks = nb;
         std::swap(a, b);
     }
     if (copy_after) {
@@ -178,8 +193,9 @@ double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* c
 int launches(int nu) { return nu / 2 + nu % 2; }
 
 // One V(nu1, nu2) cycle from level l on right-hand side f with the iterate in u (the result
-// returns to u).
-void vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, int nu1, int nu2)
+// returns to u).  Returns the number of residual partial sums the last sweep left in
+// S.partials (0: none, the norm needs its own pass).
+int vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, int nu1, int nu2)
 {
     const Lev L = level_op(S, l, a, c);
     double* ut = S.lev[l].ut;
@@ -198,11 +214,11 @@ void vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, 
         A.nu2 = nu2;
         A.nuc = S.nuc;
         launch_tail(S.stream, S.loc, A);
-        return;
+        return 0;
     }
     if (l == S.L - 1) {
         sweeps(S.stream, S.loc, L, f, u, ut, S.nuc, u);  // Remark 1: the coarsest level is smoothed
-        return;
+        return 0;
     }
     double* cur = sweeps(S.stream, S.loc, L, f, u, ut, nu1, nullptr);
     auto& C = S.lev[l + 1];
@@ -210,14 +226,26 @@ void vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, 
     launch_coarse_rhs(S.stream, level_op(S, l + 1, a, c), C.f, C.u);
     vcycle(S, l + 1, a, c, C.f, C.u, nu1, nu2);
     if (S.fused && nu2 > 0) {
+        // correction in the first post-smoothing launch, the residual norm (finest level) in
+        // the last
         const Coarse corr{C.u, C.u0, C.nx, C.ny};
-        sweeps(S.stream, S.loc, L, f, cur, cur == u ? ut : u, nu2, u, &corr);
-        return;
+        int nb = 0;
+        sweeps(S.stream, S.loc, L, f, cur, cur == u ? ut : u, nu2, u, &corr, l == 0 ? S.partials : nullptr, &nb);
+        return nb;
     }
     // the correction goes to the buffer from which nu2 sweeps end in u
     double* dst = launches(nu2) % 2 == 0 ? u : ut;
     launch_correct(S.stream, S.loc, L, C.u, C.u0, C.nx, C.ny, cur, dst);
     sweeps(S.stream, S.loc, L, f, dst, dst == u ? ut : u, nu2, u);
+    return 0;
+}
+
+double read_norm(fas_stag& S)
+{
+    double s2 = 0.0;
+    FAS_HIP_CHECK(hipMemcpyAsync(&s2, S.norm, sizeof(double), hipMemcpyDeviceToHost, S.stream));
+    FAS_HIP_CHECK(hipStreamSynchronize(S.stream));
+    return S.h * sqrt(s2);
 }
 
 double residual_norm(fas_stag& S, double a, double c, const double* f, const double* u, double* r)
@@ -243,9 +271,14 @@ int solve(fas_stag& S, double a, double c, const double* f, double* u, double to
     double res = residual_norm(S, a, c, f, u, nullptr);
     int k = 0;
     while (isfinite(res) && res > tol && k < kmax) {
-        vcycle(S, 0, a, c, f, u, nu1, nu2);
+        const int nb = vcycle(S, 0, a, c, f, u, nu1, nu2);
         ++k;
-        res = residual_norm(S, a, c, f, u, nullptr);
+        if (nb > 0) {
+            launch_sum(S.stream, S.partials, nb, S.norm);
+            res = read_norm(S);
+        } else {
+            res = residual_norm(S, a, c, f, u, nullptr);
+        }
     }
     if (cycles_out) *cycles_out = k;
     if (res_out) *res_out = res;
@@ -292,7 +325,7 @@ void init_stag(fas_stag& S, int loc, int64_t mx, int64_t my, double h, int cell_
         off += 3 * arr;
     }
     S.partials = reinterpret_cast<double*>(ws + off);
-    S.norm = S.partials + kNormBlocks;
+    S.norm = S.partials + partials_count(loc, mx, my);
     // persistent tail: the first level from which every level down to the coarsest fits
     S.fused = 1;
     S.tail_top = -1;

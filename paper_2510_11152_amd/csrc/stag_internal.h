@@ -42,9 +42,14 @@ struct Coarse {
 
 // nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers).  With corr,
 // the window is loaded as uin + P e (the correction of level L from corr), as k_correct would
-// have written it.
-void launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
-                  const Coarse* corr);
+// have written it.  With partials, each block also writes the sum of the squared residuals
+// f - L u of the values it wrote (one double per block).  Returns the number of blocks.
+int launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
+                 const Coarse* corr, double* partials);
+// Blocks of such a launch (tiles_x may be NULL).
+int sweep_blocks(const Lev& L, int nu, bool norm, int* tiles_x);
+// out[0] = sum of partials[0 .. n) in a fixed order.
+void launch_sum(hipStream_t s, const double* partials, int n, double* out);
 
 // Persistent tail: levels top .. coarsest in one workgroup's LDS.
 constexpr int kTailMaxLevels = 12;

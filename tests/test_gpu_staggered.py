@@ -289,3 +289,20 @@ def test_full_size_vcycle_bitwise(loc, bc, code):
     S.vcycle(a, c, dev(f), wd)
     ost.vcycle(P, a, c, f, w)
     assert np.array_equal(host(wd), w)
+
+
+@pytest.mark.parametrize("loc,bc,code", LOCS)
+@pytest.mark.parametrize("nu2", [1, 2, 3])
+def test_fused_norm_equals_residual_pass(loc, bc, code, nu2):
+    """The residual norm the last post-smoothing launch sums equals the separate residual
+    pass on the same iterate (to the rounding of two summation orders)."""
+    say("fused norm", loc, bc, nu2)
+    S, P = _pair(loc, bc, code, 512, 256)
+    a, c = _coef(bc)
+    f, w = _inputs(P, 31, a == 0.0)
+    fd, wd = dev(f), dev(w)
+    st, cyc, res = S.solve(a, c, fd, wd, 0.0, nu2=nu2, kmax=2)    # two cycles, never converged
+    assert cyc == 2 and st == 1
+    again = S.residual(a, c, fd, wd)
+    assert abs(res - again) <= 1e-12 * again
+    assert abs(res - ost.res_norm(P, a, c, f, host(wd))) <= 1e-12 * again
