@@ -30,28 +30,34 @@ PASS_SOURCES = ["paper_2510_11152_amd/csrc/kernels_tile2d.hip", "paper_2510_1115
                 "paper_2510_11152_amd/csrc/march_util.h"]
 
 
-def pass_sources_sha256():
+# the same for the staggered solver's red-black sweep kernel (4096^2 projection step)
+NS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns4096_sweep_traffic.md")
+NS_SOURCES = ["paper_2510_11152_amd/csrc/kernels_stag.hip", "paper_2510_11152_amd/csrc/stag_internal.h",
+              "paper_2510_11152_amd/csrc/fas_device.h"]
+
+
+def pass_sources_sha256(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for rel in PASS_SOURCES:
+    for rel in sources or PASS_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, n):
+def measured_traffic(kernel, n, record=TRAFFIC_FILE, sources=None):
     """HBM bytes per launch of a finest-level kernel class from the committed counter
     summary ('traffic-record:' line), or None when there is none for this grid or the
     kernel sources have changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(record) as fh:
             lines = [ln for ln in fh if ln.startswith("traffic-record:")]
     except OSError:
         return None
     if not lines:
         return None
     rec = json.loads(lines[-1].split(":", 1)[1])
-    if rec.get("sources_sha256") != pass_sources_sha256() or rec.get("grid") != [n, n]:
+    if rec.get("sources_sha256") != pass_sources_sha256(sources) or rec.get("grid") != [n, n]:
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
@@ -403,7 +409,7 @@ def bench_3d(dev, steps=5, inner=4, cpu=True):
     return out
 
 
-def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=True):
+def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=True, ceiling=None):
     """Section 4.4.3: Scheme 1 (first-order projection) on the staggered 4096^2 grid, Re = 10,
     tol 1e-9, V(2,2), manufactured source at t^{n+1}, t = 0 .. 1 for each dt; L2 errors at
     t = 1 against the exact solution and their orders.  Then both field layouts at one dt
@@ -499,6 +505,14 @@ def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=
     out["sweep_kernel"] = {"kernel": "k_sweep<2> (two red-black sweeps)", "grid": list(S.shape), "avg_us": us,
                            "algorithmic_bytes": alg, "gbs": alg / (us * 1e-6) / 1e9,
                            "frac": alg / (us * 1e-6) / 8e12}
+    gbs = alg / (us * 1e-6) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "k_sweep<2, *, false, false> (pre-smoothing, finest level)",
+                       "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                       "traffic": measured_traffic("sweep", n, NS_TRAFFIC_FILE, NS_SOURCES),
+                       "algorithmic_bytes": alg}
+    if ceiling:
+        out["roofline"]["attainable"] = ceiling
+        out["roofline"]["frac_of_attainable"] = gbs / ceiling
     del S, f, w
     if cpu:
         out["cpu_baseline"] = ns_cpu_baseline(n, re, out["cycles_per_step_uvp"])
@@ -778,7 +792,7 @@ def main():
     if "ns" in forms:
         print("bench: staggered projection step (4096^2)", file=sys.stderr, flush=True)
         result["ns"] = bench_ns(dev, dts=tuple(float(x) for x in args.ns_dts.split(",")),
-                                cpu=not args.no_cpu_baseline)
+                                cpu=not args.no_cpu_baseline, ceiling=attain)
 
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on two cycles", file=sys.stderr, flush=True)
