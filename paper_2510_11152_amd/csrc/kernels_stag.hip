@@ -155,10 +155,11 @@ __global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double*
 }
 
 // ---- red-black sweeps on an LDS window ------------------------------------------------------
-// A 512-thread block (8 waves) loads a 128 x 64 window of the iterate into LDS: lane l of a
-// wave owns the column pair (2l, 2l + 1) of the window and each wave 8 rows, whose
+// A 512-thread block (8 waves) loads a 128 x 32 window of the iterate into LDS: lane l of a
+// wave owns the column pair (2l, 2l + 1) of the window and each wave 4 rows, whose
 // right-hand side values stay in registers.  The block runs nu red-black sweeps on the window
-// and writes its interior, (128 - 4 nu) x (64 - 4 nu) values.  Half-sweep k updates values
+// and writes its interior, (128 - 4 nu) x (32 - 4 nu) values.  (32 rows rather than 64:
+// 54 instead of 87 VGPRs and 32 KiB of LDS, so four blocks share a compute unit.)  Half-sweep k updates values
 // at distance >= k from the window's edge correctly, so after 2 nu half-sweeps the interior
 // (distance >= 2 nu) holds exactly what nu sweeps over the whole grid give.  Values outside
 // the grid stay 0 in LDS (the 0.0 neighbours of the point formula).  Within a half-sweep the

@@ -24,7 +24,7 @@ struct Lev {
 // Red-black sweep windows: 2 * kTile columns (a column pair per lane) x kWinRows rows in
 // LDS, nu sweeps (1 or 2) per launch.
 constexpr int kTile = 64;
-constexpr int kWinRows = 64;
+constexpr int kWinRows = 32;
 constexpr int kNormBlocks = 1024;
 
 // The coarse iterate after the coarse solve and its restricted copy from before it: the FAS
