@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "fas_device.h"
+#include "fas_internal.h"
 #include "stag_internal.h"
 
 namespace fas {
@@ -138,6 +139,15 @@ __global__ __launch_bounds__(256) void k_restrict(Lev Lf, const double* __restri
     rc[t] = rr;
 }
 
+__global__ __launch_bounds__(256) void k_form_rhs(Lev L, const double* __restrict__ r, const double* __restrict__ u,
+                                                  double* __restrict__ f)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)L.nx * L.ny) return;
+    const int x = (int)(t % L.nx), y = (int)(t / L.nx);
+    f[t] = r[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
+}
+
 __global__ __launch_bounds__(256) void k_coarse_rhs(Lev L, double* __restrict__ f, const double* __restrict__ u)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -155,37 +165,41 @@ __global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double*
 }
 
 // ---- red-black sweeps on an LDS window ------------------------------------------------------
-// A 512-thread block (8 waves) loads a 128 x 32 window of the iterate into LDS: lane l of a
-// wave owns the column pair (2l, 2l + 1) of the window and each wave 4 rows, whose
+// A 512-thread block (8 waves) loads a 128-column window of the iterate into LDS: lane l of a
+// wave owns the column pair (2l, 2l + 1) of the window and each wave WY/8 rows, whose
 // right-hand side values stay in registers.  The block runs nu red-black sweeps on the window
-// and writes its interior, (128 - 4 nu) x (32 - 4 nu) values.  (32 rows rather than 64:
-// 54 instead of 87 VGPRs and 32 KiB of LDS, so four blocks share a compute unit.)  Half-sweep k updates values
-// at distance >= k from the window's edge correctly, so after 2 nu half-sweeps the interior
-// (distance >= 2 nu) holds exactly what nu sweeps over the whole grid give.  Values outside
-// the grid stay 0 in LDS (the 0.0 neighbours of the point formula).  Within a half-sweep the
-// updated points read only points of the other colour, so the update runs in place.
+// and writes its interior.  Half-sweep k updates values at distance >= k from the window's
+// edge correctly, so after 2 nu half-sweeps the values at distance >= 2 nu are exactly what
+// nu sweeps over the whole grid give.  Values outside the grid stay 0 in LDS (the 0.0
+// neighbours of the point formula).  Within a half-sweep the updated points read only
+// points of the other colour, so the update runs in place.  Window geometry (rows, margins of
+// the written region): sweep_geom().  Windows are 32 rows (54 VGPRs, 32 KiB of LDS: four
+// blocks per compute unit), 64 for the fused restriction, whose margin is wider.
 //
-// The window origin is even (2 nu and the interior width are even), so in a row of one
-// colour exactly one column of every pair is updated, the same one for the whole wave: every
-// lane updates one point per row.  Even and odd columns sit in separate LDS arrays, which
-// makes every LDS access of a wave 64 consecutive doubles.
+// The window origin is even (the margins and the interior width are even along x), so in a
+// row of one colour exactly one column of every pair is updated, the same one for the whole
+// wave: every lane updates one point per row.  Even and odd columns sit in separate LDS
+// arrays, which makes every LDS access of a wave 64 consecutive doubles.
 //
-// CORR: the FAS correction is applied as the window is loaded (u = uin + P e, the same point
-// formula as k_correct), so the corrected iterate before the post-smoothing is never stored.
-//
-// NORM: the written region keeps one more ring of margin (2 nu + 1), so that the residual
-// f - L u of every written value can be formed from the window; each block writes the sum of
-// its residuals' squares to partials (one value per block, summed afterwards in a fixed
-// order).  This replaces a separate residual pass after the cycle.
-template <int NU, int LOC, bool CORR, bool NORM>
+// Variants (each a fixed set of point formulas of the per-level kernels, so the results are
+// the same bit for bit):
+//   CORR  the FAS correction is applied as the window is loaded (u = uin + P e, as k_correct);
+//   NORM  one more ring of margin; each block writes the sum of the squared residuals of the
+//         values it wrote to io.partials (one value per block), replacing a residual pass;
+//   RHS   f holds the restricted residual r of the finer level: the FAS right-hand side
+//         f = r + L u is formed from the loaded window before the sweeps (as k_coarse_rhs)
+//         and written to io.fout;
+//   RES   after the sweeps, the residual is formed in registers and the block restricts its
+//         written region into the coarse level (as k_restrict): io.uc = io.uc0 = R u,
+//         io.rc = R r.  Along an edge axis the third tap of a coarse point lies one column
+//         (lane shuffle) or one row (exchanged through LDS across waves) past the region.
+template <int NU, int LOC, bool CORR, bool NORM, bool RHS, bool RES>
 __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__ f, const double* __restrict__ uin,
-                                               double* __restrict__ uout, int tiles_x, Coarse C,
-                                               double* __restrict__ partials)
+                                               double* __restrict__ uout, int tiles_x, SweepIO io)
 {
-    // margins of the written region: 2 nu (the sweeps' reach), one more for NORM (two along x,
-    // which keeps the window origin even)
-    constexpr int WY = kWinRows, HX = 2 * NU + (NORM ? 2 : 0), HY = 2 * NU + (NORM ? 1 : 0);
-    constexpr int OX = 2 * kTile - 2 * HX, OY = WY - 2 * HY, RPW = WY / 8;
+    constexpr SweepGeom G = sweep_geom(NU, NORM, RES);
+    constexpr int WY = G.wy, HX = G.hx, HY = G.hy, OX = G.ox, OY = G.oy, RPW = WY / 8;
+    static_assert(HX % 2 == 0 && OY % 2 == 0 && RPW % 2 == 0, "window geometry");
     __shared__ double se[WY][kTile];  // even columns of the window
     __shared__ double so[WY][kTile];  // odd columns
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
@@ -210,8 +224,8 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
         for (int i = 0; i < RPW; ++i) {
             const int gy = yw + i;
             if (gy < 0 || gy >= L.ny) continue;
-            if (in0) u0[i] = u0[i] + prolong_point<LOC>(C, x0, gy);
-            if (in1) u1[i] = u1[i] + prolong_point<LOC>(C, x0 + 1, gy);
+            if (in0) u0[i] = u0[i] + prolong_point<LOC>(io.C, x0, gy);
+            if (in1) u1[i] = u1[i] + prolong_point<LOC>(io.C, x0 + 1, gy);
         }
     }
 #pragma unroll
@@ -225,7 +239,37 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
     if (x0 == L.nx - 1) kx0 += kshift(L.kx);
     if (x0 + 1 == 0) kx1 += kshift(L.kx);
     if (x0 + 1 == L.nx - 1) kx1 += kshift(L.kx);
+    auto kyof = [&](int gy) {
+        double ky = 0.0;
+        if (gy == 0) ky += kshift(L.ky);
+        if (gy == L.ny - 1) ky += kshift(L.ky);
+        return ky;
+    };
+    // L u at the even / odd point of window row r from the values in LDS
+    auto Lu_even = [&](int r, double ky) {
+        const double D = L.a * L.h2 + L.c * (kx0 + ky);
+        const double s = (so[r][lane - 1] + so[r][lane]) + (se[r - 1][lane] + se[r + 1][lane]);
+        return (D * se[r][lane] - L.c * s) * L.ih2;
+    };
+    auto Lu_odd = [&](int r, double ky) {
+        const double D = L.a * L.h2 + L.c * (kx1 + ky);
+        const double s = (se[r][lane] + se[r][lane + 1]) + (so[r - 1][lane] + so[r + 1][lane]);
+        return (D * so[r][lane] - L.c * s) * L.ih2;
+    };
     __syncthreads();
+    if (RHS) {
+        // f = r + L u from the values as loaded, at every point with its four neighbours in
+        // the window (the sweeps update no other)
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = w * RPW + i, gy = yw + i;
+            if (r < 1 || r > WY - 2 || gy < 0 || gy >= L.ny) continue;
+            const double ky = kyof(gy);
+            if (in0 && lane >= 1) f0[i] = f0[i] + Lu_even(r, ky);
+            if (in1 && lane <= 62) f1[i] = f1[i] + Lu_odd(r, ky);
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int hs = 0; hs < 2 * NU; ++hs) {
         const int colour = (hs & 1) ^ 1;  // sets 1-2 (odd index sum) first
@@ -250,28 +294,27 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
         }
         __syncthreads();
     }
+    const bool colw = 2 * lane >= HX && 2 * lane < HX + OX;  // the lane's pair is written
     double acc = 0.0;
-    if (2 * lane >= HX && 2 * lane < HX + OX) {
+    if (colw) {
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int r = w * RPW + i, gy = yw + i;
             if (r < HY || r >= HY + OY || gy < 0 || gy >= L.ny) continue;
             if (in0) uout[(size_t)gy * L.nx + x0] = se[r][lane];
             if (in1) uout[(size_t)gy * L.nx + x0 + 1] = so[r][lane];
+            if (RHS) {
+                if (in0) io.fout[(size_t)gy * L.nx + x0] = f0[i];
+                if (in1) io.fout[(size_t)gy * L.nx + x0 + 1] = f1[i];
+            }
             if (NORM) {
-                double ky = 0.0;
-                if (gy == 0) ky += kshift(L.ky);
-                if (gy == L.ny - 1) ky += kshift(L.ky);
+                const double ky = kyof(gy);
                 if (in0) {
-                    const double D = L.a * L.h2 + L.c * (kx0 + ky);
-                    const double s = (so[r][lane - 1] + so[r][lane]) + (se[r - 1][lane] + se[r + 1][lane]);
-                    const double rv = f0[i] - (D * se[r][lane] - L.c * s) * L.ih2;
+                    const double rv = f0[i] - Lu_even(r, ky);
                     acc = acc + rv * rv;
                 }
                 if (in1) {
-                    const double D = L.a * L.h2 + L.c * (kx1 + ky);
-                    const double s = (se[r][lane] + se[r][lane + 1]) + (so[r - 1][lane] + so[r + 1][lane]);
-                    const double rv = f1[i] - (D * so[r][lane] - L.c * s) * L.ih2;
+                    const double rv = f1[i] - Lu_odd(r, ky);
                     acc = acc + rv * rv;
                 }
             }
@@ -286,7 +329,67 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
         if (threadIdx.x == 0) {
             double t = red[0];
             for (int k = 1; k < 8; ++k) t = t + red[k];
-            partials[blockIdx.x] = t;
+            io.partials[blockIdx.x] = t;
+        }
+    }
+    if (RES) {
+        // residuals f - L u in place of f, wherever every neighbour is final (distance
+        // >= 2 nu + 1 from the window edge; the written region and one ring around it)
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = w * RPW + i, gy = yw + i;
+            if (r < 2 * NU + 1 || r > WY - 2 * NU - 2 || gy < 0 || gy >= L.ny) continue;
+            const double ky = kyof(gy);
+            if (in0 && 2 * lane >= 2 * NU + 1) f0[i] = f0[i] - Lu_even(r, ky);
+            if (in1 && 2 * lane + 1 <= 2 * kTile - 2 * NU - 2) f1[i] = f1[i] - Lu_odd(r, ky);
+        }
+        // the third tap of an edge axis: the next lane's even column (EDGE_X), the next
+        // wave's first row (EDGE_Y)
+        double nx0[RPW];
+        if (LOC == LOC_EDGE_X) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) nx0[i] = __shfl_down(f0[i], 1, 64);
+        }
+        __shared__ double xre[LOC == LOC_EDGE_Y ? 8 : 1][kTile], xro[LOC == LOC_EDGE_Y ? 8 : 1][kTile];
+        if (LOC == LOC_EDGE_Y) {
+            xre[w][lane] = f0[0];
+            xro[w][lane] = f1[0];
+            __syncthreads();
+        }
+        if (colw) {
+            const int K = x0 >> 1;  // x0 >= 0 here
+#pragma unroll
+            for (int p = 0; p < RPW / 2; ++p) {
+                const int r = w * RPW + 2 * p, gy = yw + 2 * p;  // gy even
+                if (r < HY || r >= HY + OY || gy < 0) continue;
+                const int J = gy >> 1;
+                if (J >= io.ncy || K >= io.ncx) continue;
+                double ru, rr;
+                if (LOC == LOC_CELL) {
+                    ru = ((se[r][lane] + so[r][lane]) + (se[r + 1][lane] + so[r + 1][lane])) * 0.25;
+                    rr = ((f0[2 * p] + f1[2 * p]) + (f0[2 * p + 1] + f1[2 * p + 1])) * 0.25;
+                } else if (LOC == LOC_EDGE_X) {
+                    const double gu0 = (se[r][lane] + 2.0 * so[r][lane]) + se[r][lane + 1];
+                    const double gu1 = (se[r + 1][lane] + 2.0 * so[r + 1][lane]) + se[r + 1][lane + 1];
+                    const double gr0 = (f0[2 * p] + 2.0 * f1[2 * p]) + nx0[2 * p];
+                    const double gr1 = (f0[2 * p + 1] + 2.0 * f1[2 * p + 1]) + nx0[2 * p + 1];
+                    ru = (gu0 + gu1) * 0.125;
+                    rr = (gr0 + gr1) * 0.125;
+                } else {
+                    const double e2 = 2 * p + 2 < RPW ? f0[(2 * p + 2) % RPW] : xre[(w + 1) & 7][lane];
+                    const double o2 = 2 * p + 2 < RPW ? f1[(2 * p + 2) % RPW] : xro[(w + 1) & 7][lane];
+                    const double gu0 = (se[r][lane] + 2.0 * se[r + 1][lane]) + se[r + 2][lane];
+                    const double gu1 = (so[r][lane] + 2.0 * so[r + 1][lane]) + so[r + 2][lane];
+                    const double gr0 = (f0[2 * p] + 2.0 * f0[2 * p + 1]) + e2;
+                    const double gr1 = (f1[2 * p] + 2.0 * f1[2 * p + 1]) + o2;
+                    ru = (gu0 + gu1) * 0.125;
+                    rr = (gr0 + gr1) * 0.125;
+                }
+                const size_t c = (size_t)J * io.ncx + K;
+                io.uc[c] = ru;
+                io.uc0[c] = ru;
+                io.rc[c] = rr;
+            }
         }
     }
 }
@@ -318,9 +421,20 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A)
     const int n0 = A.op[0].nx * A.op[0].ny;
     for (int t = threadIdx.x; t < n0; t += blockDim.x) {
         lds[A.ou[0] + t] = A.u[t];
-        lds[A.of[0] + t] = A.f[t];
+        lds[A.of[0] + t] = A.r ? A.r[t] : A.f[t];
     }
     __syncthreads();
+    if (A.r) {
+        // f = r + L u from the loaded iterate (as k_coarse_rhs)
+        const Lev& L = A.op[0];
+        double* u = lds + A.ou[0];
+        double* f = lds + A.of[0];
+        for (int t = threadIdx.x; t < n0; t += blockDim.x) {
+            const int x = t % L.nx, y = t / L.nx;
+            f[t] = f[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
+        }
+        __syncthreads();
+    }
     for (int l = 0; l + 1 < A.nlev; ++l) {
         const Lev& L = A.op[l];
         const Lev& Lc = A.op[l + 1];
@@ -556,56 +670,58 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-template <int NU, int LOC, bool NORM>
-void sweep_loc(hipStream_t s, dim3 grid, const Lev& L, const double* f, const double* uin, double* uout, int tx,
-               const Coarse* corr, double* partials)
+template <int NU, int LOC, bool CORR, bool NORM, bool RHS, bool RES>
+void sweep_go(hipStream_t s, dim3 grid, const Lev& L, const double* f, const double* uin, double* uout, int tx,
+              const SweepIO& io)
 {
-    const Coarse C = corr ? *corr : Coarse{nullptr, nullptr, 0, 0};
-    if (corr)
-        hipLaunchKernelGGL((k_sweep<NU, LOC, true, NORM>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C, partials);
-    else
-        hipLaunchKernelGGL((k_sweep<NU, LOC, false, NORM>), grid, dim3(512), 0, s, L, f, uin, uout, tx, C, partials);
+    hipLaunchKernelGGL((k_sweep<NU, LOC, CORR, NORM, RHS, RES>), grid, dim3(512), 0, s, L, f, uin, uout, tx, io);
 }
 
-template <int LOC>
-void sweep_nu(hipStream_t s, dim3 grid, const Lev& L, int nu, const double* f, const double* uin, double* uout, int tx,
-              const Coarse* corr, double* partials)
+template <int NU, int LOC>
+void sweep_flags(hipStream_t s, dim3 grid, const Lev& L, const double* f, const double* uin, double* uout, int tx,
+                 const SweepIO& io, unsigned flags)
 {
-    if (partials) {
-        if (nu == 1)
-            sweep_loc<1, LOC, true>(s, grid, L, f, uin, uout, tx, corr, partials);
-        else
-            sweep_loc<2, LOC, true>(s, grid, L, f, uin, uout, tx, corr, partials);
-    } else {
-        if (nu == 1)
-            sweep_loc<1, LOC, false>(s, grid, L, f, uin, uout, tx, corr, partials);
-        else
-            sweep_loc<2, LOC, false>(s, grid, L, f, uin, uout, tx, corr, partials);
+    switch (flags) {
+    case 0: sweep_go<NU, LOC_CELL, false, false, false, false>(s, grid, L, f, uin, uout, tx, io); break;
+    case SW_CORR: sweep_go<NU, LOC, true, false, false, false>(s, grid, L, f, uin, uout, tx, io); break;
+    case SW_CORR | SW_NORM: sweep_go<NU, LOC, true, true, false, false>(s, grid, L, f, uin, uout, tx, io); break;
+    case SW_RHS: sweep_go<NU, LOC_CELL, false, false, true, false>(s, grid, L, f, uin, uout, tx, io); break;
+    case SW_RES: sweep_go<NU, LOC, false, false, false, true>(s, grid, L, f, uin, uout, tx, io); break;
+    case SW_RHS | SW_RES: sweep_go<NU, LOC, false, false, true, true>(s, grid, L, f, uin, uout, tx, io); break;
+    default: throw Error(FAS_ERR_ARG, "internal: unsupported sweep variant");
     }
 }
 
-int sweep_blocks(const Lev& L, int nu, bool norm, int* tiles_x)
+int sweep_blocks(const Lev& L, int nu, unsigned flags, int* tiles_x)
 {
-    const int ox = 2 * kTile - 2 * (2 * nu + (norm ? 2 : 0)), oy = kWinRows - 2 * (2 * nu + (norm ? 1 : 0));
-    const int tx = (L.nx + ox - 1) / ox, ty = (L.ny + oy - 1) / oy;
+    const SweepGeom g = sweep_geom(nu, (flags & SW_NORM) != 0, (flags & SW_RES) != 0);
+    const int tx = (L.nx + g.ox - 1) / g.ox, ty = (L.ny + g.oy - 1) / g.oy;
     if (tiles_x) *tiles_x = tx;
     return tx * ty;
 }
 
 int launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
-                 const Coarse* corr, double* partials)
+                 const SweepIO& io, unsigned flags)
 {
     int tx;
-    const int nb = sweep_blocks(L, nu, partials != nullptr, &tx);
+    const int nb = sweep_blocks(L, nu, flags, &tx);
     const dim3 grid(nb);
-    // without a correction the location does not matter: one instantiation serves all
-    if (!corr || loc == LOC_CELL)
-        sweep_nu<LOC_CELL>(s, grid, L, nu, f, uin, uout, tx, corr, partials);
-    else if (loc == LOC_EDGE_X)
-        sweep_nu<LOC_EDGE_X>(s, grid, L, nu, f, uin, uout, tx, corr, partials);
-    else
-        sweep_nu<LOC_EDGE_Y>(s, grid, L, nu, f, uin, uout, tx, corr, partials);
+    if (loc == LOC_CELL) {
+        if (nu == 1) sweep_flags<1, LOC_CELL>(s, grid, L, f, uin, uout, tx, io, flags);
+        else sweep_flags<2, LOC_CELL>(s, grid, L, f, uin, uout, tx, io, flags);
+    } else if (loc == LOC_EDGE_X) {
+        if (nu == 1) sweep_flags<1, LOC_EDGE_X>(s, grid, L, f, uin, uout, tx, io, flags);
+        else sweep_flags<2, LOC_EDGE_X>(s, grid, L, f, uin, uout, tx, io, flags);
+    } else {
+        if (nu == 1) sweep_flags<1, LOC_EDGE_Y>(s, grid, L, f, uin, uout, tx, io, flags);
+        else sweep_flags<2, LOC_EDGE_Y>(s, grid, L, f, uin, uout, tx, io, flags);
+    }
     return nb;
+}
+
+void launch_form_rhs(hipStream_t s, const Lev& L, const double* r, const double* u, double* f)
+{
+    hipLaunchKernelGGL(k_form_rhs, dim3(blocks_for((int64_t)L.nx * L.ny)), dim3(256), 0, s, L, r, u, f);
 }
 
 void launch_sum(hipStream_t s, const double* partials, int n, double* out)

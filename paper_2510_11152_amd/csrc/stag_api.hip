@@ -31,6 +31,7 @@ struct fas_stag {
         double* ut;       // second buffer of the iterate
         double* u0;       // restricted iterate before the coarse solve (levels >= 1)
         double* f;        // right-hand side (levels >= 1)
+        double* r;        // restricted residual of the finer level (levels >= 1, fused path)
     } lev[fas::kMaxLevels];
     double* partials;
     double* norm;
@@ -112,7 +113,8 @@ int partials_count(int loc, int64_t mx, int64_t my)
     Lev L{};
     L.nx = (int)nx;
     L.ny = (int)ny;
-    return std::max(kNormBlocks, std::max(sweep_blocks(L, 1, true, nullptr), sweep_blocks(L, 2, true, nullptr)));
+    return std::max(kNormBlocks, std::max(sweep_blocks(L, 1, SW_CORR | SW_NORM, nullptr),
+                                          sweep_blocks(L, 2, SW_CORR | SW_NORM, nullptr)));
 }
 
 // Bytes of the workspace of one staggered variable (0 on a bad shape).
@@ -124,7 +126,7 @@ size_t stag_bytes(int loc, int64_t mx, int64_t my, int coarsest)
         int64_t nx, ny;
         unknowns(loc, mx >> l, my >> l, nx, ny);
         const size_t arr = align_up((size_t)(nx * ny) * sizeof(double));
-        b += l == 0 ? arr : 4 * arr;
+        b += l == 0 ? arr : 5 * arr;
     }
     b += align_up((partials_count(loc, mx, my) + 8) * sizeof(double));
     return b;
@@ -148,7 +150,8 @@ Lev level_op(const fas_stag& S, int l, double a, double c)
 // nu sweeps from buffer cur (alt: the other buffer of the level).  The launches do two sweeps
 // each, one when nu is odd; with `want` set, one two-sweep launch becomes two one-sweep
 // launches (or a copy follows) so that the result lands in `want`.  corr: FAS correction
-// applied as the first launch loads its window.  Returns the buffer that holds the result.
+// applied as the first launch loads its window; partials: the last launch sums the residual
+// norm (its block count goes to norm_blocks).  Returns the buffer that holds the result.
 double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* cur, double* alt, int nu, double* want,
                const Coarse* corr = nullptr, double* partials = nullptr, int* norm_blocks = nullptr)
 {
@@ -178,9 +181,18 @@ double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* c
     const int n = twos + ones;
     for (int i = 0; i < n; ++i) {
         const bool last = i == n - 1 && !copy_after;
-        const int nb = launch_sweep(st, loc, L, i < twos ? 2 : 1, f, a, b, i == 0 ? corr : nullptr,
-                                    last ? partials : nullptr);
-        if (last && partials && norm_blocks) *norm_blocks = nb;
+        SweepIO io{};
+        unsigned flags = 0;
+        if (i == 0 && corr) {
+            io.C = *corr;
+            flags |= SW_CORR;
+        }
+        if (last && partials && (flags & SW_CORR)) {
+            io.partials = partials;
+            flags |= SW_NORM;
+        }
+        const int nb = launch_sweep(st, loc, L, i < twos ? 2 : 1, f, a, b, io, flags);
+        if (flags & SW_NORM && norm_blocks) *norm_blocks = nb;
         std::swap(a, b);
     }
     if (copy_after) {
@@ -192,10 +204,44 @@ double* sweeps(hipStream_t st, int loc, const Lev& L, const double* f, double* c
 
 int launches(int nu) { return nu / 2 + nu % 2; }
 
+// Pre-smoothing of the fused path: nu >= 1 sweeps from u (ut: the other buffer).  With r set,
+// the first launch forms the right-hand side f = r + L u (and writes f); the last restricts
+// the smoothed iterate and its residual into level C.  Returns the buffer holding the
+// smoothed iterate.
+double* pre_fused(hipStream_t st, int loc, const Lev& L, const double* r, double* f, double* u, double* ut, int nu,
+                  fas_stag::Level& C)
+{
+    const int twos = nu / 2, n = twos + nu % 2;
+    double* a = u;
+    double* b = ut;
+    for (int i = 0; i < n; ++i) {
+        SweepIO io{};
+        unsigned flags = 0;
+        const double* fin = f;
+        if (i == 0 && r) {
+            flags |= SW_RHS;
+            io.fout = f;
+            fin = r;
+        }
+        if (i == n - 1) {
+            flags |= SW_RES;
+            io.uc = C.u;
+            io.uc0 = C.u0;
+            io.rc = C.r;
+            io.ncx = C.nx;
+            io.ncy = C.ny;
+        }
+        launch_sweep(st, loc, L, i < twos ? 2 : 1, fin, a, b, io, flags);
+        std::swap(a, b);
+    }
+    return a;
+}
+
 // One V(nu1, nu2) cycle from level l on right-hand side f with the iterate in u (the result
-// returns to u).  Returns the number of residual partial sums the last sweep left in
-// S.partials (0: none, the norm needs its own pass).
-int vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, int nu1, int nu2)
+// returns to u).  r: the level's restricted residual when its right-hand side has yet to be
+// formed (f = r + L u; fused path, levels >= 1), else null.  Returns the number of residual
+// partial sums the last sweep left in S.partials (0: none, the norm needs its own pass).
+int vcycle(fas_stag& S, int l, double a, double c, double* f, double* u, int nu1, int nu2, const double* r = nullptr)
 {
     const Lev L = level_op(S, l, a, c);
     double* ut = S.lev[l].ut;
@@ -210,21 +256,32 @@ int vcycle(fas_stag& S, int l, double a, double c, const double* f, double* u, i
         }
         A.u = u;
         A.f = f;
+        A.r = r;
         A.nu1 = nu1;
         A.nu2 = nu2;
         A.nuc = S.nuc;
         launch_tail(S.stream, S.loc, A);
         return 0;
     }
+    if (r && (nu1 == 0 || l == S.L - 1)) {
+        launch_form_rhs(S.stream, L, r, u, f);  // no pre-smoothing launch to form it in
+        r = nullptr;
+    }
     if (l == S.L - 1) {
         sweeps(S.stream, S.loc, L, f, u, ut, S.nuc, u);  // Remark 1: the coarsest level is smoothed
         return 0;
     }
-    double* cur = sweeps(S.stream, S.loc, L, f, u, ut, nu1, nullptr);
     auto& C = S.lev[l + 1];
-    launch_restrict(S.stream, S.loc, L, f, cur, C.nx, C.ny, C.u, C.u0, C.f);
-    launch_coarse_rhs(S.stream, level_op(S, l + 1, a, c), C.f, C.u);
-    vcycle(S, l + 1, a, c, C.f, C.u, nu1, nu2);
+    double* cur;
+    if (S.fused && nu1 > 0) {
+        cur = pre_fused(S.stream, S.loc, L, r, f, u, ut, nu1, C);
+        vcycle(S, l + 1, a, c, C.f, C.u, nu1, nu2, C.r);
+    } else {
+        cur = sweeps(S.stream, S.loc, L, f, u, ut, nu1, nullptr);
+        launch_restrict(S.stream, S.loc, L, f, cur, C.nx, C.ny, C.u, C.u0, C.f);
+        launch_coarse_rhs(S.stream, level_op(S, l + 1, a, c), C.f, C.u);
+        vcycle(S, l + 1, a, c, C.f, C.u, nu1, nu2);
+    }
     if (S.fused && nu2 > 0) {
         // correction in the first post-smoothing launch, the residual norm (finest level) in
         // the last
@@ -271,7 +328,7 @@ int solve(fas_stag& S, double a, double c, const double* f, double* u, double to
     double res = residual_norm(S, a, c, f, u, nullptr);
     int k = 0;
     while (isfinite(res) && res > tol && k < kmax) {
-        const int nb = vcycle(S, 0, a, c, f, u, nu1, nu2);
+        const int nb = vcycle(S, 0, a, c, const_cast<double*>(f), u, nu1, nu2);
         ++k;
         if (nb > 0) {
             launch_sum(S.stream, S.partials, nb, S.norm);
@@ -316,13 +373,14 @@ void init_stag(fas_stag& S, int loc, int64_t mx, int64_t my, double h, int cell_
         V.ut = reinterpret_cast<double*>(ws + off);
         off += arr;
         if (l == 0) {
-            V.u = V.u0 = V.f = nullptr;
+            V.u = V.u0 = V.f = V.r = nullptr;
             continue;
         }
         V.u = reinterpret_cast<double*>(ws + off);
         V.u0 = reinterpret_cast<double*>(ws + off + arr);
         V.f = reinterpret_cast<double*>(ws + off + 2 * arr);
-        off += 3 * arr;
+        V.r = reinterpret_cast<double*>(ws + off + 3 * arr);
+        off += 4 * arr;
     }
     S.partials = reinterpret_cast<double*>(ws + off);
     S.norm = S.partials + partials_count(loc, mx, my);
@@ -426,7 +484,7 @@ int fas_stag_vcycle(fas_stag_t* s, double a, double c, const void* f, void* w, i
         if (!s) throw Error(FAS_ERR_ARG, "null handle");
         check_pointers(f, w);
         if (nu1 < 0 || nu2 < 0) throw Error(FAS_ERR_ARG, "negative sweep count");
-        vcycle(*s, 0, a, c, static_cast<const double*>(f), static_cast<double*>(w), nu1, nu2);
+        vcycle(*s, 0, a, c, static_cast<double*>(const_cast<void*>(f)), static_cast<double*>(w), nu1, nu2);
         FAS_HIP_CHECK(hipGetLastError());
         return FAS_OK;
     });

@@ -40,16 +40,42 @@ struct Coarse {
     }
 };
 
-// nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers).  With corr,
-// the window is loaded as uin + P e (the correction of level L from corr), as k_correct would
-// have written it.  With partials, each block also writes the sum of the squared residuals
-// f - L u of the values it wrote (one double per block).  Returns the number of blocks.
+// Window of a sweep launch: rows, margins of the written region along x and y (the sweeps
+// reach 2 nu; the norm needs one more ring, the fused restriction two, since an edge axis
+// takes a third tap one past the region; x margins stay even), and the written extents.
+struct SweepGeom {
+    int wy, hx, hy, ox, oy;
+};
+constexpr SweepGeom sweep_geom(int nu, bool norm, bool res)
+{
+    return SweepGeom{res ? 2 * kWinRows : kWinRows, 2 * nu + (norm || res ? 2 : 0),
+                     2 * nu + (res ? 2 : (norm ? 1 : 0)), 2 * kTile - 2 * (2 * nu + (norm || res ? 2 : 0)),
+                     (res ? 2 * kWinRows : kWinRows) - 2 * (2 * nu + (res ? 2 : (norm ? 1 : 0)))};
+}
+
+// Fused work of a sweep launch (flags), and its arrays.
+enum { SW_CORR = 1, SW_NORM = 2, SW_RHS = 4, SW_RES = 8 };
+struct SweepIO {
+    Coarse C;           // SW_CORR: the window is loaded as uin + P e
+    double* partials;   // SW_NORM: per block, the sum of the squared residuals written
+    double* fout;       // SW_RHS: f (the input) holds r; f = r + L u is formed and written here
+    double* uc;         // SW_RES: uc = uc0 = R u and rc = R (f - L u) of the written region
+    double* uc0;
+    double* rc;
+    int ncx, ncy;
+};
+
+// nu (1 or 2) full sweeps of level L: reads uin, writes uout (distinct buffers), with the
+// fused work of `flags` (allowed: none, CORR, CORR | NORM, RHS, RES, RHS | RES).  Returns the
+// number of blocks (the partial sums of SW_NORM).
 int launch_sweep(hipStream_t s, int loc, const Lev& L, int nu, const double* f, const double* uin, double* uout,
-                 const Coarse* corr, double* partials);
+                 const SweepIO& io, unsigned flags);
 // Blocks of such a launch (tiles_x may be NULL).
-int sweep_blocks(const Lev& L, int nu, bool norm, int* tiles_x);
+int sweep_blocks(const Lev& L, int nu, unsigned flags, int* tiles_x);
 // out[0] = sum of partials[0 .. n) in a fixed order.
 void launch_sum(hipStream_t s, const double* partials, int n, double* out);
+// f = r + L u on level L (out of place).
+void launch_form_rhs(hipStream_t s, const Lev& L, const double* r, const double* u, double* f);
 
 // Persistent tail: levels top .. coarsest in one workgroup's LDS.
 constexpr int kTailMaxLevels = 12;
@@ -60,7 +86,8 @@ struct TailArgs {
     Lev op[kTailMaxLevels];
     int ou[kTailMaxLevels], of[kTailMaxLevels], ou0[kTailMaxLevels];  // LDS offsets (doubles)
     double* u;                                  // top level iterate (in and out)
-    const double* f;                            // top level right-hand side
+    const double* f;                            // top level right-hand side, or
+    const double* r;                            // its restricted residual (f = r + L u formed here)
     int nu1, nu2, nuc;
 };
 void launch_tail(hipStream_t s, int loc, const TailArgs& A);
