@@ -417,8 +417,8 @@ def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=
     """Section 4.4.3: Scheme 1 (first-order projection) on the staggered 4096^2 grid, Re = 10,
     tol 1e-9, V(2,2), manufactured source at t^{n+1}, t = 0 .. 1 for each dt; L2 errors at
     t = 1 against the exact solution and their orders.  Then both field layouts at one dt
-    (fields, workspace, peak device memory, time per step), and the red-black sweep
-    kernel's bandwidth on the finest u grid timed with HIP events."""
+    (fields, workspace, peak device memory, time per step), and the finest level's fused
+    pre- and post-smoothing launches of the u solve timed with the library's HIP events."""
     import numpy as np
     import torch
 
@@ -490,30 +490,29 @@ def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=
     layouts["time_ratio_classical_over_memory_efficient"] = (layouts["classical"]["ms_per_step"] /
                                                             layouts["memory_efficient"]["ms_per_step"])
     out["layouts_dt_1_40"] = layouts
-    # the finest-level red-black sweep kernel (two sweeps per launch) on the u grid
+    # the finest level's fused launches of the u solve, timed by the library's HIP events
+    # (FAS_OPT_PROFILE) over a solve of six cycles
     S = StaggeredSolver("edge_x", n, n, h)
+    S.set(profile=1)
     f = torch.randn(S.shape, dtype=torch.float64, device=dev)
-    w = torch.randn_like(f)
-    S.smooth(1.0, 0.1 / re, f, w, 4)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        S.smooth(1.0, 0.1 / re, f, w, 4)       # two launches of the two-sweep kernel
-    e1.record()
-    torch.cuda.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / (2 * reps)
-    cells = S.shape[0] * S.shape[1]
-    alg = 24.0 * cells                          # read w and f, write w: 3 x 8 bytes per value
-    out["sweep_kernel"] = {"kernel": "k_sweep<2> (two red-black sweeps)", "grid": list(S.shape), "avg_us": us,
-                           "algorithmic_bytes": alg, "gbs": alg / (us * 1e-6) / 1e9,
-                           "frac": alg / (us * 1e-6) / 8e12}
-    gbs = alg / (us * 1e-6) / 1e9
-    out["roofline"] = {"bound": "hbm", "kernel": "k_sweep<2, *, false, false> (pre-smoothing, finest level)",
+    w = torch.zeros_like(f)
+    S.solve(1.0, 0.025 / re, f, w, 0.0, kmax=6)
+    pre_us, post_us, timed = S.profile()
+    fine = S.shape[0] * S.shape[1]
+    coarse = (n // 2) * (n // 2 - 1)
+    alg_pre = 24.0 * fine + 24.0 * coarse    # read w, f; write w; write R w (twice) and R r
+    alg_post = 24.0 * fine + 16.0 * coarse   # read w, f and the coarse iterate and its copy; write w
+    out["finest_kernels"] = {
+        "grid": list(S.shape), "cycles_timed": timed,
+        "pre": {"kernel": "k_sweep<2, EDGE_X, RHS=0, RES=1>: two sweeps, residual, restriction",
+                "avg_us": pre_us, "algorithmic_bytes": alg_pre, "gbs": alg_pre / (pre_us * 1e-6) / 1e9},
+        "post": {"kernel": "k_sweep<2, EDGE_X, CORR=1, NORM=1>: correction, two sweeps, residual norm",
+                 "avg_us": post_us, "algorithmic_bytes": alg_post, "gbs": alg_post / (post_us * 1e-6) / 1e9}}
+    gbs = alg_pre / (pre_us * 1e-6) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": out["finest_kernels"]["pre"]["kernel"] + " (finest level)",
                        "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                       "traffic": measured_traffic("sweep", n, NS_TRAFFIC_FILE, NS_SOURCES),
-                       "algorithmic_bytes": alg}
+                       "traffic": measured_traffic("pre", n, NS_TRAFFIC_FILE, NS_SOURCES),
+                       "algorithmic_bytes": alg_pre}
     if ceiling:
         out["roofline"]["attainable"] = ceiling
         out["roofline"]["frac_of_attainable"] = gbs / ceiling

@@ -53,11 +53,19 @@ size_t fas_stag_workspace_size(int loc, int64_t nx, int64_t ny, int coarsest);
 int fas_stag_create(int loc, int64_t nx, int64_t ny, double h, int cell_bc, int coarsest, void* workspace,
                     size_t workspace_bytes, void* stream, fas_stag_t** out);
 int fas_stag_destroy(fas_stag_t* s);
-/* Options (FAS_ERR_ARG for any other): FAS_OPT_COARSE_SWEEPS (>= 1) and FAS_OPT_FUSED
- * (1, the default: the levels from 64 x 64 unknowns down run as one persistent workgroup
- * with every array in LDS, and the FAS correction is applied inside the first
- * post-smoothing launch; 0: one kernel per step and level).  Both give identical results. */
+/* Options (FAS_ERR_ARG for any other): FAS_OPT_COARSE_SWEEPS (>= 1); FAS_OPT_FUSED (1, the
+ * default: the levels from 64 x 64 unknowns down run as one persistent workgroup with every
+ * array in LDS, the restriction and the coarse right-hand side are formed inside the
+ * pre-smoothing launches and the FAS correction and the residual norm inside the
+ * post-smoothing ones; 0: one kernel per step and level; both give identical results);
+ * FAS_OPT_PROFILE (1: HIP events time the finest level's pre- and post-smoothing launches of
+ * the fused path, one cycle in every synchronised stretch; read with fas_stag_profile). */
 int fas_stag_set(fas_stag_t* s, int option, double value);
+/* Average microseconds of the profiled finest-level pre-smoothing launches (smoothing,
+ * residual and restriction) and post-smoothing launches (correction, smoothing and, in a
+ * solve, the residual norm), and the number of cycles timed.  Synchronises the stream.
+ * FAS_ERR_ARG if FAS_OPT_PROFILE is off. */
+int fas_stag_profile(fas_stag_t* s, double* pre_us, double* post_us, int* cycles);
 int fas_stag_levels(const fas_stag_t* s);
 
 /* Algorithm 1's loop: V(nu1, nu2) cycles until res = h ||f - L w||_2 <= tol (eq.

@@ -82,6 +82,7 @@ SIGNATURES = {
     "fas_stag_destroy": (_i, [_vp]),
     "fas_stag_set": (_i, [_vp, _i, _d]),
     "fas_stag_levels": (_i, [_vp]),
+    "fas_stag_profile": (_i, [_vp, _pd, _pd, ctypes.POINTER(ctypes.c_int)]),
     "fas_stag_solve": (_i, [_vp, _d, _d, _vp, _vp, _d, _i, _i, _i, ctypes.POINTER(ctypes.c_int), _pd]),
     "fas_stag_vcycle": (_i, [_vp, _d, _d, _vp, _vp, _i, _i]),
     "fas_stag_smooth": (_i, [_vp, _d, _d, _vp, _vp, _i]),

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "fas_device.h"
 #include "fas_internal.h"
@@ -164,6 +165,86 @@ __global__ __launch_bounds__(256) void k_correct(Lev Lf, Coarse C, const double*
     udst[t] = usrc[t] + prolong_point<LOC>(C, (int)(t % Lf.nx), (int)(t / Lf.nx));
 }
 
+// Coarse corrections a lane's window columns need, loaded at once: e(K', J') for K' in
+// {K} (cells), {K-1, K} (EW edges) or {K-1, K, K+1} (NS edges), K = x0 / 2, and the RPW/2 + 3
+// coarse rows around the lane's rows.  pe<PAR, I, S>() evaluates prolong_point at
+// (x0 + S, yw + I) from the table with the same operations (yw of parity PAR), so the result
+// is the same bit for bit; entries outside the coarse grid are never used.
+template <int LOC, int RPW>
+struct CorrTable {
+    static constexpr int NK = LOC == LOC_CELL ? 1 : (LOC == LOC_EDGE_X ? 2 : 3);
+    static constexpr int NJ = RPW / 2 + 3;
+    double E[NK][NJ];
+    int K, Jb;
+    __device__ __forceinline__ void load(const Coarse& C, int x0, int yw)
+    {
+        K = x0 >> 1;
+        Jb = (yw >> 1) - 1;
+        const int Kb = K - (LOC == LOC_CELL ? 0 : 1);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const int Kq = Kb + kk, Jq = Jb + jj;
+                E[kk][jj] = (Kq >= 0 && Kq < C.ncx && Jq >= 0 && Jq < C.ncy) ? C.e(Kq, Jq) : 0.0;
+            }
+    }
+    template <int PAR, int I, int S>
+    __device__ __forceinline__ double pe(const Coarse& C) const
+    {
+        constexpr int jj = ((PAR + I) >> 1) + 1;  // J - Jb
+        constexpr bool yodd = ((PAR + I) & 1) != 0;
+        const int J = Jb + jj;
+        if constexpr (LOC == LOC_CELL) {
+            return E[0][jj];
+        } else if constexpr (LOC == LOC_EDGE_X) {
+            auto col = [&](int kk) {
+                const double e0 = E[kk][jj];
+                const double nb = yodd ? (J < C.ncy - 1 ? E[kk][jj + 1] : -e0) : (J > 0 ? E[kk][jj - 1] : -e0);
+                return lin_cell(e0, nb);
+            };
+            if constexpr (S == 1) {
+                return col(1);
+            } else {
+                const double left = K >= 1 ? col(0) : 0.0;
+                const double right = K <= C.ncx - 1 ? col(1) : 0.0;
+                return (left + right) * 0.5;
+            }
+        } else {
+            auto row = [&](int j) {
+                const double e0 = E[1][j];
+                const double nb = S == 1 ? (K < C.ncx - 1 ? E[2][j] : -e0) : (K > 0 ? E[0][j] : -e0);
+                return lin_cell(e0, nb);
+            };
+            if constexpr (yodd) {
+                return row(jj);
+            } else {
+                const double below = J >= 1 ? row(jj - 1) : 0.0;
+                const double above = J <= C.ncy - 1 ? row(jj) : 0.0;
+                return (below + above) * 0.5;
+            }
+        }
+    }
+};
+
+template <int LOC, int RPW, int PAR, int I>
+__device__ __forceinline__ void corr_row(const CorrTable<LOC, RPW>& T, const Coarse& C, int yw, int ny, bool in0,
+                                         bool in1, double (&u0)[RPW], double (&u1)[RPW])
+{
+    const int gy = yw + I;
+    if (gy < 0 || gy >= ny) return;
+    if (in0) u0[I] = u0[I] + T.template pe<PAR, I, 0>(C);
+    if (in1) u1[I] = u1[I] + T.template pe<PAR, I, 1>(C);
+}
+
+template <int LOC, int RPW, int PAR, int... I>
+__device__ __forceinline__ void corr_rows(const CorrTable<LOC, RPW>& T, const Coarse& C, int yw, int ny, bool in0,
+                                          bool in1, double (&u0)[RPW], double (&u1)[RPW],
+                                          std::integer_sequence<int, I...>)
+{
+    (corr_row<LOC, RPW, PAR, I>(T, C, yw, ny, in0, in1, u0, u1), ...);
+}
+
 // ---- red-black sweeps on an LDS window ------------------------------------------------------
 // A 512-thread block (8 waves) loads a 128-column window of the iterate into LDS: lane l of a
 // wave owns the column pair (2l, 2l + 1) of the window and each wave WY/8 rows, whose
@@ -220,13 +301,13 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
         f1[i] = row && in1 ? f[(size_t)gy * L.nx + x0 + 1] : 0.0;
     }
     if (CORR) {
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int gy = yw + i;
-            if (gy < 0 || gy >= L.ny) continue;
-            if (in0) u0[i] = u0[i] + prolong_point<LOC>(io.C, x0, gy);
-            if (in1) u1[i] = u1[i] + prolong_point<LOC>(io.C, x0 + 1, gy);
-        }
+        // the coarse values are loaded with the window, then P e is added row by row
+        CorrTable<LOC, RPW> T;
+        T.load(io.C, x0, yw);
+        if (yw & 1)
+            corr_rows<LOC, RPW, 1>(T, io.C, yw, L.ny, in0, in1, u0, u1, std::make_integer_sequence<int, RPW>{});
+        else
+            corr_rows<LOC, RPW, 0>(T, io.C, yw, L.ny, in0, in1, u0, u1, std::make_integer_sequence<int, RPW>{});
     }
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {

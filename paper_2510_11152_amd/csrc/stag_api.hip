@@ -36,6 +36,12 @@ struct fas_stag {
     double* partials;
     double* norm;
     hipStream_t stream;
+    // FAS_OPT_PROFILE: HIP events around the finest level's pre- and post-smoothing launches
+    int profile;
+    hipEvent_t ev[4];
+    bool ev_pending;
+    double prof_ms[2];
+    int prof_n;
 };
 
 struct fas_ns {
@@ -273,8 +279,11 @@ int vcycle(fas_stag& S, int l, double a, double c, double* f, double* u, int nu1
     }
     auto& C = S.lev[l + 1];
     double* cur;
+    const bool prof = S.profile && l == 0 && S.fused && nu1 > 0 && nu2 > 0 && !S.ev_pending;
+    if (prof) FAS_HIP_CHECK(hipEventRecord(S.ev[0], S.stream));
     if (S.fused && nu1 > 0) {
         cur = pre_fused(S.stream, S.loc, L, r, f, u, ut, nu1, C);
+        if (prof) FAS_HIP_CHECK(hipEventRecord(S.ev[1], S.stream));
         vcycle(S, l + 1, a, c, C.f, C.u, nu1, nu2, C.r);
     } else {
         cur = sweeps(S.stream, S.loc, L, f, u, ut, nu1, nullptr);
@@ -287,7 +296,12 @@ int vcycle(fas_stag& S, int l, double a, double c, double* f, double* u, int nu1
         // the last
         const Coarse corr{C.u, C.u0, C.nx, C.ny};
         int nb = 0;
+        if (prof) FAS_HIP_CHECK(hipEventRecord(S.ev[2], S.stream));
         sweeps(S.stream, S.loc, L, f, cur, cur == u ? ut : u, nu2, u, &corr, l == 0 ? S.partials : nullptr, &nb);
+        if (prof) {
+            FAS_HIP_CHECK(hipEventRecord(S.ev[3], S.stream));
+            S.ev_pending = true;
+        }
         return nb;
     }
     // the correction goes to the buffer from which nu2 sweeps end in u
@@ -297,11 +311,25 @@ int vcycle(fas_stag& S, int l, double a, double c, double* f, double* u, int nu1
     return 0;
 }
 
+// Adds the last cycle's event times (the stream has been synchronised).
+void profile_collect(fas_stag& S)
+{
+    if (!S.ev_pending) return;
+    float a = 0.f, b = 0.f;
+    FAS_HIP_CHECK(hipEventElapsedTime(&a, S.ev[0], S.ev[1]));
+    FAS_HIP_CHECK(hipEventElapsedTime(&b, S.ev[2], S.ev[3]));
+    S.prof_ms[0] += a;
+    S.prof_ms[1] += b;
+    S.prof_n += 1;
+    S.ev_pending = false;
+}
+
 double read_norm(fas_stag& S)
 {
     double s2 = 0.0;
     FAS_HIP_CHECK(hipMemcpyAsync(&s2, S.norm, sizeof(double), hipMemcpyDeviceToHost, S.stream));
     FAS_HIP_CHECK(hipStreamSynchronize(S.stream));
+    profile_collect(S);
     return S.h * sqrt(s2);
 }
 
@@ -312,6 +340,7 @@ double residual_norm(fas_stag& S, double a, double c, const double* f, const dou
     double s2 = 0.0;
     FAS_HIP_CHECK(hipMemcpyAsync(&s2, S.norm, sizeof(double), hipMemcpyDeviceToHost, S.stream));
     FAS_HIP_CHECK(hipStreamSynchronize(S.stream));
+    profile_collect(S);
     return S.h * sqrt(s2);
 }
 
@@ -411,10 +440,30 @@ int set_option(fas_stag& S, int option, double value)
         S.fused = (int)value;
         return FAS_OK;
     }
+    if (option == FAS_OPT_PROFILE && (value == 0.0 || value == 1.0)) {
+        if (value == 1.0 && !S.profile) {
+            for (auto& e : S.ev) FAS_HIP_CHECK(hipEventCreate(&e));
+            S.ev_pending = false;
+            S.prof_ms[0] = S.prof_ms[1] = 0.0;
+            S.prof_n = 0;
+        }
+        S.profile = (int)value;
+        return FAS_OK;
+    }
     if (option != FAS_OPT_COARSE_SWEEPS || !(value >= 1.0) || value > 1e6)
-        throw Error(FAS_ERR_ARG, "a staggered solver takes FAS_OPT_COARSE_SWEEPS (>= 1) and FAS_OPT_FUSED (0 or 1)");
+        throw Error(FAS_ERR_ARG,
+                    "a staggered solver takes FAS_OPT_COARSE_SWEEPS (>= 1), FAS_OPT_FUSED and FAS_OPT_PROFILE (0 or 1)");
     S.nuc = (int)value;
     return FAS_OK;
+}
+
+void release_events(fas_stag* s)
+{
+    if (s && s->ev[0])
+        for (auto& e : s->ev) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
 }
 
 }  // namespace
@@ -453,8 +502,23 @@ int fas_stag_create(int loc, int64_t nx, int64_t ny, double h, int cell_bc, int 
 
 int fas_stag_destroy(fas_stag_t* s)
 {
+    release_events(s);
     delete s;
     return FAS_OK;
+}
+
+int fas_stag_profile(fas_stag_t* s, double* pre_us, double* post_us, int* cycles)
+{
+    return guarded([&] {
+        if (!s || !s->profile) throw Error(FAS_ERR_ARG, "null handle or FAS_OPT_PROFILE off");
+        FAS_HIP_CHECK(hipStreamSynchronize(s->stream));
+        profile_collect(*s);
+        const int n = s->prof_n;
+        if (pre_us) *pre_us = n ? 1e3 * s->prof_ms[0] / n : 0.0;
+        if (post_us) *post_us = n ? 1e3 * s->prof_ms[1] / n : 0.0;
+        if (cycles) *cycles = n;
+        return FAS_OK;
+    });
 }
 
 int fas_stag_set(fas_stag_t* s, int option, double value)
@@ -579,6 +643,9 @@ int fas_ns_create(int64_t nx, int64_t ny, double h, double re, int layout, int c
 int fas_ns_destroy(fas_ns_t* ns)
 {
     if (ns) {
+        release_events(ns->su);
+        release_events(ns->sv);
+        release_events(ns->sp);
         delete ns->su;
         delete ns->sv;
         delete ns->sp;

@@ -66,13 +66,23 @@ class StaggeredSolver:
                 pass
             self.handle = None
 
-    def set(self, coarse_sweeps=None, fused=None):
+    def set(self, coarse_sweeps=None, fused=None, profile=None):
         """coarse_sweeps: sweeps on the coarsest level; fused: 1 (default) persistent tail
-        and fused correction, 0 one kernel per step and level (identical results)."""
+        and fused transfers, 0 one kernel per step and level (identical results); profile:
+        time the finest level's fused pre- and post-smoothing launches with HIP events."""
         if coarse_sweeps is not None:
             check(load().fas_stag_set(self.handle, _lib.FAS_OPT_COARSE_SWEEPS, float(coarse_sweeps)), "fas_stag_set")
         if fused is not None:
             check(load().fas_stag_set(self.handle, _lib.FAS_OPT_FUSED, float(int(fused))), "fas_stag_set")
+        if profile is not None:
+            check(load().fas_stag_set(self.handle, _lib.FAS_OPT_PROFILE, float(int(profile))), "fas_stag_set")
+
+    def profile(self):
+        """(pre-smoothing us, post-smoothing us, cycles timed) of the finest level."""
+        pre, post, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        check(load().fas_stag_profile(self.handle, ctypes.byref(pre), ctypes.byref(post), ctypes.byref(n)),
+              "fas_stag_profile")
+        return pre.value, post.value, n.value
 
     def _args(self, f, w):
         _check_array(f, self.shape, self.device, "f")

@@ -158,6 +158,8 @@ def test_staggered_create_errors_without_gpu(lib):
     assert lib.fas_stag_set(s, _lib.FAS_OPT_COARSE_SWEEPS, 8.0) == _lib.FAS_OK
     assert lib.fas_stag_set(s, _lib.FAS_OPT_FUSED, 0.0) == _lib.FAS_OK
     assert lib.fas_stag_set(s, _lib.FAS_OPT_FUSED, 2.0) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_set(s, _lib.FAS_OPT_PROFILE, 2.0) == _lib.FAS_ERR_ARG
+    assert lib.fas_stag_profile(s, None, None, None) == _lib.FAS_ERR_ARG   # profiling off
     buf = ctypes.c_void_p(1 << 41)
     assert lib.fas_stag_solve(s, 1.0, 0.1, buf, buf, 1e-9, 2, 2, 20, None, None) == _lib.FAS_ERR_ARG   # aliased
     assert lib.fas_stag_vcycle(s, 1.0, 0.1, None, buf, 2, 2) == _lib.FAS_ERR_ARG

@@ -306,3 +306,15 @@ def test_fused_norm_equals_residual_pass(loc, bc, code, nu2):
     again = S.residual(a, c, fd, wd)
     assert abs(res - again) <= 1e-12 * again
     assert abs(res - ost.res_norm(P, a, c, f, host(wd))) <= 1e-12 * again
+
+
+def test_profile_times_the_fused_finest_launches():
+    say("profile")
+    from paper_2510_11152_amd import StaggeredSolver
+    S = StaggeredSolver("edge_x", 512, 512, 1 / 512)
+    S.set(profile=1)
+    f = torch.randn(S.shape, dtype=torch.float64, device="cuda")
+    w = torch.zeros_like(f)
+    st, cyc, _ = S.solve(1.0, 0.01, f, w, 0.0, kmax=3)
+    pre, post, n = S.profile()
+    assert cyc == 3 and n == 3 and pre > 0.0 and post > 0.0
