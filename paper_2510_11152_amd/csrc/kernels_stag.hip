@@ -254,8 +254,9 @@ __device__ __forceinline__ void corr_rows(const CorrTable<LOC, RPW>& T, const Co
 // nu sweeps over the whole grid give.  Values outside the grid stay 0 in LDS (the 0.0
 // neighbours of the point formula).  Within a half-sweep the updated points read only
 // points of the other colour, so the update runs in place.  Window geometry (rows, margins of
-// the written region): sweep_geom().  Windows are 32 rows (54 VGPRs, 32 KiB of LDS: four
-// blocks per compute unit), 64 for the fused restriction, whose margin is wider.
+// the written region): sweep_geom().  Windows are 32 rows: 54 to 105 VGPRs and 32 KiB of
+// LDS, so two to four blocks share a compute unit (64-row windows, with half the halo share,
+// measured slower in every variant).
 //
 // The window origin is even (the margins and the interior width are even along x), so in a
 // row of one colour exactly one column of every pair is updated, the same one for the whole

@@ -42,15 +42,16 @@ struct Coarse {
 
 // Window of a sweep launch: rows, margins of the written region along x and y (the sweeps
 // reach 2 nu; the norm needs one more ring, the fused restriction two, since an edge axis
-// takes a third tap one past the region; x margins stay even), and the written extents.
+// takes a third tap one past the region; x margins and the row margin of the restriction
+// stay even, keeping 2 x 2 blocks aligned), and the written extents.
 struct SweepGeom {
     int wy, hx, hy, ox, oy;
 };
 constexpr SweepGeom sweep_geom(int nu, bool norm, bool res)
 {
-    return SweepGeom{res ? 2 * kWinRows : kWinRows, 2 * nu + (norm || res ? 2 : 0),
+    return SweepGeom{kWinRows, 2 * nu + (norm || res ? 2 : 0),
                      2 * nu + (res ? 2 : (norm ? 1 : 0)), 2 * kTile - 2 * (2 * nu + (norm || res ? 2 : 0)),
-                     (res ? 2 * kWinRows : kWinRows) - 2 * (2 * nu + (res ? 2 : (norm ? 1 : 0)))};
+                     kWinRows - 2 * (2 * nu + (res ? 2 : (norm ? 1 : 0)))};
 }
 
 // Fused work of a sweep launch (flags), and its arrays.
