@@ -318,3 +318,41 @@ def test_profile_times_the_fused_finest_launches():
     st, cyc, _ = S.solve(1.0, 0.01, f, w, 0.0, kmax=3)
     pre, post, n = S.profile()
     assert cyc == 3 and n == 3 and pre > 0.0 and post > 0.0
+
+
+def test_rectangular_cavity_steps_bitwise():
+    """A 2:1 cavity (128 x 64 cells, Re = 400), memory-efficient layout, bit for bit."""
+    say("ns rectangular cavity")
+    from paper_2510_11152_amd import NavierStokes2D
+    nx, ny = 128, 64
+    G = NavierStokes2D(nx, ny, 1.0 / nx, 400.0)
+    O = ons.Projection(nx, ny, 1.0 / nx, 400.0, lid=1.0)
+    for _ in range(3):
+        _step_both(G, O, 0.005, 1.0, (), (), (), 1e-10)
+        _check_state(G, O)
+
+
+def test_four_source_terms_bitwise():
+    """The separable source with its largest number of terms (4), random fields."""
+    say("ns four sources")
+    n = 64
+    G, O = _ns_pair(n, 50.0, "memory_efficient")
+    rng = np.random.default_rng(5)
+    Fu = [rng.standard_normal(O.u.shape) for _ in range(4)]
+    Fv = [rng.standard_normal(O.v.shape) for _ in range(4)]
+    coef = (0.5, -1.25, 2.0, 0.75)
+    for _ in range(2):
+        _step_both(G, O, 0.01, 0.0, Fu, Fv, coef, 1e-9)
+        _check_state(G, O)
+
+
+def test_step_reports_a_solve_short_of_tol():
+    """kmax = 1 cannot reach 1e-12: the step completes, status FAS_NOT_CONVERGED, and the
+    state is still the oracle's after one cycle per solve."""
+    say("ns not converged")
+    n = 64
+    G, O = _ns_pair(n, 100.0, "memory_efficient", lid=1.0)
+    st, cyc, res = G.step(0.01, 1.0, tol=1e-12, kmax=1)
+    O.step(0.01, tol=1e-12, kmax=1)
+    assert st == 1 and cyc == [1, 1, 1] and all(r > 1e-12 for r in res)
+    _check_state(G, O)
