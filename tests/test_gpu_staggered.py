@@ -347,12 +347,14 @@ def test_four_source_terms_bitwise():
 
 
 def test_step_reports_a_solve_short_of_tol():
-    """kmax = 1 cannot reach 1e-12: the step completes, status FAS_NOT_CONVERGED, and the
-    state is still the oracle's after one cycle per solve."""
+    """After one ordinary step of the cavity (the first v right-hand side from rest is
+    exactly zero, a zero-cycle solve), kmax = 1 cannot reach 1e-14: the step completes with
+    status FAS_NOT_CONVERGED and the state is still the oracle's after one cycle per solve."""
     say("ns not converged")
     n = 64
     G, O = _ns_pair(n, 100.0, "memory_efficient", lid=1.0)
-    st, cyc, res = G.step(0.01, 1.0, tol=1e-12, kmax=1)
-    O.step(0.01, tol=1e-12, kmax=1)
-    assert st == 1 and cyc == [1, 1, 1] and all(r > 1e-12 for r in res)
+    _step_both(G, O, 0.01, 1.0, (), (), (), 1e-9)
+    st, cyc, res = G.step(0.01, 1.0, tol=1e-14, kmax=1)
+    O.step(0.01, tol=1e-14, kmax=1)
+    assert st == 1 and cyc == [1, 1, 1] and all(r > 1e-14 for r in res)
     _check_state(G, O)
