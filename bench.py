@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ns-dts", default="0.1,0.05,0.025,0.0125,0.00625",
                     help="time steps of the projection convergence study (comma list)")
+    ap.add_argument("--ns-sizes", default="1024,2048,4096,8192,16384",
+                    help="cavity grids for the memory / time comparison of the two field layouts")
     ap.add_argument("--forms", default="batched,adjoint,3d,orders,ns",
                     help="other workloads timed after the headline (comma list; 'none' to skip; "
                          "'table45' adds per-cycle times at the paper's Table 4/5 sizes)")
@@ -413,7 +415,8 @@ def bench_3d(dev, steps=5, inner=4, cpu=True):
     return out
 
 
-def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=True, ceiling=None):
+def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=True, ceiling=None,
+             layout_sizes=(1024, 2048, 4096, 8192, 16384)):
     """Section 4.4.3: Scheme 1 (first-order projection) on the staggered 4096^2 grid, Re = 10,
     tol 1e-9, V(2,2), manufactured source at t^{n+1}, t = 0 .. 1 for each dt; L2 errors at
     t = 1 against the exact solution and their orders.  Then both field layouts at one dt
@@ -490,6 +493,38 @@ def bench_ns(dev, n=4096, re=10.0, dts=(0.1, 0.05, 0.025, 0.0125, 0.00625), cpu=
     layouts["time_ratio_classical_over_memory_efficient"] = (layouts["classical"]["ms_per_step"] /
                                                             layouts["memory_efficient"]["ms_per_step"])
     out["layouts_dt_1_40"] = layouts
+    # Section 4.4.1-4.4.2 across sizes: device memory and time per step of both layouts,
+    # lid-driven cavity (Re = 100, dt = 1e-3, tol 1e-9), 5 timed steps after 2
+    sizes = []
+    for m in layout_sizes:
+        row = {"grid": [m, m]}
+        for layout in ("memory_efficient", "classical"):
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats(dev)
+            base = torch.cuda.memory_allocated(dev)
+            G = NavierStokes2D(m, m, 1.0 / m, 100.0, layout=layout)
+            for _ in range(2):
+                G.step(1e-3, lid=1.0)
+
+            def run():
+                for _ in range(5):
+                    G.step(1e-3, lid=1.0)
+
+            t, _ = _timed(run, torch.cuda.synchronize)
+            fb, wb = G.memory()
+            row[layout] = {"field_bytes": fb, "workspace_bytes": wb,
+                           "peak_bytes": torch.cuda.max_memory_allocated(dev) - base, "ms_per_step": 1e3 * t / 5}
+            del G
+        row["peak_saved"] = 1.0 - row["memory_efficient"]["peak_bytes"] / row["classical"]["peak_bytes"]
+        row["time_ratio_classical_over_memory_efficient"] = (row["classical"]["ms_per_step"] /
+                                                            row["memory_efficient"]["ms_per_step"])
+        sizes.append(row)
+        print("bench: ns cavity %d^2 %.2f / %.2f ms per step, peak %.2f / %.2f GB" % (
+            m, row["memory_efficient"]["ms_per_step"], row["classical"]["ms_per_step"],
+            row["memory_efficient"]["peak_bytes"] / 1e9, row["classical"]["peak_bytes"] / 1e9), file=sys.stderr,
+            flush=True)
+    out["layouts_by_size"] = sizes
     # the finest level's fused launches of the u solve, timed by the library's HIP events
     # (FAS_OPT_PROFILE) over a solve of six cycles
     S = StaggeredSolver("edge_x", n, n, h)
@@ -795,7 +830,8 @@ def main():
     if "ns" in forms:
         print("bench: staggered projection step (4096^2)", file=sys.stderr, flush=True)
         result["ns"] = bench_ns(dev, dts=tuple(float(x) for x in args.ns_dts.split(",")),
-                                cpu=not args.no_cpu_baseline, ceiling=attain)
+                                cpu=not args.no_cpu_baseline, ceiling=attain,
+                                layout_sizes=tuple(int(x) for x in args.ns_sizes.split(",") if x))
 
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on two cycles", file=sys.stderr, flush=True)

@@ -442,7 +442,8 @@ int set_option(fas_stag& S, int option, double value)
     }
     if (option == FAS_OPT_PROFILE && (value == 0.0 || value == 1.0)) {
         if (value == 1.0 && !S.profile) {
-            for (auto& e : S.ev) FAS_HIP_CHECK(hipEventCreate(&e));
+            if (!S.ev[0])
+                for (auto& e : S.ev) FAS_HIP_CHECK(hipEventCreate(&e));
             S.ev_pending = false;
             S.prof_ms[0] = S.prof_ms[1] = 0.0;
             S.prof_n = 0;
