@@ -481,15 +481,21 @@ __global__ __launch_bounds__(512) void k_sweep(Lev L, const double* __restrict__
 // every array in LDS: the top level's iterate and right-hand side are loaded once and the
 // iterate is written back at the end, instead of five launches per level.  Each step uses
 // the point formulas of the per-level kernels, so the result is the same bit for bit.
+// The workgroup as 32 x 32 threads: (tx, ty) walks columns and rows with stride 32, so no
+// point index is divided by a row length.
+__device__ __forceinline__ int ttx() { return threadIdx.x & 31; }
+__device__ __forceinline__ int tty() { return threadIdx.x >> 5; }
+
 __device__ void tail_smooth(const Lev& L, const double* f, double* u, int nu)
 {
-    const int n = L.nx * L.ny;
     for (int sw = 0; sw < nu; ++sw) {
         for (int colour = 1; colour >= 0; --colour) {  // sets 1-2 (odd index sum) first
-            for (int t = threadIdx.x; t < n; t += blockDim.x) {
-                const int x = t % L.nx, y = t / L.nx;
-                if (((x + y) & 1) != colour) continue;
-                u[t] = (L.c * nbsum(L, u, x, y) + L.h2 * f[t]) / diag(L, x, y);
+            for (int y = tty(); y < L.ny; y += 32) {
+                const int x0 = (colour + y) & 1;  // first column of this colour in row y
+                for (int x = x0 + 2 * ttx(); x < L.nx; x += 64) {
+                    const int t = y * L.nx + x;
+                    u[t] = (L.c * nbsum(L, u, x, y) + L.h2 * f[t]) / diag(L, x, y);
+                }
             }
             __syncthreads();
         }
@@ -511,10 +517,12 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A)
         const Lev& L = A.op[0];
         double* u = lds + A.ou[0];
         double* f = lds + A.of[0];
-        for (int t = threadIdx.x; t < n0; t += blockDim.x) {
-            const int x = t % L.nx, y = t / L.nx;
-            f[t] = f[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
-        }
+        // f at a point depends on r only at that point: formed in place
+        for (int y = tty(); y < L.ny; y += 32)
+            for (int x = ttx(); x < L.nx; x += 32) {
+                const int t = y * L.nx + x;
+                f[t] = f[t] + (diag(L, x, y) * u[t] - L.c * nbsum(L, u, x, y)) * L.ih2;
+            }
         __syncthreads();
     }
     for (int l = 0; l + 1 < A.nlev; ++l) {
@@ -526,19 +534,21 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A)
         double* uc = lds + A.ou[l + 1];
         double* uc0 = lds + A.ou0[l + 1];
         double* fc = lds + A.of[l + 1];
-        const int nc = Lc.nx * Lc.ny;
-        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-            double ru, rr;
-            restrict_point<LOC>(L, f, u, t % Lc.nx, t / Lc.nx, ru, rr);
-            uc[t] = ru;
-            uc0[t] = ru;
-            fc[t] = rr;
-        }
+        for (int J = tty(); J < Lc.ny; J += 32)
+            for (int K = ttx(); K < Lc.nx; K += 32) {
+                double ru, rr;
+                restrict_point<LOC>(L, f, u, K, J, ru, rr);
+                const int t = J * Lc.nx + K;
+                uc[t] = ru;
+                uc0[t] = ru;
+                fc[t] = rr;
+            }
         __syncthreads();
-        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-            const int x = t % Lc.nx, y = t / Lc.nx;
-            fc[t] = fc[t] + (diag(Lc, x, y) * uc[t] - Lc.c * nbsum(Lc, uc, x, y)) * Lc.ih2;
-        }
+        for (int y = tty(); y < Lc.ny; y += 32)
+            for (int x = ttx(); x < Lc.nx; x += 32) {
+                const int t = y * Lc.nx + x;
+                fc[t] = fc[t] + (diag(Lc, x, y) * uc[t] - Lc.c * nbsum(Lc, uc, x, y)) * Lc.ih2;
+            }
         __syncthreads();
     }
     const int lc = A.nlev - 1;
@@ -547,8 +557,11 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs A)
         const Lev& L = A.op[l];
         const Coarse C{lds + A.ou[l + 1], lds + A.ou0[l + 1], A.op[l + 1].nx, A.op[l + 1].ny};
         double* u = lds + A.ou[l];
-        const int n = L.nx * L.ny;
-        for (int t = threadIdx.x; t < n; t += blockDim.x) u[t] = u[t] + prolong_point<LOC>(C, t % L.nx, t / L.nx);
+        for (int y = tty(); y < L.ny; y += 32)
+            for (int x = ttx(); x < L.nx; x += 32) {
+                const int t = y * L.nx + x;
+                u[t] = u[t] + prolong_point<LOC>(C, x, y);
+            }
         __syncthreads();
         tail_smooth(L, lds + A.of[l], u, A.nu2);
     }
