@@ -74,6 +74,8 @@ def parse():
                     help="pre- and post-sweeps of the FP32 inner cycles of the 2D mixed form")
     ap.add_argument("--inner3d", type=int, default=4,
                     help="FP32 V-cycles per outer correction (3D mixed form; 4 reaches 1e-10 in two corrections)")
+    ap.add_argument("--inner3d-next", type=int, default=0,
+                    help="FP32 V-cycles in the 3D mixed form's corrections after the first (0: --inner3d)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile-shape rule for the 8192^2 grids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -329,7 +331,7 @@ def bench_adjoint(dev):
     return {"grid": [n, n], "steps": T, "ckpt": 4, "forward_backward_s": t, "loss": loss}
 
 
-def bench_3d(dev, steps=5, inner=4, cpu=True):
+def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0):
     """3D heat at 512^3 (7-point, 8-set X-MCGS, Neumann, dt = 1e-4): plain FP64 V(2,2)
     steps to 1e-10, then the same steps with FP32 inner cycles in FP64 correction."""
     import numpy as np
@@ -382,16 +384,17 @@ def bench_3d(dev, steps=5, inner=4, cpu=True):
         outer = []
         for _ in range(steps):
             rhs.copy_(v)
-            assert solve_mixed(g, g32, rhs, v, dt, tol=1e-10, inner=inner) == 0
+            assert solve_mixed(g, g32, rhs, v, dt, tol=1e-10, inner=inner, inner_next=inner_next) == 0
             outer.append(g.stats()["cycles"])
         return outer
 
     v = u0.clone()
     rhs.copy_(v)
-    assert solve_mixed(g, g32, rhs, v, dt, tol=1e-10, inner=inner) == 0  # warm-up
+    assert solve_mixed(g, g32, rhs, v, dt, tol=1e-10, inner=inner, inner_next=inner_next) == 0  # warm-up
     v = u0.clone()
     t_mixed, outer = _timed(lambda: mixed(v), torch.cuda.synchronize)
     out.update({"mixed_s_per_step": t_mixed / steps, "mixed_inner_cycles": inner,
+                "mixed_inner_cycles_next": inner_next or inner,
                 "mixed_outer_per_step": float(np.mean(outer)),
                 "mixed_speedup": t_plain / t_mixed,
                 "mixed_max_rel_diff": (v - u).abs().max().item() / u.abs().max().item()})
@@ -826,7 +829,7 @@ def main():
         result["orders"] = bench_orders(dev)
     if "3d" in forms:
         print("bench: 3D heat", file=sys.stderr, flush=True)
-        result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline)
+        result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline, inner_next=args.inner3d_next)
     if "ns" in forms:
         print("bench: staggered projection step (4096^2)", file=sys.stderr, flush=True)
         result["ns"] = bench_ns(dev, dts=tuple(float(x) for x in args.ns_dts.split(",")),

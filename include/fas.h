@@ -108,6 +108,10 @@ extern "C" {
                                    (Algorithm 1 tests an absolute residual; the relative test
                                    of fas_solve is this library's default); 0 (default): none.
                                    For every solve form; stacked problems share the grid's value */
+#define FAS_OPT_MIXED_INNER_NEXT 13 /* >= 0, set on the FP64 grid of a mixed solve: FP32 cycles in
+                                   every correction after the first (the first takes the
+                                   inner_cycles argument, whose correction starts from the full
+                                   residual); 0 (default): inner_cycles for all */
 
 /* FAS_OPT_ORDER values.  A set is written by the parities of its cells' 1-based indices
  * along x, y (, z), o = odd, e = even:

@@ -67,7 +67,7 @@ def lib():
             getattr(L, "og_vcycle_" + s).restype = i
             getattr(L, "og_solve_" + s).argtypes = [P, vp, vp, vp, d, i, i, i, i, vp, vp]
             getattr(L, "og_solve_" + s).restype = i
-        L.og_solve_mixed.argtypes = [P, vp, vp, vp, d, i, i, i, i, vp, vp]
+        L.og_solve_mixed.argtypes = [P, vp, vp, vp, d, i, i, i, i, i, vp, vp]
         L.og_solve_mixed.restype = i
         L.og_kappa_grad_d.argtypes = [P, vp, vp, vp, vp]
         _lib = L
@@ -202,14 +202,16 @@ def solve(P, f, u, tol=1e-10, nu1=2, nu2=2, kmax=100, transposed=False, kap=None
     return st, cyc.value, hist[: cyc.value]
 
 
-def solve_mixed(P, f, u, tol=1e-10, nu1=2, nu2=2, inner=2, kmax=50, kap=None):
-    """FP64 defect correction around FP32 V-cycles.  Returns (status, outer, rel_hist)."""
+def solve_mixed(P, f, u, tol=1e-10, nu1=2, nu2=2, inner=2, kmax=50, kap=None, inner_next=0):
+    """FP64 defect correction around FP32 V-cycles: `inner` FP32 cycles in the first
+    correction, `inner_next` (if > 0, else `inner`) in the later ones.  Returns (status,
+    outer, rel_hist)."""
     _check(P, 0, f, u, kap)
     assert u.dtype == np.float64
     hist = np.zeros(kmax + 1, dtype=np.float64)
     outer = ctypes.c_int(0)
-    st = lib().og_solve_mixed(ctypes.byref(P.c()), _ptr(kap), _ptr(f), _ptr(u), float(tol), nu1, nu2, inner, kmax,
-                              ctypes.byref(outer), _ptr(hist))
+    st = lib().og_solve_mixed(ctypes.byref(P.c()), _ptr(kap), _ptr(f), _ptr(u), float(tol), nu1, nu2, inner,
+                              inner_next, kmax, ctypes.byref(outer), _ptr(hist))
     if st < 0:
         raise ValueError("invalid grid hierarchy for %r" % (P,))
     return st, outer.value, hist[: outer.value + 1]

@@ -160,7 +160,7 @@ static int og_diag_count(const og_problem* P, int nout)
  * tol = 0 runs exactly kmax corrections.
  * Returns 0 converged, 1 not converged; *outer = corrections applied. */
 int og_solve_mixed(const og_problem* P, const double* kap0, const double* f, double* u, double tol, int nu1,
-                   int nu2, int inner, int kmax, int* outer, double* hist)
+                   int nu2, int inner, int inner_next, int kmax, int* outer, double* hist)
 {
     long N = og_level_cells(P, 0);
     if (og_levels(P) < 1) return -1;
@@ -188,7 +188,10 @@ int og_solve_mixed(const og_problem* P, const double* kap0, const double* f, dou
             r32[p] = (float)r[p];
             e[p] = 0.0f;
         }
-        for (int m = 0; m < inner; ++m) og_vcycle_s(P, k32, r32, e, nu1, nu2, 0);
+        /* inner FP32 cycles: `inner` in the first correction, `inner_next` (if > 0) in the
+         * later ones, whose start residual is already small */
+        const int cycles = (it == 0 || inner_next <= 0) ? inner : inner_next;
+        for (int m = 0; m < cycles; ++m) og_vcycle_s(P, k32, r32, e, nu1, nu2, 0);
         for (long p = 0; p < N; ++p) u[p] = u[p] + (double)e[p];
         ++it;
     }

@@ -183,17 +183,21 @@ class Grid:
                 "rel_res": [s.rel_res[i] for i in range(min(c + 1, 64))]}
 
 
-def solve_mixed(g64, g32, rhs, u, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=2, inner=2):
-    """FP64 defect correction around FP32 V-cycles (g32 built with mixed_inner=True)."""
+def solve_mixed(g64, g32, rhs, u, dt, kappa=1.0, kappa_cell=None, tol=1e-10, nu1=2, nu2=2, inner=2, inner_next=0):
+    """FP64 defect correction around FP32 V-cycles (g32 built with mixed_inner=True):
+    `inner` FP32 cycles in the first correction, `inner_next` (if > 0) in the later ones."""
     g64._arr(rhs, name="rhs"), g64._arr(u, name="u"), g64._arr(kappa_cell, name="kappa_cell")
+    check(load().fas_grid_set(g64.handle, _lib.FAS_OPT_MIXED_INNER_NEXT, float(inner_next)), "fas_grid_set")
     return check(load().fas_solve_mixed(g64.handle, g32.handle, dt, kappa, _ptr(kappa_cell), _ptr(rhs), _ptr(u),
                                         tol, nu1, nu2, inner), "fas_solve_mixed", allow_not_converged=True)
 
 
-def solve_stacked_mixed(g64, g32, rhs, u, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2, inner=2):
+def solve_stacked_mixed(g64, g32, rhs, u, dt, kappa=1.0, tol=1e-10, nu1=2, nu2=2, inner=2, inner_next=0):
     """FP64 defect correction around FP32 V-cycles for every problem of stacked grids
     (g64 FP64, g32 FP32 with mixed_inner=True, the same batch); rhs, u shaped (batch,
-    *shape).  Returns (status per problem, outer corrections per problem)."""
+    *shape); `inner_next` as in solve_mixed.  Returns (status per problem, outer
+    corrections per problem)."""
+    check(load().fas_grid_set(g64.handle, _lib.FAS_OPT_MIXED_INNER_NEXT, float(inner_next)), "fas_grid_set")
     want = (g64.batch,) + g64.shape()
     for t, nm in ((rhs, "rhs"), (u, "u")):
         if t.dtype != torch.float64 or t.device != g64.device or not t.is_contiguous() or tuple(t.shape) != want:

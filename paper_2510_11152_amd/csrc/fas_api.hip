@@ -949,9 +949,11 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
         fas::launch_sum_update(g64, np, tol, k);
         if ((k > horizon || k == kmax + 1) && (stopped = look())) break;
         if (k == kmax + 1) break;
-        for (int m = 0; m < inner; ++m) {
+        // correction k: `inner` cycles for the first, FAS_OPT_MIXED_INNER_NEXT for the later
+        const int cyc_k = (k == 1 || g64->mixed_next <= 0) ? inner : g64->mixed_next;
+        for (int m = 0; m < cyc_k; ++m) {
             g32->zero_start = m == 0 && tile_top;
-            g32->accum64 = m == inner - 1 && tile_top ? (double*)u : nullptr;
+            g32->accum64 = m == cyc_k - 1 && tile_top ? (double*)u : nullptr;
             if (m == 0 && !tile_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
             vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
         }
@@ -1004,9 +1006,11 @@ int solve_mixed_stacked(fas_grid* g64, fas_grid* g32, const void* rhs, void* u, 
             if (hcount[0] == 0) break;
         }
         if (k == kmax + 1) break;
-        for (int m = 0; m < inner; ++m) {
+        // correction k: `inner` cycles for the first, FAS_OPT_MIXED_INNER_NEXT for the later
+        const int cyc_k = (k == 1 || g64->mixed_next <= 0) ? inner : g64->mixed_next;
+        for (int m = 0; m < cyc_k; ++m) {
             g32->zero_start = m == 0 && tile_top;
-            g32->accum64 = m == inner - 1 && tile_top ? (double*)u : nullptr;
+            g32->accum64 = m == cyc_k - 1 && tile_top ? (double*)u : nullptr;
             if (m == 0 && !tile_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
             vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
         }
@@ -1177,7 +1181,7 @@ int solve_noalloc_impl(int dim, const int64_t n[3], double h, int bc, int dtype,
     if (lay.total > kStaticWorkspace)
         throw Error(FAS_ERR_NOMEM, "grid needs " + std::to_string(lay.total) + " bytes of workspace; the static buffer "
                                    "holds " + std::to_string(kStaticWorkspace));
-    fas_grid g;
+    fas_grid g{};
     if (const int rc = setup_grid(&g, dim, n, h, bc, dtype, coarsest, flags, 1, static_workspace(), kStaticWorkspace,
                                   stream))
         throw Error(rc, g_last_error);
@@ -1553,7 +1557,8 @@ int fas_grid_set(fas_grid_t g, int option, double value)
         }
         const int v = (int)value;
         if ((double)v != value) return fail(FAS_ERR_ARG, "option value must be an integer");
-        if (option != FAS_OPT_KMAX && option != FAS_OPT_PROFILE) drop_graph(g);
+        // options that change no captured launch keep the graph
+        if (option != FAS_OPT_KMAX && option != FAS_OPT_PROFILE && option != FAS_OPT_MIXED_INNER_NEXT) drop_graph(g);
         switch (option) {
             case FAS_OPT_KMAX:
                 if (v < 1) return fail(FAS_ERR_ARG, "kmax must be >= 1");
@@ -1562,6 +1567,10 @@ int fas_grid_set(fas_grid_t g, int option, double value)
             case FAS_OPT_COARSE_SWEEPS:
                 if (v < 1) return fail(FAS_ERR_ARG, "coarse sweeps must be >= 1");
                 g->nuc = v;
+                return FAS_OK;
+            case FAS_OPT_MIXED_INNER_NEXT:
+                if (v < 0 || v > 1000) return fail(FAS_ERR_ARG, "mixed inner cycles must be 0..1000");
+                g->mixed_next = v;
                 return FAS_OK;
             case FAS_OPT_PROFILE:
                 if (v != 0 && v != 1) return fail(FAS_ERR_ARG, "profile must be 0 or 1");

@@ -86,6 +86,7 @@ struct fas_grid {
     double* accum64;     // non-null: the finest-level tile post pass adds its result into
                          // this FP64 array instead of storing it (nor the u argument)
     double atol;            // FAS_OPT_ATOL: absolute stopping tolerance on ||f - A u||_2 (0: none)
+    int mixed_next;         // FAS_OPT_MIXED_INNER_NEXT: inner cycles of corrections 2.. (0: as the first)
     int kmax, nuc, fused;   // fused: fused kernels in use (fused_opt with a two-colour order)
     int fused_opt;          // FAS_OPT_FUSED as set
     int order, symmetric;   // FAS_OPT_ORDER / FAS_OPT_SYMMETRIC

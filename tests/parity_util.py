@@ -62,13 +62,13 @@ def check_solve(P, f, u0, got, gpu_cycles, tol, nu1=2, nu2=2, transposed=False, 
     return cyc
 
 
-def check_mixed(P, f, u0, got, gpu_corrections, tol, nu1=2, nu2=2, inner=2, kap=None, gpu_hist=None):
+def check_mixed(P, f, u0, got, gpu_corrections, tol, nu1=2, nu2=2, inner=2, kap=None, gpu_hist=None, inner_next=0):
     """The same comparison for the mixed-precision defect correction: its iterates are the
     oracle's bit for bit (FP64 residual and update, FP32 inner cycles, an unscaled cast),
     and only the outer stopping test is a reduction.  Returns the oracle's corrections."""
     rtol = norm_rtol(np.asarray(f).size)
     uo = u0.copy()
-    st, outer, hist = O.solve_mixed(P, f, uo, tol, nu1, nu2, inner, kap=kap)
+    st, outer, hist = O.solve_mixed(P, f, uo, tol, nu1, nu2, inner, kap=kap, inner_next=inner_next)
     assert st == 0, "oracle mixed solve did not converge"
     assert abs(gpu_corrections - outer) <= 1, (gpu_corrections, outer)
     if gpu_corrections == outer:
@@ -77,7 +77,7 @@ def check_mixed(P, f, u0, got, gpu_corrections, tol, nu1=2, nu2=2, inner=2, kap=
         k = min(gpu_corrections, outer)
         assert abs(hist[k] - tol) <= rtol * tol, (k, hist[k], tol)
         ref = u0.copy()
-        O.solve_mixed(P, f, ref, 0.0, nu1, nu2, inner, kmax=gpu_corrections, kap=kap)
+        O.solve_mixed(P, f, ref, 0.0, nu1, nu2, inner, kmax=gpu_corrections, kap=kap, inner_next=inner_next)
         assert np.array_equal(got, ref), "iterates differ at the library's correction count"
     if gpu_hist is not None:
         k = min(gpu_corrections, outer) + 1

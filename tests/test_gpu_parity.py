@@ -250,6 +250,26 @@ def test_mixed_precision_matches_oracle(n, coarsest, bc, variable, inner):
     assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,coarsest,bc,inner,inner_next", [((128, 128), 4, "neumann", 4, 2), ((256, 128), 4, "dirichlet", 3, 1),
+                                                           ((32, 32, 32), 4, "neumann", 4, 3)])
+def test_mixed_inner_schedule_matches_oracle(n, coarsest, bc, inner, inner_next):
+    """A smaller number of inner cycles after the first correction (FAS_OPT_MIXED_INNER_NEXT):
+    bit for bit the oracle's defect correction with the same schedule."""
+    P = _problem(n, coarsest, bc, dt=1e-3, kappa=1.0)
+    f = I.cosine_modes(max(n), len(n), 16, np.random.default_rng(2))[tuple(slice(0, m) for m in P.shape())]
+    f = np.ascontiguousarray(f) + 0.01 * I.random_field(P.shape(), 9)
+    g64 = grid_for(P, np.float64, False)
+    g32 = grid_for(P, np.float32, False, mixed=True)
+    from paper_2510_11152_amd import solve_mixed
+    for rep in range(2):
+        ug = dev(f)
+        assert solve_mixed(g64, g32, dev(f), ug, P.dt, P.kappa, None, tol=1e-10, inner=inner,
+                           inner_next=inner_next) == 0
+        s = g64.stats()
+        check_mixed(P, f, f, host(ug), s["cycles"], 1e-10, inner=inner, gpu_hist=s["rel_res"][: s["cycles"] + 1],
+                    inner_next=inner_next)
+
+
 @pytest.mark.parametrize("n,bc", [((64, 64), "neumann"), ((32, 64), "dirichlet"), ((16, 16, 16), "periodic")])
 def test_kappa_grad_bitwise(n, bc):
     P = _problem(n, 4, bc)

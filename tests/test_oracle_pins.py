@@ -451,6 +451,29 @@ def test_mixed_precision_reaches_fp64_solution(variable):
     assert hist[-1] <= 1e-10
 
 
+def test_mixed_inner_schedule():
+    """inner_next equal to inner is the plain schedule bit for bit; fewer cycles after the
+    first correction still reach the FP64 solution, and one inner cycle per later
+    correction takes more corrections than two."""
+    n = 128
+    P = O.Problem(n=(n, n), h=1 / n, dt=1e-3, bc="neumann", coarsest=4)
+    f = I.heat_2d_small(n)
+    a, b = f.copy(), f.copy()
+    sa = O.solve_mixed(P, f, a, tol=1e-10, inner=3)
+    sb = O.solve_mixed(P, f, b, tol=1e-10, inner=3, inner_next=3)
+    assert np.array_equal(a, b) and sa[1] == sb[1]
+    ref = f.copy()
+    O.solve(P, f, ref, 1e-13)
+    outers = []
+    for nxt in (2, 1):
+        u = f.copy()
+        st, outer, hist = O.solve_mixed(P, f, u, tol=1e-10, inner=3, inner_next=nxt)
+        assert st == 0 and hist[-1] <= 1e-10
+        assert np.abs(u - ref).max() <= 1e-9 * np.abs(ref).max()
+        outers.append(outer)
+    assert outers[1] >= outers[0]
+
+
 # ---------------------------------------------------------------- grain-growth right-hand side
 def test_grain_rhs_is_the_free_energy_derivative():
     """f_i = eta_i - dt * d(free energy)/d eta_i: the closed-form derivative used by the
