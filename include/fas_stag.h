@@ -123,7 +123,9 @@ int fas_ns_set(fas_ns_t* ns, int option, double value);
 /* One step of size dt.  force_u / force_v: nforce device fields each (NULL if nforce = 0),
  * coef: nforce host doubles.  Each solve stops at h ||r||_2 <= tol or kmax cycles.
  * cycles_out[3] and res_out[3] (may be NULL): the u, v and p solves.  Returns FAS_OK,
- * FAS_NOT_CONVERGED (the step completed with a solve short of tol) or an error. */
+ * FAS_NOT_CONVERGED (the step completed with a solve short of tol) or an error; after
+ * FAS_ERR_NONFINITE (a solve's residual became NaN or Inf) the step stops there and the
+ * fields hold its intermediate state (u~, v~ or p~ partly solved, u^n, v^n, p^n intact). */
 int fas_ns_step(fas_ns_t* ns, double dt, double lid, int nforce, const void* const* force_u,
                 const void* const* force_v, const double* coef, double tol, int nu1, int nu2, int kmax,
                 int* cycles_out, double* res_out);
