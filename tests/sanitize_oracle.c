@@ -51,7 +51,7 @@ static int run(int dim, const long* n, int bc, int coarsest, int order, int symm
     rc |= og_vcycle_d(&P, kap, f, u, 1, 2, 1);
     rc |= og_solve_d(&P, kap, f, u, 1e-8, 2, 2, 40, 0, &cycles, hist) < 0;
     rc |= og_vcycle_s(&P, 0, f32, u32, 2, 2, 0);
-    rc |= og_solve_mixed(&P, kap, f, u, 1e-9, 2, 2, 2, 20, &cycles, hist) < 0;
+    rc |= og_solve_mixed(&P, kap, f, u, 1e-9, 2, 2, 3, 1, 20, &cycles, hist) < 0;
     if (cell) og_kappa_grad_d(&P, k, f, u, g);
     free(f);
     free(u);
