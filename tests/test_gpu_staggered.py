@@ -358,3 +358,34 @@ def test_step_reports_a_solve_short_of_tol():
     O.step(0.01, tol=1e-14, kmax=1)
     assert st == 1 and cyc == [1, 1, 1] and all(r > 1e-14 for r in res)
     _check_state(G, O)
+
+
+@pytest.mark.parametrize("loc,bc,code", LOCS)
+@pytest.mark.parametrize("fused", [1, 0])
+def test_smallest_grid_bitwise(loc, bc, code, fused):
+    """The smallest hierarchy (8 x 8 cells, two levels; the fused path runs it all in the
+    tail): V-cycles and a solve, bit for bit."""
+    say("smallest", loc, bc, fused)
+    S, P = _pair(loc, bc, code, 8, 8, fused=fused)
+    assert P.levels == 2
+    a, c = _coef(bc)
+    f, w = _inputs(P, 41, a == 0.0)
+    wd = dev(w)
+    for _ in range(3):
+        S.vcycle(a, c, dev(f), wd)
+        ost.vcycle(P, a, c, f, w)
+    assert np.array_equal(host(wd), w)
+    f, w = _inputs(P, 43, a == 0.0)
+    check_solve(S, P, a, c, f, w, 1e-11, kmax=40)
+
+
+def test_full_size_8192_ns_edge_vcycle_bitwise():
+    """One V(2,2) cycle of the NS-edge variable on an 8192^2 grid (67 M unknowns; its
+    restriction takes a row from the next wave), bit for bit."""
+    say("full-size 8192 edge_y vcycle")
+    S, P = _pair("edge_y", "dirichlet", ost.EDGE_Y, 8192, 8192)
+    f, w = _inputs(P, 47, False)
+    wd = dev(w)
+    S.vcycle(1.0, 0.025 / 10.0, dev(f), wd)
+    ost.vcycle(P, 1.0, 0.025 / 10.0, f, w)
+    assert np.array_equal(host(wd), w)
