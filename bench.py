@@ -74,6 +74,8 @@ def parse():
                     help="pre- and post-sweeps of the FP32 inner cycles of the 2D mixed form")
     ap.add_argument("--inner3d", type=int, default=4,
                     help="FP32 V-cycles per outer correction (3D mixed form; 4 reaches 1e-10 in two corrections)")
+    ap.add_argument("--march3-sweeps", type=int, default=2, choices=(1, 2),
+                    help="most sweeps per 3D plane-march pass (identical results)")
     ap.add_argument("--inner3d-next", type=int, default=0,
                     help="FP32 V-cycles in the 3D mixed form's corrections after the first (0: --inner3d)")
     ap.add_argument("--no-mixed", action="store_true")
@@ -331,7 +333,7 @@ def bench_adjoint(dev):
     return {"grid": [n, n], "steps": T, "ckpt": 4, "forward_backward_s": t, "loss": loss}
 
 
-def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0):
+def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0, march3_sweeps=2):
     """3D heat at 512^3 (7-point, 8-set X-MCGS, Neumann, dt = 1e-4): plain FP64 V(2,2)
     steps to 1e-10, then the same steps with FP32 inner cycles in FP64 correction."""
     import numpy as np
@@ -343,7 +345,7 @@ def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0):
     n, dt = 512, 1e-4
     u0_h = fas_inputs.heat_3d(n)
     u0 = torch.from_numpy(u0_h).to(dev)
-    g = Grid((n, n, n), 1.0 / n, coarsest=4, device=dev)
+    g = Grid((n, n, n), 1.0 / n, coarsest=4, device=dev).set(march3_sweeps=march3_sweeps)
     rhs = torch.empty_like(u0)
 
     def plain(u):
@@ -358,10 +360,13 @@ def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0):
     plain(u)
     u = u0.clone()
     t_plain, cyc = _timed(lambda: plain(u), torch.cuda.synchronize)
-    out = {"grid": [n, n, n], "steps": steps, "plain_s_per_step": t_plain / steps, "cycles_per_step": float(np.mean(cyc))}
+    out = {"grid": [n, n, n], "steps": steps, "plain_s_per_step": t_plain / steps, "cycles_per_step": float(np.mean(cyc)),
+           "march3_sweeps_per_pass": march3_sweeps}
     # finest-level plane-march passes of one more (untimed) step, HIP events around each
-    # class: pre = sweep pass + sweep/residual/restriction pass (3s + 3s + 2s/8 per cell),
-    # post = correction/sweep pass + sweep/norm pass (3s + s/8 + 3s), s = 8 B
+    # class.  Two sweeps per pass: pre = one sweeps/residual/restriction pass (3s + 2s/8 per
+    # cell), post = one correction/sweeps/norm pass (3s + s/8), s = 8 B; one sweep per pass:
+    # pre = sweep pass + sweep/residual/restriction pass (3s + 3s + 2s/8), post =
+    # correction/sweep pass + sweep/norm pass (3s + s/8 + 3s)
     g.set(profile=True)
     g.profile(reset=True)
     v = u.clone()
@@ -369,16 +374,18 @@ def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0):
     prof = g.profile(reset=True)
     g.set(profile=False)
     del v
-    bytes3 = {"pre": 8 * (6 + 2 / 8) * n ** 3, "post": 8 * (6 + 1 / 8) * n ** 3}
+    passes = 1 if march3_sweeps == 2 else 2
+    bytes3 = {"pre": 8 * (3 * passes + 2 / 8) * n ** 3, "post": 8 * (3 * passes + 1 / 8) * n ** 3}
     k3 = {}
     for k in ("pre", "post"):
         launches, ms = prof[k]
         if launches:
             gbs = bytes3[k] / (ms / 1e3 / launches) / 1e9
-            k3[k] = {"passes_per_launch": 2, "avg_us": ms * 1e3 / launches, "algorithmic_bytes": bytes3[k],
+            k3[k] = {"passes_per_launch": passes, "avg_us": ms * 1e3 / launches, "algorithmic_bytes": bytes3[k],
                      "gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
     out["finest_level_kernels"] = k3
-    g32 = Grid((n, n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev)
+    g32 = Grid((n, n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev).set(
+        march3_sweeps=march3_sweeps)
 
     def mixed(v):
         outer = []
@@ -829,7 +836,8 @@ def main():
         result["orders"] = bench_orders(dev)
     if "3d" in forms:
         print("bench: 3D heat", file=sys.stderr, flush=True)
-        result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline, inner_next=args.inner3d_next)
+        result["heat3d"] = bench_3d(dev, inner=args.inner3d, cpu=not args.no_cpu_baseline, inner_next=args.inner3d_next,
+                                    march3_sweeps=args.march3_sweeps)
     if "ns" in forms:
         print("bench: staggered projection step (4096^2)", file=sys.stderr, flush=True)
         result["ns"] = bench_ns(dev, dts=tuple(float(x) for x in args.ns_dts.split(",")),

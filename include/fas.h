@@ -112,6 +112,11 @@ extern "C" {
                                    every correction after the first (the first takes the
                                    inner_cycles argument, whose correction starts from the full
                                    residual); 0 (default): inner_cycles for all */
+#define FAS_OPT_MARCH3_SWEEPS 14 /* 1 or 2 (default): most sweeps one pass of the 3D plane
+                                   marches runs (constant kappa, levels from 64 x 32 x 16
+                                   up); with 2, V(2, 2) makes one pre- and one post-smoothing
+                                   pass per level instead of two each.  Results are
+                                   identical                                              */
 
 /* FAS_OPT_ORDER values.  A set is written by the parities of its cells' 1-based indices
  * along x, y (, z), o = odd, e = even:

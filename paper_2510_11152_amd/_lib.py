@@ -25,6 +25,7 @@ FAS_OPT_KMAX, FAS_OPT_COARSE_SWEEPS, FAS_OPT_FUSED, FAS_OPT_PROFILE = 1, 2, 3, 4
 FAS_OPT_GRAPH, FAS_OPT_AUTOTUNE, FAS_OPT_SEG_ROWS = 5, 6, 7
 FAS_OPT_TILE, FAS_OPT_TILE_WAVES = 8, 9
 FAS_OPT_ORDER, FAS_OPT_SYMMETRIC, FAS_OPT_ATOL, FAS_OPT_MIXED_INNER_NEXT = 10, 11, 12, 13
+FAS_OPT_MARCH3_SWEEPS = 14
 FAS_ORDER = {"x": 0, "u": 1, "z": 2}
 FAS_K_NAMES = ("smooth", "pre", "post", "norm")
 FAS_LOC = {"cell": 0, "edge_x": 1, "edge_y": 2}

@@ -67,10 +67,11 @@ class Grid:
         return tuple(m >> level for m in reversed(self.n))
 
     def set(self, kmax=None, coarse_sweeps=None, fused=None, profile=None, graph=None, autotune=None,
-            seg_rows=None, tile=None, tile_waves=None, order=None, symmetric=None, atol=None):
+            seg_rows=None, tile=None, tile_waves=None, order=None, symmetric=None, atol=None, march3_sweeps=None):
         """Solver options (fas_grid_set).  order: smoother set order 'x' (default), 'u' or
         'z'; symmetric: every second sweep in reverse set order (1234-4321); atol: a solve
-        also stops once ||rhs - A u||_2 <= atol (0: none)."""
+        also stops once ||rhs - A u||_2 <= atol (0: none); march3_sweeps: most sweeps per
+        3D plane-march pass (1 or 2, the default; identical results)."""
         L = load()
         if kmax is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_KMAX, float(kmax)), "fas_grid_set")
@@ -96,6 +97,8 @@ class Grid:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_SYMMETRIC, float(int(symmetric))), "fas_grid_set")
         if atol is not None:
             check(L.fas_grid_set(self.handle, _lib.FAS_OPT_ATOL, float(atol)), "fas_grid_set")
+        if march3_sweeps is not None:
+            check(L.fas_grid_set(self.handle, _lib.FAS_OPT_MARCH3_SWEEPS, float(march3_sweeps)), "fas_grid_set")
         return self
 
     def profile(self, reset=True):

@@ -127,11 +127,14 @@ int plan(int dim, const int64_t n[3], int dtype, int coarsest, int flags, int ba
         lay->mix_r = off;
         off = align_up(off + N0 * s);
     }
-    // one partial sum per fused tile (3D tiles are at least 64 x 32 x 32 cells), per 2D
-    // march wave (kStripCols x kMinSegRows cells at least) or per block of the
-    // stand-alone norm kernel
+    // one partial sum per fused tile (3D tiles write at least 52 x 20 cells of a plane,
+    // segments of 64 planes, 32 when the grid is small), per 2D march wave (kStripCols x
+    // kMinSegRows cells at least) or per block of the stand-alone norm kernel
     int64_t tiles = 1;
-    for (int a = 0; a < dim; ++a) tiles *= (n[a] + (a == 0 ? 63 : 31)) / (a == 0 ? 64 : 32);
+    if (dim == 3)
+        tiles = ((n[0] + 51) / 52) * ((n[1] + 19) / 20) * ((n[2] + 31) / 32);
+    else
+        for (int a = 0; a < dim; ++a) tiles *= (n[a] + (a == 0 ? 63 : 31)) / (a == 0 ? 64 : 32);
     if (dim == 2) {
         const int64_t waves = ((n[0] + fas::kStripCols - 1) / fas::kStripCols) *
                               ((n[1] + fas::kMinSegRows - 1) / fas::kMinSegRows);
@@ -334,6 +337,30 @@ void autotune_tile(fas_grid* g, int l, int first, int pre, int post, const void*
 // Whether coarse level lc forms its FAS right-hand side inside its first march pass (2D
 // strips or 3D planes); the finer level then leaves R(f - A u) in lev[lc].r (the pass
 // reads it while writing f, so it cannot be f itself).
+// Sweeps of each 3D march pass of one smoothing step of nu sweeps, in order: up to
+// march3_ns each.  pre: the step ends with the residual-restriction pass, which takes the
+// full count, the passes before it split the rest; post: the correction pass comes first
+// and takes the full count.  form (pre, nu >= 2): the first pass forms the right-hand
+// side, which the one-sweep kernel does.
+std::vector<int> march3_split(const fas_grid* g, int nu, bool form, bool pre)
+{
+    if (nu < 1 || (form && (!pre || nu < 2))) throw Error(FAS_ERR_ARG, "internal: 3D march pass split");
+    const int m = g->march3_ns;
+    std::vector<int> ns;
+    int rem = nu;
+    if (form) ns.push_back(1), --rem;
+    const int end = std::min(m, rem);  // the restriction pass (pre) / the correction pass (post)
+    rem -= end;
+    if (!pre) ns.push_back(end);
+    while (rem > 0) {
+        const int k = std::min(m, rem);
+        ns.push_back(k);
+        rem -= k;
+    }
+    if (pre) ns.push_back(end);
+    return ns;
+}
+
 bool rhs_in_pre(const fas_grid* g, int lc, int pre, int post)
 {
     if (lc < 1 || lc > g->L || !g->lev[lc].r || !g->fused || lc == fas::tail_top(g)) return false;
@@ -386,36 +413,42 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         return 0;
     }
     if (fas::fused3_ok(g, l, g->lev[l].kap != nullptr) && pre >= 1 && post >= 1) {
-        // 3D: one sweep per pass, ping-pong between u and the level's second buffer; with
-        // rc_in the first pass reads it and forms f (= lev[l].f) for the passes after it
+        // 3D: passes of up to march3_ns sweeps, ping-pong between u and the level's second
+        // buffer; with rc_in the first pass sweeps once, reading it and forming f
+        // (= lev[l].f) for the passes after it
+        const std::vector<int> pre_ns = march3_split(g, pre, rc_in != nullptr, true);
+        const std::vector<int> post_ns = march3_split(g, post, false, false);
+        const int npre = (int)pre_ns.size(), npost = (int)post_ns.size();
+        const int norm_ns = post_ns.back();
         void* bufs[2] = {u, g->lev[l].x};
         int cur = 0;
-        autotune_level(g, l, first, pre, post, f, u);  // times the sweep-residual-restriction pass
-        if (partials && fas::fused3_partials(g, l) > g->npartials / g->batch) partials = nullptr;
+        autotune_level(g, l, first, pre, post, f, u, rc_in);  // times the sweep-residual-restriction pass
+        if (partials && fas::fused3_partials(g, l, norm_ns) > g->npartials / g->batch) partials = nullptr;
         void* const rcd = rc_dst(g, l, pre, post);
         {
             ProfScope ps(g, l, FAS_K_PRE);
-            for (int i = 0; i < pre - 1; ++i, cur ^= 1) {
+            for (int i = 0; i < npre - 1; ++i, cur ^= 1) {
                 const bool form = rc_in && i == 0;
-                fas::launch_march3(g, l, g->coef[l], first, 2, 1, false, form ? rc_in : f, bufs[cur], bufs[cur ^ 1],
-                                   nullptr, nullptr, nullptr, form ? g->lev[l].f : nullptr);
+                fas::launch_march3(g, l, g->coef[l], first, 2, pre_ns[i], false, form ? rc_in : f, bufs[cur],
+                                   bufs[cur ^ 1], nullptr, nullptr, nullptr, form ? g->lev[l].f : nullptr);
             }
-            fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, bufs[cur], bufs[cur ^ 1], C.u, rcd, nullptr);
+            fas::launch_march3(g, l, g->coef[l], first, 0, pre_ns[npre - 1], false, f, bufs[cur], bufs[cur ^ 1], C.u,
+                               rcd, nullptr);
             cur ^= 1;
             ps.end();
         }
         coarse_part(g, l, pre, post, rev);
         {
             ProfScope ps(g, l, FAS_K_POST);
-            for (int i = 0; i < post; ++i, cur ^= 1)
-                fas::launch_march3(g, l, g->coef[l], first, i == 0 ? 1 : 2, 1, partials && i == post - 1, f, bufs[cur],
-                                   bufs[cur ^ 1], i == 0 ? C.u : nullptr, nullptr, partials);
+            for (int i = 0; i < npost; ++i, cur ^= 1)
+                fas::launch_march3(g, l, g->coef[l], first, i == 0 ? 1 : 2, post_ns[i], partials && i == npost - 1, f,
+                                   bufs[cur], bufs[cur ^ 1], i == 0 ? C.u : nullptr, nullptr, partials);
             ps.end();
         }
         if (cur != 0)
             FAS_HIP_CHECK(hipMemcpyAsync(u, bufs[1], (size_t)g->lev[l].N * g->elem() * g->batch, hipMemcpyDeviceToDevice,
                                          g->stream));
-        return partials ? fas::fused3_partials(g, l) : 0;
+        return partials ? fas::fused3_partials(g, l, norm_ns) : 0;
     }
     if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
         void* x = g->lev[l].x;
@@ -529,8 +562,8 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
     if (!g->autotune || g->seg_force || g->seg_rows[l]) return;
     const bool d3 = g->dim == 3;
     char key[160];
-    snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->lev[l].n[2],
-             g->dtype, g->batch, pre, post, rc_in ? 1 : 0);
+    snprintf(key, sizeof key, "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d", g->dim, g->lev[l].n[0], g->lev[l].n[1], g->lev[l].n[2],
+             g->dtype, g->batch, pre, post, rc_in ? 1 : 0, d3 ? g->march3_ns : 0);
     {
         std::lock_guard<std::mutex> lock(tune_mutex());
         auto it = tune_cache().find(key);
@@ -563,8 +596,8 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
         for (int rep = 0; rep < 3; ++rep) {
             FAS_HIP_CHECK(hipEventRecord(e0, g->stream));
             if (d3)
-                fas::launch_march3(g, l, g->coef[l], first, 0, 1, false, f, u, g->lev[l].x, C.u, rc_dst(g, l, pre, post),
-                                   nullptr);
+                fas::launch_march3(g, l, g->coef[l], first, 0, march3_split(g, pre, rc_in != nullptr, true).back(), false, f, u,
+                                   g->lev[l].x, C.u, rc_dst(g, l, pre, post), nullptr);
             else if (rc_in)
                 fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, g->lev[l].x, C.u,
                                       rc_dst(g, l, pre, post), g->lev[l].f);
@@ -1127,6 +1160,7 @@ int setup_grid(fas_grid* g, int dim, const int64_t n[3], double h, int bc, int d
     g->symmetric = 0;
     g->tile_max = INT64_MAX;
     g->tile_waves = 0;
+    g->march3_ns = 2;
     g->host = nullptr;  // pinned scalar for norm read-back, allocated on first use
     return FAS_OK;
 }
@@ -1615,6 +1649,10 @@ int fas_grid_set(fas_grid_t g, int option, double value)
             case FAS_OPT_TILE_WAVES:
                 if (v != 0 && (v < 6 || v > 16)) return fail(FAS_ERR_ARG, "tile waves must be 0 or 6..16");
                 g->tile_waves = v;
+                return FAS_OK;
+            case FAS_OPT_MARCH3_SWEEPS:
+                if (v != 1 && v != 2) return fail(FAS_ERR_ARG, "3D march sweeps per pass must be 1 or 2");
+                g->march3_ns = v;
                 return FAS_OK;
         }
         return fail(FAS_ERR_ARG, "unknown option");

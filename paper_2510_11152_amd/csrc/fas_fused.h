@@ -62,14 +62,14 @@ void launch_tile_pre(const fas_grid* g, int l, const Coef& c, int first, int nu,
 void launch_tile_post(const fas_grid* g, int l, const Coef& c, int first, int nu, const void* f, const void* u_in,
                       const void* uc, void* u_out, double* partials, double* u64 = nullptr);
 
-// 3D plane-march kernels (kernels_fused3d.hip): one sweep per pass.
+// 3D plane-march kernels (kernels_fused3d.hip): one or two sweeps per pass.
 bool fused3_ok(const fas_grid* g, int l, bool variable);
-// Norm partial sums one pass with a norm leaves per problem on level l.
-int fused3_partials(const fas_grid* g, int l);
-// mode 0: sweep, then uc = R u_out, rc = R(f - A u_out); mode 1: u_in + P(uc - R u_in),
-// then a sweep; mode 2: a sweep.  ns = sweeps in the pass (1).  norm: per-block sums of
-// r^2 (r = f - A u_out) into partials.  fout != nullptr (mode 2, no norm): f holds
-// r = R(f_fine - A_fine u_fine) and the pass first forms f = r + A u_in into fout.
+// Norm partial sums that a pass of ns sweeps with a norm leaves per problem on level l.
+int fused3_partials(const fas_grid* g, int l, int ns);
+// mode 0: sweeps, then uc = R u_out, rc = R(f - A u_out); mode 1: u_in + P(uc - R u_in),
+// then the sweeps; mode 2: the sweeps.  ns = sweeps in the pass (1 or 2).  norm: per-block
+// sums of r^2 (r = f - A u_out) into partials.  fout != nullptr (mode 2, ns 1, no norm): f
+// holds r = R(f_fine - A_fine u_fine) and the pass first forms f = r + A u_in into fout.
 void launch_march3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
                    const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout = nullptr);
 

@@ -100,6 +100,7 @@ struct fas_grid {
     int cus;                        // compute units of the device (0: not queried yet)
     int64_t tile_max;               // FAS_OPT_TILE: largest 2D level (cells) run as block tiles
     int tile_waves;                 // FAS_OPT_TILE_WAVES: waves per tile block (0: rule)
+    int march3_ns;                  // FAS_OPT_MARCH3_SWEEPS: most sweeps per 3D march pass
     int tile_wv[fas::kMaxLevels];   // FAS_OPT_AUTOTUNE: tuned waves per tile block (0: rule)
     int tile_grp[fas::kMaxLevels];  // FAS_OPT_AUTOTUNE: tuned strips per tile group (0: rule)
     int gate;                       // a solve is running its cycle loop: kernels of a single

@@ -1,18 +1,19 @@
-// Fused 3D plane-march kernels for large levels (constant kappa): one X-MCGS sweep
-// (both colour phases, Appendix B sets 1-4 then 5-8) per pass, fused with the residual
-// and restriction, or with the prolongation correction, or with the residual norm.
+// Fused 3D plane-march kernels for large levels (constant kappa): one or two X-MCGS
+// sweeps (each both colour phases, Appendix B sets 1-4 then 5-8) per pass, fused with the
+// residual and restriction, or with the prolongation correction, or with the residual norm.
 //
 // Geometry.  A 1024-thread block owns an x-y tile of 64 x 32 cells (thread (px, py) holds
 // the cell pair 2px, 2px+1 of row py) and marches along z through a segment of planes,
 // keeping a ring of planes in registers.  x-neighbours come from the adjacent lane by a
 // DPP shift (a wavefront holds two tile rows; the lanes where the shift crosses a row are
 // halo columns), y-neighbours through a double-buffered LDS exchange (one barrier per
-// plane), z-neighbours from the ring.  Phase s = 1, 2 updates plane t - s - LAG when plane
-// t arrives; the residual follows on plane t - 3 - LAG.  A halo of H cells on each side
-// of the tile and H planes above the segment are recomputed (neighbouring tiles overlap):
-// H = 2 covers the two phases of a sweep, a pass that also takes the residual needs
-// H = 4 (three cells, rounded up to keep 2 x 2 x 2 blocks aligned).  Point formulas are
-// those of fas_device.h.
+// plane), z-neighbours from the ring.  Phase s = 1 .. S (S = 2 per sweep) updates plane
+// t - s - LAG when plane t arrives; the residual follows on plane t - S - 1 - LAG.  A halo
+// of H cells on each side of the tile and H planes below the segment are recomputed
+// (neighbouring tiles overlap): each phase reaches one cell further, so H = S covers the
+// phases, and a pass that also takes the residual needs S + 1, rounded up to even to keep
+// 2 x 2 x 2 blocks aligned (one sweep: H = 2 or 4; two sweeps: 4 or 6).  Point formulas
+// are those of fas_device.h.
 //
 // Modes: 0 = sweep + residual + restriction (u_c = R u, r_c = R r);
 //        1 = correction u += P(u_c - R u) + sweep;  2 = sweep only.
@@ -104,28 +105,36 @@ __device__ __forceinline__ T pick_q3(const March3Args<T>& a, int W)
     return v;
 }
 
-// halo of a pass: even, >= the phases' reach, +1 when the residual is taken
-constexpr int halo3(int ns, int mode, bool norm) { return ns && (mode == 0 || norm) ? 4 : 2; }
+// halo of a pass: even, >= the phases' reach (one cell per phase), +1 when the residual
+// is taken
+constexpr int halo3(int ns, int mode, bool norm)
+{
+    return (2 * ns + ((mode == 0 || norm) ? 1 : 0) + 1) & ~1;
+}
 
-template <int NS, int MODE, bool NORM, bool RHS>
+template <typename T, int NS, int MODE, bool NORM, bool RHS>
 struct Geom3 {
     static constexpr int S = 2 * NS;            // colour phases in the pass
     static constexpr int H = halo3(NS, MODE, NORM);
     static constexpr bool RES = MODE == 0 || NORM;  // residual of the final plane
     // the correction (mode 1) and the right-hand side (RHS) need the plane below untouched
     static constexpr int LAG = (MODE == 1 || RHS) ? 1 : 0;
-    static constexpr int PF = 2;                // planes loaded ahead
-    static constexpr int RING = 8;              // >= S + 3 + LAG + PF, even
+    // planes loaded ahead: one for two FP64 sweeps, whose ring of planes fills the 128
+    // VGPRs of a 1024-lane block (with two, the FP64 two-sweep passes spill)
+    static constexpr int PF = (NS == 2 && sizeof(T) == 8) ? 1 : 2;
+    static constexpr int RING = (S + 3 + LAG + PF + 1) & ~1;  // planes held: >= S + 3 + LAG + PF, even
+    static constexpr int SLOTS = S + 4;         // LDS exchange slots per buffer
     static constexpr int UX = kWX - 2 * H;      // cells written per tile in x
     static constexpr int UY = kTPY - 2 * H;     // rows written per tile
 };
 
-// LDS exchange area: two buffers of 4 slots (phase 1 value, phase 2 value, residual even,
-// residual odd) plus 2 correction slots, then 4 single-buffered restriction slots.
-template <typename T>
+// LDS exchange area: two buffers of S + 4 slots: one per colour phase, residual even and
+// odd, and two for the correction pair sums (mode 1) or the initial values (RHS).  The
+// restriction of mode 0 (which uses neither) takes those last two slots of both buffers;
+// the norm reduction reuses the area after the march.
+template <typename T, int SLOTS>
 struct Xchg {
-    T buf[2][6][kThreads3];
-    T rs[4][kThreads3];
+    T buf[2][SLOTS][kThreads3];
 };
 
 // Per-problem arrays of a batched launch (the kernel arguments stay in place).
@@ -140,10 +149,11 @@ struct Arrays3 {
 };
 
 template <typename T, int NS, int MODE, bool NORM, bool RHS, bool EDGE, int FIRST>
-__device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> A, Xchg<T>& X, int tx, int ty, int seg,
+__device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> A,
+                                       Xchg<T, Geom3<T, NS, MODE, NORM, RHS>::SLOTS>& X, int tx, int ty, int seg,
                                        double* red)
 {
-    using G = Geom3<NS, MODE, NORM, RHS>;
+    using G = Geom3<T, NS, MODE, NORM, RHS>;
     using V = typename Pair3<T>::V;
     static_assert(!RHS || MODE == 2, "the right-hand side is formed by a level's first, sweep-only pass");
     constexpr int S = G::S, H = G::H, RING = G::RING, PF = G::PF, LAG = G::LAG;
@@ -252,12 +262,10 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
             const int rho = rb + j;
             load_plane(min(rho + PF, nsteps - 1), (j + PF) % RING, ((j + PF) & 1) != 0);
             constexpr int sh = 4 * RING;
-            T* B0 = X.buf[j & 1][0];
-            T* B1 = X.buf[j & 1][1];
-            T* B2 = X.buf[j & 1][2];
-            T* B3 = X.buf[j & 1][3];
-            T* B4 = X.buf[j & 1][4];
-            T* B5 = X.buf[j & 1][5];
+            T* B2 = X.buf[j & 1][S];      // residual: even / odd cells of the final plane
+            T* B3 = X.buf[j & 1][S + 1];
+            T* B4 = X.buf[j & 1][S + 2];  // correction pair sums / initial values (RHS)
+            T* B5 = X.buf[j & 1][S + 3];
             // publish the values the neighbouring rows read in this step
             // (colour of a cell: (x + y + z) parity with x, y, z local; all origins even)
 #pragma unroll
@@ -266,7 +274,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                 const int colour = ((s - 1) & 1) ^ FIRST;
                 // the other colour's cell of this pair in plane rho - s - LAG
                 const bool other_even = (((py + j - s - LAG + sh) & 1) ^ (1 - colour)) == 0;
-                (s == 1 ? B0 : B1)[tid] = other_even ? ue[a0] : uo[a0];
+                X.buf[j & 1][s - 1][tid] = other_even ? ue[a0] : uo[a0];
             }
             if constexpr (G::RES) {
                 const int a0 = (j - S - 1 - LAG + sh) % RING;
@@ -342,7 +350,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                 const int am = (j - s - LAG - 1 + sh) % RING;
                 const int ap = (j - s - LAG + 1 + sh) % RING;
                 const int colour = ((s - 1) & 1) ^ FIRST;
-                const T* Bs = s == 1 ? B0 : B1;
+                const T* Bs = X.buf[j & 1][s - 1];
                 const bool even_cell = (((py + j - s - LAG + sh) & 1) ^ colour) == 0;
                 const bool zb = zbound(gz);
                 if (even_cell) {
@@ -394,16 +402,20 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                         const T sr = re + ro;
                         // planes (r - 1, r) form coarse plane graw / 2 when r is odd
                         if (((j - S - 1 - LAG + sh) & 1) && graw - 1 >= z0 && inseg) {
-                            X.rs[0][tid] = su_prev;
-                            X.rs[1][tid] = sr_prev;
-                            X.rs[2][tid] = su;
-                            X.rs[3][tid] = sr;
+                            T* R0 = X.buf[0][S + 2];  // slots mode 0 leaves unused
+                            T* R1 = X.buf[0][S + 3];
+                            T* R2 = X.buf[1][S + 2];
+                            T* R3 = X.buf[1][S + 3];
+                            R0[tid] = su_prev;
+                            R1[tid] = sr_prev;
+                            R2[tid] = su;
+                            R3[tid] = sr;
                             __syncthreads();
                             const int pr = tid ^ kTPX;
                             if ((py & 1) == 0 && own) {
                                 // children summed along x (pair), then y (rows), then z
-                                const T ucv = ((X.rs[0][tid] + X.rs[0][pr]) + (X.rs[2][tid] + X.rs[2][pr])) * (T)0.125;
-                                const T rcv = ((X.rs[1][tid] + X.rs[1][pr]) + (X.rs[3][tid] + X.rs[3][pr])) * (T)0.125;
+                                const T ucv = ((R0[tid] + R0[pr]) + (R2[tid] + R2[pr])) * (T)0.125;
+                                const T rcv = ((R1[tid] + R1[pr]) + (R3[tid] + R3[pr])) * (T)0.125;
                                 const int64_t P = (int64_t)(graw >> 1) * cplane + (int64_t)(gy0 >> 1) * mc0 + (gxe >> 1);
                                 __builtin_nontemporal_store(ucv, A.uc + P);
                                 __builtin_nontemporal_store(rcv, A.rc + P);
@@ -417,6 +429,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
         }
     }
     if constexpr (NORM) {
+        __syncthreads();  // red aliases the exchange area
         red[tid] = acc;
         __syncthreads();
         for (int s = kThreads3 / 2; s > 0; s >>= 1) {
@@ -429,9 +442,10 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
 template <typename T, int NS, int MODE, bool NORM, bool RHS>
 __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first)
 {
-    using G = Geom3<NS, MODE, NORM, RHS>;
-    __shared__ Xchg<T> X;
-    __shared__ double red[NORM ? kThreads3 : 1];
+    using G = Geom3<T, NS, MODE, NORM, RHS>;
+    static_assert(sizeof(Xchg<T, G::SLOTS>) >= kThreads3 * sizeof(double), "norm reduction fits the exchange area");
+    __shared__ Xchg<T, G::SLOTS> X;
+    double* red = reinterpret_cast<double*>(&X.buf[0][0][0]);
     // (dispatch order, tile x fastest: the blocks resident at one time cover one z-segment
     // of neighbouring tiles across all XCDs; an XCD-contiguous renumbering measured slower)
     const int per = a.tiles_x * a.tiles_y * a.segs;
@@ -516,18 +530,19 @@ void dispatch3(const fas_grid* g, int l, const Coef& c, int first, int mode, int
     a.rc = (T*)rc;
     a.partials = partials;
     a.fout = (T*)fout;
-    if (ns != 1) throw Error(FAS_ERR_ARG, "3D march kernels run one sweep per pass");
-    if (fout && (mode != 2 || norm)) throw Error(FAS_ERR_ARG, "internal: right-hand side formed by a sweep-only pass");
+    if (ns != 1 && ns != 2) throw Error(FAS_ERR_ARG, "internal: 3D march kernels run one or two sweeps per pass");
+    if (fout && (mode != 2 || norm || ns != 1))
+        throw Error(FAS_ERR_ARG, "internal: right-hand side formed by a one-sweep, sweep-only pass");
     if (fout) {
         go3<T, 1, 2, false, true>(g, a, first);
-    } else if (mode == 0) {
-        go3<T, 1, 0, false>(g, a, first);
-    } else if (mode == 1) {
-        if (norm) go3<T, 1, 1, true>(g, a, first);
-        else go3<T, 1, 1, false>(g, a, first);
+    } else if (ns == 1) {
+        if (mode == 0) go3<T, 1, 0, false>(g, a, first);
+        else if (mode == 1) norm ? go3<T, 1, 1, true>(g, a, first) : go3<T, 1, 1, false>(g, a, first);
+        else norm ? go3<T, 1, 2, true>(g, a, first) : go3<T, 1, 2, false>(g, a, first);
     } else {
-        if (norm) go3<T, 1, 2, true>(g, a, first);
-        else go3<T, 1, 2, false>(g, a, first);
+        if (mode == 0) go3<T, 2, 0, false>(g, a, first);
+        else if (mode == 1) norm ? go3<T, 2, 1, true>(g, a, first) : go3<T, 2, 1, false>(g, a, first);
+        else norm ? go3<T, 2, 2, true>(g, a, first) : go3<T, 2, 2, false>(g, a, first);
     }
     check_launch3();
 }
@@ -540,9 +555,9 @@ bool fused3_ok(const fas_grid* g, int l, bool variable)
     return g->lev[l].n[0] >= 64 && g->lev[l].n[1] >= 32 && g->lev[l].n[2] >= 16;
 }
 
-int fused3_partials(const fas_grid* g, int l)
+int fused3_partials(const fas_grid* g, int l, int ns)
 {
-    const March3Args<double> a = make_args3<double>(g, l, g->coef[l], 1, 2, true);
+    const March3Args<double> a = make_args3<double>(g, l, g->coef[l], ns, 2, true);
     return a.tiles_x * a.tiles_y * a.segs;
 }
 

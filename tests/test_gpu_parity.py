@@ -302,13 +302,14 @@ def test_solve_reports_not_converged_and_is_deterministic():
 @pytest.mark.parametrize("n,bc", [((64, 64, 64), "neumann"), ((128, 64, 32), "dirichlet"), ((64, 64, 64), "periodic"),
                                   ((96, 64, 32), "neumann")])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("nu", [(2, 2), (1, 1), (2, 1), (1, 3)])
-def test_vcycle_3d_plane_march_bitwise(n, bc, dtype, nu):
+@pytest.mark.parametrize("nu", [(2, 2), (1, 1), (2, 1), (1, 3), (3, 2), (4, 4)])
+@pytest.mark.parametrize("sweeps", [2, 1])
+def test_vcycle_3d_plane_march_bitwise(n, bc, dtype, nu, sweeps):
     """3D grids large enough for the plane-march kernels (tiles with interior and
-    boundary tiles, ragged tiles, an odd number of passes): V-cycles equal the oracle's
-    bits and the library's own one-phase-per-launch path."""
+    boundary tiles, ragged tiles, an odd number of passes, one or two sweeps per pass):
+    V-cycles equal the oracle's bits and the library's own one-phase-per-launch path."""
     P = _problem(n, 4, bc, dt=2e-4, kappa=1.0, nuc=2)
-    g = grid_for(P, dtype)
+    g = grid_for(P, dtype).set(march3_sweeps=sweeps)
     gb = grid_for(P, dtype).set(fused=False)
     f = I.random_field(P.shape(), 18).astype(dtype)
     u = I.random_field(P.shape(), 19).astype(dtype)
@@ -433,6 +434,16 @@ def test_tile_options_are_checked():
     g.set(tile=0, tile_waves=0)
 
 
+def test_march3_sweeps_option_is_checked():
+    from paper_2510_11152_amd import Grid
+    from paper_2510_11152_amd._lib import FasError
+    g = Grid((64, 64, 64), 1 / 64)
+    for bad in (0, 3, -1, 1.5):
+        with pytest.raises(FasError):
+            g.set(march3_sweeps=bad)
+    g.set(march3_sweeps=1).set(march3_sweeps=2)
+
+
 def test_segment_height_option_is_checked():
     from paper_2510_11152_amd import Grid
     from paper_2510_11152_amd._lib import FasError
@@ -519,6 +530,9 @@ def test_full_size_512cube_vcycle_matches_oracle():
     fg = dev(f)
     ug = fg.clone()
     rel = grid_for(P, np.float64).vcycle(fg, ug, P.dt, nu1=2, nu2=2, with_residual=True)
+    assert np.array_equal(host(ug), uo)
+    ug.copy_(fg)  # the same cycle with one sweep per plane-march pass
+    grid_for(P, np.float64).set(march3_sweeps=1).vcycle(fg, ug, P.dt, nu1=2, nu2=2)
     assert np.array_equal(host(ug), uo)
     del ug, fg
     torch.cuda.empty_cache()
