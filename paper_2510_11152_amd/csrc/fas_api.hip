@@ -329,7 +329,7 @@ void smooth(fas_grid* g, int l, const void* f, void* u, int sweeps, bool reverse
 // rc_in (level >= 1, march levels only): the restricted residual from which the first pass
 // forms f itself.
 void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
-                    const void* rc_in = nullptr);
+                    const void* rc_in = nullptr, void* scratch = nullptr);
 
 void autotune_tile(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
                    const void* rc_in);
@@ -368,6 +368,16 @@ bool rhs_in_pre(const fas_grid* g, int lc, int pre, int post)
     // 3D: formed by the first sweep-only pass, so the level needs two pre-sweeps (the
     // sweep-residual-restriction pass has no registers to spare for it)
     return fas::fused_ok(g, lc, pre, post, kv) || (fas::fused3_ok(g, lc, kv) && pre >= 2 && post >= 1);
+}
+
+// Whether coarse level lc runs its 3D march passes from the level's second buffer: a level
+// whose passes form the right-hand side takes an odd number of passes when the post
+// passes are one fewer than the pre passes; the finer level then leaves the restricted
+// iterate in lev[lc].x, so that the last pass ends in lev[lc].u and no copy is needed.
+bool march3_from_x(const fas_grid* g, int lc, int pre, int post)
+{
+    if (!rhs_in_pre(g, lc, pre, post) || !fas::fused3_ok(g, lc, g->lev[lc].kap != nullptr) || post < 1) return false;
+    return (march3_split(g, pre, true, true).size() + march3_split(g, post, false, false).size()) % 2 == 1;
 }
 
 // Where level l leaves the restricted residual for level l + 1.
@@ -420,11 +430,15 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         const std::vector<int> post_ns = march3_split(g, post, false, false);
         const int npre = (int)pre_ns.size(), npost = (int)post_ns.size();
         const int norm_ns = post_ns.back();
-        void* bufs[2] = {u, g->lev[l].x};
+        // the iterate starts in the second buffer when the finer level left it there
+        const bool from_x = rc_in && march3_from_x(g, l, pre, post);
+        void* bufs[2] = {from_x ? g->lev[l].x : u, from_x ? u : g->lev[l].x};
         int cur = 0;
-        autotune_level(g, l, first, pre, post, f, u, rc_in);  // times the sweep-residual-restriction pass
+        // times the sweep-residual-restriction pass (input bufs[0], output bufs[1])
+        autotune_level(g, l, first, pre, post, f, bufs[0], rc_in, bufs[1]);
         if (partials && fas::fused3_partials(g, l, norm_ns) > g->npartials / g->batch) partials = nullptr;
         void* const rcd = rc_dst(g, l, pre, post);
+        void* const ucd = march3_from_x(g, l + 1, pre, post) ? C.x : C.u;
         {
             ProfScope ps(g, l, FAS_K_PRE);
             for (int i = 0; i < npre - 1; ++i, cur ^= 1) {
@@ -432,7 +446,7 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
                 fas::launch_march3(g, l, g->coef[l], first, 2, pre_ns[i], false, form ? rc_in : f, bufs[cur],
                                    bufs[cur ^ 1], nullptr, nullptr, nullptr, form ? g->lev[l].f : nullptr);
             }
-            fas::launch_march3(g, l, g->coef[l], first, 0, pre_ns[npre - 1], false, f, bufs[cur], bufs[cur ^ 1], C.u,
+            fas::launch_march3(g, l, g->coef[l], first, 0, pre_ns[npre - 1], false, f, bufs[cur], bufs[cur ^ 1], ucd,
                                rcd, nullptr);
             cur ^= 1;
             ps.end();
@@ -445,9 +459,9 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
                                    bufs[cur], bufs[cur ^ 1], i == 0 ? C.u : nullptr, nullptr, partials);
             ps.end();
         }
-        if (cur != 0)
-            FAS_HIP_CHECK(hipMemcpyAsync(u, bufs[1], (size_t)g->lev[l].N * g->elem() * g->batch, hipMemcpyDeviceToDevice,
-                                         g->stream));
+        if (bufs[cur] != u)
+            FAS_HIP_CHECK(hipMemcpyAsync(u, bufs[cur], (size_t)g->lev[l].N * g->elem() * g->batch,
+                                         hipMemcpyDeviceToDevice, g->stream));
         return partials ? fas::fused3_partials(g, l, norm_ns) : 0;
     }
     if (fas::fused_ok(g, l, pre, post, g->lev[l].kap != nullptr)) {
@@ -557,8 +571,10 @@ std::map<std::string, int>& tune_cache()
 }
 
 void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void* f, const void* u,
-                    const void* rc_in)
+                    const void* rc_in, void* scratch)
 {
+    // the timed passes read u and write scratch (default: the level's second buffer)
+    if (!scratch) scratch = g->lev[l].x;
     if (!g->autotune || g->seg_force || g->seg_rows[l]) return;
     const bool d3 = g->dim == 3;
     char key[160];
@@ -597,12 +613,12 @@ void autotune_level(fas_grid* g, int l, int first, int pre, int post, const void
             FAS_HIP_CHECK(hipEventRecord(e0, g->stream));
             if (d3)
                 fas::launch_march3(g, l, g->coef[l], first, 0, march3_split(g, pre, rc_in != nullptr, true).back(), false, f, u,
-                                   g->lev[l].x, C.u, rc_dst(g, l, pre, post), nullptr);
+                                   scratch, C.u, rc_dst(g, l, pre, post), nullptr);
             else if (rc_in)
-                fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, g->lev[l].x, C.u,
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, rc_in, u, scratch, C.u,
                                       rc_dst(g, l, pre, post), g->lev[l].f);
             else
-                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, g->lev[l].x, C.u, rc_dst(g, l, pre, post));
+                fas::launch_fused_pre(g, l, g->coef[l], first, pre, f, u, scratch, C.u, rc_dst(g, l, pre, post));
             FAS_HIP_CHECK(hipEventRecord(e1, g->stream));
             FAS_HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0.f;

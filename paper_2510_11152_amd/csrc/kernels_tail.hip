@@ -34,10 +34,19 @@ struct TailArgs {
     const int* act;           // per-problem active flags (nullable)
 };
 
-// Cells are visited row by row: the 1024 threads form kTX columns by kTailThreads / kTX
-// rows (x fastest), so no thread divides by a level size.
+// Cells are visited row by row: the 1024 threads form TX columns by kTailThreads / TX
+// rows (x fastest), TX the smallest power of two >= the row's work items (at most 32), so
+// narrow levels keep every lane busy and no thread divides by a level size.
 constexpr int kTX = 32;
-constexpr int kTY = kTailThreads / kTX;
+struct TMap {
+    int tx, ty, TX, TY;
+};
+__device__ __forceinline__ TMap tmap(int width)
+{
+    int lg = 0;
+    while ((1 << lg) < width && (1 << lg) < kTX) ++lg;
+    return TMap{(int)threadIdx.x & ((1 << lg) - 1), (int)threadIdx.x >> lg, 1 << lg, kTailThreads >> lg};
+}
 
 // 2D, constant kappa: the neighbourhood of cell (i, j) of a level held in LDS, with the
 // values and boundary-face count of fas_device.h's gather (neighbours across a periodic
@@ -82,14 +91,14 @@ __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int f
     const T q0 = op.q[diag_count(op.bc, DIM, 0)], q1 = op.q[diag_count(op.bc, DIM, 1)],
             q2 = op.q[diag_count(op.bc, DIM, 2)];
     const int rows = op.n1 * op.n2;
-    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    const TMap m = tmap(half);
     for (int s = 0; s < sweeps; ++s) {
         for (int ph = 0; ph < 2; ++ph) {
             const int parity = ph == 0 ? f0 : 1 - f0;
-            for (int row = ty; row < rows; row += kTY) {
+            for (int row = m.ty; row < rows; row += m.TY) {
                 const int l = DIM == 3 ? row / op.n1 : 0, j = DIM == 3 ? row - l * op.n1 : row;
                 const int odd = (parity + j + l) & 1;
-                for (int tt = tx; tt < half; tt += kTX) {
+                for (int tt = m.tx; tt < half; tt += m.TX) {
                     const int i = 2 * tt + odd;
                     if (i >= op.n0) continue;
                     Nbhd<T, DIM> nb;
@@ -138,13 +147,13 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         }
     }
     __syncthreads();
-    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
     if (a.form_rhs) {
         // f = r_c + A_c u_c
         const Op<T> op = OP(0);
-        for (int row = ty; row < op.n1 * op.n2; row += kTY) {
+        const TMap m = tmap(op.n0);
+        for (int row = m.ty; row < op.n1 * op.n2; row += m.TY) {
             const int l = DIM == 3 ? row / op.n1 : 0, j = DIM == 3 ? row - l * op.n1 : row;
-            for (int i = tx; i < op.n0; i += kTX) {
+            for (int i = m.tx; i < op.n0; i += m.TX) {
                 const int p = (int)cell_index(op.n0, op.n1, i, j, l);
                 Nbhd<T, DIM> nb;
                 tail_gather<T, DIM, KV>(op, U(0), i, j, l, nb);
@@ -161,8 +170,9 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         T* u = U(lv);
         const T* f = F(lv);
         tail_smooth<T, DIM, KV>(op, u, f, a.pre, a.first, rev);
-        for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
-        for (int I = tx; I < oc.n0; I += kTX) {
+        const TMap m = tmap(oc.n0);
+        for (int crow = m.ty; crow < oc.n1 * oc.n2; crow += m.TY)
+        for (int I = m.tx; I < oc.n0; I += m.TX) {
             const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
             const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             T uu[8], rr[8];
@@ -184,8 +194,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
             }
         }
         __syncthreads();
-        for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
-        for (int I = tx; I < oc.n0; I += kTX) {
+        for (int crow = m.ty; crow < oc.n1 * oc.n2; crow += m.TY)
+        for (int I = m.tx; I < oc.n0; I += m.TX) {
             const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
             const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             Nbhd<T, DIM> nb;
@@ -201,8 +211,9 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         const Op<T> op = OP(lv);
         const Op<T> oc = OP(lv + 1);
         T* u = U(lv);
-        for (int crow = ty; crow < oc.n1 * oc.n2; crow += kTY)
-        for (int I = tx; I < oc.n0; I += kTX) {
+        const TMap m = tmap(oc.n0);
+        for (int crow = m.ty; crow < oc.n1 * oc.n2; crow += m.TY)
+        for (int I = m.tx; I < oc.n0; I += m.TX) {
             const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
             const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             const int i = 2 * I, j = 2 * J, l = 2 * K;
