@@ -439,15 +439,21 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
         if (partials && fas::fused3_partials(g, l, norm_ns) > g->npartials / g->batch) partials = nullptr;
         void* const rcd = rc_dst(g, l, pre, post);
         void* const ucd = march3_from_x(g, l + 1, pre, post) ? C.x : C.u;
+        // a defect correction's first inner cycle starts from zero; its last adds the
+        // finest-level result into the FP64 iterate instead of storing it
+        const bool zero = l == 0 && g->zero_start;
+        double* const acc64 = l == 0 ? g->accum64 : nullptr;
+        if (acc64 && partials) throw Error(FAS_ERR_ARG, "internal: accumulation with a norm");
         {
             ProfScope ps(g, l, FAS_K_PRE);
             for (int i = 0; i < npre - 1; ++i, cur ^= 1) {
                 const bool form = rc_in && i == 0;
                 fas::launch_march3(g, l, g->coef[l], first, 2, pre_ns[i], false, form ? rc_in : f, bufs[cur],
-                                   bufs[cur ^ 1], nullptr, nullptr, nullptr, form ? g->lev[l].f : nullptr);
+                                   bufs[cur ^ 1], nullptr, nullptr, nullptr, form ? g->lev[l].f : nullptr,
+                                   zero && i == 0);
             }
             fas::launch_march3(g, l, g->coef[l], first, 0, pre_ns[npre - 1], false, f, bufs[cur], bufs[cur ^ 1], ucd,
-                               rcd, nullptr);
+                               rcd, nullptr, nullptr, zero && npre == 1);
             cur ^= 1;
             ps.end();
         }
@@ -456,9 +462,11 @@ int vcycle_level(fas_grid* g, int l, const void* f, void* u, int pre, int post, 
             ProfScope ps(g, l, FAS_K_POST);
             for (int i = 0; i < npost; ++i, cur ^= 1)
                 fas::launch_march3(g, l, g->coef[l], first, i == 0 ? 1 : 2, post_ns[i], partials && i == npost - 1, f,
-                                   bufs[cur], bufs[cur ^ 1], i == 0 ? C.u : nullptr, nullptr, partials);
+                                   bufs[cur], bufs[cur ^ 1], i == 0 ? C.u : nullptr, nullptr, partials, nullptr, false,
+                                   i == npost - 1 ? acc64 : nullptr);
             ps.end();
         }
+        if (acc64) return 0;  // the result went into the FP64 iterate; the FP32 one is dead
         if (bufs[cur] != u)
             FAS_HIP_CHECK(hipMemcpyAsync(u, bufs[cur], (size_t)g->lev[l].N * g->elem() * g->batch,
                                          hipMemcpyDeviceToDevice, g->stream));
@@ -533,6 +541,14 @@ bool finest_is_tile(const fas_grid* g, int pre, int post, bool kv)
     if (g->fused && fas::tail_top(g) == 0) return false;
     if (fas::fused3_ok(g, 0, kv) && pre >= 1 && post >= 1) return false;
     return fas::fused_ok(g, 0, pre, post, kv) && fas::tile_ok(g, 0, pre, post, kv);
+}
+
+// Whether a V(pre, post)-cycle of g runs its finest level as 3D plane-march passes (which
+// can also start from zero and add their result into an FP64 array).
+bool finest_is_march3(const fas_grid* g, int pre, int post, bool kv)
+{
+    if (g->fused && fas::tail_top(g) == 0) return false;
+    return fas::fused3_ok(g, 0, kv) && pre >= 1 && post >= 1;
 }
 
 // One cycle on the finest level; with want_norm the squared residual norm of the result
@@ -928,7 +944,7 @@ int solve_impl(fas_grid* g, double dt, double kappa, const void* kcell, const vo
 // its result into u itself.  Every kernel, FP32 cycles included, checks the outer active
 // flag, so the host looks at the status only near the expected end, as in solve_impl.
 int solve_mixed_stacked(fas_grid* g64, fas_grid* g32, const void* rhs, void* u, double tol, int nu1, int nu2,
-                        int inner, bool tile_top, int* status_out, int* cycles_out);
+                        int inner, bool fold_top, int* status_out, int* cycles_out);
 
 int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, const void* kcell, const void* rhs,
                      void* u, double tol, int nu1, int nu2, int inner, bool stacked = false, int* status_out = nullptr,
@@ -972,8 +988,11 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
     GateScope gate(g64);
     g32->active = g64->active;
     g32->gate = 1;
-    const bool tile_top = finest_is_tile(g32, nu1, nu2, kcell != nullptr);
-    if (stacked) return solve_mixed_stacked(g64, g32, rhs, u, tol, nu1, nu2, inner, tile_top, status_out, cycles_out);
+    // the finest FP32 passes start from zero and add into u themselves (tile passes, 3D
+    // plane marches); else the inner iterate is zeroed and added by kernels of their own
+    const bool fold_top = finest_is_tile(g32, nu1, nu2, kcell != nullptr) ||
+                          finest_is_march3(g32, nu1, nu2, kcell != nullptr);
+    if (stacked) return solve_mixed_stacked(g64, g32, rhs, u, tol, nu1, nu2, inner, fold_top, status_out, cycles_out);
     char* const span = (char*)g64->rnorm;
     const size_t span_bytes = (size_t)((char*)(g64->hist + fas::kHist) - span);
     if (span_bytes > kHostStatus) throw Error(FAS_ERR_ARG, "internal: status span exceeds the pinned buffer");
@@ -1001,14 +1020,14 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
         // correction k: `inner` cycles for the first, FAS_OPT_MIXED_INNER_NEXT for the later
         const int cyc_k = (k == 1 || g64->mixed_next <= 0) ? inner : g64->mixed_next;
         for (int m = 0; m < cyc_k; ++m) {
-            g32->zero_start = m == 0 && tile_top;
-            g32->accum64 = m == cyc_k - 1 && tile_top ? (double*)u : nullptr;
-            if (m == 0 && !tile_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
+            g32->zero_start = m == 0 && fold_top;
+            g32->accum64 = m == cyc_k - 1 && fold_top ? (double*)u : nullptr;
+            if (m == 0 && !fold_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
             vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
         }
         g32->zero_start = 0;
         g32->accum64 = nullptr;
-        if (!tile_top) fas::launch_update_mixed(g64, g32->mix_e, u);
+        if (!fold_top) fas::launch_update_mixed(g64, g32->mix_e, u);
     }
     const double nf = sqrt(*(const double*)host_at(g64->rnorm));
     const double* hist = (const double*)host_at(g64->hist);
@@ -1038,7 +1057,7 @@ int solve_mixed_impl(fas_grid* g64, fas_grid* g32, double dt, double kappa, cons
 // evaluations 1 .. c run without a look).  Every problem's iterates are those of its own
 // mixed solve.
 int solve_mixed_stacked(fas_grid* g64, fas_grid* g32, const void* rhs, void* u, double tol, int nu1, int nu2,
-                        int inner, bool tile_top, int* status_out, int* cycles_out)
+                        int inner, bool fold_top, int* status_out, int* cycles_out)
 {
     const int kmax = std::min(g64->kmax, fas::kHist - 1);
     const int horizon = g64->last_cycles > 0 ? g64->last_cycles : 0;
@@ -1058,14 +1077,14 @@ int solve_mixed_stacked(fas_grid* g64, fas_grid* g32, const void* rhs, void* u, 
         // correction k: `inner` cycles for the first, FAS_OPT_MIXED_INNER_NEXT for the later
         const int cyc_k = (k == 1 || g64->mixed_next <= 0) ? inner : g64->mixed_next;
         for (int m = 0; m < cyc_k; ++m) {
-            g32->zero_start = m == 0 && tile_top;
-            g32->accum64 = m == cyc_k - 1 && tile_top ? (double*)u : nullptr;
-            if (m == 0 && !tile_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
+            g32->zero_start = m == 0 && fold_top;
+            g32->accum64 = m == cyc_k - 1 && fold_top ? (double*)u : nullptr;
+            if (m == 0 && !fold_top) fas::launch_zero_f32(g32, g32->lev[0].N, g32->mix_e);
             vcycle_top(g32, g32->mix_r, g32->mix_e, nu1, nu2, false);
         }
         g32->zero_start = 0;
         g32->accum64 = nullptr;
-        if (!tile_top) fas::launch_update_mixed(g64, g32->mix_e, u);
+        if (!fold_top) fas::launch_update_mixed(g64, g32->mix_e, u);
     }
     // cyc[b]: evaluation at which problem b stopped (0: none, -k: not finite)
     std::vector<int> cyc((size_t)g64->batch);

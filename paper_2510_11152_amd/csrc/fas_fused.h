@@ -70,7 +70,16 @@ int fused3_partials(const fas_grid* g, int l, int ns);
 // then the sweeps; mode 2: the sweeps.  ns = sweeps in the pass (1 or 2).  norm: per-block
 // sums of r^2 (r = f - A u_out) into partials.  fout != nullptr (mode 2, ns 1, no norm): f
 // holds r = R(f_fine - A_fine u_fine) and the pass first forms f = r + A u_in into fout.
+// zero_in (FP32, modes 0 and 2, no fout): u_in is taken as 0 and not read.  acc64 (FP32, modes 1
+// and 2): acc64 += fp64(result) replaces the store into u_out.
 void launch_march3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
-                   const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout = nullptr);
+                   const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout = nullptr,
+                   bool zero_in = false, double* acc64 = nullptr);
+// The mixed form's FP64 pass on the finest level of an FP64 grid that runs plane marches:
+// r32 = fp32(f - A u), r^2 partial sums into partials and, if fpartials is given, f^2 into
+// fpartials (per problem, one per block).  Returns the partial sums per problem, or 0 (no
+// launch) when the grid has no such march or too many blocks.
+int launch_march3_resid(const fas_grid* g, const Coef& c, const void* f, const void* u, void* r32, double* partials,
+                        double* fpartials);
 
 }  // namespace fas

@@ -10,6 +10,7 @@
 
 #include "fas_batch.h"
 #include "fas_device.h"
+#include "fas_fused.h"
 #include "fas_internal.h"
 
 namespace fas {
@@ -967,6 +968,11 @@ int launch_mixed_resid(const fas_grid* g, const Coef& c, const void* kap, const 
     double* fp = fnorm ? g->fpartials : nullptr;
     const bool kv = kap != nullptr;
     const int64_t stride = g->lev[0].N;
+    if (g->dim == 3 && !kap) {
+        // plane march: each block keeps a ring of planes, so u is read about once
+        const int np = launch_march3_resid(g, c, f, u, r32, g->partials, fp);
+        if (np) return np;
+    }
     if (g->dim == 2 && !kap) {
         // row marches: one block per 512 columns and kMixedSeg rows
         const unsigned bx = (unsigned)((g->lev[0].n[0] / 2 + kBlock - 1) / kBlock);

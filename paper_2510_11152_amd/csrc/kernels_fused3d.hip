@@ -16,12 +16,17 @@
 // are those of fas_device.h.
 //
 // Modes: 0 = sweep + residual + restriction (u_c = R u, r_c = R r);
-//        1 = correction u += P(u_c - R u) + sweep;  2 = sweep only.
+//        1 = correction u += P(u_c - R u) + sweep;  2 = sweep only;
+//        3 = no sweep (FP64): the residual r = f - A u cast to FP32 for the inner solve of
+//            the mixed form, with the partial sums of r^2 (and of f^2 if asked).
 // RHS (the first pass of a coarse level, mode 2): f holds r = R(f - A u) of the finer
 // level, and the pass first forms the FAS right-hand side f = r + A u, one plane ahead of
 // the sweep while every neighbour still holds its initial value, then uses it and writes
 // it for the level's later passes.
 // Any mode with NORM leaves one partial sum of the squared residual per block.
+// Inner solves of the mixed form (FP32 only): zero_in makes a pass start from u = 0 without
+// reading u; acc64 makes a pass add its result into an FP64 iterate (acc64 += fp64(u))
+// instead of storing u.
 #include <hip/hip_runtime.h>
 
 #include "fas_device.h"
@@ -54,6 +59,10 @@ struct March3Args {
     T* rc;
     T* fout;  // RHS passes: the formed right-hand side
     double* partials;
+    float* r32;          // mode 3: the FP32 residual
+    double* fpartials;   // mode 3 (nullable): partial sums of f^2
+    int zero_in;         // FP32: 1: u_in is taken as 0 and not read (modes 0 and 2)
+    double* acc64;       // FP32 (nullable): acc64 += fp64(u) in place of storing u_out
 };
 
 constexpr int kShr1 = 0x138;  // wave_shr:1 (lane i gets lane i - 1)
@@ -109,14 +118,14 @@ __device__ __forceinline__ T pick_q3(const March3Args<T>& a, int W)
 // is taken
 constexpr int halo3(int ns, int mode, bool norm)
 {
-    return (2 * ns + ((mode == 0 || norm) ? 1 : 0) + 1) & ~1;
+    return (2 * ns + ((mode == 0 || mode == 3 || norm) ? 1 : 0) + 1) & ~1;
 }
 
 template <typename T, int NS, int MODE, bool NORM, bool RHS>
 struct Geom3 {
     static constexpr int S = 2 * NS;            // colour phases in the pass
     static constexpr int H = halo3(NS, MODE, NORM);
-    static constexpr bool RES = MODE == 0 || NORM;  // residual of the final plane
+    static constexpr bool RES = MODE == 0 || MODE == 3 || NORM;  // residual of the final plane
     // the correction (mode 1) and the right-hand side (RHS) need the plane below untouched
     static constexpr int LAG = (MODE == 1 || RHS) ? 1 : 0;
     // planes loaded ahead: one for two FP64 sweeps, whose ring of planes fills the 128
@@ -146,6 +155,8 @@ struct Arrays3 {
     T* uc;
     T* rc;
     T* fout;
+    float* r32;
+    double* acc64;
 };
 
 template <typename T, int NS, int MODE, bool NORM, bool RHS, bool EDGE, int FIRST>
@@ -211,7 +222,7 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
 
     T ue[RING], uo[RING], fe[RING], fo[RING], cr[RING];
     T su_prev = 0, sr_prev = 0;  // restriction: pair sums of the previous plane
-    double acc = 0.0;
+    double acc = 0.0, facc = 0.0;
 
     auto plane_of = [&](int rho, int& gz) -> bool {
         gz = rA + rho;
@@ -228,7 +239,13 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
         int gz;
         const bool zin = plane_of(rho, gz);
         const int64_t off = (int64_t)gz * plane + (int64_t)gyl * a.n0 + gxl;
-        V zu = *reinterpret_cast<const V*>(A.u_in + off);
+        V zu;
+        if (sizeof(T) == 4 && a.zero_in) {
+            zu.x = (T)0;
+            zu.y = (T)0;
+        } else {
+            zu = *reinterpret_cast<const V*>(A.u_in + off);
+        }
         V zf = *reinterpret_cast<const V*>(A.f + off);
         T c = (T)0;
         if constexpr (MODE == 1) {
@@ -391,7 +408,25 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
                         ro = fo[a0] - (uo[a0] + k * (Wo * uo[a0] - So));
                     }
                     if (inseg && own) {
-                        store_pair_nt(A.u_out + (int64_t)graw * plane + (int64_t)gy0 * a.n0 + gxe, ue[a0], uo[a0]);
+                        const int64_t o = (int64_t)graw * plane + (int64_t)gy0 * a.n0 + gxe;
+                        if constexpr (MODE == 3) {
+                            float2 rv;
+                            rv.x = (float)re;
+                            rv.y = (float)ro;
+                            *reinterpret_cast<float2*>(A.r32 + o) = rv;
+                            if (a.fpartials) {
+                                facc += (double)fe[a0] * (double)fe[a0];
+                                facc += (double)fo[a0] * (double)fo[a0];
+                            }
+                        } else if (sizeof(T) == 4 && A.acc64) {
+                            double2* const d = reinterpret_cast<double2*>(A.acc64 + o);
+                            double2 v = *d;
+                            v.x = v.x + (double)ue[a0];
+                            v.y = v.y + (double)uo[a0];
+                            *d = v;
+                        } else {
+                            store_pair_nt(A.u_out + o, ue[a0], uo[a0]);
+                        }
                         if constexpr (NORM) {
                             acc += (double)re * (double)re;
                             acc += (double)ro * (double)ro;
@@ -429,11 +464,16 @@ __device__ __forceinline__ void march3(const March3Args<T>& a, const Arrays3<T> 
         }
     }
     if constexpr (NORM) {
-        __syncthreads();  // red aliases the exchange area
+        // red aliases the exchange area; mode 3 sums f^2 beside r^2 in red[kThreads3 ..)
+        __syncthreads();
         red[tid] = acc;
+        if constexpr (MODE == 3) red[kThreads3 + tid] = facc;
         __syncthreads();
         for (int s = kThreads3 / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] = red[tid] + red[tid + s];
+            if (tid < s) {
+                red[tid] = red[tid] + red[tid + s];
+                if constexpr (MODE == 3) red[kThreads3 + tid] = red[kThreads3 + tid] + red[kThreads3 + tid + s];
+            }
             __syncthreads();
         }
     }
@@ -443,7 +483,9 @@ template <typename T, int NS, int MODE, bool NORM, bool RHS>
 __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first)
 {
     using G = Geom3<T, NS, MODE, NORM, RHS>;
-    static_assert(sizeof(Xchg<T, G::SLOTS>) >= kThreads3 * sizeof(double), "norm reduction fits the exchange area");
+    static_assert(sizeof(Xchg<T, G::SLOTS>) >= (MODE == 3 ? 2 : 1) * kThreads3 * sizeof(double),
+                  "norm reductions fit the exchange area");
+    static_assert(MODE != 3 || (NS == 0 && NORM && !RHS && sizeof(T) == 8), "mode 3: FP64 residual pass");
     __shared__ Xchg<T, G::SLOTS> X;
     double* red = reinterpret_cast<double*>(&X.buf[0][0][0]);
     // (dispatch order, tile x fastest: the blocks resident at one time cover one z-segment
@@ -458,6 +500,8 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
     A.uc = a.uc ? a.uc + b * a.cstride : nullptr;
     A.rc = a.rc ? a.rc + b * a.cstride : nullptr;
     A.fout = a.fout ? a.fout + b * a.stride : nullptr;
+    A.r32 = a.r32 ? a.r32 + b * a.stride : nullptr;
+    A.acc64 = a.acc64 ? a.acc64 + b * a.stride : nullptr;
     const int tx = w % a.tiles_x, ty = (w / a.tiles_x) % a.tiles_y, seg = w / (a.tiles_x * a.tiles_y);
     const int x0 = tx * G::UX, y0 = ty * G::UY, z0 = seg * a.seg_planes;
     const int planes_read = a.seg_planes + G::H + G::S + 1 + G::LAG;  // the steps of a full segment
@@ -475,7 +519,12 @@ __global__ __launch_bounds__(kThreads3) void k_march3(March3Args<T> a, int first
             march3<T, NS, MODE, NORM, RHS, false, 0>(a, A, X, tx, ty, seg, red);
     }
     if constexpr (NORM) {
-        if (threadIdx.x == 0) a.partials[(int64_t)b * per + w] = red[0];
+        if (threadIdx.x == 0) {
+            a.partials[(int64_t)b * per + w] = red[0];
+            if constexpr (MODE == 3) {
+                if (a.fpartials) a.fpartials[(int64_t)b * per + w] = red[kThreads3];
+            }
+        }
     }
 }
 
@@ -520,9 +569,14 @@ void go3(const fas_grid* g, const March3Args<T>& a, int first)
 
 template <typename T>
 void dispatch3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
-               const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout)
+               const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout, bool zero_in,
+               double* acc64)
 {
+    if ((zero_in && (sizeof(T) != 4 || mode == 1 || fout)) || (acc64 && (sizeof(T) != 4 || mode == 0)))
+        throw Error(FAS_ERR_ARG, "internal: zero start / FP64 accumulation on a pass that cannot take it");
     March3Args<T> a = make_args3<T>(g, l, c, ns, mode, norm && mode != 0);
+    a.zero_in = zero_in ? 1 : 0;
+    a.acc64 = acc64;
     a.f = (const T*)f;
     a.u_in = (const T*)u_in;
     a.u_out = (T*)u_out;
@@ -561,13 +615,31 @@ int fused3_partials(const fas_grid* g, int l, int ns)
     return a.tiles_x * a.tiles_y * a.segs;
 }
 
+int launch_march3_resid(const fas_grid* g, const Coef& c, const void* f, const void* u, void* r32, double* partials,
+                        double* fpartials)
+{
+    if (g->dtype != FAS_F64 || !fused3_ok(g, 0, g->lev[0].kap != nullptr)) return 0;
+    March3Args<double> a = make_args3<double>(g, 0, c, 0, 3, true);
+    const int per = a.tiles_x * a.tiles_y * a.segs;
+    if (per > g->npartials / g->batch) return 0;
+    a.f = (const double*)f;
+    a.u_in = (const double*)u;
+    a.r32 = (float*)r32;
+    a.partials = partials;
+    a.fpartials = fpartials;
+    go3<double, 0, 3, true>(g, a, 0);
+    check_launch3();
+    return per;
+}
+
 void launch_march3(const fas_grid* g, int l, const Coef& c, int first, int mode, int ns, bool norm, const void* f,
-                   const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout)
+                   const void* u_in, void* u_out, void* uc, void* rc, double* partials, void* fout, bool zero_in,
+                   double* acc64)
 {
     if (g->dtype == FAS_F64)
-        dispatch3<double>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials, fout);
+        dispatch3<double>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials, fout, zero_in, acc64);
     else
-        dispatch3<float>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials, fout);
+        dispatch3<float>(g, l, c, first, mode, ns, norm, f, u_in, u_out, uc, rc, partials, fout, zero_in, acc64);
 }
 
 }  // namespace fas

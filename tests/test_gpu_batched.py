@@ -316,7 +316,7 @@ def test_grain_rhs_coefficients_match_oracle_bitwise(coef, dtype):
 
 
 @pytest.mark.parametrize("n,bc,inner", [((128, 128), "periodic", 2), ((256, 128), "neumann", 3), ((64, 64), "dirichlet", 2),
-                                        ((16, 16, 16), "neumann", 2)])
+                                        ((16, 16, 16), "neumann", 2), ((64, 32, 16), "dirichlet", 2)])
 def test_stacked_mixed_members_equal_single_mixed_solves(n, bc, inner):
     """fas_solve_stacked_mixed: each member's iterate and outer-correction count equal its
     own fas_solve_mixed (same kernels and stopping tests), and one member against the

@@ -223,14 +223,15 @@ def test_solve_after_a_longer_solve_is_unchanged(n, dtype, transposed):
 @pytest.mark.parametrize("n,coarsest,bc", [((128, 128), 4, "neumann"), ((32, 32, 32), 4, "neumann"),
                                            ((128, 64), 4, "dirichlet"), ((512, 384), 6, "periodic"),
                                            ((1024, 512), 4, "neumann"), ((64, 64, 64), 4, "dirichlet"),
-                                           ((32, 32), 4, "neumann")])
+                                           ((32, 32), 4, "neumann"), ((96, 64, 32), 4, "periodic")])
 @pytest.mark.parametrize("variable", [False, True])
 @pytest.mark.parametrize("inner", [1, 3])
 def test_mixed_precision_matches_oracle(n, coarsest, bc, variable, inner):
     """FP32 inner cycles inside FP64 defect correction (tile passes that start from zero
-    and add into the FP64 iterate, 3D plane marches, a grid held entirely by the coarse
-    tail): the corrections equal the oracle's mixed solve bit for bit at equal correction
-    counts, with its residual history, and the result is within 1e-9 of the FP64 solution."""
+    and add into the FP64 iterate, 3D plane marches and the 3D residual march of the outer
+    step, a grid held entirely by the coarse tail): the corrections equal the oracle's mixed
+    solve bit for bit at equal correction counts, with its residual history, and the result
+    is within 1e-9 of the FP64 solution."""
     P = _problem(n, coarsest, bc, dt=1e-3, kappa=1.0)
     kap = np.exp(0.5 * I.random_field(P.shape(), 7)) if variable else None
     f = I.cosine_modes(max(n), len(n), 16, np.random.default_rng(1))[tuple(slice(0, m) for m in P.shape())]
