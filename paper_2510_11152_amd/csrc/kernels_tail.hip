@@ -17,7 +17,8 @@ namespace {
 
 constexpr int kTailThreads = 1024;
 constexpr int kTailLds = 96 * 1024;     // bytes of LDS for u and f of the tail levels
-constexpr int kTailLdsKV = 144 * 1024;  // cell kappa: u, f and kappa of the tail levels
+constexpr int kTailLdsKV = 156 * 1024;  // cell kappa: u and f of the tail levels, and in 2D
+                                        // the face weights of one level (3D: kappa per level)
 
 template <typename T>
 struct TailArgs {
@@ -26,7 +27,8 @@ struct TailArgs {
     int first;                // parity of the first phase of a sweep
     int form_rhs;             // 1: f_top = r_top + A u_top (FAS coarse right-hand side)
     int lds_off[kMaxTail];    // element offset of u of each level; f follows u
-    int kap_off[kMaxTail];    // cell kappa: element offset of each level's kappa copy
+    int kap_off[kMaxTail];    // 3D cell kappa: element offset of each level's kappa copy
+    int face_off;             // 2D cell kappa: element offset of the face-weight tables
     Op<T> op[kMaxTail];
     T* u_top;                 // in: initial guess of the top level; out: its new values
     const T* r_top;           // in: restricted residual (form_rhs) or the right-hand side
@@ -71,18 +73,76 @@ __device__ __forceinline__ void gather2(const Op<T>& op, const T* U, int i, int 
     s.nout = per ? 0 : (!xl) + (!xr) + (!yl) + (!yr);
 }
 
-// Neighbourhood of cell (i, j, l) of a level held in LDS.
+// 2D cell kappa: the face weights of one level, built in LDS once per visit of the level,
+// so that a phase reads each face's harmonic mean instead of recomputing it (a division)
+// for both of its cells.  wx[j (n0 + 1) + i] is the face between cells i - 1 and i of row j
+// (i = 0 and n0: the boundary faces), wy[j n0 + i] the face between rows j - 1 and j of
+// column i.  The values and argument orders are those of the per-cell gather (fas_device.h):
+// across a periodic edge the face of the wrapped pair, across another edge 2 kappa of the
+// cell (Dirichlet) or 0 (Neumann).
+template <typename T>
+__device__ void build_faces2(const Op<T>& op, const T* __restrict__ kap, T* wx, T* wy)
+{
+    const int n0 = op.n0, n1 = op.n1;
+    const bool per = op.bc == BC_PERIODIC, dir = op.bc == BC_DIRICHLET;
+    const TMap m = tmap(n0 + 1);
+    for (int j = m.ty; j < n1; j += m.TY) {
+        const T* const kr = kap + (size_t)j * n0;
+        for (int i = m.tx; i <= n0; i += m.TX) {
+            T w;
+            if (i > 0 && i < n0)
+                w = face_w(kr[i - 1], kr[i]);
+            else if (per)
+                w = face_w(kr[n0 - 1], kr[0]);
+            else
+                w = dir ? (T)2 * kr[i == 0 ? 0 : n0 - 1] : (T)0;
+            wx[j * (n0 + 1) + i] = w;
+        }
+    }
+    for (int j = m.ty; j <= n1; j += m.TY) {
+        for (int i = m.tx; i < n0; i += m.TX) {
+            T w;
+            if (j > 0 && j < n1)
+                w = face_w(kap[(size_t)(j - 1) * n0 + i], kap[(size_t)j * n0 + i]);
+            else if (per)
+                w = face_w(kap[(size_t)(n1 - 1) * n0 + i], kap[i]);
+            else
+                w = dir ? (T)2 * kap[(size_t)(j == 0 ? 0 : n1 - 1) * n0 + i] : (T)0;
+            wy[j * n0 + i] = w;
+        }
+    }
+}
+
+// 2D cell kappa: neighbour values as gather2, face weights from the level's tables.
+template <typename T>
+__device__ __forceinline__ void gather2kv(const Op<T>& op, const T* U, const T* wx, const T* wy, int i, int j,
+                                          Nbhd<T, 2>& s)
+{
+    gather2<T>(op, U, i, j, s);
+    const int fx = j * (op.n0 + 1) + i, fy = j * op.n0 + i;
+    s.w[0] = wx[fx];
+    s.w[1] = wx[fx + 1];
+    s.w[2] = wy[fy];
+    s.w[3] = wy[fy + op.n0];
+}
+
+// Neighbourhood of cell (i, j, l) of a level held in LDS (wx, wy: the 2D cell-kappa face
+// tables of that level).
 template <typename T, int DIM, bool KV>
-__device__ __forceinline__ void tail_gather(const Op<T>& op, const T* U, int i, int j, int l, Nbhd<T, DIM>& s)
+__device__ __forceinline__ void tail_gather(const Op<T>& op, const T* U, const T* wx, const T* wy, int i, int j,
+                                            int l, Nbhd<T, DIM>& s)
 {
     if constexpr (DIM == 2 && !KV)
         gather2<T>(op, U, i, j, s);
+    else if constexpr (DIM == 2 && KV)
+        gather2kv<T>(op, U, wx, wy, i, j, s);
     else
         gather<T, DIM, KV>(op, U, i, j, l, s);
 }
 
 template <typename T, int DIM, bool KV>
-__device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int first, bool reverse)
+__device__ void tail_smooth(const Op<T>& op, T* U, const T* F, const T* wx, const T* wy, int sweeps, int first,
+                            bool reverse)
 {
     const int f0 = reverse ? 1 - first : first;
     const int half = (op.n0 + 1) >> 1;
@@ -102,7 +162,7 @@ __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int f
                     const int i = 2 * tt + odd;
                     if (i >= op.n0) continue;
                     Nbhd<T, DIM> nb;
-                    tail_gather<T, DIM, KV>(op, U, i, j, l, nb);
+                    tail_gather<T, DIM, KV>(op, U, wx, wy, i, j, l, nb);
                     const int p = (int)cell_index(op.n0, op.n1, i, j, l);
                     if constexpr (DIM == 2 && !KV) {  // gs_value's tree
                         const T S = nbsum<T, DIM>(nb.v);
@@ -121,24 +181,42 @@ __device__ void tail_smooth(const Op<T>& op, T* U, const T* F, int sweeps, int f
 template <typename T, int DIM, bool KV>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, const T* const r_top)
 {
-    // cell kappa: every level's kappa is copied into LDS too, so the face weights of each
-    // phase read it there rather than from global memory
+    // cell kappa: in 2D each level's face weights are built in LDS when the level is
+    // visited (from its kappa in global memory); in 3D every level's kappa is copied into
+    // LDS, so the face weights of each phase read it there rather than from global memory
+    constexpr bool KV2 = KV && DIM == 2;
     __shared__ __attribute__((aligned(16))) char lds[KV ? kTailLdsKV : kTailLds];
     T* base = reinterpret_cast<T*>(lds);
     auto U = [&](int l) { return base + a.lds_off[l]; };
     auto F = [&](int l) { return base + a.lds_off[l] + (a.op[l].n0 * a.op[l].n1 * a.op[l].n2); };
-    // the operator of level l, its cell kappa (if any) read from the LDS copy
+    // the operator of level l, its cell kappa (if any) read from the LDS copy (3D)
     auto OP = [&](int l) {
         Op<T> o = a.op[l];
-        if constexpr (KV) o.kap = base + a.kap_off[l];
+        if constexpr (KV && DIM == 3) o.kap = base + a.kap_off[l];
         return o;
     };
+    T* const wx = KV2 ? base + a.face_off : nullptr;
+    T* const wy = KV2 ? wx + (a.op[0].n0 + 1) * a.op[0].n1 : nullptr;
+    int faces_of = -1;  // level whose face tables are in LDS
+    auto faces = [&](int l) {
+        if constexpr (KV2) {
+            if (faces_of != l) {
+                __syncthreads();  // the previous tables' readers are done
+                build_faces2<T>(a.op[l], a.op[l].kap, wx, wx + (a.op[l].n0 + 1) * a.op[l].n1);
+                __syncthreads();
+                faces_of = l;
+            }
+        }
+    };
+    // the y-face table of level l starts after its x faces
+    auto WY = [&](int l) { return KV2 ? wx + (a.op[l].n0 + 1) * a.op[l].n1 : nullptr; };
+    (void)wy;
     const int N0 = a.op[0].n0 * a.op[0].n1 * a.op[0].n2;
     for (int p = threadIdx.x; p < N0; p += kTailThreads) {
         U(0)[p] = u_top[p];
         F(0)[p] = r_top[p];
     }
-    if constexpr (KV) {
+    if constexpr (KV && DIM == 3) {
         for (int l = 0; l < a.nl; ++l) {
             const int Nl = a.op[l].n0 * a.op[l].n1 * a.op[l].n2;
             T* const kl = base + a.kap_off[l];
@@ -147,6 +225,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         }
     }
     __syncthreads();
+    faces(0);
     if (a.form_rhs) {
         // f = r_c + A_c u_c
         const Op<T> op = OP(0);
@@ -156,7 +235,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
             for (int i = m.tx; i < op.n0; i += m.TX) {
                 const int p = (int)cell_index(op.n0, op.n1, i, j, l);
                 Nbhd<T, DIM> nb;
-                tail_gather<T, DIM, KV>(op, U(0), i, j, l, nb);
+                tail_gather<T, DIM, KV>(op, U(0), wx, WY(0), i, j, l, nb);
                 F(0)[p] = F(0)[p] + apply_value<T, DIM, KV>(op, nb, U(0)[p]);
             }
         }
@@ -169,7 +248,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         const Op<T> oc = OP(lv + 1);
         T* u = U(lv);
         const T* f = F(lv);
-        tail_smooth<T, DIM, KV>(op, u, f, a.pre, a.first, rev);
+        faces(lv);
+        tail_smooth<T, DIM, KV>(op, u, f, wx, WY(lv), a.pre, a.first, rev);
         const TMap m = tmap(oc.n0);
         for (int crow = m.ty; crow < oc.n1 * oc.n2; crow += m.TY)
         for (int I = m.tx; I < oc.n0; I += m.TX) {
@@ -181,7 +261,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
                 const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), l = DIM == 3 ? 2 * K + (c >> 2) : 0;
                 const int p = (int)cell_index(op.n0, op.n1, i, j, l);
                 Nbhd<T, DIM> nb;
-                tail_gather<T, DIM, KV>(op, u, i, j, l, nb);
+                tail_gather<T, DIM, KV>(op, u, wx, WY(lv), i, j, l, nb);
                 uu[c] = u[p];
                 rr[c] = f[p] - apply_value<T, DIM, KV>(op, nb, uu[c]);
             }
@@ -194,18 +274,20 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
             }
         }
         __syncthreads();
+        faces(lv + 1);
         for (int crow = m.ty; crow < oc.n1 * oc.n2; crow += m.TY)
         for (int I = m.tx; I < oc.n0; I += m.TX) {
             const int K = DIM == 3 ? crow / oc.n1 : 0, J = DIM == 3 ? crow - K * oc.n1 : crow;
             const int P = (int)cell_index(oc.n0, oc.n1, I, J, K);
             Nbhd<T, DIM> nb;
-            tail_gather<T, DIM, KV>(oc, U(lv + 1), I, J, K, nb);
+            tail_gather<T, DIM, KV>(oc, U(lv + 1), wx, WY(lv + 1), I, J, K, nb);
             F(lv + 1)[P] = F(lv + 1)[P] + apply_value<T, DIM, KV>(oc, nb, U(lv + 1)[P]);
         }
         __syncthreads();
     }
     // coarsest level: smoothing only (Remark 1)
-    tail_smooth<T, DIM, KV>(OP(a.nl - 1), U(a.nl - 1), F(a.nl - 1), a.nuc, a.first, rev);
+    faces(a.nl - 1);
+    tail_smooth<T, DIM, KV>(OP(a.nl - 1), U(a.nl - 1), F(a.nl - 1), wx, WY(a.nl - 1), a.nuc, a.first, rev);
     // ascend: u += P(u_c - R u), post-smoothing
     for (int lv = a.nl - 2; lv >= 0; --lv) {
         const Op<T> op = OP(lv);
@@ -236,7 +318,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
             }
         }
         __syncthreads();
-        tail_smooth<T, DIM, KV>(op, u, F(lv), a.post, a.first, rev);
+        faces(lv);
+        tail_smooth<T, DIM, KV>(op, u, F(lv), wx, WY(lv), a.post, a.first, rev);
     }
     for (int p = threadIdx.x; p < N0; p += kTailThreads) u_top[p] = U(0)[p];
 }
@@ -282,9 +365,15 @@ TailArgs<T> make_tail_args(const fas_grid* g, int top, const Coef* coef, int pre
         off += 2 * (int)g->lev[l].N;
     }
     const bool kv = g->lev[top].kap != nullptr;
-    for (int i = 0; i < a.nl; ++i) {  // cell kappa: copies after every level's u and f
-        a.kap_off[i] = off;
-        if (kv) off += (int)g->lev[top + i].N;
+    a.face_off = off;
+    if (kv && g->dim == 2) {
+        // 2D cell kappa: the face tables of one level, sized for the top level
+        off += (int)((g->lev[top].n[0] + 1) * g->lev[top].n[1] + g->lev[top].n[0] * (g->lev[top].n[1] + 1));
+    } else {
+        for (int i = 0; i < a.nl; ++i) {  // 3D cell kappa: copies after every level's u and f
+            a.kap_off[i] = off;
+            if (kv) off += (int)g->lev[top + i].N;
+        }
     }
     if ((size_t)off * sizeof(T) > (size_t)(kv ? kTailLdsKV : kTailLds))
         throw Error(FAS_ERR_ARG, "internal: tail levels exceed the tail's LDS");
@@ -327,16 +416,19 @@ void launch_t(const fas_grid* g, int top, const Coef* coef, int pre, int post, i
 
 int tail_top(const fas_grid* g)
 {
-    // the largest level from which every coarser level's u and f (and the cell kappa on a
-    // grid that may take one) fit the tail's LDS; the two budgets admit the same levels
+    // the largest level from which every coarser level's u and f (and, on a grid that may
+    // take a cell kappa, the top level's face tables in 2D or every level's kappa in 3D) fit
+    // the tail's LDS; the budgets admit the same levels
     const size_t s = g->elem();
     const bool kv = (g->flags & FAS_FLAG_VARIABLE_KAPPA) != 0;
     const size_t cap = kv ? (size_t)kTailLdsKV : (size_t)kTailLds;
     size_t bytes = 0;
     int top = g->L + 1;
     for (int l = g->L; l >= 0; --l) {
-        bytes += (kv ? 3 : 2) * (size_t)g->lev[l].N * s;
-        if (bytes > cap || g->L - l + 1 > kMaxTail) break;
+        bytes += (kv && g->dim == 3 ? 3 : 2) * (size_t)g->lev[l].N * s;
+        const int64_t n0 = g->lev[l].n[0], n1 = g->lev[l].n[1];
+        const size_t faces = kv && g->dim == 2 ? (size_t)((n0 + 1) * n1 + n0 * (n1 + 1)) * s : 0;
+        if (bytes + faces > cap || g->L - l + 1 > kMaxTail) break;
         top = l;
     }
     return top;  // L + 1: not even the coarsest level fits
