@@ -223,7 +223,8 @@ def test_solve_after_a_longer_solve_is_unchanged(n, dtype, transposed):
 @pytest.mark.parametrize("n,coarsest,bc", [((128, 128), 4, "neumann"), ((32, 32, 32), 4, "neumann"),
                                            ((128, 64), 4, "dirichlet"), ((512, 384), 6, "periodic"),
                                            ((1024, 512), 4, "neumann"), ((64, 64, 64), 4, "dirichlet"),
-                                           ((32, 32), 4, "neumann"), ((96, 64, 32), 4, "periodic")])
+                                           ((32, 32), 4, "neumann"), ((96, 64, 32), 4, "periodic"),
+                                           ((128, 64, 32), 4, "dirichlet")])
 @pytest.mark.parametrize("variable", [False, True])
 @pytest.mark.parametrize("inner", [1, 3])
 def test_mixed_precision_matches_oracle(n, coarsest, bc, variable, inner):
