@@ -376,13 +376,18 @@ def bench_3d(dev, steps=5, inner=4, cpu=True, inner_next=0, march3_sweeps=2):
     del v
     passes = 1 if march3_sweeps == 2 else 2
     bytes3 = {"pre": 8 * (3 * passes + 2 / 8) * n ** 3, "post": 8 * (3 * passes + 1 / 8) * n ** 3}
+    # the bytes the same two sweeps would move as one-sweep passes: a rate for comparing the
+    # two pass sizes (the work is the same, only the bytes per pass differ)
+    bytes1 = {"pre": 8 * (6 + 2 / 8) * n ** 3, "post": 8 * (6 + 1 / 8) * n ** 3}
     k3 = {}
     for k in ("pre", "post"):
         launches, ms = prof[k]
         if launches:
-            gbs = bytes3[k] / (ms / 1e3 / launches) / 1e9
+            sec = ms / 1e3 / launches
+            gbs = bytes3[k] / sec / 1e9
             k3[k] = {"passes_per_launch": passes, "avg_us": ms * 1e3 / launches, "algorithmic_bytes": bytes3[k],
-                     "gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
+                     "gbs": gbs, "frac": gbs / PEAK_HBM_GBS,
+                     "one_sweep_pass_bytes": bytes1[k], "one_sweep_pass_equivalent_gbs": bytes1[k] / sec / 1e9}
     out["finest_level_kernels"] = k3
     g32 = Grid((n, n, n), 1.0 / n, dtype=torch.float32, coarsest=4, mixed_inner=True, device=dev).set(
         march3_sweeps=march3_sweeps)
