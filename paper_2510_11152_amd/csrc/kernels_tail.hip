@@ -195,8 +195,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
         if constexpr (KV && DIM == 3) o.kap = base + a.kap_off[l];
         return o;
     };
-    T* const wx = KV2 ? base + a.face_off : nullptr;
-    T* const wy = KV2 ? wx + (a.op[0].n0 + 1) * a.op[0].n1 : nullptr;
+    T* const wx = KV2 ? base + a.face_off : nullptr;  // x faces of the current level
     int faces_of = -1;  // level whose face tables are in LDS
     auto faces = [&](int l) {
         if constexpr (KV2) {
@@ -210,7 +209,6 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a, T* const u_top, 
     };
     // the y-face table of level l starts after its x faces
     auto WY = [&](int l) { return KV2 ? wx + (a.op[l].n0 + 1) * a.op[l].n1 : nullptr; };
-    (void)wy;
     const int N0 = a.op[0].n0 * a.op[0].n1 * a.op[0].n2;
     for (int p = threadIdx.x; p < N0; p += kTailThreads) {
         U(0)[p] = u_top[p];
