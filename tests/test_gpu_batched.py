@@ -20,7 +20,8 @@ TD = {np.float64: torch.float64, np.float32: torch.float32}
                                                  ((512, 256), "dirichlet", np.float64, 4), ((64, 64), "neumann", np.float32, 4),
                                                  ((16, 16, 16), "neumann", np.float64, 4),
                                                  ((64, 64, 64), "periodic", np.float32, 4),
-                                                 ((64, 32, 32), "neumann", np.float64, 4)])
+                                                 ((64, 32, 32), "neumann", np.float64, 4),
+                                                 ((128, 64, 32), "dirichlet", np.float64, 4)])
 def test_batch_members_equal_single_solves(n, bc, dtype, coarsest):
     from paper_2510_11152_amd import Grid
     B, dt, tol = 5, 2e-3, 1e-10 if dtype == np.float64 else 1e-5
